@@ -1,0 +1,80 @@
+"""The oracle's own dof maps for a periodic extruded box (test infrastructure).
+
+Numbering convention (the documented layout of trace vectors, shared as a
+convention with the library's header, not as code):
+
+* cells: ``k * ncol + iy * nx + ix``
+* trace faces: first the horizontal facets (bottom/top of cells),
+  ``k * ncol + col`` for k = 0..L, then the vertical facets,
+  ``(L + 1) * ncol + k * 2 ncol + e`` with x-facet ``e = iy*nx + ix`` on the
+  west side of column (ix, iy) and y-facet ``e = ncol + iy*nx + ix`` on its
+  south side.
+* local faces of a cell: W, E, S, N, B, T.
+* global orientation of a facet normal: +x, +y, +z.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+
+class BoxMesh:
+    def __init__(self, nx, ny, nlev, dx, dy, z):
+        self.nx, self.ny, self.nlev = int(nx), int(ny), int(nlev)
+        self.dx, self.dy = float(dx), float(dy)
+        self.z = np.asarray(z, np.float64)
+        self.dz = np.diff(self.z)
+        self.ncol = self.nx * self.ny
+        self.ncell = self.ncol * self.nlev
+        self.n_zface = self.ncol * (self.nlev + 1)
+        self.n_hface = 2 * self.ncol * self.nlev
+        self.ntrace = self.n_zface + self.n_hface
+        self._build()
+
+    def zface(self, k, ix, iy):
+        return k * self.ncol + (iy % self.ny) * self.nx + (ix % self.nx)
+
+    def xface(self, k, ix, iy):
+        return self.n_zface + k * 2 * self.ncol + (iy % self.ny) * self.nx + (ix % self.nx)
+
+    def yface(self, k, ix, iy):
+        return self.n_zface + k * 2 * self.ncol + self.ncol + (iy % self.ny) * self.nx + (ix % self.nx)
+
+    def _build(self):
+        L, nx, ny = self.nlev, self.nx, self.ny
+        faces = np.empty((self.ncell, 6), np.int64)
+        sign = np.empty((self.ncell, 6), np.float64)
+        layer = np.empty(self.ncell, np.int64)
+        cix = np.empty(self.ncell, np.int64)
+        ciy = np.empty(self.ncell, np.int64)
+        for k in range(L):
+            for iy in range(ny):
+                for ix in range(nx):
+                    c = k * self.ncol + iy * nx + ix
+                    faces[c] = (
+                        self.xface(k, ix, iy),
+                        self.xface(k, ix + 1, iy),
+                        self.yface(k, ix, iy),
+                        self.yface(k, ix, iy + 1),
+                        self.zface(k, ix, iy),
+                        self.zface(k + 1, ix, iy),
+                    )
+                    # the +x/+y/+z normal leaves the cell through E, N, T
+                    sign[c] = (-1.0, 1.0, -1.0, 1.0, -1.0, 1.0)
+                    layer[c], cix[c], ciy[c] = k, ix, iy
+        self.cell_faces = faces
+        self.cell_sign = sign
+        self.cell_layer = layer
+        self.cell_ix = cix
+        self.cell_iy = ciy
+        # a facet is on the rigid lid / ground when it is the bottom of layer 0 or the top of layer L-1
+        bnd = np.zeros(self.ntrace, bool)
+        bnd[: self.ncol] = True
+        bnd[L * self.ncol : (L + 1) * self.ncol] = True
+        self.boundary = bnd
+
+    def column_of_zface(self, f):
+        return f % self.ncol
+
+    def is_zface(self, f):
+        return f < self.n_zface

@@ -1,0 +1,161 @@
+"""Preconditioner of the trace system (test infrastructure).
+
+Follows the paper:
+
+* Sec. 2.3: the lumped velocity mass matrix, the approximate Schur complement
+  H = -(Q32 + M3^rho M3^{-1} D) M2lumped^{-1} G + M3^Pi (Eq. of the elliptic
+  pressure system), the block-Jacobi smoother with the column operator H_z
+  and relaxation omega (Eq. of the pressure block-Jacobi iteration) inside a
+  tensor-product multigrid V-cycle.
+* Sec. 2.5: LineSmooth (Alg. 1), prolongation by facet averaging and
+  restriction by its transpose (intergrid operators), the row-sum scaling
+  Gamma (Eq. of the scaling matrix) and the non-nested two-level cycle
+  (Alg. 2).
+
+Readings of the paper taken here (the paper defers the pressure multigrid
+details to earlier work and prints one sign that diverges):
+
+* Alg. 1 is applied with the update lambda <- lambda + omega * delta (the
+  printed minus sign makes the sweep diverge; the pressure smoother of
+  Sec. 2.3 uses the plus sign).
+* Lumping: row sums of the assembled continuous velocity block
+  (M2 - Q22) in global orientation, over the interior (non-lid) dofs.
+* H_z: the diagonal of H plus its couplings to the cells above and below,
+  i.e. one tridiagonal block per column.
+* Multigrid levels: 2x2 horizontal agglomeration, no vertical coarsening;
+  restriction = sum over the four children, prolongation = injection, coarse
+  operators by the Galerkin product R H P; the coarsest level is smoothed
+  with a fixed number of block-Jacobi sweeps.
+* Prolongation to a facet on the ground or lid is one sided (the value of the
+  single adjacent cell), so the restriction weight there is 1 (1/2 elsewhere).
+
+Parity: the smoother, V-cycle and two-level cycle are fixed linear maps;
+they are pinned by tests against textbook limits (exact column solves when
+the horizontal coupling vanishes, convergence of the stationary iterations,
+the divergence of the printed smoother sign), against H 1 = M3^Pi 1 and the
+Galerkin identity of the coarse operators, and by brute force on dense
+matrices for Gamma.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from .mesh import BoxMesh
+
+
+def lumped_velocity_mass(mixed):
+    """Row sums of the assembled continuous (M2 - Q22) over interior dofs."""
+    return np.asarray(mixed.Muu.sum(axis=1)).ravel()
+
+
+def pressure_operator(mixed, m2lumped=None):
+    """H = -(Q32 + M3rho M3^-1 D) M2lumped^-1 G + M3Pi (sparse, cells x cells)."""
+    if m2lumped is None:
+        m2lumped = lumped_velocity_mass(mixed)
+    H = -(mixed.Bp @ sp.diags(1.0 / m2lumped) @ mixed.G) + mixed.M3pi
+    return sp.csr_matrix(H)
+
+
+def column_part(H, ncol):
+    """Keep the couplings of H between cells of the same column (block tridiagonal here)."""
+    Hc = sp.coo_matrix(H)
+    keep = (Hc.row % ncol) == (Hc.col % ncol)
+    return sp.csr_matrix((Hc.data[keep], (Hc.row[keep], Hc.col[keep])), shape=H.shape)
+
+
+def agglomeration(nx, ny, nlev):
+    """Injection P (fine cells x coarse cells) of the 2x2 horizontal agglomeration."""
+    cx, cy = nx // 2, ny // 2
+    nf, nc = nx * ny * nlev, cx * cy * nlev
+    fine = np.arange(nf)
+    k = fine // (nx * ny)
+    col = fine % (nx * ny)
+    ix, iy = col % nx, col // nx
+    coarse = k * cx * cy + (iy // 2) * cx + ix // 2
+    return sp.csr_matrix((np.ones(nf), (fine, coarse)), shape=(nf, nc))
+
+
+class PressureMultigrid:
+    def __init__(self, H, nx, ny, nlev, levels=4, omega=0.9, pre=1, post=2, coarse_sweeps=3):
+        self.omega, self.pre, self.post, self.coarse_sweeps = omega, pre, post, coarse_sweeps
+        self.H = [sp.csr_matrix(H)]
+        self.P = []
+        self.ncol = [nx * ny]
+        for _ in range(1, levels):
+            P = agglomeration(nx, ny, nlev)
+            self.P.append(P)
+            self.H.append(sp.csr_matrix(P.T @ self.H[-1] @ P))
+            nx, ny = nx // 2, ny // 2
+            self.ncol.append(nx * ny)
+        self.Hz = [column_part(h, n) for h, n in zip(self.H, self.ncol)]
+        self.Hz_lu = [spla.splu(h.tocsc()) for h in self.Hz]
+
+    @property
+    def nlevels(self):
+        return len(self.H)
+
+    def smooth(self, level, x, b, sweeps):
+        for _ in range(sweeps):
+            x = x + self.omega * self.Hz_lu[level].solve(b - self.H[level] @ x)
+        return x
+
+    def vcycle(self, b, level=0):
+        x = np.zeros_like(b)
+        if level == self.nlevels - 1:
+            return self.smooth(level, x, b, self.coarse_sweeps)
+        x = self.smooth(level, x, b, self.pre)
+        r = b - self.H[level] @ x
+        xc = self.vcycle(self.P[level].T @ r, level + 1)
+        x = x + self.P[level] @ xc
+        return self.smooth(level, x, b, self.post)
+
+
+def trace_prolongation(mesh: BoxMesh):
+    """P: cells -> trace facets, lambda_F = average of the adjacent cells (one sided on lid/ground)."""
+    rows = mesh.cell_faces.ravel()
+    cols = np.repeat(np.arange(mesh.ncell), 6)
+    w = np.where(mesh.boundary[rows], 1.0, 0.5)
+    return sp.csr_matrix((w, (rows, cols)), shape=(mesh.ntrace, mesh.ncell))
+
+
+def line_smoother_matrix(mesh: BoxMesh, S):
+    """D = blockdiag(S^zz_j) + diag(S^hh): the part of S inverted by LineSmooth."""
+    Sc = sp.coo_matrix(S)
+    zr, zc = Sc.row < mesh.n_zface, Sc.col < mesh.n_zface
+    same_col = (Sc.row % mesh.ncol) == (Sc.col % mesh.ncol)
+    keep = (zr & zc & same_col) | (~zr & (Sc.row == Sc.col))
+    return sp.csr_matrix((Sc.data[keep], (Sc.row[keep], Sc.col[keep])), shape=S.shape)
+
+
+class TwoLevel:
+    """Alg. 2 with LineSmooth (Alg. 1) and a pressure multigrid V-cycle coarse solve."""
+
+    def __init__(self, mesh: BoxMesh, S, H, omega=0.6, n_pre=1, n_post=2, mg_levels=4,
+                 omega_p=0.9, mg_pre=1, mg_post=2, mg_coarse_sweeps=3, sign=+1.0):
+        self.mesh, self.S = mesh, sp.csr_matrix(S)
+        self.omega, self.n_pre, self.n_post, self.sign = omega, n_pre, n_post, sign
+        self.D = line_smoother_matrix(mesh, self.S)
+        self.D_lu = spla.splu(self.D.tocsc())
+        self.P = trace_prolongation(mesh)
+        self.mg = PressureMultigrid(H, mesh.nx, mesh.ny, mesh.nlev, mg_levels, omega_p, mg_pre,
+                                    mg_post, mg_coarse_sweeps)
+        ones_c = np.ones(mesh.ncell)
+        self.gamma = (H @ ones_c) / (self.P.T @ (self.S @ (self.P @ ones_c)))
+
+    def line_smooth(self, lam, B, sweeps):
+        for _ in range(sweeps):
+            R = B - self.S @ lam
+            lam = lam + self.sign * self.omega * self.D_lu.solve(R)
+        return lam
+
+    def __call__(self, B):
+        lam = np.zeros_like(B)
+        lam = self.line_smooth(lam, B, self.n_pre)
+        R = B - self.S @ lam
+        Bbar = self.gamma * (self.P.T @ R)
+        dpi = self.mg.vcycle(Bbar)
+        lam = lam + self.P @ dpi
+        return self.line_smooth(lam, B, self.n_post)

@@ -1,0 +1,40 @@
+"""Glue: build every oracle object for one synthetic box problem (test infrastructure)."""
+
+from __future__ import annotations
+
+import numpy as np
+
+from .hybrid import HybridSystem
+from .krylov import fgmres
+from .local import local_matrices
+from .mesh import BoxMesh
+from .mixed import MixedSystem
+from .precond import TwoLevel, pressure_operator
+
+
+def cells_from_soa(r_ub, r_pi):
+    """[6][L][ncol] and [L][ncol] -> (ncell, 6) and (ncell,) in cell order k*ncol+col."""
+    L, ncol = r_pi.shape
+    return np.ascontiguousarray(r_ub.reshape(6, L * ncol).T), r_pi.reshape(L * ncol).copy()
+
+
+class OracleProblem:
+    def __init__(self, prob, *, with_mixed=True, with_precond=True, omega=0.6, n_pre=1,
+                 n_post=2, mg_levels=None, omega_p=0.9, mg_pre=1, mg_post=2, mg_coarse_sweeps=3):
+        self.prob = prob
+        self.mesh = BoxMesh(prob.nx, prob.ny, prob.nlev, prob.dx, prob.dy, prob.z)
+        self.loc = local_matrices(self.mesh, prob)
+        self.hyb = HybridSystem(self.mesh, self.loc)
+        self.mixed = MixedSystem(self.mesh, self.loc, prob) if (with_mixed or with_precond) else None
+        self.pc = None
+        if with_precond:
+            self.H = pressure_operator(self.mixed)
+            if mg_levels is None:
+                mg_levels = len(prob.levels)
+            self.pc = TwoLevel(self.mesh, self.hyb.S, self.H, omega=omega, n_pre=n_pre,
+                               n_post=n_post, mg_levels=mg_levels, omega_p=omega_p, mg_pre=mg_pre,
+                               mg_post=mg_post, mg_coarse_sweeps=mg_coarse_sweeps)
+
+    def solve_fgmres(self, B, rtol=1e-8, restart=30, maxit=500, precondition=True):
+        M = self.pc if precondition else (lambda r: r)
+        return fgmres(lambda x: self.hyb.S @ x, M, B, rtol=rtol, restart=restart, maxit=maxit)

@@ -1,0 +1,10 @@
+"""Seeded synthetic inputs shared by the oracle and the GPU path.
+
+This package holds no arithmetic of the solver: it only describes meshes
+(connectivity tables, cell sizes), the linearisation state (reference
+profiles of potential temperature and Exner pressure, density) and the
+random right-hand sides.  Both the CPU oracle and the HIP library consume
+what it produces; neither imports the other.
+"""
+
+from .box import BoxProblem, make_box, make_rhs, config_box  # noqa: F401

@@ -1,0 +1,137 @@
+"""Pins of the oracle's preconditioner and Krylov solver (CPU only)."""
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle.krylov import fgmres
+from oracle.precond import PressureMultigrid, trace_prolongation
+from oracle.problem import OracleProblem, cells_from_soa
+from synth import make_box, make_rhs
+
+
+@pytest.fixture(scope="module")
+def box():
+    prob = make_box(nx=8, ny=8, nlev=6, dx=10e3, dy=8e3, dz=1250.0, mg_levels=3, perturb=0.05)
+    return prob, OracleProblem(prob)
+
+
+def test_pressure_operator_row_sums_and_stencil(box):
+    prob, o = box
+    H = o.H
+    # the discrete gradient G annihilates constants (volume and facet terms cancel), so H 1 = M3^Pi 1
+    ones = np.ones(H.shape[0])
+    np.testing.assert_allclose(H @ ones, o.mixed.M3pi.diagonal(), rtol=1e-9, atol=0)
+    np.testing.assert_allclose(o.mixed.G @ ones, 0.0, atol=1e-9 * np.abs(o.mixed.G).max())
+    # 7-point stencil on every level, off-diagonals negative; coarse operators keep the row sums
+    mg = o.pc.mg
+    for lev, Hl in enumerate(mg.H):
+        assert np.diff(Hl.indptr).max() <= 7
+        off = Hl - sp.diags(Hl.diagonal())
+        assert off.data.max() < 0
+        if lev:
+            P = mg.P[lev - 1]
+            np.testing.assert_allclose(Hl @ np.ones(Hl.shape[0]), P.T @ (mg.H[lev - 1] @ np.ones(P.shape[0])), rtol=1e-9)
+    # lumped mass: every entry positive
+    from oracle.precond import lumped_velocity_mass
+
+    assert lumped_velocity_mass(o.mixed).min() > 0
+
+
+def test_line_smoother_exact_when_columns_decouple():
+    """As dx -> infinity the horizontal couplings vanish and one sweep with omega = 1 solves the z part."""
+    errs = []
+    for dx in (1e6, 1e8):
+        prob = make_box(nx=4, ny=4, nlev=5, dx=dx, dz=1000.0, mg_levels=1)
+        o = OracleProblem(prob)
+        ruc, rpc = cells_from_soa(*make_rhs(prob, 0))
+        lam, _, _, B = o.hyb.solve_direct(ruc, rpc)
+        o.pc.omega = 1.0
+        l1 = o.pc.line_smooth(np.zeros_like(B), B, 1)
+        nz = o.mesh.n_zface
+        errs.append(np.linalg.norm(l1[:nz] - lam[:nz]) / np.linalg.norm(lam[:nz]))
+    assert errs[1] < 1e-4 and errs[1] < 1e-2 * errs[0]
+
+
+def test_smoother_sign_reading():
+    """With the update lambda - omega*delta the sweep diverges; with + it contracts for omega <= 0.8
+    and diverges beyond, matching the stability limit reported for omega > 0.8."""
+    prob = make_box(nx=6, ny=6, nlev=4, dx=10e3, dz=1250.0, mg_levels=1)
+    o = OracleProblem(prob)
+    S, D = o.hyb.S.toarray(), o.pc.D.toarray()
+    DinvS = np.linalg.solve(D, S)
+    rho = lambda sgn, om: np.abs(np.linalg.eigvals(np.eye(len(S)) - sgn * om * DinvS)).max()  # noqa: E731
+    assert rho(-1, 0.6) > 2.0
+    assert rho(+1, 0.6) < 1.0
+    assert rho(+1, 0.8) < 1.0
+    assert rho(+1, 1.0) > 1.0
+
+
+def test_vcycle_and_two_level_contract(box):
+    prob, o = box
+    rng = np.random.default_rng(5)
+    H = o.H
+    b = rng.standard_normal(H.shape[0])
+    x = np.zeros_like(b)
+    r0 = np.linalg.norm(b)
+    for _ in range(6):
+        x = x + o.pc.mg.vcycle(b - H @ x)
+    assert np.linalg.norm(b - H @ x) < 0.1 * r0
+    # when the horizontal coupling vanishes (dx -> infinity) H_z = H and one sweep with omega = 1 is exact
+    wide = make_box(nx=4, ny=4, nlev=6, dx=1e11, dz=1250.0, mg_levels=1)
+    ow = OracleProblem(wide)
+    bw = rng.standard_normal(ow.H.shape[0])
+    mg1 = PressureMultigrid(ow.H, 4, 4, 6, levels=1, omega=1.0, coarse_sweeps=1)
+    y = mg1.vcycle(bw)
+    assert np.linalg.norm(bw - ow.H @ y) < 1e-10 * np.linalg.norm(bw)
+    # the two-level cycle is a linear map
+    B1, B2 = rng.standard_normal(o.mesh.ntrace), rng.standard_normal(o.mesh.ntrace)
+    np.testing.assert_allclose(o.pc(2.0 * B1 - 3.0 * B2), 2.0 * o.pc(B1) - 3.0 * o.pc(B2), rtol=1e-10,
+                               atol=1e-12 * np.abs(o.pc(B1)).max())
+    # as a stationary iteration on S it converges
+    S = o.hyb.S
+    lam = np.zeros_like(B1)
+    for _ in range(15):
+        lam = lam + o.pc(B1 - S @ lam)
+    assert np.linalg.norm(B1 - S @ lam) < 0.1 * np.linalg.norm(B1)
+
+
+def test_gamma_against_dense_products(box):
+    prob, o = box
+    P = trace_prolongation(o.mesh).toarray()
+    # P maps a constant to a constant (one-sided on lid/ground facets)
+    np.testing.assert_allclose(P @ np.ones(P.shape[1]), 1.0)
+    S = o.hyb.S.toarray()
+    HG = P.T @ S @ P
+    gamma = o.H.toarray().sum(axis=1) / HG.sum(axis=1)
+    np.testing.assert_allclose(o.pc.gamma, gamma, rtol=1e-9)
+    assert o.pc.gamma.min() > 0
+
+
+def test_fgmres_minimal_residual_property():
+    rng = np.random.default_rng(0)
+    n = 40
+    A = np.eye(n) * 4 + rng.standard_normal((n, n)) * 0.3
+    b = rng.standard_normal(n)
+    Mmat = np.diag(1.0 / np.diag(A))
+    for k in (1, 3, 7):
+        x, hist, its, conv = fgmres(lambda v: A @ v, lambda v: Mmat @ v, b, rtol=0.0, restart=50, maxit=k)
+        # brute force: minimise ||b - A M y|| over the Krylov space of A M
+        AM = A @ Mmat
+        K = np.stack([np.linalg.matrix_power(AM, i) @ b for i in range(k)], axis=1)
+        y, *_ = np.linalg.lstsq(AM @ K, b, rcond=None)
+        best = np.linalg.norm(b - AM @ K @ y)
+        assert abs(np.linalg.norm(b - A @ x) - best) <= 1e-10 * np.linalg.norm(b)
+        assert abs(hist[-1] * np.linalg.norm(b) - best) <= 1e-10 * np.linalg.norm(b)
+
+
+def test_preconditioned_solve_reaches_tolerance(box):
+    prob, o = box
+    ruc, rpc = cells_from_soa(*make_rhs(prob, 2))
+    B = o.hyb.rhs(ruc, rpc)
+    x, hist, its, conv = o.solve_fgmres(B, rtol=1e-10)
+    assert conv and its < 40
+    assert np.linalg.norm(B - o.hyb.S @ x) <= 1e-10 * np.linalg.norm(B) * 1.01
+    assert all(h2 <= h1 * (1 + 1e-12) for h1, h2 in zip(hist, hist[1:]))
+    xu, hu, itu, cu = o.solve_fgmres(B, rtol=1e-10, precondition=False, maxit=2000)
+    assert itu > 2 * its
