@@ -1,0 +1,184 @@
+/*
+ * hyb.h - C ABI of the MI355X hybridised trace solver.
+ *
+ * The library solves the hybridised velocity / Exner-pressure system of one
+ * semi-implicit timestep of a compatible finite element dynamical core, the
+ * method of Betteridge, Cotter, Gibson, Griffith, Melvin and Mueller,
+ * "Hybridised multigrid preconditioners for a compatible finite element
+ * dynamical core":
+ *
+ *   [ A    K ] [ X      ]   [ R_X ]      A = [[M2b - Q22b, Gb], [Q32b + M3rho M3^-1 Db, M3Pi]]
+ *   [ C^T  0 ] [ lambda ] = [ 0   ]      (Sec. 2.4, hybridisable system and its block form)
+ *
+ * by static condensation S lambda = B_lambda with S = C^T A^-1 K and
+ * B_lambda = C^T A^-1 R_X (Sec. 2.4, Eqs. of S and B_lambda), a flexible
+ * GMRES solve of that trace system preconditioned by the non-nested
+ * two-level cycle (Sec. 2.5, Alg. 2 with LineSmooth, Alg. 1, and a pressure
+ * multigrid V-cycle on the approximate Schur complement H of Sec. 2.3), and
+ * the cellwise recovery X = A^-1 (R_X - K lambda) (Sec. 2.4, Eq. of the
+ * recovery).  Lowest order (p = 0): six outward-flux broken Raviart-Thomas
+ * dofs and one Exner-pressure dof per cell, one trace dof per facet.
+ *
+ * Layout (every per-cell or per-facet array is structure-of-arrays):
+ *   ncol columns, nlev layers; cell c = k * ncol + col (k = 0 at the ground).
+ *   Local faces of a cell: 0 W, 1 E, 2 S, 3 N (vertical facets, the "edges"
+ *   of the horizontal mesh), 4 B, 5 T (horizontal facets).
+ *   Trace vector (ntrace = (nlev+1)*ncol + nlev*nedge entries): first the
+ *   horizontal facets, index k*ncol + col for k = 0..nlev (the bottom of layer
+ *   k), then the vertical facets, index (nlev+1)*ncol + k*nedge + e.
+ *   Broken velocity arrays are [6][nlev][ncol]; cell arrays are [nlev][ncol];
+ *   theta / projected Exner fields on the vertically continuous points are
+ *   [nlev+1][ncol].
+ *
+ * Ownership: the caller allocates and frees every array it passes.  Mesh
+ * tables are HOST pointers, copied at hyb_create.  All field and vector
+ * arguments of the other calls are DEVICE pointers (FP64); the library keeps
+ * its own workspace (cell factors, trace stencil, multigrid hierarchy,
+ * Krylov basis), allocated by hyb_create / hyb_assemble_local / hyb_condense
+ * and freed by hyb_destroy.  Calls enqueue work on the context's stream and
+ * return without synchronising, except hyb_solve, which reads one small
+ * vector back to the host per iteration for its stopping test.
+ *
+ * Errors: every call returns HYB_OK (0) or a negative code; no exception or
+ * abort crosses the ABI.  hyb_last_error gives the text of the last error of
+ * a context.  One context per stream and host thread.
+ */
+#ifndef HYB_H
+#define HYB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HYB_OK 0
+#define HYB_EINVAL (-1)        /* null pointer, bad size or parameter */
+#define HYB_ESTATE (-2)        /* call out of order (e.g. solve before condense) */
+#define HYB_EHIP (-3)          /* HIP runtime error; text in hyb_last_error */
+#define HYB_ENOMEM (-4)        /* device allocation failed */
+#define HYB_NOT_CONVERGED 1    /* hyb_solve: maxit reached above rtol */
+#define HYB_BREAKDOWN 2        /* hyb_solve: NaN/Inf or a zero Arnoldi vector before convergence */
+
+#define HYB_PREC_FP64 0        /* every step in FP64 */
+#define HYB_PREC_MIXED 1       /* FP32 preconditioner and preconditioned basis, FP64 outer Krylov */
+
+typedef struct hyb_ctx hyb_ctx;
+
+/* Horizontal mesh of one multigrid level (host arrays). */
+typedef struct {
+  int32_t ncol;              /* columns */
+  const int32_t *col_edge;   /* [4][ncol]: edge of local face f (0..3) of a column */
+  const int32_t *edge_col;   /* [2][2*ncol]: column the edge normal leaves (0) / enters (1) */
+  const int32_t *edge_lf;    /* [2][2*ncol]: local face index of the edge in those columns */
+  const int32_t *parent;     /* [ncol of the next finer level]; NULL on level 0 */
+} hyb_level;
+
+/* Extruded mesh: a periodic box of nx*ny columns with cell sizes dx, dy and
+   layer thicknesses dz[nlev] (host), plus the 2x2-agglomerated multigrid
+   levels (levels[0] = the mesh itself; each coarser level keeps the local
+   face orientation of its children; no vertical coarsening). */
+typedef struct {
+  int32_t nlev;
+  int32_t nlevels;           /* multigrid levels, >= 1 */
+  const hyb_level *levels;   /* [nlevels] */
+  double dx, dy;
+  const double *dz;          /* host [nlev] */
+} hyb_mesh;
+
+typedef struct {
+  /* linearisation (Sec. 2.1): time step, off-centring weights, c_p, gas constant R */
+  double dt, tau_u, tau_rho, tau_theta, cp, rd;
+  /* LineSmooth / two-level cycle (Alg. 1 / Alg. 2): relaxation, pre and post sweeps */
+  double omega;
+  int32_t n_pre, n_post;
+  /* pressure multigrid (Sec. 2.3): block-Jacobi relaxation, sweeps per level, coarsest sweeps */
+  double omega_p;
+  int32_t mg_pre, mg_post, mg_coarse_sweeps;
+  /* flexible GMRES restart length and arithmetic of the preconditioner (HYB_PREC_*) */
+  int32_t restart;
+  int32_t precision;
+} hyb_params;
+
+typedef struct {
+  int32_t iters;        /* FGMRES iterations (preconditioner applications) */
+  int32_t status;       /* HYB_OK, HYB_NOT_CONVERGED or HYB_BREAKDOWN */
+  int32_t restarts;
+  double rel_res;       /* true ||B - S lambda||_2 / ||B||_2 at exit, computed in FP64 */
+  double *history;      /* optional host array: Arnoldi residual estimate per iteration */
+  int32_t history_cap;
+  int32_t history_len;
+} hyb_info;
+
+/* Create a context for one mesh.  stream: a hipStream_t (NULL = default stream).
+   Fails with HYB_EINVAL on inconsistent tables (every edge must appear on
+   two distinct (column, face) pairs; each coarse column must have 4 children). */
+int hyb_create(const hyb_mesh *mesh, const hyb_params *params, void *stream, hyb_ctx **out);
+
+/* Replace the solver parameters (not the physics: dt, tau_*, cp, rd are read by
+   hyb_assemble_local).  Sec. 3.2 and App. B tune n_pre, n_post, omega, omega_p. */
+int hyb_set_params(hyb_ctx *ctx, const hyb_params *params);
+
+/* Cell matrices A_K (7x7) and the diagonal of K_K (C_K is the identity for
+   outward-flux dofs) of every cell, from the bilinear forms of Sec. 2.2
+   (Eq. of the bilinear forms; q32, M3^rho and M3^Pi by the one-point rule
+   at the cell centre) and the hybrid forms of Sec. 2.4.  theta_w and
+   exner_hat_w: [nlev+1][ncol] values of theta* and the projected Exner
+   pressure on the bottom/top facet points (linear in the vertical inside a
+   cell); exner_c, rho_c: [nlev][ncol] cell values.  theta* must be single
+   valued on every facet for the hybridised solution to equal the mixed one. */
+int hyb_assemble_local(hyb_ctx *ctx, const double *theta_w, const double *exner_hat_w,
+                       const double *exner_c, const double *rho_c);
+
+/* Static condensation (Sec. 2.4).  With r_ub == NULL (first call after
+   hyb_assemble_local): factor every A_K, form S = C^T A^-1 K as an 11-point
+   stencil per trace row and set up the preconditioner (lumped mass, H on
+   every multigrid level, Gamma of Eq. of the scaling matrix).  With r_ub
+   given: B_lambda = C^T A^-1 R_X for R_X = (r_ub [6][nlev][ncol] broken
+   velocity residual, r_pi [nlev][ncol] pressure residual); b_lambda [ntrace]. */
+int hyb_condense(hyb_ctx *ctx, const double *r_ub, const double *r_pi, double *b_lambda);
+
+/* y = S x for trace vectors x, y [ntrace] (x and y must not alias). */
+int hyb_trace_apply(hyb_ctx *ctx, const double *x, double *y);
+
+/* z = M(r): one application of the two-level cycle (Alg. 2) from zero:
+   LineSmooth (n_pre), residual, restriction P^T scaled by Gamma, one pressure
+   multigrid V-cycle on H, prolongation by facet averaging, LineSmooth
+   (n_post).  r, z [ntrace], must not alias. */
+int hyb_precondition(hyb_ctx *ctx, const double *r, double *z);
+
+/* Flexible GMRES on S lambda = B_lambda, right preconditioned by Alg. 2.
+   lambda [ntrace] is the initial guess on entry and the solution on exit.
+   Stops when the FP64 relative residual ||B - S lambda|| / ||B|| <= rtol or
+   after maxit iterations.  Returns HYB_OK, HYB_NOT_CONVERGED, HYB_BREAKDOWN
+   or a negative error; info (may be NULL) gets iterations and residuals. */
+int hyb_solve(hyb_ctx *ctx, const double *b_lambda, double *lambda, double rtol, int32_t maxit,
+              hyb_info *info);
+
+/* Cellwise recovery X = A^-1 (R_X - K lambda) (Sec. 2.4): u_b [6][nlev][ncol]
+   outward fluxes of the broken velocity, pi [nlev][ncol] Exner pressure. */
+int hyb_recover(hyb_ctx *ctx, const double *r_ub, const double *r_pi, const double *lambda,
+                double *u_b, double *pi);
+
+/* Sizes of the trace system: ntrace, and the bytes of device workspace held. */
+int hyb_sizes(const hyb_ctx *ctx, int64_t *ntrace, int64_t *ncell, int64_t *workspace_bytes);
+
+/* Kernel timing with HIP events on the context's stream, for measurement.
+   hyb_profile(ctx, 1) clears the counters and starts recording every launch
+   of the named kernel families; hyb_profile(ctx, 0) stops.  hyb_profile_read
+   synchronises the stream and returns the number of launches and their total
+   duration in milliseconds for one family: "line_smooth" (sweeps from a
+   nonzero iterate), "line_smooth0" (first presmoothing sweep), "trace_apply",
+   "mg_smooth", "restrict", "prolong", "krylov", "cell_solve". */
+int hyb_profile(hyb_ctx *ctx, int32_t enable);
+int hyb_profile_read(hyb_ctx *ctx, const char *family, int64_t *launches, double *total_ms);
+
+const char *hyb_last_error(const hyb_ctx *ctx);
+void hyb_destroy(hyb_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HYB_H */

@@ -22,19 +22,38 @@ import scipy.sparse.linalg as spla
 from .mesh import BoxMesh
 
 
+def cell_trace_operator(loc):
+    """S_K = C_K^T [A_K^{-1} Khat_K]_u with Khat_K = [K_K; 0] (Eq. of S, one cell) -> (n, 6, 6)."""
+    n = loc["A"].shape[0]
+    Khat = np.zeros((n, 7, 6))
+    Khat[:, :6, :] = loc["K"]
+    AinvK = np.linalg.solve(loc["A"], Khat)
+    return np.einsum("caf,cag->cfg", loc["C"], AinvK[:, :6, :])
+
+
+def cell_rhs(loc, r_ub_cells, r_pi_cells):
+    """b_K = C_K^T [A_K^{-1} R_K]_u (Eq. of B_lambda, one cell) -> (n, 6) indexed by trace face."""
+    R = np.concatenate([r_ub_cells, r_pi_cells[:, None]], axis=1)
+    X = np.linalg.solve(loc["A"], R[:, :, None])[:, :, 0]
+    return np.einsum("caf,ca->cf", loc["C"], X[:, :6])
+
+
+def cell_recover(loc, lam_cells, r_ub_cells, r_pi_cells):
+    """X_K = A_K^{-1}(R_K - Khat_K lambda_K) (Eq. of the recovery) -> (u_b (n, 6), Pi (n,))."""
+    R = np.concatenate([r_ub_cells, r_pi_cells[:, None]], axis=1)
+    R[:, :6] -= np.einsum("caf,cf->ca", loc["K"], lam_cells)
+    X = np.linalg.solve(loc["A"], R[:, :, None])[:, :, 0]
+    return X[:, :6], X[:, 6]
+
+
 class HybridSystem:
     def __init__(self, mesh: BoxMesh, loc: dict):
         self.mesh = mesh
+        self.loc = loc
         self.A = loc["A"]
         self.Kc = loc["K"]
         self.Cc = loc["C"]
-        n = mesh.ncell
-        # Khat_K = [K_K; 0] (7 x 6); A_K^{-1} Khat_K for all cells
-        Khat = np.zeros((n, 7, 6))
-        Khat[:, :6, :] = self.Kc
-        self.AinvK = np.linalg.solve(self.A, Khat)  # (n, 7, 6)
-        # S_K = C_K^T [A_K^{-1} Khat_K]_u
-        self.S_cell = np.einsum("caf,cag->cfg", self.Cc, self.AinvK[:, :6, :])
+        self.S_cell = cell_trace_operator(loc)
         cf = mesh.cell_faces
         rows = np.repeat(cf[:, :, None], 6, axis=2).ravel()
         cols = np.repeat(cf[:, None, :], 6, axis=1).ravel()
@@ -43,20 +62,14 @@ class HybridSystem:
 
     def rhs(self, r_ub_cells, r_pi_cells):
         """B_lambda = C^T A^{-1} R_X."""
-        R = np.concatenate([r_ub_cells, r_pi_cells[:, None]], axis=1)
-        X = np.linalg.solve(self.A, R[:, :, None])[:, :, 0]
-        b = np.einsum("caf,ca->cf", self.Cc, X[:, :6])
+        b = cell_rhs(self.loc, r_ub_cells, r_pi_cells)
         B = np.zeros(self.mesh.ntrace)
         np.add.at(B, self.mesh.cell_faces.ravel(), b.ravel())
         return B
 
     def recover(self, lam, r_ub_cells, r_pi_cells):
         """X = A^{-1}(R_X - K lambda) -> (u_b (ncell, 6), Pi (ncell,))."""
-        lam_c = lam[self.mesh.cell_faces]  # (n, 6)
-        R = np.concatenate([r_ub_cells, r_pi_cells[:, None]], axis=1)
-        R[:, :6] -= np.einsum("caf,cf->ca", self.Kc, lam_c)
-        X = np.linalg.solve(self.A, R[:, :, None])[:, :, 0]
-        return X[:, :6], X[:, 6]
+        return cell_recover(self.loc, lam[self.mesh.cell_faces], r_ub_cells, r_pi_cells)
 
     def solve_direct(self, r_ub_cells, r_pi_cells):
         B = self.rhs(r_ub_cells, r_pi_cells)

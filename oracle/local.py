@@ -87,13 +87,14 @@ def face_rule(f):
     return s, t, c, w
 
 
-def cell_data(mesh: BoxMesh, prob):
-    """Per-cell geometry and reference-state values in the oracle's cell order."""
-    k = mesh.cell_layer
-    col = mesh.cell_iy * mesh.nx + mesh.cell_ix
+def cell_data(mesh: BoxMesh, prob, cells=None):
+    """Per-cell geometry and reference-state values in the oracle's cell order (or for ``cells``)."""
+    sel = slice(None) if cells is None else np.asarray(cells)
+    k = mesh.cell_layer[sel]
+    col = (mesh.cell_iy * mesh.nx + mesh.cell_ix)[sel]
     hz = mesh.dz[k]
-    hx = np.full(mesh.ncell, mesh.dx)
-    hy = np.full(mesh.ncell, mesh.dy)
+    hx = np.full(k.shape[0], mesh.dx)
+    hy = np.full(k.shape[0], mesh.dy)
     return dict(
         hx=hx,
         hy=hy,
@@ -107,8 +108,8 @@ def cell_data(mesh: BoxMesh, prob):
     )
 
 
-def local_matrices(mesh: BoxMesh, prob, chunk: int = 8192):
-    """Cell matrices of the hybridised system for every cell.
+def local_matrices(mesh: BoxMesh, prob, chunk: int = 8192, cells=None):
+    """Cell matrices of the hybridised system for every cell (or only for ``cells``).
 
     Returns a dict of arrays (leading axis = cell):
       A  (7,7): [[M2 - Q22, G^b], [Q32 + M3rho M3^-1 D, M3Pi]] (velocity dofs 0..5, pressure 6)
@@ -118,10 +119,10 @@ def local_matrices(mesh: BoxMesh, prob, chunk: int = 8192):
     and the separate blocks m2, q22, gb, d (the combined pressure row), q32,
     m3, m3rho, m3pi.
     """
-    cd = cell_data(mesh, prob)
+    cd = cell_data(mesh, prob, cells)
     dt, tu, tr, tt = prob.dt, prob.tau_u, prob.tau_rho, prob.tau_theta
     cp, kappa = prob.cp, prob.kappa
-    n = mesh.ncell
+    n = cd["hz"].shape[0]
     out = {key: np.zeros((n,) + shp) for key, shp in (
         ("A", (7, 7)), ("K", (6, 6)), ("C", (6, 6)), ("m2", (6, 6)), ("q22", (6, 6)),
         ("gb", (6,)), ("d", (6,)), ("q32", (6,)), ("m3", ()), ("m3rho", ()), ("m3pi", ()), ("thF", (6,)),

@@ -41,37 +41,48 @@ class BoxMesh:
         return self.n_zface + k * 2 * self.ncol + self.ncol + (iy % self.ny) * self.nx + (ix % self.nx)
 
     def _build(self):
-        L, nx, ny = self.nlev, self.nx, self.ny
-        faces = np.empty((self.ncell, 6), np.int64)
-        sign = np.empty((self.ncell, 6), np.float64)
-        layer = np.empty(self.ncell, np.int64)
-        cix = np.empty(self.ncell, np.int64)
-        ciy = np.empty(self.ncell, np.int64)
-        for k in range(L):
-            for iy in range(ny):
-                for ix in range(nx):
-                    c = k * self.ncol + iy * nx + ix
-                    faces[c] = (
-                        self.xface(k, ix, iy),
-                        self.xface(k, ix + 1, iy),
-                        self.yface(k, ix, iy),
-                        self.yface(k, ix, iy + 1),
-                        self.zface(k, ix, iy),
-                        self.zface(k + 1, ix, iy),
-                    )
-                    # the +x/+y/+z normal leaves the cell through E, N, T
-                    sign[c] = (-1.0, 1.0, -1.0, 1.0, -1.0, 1.0)
-                    layer[c], cix[c], ciy[c] = k, ix, iy
+        L, nx, ny, ncol = self.nlev, self.nx, self.ny, self.ncol
+        c = np.arange(self.ncell)
+        k = c // ncol
+        col = c % ncol
+        ix, iy = col % nx, col // nx
+        faces = np.stack(
+            [
+                self.xface(k, ix, iy),
+                self.xface(k, ix + 1, iy),
+                self.yface(k, ix, iy),
+                self.yface(k, ix, iy + 1),
+                self.zface(k, ix, iy),
+                self.zface(k + 1, ix, iy),
+            ],
+            axis=1,
+        ).astype(np.int64)
+        # the +x/+y/+z normal leaves the cell through E, N, T
+        sign = np.tile(np.array([-1.0, 1.0, -1.0, 1.0, -1.0, 1.0]), (self.ncell, 1))
         self.cell_faces = faces
         self.cell_sign = sign
-        self.cell_layer = layer
-        self.cell_ix = cix
-        self.cell_iy = ciy
+        self.cell_layer = k
+        self.cell_ix = ix
+        self.cell_iy = iy
         # a facet is on the rigid lid / ground when it is the bottom of layer 0 or the top of layer L-1
         bnd = np.zeros(self.ntrace, bool)
-        bnd[: self.ncol] = True
-        bnd[L * self.ncol : (L + 1) * self.ncol] = True
+        bnd[:ncol] = True
+        bnd[L * ncol : (L + 1) * ncol] = True
         self.boundary = bnd
+
+    def face_cells(self):
+        """For every trace facet the (cell, local face) pairs touching it: arrays (ntrace, 2), -1 if absent."""
+        flat = self.cell_faces.ravel()
+        order = np.argsort(flat, kind="stable")
+        fsorted = flat[order]
+        cells = np.full((self.ntrace, 2), -1, np.int64)
+        lfs = np.full((self.ntrace, 2), -1, np.int64)
+        first = np.ones(flat.shape[0], bool)
+        first[1:] = fsorted[1:] != fsorted[:-1]
+        slot = np.where(first, 0, 1)
+        cells[fsorted, slot] = order // 6
+        lfs[fsorted, slot] = order % 6
+        return cells, lfs
 
     def column_of_zface(self, f):
         return f % self.ncol

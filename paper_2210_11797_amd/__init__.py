@@ -1,0 +1,20 @@
+"""MI355X-native hybridised trace solver (HIP library + thin Python binding).
+
+The compute path lives in libhyb.so (C ABI in include/hyb.h); this package only marshals
+arguments to it.  Importing the package does not load the library; ``HybSolver`` does, and
+raises if it has not been built.
+"""
+
+from ._native import (  # noqa: F401
+    ABI_FUNCTIONS,
+    HYB_BREAKDOWN,
+    HYB_NOT_CONVERGED,
+    HYB_OK,
+    LIB_PATH,
+    PREC_FP64,
+    PREC_MIXED,
+    HybSolver,
+    Params,
+    levels_of,
+    load,
+)

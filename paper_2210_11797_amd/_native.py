@@ -1,0 +1,258 @@
+"""ctypes binding of libhyb.so (argument marshalling only; every step runs in the HIP library).
+
+The names mirror the C ABI of include/hyb.h.  Device arrays are torch CUDA tensors (FP64,
+contiguous); torch provides the memory and the stream, nothing else.  There is no fallback:
+if the library is missing or a call fails, an exception is raised.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, fields
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhyb.so")
+
+HYB_OK = 0
+HYB_NOT_CONVERGED = 1
+HYB_BREAKDOWN = 2
+PREC_FP64 = 0
+PREC_MIXED = 1
+
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_f64p = ctypes.POINTER(ctypes.c_double)
+
+
+class _Level(ctypes.Structure):
+    _fields_ = [("ncol", ctypes.c_int32), ("col_edge", _i32p), ("edge_col", _i32p), ("edge_lf", _i32p),
+                ("parent", _i32p)]
+
+
+class _Mesh(ctypes.Structure):
+    _fields_ = [("nlev", ctypes.c_int32), ("nlevels", ctypes.c_int32), ("levels", ctypes.POINTER(_Level)),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", _f64p)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("tau_u", ctypes.c_double), ("tau_rho", ctypes.c_double),
+                ("tau_theta", ctypes.c_double), ("cp", ctypes.c_double), ("rd", ctypes.c_double),
+                ("omega", ctypes.c_double), ("n_pre", ctypes.c_int32), ("n_post", ctypes.c_int32),
+                ("omega_p", ctypes.c_double), ("mg_pre", ctypes.c_int32), ("mg_post", ctypes.c_int32),
+                ("mg_coarse_sweeps", ctypes.c_int32), ("restart", ctypes.c_int32), ("precision", ctypes.c_int32)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("rel_res", ctypes.c_double), ("history", _f64p), ("history_cap", ctypes.c_int32),
+                ("history_len", ctypes.c_int32)]
+
+
+@dataclass
+class Params:
+    """Solver parameters; defaults are the paper's (Sec. 3.3): omega = 0.6 with 1 pre- and 2
+    post-smoothing sweeps, a 4-level pressure multigrid with omega_p = 0.9, 1 pre / 2 post sweeps."""
+
+    dt: float = 600.0
+    tau_u: float = 0.5
+    tau_rho: float = 0.5
+    tau_theta: float = 0.5
+    cp: float = 1005.0
+    rd: float = 287.05
+    omega: float = 0.6
+    n_pre: int = 1
+    n_post: int = 2
+    omega_p: float = 0.9
+    mg_pre: int = 1
+    mg_post: int = 2
+    mg_coarse_sweeps: int = 3
+    restart: int = 30
+    precision: int = PREC_FP64
+
+    def to_c(self) -> _Params:
+        return _Params(**{f.name: getattr(self, f.name) for f in fields(self)})
+
+
+ABI_FUNCTIONS = [
+    "hyb_create", "hyb_set_params", "hyb_assemble_local", "hyb_condense", "hyb_trace_apply",
+    "hyb_precondition", "hyb_solve", "hyb_recover", "hyb_sizes", "hyb_profile", "hyb_profile_read",
+    "hyb_last_error", "hyb_destroy",
+]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libhyb.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} (run paper_2210_11797_amd/build.py)")
+    lib = ctypes.CDLL(path)
+    vp = ctypes.c_void_p
+    lib.hyb_create.argtypes = [ctypes.POINTER(_Mesh), ctypes.POINTER(_Params), vp, ctypes.POINTER(vp)]
+    lib.hyb_set_params.argtypes = [vp, ctypes.POINTER(_Params)]
+    lib.hyb_assemble_local.argtypes = [vp, vp, vp, vp, vp]
+    lib.hyb_condense.argtypes = [vp, vp, vp, vp]
+    lib.hyb_trace_apply.argtypes = [vp, vp, vp]
+    lib.hyb_precondition.argtypes = [vp, vp, vp]
+    lib.hyb_solve.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(_Info)]
+    lib.hyb_recover.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.hyb_sizes.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                              ctypes.POINTER(ctypes.c_int64)]
+    lib.hyb_profile.argtypes = [vp, ctypes.c_int32]
+    lib.hyb_profile_read.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.POINTER(ctypes.c_double)]
+    lib.hyb_last_error.argtypes = [vp]
+    lib.hyb_last_error.restype = ctypes.c_char_p
+    lib.hyb_destroy.argtypes = [vp]
+    lib.hyb_destroy.restype = None
+    for name in ABI_FUNCTIONS:
+        if name not in ("hyb_last_error", "hyb_destroy"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(t, n=None, what="array"):
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what}: expected a CUDA tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{what}: expected a contiguous float64 tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{what}: expected {n} entries, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class HybSolver:
+    """One context of the C library for an extruded mesh and its multigrid hierarchy.
+
+    levels: list of dicts (fine to coarse) with ncol, col_edge [4, ncol], edge_col [2, 2ncol],
+    edge_lf [2, 2ncol] and, for coarse levels, parent [ncol of the finer level].
+    """
+
+    def __init__(self, nlev, levels, dx, dy, dz, params: Params | None = None, stream=None):
+        import torch
+
+        self.lib = load()
+        self.params = params or Params()
+        self.nlev = int(nlev)
+        self._keep = []
+        lv = (_Level * len(levels))()
+        for i, L in enumerate(levels):
+            arrs = {}
+            for key in ("col_edge", "edge_col", "edge_lf"):
+                a = np.ascontiguousarray(L[key], dtype=np.int32)
+                self._keep.append(a)
+                arrs[key] = a.ctypes.data_as(_i32p)
+            par = None
+            if L.get("parent") is not None:
+                a = np.ascontiguousarray(L["parent"], dtype=np.int32)
+                self._keep.append(a)
+                par = a.ctypes.data_as(_i32p)
+            lv[i] = _Level(int(L["ncol"]), arrs["col_edge"], arrs["edge_col"], arrs["edge_lf"], par)
+        dzh = np.ascontiguousarray(dz, dtype=np.float64)
+        self._keep += [lv, dzh]
+        mesh = _Mesh(self.nlev, len(levels), lv, float(dx), float(dy), dzh.ctypes.data_as(_f64p))
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        cp = self.params.to_c()
+        h = ctypes.c_void_p()
+        rc = self.lib.hyb_create(ctypes.byref(mesh), ctypes.byref(cp), ctypes.c_void_p(stream.cuda_stream),
+                                 ctypes.byref(h))
+        if rc != HYB_OK:
+            raise RuntimeError(f"hyb_create failed with code {rc}")
+        self.h = h
+        nt, nc, nb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        self.lib.hyb_sizes(self.h, ctypes.byref(nt), ctypes.byref(nc), ctypes.byref(nb))
+        self.ntrace, self.ncell = nt.value, nc.value
+        self.ncol = int(levels[0]["ncol"])
+
+    # -- helpers --
+    def _check(self, rc, what):
+        if rc < 0:
+            msg = self.lib.hyb_last_error(self.h).decode()
+            raise RuntimeError(f"{what} failed ({rc}): {msg}")
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.hyb_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self):
+        nb = ctypes.c_int64()
+        self.lib.hyb_sizes(self.h, None, None, ctypes.byref(nb))
+        return nb.value
+
+    # -- ABI calls --
+    def set_params(self, params: Params):
+        cp = params.to_c()
+        self._check(self.lib.hyb_set_params(self.h, ctypes.byref(cp)), "hyb_set_params")
+        self.params = params
+
+    def assemble_local(self, theta_w, exner_hat_w, exner_c, rho_c):
+        nw, nc = (self.nlev + 1) * self.ncol, self.ncell
+        self._check(self.lib.hyb_assemble_local(self.h, _ptr(theta_w, nw, "theta_w"),
+                                                _ptr(exner_hat_w, nw, "exner_hat_w"),
+                                                _ptr(exner_c, nc, "exner_c"), _ptr(rho_c, nc, "rho_c")),
+                    "hyb_assemble_local")
+
+    def condense(self, r_ub=None, r_pi=None, b_lambda=None):
+        if r_ub is None:
+            self._check(self.lib.hyb_condense(self.h, None, None, None), "hyb_condense")
+            return
+        self._check(self.lib.hyb_condense(self.h, _ptr(r_ub, 6 * self.ncell, "r_ub"), _ptr(r_pi, self.ncell, "r_pi"),
+                                          _ptr(b_lambda, self.ntrace, "b_lambda")), "hyb_condense")
+
+    def trace_apply(self, x, y):
+        self._check(self.lib.hyb_trace_apply(self.h, _ptr(x, self.ntrace, "x"), _ptr(y, self.ntrace, "y")),
+                    "hyb_trace_apply")
+
+    def precondition(self, r, z):
+        self._check(self.lib.hyb_precondition(self.h, _ptr(r, self.ntrace, "r"), _ptr(z, self.ntrace, "z")),
+                    "hyb_precondition")
+
+    def solve(self, b_lambda, lam, rtol=1e-8, maxit=500, history=256):
+        hist = (ctypes.c_double * max(1, history))()
+        info = _Info(0, 0, 0, 0.0, ctypes.cast(hist, _f64p), history, 0)
+        rc = self._check(self.lib.hyb_solve(self.h, _ptr(b_lambda, self.ntrace, "b_lambda"),
+                                            _ptr(lam, self.ntrace, "lambda"), float(rtol), int(maxit),
+                                            ctypes.byref(info)), "hyb_solve")
+        return dict(status=rc, iters=info.iters, restarts=info.restarts, rel_res=info.rel_res,
+                    history=[hist[i] for i in range(info.history_len)])
+
+    def recover(self, r_ub, r_pi, lam, u_b, pi):
+        self._check(self.lib.hyb_recover(self.h, _ptr(r_ub, 6 * self.ncell, "r_ub"), _ptr(r_pi, self.ncell, "r_pi"),
+                                         _ptr(lam, self.ntrace, "lambda"), _ptr(u_b, 6 * self.ncell, "u_b"),
+                                         _ptr(pi, self.ncell, "pi")), "hyb_recover")
+
+    def profile(self, enable: bool):
+        self._check(self.lib.hyb_profile(self.h, 1 if enable else 0), "hyb_profile")
+
+    def profile_read(self, family: str):
+        n, ms = ctypes.c_int64(), ctypes.c_double()
+        self._check(self.lib.hyb_profile_read(self.h, family.encode(), ctypes.byref(n), ctypes.byref(ms)),
+                    "hyb_profile_read")
+        return n.value, ms.value
+
+
+def levels_of(prob):
+    """Mesh hierarchy of a synthetic box problem as the dicts HybSolver takes."""
+    out = []
+    for i, L in enumerate(prob.levels):
+        out.append(dict(ncol=L.ncol, col_edge=L.col_edge, edge_col=L.edge_col, edge_lf=L.edge_lf,
+                        parent=None if i == 0 else L.parent))
+    return out

@@ -1,0 +1,558 @@
+// C ABI of the hybridised trace solver: context management, the setup sequence and the flexible
+// GMRES outer loop (host-driven; every vector operation runs in the kernels of this library).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "hyb_internal.h"
+
+using namespace hyb;
+
+namespace hyb {
+int reduction_blocks();
+}
+
+namespace {
+
+const char *kFamilyNames[F_COUNT] = {"line_smooth", "line_smooth0", "trace_apply", "mg_smooth",
+                                     "restrict",    "prolong",      "krylov",      "cell_solve"};
+
+int fail(hyb_ctx *c, int code, const std::string &msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int hipfail(hyb_ctx *c, hipError_t e, const char *where) {
+  return fail(c, HYB_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define CHECK_HIP(expr, where)                  \
+  do {                                          \
+    hipError_t e_ = (expr);                     \
+    if (e_ != hipSuccess) return hipfail(c, e_, where); \
+  } while (0)
+
+template <typename T>
+int dalloc(hyb_ctx *c, T **p, size_t count) {
+  if (*p) return HYB_OK;
+  size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  hipError_t e = hipMalloc((void **)p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(c, HYB_ENOMEM, std::string("hipMalloc of ") + std::to_string(bytes) + " bytes failed");
+  }
+  c->bytes += bytes;
+  return HYB_OK;
+}
+
+template <typename T>
+void dfree(T *&p) {
+  if (p) (void)hipFree((void *)p);
+  p = nullptr;
+}
+
+int upload(hyb_ctx *c, int32_t **dst, const std::vector<int32_t> &v) {
+  int rc = dalloc(c, dst, v.size());
+  if (rc) return rc;
+  CHECK_HIP(hipMemcpy(*dst, v.data(), v.size() * sizeof(int32_t), hipMemcpyHostToDevice), "upload table");
+  return HYB_OK;
+}
+
+int check_params(hyb_ctx *c, const hyb_params *p) {
+  if (!p) return fail(c, HYB_EINVAL, "params is NULL");
+  if (!(p->omega > 0) || !(p->omega_p > 0)) return fail(c, HYB_EINVAL, "omega and omega_p must be positive");
+  if (p->n_pre < 0 || p->n_post < 0 || p->mg_pre < 0 || p->mg_post < 0 || p->mg_coarse_sweeps < 1)
+    return fail(c, HYB_EINVAL, "sweep counts must be >= 0 (coarse sweeps >= 1)");
+  if (p->restart < 1 || p->restart > 200) return fail(c, HYB_EINVAL, "restart must be in [1, 200]");
+  if (p->precision != HYB_PREC_FP64 && p->precision != HYB_PREC_MIXED)
+    return fail(c, HYB_EINVAL, "unknown precision mode");
+  return HYB_OK;
+}
+
+// Host-side checks and derived tables of one level.
+int setup_level(hyb_ctx *c, const hyb_mesh *mesh, int l) {
+  const hyb_level &hl = mesh->levels[l];
+  LevelDev &L = c->lv[l];
+  int ncol = hl.ncol, nedge = 2 * hl.ncol;
+  if (ncol < 1 || !hl.col_edge || !hl.edge_col || !hl.edge_lf) return fail(c, HYB_EINVAL, "level tables missing");
+  L.ncol = ncol;
+  L.nedge = nedge;
+  std::vector<int32_t> ce(hl.col_edge, hl.col_edge + 4 * (size_t)ncol);
+  std::vector<int32_t> ec(hl.edge_col, hl.edge_col + 2 * (size_t)nedge);
+  std::vector<int32_t> el(hl.edge_lf, hl.edge_lf + 2 * (size_t)nedge);
+  for (int e = 0; e < nedge; ++e) {
+    for (int s = 0; s < 2; ++s) {
+      int col = ec[(size_t)s * nedge + e], f = el[(size_t)s * nedge + e];
+      if (col < 0 || col >= ncol || f < 0 || f > 3) return fail(c, HYB_EINVAL, "edge table out of range");
+      if (ce[(size_t)f * ncol + col] != e) return fail(c, HYB_EINVAL, "col_edge / edge_col / edge_lf disagree");
+    }
+    if (ec[e] == ec[(size_t)nedge + e]) return fail(c, HYB_EINVAL, "an edge joins a column to itself");
+  }
+  std::vector<int32_t> nbr(4 * (size_t)ncol), nlf(4 * (size_t)ncol), own(4 * (size_t)ncol, -1);
+  std::vector<int> nown(ncol, 0);
+  for (int col = 0; col < ncol; ++col)
+    for (int f = 0; f < 4; ++f) {
+      int e = ce[(size_t)f * ncol + col];
+      if (e < 0 || e >= nedge) return fail(c, HYB_EINVAL, "col_edge out of range");
+      int side = (ec[e] == col && el[e] == f) ? 0 : 1;
+      if (ec[(size_t)side * nedge + e] != col || el[(size_t)side * nedge + e] != f)
+        return fail(c, HYB_EINVAL, "column face not found on its edge");
+      nbr[(size_t)f * ncol + col] = ec[(size_t)(1 - side) * nedge + e];
+      nlf[(size_t)f * ncol + col] = el[(size_t)(1 - side) * nedge + e];
+    }
+  for (int e = 0; e < nedge; ++e) {
+    int c1 = ec[(size_t)nedge + e];
+    own[(size_t)nown[c1] * ncol + c1] = e;  // at most 4 edges enter a column
+    nown[c1]++;
+  }
+  std::vector<int32_t> est(8 * (size_t)nedge);
+  for (int e = 0; e < nedge; ++e) {
+    int c0 = ec[e], c1 = ec[(size_t)nedge + e], l0 = el[e], l1 = el[(size_t)nedge + e];
+    est[e] = c0;
+    est[(size_t)nedge + e] = c1;
+    int j0 = 2, j1 = 5;
+    for (int f = 0; f < 4; ++f) {
+      if (f != l0) est[(size_t)(j0++) * nedge + e] = ce[(size_t)f * ncol + c0];
+      if (f != l1) est[(size_t)(j1++) * nedge + e] = ce[(size_t)f * ncol + c1];
+    }
+  }
+  int rc;
+  if ((rc = upload(c, &L.col_edge, ce)) || (rc = upload(c, &L.edge_col, ec)) || (rc = upload(c, &L.edge_lf, el)) ||
+      (rc = upload(c, &L.nbr, nbr)) || (rc = upload(c, &L.nlf, nlf)))
+    return rc;
+  if (l == 0) {
+    if ((rc = upload(c, &L.own, own)) || (rc = upload(c, &L.est, est))) return rc;
+  }
+  if (l > 0) {
+    const hyb_level &fine = mesh->levels[l - 1];
+    if (!hl.parent) return fail(c, HYB_EINVAL, "coarse level without parent map");
+    std::vector<int32_t> par(hl.parent, hl.parent + fine.ncol);
+    std::vector<int32_t> ch(4 * (size_t)ncol, -1);
+    std::vector<int> cnt(ncol, 0);
+    for (int fc = 0; fc < fine.ncol; ++fc) {
+      int P = par[fc];
+      if (P < 0 || P >= ncol || cnt[P] >= 4) return fail(c, HYB_EINVAL, "every coarse column needs 4 children");
+      ch[(size_t)cnt[P] * ncol + P] = fc;
+      cnt[P]++;
+    }
+    for (int P = 0; P < ncol; ++P)
+      if (cnt[P] != 4) return fail(c, HYB_EINVAL, "every coarse column needs 4 children");
+    if ((rc = upload(c, &L.children, ch)) || (rc = upload(c, &c->lv[l - 1].parent, par))) return rc;
+  }
+  size_t n = (size_t)ncol * c->nlev;
+  if ((rc = dalloc(c, &L.H, 7 * n)) || (rc = dalloc(c, &L.Hf, 7 * n))) return rc;
+  double **vecs[3] = {(double **)&L.b, (double **)&L.x, (double **)&L.y};
+  for (auto v : vecs)
+    if ((rc = dalloc(c, v, n))) return rc;
+  return HYB_OK;
+}
+
+void free_all(hyb_ctx *c) {
+  for (auto &L : c->lv) {
+    dfree(L.col_edge), dfree(L.edge_col), dfree(L.edge_lf), dfree(L.nbr), dfree(L.nlf), dfree(L.own);
+    dfree(L.est), dfree(L.parent), dfree(L.children), dfree(L.H), dfree(L.Hf);
+    dfree(L.b), dfree(L.x), dfree(L.y);
+  }
+  dfree(c->dz_d), dfree(c->A), dfree(c->LU), dfree(c->kv), dfree(c->Scell), dfree(c->bcell);
+  dfree(c->S), dfree(c->Sf), dfree(c->m2l), dfree(c->gamma), dfree(c->gammaf);
+  dfree(c->tIn), dfree(c->tA), dfree(c->tB), dfree(c->tR), dfree(c->t64);
+  dfree(c->V), dfree(c->Z), dfree(c->partial), dfree(c->hdev);
+  if (c->hhost) (void)hipHostFree(c->hhost);
+  c->hhost = nullptr;
+  for (auto &f : c->fam)
+    for (auto ev : f.ev) (void)hipEventDestroy(ev);
+  c->fam.clear();
+}
+
+int alloc_krylov(hyb_ctx *c) {
+  int m = c->p.restart;
+  if (c->V && c->m == m) return HYB_OK;
+  dfree(c->V), dfree(c->Z), dfree(c->partial), dfree(c->hdev);
+  if (c->hhost) (void)hipHostFree(c->hhost);
+  c->hhost = nullptr;
+  c->m = m;
+  size_t n = (size_t)c->ntrace;
+  int rc;
+  c->nblk_red = reduction_blocks();
+  if ((rc = dalloc(c, &c->V, (size_t)(m + 1) * n)) || (rc = dalloc(c, (double **)&c->Z, (size_t)m * n)) ||
+      (rc = dalloc(c, &c->partial, (size_t)c->nblk_red * (m + 2))) || (rc = dalloc(c, &c->hdev, 4 * (size_t)(m + 2))))
+    return rc;
+  CHECK_HIP(hipHostMalloc((void **)&c->hhost, 4 * (size_t)(m + 2) * sizeof(double), hipHostMallocDefault),
+            "hipHostMalloc");
+  return HYB_OK;
+}
+
+}  // namespace
+
+namespace hyb {
+
+int prof_begin(hyb_ctx *c, int fam) {
+  if (!c->prof) return -1;
+  ProfFamily &f = c->fam[fam];
+  if (f.used + 2 > f.ev.size()) {
+    for (int i = 0; i < 64; ++i) {
+      hipEvent_t ev;
+      if (hipEventCreate(&ev) != hipSuccess) return -1;
+      f.ev.push_back(ev);
+    }
+  }
+  int slot = (int)f.used;
+  f.used += 2;
+  (void)hipEventRecord(f.ev[slot], c->stream);
+  return slot;
+}
+
+void prof_end(hyb_ctx *c, int fam, int slot) {
+  if (slot < 0) return;
+  (void)hipEventRecord(c->fam[fam].ev[slot + 1], c->stream);
+}
+
+}  // namespace hyb
+
+extern "C" {
+
+int hyb_create(const hyb_mesh *mesh, const hyb_params *params, void *stream, hyb_ctx **out) {
+  if (!out) return HYB_EINVAL;
+  *out = nullptr;
+  hyb_ctx *c = new (std::nothrow) hyb_ctx();
+  if (!c) return HYB_ENOMEM;
+  int rc = check_params(c, params);
+  if (rc) {
+    delete c;
+    return rc;
+  }
+  if (!mesh || mesh->nlev < 1 || mesh->nlevels < 1 || !mesh->levels || !mesh->dz || !(mesh->dx > 0) ||
+      !(mesh->dy > 0)) {
+    delete c;
+    return HYB_EINVAL;
+  }
+  c->p = *params;
+  c->stream = (hipStream_t)stream;
+  c->nlev = mesh->nlev;
+  c->nlevels = mesh->nlevels;
+  c->ncol = mesh->levels[0].ncol;
+  c->nedge = 2 * c->ncol;
+  c->ncell = c->nlev * c->ncol;
+  c->nz = (c->nlev + 1) * c->ncol;
+  c->ntrace = c->nz + c->nlev * c->nedge;
+  c->dx = mesh->dx;
+  c->dy = mesh->dy;
+  c->dz.assign(mesh->dz, mesh->dz + c->nlev);
+  for (double d : c->dz)
+    if (!(d > 0)) {
+      delete c;
+      return HYB_EINVAL;
+    }
+  if ((size_t)c->ntrace * 11 > (size_t)INT64_MAX / 8) {
+    delete c;
+    return HYB_EINVAL;
+  }
+  if ((size_t)2 * sizeof(double) * (c->nlev + 1) * kColBlock > 160 * 1024) {
+    delete c;
+    return HYB_EINVAL;  // column coefficients must fit in the 160 KiB LDS of a CU
+  }
+  if (configure_kernels(c->nlev) != hipSuccess) {
+    delete c;
+    return HYB_EHIP;
+  }
+  c->fam.resize(F_COUNT);
+  for (int i = 0; i < F_COUNT; ++i) c->fam[i].name = kFamilyNames[i];
+  c->lv.resize(c->nlevels);
+  for (int l = 0; l < c->nlevels && rc == HYB_OK; ++l) rc = setup_level(c, mesh, l);
+  if (rc == HYB_OK) {
+    rc = dalloc(c, &c->dz_d, c->nlev);
+    if (rc == HYB_OK && hipMemcpy(c->dz_d, c->dz.data(), c->nlev * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+      rc = HYB_EHIP;
+  }
+  if (rc != HYB_OK) {
+    fprintf(stderr, "hyb_create: %s\n", c->err.c_str());
+    free_all(c);
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return HYB_OK;
+}
+
+int hyb_set_params(hyb_ctx *c, const hyb_params *params) {
+  if (!c) return HYB_EINVAL;
+  int rc = check_params(c, params);
+  if (rc) return rc;
+  bool prec_change = params->precision != c->p.precision;
+  c->p = *params;
+  if (prec_change && c->condensed && c->p.precision == HYB_PREC_MIXED) {
+    // FP32 copies are made at condensation; refresh them for the new mode
+    CHECK_HIP(launch_to_float(c, c->S, c->Sf, (size_t)11 * c->ntrace), "to_float S");
+    CHECK_HIP(launch_to_float(c, c->gamma, c->gammaf, (size_t)c->ncell), "to_float gamma");
+    for (int l = 0; l < c->nlevels; ++l)
+      CHECK_HIP(launch_to_float(c, c->lv[l].H, c->lv[l].Hf, (size_t)7 * c->nlev * c->lv[l].ncol), "to_float H");
+  }
+  return alloc_krylov(c);
+}
+
+int hyb_assemble_local(hyb_ctx *c, const double *theta_w, const double *exner_hat_w, const double *exner_c,
+                       const double *rho_c) {
+  if (!c) return HYB_EINVAL;
+  if (!theta_w || !exner_hat_w || !exner_c || !rho_c) return fail(c, HYB_EINVAL, "null field");
+  int rc;
+  if ((rc = dalloc(c, &c->A, (size_t)49 * c->ncell)) || (rc = dalloc(c, &c->kv, (size_t)6 * c->ncell))) return rc;
+  CHECK_HIP(launch_assemble_box(c, theta_w, exner_hat_w, exner_c, rho_c), "assemble_local");
+  c->assembled = true;
+  c->condensed = false;
+  return HYB_OK;
+}
+
+int hyb_condense(hyb_ctx *c, const double *r_ub, const double *r_pi, double *b_lambda) {
+  if (!c) return HYB_EINVAL;
+  if (!c->assembled) return fail(c, HYB_ESTATE, "condense before assemble_local");
+  int rc;
+  if (r_ub == nullptr) {
+    size_t ntr = (size_t)c->ntrace, nc = (size_t)c->ncell;
+    if ((rc = dalloc(c, &c->LU, 49 * nc)) || (rc = dalloc(c, &c->Scell, 36 * nc)) || (rc = dalloc(c, &c->S, 11 * ntr)) ||
+        (rc = dalloc(c, &c->Sf, 11 * ntr)) || (rc = dalloc(c, &c->m2l, ntr)) || (rc = dalloc(c, &c->gamma, nc)) ||
+        (rc = dalloc(c, &c->gammaf, nc)) || (rc = dalloc(c, &c->bcell, 6 * nc)) ||
+        (rc = dalloc(c, (double **)&c->tIn, ntr)) || (rc = dalloc(c, (double **)&c->tA, ntr)) ||
+        (rc = dalloc(c, (double **)&c->tB, ntr)) || (rc = dalloc(c, (double **)&c->tR, ntr)) ||
+        (rc = dalloc(c, &c->t64, ntr)))
+      return rc;
+    if ((rc = alloc_krylov(c))) return rc;
+    CHECK_HIP(launch_factor_cells(c), "factor_cells");
+    CHECK_HIP(launch_build_stencil(c), "build_stencil");
+    CHECK_HIP(launch_lumped_mass(c), "lumped_mass");
+    CHECK_HIP(launch_pressure_stencil(c), "pressure_stencil");
+    for (int l = 1; l < c->nlevels; ++l) CHECK_HIP(launch_galerkin(c, l), "galerkin");
+    CHECK_HIP(launch_gamma(c), "gamma");
+    CHECK_HIP(launch_to_float(c, c->S, c->Sf, 11 * ntr), "to_float S");
+    CHECK_HIP(launch_to_float(c, c->gamma, c->gammaf, nc), "to_float gamma");
+    for (int l = 0; l < c->nlevels; ++l)
+      CHECK_HIP(launch_to_float(c, c->lv[l].H, c->lv[l].Hf, (size_t)7 * c->nlev * c->lv[l].ncol), "to_float H");
+    CHECK_HIP(hipStreamSynchronize(c->stream), "condense sync");
+    dfree(c->Scell);
+    c->condensed = true;
+    return HYB_OK;
+  }
+  if (!c->condensed) return fail(c, HYB_ESTATE, "condense the operator (r_ub = NULL) first");
+  if (!r_pi || !b_lambda) return fail(c, HYB_EINVAL, "null argument");
+  CHECK_HIP(launch_cell_rhs(c, r_ub, r_pi, b_lambda), "condense rhs");
+  return HYB_OK;
+}
+
+int hyb_trace_apply(hyb_ctx *c, const double *x, double *y) {
+  if (!c) return HYB_EINVAL;
+  if (!c->condensed) return fail(c, HYB_ESTATE, "trace_apply before condense");
+  if (!x || !y || x == y) return fail(c, HYB_EINVAL, "bad vectors");
+  CHECK_HIP((launch_trace_apply<double, double, double>(c, c->S, x, nullptr, y, 0)), "trace_apply");
+  return HYB_OK;
+}
+
+int hyb_precondition(hyb_ctx *c, const double *r, double *z) {
+  if (!c) return HYB_EINVAL;
+  if (!c->condensed) return fail(c, HYB_ESTATE, "precondition before condense");
+  if (!r || !z || r == z) return fail(c, HYB_EINVAL, "bad vectors");
+  if (c->p.precision == HYB_PREC_FP64) {
+    CHECK_HIP(precondition<double>(c, r, z), "precondition");
+  } else {
+    size_t n = (size_t)c->ntrace;
+    float *rf = (float *)c->tIn;
+    float *zf = (float *)c->Z;  // first basis slot as scratch
+    CHECK_HIP(launch_convert(c, r, rf, n), "convert");
+    CHECK_HIP(precondition<float>(c, rf, zf), "precondition");
+    CHECK_HIP(launch_copy_widen(c, zf, z, n), "widen");
+  }
+  return HYB_OK;
+}
+
+int hyb_solve(hyb_ctx *c, const double *b, double *lam, double rtol, int32_t maxit, hyb_info *info) {
+  if (!c) return HYB_EINVAL;
+  if (!c->condensed) return fail(c, HYB_ESTATE, "solve before condense");
+  if (!b || !lam || b == lam || !(rtol >= 0) || maxit < 0) return fail(c, HYB_EINVAL, "bad solve arguments");
+  int rc = alloc_krylov(c);
+  if (rc) return rc;
+  const size_t n = (size_t)c->ntrace;
+  const int m = c->m;
+  const bool mixed = c->p.precision == HYB_PREC_MIXED;
+  double *V = c->V;
+  double *h1 = c->hdev, *h2 = c->hdev + (m + 2), *nrm = c->hdev + 2 * (m + 2);
+  double *hh = c->hhost;
+  std::vector<double> R((size_t)(m + 1) * m, 0.0), g(m + 1), cs(m), sn(m), y(m);
+  if (info) {
+    info->iters = 0, info->restarts = 0, info->history_len = 0, info->rel_res = 0, info->status = HYB_OK;
+  }
+  // ||b||
+  CHECK_HIP(launch_multidot(c, b, 0, 0, b, n, nrm, true), "norm b");
+  CHECK_HIP(hipMemcpyAsync(hh, nrm, sizeof(double), hipMemcpyDeviceToHost, c->stream), "d2h");
+  CHECK_HIP(hipStreamSynchronize(c->stream), "sync");
+  double bnorm = std::sqrt(hh[0]);
+  if (!std::isfinite(bnorm)) return fail(c, HYB_EINVAL, "right-hand side is not finite");
+  if (bnorm == 0.0) {
+    CHECK_HIP(launch_fill(c, lam, n, 0.0), "zero");
+    return HYB_OK;
+  }
+  int its = 0, restarts = 0, status = HYB_NOT_CONVERGED;
+  double rel = 0.0;
+  for (;;) {
+    // true residual r = b - S lam into V_0
+    CHECK_HIP((launch_trace_apply<double, double, double>(c, c->S, lam, b, V, 1)), "residual");
+    CHECK_HIP(launch_multidot(c, V, 0, 0, V, n, nrm, true), "norm r");
+    CHECK_HIP(hipMemcpyAsync(hh, nrm, sizeof(double), hipMemcpyDeviceToHost, c->stream), "d2h");
+    CHECK_HIP(hipStreamSynchronize(c->stream), "sync");
+    double beta = std::sqrt(hh[0]);
+    rel = beta / bnorm;
+    if (!std::isfinite(rel)) {
+      status = HYB_BREAKDOWN;
+      break;
+    }
+    if (rel <= rtol) {
+      status = HYB_OK;
+      break;
+    }
+    if (its >= maxit) break;
+    if (its > 0) restarts++;
+    CHECK_HIP(launch_scale(c, V, n, 1.0 / beta), "scale");
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int jend = 0;
+    bool breakdown = false;
+    for (int j = 0; j < m; ++j) {
+      double *vj = V + (size_t)j * n, *w = V + (size_t)(j + 1) * n;
+      if (mixed) {
+        float *zf = (float *)c->Z + (size_t)j * n;
+        CHECK_HIP(launch_convert(c, vj, (float *)c->tIn, n), "convert");
+        CHECK_HIP(precondition<float>(c, (const float *)c->tIn, zf), "precondition");
+        CHECK_HIP((launch_trace_apply<double, float, double>(c, c->S, zf, nullptr, w, 0)), "matvec");
+      } else {
+        double *zj = (double *)c->Z + (size_t)j * n;
+        CHECK_HIP(precondition<double>(c, vj, zj), "precondition");
+        CHECK_HIP((launch_trace_apply<double, double, double>(c, c->S, zj, nullptr, w, 0)), "matvec");
+      }
+      // classical Gram-Schmidt with one reorthogonalisation
+      CHECK_HIP(launch_multidot(c, V, n, j + 1, w, n, h1, false), "cgs1");
+      CHECK_HIP(launch_multi_axpy_dev(c, V, n, j + 1, h1, w, n), "cgs1 update");
+      CHECK_HIP(launch_multidot(c, V, n, j + 1, w, n, h2, false), "cgs2");
+      CHECK_HIP(launch_multi_axpy_dev(c, V, n, j + 1, h2, w, n), "cgs2 update");
+      CHECK_HIP(launch_multidot(c, V, 0, 0, w, n, nrm, true), "norm w");
+      CHECK_HIP(hipMemcpyAsync(hh, c->hdev, 3 * (size_t)(m + 2) * sizeof(double), hipMemcpyDeviceToHost, c->stream),
+                "d2h");
+      CHECK_HIP(hipStreamSynchronize(c->stream), "sync");
+      double *col = &R[(size_t)j * (m + 1)];
+      for (int i = 0; i <= j; ++i) col[i] = hh[i] + hh[(m + 2) + i];
+      double hn = std::sqrt(hh[2 * (m + 2)]);
+      col[j + 1] = hn;
+      for (int i = 0; i < j; ++i) {
+        double a = col[i], bb = col[i + 1];
+        col[i] = cs[i] * a + sn[i] * bb;
+        col[i + 1] = -sn[i] * a + cs[i] * bb;
+      }
+      double a = col[j], bb = col[j + 1];
+      double rr = std::hypot(a, bb);
+      if (!(rr > 0) || !std::isfinite(rr)) {
+        breakdown = true;
+        jend = j;
+        break;
+      }
+      cs[j] = a / rr;
+      sn[j] = bb / rr;
+      col[j] = rr;
+      col[j + 1] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      its++;
+      jend = j + 1;
+      double est = std::fabs(g[j + 1]) / bnorm;
+      if (info && info->history && info->history_len < info->history_cap) info->history[info->history_len++] = est;
+      if (!std::isfinite(est)) {
+        breakdown = true;
+        break;
+      }
+      if (est <= rtol || its >= maxit || hn == 0.0) break;
+      CHECK_HIP(launch_scale(c, w, n, 1.0 / hn), "scale");
+    }
+    if (jend > 0) {
+      for (int i = jend - 1; i >= 0; --i) {
+        double s = g[i];
+        for (int k = i + 1; k < jend; ++k) s -= R[(size_t)k * (m + 1) + i] * y[k];
+        y[i] = s / R[(size_t)i * (m + 1) + i];
+      }
+      // y goes to the device through the pinned buffer (after the last sync the buffer is free)
+      std::copy(y.begin(), y.begin() + jend, hh + 3 * (m + 2));
+      double *ydev = c->hdev + 3 * (m + 2);
+      CHECK_HIP(hipMemcpyAsync(ydev, hh + 3 * (m + 2), jend * sizeof(double), hipMemcpyHostToDevice, c->stream),
+                "h2d");
+      if (mixed)
+        CHECK_HIP(launch_update_solution<float>(c, (const float *)c->Z, n, jend, ydev, lam, n), "update");
+      else
+        CHECK_HIP(launch_update_solution<double>(c, (const double *)c->Z, n, jend, ydev, lam, n), "update");
+      CHECK_HIP(hipStreamSynchronize(c->stream), "sync");
+    }
+    if (breakdown && jend == 0) {
+      status = HYB_BREAKDOWN;
+      break;
+    }
+  }
+  if (info) {
+    info->iters = its;
+    info->restarts = restarts;
+    info->rel_res = rel;
+    info->status = status;
+  }
+  return status;
+}
+
+int hyb_recover(hyb_ctx *c, const double *r_ub, const double *r_pi, const double *lambda, double *u_b, double *pi) {
+  if (!c) return HYB_EINVAL;
+  if (!c->condensed) return fail(c, HYB_ESTATE, "recover before condense");
+  if (!r_ub || !r_pi || !lambda || !u_b || !pi) return fail(c, HYB_EINVAL, "null argument");
+  CHECK_HIP(launch_recover(c, r_ub, r_pi, lambda, u_b, pi), "recover");
+  return HYB_OK;
+}
+
+int hyb_sizes(const hyb_ctx *c, int64_t *ntrace, int64_t *ncell, int64_t *bytes) {
+  if (!c) return HYB_EINVAL;
+  if (ntrace) *ntrace = c->ntrace;
+  if (ncell) *ncell = c->ncell;
+  if (bytes) *bytes = (int64_t)c->bytes;
+  return HYB_OK;
+}
+
+int hyb_profile(hyb_ctx *c, int32_t enable) {
+  if (!c) return HYB_EINVAL;
+  CHECK_HIP(hipStreamSynchronize(c->stream), "profile sync");
+  for (auto &f : c->fam) f.used = 0;
+  c->prof = enable != 0;
+  return HYB_OK;
+}
+
+int hyb_profile_read(hyb_ctx *c, const char *family, int64_t *launches, double *total_ms) {
+  if (!c || !family) return HYB_EINVAL;
+  CHECK_HIP(hipStreamSynchronize(c->stream), "profile sync");
+  for (auto &f : c->fam) {
+    if (f.name != family) continue;
+    double tot = 0.0;
+    for (size_t i = 0; i + 1 < f.used; i += 2) {
+      float ms = 0.f;
+      CHECK_HIP(hipEventElapsedTime(&ms, f.ev[i], f.ev[i + 1]), "event elapsed");
+      tot += ms;
+    }
+    if (launches) *launches = (int64_t)(f.used / 2);
+    if (total_ms) *total_ms = tot;
+    return HYB_OK;
+  }
+  return fail(c, HYB_EINVAL, std::string("unknown kernel family ") + family);
+}
+
+const char *hyb_last_error(const hyb_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+void hyb_destroy(hyb_ctx *c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  free_all(c);
+  delete c;
+}
+
+}  // extern "C"

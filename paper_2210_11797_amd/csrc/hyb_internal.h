@@ -1,0 +1,144 @@
+// Internal declarations of the hybridised trace solver library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hyb.h"
+
+namespace hyb {
+
+// ---------------------------------------------------------------------------------------------
+// Device-side mesh description of one multigrid level.
+//   col_edge[f][col]: edge of local face f (0..3 = W,E,S,N)
+//   nbr[f][col]:      column across local face f
+//   nlf[f][col]:      local face index of that edge inside the neighbour column
+//   own[j][col]:      edges whose normal enters this column (the column that owns the
+//                     trace rows of the edge), -1 padded, j = 0..3
+//   est[i][e]:        row neighbours of edge e: columns c0, c1 and the other three edges of each
+//   parent[col]:      coarse column (next level) of this column; children[q][ccol] the reverse
+// ---------------------------------------------------------------------------------------------
+struct LevelDev {
+  int ncol = 0, nedge = 0;
+  int32_t *col_edge = nullptr, *edge_col = nullptr, *edge_lf = nullptr;
+  int32_t *nbr = nullptr, *nlf = nullptr, *own = nullptr;
+  int32_t *est = nullptr;       // [8][nedge]: c0, c1, other 3 edges of c0, other 3 edges of c1
+  int32_t *parent = nullptr;    // [ncol] -> column of level l+1 (nullptr on the coarsest level)
+  int32_t *children = nullptr;  // [4][ncol] -> columns of level l-1 (nullptr on level 0)
+  double *H = nullptr;          // [7][nlev*ncol] pressure stencil: diag, W, E, S, N, below, above
+  float *Hf = nullptr;          // FP32 copy
+  void *b = nullptr, *x = nullptr, *y = nullptr;  // [nlev*ncol] work vectors in preconditioner precision
+};
+
+struct ProfFamily {
+  std::string name;
+  std::vector<hipEvent_t> ev;  // start/stop pairs
+  size_t used = 0;
+};
+
+}  // namespace hyb
+
+struct hyb_ctx {
+  hipStream_t stream = nullptr;
+  hyb_params p{};
+  int nlev = 0, ncol = 0, nedge = 0, ncell = 0, nz = 0, ntrace = 0, nlevels = 0;
+  double dx = 0, dy = 0;
+  std::vector<double> dz;
+  double *dz_d = nullptr;
+  std::vector<hyb::LevelDev> lv;
+
+  // cell data
+  double *A = nullptr;      // [49][ncell] A_K row-major (i*7+j)
+  double *LU = nullptr;     // [49][ncell] LU factors of A_K (unit lower, no pivoting)
+  double *kv = nullptr;     // [6][ncell] diagonal of K_K
+  double *Scell = nullptr;  // [36][ncell] S_K = [A_K^-1]_uu diag(k)  (setup only)
+  double *bcell = nullptr;  // [6][ncell] [A_K^-1 R_K]_u
+  // trace operator
+  double *S = nullptr;      // [11][ntrace]
+  float *Sf = nullptr;      // [11][ntrace] FP32 copy
+  double *m2l = nullptr;    // [ntrace] lumped velocity mass (interior facets)
+  double *gamma = nullptr;  // [ncell]
+  float *gammaf = nullptr;
+  // preconditioner work vectors (precision of the preconditioner)
+  void *tIn = nullptr, *tA = nullptr, *tB = nullptr, *tR = nullptr;  // [ntrace]
+  double *t64 = nullptr;    // [ntrace]
+  // Krylov workspace
+  int m = 0;
+  double *V = nullptr;      // [(m+1)][ntrace]
+  void *Z = nullptr;        // [m][ntrace] (double or float)
+  double *partial = nullptr;  // [nblk_red][2*(m+2)]
+  double *hdev = nullptr;   // [4*(m+2)]
+  double *hhost = nullptr;  // pinned [4*(m+2)]
+  int nblk_red = 0;
+
+  bool assembled = false, condensed = false;
+  std::string err;
+  size_t bytes = 0;
+
+  bool prof = false;
+  std::vector<hyb::ProfFamily> fam;
+};
+
+namespace hyb {
+
+constexpr int kBlock = 256;
+constexpr int kColBlock = 64;  // one wavefront per workgroup for the column (Thomas) kernels
+
+// profiling helpers (no-ops unless ctx->prof)
+int prof_begin(hyb_ctx *c, int fam);
+void prof_end(hyb_ctx *c, int fam, int slot);
+enum Family {
+  F_LINE_SMOOTH = 0,  // LineSmooth sweeps from a nonzero iterate
+  F_LINE_SMOOTH0,     // the first presmoothing sweep (iterate zero)
+  F_TRACE_APPLY,
+  F_MG_SMOOTH,
+  F_RESTRICT,
+  F_PROLONG,
+  F_KRYLOV,
+  F_CELL,
+  F_COUNT
+};
+
+// ----- setup kernels (assemble.hip) -----
+hipError_t launch_assemble_box(hyb_ctx *c, const double *theta_w, const double *exner_hat_w,
+                               const double *exner_c, const double *rho_c);
+hipError_t launch_factor_cells(hyb_ctx *c);
+hipError_t launch_build_stencil(hyb_ctx *c);
+hipError_t launch_lumped_mass(hyb_ctx *c);
+hipError_t launch_pressure_stencil(hyb_ctx *c);
+hipError_t launch_galerkin(hyb_ctx *c, int coarse_level);
+hipError_t launch_gamma(hyb_ctx *c);
+hipError_t launch_to_float(hyb_ctx *c, const double *src, float *dst, size_t n);
+hipError_t launch_fill(hyb_ctx *c, double *dst, size_t n, double v);
+
+// ----- cell solves (assemble.hip) -----
+hipError_t launch_cell_rhs(hyb_ctx *c, const double *r_ub, const double *r_pi, double *b_lambda);
+hipError_t launch_recover(hyb_ctx *c, const double *r_ub, const double *r_pi, const double *lambda,
+                          double *u_b, double *pi);
+
+// ----- trace operator and preconditioner (solve.hip) -----
+// y = S x (mode 0) or y = b - S x (mode 1); Tm matrix, Tx input, Ty output precision
+template <typename Tm, typename Tx, typename Ty>
+hipError_t launch_trace_apply(hyb_ctx *c, const Tm *S, const Tx *x, const Ty *b, Ty *y, int mode);
+template <typename T>
+hipError_t precondition(hyb_ctx *c, const T *r, T *z);
+hipError_t configure_kernels(int nlev);
+
+// ----- Krylov (krylov.hip) -----
+hipError_t launch_convert(hyb_ctx *c, const double *src, float *dst, size_t n);
+hipError_t launch_copy_widen(hyb_ctx *c, const float *src, double *dst, size_t n);
+// out[i] = sum_k a[k][i] * w[i] for k < nv (rows of a with stride lda), plus ||w||^2 when with_norm
+hipError_t launch_multidot(hyb_ctx *c, const double *a, size_t lda, int nv, const double *w, size_t n,
+                           double *out_dev, bool with_norm);
+// w -= sum_k h[k] a[k]  (h on device)
+hipError_t launch_multi_axpy_dev(hyb_ctx *c, const double *a, size_t lda, int nv, const double *h_dev,
+                                 double *w, size_t n);
+template <typename Tz>
+hipError_t launch_update_solution(hyb_ctx *c, const Tz *Z, size_t ldz, int nv, const double *y_dev,
+                                  double *x, size_t n);
+hipError_t launch_scale(hyb_ctx *c, double *w, size_t n, double s);
+
+}  // namespace hyb

@@ -1,0 +1,48 @@
+"""Helpers shared by the GPU tests: move a synthetic problem onto the device and build a solver."""
+
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+
+from paper_2210_11797_amd import HybSolver, Params, levels_of
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def params_for(prob, **kw):
+    base = dict(dt=prob.dt, tau_u=prob.tau_u, tau_rho=prob.tau_rho, tau_theta=prob.tau_theta, cp=prob.cp,
+                rd=prob.rd)
+    base.update(kw)
+    return Params(**base)
+
+
+def make_solver(prob, **kw):
+    s = HybSolver(prob.nlev, levels_of(prob), prob.dx, prob.dy, prob.dz, params_for(prob, **kw))
+    s.assemble_local(dev(prob.theta_w), dev(prob.exner_hat_w), dev(prob.exner_c), dev(prob.rho_c))
+    s.condense()
+    return s
+
+
+def rel_max(a, ref):
+    ref = np.asarray(ref)
+    return float(np.abs(np.asarray(a) - ref).max() / max(np.abs(ref).max(), 1e-300))
+
+
+def rel_norm(a, ref):
+    ref = np.asarray(ref)
+    return float(np.linalg.norm(np.asarray(a) - ref) / max(np.linalg.norm(ref), 1e-300))
