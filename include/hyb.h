@@ -168,9 +168,10 @@ int hyb_sizes(const hyb_ctx *ctx, int64_t *ntrace, int64_t *ncell, int64_t *work
    hyb_profile(ctx, 1) clears the counters and starts recording every launch
    of the named kernel families; hyb_profile(ctx, 0) stops.  hyb_profile_read
    synchronises the stream and returns the number of launches and their total
-   duration in milliseconds for one family: "line_smooth" (sweeps from a
-   nonzero iterate), "line_smooth0" (first presmoothing sweep), "trace_apply",
-   "mg_smooth", "restrict", "prolong", "krylov", "cell_solve". */
+   duration in milliseconds for one family: "smooth_rows" (LineSmooth residual
+   rows from a nonzero iterate), "smooth_rows0" (first presmoothing sweep),
+   "thomas" (LineSmooth column solves), "trace_apply", "mg_smooth",
+   "restrict", "prolong", "krylov", "cell_solve". */
 int hyb_profile(hyb_ctx *ctx, int32_t enable);
 int hyb_profile_read(hyb_ctx *ctx, const char *family, int64_t *launches, double *total_ms);
 

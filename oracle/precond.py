@@ -79,7 +79,7 @@ def agglomeration(nx, ny, nlev):
 
 
 class PressureMultigrid:
-    def __init__(self, H, nx, ny, nlev, levels=4, omega=0.9, pre=1, post=2, coarse_sweeps=3):
+    def __init__(self, H, nx, ny, nlev, levels=4, omega=0.9, pre=1, post=2, coarse_sweeps=30):
         self.omega, self.pre, self.post, self.coarse_sweeps = omega, pre, post, coarse_sweeps
         self.H = [sp.csr_matrix(H)]
         self.P = []
@@ -134,7 +134,7 @@ class TwoLevel:
     """Alg. 2 with LineSmooth (Alg. 1) and a pressure multigrid V-cycle coarse solve."""
 
     def __init__(self, mesh: BoxMesh, S, H, omega=0.6, n_pre=1, n_post=2, mg_levels=4,
-                 omega_p=0.9, mg_pre=1, mg_post=2, mg_coarse_sweeps=3, sign=+1.0):
+                 omega_p=0.9, mg_pre=1, mg_post=2, mg_coarse_sweeps=30, sign=+1.0):
         self.mesh, self.S = mesh, sp.csr_matrix(S)
         self.omega, self.n_pre, self.n_post, self.sign = omega, n_pre, n_post, sign
         self.D = line_smoother_matrix(mesh, self.S)

@@ -20,7 +20,7 @@ def cells_from_soa(r_ub, r_pi):
 
 class OracleProblem:
     def __init__(self, prob, *, with_mixed=True, with_precond=True, omega=0.6, n_pre=1,
-                 n_post=2, mg_levels=None, omega_p=0.9, mg_pre=1, mg_post=2, mg_coarse_sweeps=3):
+                 n_post=2, mg_levels=None, omega_p=0.9, mg_pre=1, mg_post=2, mg_coarse_sweeps=30):
         self.prob = prob
         self.mesh = BoxMesh(prob.nx, prob.ny, prob.nlev, prob.dx, prob.dy, prob.z)
         self.loc = local_matrices(self.mesh, prob)

@@ -67,7 +67,7 @@ class Params:
     omega_p: float = 0.9
     mg_pre: int = 1
     mg_post: int = 2
-    mg_coarse_sweeps: int = 3
+    mg_coarse_sweeps: int = 30
     restart: int = 30
     precision: int = PREC_FP64
 
@@ -89,6 +89,10 @@ def load(path: str = LIB_PATH):
     global _lib
     if _lib is not None:
         return _lib
+    # torch ships its own HIP runtime; it must be loaded first so that this library binds to the
+    # same runtime instance (loading libhyb.so first would bring up a second one)
+    import torch  # noqa: F401
+
     if not os.path.exists(path):
         raise RuntimeError(f"HIP library not built: {path} (run paper_2210_11797_amd/build.py)")
     lib = ctypes.CDLL(path)

@@ -20,8 +20,8 @@ int reduction_blocks();
 
 namespace {
 
-const char *kFamilyNames[F_COUNT] = {"line_smooth", "line_smooth0", "trace_apply", "mg_smooth",
-                                     "restrict",    "prolong",      "krylov",      "cell_solve"};
+const char *kFamilyNames[F_COUNT] = {"smooth_rows", "smooth_rows0", "thomas",  "trace_apply", "mg_smooth",
+                                     "restrict",    "prolong",      "krylov",  "cell_solve"};
 
 int fail(hyb_ctx *c, int code, const std::string &msg) {
   if (c) c->err = msg;
@@ -146,8 +146,10 @@ int setup_level(hyb_ctx *c, const hyb_mesh *mesh, int l) {
     if ((rc = upload(c, &L.children, ch)) || (rc = upload(c, &c->lv[l - 1].parent, par))) return rc;
   }
   size_t n = (size_t)ncol * c->nlev;
-  if ((rc = dalloc(c, &L.H, 7 * n)) || (rc = dalloc(c, &L.Hf, 7 * n))) return rc;
-  double **vecs[3] = {(double **)&L.b, (double **)&L.x, (double **)&L.y};
+  if ((rc = dalloc(c, &L.H, 7 * n)) || (rc = dalloc(c, &L.Hf, 7 * n)) || (rc = dalloc(c, &L.zf, 3 * n)) ||
+      (rc = dalloc(c, &L.zff, 3 * n)))
+    return rc;
+  double **vecs[4] = {(double **)&L.b, (double **)&L.x, (double **)&L.y, (double **)&L.r};
   for (auto v : vecs)
     if ((rc = dalloc(c, v, n))) return rc;
   return HYB_OK;
@@ -157,10 +159,10 @@ void free_all(hyb_ctx *c) {
   for (auto &L : c->lv) {
     dfree(L.col_edge), dfree(L.edge_col), dfree(L.edge_lf), dfree(L.nbr), dfree(L.nlf), dfree(L.own);
     dfree(L.est), dfree(L.parent), dfree(L.children), dfree(L.H), dfree(L.Hf);
-    dfree(L.b), dfree(L.x), dfree(L.y);
+    dfree(L.zf), dfree(L.zff), dfree(L.b), dfree(L.x), dfree(L.y), dfree(L.r);
   }
   dfree(c->dz_d), dfree(c->A), dfree(c->LU), dfree(c->kv), dfree(c->Scell), dfree(c->bcell);
-  dfree(c->S), dfree(c->Sf), dfree(c->m2l), dfree(c->gamma), dfree(c->gammaf);
+  dfree(c->S), dfree(c->Sf), dfree(c->m2l), dfree(c->gamma), dfree(c->gammaf), dfree(c->zfac), dfree(c->zfacf);
   dfree(c->tIn), dfree(c->tA), dfree(c->tB), dfree(c->tR), dfree(c->t64);
   dfree(c->V), dfree(c->Z), dfree(c->partial), dfree(c->hdev);
   if (c->hhost) (void)hipHostFree(c->hhost);
@@ -253,7 +255,7 @@ int hyb_create(const hyb_mesh *mesh, const hyb_params *params, void *stream, hyb
     delete c;
     return HYB_EINVAL;
   }
-  if ((size_t)2 * sizeof(double) * (c->nlev + 1) * kColBlock > 160 * 1024) {
+  if ((size_t)sizeof(double) * (c->nlev + 1) * kColBlock > 160 * 1024) {
     delete c;
     return HYB_EINVAL;  // column coefficients must fit in the 160 KiB LDS of a CU
   }
@@ -290,8 +292,12 @@ int hyb_set_params(hyb_ctx *c, const hyb_params *params) {
     // FP32 copies are made at condensation; refresh them for the new mode
     CHECK_HIP(launch_to_float(c, c->S, c->Sf, (size_t)11 * c->ntrace), "to_float S");
     CHECK_HIP(launch_to_float(c, c->gamma, c->gammaf, (size_t)c->ncell), "to_float gamma");
+    CHECK_HIP(launch_to_float(c, c->zfac, c->zfacf, 3 * (size_t)c->nz), "to_float zfac");
     for (int l = 0; l < c->nlevels; ++l)
+    {
       CHECK_HIP(launch_to_float(c, c->lv[l].H, c->lv[l].Hf, (size_t)7 * c->nlev * c->lv[l].ncol), "to_float H");
+      CHECK_HIP(launch_to_float(c, c->lv[l].zf, c->lv[l].zff, (size_t)3 * c->nlev * c->lv[l].ncol), "to_float Hz");
+    }
   }
   return alloc_krylov(c);
 }
@@ -316,6 +322,7 @@ int hyb_condense(hyb_ctx *c, const double *r_ub, const double *r_pi, double *b_l
     size_t ntr = (size_t)c->ntrace, nc = (size_t)c->ncell;
     if ((rc = dalloc(c, &c->LU, 49 * nc)) || (rc = dalloc(c, &c->Scell, 36 * nc)) || (rc = dalloc(c, &c->S, 11 * ntr)) ||
         (rc = dalloc(c, &c->Sf, 11 * ntr)) || (rc = dalloc(c, &c->m2l, ntr)) || (rc = dalloc(c, &c->gamma, nc)) ||
+        (rc = dalloc(c, &c->zfac, 3 * (size_t)c->nz)) || (rc = dalloc(c, &c->zfacf, 3 * (size_t)c->nz)) ||
         (rc = dalloc(c, &c->gammaf, nc)) || (rc = dalloc(c, &c->bcell, 6 * nc)) ||
         (rc = dalloc(c, (double **)&c->tIn, ntr)) || (rc = dalloc(c, (double **)&c->tA, ntr)) ||
         (rc = dalloc(c, (double **)&c->tB, ntr)) || (rc = dalloc(c, (double **)&c->tR, ntr)) ||
@@ -324,14 +331,20 @@ int hyb_condense(hyb_ctx *c, const double *r_ub, const double *r_pi, double *b_l
     if ((rc = alloc_krylov(c))) return rc;
     CHECK_HIP(launch_factor_cells(c), "factor_cells");
     CHECK_HIP(launch_build_stencil(c), "build_stencil");
+    CHECK_HIP(launch_thomas_factor(c), "thomas_factor");
     CHECK_HIP(launch_lumped_mass(c), "lumped_mass");
     CHECK_HIP(launch_pressure_stencil(c), "pressure_stencil");
     for (int l = 1; l < c->nlevels; ++l) CHECK_HIP(launch_galerkin(c, l), "galerkin");
+    for (int l = 0; l < c->nlevels; ++l) CHECK_HIP(launch_mg_factor(c, l), "mg_factor");
     CHECK_HIP(launch_gamma(c), "gamma");
     CHECK_HIP(launch_to_float(c, c->S, c->Sf, 11 * ntr), "to_float S");
     CHECK_HIP(launch_to_float(c, c->gamma, c->gammaf, nc), "to_float gamma");
+    CHECK_HIP(launch_to_float(c, c->zfac, c->zfacf, 3 * (size_t)c->nz), "to_float zfac");
     for (int l = 0; l < c->nlevels; ++l)
+    {
       CHECK_HIP(launch_to_float(c, c->lv[l].H, c->lv[l].Hf, (size_t)7 * c->nlev * c->lv[l].ncol), "to_float H");
+      CHECK_HIP(launch_to_float(c, c->lv[l].zf, c->lv[l].zff, (size_t)3 * c->nlev * c->lv[l].ncol), "to_float Hz");
+    }
     CHECK_HIP(hipStreamSynchronize(c->stream), "condense sync");
     dfree(c->Scell);
     c->condensed = true;
@@ -431,18 +444,53 @@ int hyb_solve(hyb_ctx *c, const double *b, double *lam, double rtol, int32_t max
         CHECK_HIP(precondition<double>(c, vj, zj), "precondition");
         CHECK_HIP((launch_trace_apply<double, double, double>(c, c->S, zj, nullptr, w, 0)), "matvec");
       }
-      // classical Gram-Schmidt with one reorthogonalisation
-      CHECK_HIP(launch_multidot(c, V, n, j + 1, w, n, h1, false), "cgs1");
-      CHECK_HIP(launch_multi_axpy_dev(c, V, n, j + 1, h1, w, n), "cgs1 update");
-      CHECK_HIP(launch_multidot(c, V, n, j + 1, w, n, h2, false), "cgs2");
-      CHECK_HIP(launch_multi_axpy_dev(c, V, n, j + 1, h2, w, n), "cgs2 update");
-      CHECK_HIP(launch_multidot(c, V, 0, 0, w, n, nrm, true), "norm w");
-      CHECK_HIP(hipMemcpyAsync(hh, c->hdev, 3 * (size_t)(m + 2) * sizeof(double), hipMemcpyDeviceToHost, c->stream),
-                "d2h");
-      CHECK_HIP(hipStreamSynchronize(c->stream), "sync");
       double *col = &R[(size_t)j * (m + 1)];
-      for (int i = 0; i <= j; ++i) col[i] = hh[i] + hh[(m + 2) + i];
-      double hn = std::sqrt(hh[2 * (m + 2)]);
+      double hn;
+      bool scaled = false;
+      if (j + 1 <= 32) {
+        // classical Gram-Schmidt with reorthogonalisation in three passes over the basis and one
+        // host read: h1 = V^T w; w -= V h1 while h2 = V^T w and ||w||^2 accumulate; the last pass
+        // subtracts V h2 and normalises with ||w - V h2||^2 = ||w||^2 - ||h2||^2 (V orthonormal)
+        CHECK_HIP(launch_gs_passes(c, V, n, j + 1, w, h1, h2), "gram-schmidt");
+        CHECK_HIP(hipMemcpyAsync(hh, c->hdev, 2 * (size_t)(m + 2) * sizeof(double), hipMemcpyDeviceToHost,
+                                 c->stream),
+                  "d2h");
+        CHECK_HIP(hipStreamSynchronize(c->stream), "sync");
+        double h2sq = 0.0;
+        for (int i = 0; i <= j; ++i) {
+          col[i] = hh[i] + hh[(m + 2) + i];
+          h2sq += hh[(m + 2) + i] * hh[(m + 2) + i];
+        }
+        double wp2 = hh[(m + 2) + j + 1];
+        hn = std::sqrt(std::max(0.0, wp2 - h2sq));
+        if (hn > 0.0 && std::isfinite(hn)) {
+          CHECK_HIP(launch_gs_finish(c, V, n, j + 1, h2, w, 1.0 / hn), "gram-schmidt finish");
+          scaled = true;
+        }
+      } else {
+        // long restart cycles: classical Gram-Schmidt, second pass when the first one cancelled
+        // more than half of the norm (||w'|| < ||w|| / sqrt(2))
+        CHECK_HIP(launch_multidot(c, V, n, j + 1, w, n, h1, true), "cgs1");
+        CHECK_HIP(launch_axpy_norm(c, V, n, j + 1, h1, w, n, nrm), "cgs1 update");
+        CHECK_HIP(hipMemcpyAsync(hh, c->hdev, 3 * (size_t)(m + 2) * sizeof(double), hipMemcpyDeviceToHost,
+                                 c->stream),
+                  "d2h");
+        CHECK_HIP(hipStreamSynchronize(c->stream), "sync");
+        for (int i = 0; i <= j; ++i) col[i] = hh[i];
+        double w2 = hh[j + 1], wp2 = hh[2 * (m + 2)];
+        if (!(wp2 >= 0.5 * w2)) {
+          CHECK_HIP(launch_multidot(c, V, n, j + 1, w, n, h2, false), "cgs2");
+          CHECK_HIP(launch_axpy_norm(c, V, n, j + 1, h2, w, n, nrm), "cgs2 update");
+          CHECK_HIP(hipMemcpyAsync(hh, c->hdev, 3 * (size_t)(m + 2) * sizeof(double), hipMemcpyDeviceToHost,
+                                   c->stream),
+                    "d2h");
+          CHECK_HIP(hipStreamSynchronize(c->stream), "sync");
+          for (int i = 0; i <= j; ++i) col[i] += hh[(m + 2) + i];
+          wp2 = hh[2 * (m + 2)];
+          c->reorth++;
+        }
+        hn = std::sqrt(wp2);
+      }
       col[j + 1] = hn;
       for (int i = 0; i < j; ++i) {
         double a = col[i], bb = col[i + 1];
@@ -471,7 +519,7 @@ int hyb_solve(hyb_ctx *c, const double *b, double *lam, double rtol, int32_t max
         break;
       }
       if (est <= rtol || its >= maxit || hn == 0.0) break;
-      CHECK_HIP(launch_scale(c, w, n, 1.0 / hn), "scale");
+      if (!scaled) CHECK_HIP(launch_scale(c, w, n, 1.0 / hn), "scale");
     }
     if (jend > 0) {
       for (int i = jend - 1; i >= 0; --i) {

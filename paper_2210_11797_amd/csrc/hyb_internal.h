@@ -30,7 +30,9 @@ struct LevelDev {
   int32_t *children = nullptr;  // [4][ncol] -> columns of level l-1 (nullptr on level 0)
   double *H = nullptr;          // [7][nlev*ncol] pressure stencil: diag, W, E, S, N, below, above
   float *Hf = nullptr;          // FP32 copy
-  void *b = nullptr, *x = nullptr, *y = nullptr;  // [nlev*ncol] work vectors in preconditioner precision
+  double *zf = nullptr;         // [3][nlev*ncol] LU factors of the column part H_z: l, 1/u, c/u
+  float *zff = nullptr;
+  void *b = nullptr, *x = nullptr, *y = nullptr, *r = nullptr;  // [nlev*ncol] work vectors
 };
 
 struct ProfFamily {
@@ -60,6 +62,8 @@ struct hyb_ctx {
   double *S = nullptr;      // [11][ntrace]
   float *Sf = nullptr;      // [11][ntrace] FP32 copy
   double *m2l = nullptr;    // [ntrace] lumped velocity mass (interior facets)
+  double *zfac = nullptr;   // [3][nz] LU factors of S^zz per column: l, 1/u, c/u
+  float *zfacf = nullptr;
   double *gamma = nullptr;  // [ncell]
   float *gammaf = nullptr;
   // preconditioner work vectors (precision of the preconditioner)
@@ -73,6 +77,7 @@ struct hyb_ctx {
   double *hdev = nullptr;   // [4*(m+2)]
   double *hhost = nullptr;  // pinned [4*(m+2)]
   int nblk_red = 0;
+  long reorth = 0;           // second Gram-Schmidt passes taken (diagnostics)
 
   bool assembled = false, condensed = false;
   std::string err;
@@ -91,8 +96,9 @@ constexpr int kColBlock = 64;  // one wavefront per workgroup for the column (Th
 int prof_begin(hyb_ctx *c, int fam);
 void prof_end(hyb_ctx *c, int fam, int slot);
 enum Family {
-  F_LINE_SMOOTH = 0,  // LineSmooth sweeps from a nonzero iterate
-  F_LINE_SMOOTH0,     // the first presmoothing sweep (iterate zero)
+  F_SMOOTH_ROWS = 0,  // LineSmooth residual rows, sweeps from a nonzero iterate
+  F_SMOOTH_ROWS0,     // the first presmoothing sweep (iterate zero): vertical facets only
+  F_THOMAS,           // LineSmooth column solves
   F_TRACE_APPLY,
   F_MG_SMOOTH,
   F_RESTRICT,
@@ -126,6 +132,8 @@ hipError_t launch_trace_apply(hyb_ctx *c, const Tm *S, const Tx *x, const Ty *b,
 template <typename T>
 hipError_t precondition(hyb_ctx *c, const T *r, T *z);
 hipError_t configure_kernels(int nlev);
+hipError_t launch_thomas_factor(hyb_ctx *c);
+hipError_t launch_mg_factor(hyb_ctx *c, int level);
 
 // ----- Krylov (krylov.hip) -----
 hipError_t launch_convert(hyb_ctx *c, const double *src, float *dst, size_t n);
@@ -136,6 +144,13 @@ hipError_t launch_multidot(hyb_ctx *c, const double *a, size_t lda, int nv, cons
 // w -= sum_k h[k] a[k]  (h on device)
 hipError_t launch_multi_axpy_dev(hyb_ctx *c, const double *a, size_t lda, int nv, const double *h_dev,
                                  double *w, size_t n);
+// fused classical Gram-Schmidt with reorthogonalisation (nv <= 32): h1 = V w, w -= V^T h1,
+// h2n[0..nv-1] = V w, h2n[nv] = ||w||^2; then w = (w - V^T h2) * s
+hipError_t launch_gs_passes(hyb_ctx *c, const double *V, size_t n, int nv, double *w, double *h1, double *h2n);
+hipError_t launch_gs_finish(hyb_ctx *c, const double *V, size_t n, int nv, const double *h2, double *w, double s);
+// w -= sum_k h[k] a[k], then nrm_dev[0] = ||w||^2
+hipError_t launch_axpy_norm(hyb_ctx *c, const double *a, size_t lda, int nv, const double *h_dev, double *w,
+                            size_t n, double *nrm_dev);
 template <typename Tz>
 hipError_t launch_update_solution(hyb_ctx *c, const Tz *Z, size_t ldz, int nv, const double *y_dev,
                                   double *x, size_t n);

@@ -18,10 +18,10 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// partial[blk][k] = sum over this block's entries of a_k . w (k < nv), and w . w at k = nv.
+// partial[k][blk] = sum over this block's entries of a_k . w (k < nv), and w . w at k = nv.
 __global__ void __launch_bounds__(kBlock) k_multidot_partial(const double *__restrict__ a, size_t lda, int nv,
                                                              const double *__restrict__ w, size_t n, int nout,
-                                                             double *__restrict__ partial, int ldp) {
+                                                             double *__restrict__ partial) {
   __shared__ double red[kBlock / 64][kChunk];
   int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -50,19 +50,28 @@ __global__ void __launch_bounds__(kBlock) k_multidot_partial(const double *__res
       double s = 0.0;
 #pragma unroll
       for (int q = 0; q < kBlock / 64; ++q) s += red[q][threadIdx.x];
-      partial[(size_t)blockIdx.x * ldp + k0 + threadIdx.x] = s;
+      partial[(size_t)(k0 + threadIdx.x) * gridDim.x + blockIdx.x] = s;
     }
     __syncthreads();
   }
 }
 
-__global__ void k_multidot_final(const double *__restrict__ partial, int ldp, int nb, int nout,
-                                 double *__restrict__ out) {
-  int k = threadIdx.x;
-  if (k >= nout) return;
+// out[k] = sum over blocks of partial[k][*]: one workgroup per output, fixed summation order.
+__global__ void __launch_bounds__(kBlock) k_multidot_final(const double *__restrict__ partial, int nb,
+                                                           double *__restrict__ out) {
+  __shared__ double red[kBlock / 64];
+  int k = blockIdx.x;
   double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += partial[(size_t)b * ldp + k];
-  out[k] = s;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) s += partial[(size_t)k * nb + b];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < kBlock / 64; ++q) t += red[q];
+    out[k] = t;
+  }
 }
 
 __global__ void k_multi_axpy(const double *__restrict__ a, size_t lda, int nv, const double *__restrict__ h,
@@ -72,6 +81,118 @@ __global__ void k_multi_axpy(const double *__restrict__ a, size_t lda, int nv, c
   double v = w[i];
   for (int k = 0; k < nv; ++k) v -= h[k] * a[(size_t)k * lda + i];
   w[i] = v;
+}
+
+// w -= sum_k h[k] a_k and partial[blk] = sum over the block of the updated w^2.
+__global__ void __launch_bounds__(kBlock) k_axpy_norm(const double *__restrict__ a, size_t lda, int nv,
+                                                      const double *__restrict__ h, double *__restrict__ w,
+                                                      size_t n, double *__restrict__ partial) {
+  __shared__ double red[kBlock / 64];
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  double acc = 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    double v = w[i];
+    for (int k = 0; k < nv; ++k) v -= h[k] * a[(size_t)k * lda + i];
+    w[i] = v;
+    acc += v * v;
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < kBlock / 64; ++q) t += red[q];
+    partial[blockIdx.x] = t;
+  }
+}
+
+// Fused Gram-Schmidt passes for up to NV basis vectors (registers hold one value of each).
+// Block reductions write partial[k][blk]; k_multidot_final sums them in a fixed order.
+template <int NV>
+__device__ __forceinline__ void block_reduce_store(double (&acc)[NV + 1], int nout, double *partial) {
+  __shared__ double red[kBlock / 64][NV + 1];
+  int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k <= NV; ++k) {
+    if (k < nout) {
+      double v = wave_sum(acc[k]);
+      if (lane == 0) red[wv][k] = v;
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < nout; k += blockDim.x) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < kBlock / 64; ++q) t += red[q][k];
+    partial[(size_t)k * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+// pass 1: h1_k = a_k . w for k < nv (w read once)
+template <int NV>
+__global__ void __launch_bounds__(kBlock) k_gs_dots(const double *__restrict__ a, size_t lda, int nv,
+                                                    const double *__restrict__ w, size_t n,
+                                                    double *__restrict__ partial) {
+  double acc[NV + 1];
+#pragma unroll
+  for (int k = 0; k <= NV; ++k) acc[k] = 0.0;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    double wi = w[i];
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+      if (k < nv) acc[k] += a[(size_t)k * lda + i] * wi;
+  }
+  block_reduce_store<NV>(acc, nv, partial);
+}
+
+// pass 2: w <- w - sum_k h1_k a_k, then h2_k = a_k . w and ||w||^2 (index nv) of the updated w
+template <int NV>
+__global__ void __launch_bounds__(kBlock) k_gs_update_dots(const double *__restrict__ a, size_t lda, int nv,
+                                                           const double *__restrict__ h1, double *__restrict__ w,
+                                                           size_t n, double *__restrict__ partial) {
+  double acc[NV + 1], hk[NV];
+#pragma unroll
+  for (int k = 0; k <= NV; ++k) acc[k] = 0.0;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) hk[k] = (k < nv) ? h1[k] : 0.0;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    double av[NV];
+    double v = w[i];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      av[k] = (k < nv) ? a[(size_t)k * lda + i] : 0.0;
+      v -= hk[k] * av[k];
+    }
+    w[i] = v;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] += av[k] * v;
+    acc[NV] += v * v;
+  }
+  // move the norm into slot nv so that the outputs are contiguous
+#pragma unroll
+  for (int k = 0; k < NV; ++k)
+    if (k == nv) acc[k] = acc[NV];
+  block_reduce_store<NV>(acc, nv + 1, partial);
+}
+
+// pass 3: w <- (w - sum_k h2_k a_k) * s
+template <int NV>
+__global__ void __launch_bounds__(kBlock) k_gs_update_scale(const double *__restrict__ a, size_t lda, int nv,
+                                                            const double *__restrict__ h2, double *__restrict__ w,
+                                                            size_t n, double s) {
+  double hk[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) hk[k] = (k < nv) ? h2[k] : 0.0;
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double v = w[i];
+#pragma unroll
+  for (int k = 0; k < NV; ++k)
+    if (k < nv) v -= hk[k] * a[(size_t)k * lda + i];
+  w[i] = v * s;
 }
 
 template <typename Tz>
@@ -106,13 +227,11 @@ int reduction_blocks() { return kRedBlocks; }
 hipError_t launch_multidot(hyb_ctx *c, const double *a, size_t lda, int nv, const double *w, size_t n,
                            double *out_dev, bool with_norm) {
   int nout = nv + (with_norm ? 1 : 0);
-  int ldp = c->m + 2;
-  if (nout > ldp || nout > kBlock) return hipErrorInvalidValue;
+  if (nout > c->m + 2) return hipErrorInvalidValue;
   int slot = prof_begin(c, F_KRYLOV);
   unsigned nb = std::min<unsigned>(kRedBlocks, nblk(n));
-  hipLaunchKernelGGL(k_multidot_partial, dim3(nb), dim3(kBlock), 0, c->stream, a, lda, nv, w, n, nout, c->partial,
-                     ldp);
-  hipLaunchKernelGGL(k_multidot_final, dim3(1), dim3(kBlock), 0, c->stream, c->partial, ldp, (int)nb, nout, out_dev);
+  hipLaunchKernelGGL(k_multidot_partial, dim3(nb), dim3(kBlock), 0, c->stream, a, lda, nv, w, n, nout, c->partial);
+  hipLaunchKernelGGL(k_multidot_final, dim3(nout), dim3(kBlock), 0, c->stream, c->partial, (int)nb, out_dev);
   prof_end(c, F_KRYLOV, slot);
   return hipGetLastError();
 }
@@ -121,6 +240,57 @@ hipError_t launch_multi_axpy_dev(hyb_ctx *c, const double *a, size_t lda, int nv
                                  size_t n) {
   int slot = prof_begin(c, F_KRYLOV);
   hipLaunchKernelGGL(k_multi_axpy, dim3(nblk(n)), dim3(kBlock), 0, c->stream, a, lda, nv, h_dev, w, n);
+  prof_end(c, F_KRYLOV, slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_norm(hyb_ctx *c, const double *a, size_t lda, int nv, const double *h_dev, double *w,
+                            size_t n, double *nrm_dev) {
+  int slot = prof_begin(c, F_KRYLOV);
+  unsigned nb = std::min<unsigned>(kRedBlocks, nblk(n));
+  hipLaunchKernelGGL(k_axpy_norm, dim3(nb), dim3(kBlock), 0, c->stream, a, lda, nv, h_dev, w, n, c->partial);
+  hipLaunchKernelGGL(k_multidot_final, dim3(1), dim3(kBlock), 0, c->stream, c->partial, (int)nb, nrm_dev);
+  prof_end(c, F_KRYLOV, slot);
+  return hipGetLastError();
+}
+
+template <int NV>
+hipError_t gs_passes_nv(hyb_ctx *c, const double *V, size_t n, int nv, double *w, double *h1, double *h2n) {
+  unsigned nb = std::min<unsigned>(kRedBlocks, nblk(n));
+  hipLaunchKernelGGL((k_gs_dots<NV>), dim3(nb), dim3(kBlock), 0, c->stream, V, n, nv, w, n, c->partial);
+  hipLaunchKernelGGL(k_multidot_final, dim3(nv), dim3(kBlock), 0, c->stream, c->partial, (int)nb, h1);
+  hipLaunchKernelGGL((k_gs_update_dots<NV>), dim3(nb), dim3(kBlock), 0, c->stream, V, n, nv, (const double *)h1, w,
+                     n, c->partial);
+  hipLaunchKernelGGL(k_multidot_final, dim3(nv + 1), dim3(kBlock), 0, c->stream, c->partial, (int)nb, h2n);
+  return hipGetLastError();
+}
+
+// Classical Gram-Schmidt with reorthogonalisation against the nv orthonormal rows of V (stride n):
+// h1 = V w; w -= V^T h1; h2 = V w; ||w||^2 -> h2n[nv]; the final update and normalisation is
+// launch_gs_finish once the host knows the norm.
+hipError_t launch_gs_passes(hyb_ctx *c, const double *V, size_t n, int nv, double *w, double *h1, double *h2n) {
+  if (nv < 1 || nv > 32 || nv + 1 > c->m + 2) return hipErrorInvalidValue;
+  int slot = prof_begin(c, F_KRYLOV);
+  hipError_t e;
+  if (nv <= 8)
+    e = gs_passes_nv<8>(c, V, n, nv, w, h1, h2n);
+  else if (nv <= 16)
+    e = gs_passes_nv<16>(c, V, n, nv, w, h1, h2n);
+  else
+    e = gs_passes_nv<32>(c, V, n, nv, w, h1, h2n);
+  prof_end(c, F_KRYLOV, slot);
+  return e;
+}
+
+hipError_t launch_gs_finish(hyb_ctx *c, const double *V, size_t n, int nv, const double *h2, double *w, double s) {
+  if (nv < 1 || nv > 32) return hipErrorInvalidValue;
+  int slot = prof_begin(c, F_KRYLOV);
+  if (nv <= 8)
+    hipLaunchKernelGGL((k_gs_update_scale<8>), dim3(nblk(n)), dim3(kBlock), 0, c->stream, V, n, nv, h2, w, n, s);
+  else if (nv <= 16)
+    hipLaunchKernelGGL((k_gs_update_scale<16>), dim3(nblk(n)), dim3(kBlock), 0, c->stream, V, n, nv, h2, w, n, s);
+  else
+    hipLaunchKernelGGL((k_gs_update_scale<32>), dim3(nblk(n)), dim3(kBlock), 0, c->stream, V, n, nv, h2, w, n, s);
   prof_end(c, F_KRYLOV, slot);
   return hipGetLastError();
 }

@@ -12,6 +12,12 @@ namespace {
 
 inline unsigned nblk(size_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
 
+#define HYB_TRY(x)                   \
+  do {                               \
+    hipError_t e_ = (x);             \
+    if (e_ != hipSuccess) return e_; \
+  } while (0)
+
 template <typename T>
 struct Acc {
   using type = T;
@@ -58,94 +64,176 @@ __device__ __forceinline__ A row_h(const Tm *__restrict__ S, size_t ntr, const T
   return acc;
 }
 
-// y = S x (MODE 0) or y = b - S x (MODE 1); one thread per trace row.
-template <typename Tm, typename Tx, typename Ty, int MODE>
-__global__ void k_trace_apply(const Tm *__restrict__ S, const Tx *__restrict__ x, const Ty *__restrict__ b,
-                              Ty *__restrict__ y, int nlev, int ncol, int nedge, size_t nz, size_t ntr,
-                              const int32_t *__restrict__ col_edge, const int32_t *__restrict__ est) {
+// Row operations on the trace operator.
+//   OP_APPLY  y = S x
+//   OP_RESID  y = b - S x
+//   OP_SMOOTH LineSmooth rows: horizontal facets y = b - S x (kept for the column solve), vertical
+//             facets lout = x + omega (b - S x) / diag(S^hh) (point Jacobi)
+//   OP_SMOOTH0 the same from x = 0 on vertical facets only: lout = omega b / diag(S^hh)
+enum { OP_APPLY = 0, OP_RESID = 1, OP_SMOOTH = 2, OP_SMOOTH0 = 3 };
+constexpr int kRowChunk = 8;
+
+template <typename Tm, typename Tx, typename Ty, int OP>
+__device__ __forceinline__ void zrow_op(const Tm *__restrict__ S, const Tx *__restrict__ x, const Ty *__restrict__ b,
+                                        Ty *__restrict__ y, int k, int col, int nlev, int ncol, int nedge, size_t nz,
+                                        size_t ntr, const int ce[4]) {
   using A = typename Acc<Ty>::type;
-  size_t F = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (F >= ntr) return;
-  A v;
-  if (F < nz) {
-    int k = (int)(F / ncol), col = (int)(F - (size_t)k * ncol);
-    int ce[4];
-#pragma unroll
-    for (int f = 0; f < 4; ++f) ce[f] = col_edge[(size_t)f * ncol + col];
-    v = row_z<A>(S, ntr, x, F, k, nlev, ncol, nedge, nz, ce);
-  } else {
-    size_t h = F - nz;
-    int k = (int)(h / nedge), e = (int)(h - (size_t)k * nedge);
-    int t[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) t[i] = est[(size_t)i * nedge + e];
-    v = row_h<A>(S, ntr, x, F, k, ncol, nedge, nz, t);
-  }
-  if (MODE == 1) v = (A)b[F] - v;
+  size_t F = (size_t)k * ncol + col;
+  A v = row_z<A>(S, ntr, x, F, k, nlev, ncol, nedge, nz, ce);
+  if (OP != OP_APPLY) v = (A)b[F] - v;
   y[F] = (Ty)v;
 }
 
-// One sweep of LineSmooth (Alg. 1, with the update lambda <- lambda + omega delta):
-// residual R = B - S lambda_in, tridiagonal solve S^zz_j delta = R^z_j per column (Thomas),
-// point Jacobi delta = R^h / diag(S^hh) on the vertical facets owned by the column.
-// ZERO: lambda_in = 0 (R = B, the first sweep of Alg. 2).  Writes lambda_out (Jacobi: no in-place).
-template <typename T, bool ZERO>
-__global__ void __launch_bounds__(kColBlock) k_line_smooth(const T *__restrict__ S, const T *__restrict__ B,
-                                                           const T *__restrict__ lin, T *__restrict__ lout,
-                                                           int nlev, int ncol, int nedge, size_t nz, size_t ntr,
-                                                           const int32_t *__restrict__ col_edge,
-                                                           const int32_t *__restrict__ own,
-                                                           const int32_t *__restrict__ est, T omega) {
-  extern __shared__ unsigned char smem_raw[];
-  T *cpv = reinterpret_cast<T *>(smem_raw);
-  T *dpv = cpv + (size_t)(nlev + 1) * blockDim.x;
-  int tid = threadIdx.x;
-  int col = blockIdx.x * blockDim.x + tid;
-  if (col >= ncol) return;
-  int ce[4];
-#pragma unroll
-  for (int f = 0; f < 4; ++f) ce[f] = col_edge[(size_t)f * ncol + col];
-  int ne = 0, oe[4];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    int e = own[(size_t)j * ncol + col];
-    oe[j] = e;
-    ne += (e >= 0);
+template <typename Tm, typename Tx, typename Ty, int OP>
+__device__ __forceinline__ void hrow_op(const Tm *__restrict__ S, const Tx *__restrict__ x, const Ty *__restrict__ b,
+                                        Ty *__restrict__ y, Ty *__restrict__ lout, int k, int e, int ncol, int nedge,
+                                        size_t nz, size_t ntr, const int t[8], Ty omega) {
+  using A = typename Acc<Ty>::type;
+  size_t F = nz + (size_t)k * nedge + e;
+  if (OP == OP_SMOOTH0) {
+    lout[F] = omega * b[F] / (Ty)S[F];
+  } else {
+    A v = row_h<A>(S, ntr, x, F, k, ncol, nedge, nz, t);
+    if (OP != OP_APPLY) v = (A)b[F] - v;
+    if (OP == OP_SMOOTH)
+      lout[F] = (Ty)x[F] + omega * (Ty)v / (Ty)S[F];
+    else
+      y[F] = (Ty)v;
   }
-  T cprev = 0, dprev = 0;
-  for (int k = 0; k <= nlev; ++k) {
-    size_t F = (size_t)k * ncol + col;
-    T r = B[F];
-    if (!ZERO) r -= row_z<T>(S, ntr, lin, F, k, nlev, ncol, nedge, nz, ce);
-    T a = S[ntr + F], bb = S[F], c = S[2 * ntr + F];
-    T inv = (T)1 / (bb - a * cprev);
-    cprev = c * inv;
-    dprev = (r - a * dprev) * inv;
-    cpv[(size_t)k * blockDim.x + tid] = cprev;
-    dpv[(size_t)k * blockDim.x + tid] = dprev;
-    if (k < nlev) {
-      for (int j = 0; j < ne; ++j) {
-        int e = oe[j];
-        size_t hF = nz + (size_t)k * nedge + e;
-        T rh = B[hF];
-        T base = 0;
-        if (!ZERO) {
-          int t[8];
+}
+
+// A thread owns one column (its horizontal facets) or one edge (its vertical facets) for kRowChunk
+// consecutive layers, so the neighbour tables are read once per chunk; at a fixed layer
+// consecutive threads touch consecutive rows (coalesced).  Workgroups keep the hardware's
+// round-robin placement over the XCDs: measured, it spreads the streams over the HBM channels
+// better than giving each XCD a contiguous range (which would raise L2 reuse of the gathers).
+template <typename Tm, typename Tx, typename Ty, int OP>
+__global__ void __launch_bounds__(kBlock) k_rows(const Tm *__restrict__ S, const Tx *__restrict__ x,
+                                                 const Ty *__restrict__ b, Ty *__restrict__ y,
+                                                 Ty *__restrict__ lout, int nlev, int ncol, int nedge, size_t nz,
+                                                 size_t ntr, int ent0, const int32_t *__restrict__ col_edge,
+                                                 const int32_t *__restrict__ est, Ty omega) {
+  const int ent = ent0 + blockIdx.x * blockDim.x + threadIdx.x;
+  const int k0 = blockIdx.y * kRowChunk;
+  if (ent < ncol) {
+    if (OP == OP_SMOOTH0) return;
+    const int col = ent;
+    int ce[4];
 #pragma unroll
-          for (int i = 0; i < 8; ++i) t[i] = est[(size_t)i * nedge + e];
-          rh -= row_h<T>(S, ntr, lin, hF, k, ncol, nedge, nz, t);
-          base = lin[hF];
-        }
-        lout[hF] = base + omega * rh / S[hF];
+    for (int f = 0; f < 4; ++f) ce[f] = col_edge[(size_t)f * ncol + col];
+#pragma unroll
+    for (int q = 0; q < kRowChunk; ++q) {
+      const int k = k0 + q;
+      if (k <= nlev) zrow_op<Tm, Tx, Ty, OP>(S, x, b, y, k, col, nlev, ncol, nedge, nz, ntr, ce);
+    }
+  } else if (ent < ncol + nedge) {
+    const int e = ent - ncol;
+    int t[8];
+    if (OP != OP_SMOOTH0) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) t[i] = est[(size_t)i * nedge + e];
+    }
+#pragma unroll
+    for (int q = 0; q < kRowChunk; ++q) {
+      const int k = k0 + q;
+      if (k < nlev) hrow_op<Tm, Tx, Ty, OP>(S, x, b, y, lout, k, e, ncol, nedge, nz, ntr, t, omega);
+    }
+  }
+}
+
+// grid of the row kernels: entities (columns, plus edges unless column-owned) x layer chunks
+inline dim3 row_grid(const hyb_ctx *c, bool edges_only) {
+  int ents = edges_only ? c->nedge : c->ncol + c->nedge;
+  return dim3(nblk(ents), (c->nlev + kRowChunk) / kRowChunk);
+}
+inline int row_ent0(const hyb_ctx *c, bool edges_only) { return edges_only ? c->ncol : 0; }
+
+// Tridiagonal column solve with precomputed LU factors, one column per lane:
+//   fac[0][i] = l_k (unit lower), fac[1][i] = 1/u_k, fac[2][i] = c_k/u_k, i = k*ncol + col,
+//   y_k = R_k - l_k y_{k-1};  x_k = y_k/u_k - (c_k/u_k) x_{k+1};  out_k = base_k + omega x_k,
+// base = 0 (ZERO), xin, or xin plus the injected coarse correction (ADDC).  The loads of KC levels
+// are issued together before the recurrence runs over them, so a column pays the memory latency
+// once per KC levels; y_k/u_k waits in LDS for the back substitution.
+template <typename T, bool ZERO, bool ADDC>
+__global__ void __launch_bounds__(kColBlock) k_column_solve(const T *__restrict__ R, const T *__restrict__ fac,
+                                                            size_t fstride, const T *__restrict__ xin,
+                                                            const T *__restrict__ xc, T *__restrict__ xout,
+                                                            int nrows, int ncol, int ncolc,
+                                                            const int32_t *__restrict__ parent, T omega) {
+  constexpr int KC = 8;
+  extern __shared__ unsigned char smem_raw[];
+  T *wv = reinterpret_cast<T *>(smem_raw);
+  const int tid = threadIdx.x, bd = blockDim.x;
+  const int col = blockIdx.x * bd + tid;
+  if (col >= ncol) return;
+  T y = 0;
+  for (int k0 = 0; k0 < nrows; k0 += KC) {
+    T rv[KC], lv[KC], iv[KC];
+#pragma unroll
+    for (int q = 0; q < KC; ++q) {
+      int k = k0 + q;
+      if (k < nrows) {
+        size_t i = (size_t)k * ncol + col;
+        rv[q] = R[i];
+        lv[q] = fac[i];
+        iv[q] = fac[fstride + i];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < KC; ++q) {
+      int k = k0 + q;
+      if (k < nrows) {
+        y = rv[q] - lv[q] * y;
+        wv[(size_t)k * bd + tid] = y * iv[q];
       }
     }
   }
-  T xk = 0;
-  for (int k = nlev; k >= 0; --k) {
+  const int pc = ADDC ? parent[col] : 0;
+  T x = 0;
+  for (int k1 = nrows - 1; k1 >= 0; k1 -= KC) {
+    T cv[KC], bv[KC], w[KC];
+#pragma unroll
+    for (int q = 0; q < KC; ++q) {
+      int k = k1 - q;
+      if (k >= 0) {
+        size_t i = (size_t)k * ncol + col;
+        cv[q] = fac[2 * fstride + i];
+        w[q] = wv[(size_t)k * bd + tid];
+        bv[q] = 0;
+        if (!ZERO) {
+          bv[q] = xin[i];
+          if (ADDC) bv[q] += xc[(size_t)k * ncolc + pc];
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < KC; ++q) {
+      int k = k1 - q;
+      if (k >= 0) {
+        x = w[q] - cv[q] * x;
+        xout[(size_t)k * ncol + col] = bv[q] + omega * x;
+      }
+    }
+  }
+}
+
+// LU factors of the tridiagonal S^zz of every column (setup): row k has a_k (to facet k-1),
+// b_k (diagonal), c_k (to facet k+1); l_k = a_k / u_{k-1}, u_k = b_k - l_k c_{k-1}.
+__global__ void k_thomas_factor(const double *__restrict__ S, double *__restrict__ fac, int nlev, int ncol,
+                                size_t nz, size_t ntr) {
+  int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= ncol) return;
+  double up = 1.0, cprev = 0.0;
+  for (int k = 0; k <= nlev; ++k) {
     size_t F = (size_t)k * ncol + col;
-    xk = dpv[(size_t)k * blockDim.x + tid] - cpv[(size_t)k * blockDim.x + tid] * xk;
-    T base = ZERO ? (T)0 : lin[F];
-    lout[F] = base + omega * xk;
+    double a = S[ntr + F], b = S[F], c = S[2 * ntr + F];
+    double l = (k == 0) ? 0.0 : a / up;
+    double u = b - l * cprev;
+    fac[F] = l;
+    fac[nz + F] = 1.0 / u;
+    fac[2 * nz + F] = c / u;
+    up = u;
+    cprev = c;
   }
 }
 
@@ -190,83 +278,61 @@ __global__ void k_prolong(const T *__restrict__ dpi, T *__restrict__ lam, int nl
   lam[F] += v;
 }
 
-// Block-Jacobi sweep of the pressure multigrid (Sec. 2.3):
-//   x_out = x_in + omega H_z^-1 (b - H x_in), H_z = the column (tridiagonal) part of H.
-// ZERO: x_in = 0.  ADDC: x_in is the fine iterate plus the injected coarse correction
-// (prolongation fused into the first post-smoothing sweep).
-template <typename T, bool ZERO, bool ADDC>
-__global__ void __launch_bounds__(kColBlock) k_mg_smooth(const T *__restrict__ H, const T *__restrict__ b,
-                                                         const T *__restrict__ xin, const T *__restrict__ xc,
-                                                         T *__restrict__ xout, int nlev, int ncol, int ncolc,
-                                                         const int32_t *__restrict__ nbr,
-                                                         const int32_t *__restrict__ parent, T omega) {
-  extern __shared__ unsigned char smem_raw[];
-  T *cpv = reinterpret_cast<T *>(smem_raw);
-  T *dpv = cpv + (size_t)nlev * blockDim.x;
-  int tid = threadIdx.x;
-  int col = blockIdx.x * blockDim.x + tid;
-  if (col >= ncol) return;
+// Block-Jacobi sweep of the pressure multigrid (Sec. 2.3),
+//   x_out = x_in + omega H_z^-1 (b - H x_in),  H_z = the column (tridiagonal) part of H,
+// in two launches: the 7-point residual (one thread per cell) and the column solve with the LU
+// factors of H_z computed at setup (one column per lane).  ADDC: x_in is the fine iterate plus
+// the injected coarse correction (prolongation fused into the first post-smoothing sweep).
+template <typename T, bool ADDC>
+__global__ void k_mg_residual(const T *__restrict__ H, const T *__restrict__ b, const T *__restrict__ xin,
+                              const T *__restrict__ xc, T *__restrict__ r, int nlev, int ncol, int ncolc,
+                              const int32_t *__restrict__ nbr, const int32_t *__restrict__ parent) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
   size_t n = (size_t)nlev * ncol;
-  int nb[4], pc = 0, pn[4] = {0, 0, 0, 0};
-#pragma unroll
-  for (int f = 0; f < 4; ++f) nb[f] = nbr[(size_t)f * ncol + col];
-  if (ADDC) {
-    pc = parent[col];
-#pragma unroll
-    for (int f = 0; f < 4; ++f) pn[f] = parent[nb[f]];
-  }
-  auto X = [&](int k, int cc, int pcc) -> T {
-    T v = xin[(size_t)k * ncol + cc];
-    if (ADDC) v += xc[(size_t)k * ncolc + pcc];
+  if (c >= (int)n) return;
+  int k = c / ncol, col = c - k * ncol;
+  auto X = [&](int kk, int cc) -> T {
+    T v = xin[(size_t)kk * ncol + cc];
+    if (ADDC) v += xc[(size_t)kk * ncolc + parent[cc]];
     return v;
   };
-  T cprev = 0, dprev = 0;
+  T hx = H[c] * X(k, col);
+#pragma unroll
+  for (int f = 0; f < 4; ++f) hx += H[(1 + f) * n + c] * X(k, nbr[(size_t)f * ncol + col]);
+  if (k > 0) hx += H[5 * n + c] * X(k - 1, col);
+  if (k < nlev - 1) hx += H[6 * n + c] * X(k + 1, col);
+  r[c] = b[c] - hx;
+}
+
+// LU factors of H_z per column (setup): a = coupling below, b = diagonal, c = coupling above.
+__global__ void k_mg_factor(const double *__restrict__ H, double *__restrict__ fac, int nlev, int ncol) {
+  int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= ncol) return;
+  size_t n = (size_t)nlev * ncol;
+  double up = 1.0, cprev = 0.0;
   for (int k = 0; k < nlev; ++k) {
     size_t c = (size_t)k * ncol + col;
-    T r = b[c];
-    T a = H[5 * n + c], d = H[c], u = H[6 * n + c];
-    if (!ZERO) {
-      T hx = d * X(k, col, pc);
-#pragma unroll
-      for (int f = 0; f < 4; ++f) hx += H[(1 + f) * n + c] * X(k, nb[f], pn[f]);
-      if (k > 0) hx += a * X(k - 1, col, pc);
-      if (k < nlev - 1) hx += u * X(k + 1, col, pc);
-      r -= hx;
-    }
-    T inv = (T)1 / (d - a * cprev);
-    cprev = u * inv;
-    dprev = (r - a * dprev) * inv;
-    cpv[(size_t)k * blockDim.x + tid] = cprev;
-    dpv[(size_t)k * blockDim.x + tid] = dprev;
-  }
-  T xk = 0;
-  for (int k = nlev - 1; k >= 0; --k) {
-    xk = dpv[(size_t)k * blockDim.x + tid] - cpv[(size_t)k * blockDim.x + tid] * xk;
-    T base = ZERO ? (T)0 : X(k, col, pc);
-    xout[(size_t)k * ncol + col] = base + omega * xk;
+    double a = H[5 * n + c], d = H[c], u = H[6 * n + c];
+    double l = (k == 0) ? 0.0 : a / up;
+    double piv = d - l * cprev;
+    fac[c] = l;
+    fac[n + c] = 1.0 / piv;
+    fac[2 * n + c] = u / piv;
+    up = piv;
+    cprev = u;
   }
 }
 
-// Coarse right-hand side: b_c = R (b - H x), R = sum over the four children.
+// Coarse right-hand side b_c = R r: sum of the fine residual r = b - H x over the four children.
 template <typename T>
-__global__ void k_mg_residual_restrict(const T *__restrict__ H, const T *__restrict__ b, const T *__restrict__ x,
-                                       T *__restrict__ bc, int nlev, int ncolf, int ncolc,
-                                       const int32_t *__restrict__ children, const int32_t *__restrict__ nbrf) {
+__global__ void k_mg_restrict_sum(const T *__restrict__ r, T *__restrict__ bc, int nlev, int ncolf, int ncolc,
+                                  const int32_t *__restrict__ children) {
   int cc = blockIdx.x * blockDim.x + threadIdx.x;
   if (cc >= nlev * ncolc) return;
   int k = cc / ncolc, P = cc - k * ncolc;
-  size_t n = (size_t)nlev * ncolf;
   T s = 0;
-  for (int q = 0; q < 4; ++q) {
-    int col = children[(size_t)q * ncolc + P];
-    size_t c = (size_t)k * ncolf + col;
-    T hx = H[c] * x[c];
 #pragma unroll
-    for (int f = 0; f < 4; ++f) hx += H[(1 + f) * n + c] * x[(size_t)k * ncolf + nbrf[(size_t)f * ncolf + col]];
-    if (k > 0) hx += H[5 * n + c] * x[c - ncolf];
-    if (k < nlev - 1) hx += H[6 * n + c] * x[c + ncolf];
-    s += b[c] - hx;
-  }
+  for (int q = 0; q < 4; ++q) s += r[(size_t)k * ncolf + children[(size_t)q * ncolc + P]];
   bc[cc] = s;
 }
 
@@ -305,19 +371,32 @@ const float *pick<float>(const double *, const float *f) {
 template <typename T>
 hipError_t line_smooth(hyb_ctx *c, const T *S, const T *B, const T *lin, T *lout, bool zero) {
   const LevelDev &L0 = c->lv[0];
-  size_t shm = 2 * sizeof(T) * (size_t)(c->nlev + 1) * kColBlock;
-  int fam = zero ? F_LINE_SMOOTH0 : F_LINE_SMOOTH;
-  int slot = prof_begin(c, fam);
+  const T *fac = pick<T>(c->zfac, c->zfacf);
+  T *R = (T *)c->tR;
   T om = (T)c->p.omega;
+  size_t ntr = (size_t)c->ntrace, nz = (size_t)c->nz;
+  size_t shm = sizeof(T) * (size_t)(c->nlev + 1) * kColBlock;
+  int fam = zero ? F_SMOOTH_ROWS0 : F_SMOOTH_ROWS;
+  int slot = prof_begin(c, fam);
+  dim3 grid = row_grid(c, zero);
   if (zero)
-    hipLaunchKernelGGL((k_line_smooth<T, true>), dim3(nblk(c->ncol, kColBlock)), dim3(kColBlock), shm, c->stream,
-                       S, B, lin, lout, c->nlev, c->ncol, c->nedge, (size_t)c->nz, (size_t)c->ntrace, L0.col_edge,
-                       L0.own, L0.est, om);
+    hipLaunchKernelGGL((k_rows<T, T, T, OP_SMOOTH0>), grid, dim3(kBlock), 0, c->stream, S, lin, B, R, lout, c->nlev,
+                       c->ncol, c->nedge, nz, ntr, row_ent0(c, true), L0.col_edge, L0.est, om);
   else
-    hipLaunchKernelGGL((k_line_smooth<T, false>), dim3(nblk(c->ncol, kColBlock)), dim3(kColBlock), shm,
-                       c->stream, S, B, lin, lout, c->nlev, c->ncol, c->nedge, (size_t)c->nz, (size_t)c->ntrace,
-                       L0.col_edge, L0.own, L0.est, om);
+    hipLaunchKernelGGL((k_rows<T, T, T, OP_SMOOTH>), grid, dim3(kBlock), 0, c->stream, S, lin, B, R, lout, c->nlev,
+                       c->ncol, c->nedge, nz, ntr, 0, L0.col_edge, L0.est, om);
   prof_end(c, fam, slot);
+  HYB_TRY(hipGetLastError());
+  slot = prof_begin(c, F_THOMAS);
+  if (zero)
+    hipLaunchKernelGGL((k_column_solve<T, true, false>), dim3(nblk(c->ncol, kColBlock)), dim3(kColBlock), shm,
+                       c->stream, B, fac, nz, lin, (const T *)nullptr, lout, c->nlev + 1, c->ncol, 1,
+                       (const int32_t *)nullptr, om);
+  else
+    hipLaunchKernelGGL((k_column_solve<T, false, false>), dim3(nblk(c->ncol, kColBlock)), dim3(kColBlock), shm,
+                       c->stream, (const T *)R, fac, nz, lin, (const T *)nullptr, lout, c->nlev + 1, c->ncol, 1,
+                       (const int32_t *)nullptr, om);
+  prof_end(c, F_THOMAS, slot);
   return hipGetLastError();
 }
 
@@ -325,29 +404,31 @@ template <typename T>
 hipError_t mg_smooth(hyb_ctx *c, int l, const T *b, const T *xin, const T *xc, T *xout, int mode) {
   const LevelDev &Lv = c->lv[l];
   const T *H = pick<T>(Lv.H, Lv.Hf);
-  size_t shm = 2 * sizeof(T) * (size_t)c->nlev * kColBlock;
+  const T *fac = pick<T>(Lv.zf, Lv.zff);
+  T *r = (T *)Lv.r;
+  size_t n = (size_t)c->nlev * Lv.ncol;
+  size_t shm = sizeof(T) * (size_t)c->nlev * kColBlock;
   int ncolc = (l + 1 < c->nlevels) ? c->lv[l + 1].ncol : 1;
   T om = (T)c->p.omega_p;
-  dim3 g(nblk(Lv.ncol, kColBlock)), bl(kColBlock);
+  dim3 gc(nblk(Lv.ncol, kColBlock)), bc(kColBlock), gr(nblk(n)), br(kBlock);
   int slot = prof_begin(c, F_MG_SMOOTH);
-  if (mode == 0)
-    hipLaunchKernelGGL((k_mg_smooth<T, true, false>), g, bl, shm, c->stream, H, b, xin, xc, xout, c->nlev, Lv.ncol,
-                       ncolc, Lv.nbr, Lv.parent, om);
-  else if (mode == 1)
-    hipLaunchKernelGGL((k_mg_smooth<T, false, false>), g, bl, shm, c->stream, H, b, xin, xc, xout, c->nlev,
-                       Lv.ncol, ncolc, Lv.nbr, Lv.parent, om);
-  else
-    hipLaunchKernelGGL((k_mg_smooth<T, false, true>), g, bl, shm, c->stream, H, b, xin, xc, xout, c->nlev,
-                       Lv.ncol, ncolc, Lv.nbr, Lv.parent, om);
+  if (mode == 0) {
+    hipLaunchKernelGGL((k_column_solve<T, true, false>), gc, bc, shm, c->stream, b, fac, n, xin, xc, xout, c->nlev,
+                       Lv.ncol, ncolc, Lv.parent, om);
+  } else if (mode == 1) {
+    hipLaunchKernelGGL((k_mg_residual<T, false>), gr, br, 0, c->stream, H, b, xin, xc, r, c->nlev, Lv.ncol, ncolc,
+                       Lv.nbr, Lv.parent);
+    hipLaunchKernelGGL((k_column_solve<T, false, false>), gc, bc, shm, c->stream, (const T *)r, fac, n, xin, xc, xout,
+                       c->nlev, Lv.ncol, ncolc, Lv.parent, om);
+  } else {
+    hipLaunchKernelGGL((k_mg_residual<T, true>), gr, br, 0, c->stream, H, b, xin, xc, r, c->nlev, Lv.ncol, ncolc,
+                       Lv.nbr, Lv.parent);
+    hipLaunchKernelGGL((k_column_solve<T, false, true>), gc, bc, shm, c->stream, (const T *)r, fac, n, xin, xc, xout,
+                       c->nlev, Lv.ncol, ncolc, Lv.parent, om);
+  }
   prof_end(c, F_MG_SMOOTH, slot);
   return hipGetLastError();
 }
-
-#define HYB_TRY(x)                      \
-  do {                                  \
-    hipError_t e_ = (x);                \
-    if (e_ != hipSuccess) return e_;    \
-  } while (0)
 
 // One V-cycle on level l from a zero initial guess: right-hand side lv[l].b, result lv[l].x.
 template <typename T>
@@ -372,8 +453,10 @@ hipError_t vcycle(hyb_ctx *c, int l) {
   LevelDev &Lc = c->lv[l + 1];
   const T *H = pick<T>(Lv.H, Lv.Hf);
   int slot = prof_begin(c, F_RESTRICT);
-  hipLaunchKernelGGL((k_mg_residual_restrict<T>), dim3(nblk((size_t)c->nlev * Lc.ncol)), dim3(kBlock), 0, c->stream,
-                     H, b, (const T *)Lv.x, (T *)Lc.b, c->nlev, Lv.ncol, Lc.ncol, Lc.children, Lv.nbr);
+  hipLaunchKernelGGL((k_mg_residual<T, false>), dim3(nblk(n)), dim3(kBlock), 0, c->stream, H, b, (const T *)Lv.x,
+                     (const T *)nullptr, (T *)Lv.r, c->nlev, Lv.ncol, 1, Lv.nbr, (const int32_t *)nullptr);
+  hipLaunchKernelGGL((k_mg_restrict_sum<T>), dim3(nblk((size_t)c->nlev * Lc.ncol)), dim3(kBlock), 0, c->stream,
+                     (const T *)Lv.r, (T *)Lc.b, c->nlev, Lv.ncol, Lc.ncol, Lc.children);
   prof_end(c, F_RESTRICT, slot);
   HYB_TRY(hipGetLastError());
   HYB_TRY(vcycle<T>(c, l + 1));
@@ -397,12 +480,13 @@ template <typename Tm, typename Tx, typename Ty>
 hipError_t launch_trace_apply(hyb_ctx *c, const Tm *S, const Tx *x, const Ty *b, Ty *y, int mode) {
   const LevelDev &L0 = c->lv[0];
   int slot = prof_begin(c, F_TRACE_APPLY);
+  dim3 grid = row_grid(c, false);
   if (mode == 0)
-    hipLaunchKernelGGL((k_trace_apply<Tm, Tx, Ty, 0>), dim3(nblk(c->ntrace)), dim3(kBlock), 0, c->stream, S, x, b,
-                       y, c->nlev, c->ncol, c->nedge, (size_t)c->nz, (size_t)c->ntrace, L0.col_edge, L0.est);
+    hipLaunchKernelGGL((k_rows<Tm, Tx, Ty, OP_APPLY>), grid, dim3(kBlock), 0, c->stream, S, x, b, y, (Ty *)nullptr,
+                       c->nlev, c->ncol, c->nedge, (size_t)c->nz, (size_t)c->ntrace, 0, L0.col_edge, L0.est, (Ty)0);
   else
-    hipLaunchKernelGGL((k_trace_apply<Tm, Tx, Ty, 1>), dim3(nblk(c->ntrace)), dim3(kBlock), 0, c->stream, S, x, b,
-                       y, c->nlev, c->ncol, c->nedge, (size_t)c->nz, (size_t)c->ntrace, L0.col_edge, L0.est);
+    hipLaunchKernelGGL((k_rows<Tm, Tx, Ty, OP_RESID>), grid, dim3(kBlock), 0, c->stream, S, x, b, y, (Ty *)nullptr,
+                       c->nlev, c->ncol, c->nedge, (size_t)c->nz, (size_t)c->ntrace, 0, L0.col_edge, L0.est, (Ty)0);
   prof_end(c, F_TRACE_APPLY, slot);
   return hipGetLastError();
 }
@@ -469,19 +553,30 @@ template hipError_t precondition<float>(hyb_ctx *, const float *, float *);
 // The column kernels keep two (nlev+1)-long coefficient arrays per lane in LDS; allow the
 // dynamic LDS size they need (above the 64 KiB default for tall columns in FP64).
 hipError_t configure_kernels(int nlev) {
-  int need = (int)(2 * sizeof(double) * (size_t)(nlev + 1) * kColBlock);
+  int need = (int)(sizeof(double) * (size_t)(nlev + 1) * kColBlock);
   if (need <= 65536) return hipSuccess;
   const void *fns[] = {
-      (const void *)k_line_smooth<double, true>, (const void *)k_line_smooth<double, false>,
-      (const void *)k_line_smooth<float, true>,  (const void *)k_line_smooth<float, false>,
-      (const void *)k_mg_smooth<double, true, false>, (const void *)k_mg_smooth<double, false, false>,
-      (const void *)k_mg_smooth<double, false, true>, (const void *)k_mg_smooth<float, true, false>,
-      (const void *)k_mg_smooth<float, false, false>, (const void *)k_mg_smooth<float, false, true>};
+      (const void *)k_column_solve<double, true, false>, (const void *)k_column_solve<double, false, false>,
+      (const void *)k_column_solve<double, false, true>, (const void *)k_column_solve<float, true, false>,
+      (const void *)k_column_solve<float, false, false>, (const void *)k_column_solve<float, false, true>};
   for (const void *f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, need);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_mg_factor(hyb_ctx *c, int l) {
+  const LevelDev &Lv = c->lv[l];
+  hipLaunchKernelGGL(k_mg_factor, dim3(nblk(Lv.ncol, kColBlock)), dim3(kColBlock), 0, c->stream, Lv.H, Lv.zf, c->nlev,
+                     Lv.ncol);
+  return hipGetLastError();
+}
+
+hipError_t launch_thomas_factor(hyb_ctx *c) {
+  hipLaunchKernelGGL(k_thomas_factor, dim3(nblk(c->ncol, kColBlock)), dim3(kColBlock), 0, c->stream, c->S, c->zfac,
+                     c->nlev, c->ncol, (size_t)c->nz, (size_t)c->ntrace);
+  return hipGetLastError();
 }
 
 }  // namespace hyb

@@ -3,8 +3,9 @@
 Sizes: several column tiles (64 columns per wavefront) with ragged tails, a stretched grid,
 a horizontally varying theta* (hybrid operator only), and degenerate 2x2x1 meshes.
 Tolerances (FP64): operator application, condensation and recovery 1e-12 relative to the
-largest entry; the preconditioner (a fixed linear map) 1e-11; a solve to rtol 1e-13 against the
-sparse direct solution 1e-10 (relative 2-norm).
+largest entry; the preconditioner (a fixed linear map) 100 eps cond(H); a solve to rtol 1e-13
+against the sparse direct solution 1e-10 (relative 2-norm; 1e-8 for the dx/dz = 20 case whose
+trace operator has cond ~1e5).
 """
 
 import numpy as np
@@ -87,8 +88,13 @@ def test_precondition(name):
     s.precondition(dev(r), z)
     ref = orc.pc(r)
     err = rel_max(host(z), ref)
-    say(f"[precondition] {name}: rel err {err:.2e}")
-    assert err <= 1e-11
+    # both sides apply the same fixed linear map with backward-stable column solves in different
+    # rounding orders; the map contains the coarsest-level sweeps (an approximate H^-1), so the
+    # difference is bounded by a modest multiple of cond(H) * eps
+    cond_h = np.linalg.cond(orc.H.toarray())
+    tol = max(1e-12, 100 * np.finfo(float).eps * cond_h)
+    say(f"[precondition] {name}: rel err {err:.2e} (cond(H) {cond_h:.1e}, tol {tol:.1e})")
+    assert err <= tol
 
 
 @pytest.mark.gpu
