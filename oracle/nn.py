@@ -1,0 +1,130 @@
+"""Learned coarse correction network (test infrastructure, FP64 NumPy reference).
+
+The network maps a DG0 field (one value per cell, [L][ncol]) to a DG0 field through three 3D
+convolutions, 1 -> C -> C -> 1 channels, each tap set being the 3 x 3 horizontal neighbourhood of a
+column (the column, its four edge neighbours and four corner neighbours) times 5 vertical offsets
+(-2..2, zero padded above the lid and below the ground); ReLU after the first two layers.  This is
+the extra coarse-correction stage of the learned form (not part of the paper): its input is the
+scaled restriction Gamma P^T r' of the residual left by the two-level cycle, its target the cell
+average of the remaining error.
+
+Parity: pinned by central finite differences of the loss with respect to every weight group and
+the input (tests), by translation equivariance on the periodic box, and by one-hot weights that
+must reproduce shifted copies of the input.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+NH = 9  # horizontal taps: centre, W, E, S, N, SW, SE, NW, NE
+NV = 5  # vertical taps: dk = -2..2
+NT = NH * NV
+# horizontal direction of each tap and its opposite
+H_OFFSETS = [(0, 0), (-1, 0), (1, 0), (0, -1), (0, 1), (-1, -1), (1, -1), (-1, 1), (1, 1)]
+
+
+def neighbour_table(nx, ny):
+    """nb[h][col] = column at horizontal offset H_OFFSETS[h] on the periodic nx x ny box."""
+    col = np.arange(nx * ny)
+    ix, iy = col % nx, col // nx
+    return np.stack([((iy + dy) % ny) * nx + (ix + dx) % nx for (dx, dy) in H_OFFSETS]).astype(np.int64)
+
+
+def init_weights(channels=16, seed=0):
+    rng = np.random.default_rng(seed)
+    shapes = [(channels, 1), (channels, channels), (1, channels)]
+    W, b = [], []
+    for co, ci in shapes:
+        fan_in = ci * NT
+        W.append(rng.standard_normal((co, ci, NT)) * np.sqrt(2.0 / fan_in))
+        b.append(np.zeros(co))
+    W[-1] *= 0.1
+    return W, b
+
+
+def conv(x, W, bias, nb, nlev):
+    """x: (ci, L*ncol) -> (co, L*ncol); y[co, k, c] = b[co] + sum W[co, ci, t] x[ci, k+dk, nb[h, c]]."""
+    ci, n = x.shape
+    ncol = n // nlev
+    co = W.shape[0]
+    xr = x.reshape(ci, nlev, ncol)
+    y = np.repeat(bias[:, None], n, axis=1).reshape(co, nlev, ncol).copy()
+    for h in range(NH):
+        xh = xr[:, :, nb[h]]  # (ci, L, ncol): value at the neighbour column
+        for v in range(NV):
+            dk = v - 2
+            shifted = np.zeros_like(xh)
+            if dk >= 0:
+                shifted[:, : nlev - dk] = xh[:, dk:]
+            else:
+                shifted[:, -dk:] = xh[:, : nlev + dk]
+            y += np.einsum("oi,ilc->olc", W[:, :, h * NV + v], shifted)
+    return y.reshape(co, n)
+
+
+def conv_grads(x, W, dy, nb, nlev):
+    """Gradients of sum(dy * conv(x)) with respect to x, W and the bias."""
+    ci, n = x.shape
+    ncol = n // nlev
+    co = W.shape[0]
+    xr = x.reshape(ci, nlev, ncol)
+    dyr = dy.reshape(co, nlev, ncol)
+    dW = np.zeros_like(W)
+    dx = np.zeros((ci, nlev, ncol))
+    for h in range(NH):
+        xh = xr[:, :, nb[h]]
+        for v in range(NV):
+            dk = v - 2
+            shifted = np.zeros_like(xh)
+            if dk >= 0:
+                shifted[:, : nlev - dk] = xh[:, dk:]
+            else:
+                shifted[:, -dk:] = xh[:, : nlev + dk]
+            dW[:, :, h * NV + v] = np.einsum("olc,ilc->oi", dyr, shifted)
+            # transpose: contribution W^T dy placed back at (k + dk, nb[h, c])
+            g = np.einsum("oi,olc->ilc", W[:, :, h * NV + v], dyr)
+            back = np.zeros_like(g)
+            if dk >= 0:
+                back[:, dk:] = g[:, : nlev - dk]
+            else:
+                back[:, : nlev + dk] = g[:, -dk:]
+            np.add.at(dx, (slice(None), slice(None), nb[h]), back)
+    return dx.reshape(ci, n), dW, dyr.sum(axis=(1, 2))
+
+
+def forward(x, W, b, nb, nlev):
+    """Returns the output and the post-activation values of every layer (x is (L*ncol,))."""
+    acts = [x[None, :]]
+    h = acts[0]
+    for i in range(3):
+        h = conv(h, W[i], b[i], nb, nlev)
+        if i < 2:
+            h = np.maximum(h, 0.0)
+        acts.append(h)
+    return h[0], acts
+
+
+def loss_and_grads(x, target, W, b, nb, nlev):
+    """Mean squared error over cells and its gradients (dW list, db list, dx)."""
+    y, acts = forward(x, W, b, nb, nlev)
+    n = y.shape[0]
+    diff = y - target
+    loss = float(np.mean(diff * diff))
+    dy = (2.0 / n) * diff[None, :]
+    dWs, dbs = [None] * 3, [None] * 3
+    for i in (2, 1, 0):
+        if i < 2:
+            dy = dy * (acts[i + 1] > 0.0)
+        dx, dWs[i], dbs[i] = conv_grads(acts[i], W[i], dy, nb, nlev)
+        dy = dx
+    return loss, dWs, dbs, dy[0]
+
+
+def bf16_round(a):
+    """Round FP64 values to the nearest bfloat16 (ties to even), returned as FP64."""
+    f = np.asarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    u = ((u + 0x7FFF + lsb) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
