@@ -99,6 +99,8 @@ typedef struct {
   /* flexible GMRES restart length and arithmetic of the preconditioner (HYB_PREC_*) */
   int32_t restart;
   int32_t precision;
+  /* 1: hyb_solve appends the learned coarse correction (hyb_nn_*) after every two-level cycle */
+  int32_t learned;
 } hyb_params;
 
 typedef struct {
@@ -109,6 +111,7 @@ typedef struct {
   double *history;      /* optional host array: Arnoldi residual estimate per iteration */
   int32_t history_cap;
   int32_t history_len;
+  int32_t fallbacks;    /* learned stage skipped because its output was not finite */
 } hyb_info;
 
 /* Create a context for one mesh.  stream: a hipStream_t (NULL = default stream).
@@ -174,6 +177,29 @@ int hyb_sizes(const hyb_ctx *ctx, int64_t *ntrace, int64_t *ncell, int64_t *work
    "restrict", "prolong", "krylov", "cell_solve". */
 int hyb_profile(hyb_ctx *ctx, int32_t enable);
 int hyb_profile_read(hyb_ctx *ctx, const char *family, int64_t *launches, double *total_ms);
+
+/* Restriction of a trace vector r [ntrace] to cells [nlev][ncol]: mode 0 Gamma P^T r (the scaled
+   right-hand side of the coarse level in Alg. 2), mode 1 the facet average P^T r / P^T 1. */
+int hyb_restrict(hyb_ctx *ctx, const double *r, double *cells, int32_t mode);
+
+/* Learned coarse correction (not part of the paper): a network of three 3D convolutions on cell
+   fields (1 -> 16 -> 16 -> 1 channels; taps = the 3x3 horizontal neighbourhood of a column times
+   5 vertical offsets, zero padded at ground and lid; ReLU after the first two), BF16 weights with
+   FP32 accumulation.  With params.learned = 1, hyb_solve follows every two-level cycle z = M(v)
+   with r' = v - S z, c = Gamma P^T r', s = rms(c), z += s P N(c / s); a non-finite network output
+   leaves z unchanged (counted in hyb_info.fallbacks).
+   Parameters (FP32, host arrays of hyb_nn_param_count() values): W1 [16][1][45], b1 [16],
+   W2 [16][16][45], b2 [16], W3 [1][16][45], b3 [1], tap index = 5*h + (dk+2), h = centre, W, E,
+   S, N, SW, SE, NW, NE.  Cell fields x, t, y are DEVICE FP32 arrays [nsamp][nlev][ncol]. */
+int hyb_nn_param_count(void);
+int hyb_nn_set_weights(hyb_ctx *ctx, const float *weights, int64_t n);
+int hyb_nn_get_weights(hyb_ctx *ctx, float *weights, int64_t n);
+int hyb_nn_forward(hyb_ctx *ctx, const float *x, float *y, int32_t nsamp);
+/* mean squared error of N(x) against t over all cells and samples; gradient (host, may be NULL)
+   in the parameter layout above */
+int hyb_nn_loss_grad(hyb_ctx *ctx, const float *x, const float *t, int32_t nsamp, float *loss, float *grad);
+/* one Adam step (beta 0.9 / 0.999, eps 1e-8) on the FP32 master weights; loss (host) may be NULL */
+int hyb_nn_train_step(hyb_ctx *ctx, const float *x, const float *t, int32_t nsamp, float lr, float *loss);
 
 const char *hyb_last_error(const hyb_ctx *ctx);
 void hyb_destroy(hyb_ctx *ctx);

@@ -41,13 +41,14 @@ class _Params(ctypes.Structure):
                 ("tau_theta", ctypes.c_double), ("cp", ctypes.c_double), ("rd", ctypes.c_double),
                 ("omega", ctypes.c_double), ("n_pre", ctypes.c_int32), ("n_post", ctypes.c_int32),
                 ("omega_p", ctypes.c_double), ("mg_pre", ctypes.c_int32), ("mg_post", ctypes.c_int32),
-                ("mg_coarse_sweeps", ctypes.c_int32), ("restart", ctypes.c_int32), ("precision", ctypes.c_int32)]
+                ("mg_coarse_sweeps", ctypes.c_int32), ("restart", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("learned", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("restarts", ctypes.c_int32),
                 ("rel_res", ctypes.c_double), ("history", _f64p), ("history_cap", ctypes.c_int32),
-                ("history_len", ctypes.c_int32)]
+                ("history_len", ctypes.c_int32), ("fallbacks", ctypes.c_int32)]
 
 
 @dataclass
@@ -70,6 +71,7 @@ class Params:
     mg_coarse_sweeps: int = 30
     restart: int = 30
     precision: int = PREC_FP64
+    learned: int = 0
 
     def to_c(self) -> _Params:
         return _Params(**{f.name: getattr(self, f.name) for f in fields(self)})
@@ -78,7 +80,8 @@ class Params:
 ABI_FUNCTIONS = [
     "hyb_create", "hyb_set_params", "hyb_assemble_local", "hyb_condense", "hyb_trace_apply",
     "hyb_precondition", "hyb_solve", "hyb_recover", "hyb_sizes", "hyb_profile", "hyb_profile_read",
-    "hyb_last_error", "hyb_destroy",
+    "hyb_restrict", "hyb_nn_param_count", "hyb_nn_set_weights", "hyb_nn_get_weights", "hyb_nn_forward",
+    "hyb_nn_loss_grad", "hyb_nn_train_step", "hyb_last_error", "hyb_destroy",
 ]
 
 _lib = None
@@ -95,7 +98,12 @@ def load(path: str = LIB_PATH):
 
     if not os.path.exists(path):
         raise RuntimeError(f"HIP library not built: {path} (run paper_2210_11797_amd/build.py)")
-    lib = ctypes.CDLL(path)
+    _lib = declare(ctypes.CDLL(path))
+    return _lib
+
+
+def declare(lib):
+    """Set the ctypes signatures of every entry point of include/hyb.h on a loaded library."""
     vp = ctypes.c_void_p
     lib.hyb_create.argtypes = [ctypes.POINTER(_Mesh), ctypes.POINTER(_Params), vp, ctypes.POINTER(vp)]
     lib.hyb_set_params.argtypes = [vp, ctypes.POINTER(_Params)]
@@ -110,6 +118,13 @@ def load(path: str = LIB_PATH):
     lib.hyb_profile.argtypes = [vp, ctypes.c_int32]
     lib.hyb_profile_read.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
                                      ctypes.POINTER(ctypes.c_double)]
+    lib.hyb_restrict.argtypes = [vp, vp, vp, ctypes.c_int32]
+    lib.hyb_nn_param_count.argtypes = []
+    lib.hyb_nn_set_weights.argtypes = [vp, vp, ctypes.c_int64]
+    lib.hyb_nn_get_weights.argtypes = [vp, vp, ctypes.c_int64]
+    lib.hyb_nn_forward.argtypes = [vp, vp, vp, ctypes.c_int32]
+    lib.hyb_nn_loss_grad.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_float), vp]
+    lib.hyb_nn_train_step.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.c_float, ctypes.POINTER(ctypes.c_float)]
     lib.hyb_last_error.argtypes = [vp]
     lib.hyb_last_error.restype = ctypes.c_char_p
     lib.hyb_destroy.argtypes = [vp]
@@ -117,17 +132,16 @@ def load(path: str = LIB_PATH):
     for name in ABI_FUNCTIONS:
         if name not in ("hyb_last_error", "hyb_destroy"):
             getattr(lib, name).restype = ctypes.c_int
-    _lib = lib
     return lib
 
 
-def _ptr(t, n=None, what="array"):
+def _ptr(t, n=None, what="array", dtype="float64"):
     import torch
 
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError(f"{what}: expected a CUDA tensor")
-    if t.dtype != torch.float64 or not t.is_contiguous():
-        raise TypeError(f"{what}: expected a contiguous float64 tensor")
+    if t.dtype != getattr(torch, dtype) or not t.is_contiguous():
+        raise TypeError(f"{what}: expected a contiguous {dtype} tensor")
     if n is not None and t.numel() != n:
         raise ValueError(f"{what}: expected {n} entries, got {t.numel()}")
     return ctypes.c_void_p(t.data_ptr())
@@ -236,12 +250,53 @@ class HybSolver:
                                             _ptr(lam, self.ntrace, "lambda"), float(rtol), int(maxit),
                                             ctypes.byref(info)), "hyb_solve")
         return dict(status=rc, iters=info.iters, restarts=info.restarts, rel_res=info.rel_res,
-                    history=[hist[i] for i in range(info.history_len)])
+                    history=[hist[i] for i in range(info.history_len)], fallbacks=info.fallbacks)
 
     def recover(self, r_ub, r_pi, lam, u_b, pi):
         self._check(self.lib.hyb_recover(self.h, _ptr(r_ub, 6 * self.ncell, "r_ub"), _ptr(r_pi, self.ncell, "r_pi"),
                                          _ptr(lam, self.ntrace, "lambda"), _ptr(u_b, 6 * self.ncell, "u_b"),
                                          _ptr(pi, self.ncell, "pi")), "hyb_recover")
+
+    def restrict(self, r, cells, mode=0):
+        self._check(self.lib.hyb_restrict(self.h, _ptr(r, self.ntrace, "r"), _ptr(cells, self.ncell, "cells"),
+                                          int(mode)), "hyb_restrict")
+
+    # -- learned coarse correction --
+    def nn_param_count(self):
+        return int(self.lib.hyb_nn_param_count())
+
+    def nn_set_weights(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        self._check(self.lib.hyb_nn_set_weights(self.h, w.ctypes.data_as(ctypes.c_void_p), w.size),
+                    "hyb_nn_set_weights")
+
+    def nn_get_weights(self):
+        w = np.empty(self.nn_param_count(), np.float32)
+        self._check(self.lib.hyb_nn_get_weights(self.h, w.ctypes.data_as(ctypes.c_void_p), w.size),
+                    "hyb_nn_get_weights")
+        return w
+
+    def nn_forward(self, x, y, nsamp=1):
+        n = self.ncell * nsamp
+        self._check(self.lib.hyb_nn_forward(self.h, _ptr(x, n, "x", "float32"), _ptr(y, n, "y", "float32"),
+                                            int(nsamp)), "hyb_nn_forward")
+
+    def nn_loss_grad(self, x, t, nsamp=1, want_grad=True):
+        n = self.ncell * nsamp
+        loss = ctypes.c_float()
+        g = np.empty(self.nn_param_count(), np.float32) if want_grad else None
+        self._check(self.lib.hyb_nn_loss_grad(self.h, _ptr(x, n, "x", "float32"), _ptr(t, n, "t", "float32"),
+                                              int(nsamp), ctypes.byref(loss),
+                                              g.ctypes.data_as(ctypes.c_void_p) if g is not None else None),
+                    "hyb_nn_loss_grad")
+        return loss.value, g
+
+    def nn_train_step(self, x, t, nsamp, lr):
+        n = self.ncell * nsamp
+        loss = ctypes.c_float()
+        self._check(self.lib.hyb_nn_train_step(self.h, _ptr(x, n, "x", "float32"), _ptr(t, n, "t", "float32"),
+                                               int(nsamp), float(lr), ctypes.byref(loss)), "hyb_nn_train_step")
+        return loss.value
 
     def profile(self, enable: bool):
         self._check(self.lib.hyb_profile(self.h, 1 if enable else 0), "hyb_profile")

@@ -20,8 +20,8 @@ int reduction_blocks();
 
 namespace {
 
-const char *kFamilyNames[F_COUNT] = {"smooth_rows", "smooth_rows0", "thomas",  "trace_apply", "mg_smooth",
-                                     "restrict",    "prolong",      "krylov",  "cell_solve"};
+const char *kFamilyNames[F_COUNT] = {"smooth_rows", "smooth_rows0", "thomas", "trace_apply", "mg_smooth",
+                                     "restrict",    "prolong",      "krylov", "cell_solve",  "nn"};
 
 int fail(hyb_ctx *c, int code, const std::string &msg) {
   if (c) c->err = msg;
@@ -72,6 +72,7 @@ int check_params(hyb_ctx *c, const hyb_params *p) {
   if (p->restart < 1 || p->restart > 200) return fail(c, HYB_EINVAL, "restart must be in [1, 200]");
   if (p->precision != HYB_PREC_FP64 && p->precision != HYB_PREC_MIXED)
     return fail(c, HYB_EINVAL, "unknown precision mode");
+  if (p->learned != 0 && p->learned != 1) return fail(c, HYB_EINVAL, "learned must be 0 or 1");
   return HYB_OK;
 }
 
@@ -170,6 +171,7 @@ void free_all(hyb_ctx *c) {
   for (auto &f : c->fam)
     for (auto ev : f.ev) (void)hipEventDestroy(ev);
   c->fam.clear();
+  nn_free(c);
 }
 
 int alloc_krylov(hyb_ctx *c) {
@@ -396,7 +398,10 @@ int hyb_solve(hyb_ctx *c, const double *b, double *lam, double rtol, int32_t max
   std::vector<double> R((size_t)(m + 1) * m, 0.0), g(m + 1), cs(m), sn(m), y(m);
   if (info) {
     info->iters = 0, info->restarts = 0, info->history_len = 0, info->rel_res = 0, info->status = HYB_OK;
+    info->fallbacks = 0;
   }
+  const bool learned = c->p.learned && c->nn.loaded;
+  if (c->p.learned && !c->nn.loaded) return fail(c, HYB_ESTATE, "learned stage requested without weights");
   // ||b||
   CHECK_HIP(launch_multidot(c, b, 0, 0, b, n, nrm, true), "norm b");
   CHECK_HIP(hipMemcpyAsync(hh, nrm, sizeof(double), hipMemcpyDeviceToHost, c->stream), "d2h");
@@ -408,7 +413,11 @@ int hyb_solve(hyb_ctx *c, const double *b, double *lam, double rtol, int32_t max
     return HYB_OK;
   }
   int its = 0, restarts = 0, status = HYB_NOT_CONVERGED;
-  double rel = 0.0;
+  double rel = 0.0, fb0 = 0.0;
+  if (learned && c->nn.scal) {
+    CHECK_HIP(hipMemcpyAsync(&fb0, c->nn.scal + 2, sizeof(double), hipMemcpyDeviceToHost, c->stream), "d2h");
+    CHECK_HIP(hipStreamSynchronize(c->stream), "sync");
+  }
   for (;;) {
     // true residual r = b - S lam into V_0
     CHECK_HIP((launch_trace_apply<double, double, double>(c, c->S, lam, b, V, 1)), "residual");
@@ -438,10 +447,12 @@ int hyb_solve(hyb_ctx *c, const double *b, double *lam, double rtol, int32_t max
         float *zf = (float *)c->Z + (size_t)j * n;
         CHECK_HIP(launch_convert(c, vj, (float *)c->tIn, n), "convert");
         CHECK_HIP(precondition<float>(c, (const float *)c->tIn, zf), "precondition");
+        if (learned) CHECK_HIP(learned_stage<float>(c, vj, zf), "learned stage");
         CHECK_HIP((launch_trace_apply<double, float, double>(c, c->S, zf, nullptr, w, 0)), "matvec");
       } else {
         double *zj = (double *)c->Z + (size_t)j * n;
         CHECK_HIP(precondition<double>(c, vj, zj), "precondition");
+        if (learned) CHECK_HIP(learned_stage<double>(c, vj, zj), "learned stage");
         CHECK_HIP((launch_trace_apply<double, double, double>(c, c->S, zj, nullptr, w, 0)), "matvec");
       }
       double *col = &R[(size_t)j * (m + 1)];
@@ -548,6 +559,12 @@ int hyb_solve(hyb_ctx *c, const double *b, double *lam, double rtol, int32_t max
     info->restarts = restarts;
     info->rel_res = rel;
     info->status = status;
+    if (learned) {
+      double fb = 0.0;
+      CHECK_HIP(hipMemcpyAsync(&fb, c->nn.scal + 2, sizeof(double), hipMemcpyDeviceToHost, c->stream), "d2h");
+      CHECK_HIP(hipStreamSynchronize(c->stream), "sync");
+      info->fallbacks = (int32_t)(fb - fb0);
+    }
   }
   return status;
 }
@@ -592,6 +609,64 @@ int hyb_profile_read(hyb_ctx *c, const char *family, int64_t *launches, double *
     return HYB_OK;
   }
   return fail(c, HYB_EINVAL, std::string("unknown kernel family ") + family);
+}
+
+int hyb_restrict(hyb_ctx *c, const double *r, double *cells, int32_t mode) {
+  if (!c) return HYB_EINVAL;
+  if (!c->condensed) return fail(c, HYB_ESTATE, "restrict before condense");
+  if (!r || !cells || (mode != 0 && mode != 1)) return fail(c, HYB_EINVAL, "bad restrict arguments");
+  CHECK_HIP(launch_restrict_cells(c, r, cells, mode), "restrict");
+  return HYB_OK;
+}
+
+int hyb_nn_param_count(void) { return nn_param_count(); }
+
+int hyb_nn_set_weights(hyb_ctx *c, const float *w, int64_t n) {
+  if (!c) return HYB_EINVAL;
+  if (!w || n != nn_param_count()) return fail(c, HYB_EINVAL, "weights: wrong size");
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(w[i])) return fail(c, HYB_EINVAL, "weights: not finite");
+  CHECK_HIP(nn_setup(c), "nn setup");
+  CHECK_HIP(nn_set_weights(c, w), "nn set weights");
+  c->nn.loaded = true;
+  return HYB_OK;
+}
+
+int hyb_nn_get_weights(hyb_ctx *c, float *w, int64_t n) {
+  if (!c) return HYB_EINVAL;
+  if (!c->nn.loaded) return fail(c, HYB_ESTATE, "no weights");
+  if (!w || n != nn_param_count()) return fail(c, HYB_EINVAL, "weights: wrong size");
+  CHECK_HIP(nn_get_weights(c, w), "nn get weights");
+  return HYB_OK;
+}
+
+int hyb_nn_forward(hyb_ctx *c, const float *x, float *y, int32_t nsamp) {
+  if (!c) return HYB_EINVAL;
+  if (!c->nn.loaded) return fail(c, HYB_ESTATE, "no weights");
+  if (!x || !y || nsamp < 1) return fail(c, HYB_EINVAL, "bad forward arguments");
+  CHECK_HIP(nn_forward(c, x, y, nsamp), "nn forward");
+  return HYB_OK;
+}
+
+int hyb_nn_loss_grad(hyb_ctx *c, const float *x, const float *t, int32_t nsamp, float *loss, float *grad) {
+  if (!c) return HYB_EINVAL;
+  if (!c->nn.loaded) return fail(c, HYB_ESTATE, "no weights");
+  if (!x || !t || nsamp < 1) return fail(c, HYB_EINVAL, "bad loss arguments");
+  CHECK_HIP(nn_loss_grad(c, x, t, nsamp, loss), "nn loss/grad");
+  if (grad) {
+    CHECK_HIP(hipStreamSynchronize(c->stream), "sync");
+    CHECK_HIP(hipMemcpy(grad, c->nn.g, nn_param_count() * sizeof(float), hipMemcpyDeviceToHost), "d2h grad");
+  }
+  return HYB_OK;
+}
+
+int hyb_nn_train_step(hyb_ctx *c, const float *x, const float *t, int32_t nsamp, float lr, float *loss) {
+  if (!c) return HYB_EINVAL;
+  if (!c->nn.loaded) return fail(c, HYB_ESTATE, "no weights");
+  if (!x || !t || nsamp < 1 || !(lr > 0)) return fail(c, HYB_EINVAL, "bad train arguments");
+  CHECK_HIP(nn_loss_grad(c, x, t, nsamp, loss), "nn loss/grad");
+  CHECK_HIP(nn_adam(c, lr), "nn adam");
+  return HYB_OK;
 }
 
 const char *hyb_last_error(const hyb_ctx *c) { return c ? c->err.c_str() : "null context"; }

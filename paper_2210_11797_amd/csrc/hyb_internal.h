@@ -35,6 +35,24 @@ struct LevelDev {
   void *b = nullptr, *x = nullptr, *y = nullptr, *r = nullptr;  // [nlev*ncol] work vectors
 };
 
+constexpr int kNNChannels = 16;
+
+// Learned coarse-correction network state (device buffers).
+struct NNState {
+  float *w = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;  // FP32 parameters, Adam moments, gradient
+  uint16_t *wb = nullptr;                                         // BF16 copy of the weights
+  int32_t *isbf = nullptr;                                        // parameter -> BF16 index (-1: bias)
+  int32_t *nb9 = nullptr;                                         // [9][ncol] 3x3 horizontal neighbourhood
+  float *a1 = nullptr, *a2 = nullptr, *y = nullptr;               // activations [nsamp][C][ncell]
+  float *d1 = nullptr, *d2 = nullptr, *dy = nullptr;              // their gradients
+  float *part = nullptr, *tmpg = nullptr, *lpart = nullptr;       // reduction scratch
+  float *cin = nullptr, *cout = nullptr;                          // learned stage input / output [ncell]
+  double *scal = nullptr;                                         // learned stage scalars (device)
+  size_t cap = 0;                                                 // cells x samples the activations hold
+  long step = 0;
+  bool loaded = false;
+};
+
 struct ProfFamily {
   std::string name;
   std::vector<hipEvent_t> ev;  // start/stop pairs
@@ -85,6 +103,9 @@ struct hyb_ctx {
 
   bool prof = false;
   std::vector<hyb::ProfFamily> fam;
+
+  hyb::NNState nn;
+  double *cell64 = nullptr;  // [ncell] scratch of the learned stage
 };
 
 namespace hyb {
@@ -105,6 +126,7 @@ enum Family {
   F_PROLONG,
   F_KRYLOV,
   F_CELL,
+  F_NN,               // learned coarse-correction stage
   F_COUNT
 };
 
@@ -155,5 +177,20 @@ template <typename Tz>
 hipError_t launch_update_solution(hyb_ctx *c, const Tz *Z, size_t ldz, int nv, const double *y_dev,
                                   double *x, size_t n);
 hipError_t launch_scale(hyb_ctx *c, double *w, size_t n, double s);
+
+// ----- learned coarse correction (nn.hip) -----
+int nn_param_count();
+hipError_t nn_setup(hyb_ctx *c);
+hipError_t nn_set_weights(hyb_ctx *c, const float *host_w);
+hipError_t nn_get_weights(hyb_ctx *c, float *host_w);
+hipError_t nn_forward(hyb_ctx *c, const float *x, float *out, int nsamp);
+hipError_t nn_loss_grad(hyb_ctx *c, const float *x, const float *target, int nsamp, float *loss_host);
+hipError_t nn_adam(hyb_ctx *c, float lr);
+void nn_free(hyb_ctx *c);
+// restriction of a trace vector to cells: mode 0 Gamma P^T r, mode 1 P^T r / P^T 1 (cell average)
+hipError_t launch_restrict_cells(hyb_ctx *c, const double *r, double *cells, int mode);
+// learned stage: z += s P N(c / s), c = Gamma P^T (r - S z), s = rms(c); skipped if not finite
+template <typename Tz>
+hipError_t learned_stage(hyb_ctx *c, const double *r, Tz *z);
 
 }  // namespace hyb

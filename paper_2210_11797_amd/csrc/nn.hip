@@ -1,0 +1,544 @@
+// Learned coarse-correction network: three 3D convolutions on DG0 fields (1 -> C -> C -> 1
+// channels, taps = the 3x3 horizontal neighbourhood of a column x 5 vertical offsets, zero padded
+// below the ground and above the lid), ReLU after the first two.  Weights are kept in FP32 (master
+// copy, Adam state) and used in BF16; activations and accumulation are FP32.
+//
+// Fields are [sample][channel][k][col].  One thread computes all output channels of one cell, so
+// every gathered input value is reused for all of them; the weights of a layer sit in LDS.
+// Weight gradients are reduced per workgroup and then summed over workgroups in a fixed order.
+#include <hip/hip_bf16.h>
+
+#include "hyb_internal.h"
+
+namespace hyb {
+
+namespace {
+
+constexpr int NHT = 9, NVT = 5, NTAP = NHT * NVT;
+// opposite horizontal direction of each tap (centre, W, E, S, N, SW, SE, NW, NE)
+__constant__ int kOpp[NHT] = {0, 2, 1, 4, 3, 8, 7, 6, 5};
+
+inline unsigned nblk(size_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
+
+__device__ __forceinline__ float bf2f(uint16_t v) { return __uint_as_float(((uint32_t)v) << 16); }
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  // round to nearest, ties to even (finite inputs)
+  uint32_t u = __float_as_uint(f);
+  uint32_t lsb = (u >> 16) & 1u;
+  return (uint16_t)((u + 0x7FFFu + lsb) >> 16);
+}
+
+// y[s][co][cell] = bias[co] + sum_{ci,t} W[co][ci][t] x[s][ci][k+dk][nb[h][col]]   (RELU: max(.,0))
+template <int CI, int CO, bool RELU>
+__global__ void __launch_bounds__(kBlock) k_conv_fwd(const float *__restrict__ x, const uint16_t *__restrict__ wb,
+                                                     const float *__restrict__ bias, float *__restrict__ y, int nlev,
+                                                     int ncol, int nsamp, const int32_t *__restrict__ nb9) {
+  __shared__ float w[CO * CI * NTAP];
+  for (int i = threadIdx.x; i < CO * CI * NTAP; i += blockDim.x) w[i] = bf2f(wb[i]);
+  __syncthreads();
+  const size_t n = (size_t)nlev * ncol;
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= n * nsamp) return;
+  const int s = (int)(gid / n);
+  const int cell = (int)(gid - (size_t)s * n);
+  const int k = cell / ncol, col = cell - k * ncol;
+  float acc[CO];
+#pragma unroll
+  for (int co = 0; co < CO; ++co) acc[co] = bias[co];
+  const float *xs = x + (size_t)s * CI * n;
+  for (int h = 0; h < NHT; ++h) {
+    const int c2 = nb9[(size_t)h * ncol + col];
+#pragma unroll
+    for (int v = 0; v < NVT; ++v) {
+      const int kk = k + v - 2;
+      if (kk < 0 || kk >= nlev) continue;
+      const int t = h * NVT + v;
+#pragma unroll
+      for (int ci = 0; ci < CI; ++ci) {
+        const float xv = xs[(size_t)ci * n + (size_t)kk * ncol + c2];
+#pragma unroll
+        for (int co = 0; co < CO; ++co) acc[co] += w[(co * CI + ci) * NTAP + t] * xv;
+      }
+    }
+  }
+  float *ys = y + (size_t)s * CO * n;
+#pragma unroll
+  for (int co = 0; co < CO; ++co) ys[(size_t)co * n + cell] = RELU ? fmaxf(acc[co], 0.f) : acc[co];
+}
+
+// dx[s][ci][cell] = (sum_{co,t} W[co][ci][t] dy[s][co][k-dk][nb[opp h][col]]) * (xin > 0 if MASK)
+template <int CI, int CO, bool MASK>
+__global__ void __launch_bounds__(kBlock) k_conv_bwd_data(const float *__restrict__ dy, const uint16_t *__restrict__ wb,
+                                                          const float *__restrict__ xin, float *__restrict__ dx,
+                                                          int nlev, int ncol, int nsamp,
+                                                          const int32_t *__restrict__ nb9) {
+  __shared__ float w[CO * CI * NTAP];
+  for (int i = threadIdx.x; i < CO * CI * NTAP; i += blockDim.x) w[i] = bf2f(wb[i]);
+  __syncthreads();
+  const size_t n = (size_t)nlev * ncol;
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= n * nsamp) return;
+  const int s = (int)(gid / n);
+  const int cell = (int)(gid - (size_t)s * n);
+  const int k = cell / ncol, col = cell - k * ncol;
+  float acc[CI];
+#pragma unroll
+  for (int ci = 0; ci < CI; ++ci) acc[ci] = 0.f;
+  const float *dys = dy + (size_t)s * CO * n;
+  for (int h = 0; h < NHT; ++h) {
+    const int c2 = nb9[(size_t)kOpp[h] * ncol + col];
+#pragma unroll
+    for (int v = 0; v < NVT; ++v) {
+      const int kk = k - (v - 2);
+      if (kk < 0 || kk >= nlev) continue;
+      const int t = h * NVT + v;
+#pragma unroll
+      for (int co = 0; co < CO; ++co) {
+        const float g = dys[(size_t)co * n + (size_t)kk * ncol + c2];
+#pragma unroll
+        for (int ci = 0; ci < CI; ++ci) acc[ci] += w[(co * CI + ci) * NTAP + t] * g;
+      }
+    }
+  }
+  float *dxs = dx + (size_t)s * CI * n;
+  const float *xs = xin + (size_t)s * CI * n;
+#pragma unroll
+  for (int ci = 0; ci < CI; ++ci) {
+    float v = acc[ci];
+    if (MASK && !(xs[(size_t)ci * n + cell] > 0.f)) v = 0.f;
+    dxs[(size_t)ci * n + cell] = v;
+  }
+}
+
+// Per-workgroup partial weight gradients over a tile of cells:
+//   part[blk][co][ci][t] = sum_cells dy[co][cell] x[ci][k+dk][nb[h][col]],  part[blk][wsize+co] = sum dy[co]
+constexpr int kTile = 512;
+template <int CI, int CO>
+__global__ void __launch_bounds__(kBlock) k_conv_bwd_weight(const float *__restrict__ dy, const float *__restrict__ x,
+                                                            float *__restrict__ part, int nlev, int ncol, int nsamp,
+                                                            const int32_t *__restrict__ nb9) {
+  constexpr int WS = CO * CI * NTAP;
+  __shared__ float sdy[kTile][CO];
+  __shared__ int scell[kTile];
+  const size_t n = (size_t)nlev * ncol, total = n * nsamp;
+  const size_t t0 = (size_t)blockIdx.x * kTile;
+  const int cnt = (int)min((size_t)kTile, total - t0);
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+    size_t g = t0 + i;
+    int s = (int)(g / n), cell = (int)(g - (size_t)s * n);
+#pragma unroll
+    for (int co = 0; co < CO; ++co) sdy[i][co] = dy[((size_t)s * CO + co) * n + cell];
+    scell[i] = (int)(g - (size_t)s * n);
+  }
+  __syncthreads();
+  float *out = part + (size_t)blockIdx.x * (WS + CO);
+  // one thread per (ci, tap) pair accumulates all CO outputs
+  for (int p = threadIdx.x; p < CI * NTAP; p += blockDim.x) {
+    const int ci = p / NTAP, t = p - ci * NTAP;
+    const int h = t / NVT, dk = t - h * NVT - 2;
+    float acc[CO];
+#pragma unroll
+    for (int co = 0; co < CO; ++co) acc[co] = 0.f;
+    for (int i = 0; i < cnt; ++i) {
+      const size_t g = t0 + i;
+      const int s = (int)(g / n), cell = scell[i];
+      const int k = cell / ncol, col = cell - k * ncol;
+      const int kk = k + dk;
+      if (kk < 0 || kk >= nlev) continue;
+      const float xv = x[((size_t)s * CI + ci) * n + (size_t)kk * ncol + nb9[(size_t)h * ncol + col]];
+#pragma unroll
+      for (int co = 0; co < CO; ++co) acc[co] += sdy[i][co] * xv;
+    }
+#pragma unroll
+    for (int co = 0; co < CO; ++co) out[(co * CI + ci) * NTAP + t] = acc[co];
+  }
+  if (threadIdx.x < CO) {
+    float sb = 0.f;
+    for (int i = 0; i < cnt; ++i) sb += sdy[i][threadIdx.x];
+    out[WS + threadIdx.x] = sb;
+  }
+}
+
+// grad[j] = sum over workgroups of part[blk][j] (fixed order)
+__global__ void k_sum_parts(const float *__restrict__ part, int nparts, int len, float *__restrict__ grad) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= len) return;
+  float s = 0.f;
+  for (int b = 0; b < nparts; ++b) s += part[(size_t)b * len + j];
+  grad[j] = s;
+}
+
+// dy = 2 (y - t) / N and partial sums of (y - t)^2
+__global__ void __launch_bounds__(kBlock) k_mse(const float *__restrict__ y, const float *__restrict__ t,
+                                                float *__restrict__ dy, size_t total, float *__restrict__ part) {
+  __shared__ float red[kBlock / 64];
+  float acc = 0.f;
+  const float sc = 2.f / (float)total;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    float d = y[i] - t[i];
+    dy[i] = sc * d;
+    acc += d * d;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float s = 0.f;
+    for (int q = 0; q < kBlock / 64; ++q) s += red[q];
+    part[blockIdx.x] = s;
+  }
+}
+
+// Adam on the FP32 master weights; refresh the BF16 copy of the weights (not of the biases)
+__global__ void k_adam(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
+                       const float *__restrict__ g, uint16_t *__restrict__ wb, const int32_t *__restrict__ isbf,
+                       int len, float lr, float b1, float b2, float eps, float c1, float c2) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= len) return;
+  float gj = g[j];
+  float mj = b1 * m[j] + (1.f - b1) * gj;
+  float vj = b2 * v[j] + (1.f - b2) * gj * gj;
+  m[j] = mj;
+  v[j] = vj;
+  float wj = w[j] - lr * (mj / c1) / (sqrtf(vj / c2) + eps);
+  w[j] = wj;
+  int q = isbf[j];
+  if (q >= 0) wb[q] = f2bf(wj);
+}
+
+__global__ void k_weights_to_bf16(const float *__restrict__ w, uint16_t *__restrict__ wb,
+                                  const int32_t *__restrict__ isbf, int len) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= len) return;
+  int q = isbf[j];
+  if (q >= 0) wb[q] = f2bf(w[j]);
+}
+
+// cells[c] = mode 0: Gamma_c sum_F w_F r_F;  mode 1: sum_F w_F r_F / sum_F w_F  (w = 1/2, 1 on
+// ground and lid facets: the transpose of the facet-average prolongation)
+__global__ void k_restrict_cells(const double *__restrict__ r, const double *__restrict__ gamma,
+                                 double *__restrict__ out, int nlev, int ncol, int nedge, size_t nz,
+                                 const int32_t *__restrict__ col_edge, int mode) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nlev * ncol) return;
+  int k = c / ncol, col = c - k * ncol;
+  size_t hb = nz + (size_t)k * nedge;
+  double s = 0.0;
+#pragma unroll
+  for (int f = 0; f < 4; ++f) s += r[hb + col_edge[(size_t)f * ncol + col]];
+  s *= 0.5;
+  double wb = (k == 0 ? 1.0 : 0.5), wt = (k == nlev - 1 ? 1.0 : 0.5);
+  s += wb * r[(size_t)k * ncol + col] + wt * r[(size_t)(k + 1) * ncol + col];
+  out[c] = mode == 0 ? gamma[c] * s : s / (2.0 + wb + wt);
+}
+
+// sum of squares of a vector into part[blk]
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_sumsq(const T *__restrict__ x, size_t n, double *__restrict__ part) {
+  __shared__ double red[kBlock / 64];
+  double acc = 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    double v = (double)x[i];
+    acc += v * v;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < kBlock / 64; ++q) t += red[q];
+    part[blockIdx.x] = t;
+  }
+}
+
+__global__ void k_sum_into(const double *__restrict__ part, int nb, double *__restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += part[b];
+  *out = s;
+}
+
+// x = c / s with s = sqrt(scal[0] / n) (0 when s = 0)
+__global__ void k_normalise(const double *__restrict__ c, const double *__restrict__ scal, float *__restrict__ x,
+                            size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = sqrt(scal[0] / (double)n);
+  x[i] = s > 0.0 ? (float)(c[i] / s) : 0.f;
+}
+
+// z_F += s (P y)_F when the network output is finite (scal[1] = sum y^2); else count a fallback
+template <typename Tz>
+__global__ void k_prolong_scaled(const float *__restrict__ y, double *__restrict__ scal, Tz *__restrict__ z,
+                                 int nlev, int ncol, int nedge, size_t nz, size_t ntr,
+                                 const int32_t *__restrict__ edge_col) {
+  size_t F = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool ok = isfinite(scal[1]);
+  if (!ok) {
+    if (F == 0) scal[2] += 1.0;
+    return;
+  }
+  if (F >= ntr) return;
+  const double s = sqrt(scal[0] / (double)((size_t)nlev * ncol));
+  double v;
+  if (F < nz) {
+    int k = (int)(F / ncol), col = (int)(F - (size_t)k * ncol);
+    if (k == 0)
+      v = y[col];
+    else if (k == nlev)
+      v = y[(size_t)(nlev - 1) * ncol + col];
+    else
+      v = 0.5 * ((double)y[(size_t)(k - 1) * ncol + col] + (double)y[(size_t)k * ncol + col]);
+  } else {
+    size_t h = F - nz;
+    int k = (int)(h / nedge), e = (int)(h - (size_t)k * nedge);
+    v = 0.5 * ((double)y[(size_t)k * ncol + edge_col[e]] + (double)y[(size_t)k * ncol + edge_col[nedge + e]]);
+  }
+  z[F] = (Tz)((double)z[F] + s * v);
+}
+
+__global__ void k_zero_scal(double *p, int n) {
+  if (threadIdx.x < n) p[threadIdx.x] = 0.0;
+}
+
+}  // namespace
+
+hipError_t launch_restrict_cells(hyb_ctx *c, const double *r, double *cells, int mode) {
+  const LevelDev &L0 = c->lv[0];
+  hipLaunchKernelGGL(k_restrict_cells, dim3(nblk(c->ncell)), dim3(kBlock), 0, c->stream, r, c->gamma, cells, c->nlev,
+                     c->ncol, c->nedge, (size_t)c->nz, L0.col_edge, mode);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
+// Host side.  Parameter vector layout (FP32): W1 [C][1][45], b1 [C], W2 [C][C][45], b2 [C],
+// W3 [1][C][45], b3 [1].  The BF16 copy holds W1, W2, W3 back to back.
+// ---------------------------------------------------------------------------------------------
+static constexpr int C = kNNChannels;
+static constexpr int W1N = C * 1 * NTAP, W2N = C * C * NTAP, W3N = 1 * C * NTAP;
+static constexpr int OFF_W1 = 0, OFF_B1 = W1N, OFF_W2 = OFF_B1 + C, OFF_B2 = OFF_W2 + W2N, OFF_W3 = OFF_B2 + C,
+                     OFF_B3 = OFF_W3 + W3N, NPARAM = OFF_B3 + 1;
+
+int nn_param_count() { return NPARAM; }
+
+hipError_t nn_setup(hyb_ctx *c) {
+  NNState &s = c->nn;
+  if (s.w) return hipSuccess;
+  hipError_t e;
+  auto A = [&](void **p, size_t b) -> hipError_t {
+    hipError_t r = hipMalloc(p, b);
+    if (r == hipSuccess) c->bytes += b;
+    return r;
+  };
+  if ((e = A((void **)&s.w, NPARAM * 4)) || (e = A((void **)&s.m, NPARAM * 4)) || (e = A((void **)&s.v, NPARAM * 4)) ||
+      (e = A((void **)&s.g, NPARAM * 4)) || (e = A((void **)&s.wb, (W1N + W2N + W3N) * 2)) ||
+      (e = A((void **)&s.isbf, NPARAM * 4)) || (e = A((void **)&s.nb9, 9 * (size_t)c->ncol * 4)))
+    return e;
+  std::vector<int32_t> isbf(NPARAM, -1);
+  for (int j = 0; j < W1N; ++j) isbf[OFF_W1 + j] = j;
+  for (int j = 0; j < W2N; ++j) isbf[OFF_W2 + j] = W1N + j;
+  for (int j = 0; j < W3N; ++j) isbf[OFF_W3 + j] = W1N + W2N + j;
+  if ((e = hipMemcpy(s.isbf, isbf.data(), NPARAM * 4, hipMemcpyHostToDevice))) return e;
+  // 3x3 horizontal neighbourhood from the edge neighbours: corners are the W/E neighbours of the
+  // S/N neighbours
+  std::vector<int32_t> nbr(4 * (size_t)c->ncol), nb9(9 * (size_t)c->ncol);
+  if ((e = hipMemcpy(nbr.data(), c->lv[0].nbr, nbr.size() * 4, hipMemcpyDeviceToHost))) return e;
+  const size_t n = c->ncol;
+  for (size_t col = 0; col < n; ++col) {
+    int W = nbr[0 * n + col], E = nbr[1 * n + col], S = nbr[2 * n + col], N = nbr[3 * n + col];
+    int v[9] = {(int)col, W, E, S, N, nbr[0 * n + S], nbr[1 * n + S], nbr[0 * n + N], nbr[1 * n + N]};
+    for (int h = 0; h < 9; ++h) nb9[h * n + col] = v[h];
+  }
+  if ((e = hipMemcpy(s.nb9, nb9.data(), nb9.size() * 4, hipMemcpyHostToDevice))) return e;
+  std::vector<float> zero(NPARAM, 0.f);
+  if ((e = hipMemcpy(s.m, zero.data(), NPARAM * 4, hipMemcpyHostToDevice)) ||
+      (e = hipMemcpy(s.v, zero.data(), NPARAM * 4, hipMemcpyHostToDevice)) ||
+      (e = hipMemcpy(s.w, zero.data(), NPARAM * 4, hipMemcpyHostToDevice)))
+    return e;
+  s.step = 0;
+  return hipSuccess;
+}
+
+hipError_t nn_set_weights(hyb_ctx *c, const float *host_w) {
+  NNState &s = c->nn;
+  hipError_t e = hipMemcpy(s.w, host_w, NPARAM * 4, hipMemcpyHostToDevice);
+  if (e) return e;
+  std::vector<float> zero(NPARAM, 0.f);
+  if ((e = hipMemcpy(s.m, zero.data(), NPARAM * 4, hipMemcpyHostToDevice)) ||
+      (e = hipMemcpy(s.v, zero.data(), NPARAM * 4, hipMemcpyHostToDevice)))
+    return e;
+  s.step = 0;
+  hipLaunchKernelGGL(k_weights_to_bf16, dim3(nblk(NPARAM)), dim3(kBlock), 0, c->stream, s.w, s.wb, s.isbf, NPARAM);
+  e = hipGetLastError();
+  if (e) return e;
+  return hipStreamSynchronize(c->stream);
+}
+
+hipError_t nn_get_weights(hyb_ctx *c, float *host_w) {
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e) return e;
+  return hipMemcpy(host_w, c->nn.w, NPARAM * 4, hipMemcpyDeviceToHost);
+}
+
+static hipError_t ensure_acts(hyb_ctx *c, int nsamp) {
+  NNState &s = c->nn;
+  size_t n = (size_t)c->ncell * nsamp;
+  if (s.cap >= n) return hipSuccess;
+  for (float **p : {&s.a1, &s.a2, &s.y, &s.d1, &s.d2, &s.dy})
+    if (*p) (void)hipFree(*p), *p = nullptr;
+  if (s.part) (void)hipFree(s.part), s.part = nullptr;
+  hipError_t e;
+  if ((e = hipMalloc((void **)&s.a1, n * C * 4)) || (e = hipMalloc((void **)&s.a2, n * C * 4)) ||
+      (e = hipMalloc((void **)&s.d1, n * C * 4)) || (e = hipMalloc((void **)&s.d2, n * C * 4)) ||
+      (e = hipMalloc((void **)&s.y, n * 4)) || (e = hipMalloc((void **)&s.dy, n * 4)))
+    return e;
+  size_t nparts = (n + kTile - 1) / kTile;
+  if ((e = hipMalloc((void **)&s.part, nparts * (size_t)(W2N + C) * 4))) return e;
+  c->bytes += n * (4 * C + 2) * 4 + nparts * (size_t)(W2N + C) * 4;
+  s.cap = n;
+  return hipSuccess;
+}
+
+// Forward pass of nsamp fields x [nsamp][ncell] -> out [nsamp][ncell] (activations kept for backward).
+hipError_t nn_forward(hyb_ctx *c, const float *x, float *out, int nsamp) {
+  NNState &s = c->nn;
+  hipError_t e = ensure_acts(c, nsamp);
+  if (e) return e;
+  size_t n = (size_t)c->ncell * nsamp;
+  dim3 g(nblk(n)), b(kBlock);
+  int L = c->nlev, nc = c->ncol;
+  hipLaunchKernelGGL((k_conv_fwd<1, C, true>), g, b, 0, c->stream, x, s.wb, s.w + OFF_B1, s.a1, L, nc, nsamp, s.nb9);
+  hipLaunchKernelGGL((k_conv_fwd<C, C, true>), g, b, 0, c->stream, s.a1, s.wb + W1N, s.w + OFF_B2, s.a2, L, nc, nsamp,
+                     s.nb9);
+  hipLaunchKernelGGL((k_conv_fwd<C, 1, false>), g, b, 0, c->stream, s.a2, s.wb + W1N + W2N, s.w + OFF_B3, out, L, nc,
+                     nsamp, s.nb9);
+  return hipGetLastError();
+}
+
+template <int CI, int CO>
+static hipError_t weight_grad(hyb_ctx *c, const float *dy, const float *x, int nsamp, float *grad_w, float *grad_b) {
+  NNState &s = c->nn;
+  size_t n = (size_t)c->ncell * nsamp;
+  int nparts = (int)((n + kTile - 1) / kTile);
+  constexpr int WS = CO * CI * NTAP;
+  hipLaunchKernelGGL((k_conv_bwd_weight<CI, CO>), dim3(nparts), dim3(kBlock), 0, c->stream, dy, x, s.part, c->nlev,
+                     c->ncol, nsamp, s.nb9);
+  hipError_t e = hipGetLastError();
+  if (e) return e;
+  // sum: weights then biases (contiguous WS + CO per part; the grad layout keeps W and b apart)
+  hipLaunchKernelGGL(k_sum_parts, dim3(nblk(WS + CO)), dim3(kBlock), 0, c->stream, s.part, nparts, WS + CO, s.tmpg);
+  e = hipGetLastError();
+  if (e) return e;
+  e = hipMemcpyAsync(grad_w, s.tmpg, WS * 4, hipMemcpyDeviceToDevice, c->stream);
+  if (e) return e;
+  return hipMemcpyAsync(grad_b, s.tmpg + WS, CO * 4, hipMemcpyDeviceToDevice, c->stream);
+}
+
+// Loss (mean squared error over all cells and samples) and gradients into s.g.
+hipError_t nn_loss_grad(hyb_ctx *c, const float *x, const float *target, int nsamp, float *loss_host) {
+  NNState &s = c->nn;
+  // the activation buffers (s.y among them) must exist at this size before s.y is passed on
+  hipError_t e = ensure_acts(c, nsamp);
+  if (e) return e;
+  if ((e = nn_forward(c, x, s.y, nsamp))) return e;
+  if (!s.tmpg) {
+    if ((e = hipMalloc((void **)&s.tmpg, (W2N + C) * 4))) return e;
+    if ((e = hipMalloc((void **)&s.lpart, 1024 * 4))) return e;
+  }
+  size_t n = (size_t)c->ncell * nsamp;
+  unsigned nb = std::min<unsigned>(1024, nblk(n));
+  hipLaunchKernelGGL(k_mse, dim3(nb), dim3(kBlock), 0, c->stream, s.y, target, s.dy, n, s.lpart);
+  if ((e = hipGetLastError())) return e;
+  dim3 g(nblk(n)), b(kBlock);
+  int L = c->nlev, nc = c->ncol;
+  // layer 3: dy -> dW3, db3, d(a2) masked by a2 > 0
+  if ((e = weight_grad<C, 1>(c, s.dy, s.a2, nsamp, s.g + OFF_W3, s.g + OFF_B3))) return e;
+  hipLaunchKernelGGL((k_conv_bwd_data<C, 1, true>), g, b, 0, c->stream, s.dy, s.wb + W1N + W2N, s.a2, s.d2, L, nc,
+                     nsamp, s.nb9);
+  if ((e = hipGetLastError())) return e;
+  // layer 2
+  if ((e = weight_grad<C, C>(c, s.d2, s.a1, nsamp, s.g + OFF_W2, s.g + OFF_B2))) return e;
+  hipLaunchKernelGGL((k_conv_bwd_data<C, C, true>), g, b, 0, c->stream, s.d2, s.wb + W1N, s.a1, s.d1, L, nc, nsamp,
+                     s.nb9);
+  if ((e = hipGetLastError())) return e;
+  // layer 1 (input x)
+  if ((e = weight_grad<1, C>(c, s.d1, x, nsamp, s.g + OFF_W1, s.g + OFF_B1))) return e;
+  if (loss_host) {
+    std::vector<float> lp(nb);
+    if ((e = hipMemcpyAsync(lp.data(), s.lpart, nb * 4, hipMemcpyDeviceToHost, c->stream))) return e;
+    if ((e = hipStreamSynchronize(c->stream))) return e;
+    double acc = 0.0;
+    for (unsigned i = 0; i < nb; ++i) acc += lp[i];
+    *loss_host = (float)(acc / (double)n);
+  }
+  return hipSuccess;
+}
+
+hipError_t nn_adam(hyb_ctx *c, float lr) {
+  NNState &s = c->nn;
+  s.step++;
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  float c1 = 1.f - powf(b1, (float)s.step), c2 = 1.f - powf(b2, (float)s.step);
+  hipLaunchKernelGGL(k_adam, dim3(nblk(NPARAM)), dim3(kBlock), 0, c->stream, s.w, s.m, s.v, s.g, s.wb, s.isbf, NPARAM,
+                     lr, b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+// The learned coarse correction applied after the two-level cycle: r' = r - S z,
+// c = Gamma P^T r', s = rms(c), z += s P N(c / s).  Everything stays on the device; a non-finite
+// network output leaves z unchanged and increments the fallback counter scal[2].
+template <typename Tz>
+hipError_t learned_stage(hyb_ctx *c, const double *r, Tz *z) {
+  NNState &s = c->nn;
+  hipError_t e;
+  size_t n = (size_t)c->ncell;
+  if (!s.cin) {
+    if ((e = hipMalloc((void **)&s.cin, n * 4)) || (e = hipMalloc((void **)&s.cout, n * 4)) ||
+        (e = hipMalloc((void **)&s.scal, 4 * sizeof(double))))
+      return e;
+    hipLaunchKernelGGL(k_zero_scal, dim3(1), dim3(64), 0, c->stream, s.scal, 4);
+    if ((e = hipGetLastError())) return e;
+    c->bytes += n * 8 + 32;
+  }
+  if (!c->cell64) {
+    if ((e = hipMalloc((void **)&c->cell64, n * 8))) return e;
+    c->bytes += n * 8;
+  }
+  int slot = prof_begin(c, F_NN);
+  if ((e = launch_trace_apply<double, Tz, double>(c, c->S, z, r, c->t64, 1))) return e;
+  if ((e = launch_restrict_cells(c, c->t64, c->cell64, 0))) return e;
+  unsigned nb = std::min<unsigned>(1024, nblk(n));
+  double *part = c->partial;  // Krylov reduction scratch (>= 1024 doubles)
+  hipLaunchKernelGGL((k_sumsq<double>), dim3(nb), dim3(kBlock), 0, c->stream, c->cell64, n, part);
+  hipLaunchKernelGGL(k_sum_into, dim3(1), dim3(64), 0, c->stream, part, (int)nb, s.scal);
+  hipLaunchKernelGGL(k_normalise, dim3(nblk(n)), dim3(kBlock), 0, c->stream, c->cell64, s.scal, s.cin, n);
+  if ((e = hipGetLastError())) return e;
+  if ((e = nn_forward(c, s.cin, s.cout, 1))) return e;
+  hipLaunchKernelGGL((k_sumsq<float>), dim3(nb), dim3(kBlock), 0, c->stream, s.cout, n, part);
+  hipLaunchKernelGGL(k_sum_into, dim3(1), dim3(64), 0, c->stream, part, (int)nb, s.scal + 1);
+  const LevelDev &L0 = c->lv[0];
+  hipLaunchKernelGGL((k_prolong_scaled<Tz>), dim3(nblk(c->ntrace)), dim3(kBlock), 0, c->stream, s.cout, s.scal, z,
+                     c->nlev, c->ncol, c->nedge, (size_t)c->nz, (size_t)c->ntrace, L0.edge_col);
+  prof_end(c, F_NN, slot);
+  return hipGetLastError();
+}
+template hipError_t learned_stage<double>(hyb_ctx *, const double *, double *);
+template hipError_t learned_stage<float>(hyb_ctx *, const double *, float *);
+
+void nn_free(hyb_ctx *c) {
+  NNState &s = c->nn;
+  for (float **p : {&s.w, &s.m, &s.v, &s.g, &s.a1, &s.a2, &s.y, &s.d1, &s.d2, &s.dy, &s.part, &s.tmpg, &s.lpart,
+                    &s.cin, &s.cout})
+    if (*p) (void)hipFree(*p), *p = nullptr;
+  if (s.wb) (void)hipFree(s.wb), s.wb = nullptr;
+  if (s.isbf) (void)hipFree(s.isbf), s.isbf = nullptr;
+  if (s.nb9) (void)hipFree(s.nb9), s.nb9 = nullptr;
+  if (s.scal) (void)hipFree(s.scal), s.scal = nullptr;
+  if (c->cell64) (void)hipFree(c->cell64), c->cell64 = nullptr;
+  s.cap = 0;
+}
+
+}  // namespace hyb

@@ -1,0 +1,198 @@
+"""Drive the C ABI of a library built by build.py through the call sequences that matter for memory
+safety, on small synthetic boxes (run under AddressSanitizer by tests/test_memcheck.py).
+
+The sequences cover: setup, condensation, every trace-space operator, FGMRES in both precisions
+(with restarts), recovery, profiling, the learned stage (a training step as the first network call
+of a context, batch sizes that grow and shrink, the solve with the stage in both precisions, the
+non-finite fallback) and argument errors.  A few results are checked for sanity (the solve meets
+its tolerance, the network output matches the oracle's formula); the parity tests proper run on the
+GPU.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+from oracle import nn as onn  # noqa: E402
+from paper_2210_11797_amd import _native as N  # noqa: E402
+from paper_2210_11797_amd import learned  # noqa: E402
+from synth import make_box, make_rhs  # noqa: E402
+
+vp = ctypes.c_void_p
+
+
+def P(a):
+    return a.ctypes.data_as(vp)
+
+
+class Ctx:
+    def __init__(self, lib, prob, **kw):
+        self.lib, self.prob = lib, prob
+        keep = []
+        levels = N.levels_of(prob)
+        lv = (N._Level * len(levels))()
+        for i, L in enumerate(levels):
+            arr = {}
+            for key in ("col_edge", "edge_col", "edge_lf"):
+                a = np.ascontiguousarray(L[key], np.int32)
+                keep.append(a)
+                arr[key] = a.ctypes.data_as(N._i32p)
+            par = None
+            if L["parent"] is not None:
+                a = np.ascontiguousarray(L["parent"], np.int32)
+                keep.append(a)
+                par = a.ctypes.data_as(N._i32p)
+            lv[i] = N._Level(int(L["ncol"]), arr["col_edge"], arr["edge_col"], arr["edge_lf"], par)
+        dz = np.ascontiguousarray(prob.dz, np.float64)
+        mesh = N._Mesh(prob.nlev, len(levels), lv, prob.dx, prob.dy, dz.ctypes.data_as(N._f64p))
+        base = dict(dt=prob.dt, tau_u=prob.tau_u, tau_rho=prob.tau_rho, tau_theta=prob.tau_theta, cp=prob.cp,
+                    rd=prob.rd)
+        base.update(kw)
+        self.params = N.Params(**base)
+        cp = self.params.to_c()
+        self.h = vp()
+        rc = lib.hyb_create(ctypes.byref(mesh), ctypes.byref(cp), None, ctypes.byref(self.h))
+        assert rc == 0, rc
+        nt, nc = ctypes.c_int64(), ctypes.c_int64()
+        lib.hyb_sizes(self.h, ctypes.byref(nt), ctypes.byref(nc), None)
+        self.ntrace, self.ncell = nt.value, nc.value
+        f = lambda a: np.ascontiguousarray(a, np.float64)  # noqa: E731
+        self.call("hyb_assemble_local", P(f(prob.theta_w)), P(f(prob.exner_hat_w)), P(f(prob.exner_c)),
+                  P(f(prob.rho_c)))
+        self.call("hyb_condense", None, None, None)
+
+    def call(self, name, *args):
+        rc = getattr(self.lib, name)(self.h, *args)
+        if rc < 0:
+            raise RuntimeError(f"{name} failed ({rc}): {self.lib.hyb_last_error(self.h).decode()}")
+        return rc
+
+    def set(self, **kw):
+        for k, v in kw.items():
+            setattr(self.params, k, v)
+        cp = self.params.to_c()
+        self.call("hyb_set_params", ctypes.byref(cp))
+
+    def rhs(self, seed):
+        r_ub, r_pi = make_rhs(self.prob, seed)
+        r_ub, r_pi = np.ascontiguousarray(r_ub, np.float64), np.ascontiguousarray(r_pi, np.float64)
+        b = np.empty(self.ntrace)
+        self.call("hyb_condense", P(r_ub), P(r_pi), P(b))
+        return r_ub, r_pi, b
+
+    def solve(self, b, rtol, maxit=500):
+        lam = np.zeros(self.ntrace)
+        hist = (ctypes.c_double * 64)()
+        info = N._Info(0, 0, 0, 0.0, ctypes.cast(hist, N._f64p), 64, 0)
+        rc = self.call("hyb_solve", P(b), P(lam), rtol, maxit, ctypes.byref(info))
+        return rc, info, lam
+
+    def residual(self, b, lam):
+        y = np.empty(self.ntrace)
+        self.call("hyb_trace_apply", P(lam), P(y))
+        return np.linalg.norm(b - y) / np.linalg.norm(b)
+
+    def close(self):
+        self.lib.hyb_destroy(self.h)
+
+
+def check(cond, what):
+    print(("ok   " if cond else "FAIL ") + what, flush=True)
+    if not cond:
+        sys.exit(3)
+
+
+def solver_sequence(lib):
+    prob = make_box(nx=8, ny=6, nlev=7, dx=5e3, dz=250.0, mg_levels=2, perturb=0.05, seed=4)
+    c = Ctx(lib, prob, restart=5)
+    r_ub, r_pi, b = c.rhs(1)
+    y, z, cells = np.empty(c.ntrace), np.empty(c.ntrace), np.empty(c.ncell)
+    c.call("hyb_trace_apply", P(b), P(y))
+    c.call("hyb_precondition", P(b), P(z))
+    c.call("hyb_restrict", P(b), P(cells), 0)
+    c.call("hyb_restrict", P(b), P(cells), 1)
+    rc, info, lam = c.solve(b, 1e-10)
+    check(rc == 0 and info.restarts > 0 and c.residual(b, lam) <= 1.01e-10,
+          f"fp64 FGMRES(5): {info.iters} iterations, {info.restarts} restarts")
+    u_b, pi = np.empty(6 * c.ncell), np.empty(c.ncell)
+    c.call("hyb_recover", P(r_ub), P(r_pi), P(lam), P(u_b), P(pi))
+    c.set(precision=N.PREC_MIXED, restart=30)
+    c.call("hyb_precondition", P(b), P(z))
+    rc, info, lam = c.solve(b, 1e-8)
+    check(rc == 0 and c.residual(b, lam) <= 1.01e-8, f"mixed FGMRES: {info.iters} iterations")
+    c.call("hyb_profile", 1)
+    c.solve(b, 1e-6)
+    n, ms = ctypes.c_int64(), ctypes.c_double()
+    for fam in ("smooth_rows", "smooth_rows0", "thomas", "trace_apply", "mg_smooth", "restrict", "prolong",
+                "krylov", "cell_solve", "nn"):
+        c.call("hyb_profile_read", fam.encode(), ctypes.byref(n), ctypes.byref(ms))
+    c.call("hyb_profile", 0)
+    # argument errors come back as codes
+    check(lib.hyb_restrict(c.h, P(b), P(cells), 2) < 0, "bad restriction mode rejected")
+    check(lib.hyb_solve(c.h, P(b), P(b), 1e-8, 10, None) < 0, "aliased solve vectors rejected")
+    c.close()
+
+
+def network_sequence(lib):
+    prob = make_box(nx=8, ny=6, nlev=7, dx=5e3, dz=250.0, mg_levels=2, perturb=0.05, seed=5)
+    c = Ctx(lib, prob)
+    nc = c.ncell
+    rng = np.random.default_rng(0)
+    check(lib.hyb_nn_forward(c.h, None, None, 1) < 0, "network call before weights rejected")
+    w = learned.init_params(16, seed=2)
+    c.call("hyb_nn_set_weights", P(w), w.size)
+    loss = ctypes.c_float()
+    # a training step as the very first network call (activation buffers not yet allocated)
+    x3 = rng.standard_normal((3, nc)).astype(np.float32)
+    t3 = rng.standard_normal((3, nc)).astype(np.float32)
+    c.call("hyb_nn_train_step", P(x3), P(t3), 3, ctypes.c_float(1e-3), ctypes.byref(loss))
+    check(np.isfinite(loss.value), f"first call is a training step (batch 3): loss {loss.value:.4f}")
+    g = np.empty(w.size, np.float32)
+    c.call("hyb_nn_loss_grad", P(x3[:2].copy()), P(t3[:2].copy()), 2, ctypes.byref(loss), P(g))
+    x5 = rng.standard_normal((5, nc)).astype(np.float32)  # larger batch: buffers grow
+    y5 = np.empty((5, nc), np.float32)
+    c.call("hyb_nn_forward", P(x5), P(y5), 5)
+    c.call("hyb_nn_train_step", P(x5), P(x5), 5, ctypes.c_float(1e-3), None)
+    x1 = x5[:1].copy()
+    y1 = np.empty((1, nc), np.float32)
+    c.call("hyb_nn_forward", P(x1), P(y1), 1)
+    wc = np.empty(w.size, np.float32)
+    c.call("hyb_nn_get_weights", P(wc), wc.size)
+    W, bias = learned.unpack(wc)
+    ref = onn.forward(x1[0].astype(np.float64), [onn.bf16_round(a) for a in W], bias,
+                      onn.neighbour_table(prob.nx, prob.ny), prob.nlev)[0]
+    err = float(np.abs(y1[0] - ref).max() / np.abs(ref).max())
+    check(err <= 1e-5, f"forward after training matches the oracle's formula: {err:.1e}")
+    _, _, b = c.rhs(2)
+    for prec in (N.PREC_FP64, N.PREC_MIXED):
+        c.set(learned=1, precision=prec)
+        rc, info, lam = c.solve(b, 1e-8, maxit=40)
+        check(rc >= 0, f"solve with the learned stage (precision {prec}): {info.iters} iterations")
+    wo = w.copy()
+    wo[: 16 * 45] = np.repeat(np.where(np.arange(16) % 2 == 0, 1e30, -1e30), 45)
+    wo[16 * 45 + 16: 16 * 45 + 16 + 16 * 16 * 45] = 1e30
+    c.call("hyb_nn_set_weights", P(wo), wo.size)
+    c.set(precision=N.PREC_FP64)
+    rc, info, lam = c.solve(b, 1e-8)
+    check(rc == 0 and info.fallbacks == info.iters, f"overflowing network falls back: {info.fallbacks}/{info.iters}")
+    c.close()
+
+
+def main():
+    lib = N.declare(ctypes.CDLL(sys.argv[1]))
+    which = sys.argv[2:] or ["solver", "network"]
+    if "solver" in which:
+        solver_sequence(lib)
+    if "network" in which:
+        network_sequence(lib)
+    print("sequence complete", flush=True)
+
+
+if __name__ == "__main__":
+    main()

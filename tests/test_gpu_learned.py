@@ -1,0 +1,155 @@
+"""Learned coarse correction on the GPU: network passes and gradients against the FP64 oracle,
+restriction, training, the solve with the stage, its fallback, and what it gains (GPU)."""
+
+import numpy as np
+import pytest
+
+from gpu_common import dev, host, make_solver, rel_max, say
+from oracle import nn as onn
+from oracle.problem import OracleProblem, cells_from_soa
+from paper_2210_11797_amd import learned
+from synth import make_box, make_rhs
+
+
+def _f32(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+@pytest.fixture(scope="module")
+def small():
+    prob = make_box(nx=12, ny=10, nlev=9, dx=5e3, dz=250.0, mg_levels=2, perturb=0.05)
+    s = make_solver(prob)
+    return prob, s
+
+
+@pytest.mark.gpu
+def test_network_forward_and_gradients_match_oracle(small):
+    prob, s = small
+    rng = np.random.default_rng(0)
+    vec = learned.init_params(16, seed=1)
+    vec[16 * 45 : 16 * 45 + 16] = rng.standard_normal(16) * 0.1  # b1
+    s.nn_set_weights(vec)
+    x = rng.standard_normal((2, prob.ncell)).astype(np.float32)
+    t = rng.standard_normal((2, prob.ncell)).astype(np.float32)
+    W, b = learned.unpack(vec)
+    Wr = [onn.bf16_round(w) for w in W]  # the kernels use BF16 weights, FP32 biases
+    nb = onn.neighbour_table(prob.nx, prob.ny)
+    import torch
+
+    y = torch.empty((2, prob.ncell), dtype=torch.float32, device="cuda")
+    s.nn_forward(_f32(x), y, 2)
+    yref = np.stack([onn.forward(x[i].astype(np.float64), Wr, b, nb, prob.nlev)[0] for i in range(2)])
+    err_y = rel_max(host(y), yref)
+    loss, g = s.nn_loss_grad(_f32(x), _f32(t), 2)
+    # oracle: mean over both samples = average of the per-sample means
+    refs = [onn.loss_and_grads(x[i].astype(np.float64), t[i].astype(np.float64), Wr, b, nb, prob.nlev)
+            for i in range(2)]
+    lref = 0.5 * (refs[0][0] + refs[1][0])
+    gW = [0.5 * (refs[0][1][j] + refs[1][1][j]) for j in range(3)]
+    gb = [0.5 * (refs[0][2][j] + refs[1][2][j]) for j in range(3)]
+    gref = learned.pack(gW, gb).astype(np.float64)
+    errs = []
+    off = 0
+    for name, shp in learned.layout():
+        nn_ = int(np.prod(shp))
+        errs.append(rel_max(g[off : off + nn_], gref[off : off + nn_]))
+        off += nn_
+    say(f"[nn] forward {err_y:.2e} loss {loss:.6e} vs {lref:.6e} grads {['%.1e' % e for e in errs]}")
+    assert err_y <= 1e-5
+    assert abs(loss - lref) <= 1e-5 * lref
+    assert max(errs) <= 1e-4
+
+
+@pytest.mark.gpu
+def test_restriction_modes(small):
+    prob, s = small
+    import torch
+
+    orc = OracleProblem(prob)
+    r = np.random.default_rng(2).standard_normal(orc.mesh.ntrace)
+    c = torch.empty(prob.ncell, dtype=torch.float64, device="cuda")
+    s.restrict(dev(r), c, 0)
+    P, S, H = orc.pc.P, orc.pc.S, orc.pc.mg.H[0]
+    # Gamma = (H 1) / (P^T S P 1): both sums cancel (row sums of H and S are small against their
+    # entries), so the rounding of either side is eps times the cancellation ratio sum|a| / |sum a|
+    one = np.ones(prob.ncell)
+    ratio = np.max((abs(H) @ one) / abs(H @ one)) + np.max(
+        (abs(P).T @ (abs(S) @ (abs(P) @ one))) / abs(P.T @ (S @ (P @ one))))
+    tol = 4 * np.finfo(float).eps * ratio
+    err = rel_max(host(c), orc.pc.gamma * (P.T @ r))
+    say(f"[restrict] Gamma P^T r: {err:.2e} (tol {tol:.2e}, cancellation ratio {ratio:.2e})")
+    assert err <= tol
+    s.restrict(dev(r), c, 1)
+    assert rel_max(host(c), (P.T @ r) / (P.T @ np.ones(orc.mesh.ntrace))) <= 1e-12
+
+
+@pytest.mark.gpu
+def test_learned_stage_trains_and_gains():
+    """Train on pairs from the plain method on a 32x32x64 box (dx = 5 km, dz = 250 m), then compare
+    FGMRES iterations with and without the stage on held-out right-hand sides."""
+    import torch
+
+    prob = make_box(nx=32, ny=32, nlev=64, dx=5e3, dz=250.0, dt=600.0, mg_levels=4)
+    s = make_solver(prob)
+    s.nn_set_weights(learned.init_params(16, seed=0))
+
+    def rhs(seed):
+        r_ub, r_pi = make_rhs(prob, seed)
+        b = torch.empty(s.ntrace, dtype=torch.float64, device="cuda")
+        s.condense(dev(r_ub), dev(r_pi), b)
+        return b
+
+    X, T = learned.generate_pairs(s, [rhs(10000 + i) for i in range(48)], steps=8)
+    say(f"[learned] {X.shape[0]} pairs")
+    hist = learned.train(s, X, T, steps=400, batch=8, lr=2e-3, log=say)
+    assert np.mean(hist[-20:]) < 0.5 * np.mean(hist[:5])
+    orc = OracleProblem(prob, with_precond=False)
+    plain, with_nn = [], []
+    for seed in (1000, 1001, 1002):
+        r_ub, r_pi = make_rhs(prob, seed)
+        b = rhs(seed)
+        for flag, out in ((0, plain), (1, with_nn)):
+            p = s.params
+            p.learned = flag
+            s.set_params(p)
+            lam = torch.zeros_like(b)
+            info = s.solve(b, lam, rtol=1e-8)
+            ruc, rpc = cells_from_soa(r_ub, r_pi)
+            B = orc.hyb.rhs(ruc, rpc)
+            res = np.linalg.norm(B - orc.hyb.S @ host(lam)) / np.linalg.norm(B)
+            assert info["status"] == 0 and res <= 1.01e-8 and info["fallbacks"] == 0
+            out.append(info["iters"])
+    p = s.params
+    p.learned = 0
+    s.set_params(p)
+    say(f"[learned] held-out iterations: plain {plain}, with learned stage {with_nn}")
+    assert sum(with_nn) <= sum(plain) + 3
+
+
+@pytest.mark.gpu
+def test_learned_stage_falls_back_on_overflow(small):
+    prob, s = small
+    import torch
+
+    vec = learned.init_params(16, seed=3)
+    # layer 1: +1e30 on even and -1e30 on odd channels, so that some channel is positive wherever
+    # the input's 3x3x5 box sum is nonzero; layer 2 (all 1e30) then overflows to inf, and layer 3
+    # (mixed signs) gives inf or NaN.  (All-positive weights would give an exactly zero, finite
+    # output for inputs whose box sums are all negative.)
+    vec[: 16 * 45] = np.repeat(np.where(np.arange(16) % 2 == 0, 1e30, -1e30), 45)
+    vec[16 * 45 + 16 : 16 * 45 + 16 + 16 * 16 * 45] = 1e30
+    s.nn_set_weights(vec)
+    p = s.params
+    p.learned = 1
+    s.set_params(p)
+    r_ub, r_pi = make_rhs(prob, 3)
+    b = torch.empty(s.ntrace, dtype=torch.float64, device="cuda")
+    s.condense(dev(r_ub), dev(r_pi), b)
+    lam = torch.zeros_like(b)
+    info = s.solve(b, lam, rtol=1e-8)
+    p.learned = 0
+    s.set_params(p)
+    say(f"[learned] overflow weights: iters {info['iters']} fallbacks {info['fallbacks']}")
+    assert info["status"] == 0 and info["fallbacks"] == info["iters"]
