@@ -1,16 +1,30 @@
-"""Learned coarse correction network (test infrastructure, FP64 NumPy reference).
+"""Learned coarse correction network and stage (test infrastructure, FP64 NumPy reference).
 
 The network maps a DG0 field (one value per cell, [L][ncol]) to a DG0 field through three 3D
 convolutions, 1 -> C -> C -> 1 channels, each tap set being the 3 x 3 horizontal neighbourhood of a
 column (the column, its four edge neighbours and four corner neighbours) times 5 vertical offsets
-(-2..2, zero padded above the lid and below the ground); ReLU after the first two layers.  This is
-the extra coarse-correction stage of the learned form (not part of the paper): its input is the
-scaled restriction Gamma P^T r' of the residual left by the two-level cycle, its target the cell
-average of the remaining error.
+(-2..2, zero padded above the lid and below the ground); ReLU after the first two layers.
 
-Parity: pinned by central finite differences of the loss with respect to every weight group and
-the input (tests), by translation equivariance on the periodic box, and by one-hot weights that
-must reproduce shifted copies of the input.
+The stage (not part of the paper) follows the two-level cycle z = M(v) of Alg. 2: with the residual
+r' = v - S z it left, the coarse right-hand side c = Gamma P^T r' of Alg. 2 and s = rms(c), the
+network proposes d = s P (N(c / s) / H_KK) (H_KK the diagonal of the pressure operator, which makes
+the network's target dimensionless), and the FP64 residual decides: z + d is kept only if
+||r' - S d|| < tau ||r'||, else z (also when N's output is not finite).
+
+Training minimises the error energy left after the correction.  With e' = S^-1 r' and the
+correction P delta, delta = s q, q = N(x) / H_KK, the energy changes by
+    (e' - P delta)^T S (e' - P delta) - e'^T S e' = delta^T G delta - 2 delta^T P^T r'   (S symmetric)
+with G = P^T S P, so the loss per pair is q^T G q - 2 q^T rhat, rhat = P^T r' / s: it needs r' and
+applications of G only, never S^-1.  Pairs (x = c / s, rhat) come from the plain method's
+stationary iteration.
+
+Parity: the network is pinned by central finite differences of the loss with respect to every
+weight group and the input, by translation equivariance on the periodic box, and by one-hot weights
+that must reproduce shifted copies of the input; the stage by an exact identity network (the
+correction must equal the closed form P H_KK^-1 Gamma P^T r'), by positive homogeneity of degree one
+in (v, z), and by networks that must be rejected (zero output; a correction far too large); the
+energy loss by central finite differences and, in the symmetric case, by the error energies
+computed with a direct solve.
 """
 
 from __future__ import annotations
@@ -128,3 +142,52 @@ def bf16_round(a):
     lsb = (u >> 16) & 1
     u = ((u + 0x7FFF + lsb) >> 16) << 16
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def learned_correction(v, z, S, P, gamma, hdiag, W, b, nb, nlev, tau=3.0):
+    """The learned stage after z = M(v).  Returns (z_new, accepted)."""
+    rp = v - S @ z
+    c = gamma * (P.T @ rp)
+    s = float(np.sqrt(np.mean(c * c)))
+    x = c / s if s > 0.0 else np.zeros_like(c)
+    y, _ = forward(x, W, b, nb, nlev)
+    if not np.all(np.isfinite(y)):
+        return z, False
+    d = s * (P @ (y / hdiag))
+    if np.linalg.norm(rp - S @ d) < tau * np.linalg.norm(rp):
+        return z + d, True
+    return z, False
+
+
+def identity_weights(channels=16):
+    """Weights for which the network is exactly the identity: channel 0 carries relu(x), channel 1
+    relu(-x), the last layer returns their difference (centre tap, dk = 0, zero biases)."""
+    W = [np.zeros((channels, 1, NT)), np.zeros((channels, channels, NT)), np.zeros((1, channels, NT))]
+    centre = 0 * NV + 2
+    W[0][0, 0, centre], W[0][1, 0, centre] = 1.0, -1.0
+    W[1][0, 0, centre], W[1][1, 1, centre] = 1.0, 1.0
+    W[2][0, 0, centre], W[2][0, 1, centre] = 1.0, -1.0
+    return W, [np.zeros(channels), np.zeros(channels), np.zeros(1)]
+
+
+def energy_loss_and_grads(x, rhat, W, b, nb, nlev, G, hdiag):
+    """Energy loss of one pair and its gradients (dW list, db list).
+
+    q = N(x) / H_KK,  loss = (q^T G q - 2 q^T rhat) * mean(H_KK) / ncell  (the scale makes the loss
+    dimensionless and of order one; averaging over a batch is the caller's)."""
+    y, acts = forward(x, W, b, nb, nlev)
+    n = y.shape[0]
+    scale = float(np.mean(hdiag)) / n
+    q = y / hdiag
+    Gq = G @ q
+    loss = float(q @ Gq - 2.0 * q @ rhat) * scale
+    # d loss / d q = (G + G^T) q - 2 rhat; the library uses 2 G q (G is symmetric up to the small
+    # asymmetry of S), and so does this reference
+    dy = (2.0 * (Gq - rhat) / hdiag * scale)[None, :]
+    dWs, dbs = [None] * 3, [None] * 3
+    for i in (2, 1, 0):
+        if i < 2:
+            dy = dy * (acts[i + 1] > 0.0)
+        dx, dWs[i], dbs[i] = conv_grads(acts[i], W[i], dy, nb, nlev)
+        dy = dx
+    return loss, dWs, dbs

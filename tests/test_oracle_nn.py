@@ -80,3 +80,138 @@ def test_bf16_rounding():
     assert r[2] == 1.0 + 2.0**-7
     assert abs(r[3] + 3.14159) <= 2.0**-8 * 4
     assert np.all(np.abs(r - vals) <= np.abs(vals) * 2.0**-8)
+
+
+# ---- the stage after the two-level cycle ----
+
+def _stage_problem():
+    from oracle.problem import OracleProblem
+    from synth import make_box
+
+    prob = make_box(nx=6, ny=4, nlev=5, dx=5e3, dz=250.0, mg_levels=2, perturb=0.05, seed=3)
+    orc = OracleProblem(prob)
+    return prob, orc, orc.H.diagonal().copy(), nn.neighbour_table(prob.nx, prob.ny)
+
+
+def test_identity_weights_give_the_identity():
+    W, b = nn.identity_weights(4)
+    x = np.random.default_rng(1).standard_normal(5 * 20)
+    np.testing.assert_array_equal(nn.forward(x, W, b, nn.neighbour_table(5, 4), 5)[0], x)
+
+
+def test_stage_with_identity_network_is_the_diagonal_coarse_correction():
+    """N = identity turns the stage into d = P H_KK^-1 Gamma P^T r' (written out here directly)."""
+    prob, orc, hd, nb = _stage_problem()
+    S, P, gam = orc.hyb.S, orc.pc.P, orc.pc.gamma
+    W, b = nn.identity_weights(16)
+    rng = np.random.default_rng(4)
+    accepted_any = False
+    for _ in range(4):
+        v = rng.standard_normal(S.shape[0])
+        z = orc.pc(v)
+        znew, acc = nn.learned_correction(v, z, S, P, gam, hd, W, b, nb, prob.nlev)
+        rp = v - S @ z
+        d = P @ ((gam * (P.T @ rp)) / hd)
+        expect_acc = np.linalg.norm(rp - S @ d) < np.linalg.norm(rp)
+        assert acc == expect_acc
+        np.testing.assert_allclose(znew, z + d if acc else z, rtol=1e-12, atol=1e-12 * np.abs(z).max())
+        accepted_any |= acc
+    assert accepted_any  # the diagonal coarse correction helps on at least one of the vectors
+
+
+def test_stage_is_positively_homogeneous():
+    prob, orc, hd, nb = _stage_problem()
+    S, P, gam = orc.hyb.S, orc.pc.P, orc.pc.gamma
+    W, b = nn.init_weights(16, seed=5)
+    rng = np.random.default_rng(6)
+    v = rng.standard_normal(S.shape[0])
+    z = orc.pc(v)
+    z1, a1 = nn.learned_correction(v, z, S, P, gam, hd, W, b, nb, prob.nlev)
+    for a in (3.7, 1e-5):
+        za, aa = nn.learned_correction(a * v, a * z, S, P, gam, hd, W, b, nb, prob.nlev)
+        assert aa == a1
+        np.testing.assert_allclose(za, a * z1, rtol=1e-10, atol=1e-12 * a * np.abs(z1).max())
+
+
+def test_stage_rejects_useless_and_harmful_corrections():
+    prob, orc, hd, nb = _stage_problem()
+    S, P, gam = orc.hyb.S, orc.pc.P, orc.pc.gamma
+    v = np.random.default_rng(7).standard_normal(S.shape[0])
+    z = orc.pc(v)
+    W0 = [np.zeros((16, 1, nn.NT)), np.zeros((16, 16, nn.NT)), np.zeros((1, 16, nn.NT))]
+    b0 = [np.zeros(16), np.zeros(16), np.zeros(1)]
+    zn, acc = nn.learned_correction(v, z, S, P, gam, hd, W0, b0, nb, prob.nlev)
+    assert np.array_equal(zn, z)  # a zero correction leaves z as it is, accepted or not
+    W, b = nn.identity_weights(16)
+    W[2] = W[2] * 1e8  # a correction far larger than the error
+    zn, acc = nn.learned_correction(v, z, S, P, gam, hd, W, b, nb, prob.nlev)
+    assert not acc and np.array_equal(zn, z)
+
+
+def _symmetric_problem():
+    """theta* constant (N = 0) makes S symmetric positive definite."""
+    from oracle.problem import OracleProblem
+    from synth import make_box
+
+    prob = make_box(nx=6, ny=4, nlev=5, dx=5e3, dz=250.0, mg_levels=2, nbv=0.0, seed=3)
+    orc = OracleProblem(prob)
+    return prob, orc
+
+
+def test_energy_loss_is_the_change_of_error_energy():
+    """In the symmetric case the loss equals, up to its scale, the change of e'^T S e' when the
+    correction P (s q) is added, with e' = S^-1 r' from a direct solve."""
+    import scipy.sparse.linalg as spla
+
+    prob, orc = _symmetric_problem()
+    S, P, gam = orc.hyb.S.tocsc(), orc.pc.P, orc.pc.gamma
+    assert abs(S - S.T).max() <= 1e-12 * abs(S).max()
+    hd = orc.H.diagonal().copy()
+    nb = nn.neighbour_table(prob.nx, prob.ny)
+    W, b = nn.identity_weights(16)  # a correction of the size of the error (random weights are tiny)
+    rng = np.random.default_rng(9)
+    v = rng.standard_normal(S.shape[0])
+    rp = v - S @ orc.pc(v)
+    c = gam * (P.T @ rp)
+    s = np.sqrt(np.mean(c * c))
+    x, rhat = c / s, (P.T @ rp) / s
+    loss = nn.energy_loss_and_grads(x, rhat, W, b, nb, prob.nlev, (P.T @ S @ P).tocsr(), hd)[0]
+    e = spla.spsolve(S, rp)
+    y = nn.forward(x, W, b, nb, prob.nlev)[0]
+    d = P @ (s * y / hd)
+    e_before, e_after = e @ (S @ e), (e - d) @ (S @ (e - d))
+    scale = np.mean(hd) / prob.ncell / s**2
+    # the change is a small difference of two energies: compare to the rounding of the energies
+    assert abs(loss - (e_after - e_before) * scale) <= 1e-10 * (e_before + e_after) * scale
+    assert abs(e_after - e_before) > 1e-4 * e_before  # the check is not vacuous
+
+
+def test_energy_gradients_match_central_differences():
+    prob, orc, hd, nb_ = _stage_problem()
+    S, P = orc.hyb.S, orc.pc.P
+    G = (P.T @ S @ P).tocsr()
+    G = 0.5 * (G + G.T)  # the gradient assumes a symmetric G
+    W, b = nn.init_weights(8, seed=11)
+    rng = np.random.default_rng(12)
+    for bi in b:
+        bi[:] = rng.standard_normal(bi.shape) * 0.1
+    x = rng.standard_normal(prob.ncell)
+    rhat = rng.standard_normal(prob.ncell)
+    f = lambda W_, b_: nn.energy_loss_and_grads(x, rhat, W_, b_, nb_, prob.nlev, G, hd)  # noqa: E731
+    loss, dW, db = f(W, b)
+    h = 1e-6
+    for layer in range(3):
+        for _ in range(4):
+            idx = tuple(rng.integers(0, k) for k in W[layer].shape)
+            Wp = [w.copy() for w in W]
+            Wm = [w.copy() for w in W]
+            Wp[layer][idx] += h
+            Wm[layer][idx] -= h
+            fd = (f(Wp, b)[0] - f(Wm, b)[0]) / (2 * h)
+            assert abs(fd - dW[layer][idx]) <= 1e-6 * max(1.0, abs(fd)), (layer, idx, fd, dW[layer][idx])
+        bp = [v.copy() for v in b]
+        bm = [v.copy() for v in b]
+        bp[layer][0] += h
+        bm[layer][0] -= h
+        fd = (f(W, bp)[0] - f(W, bm)[0]) / (2 * h)
+        assert abs(fd - db[layer][0]) <= 1e-6 * max(1.0, abs(fd))
