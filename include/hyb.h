@@ -99,8 +99,10 @@ typedef struct {
   /* flexible GMRES restart length and arithmetic of the preconditioner (HYB_PREC_*) */
   int32_t restart;
   int32_t precision;
-  /* 1: hyb_solve appends the learned coarse correction (hyb_nn_*) after every two-level cycle */
+  /* 1: hyb_solve and hyb_precondition append the learned coarse correction (hyb_nn_*) after every
+     two-level cycle; learned_tau > 0: a correction d is kept only if ||r' - S d|| < learned_tau ||r'|| */
   int32_t learned;
+  double learned_tau;
 } hyb_params;
 
 typedef struct {
@@ -111,7 +113,7 @@ typedef struct {
   double *history;      /* optional host array: Arnoldi residual estimate per iteration */
   int32_t history_cap;
   int32_t history_len;
-  int32_t fallbacks;    /* learned stage skipped because its output was not finite */
+  int32_t fallbacks;    /* learned corrections dropped (output not finite, or rejected by the residual test) */
 } hyb_info;
 
 /* Create a context for one mesh.  stream: a hipStream_t (NULL = default stream).
@@ -148,7 +150,8 @@ int hyb_trace_apply(hyb_ctx *ctx, const double *x, double *y);
 /* z = M(r): one application of the two-level cycle (Alg. 2) from zero:
    LineSmooth (n_pre), residual, restriction P^T scaled by Gamma, one pressure
    multigrid V-cycle on H, prolongation by facet averaging, LineSmooth
-   (n_post).  r, z [ntrace], must not alias. */
+   (n_post); with params.learned = 1 followed by the learned stage (below).
+   r, z [ntrace], must not alias. */
 int hyb_precondition(hyb_ctx *ctx, const double *r, double *z);
 
 /* Flexible GMRES on S lambda = B_lambda, right preconditioned by Alg. 2.
@@ -178,19 +181,25 @@ int hyb_sizes(const hyb_ctx *ctx, int64_t *ntrace, int64_t *ncell, int64_t *work
 int hyb_profile(hyb_ctx *ctx, int32_t enable);
 int hyb_profile_read(hyb_ctx *ctx, const char *family, int64_t *launches, double *total_ms);
 
-/* Restriction of a trace vector r [ntrace] to cells [nlev][ncol]: mode 0 Gamma P^T r (the scaled
-   right-hand side of the coarse level in Alg. 2), mode 1 the facet average P^T r / P^T 1. */
+/* Restriction of a trace vector r [ntrace] to cells [nlev][ncol] (device FP64 arrays): mode 0
+   Gamma P^T r (the scaled right-hand side of the coarse level in Alg. 2), mode 1 the facet average
+   P^T r / P^T 1, mode 2 H_KK times the facet average (H_KK: diagonal of the pressure operator H),
+   mode 3 P^T r (P: the facet-average prolongation of Alg. 2).  HYB_EINVAL for another mode. */
 int hyb_restrict(hyb_ctx *ctx, const double *r, double *cells, int32_t mode);
 
 /* Learned coarse correction (not part of the paper): a network of three 3D convolutions on cell
    fields (1 -> 16 -> 16 -> 1 channels; taps = the 3x3 horizontal neighbourhood of a column times
    5 vertical offsets, zero padded at ground and lid; ReLU after the first two), BF16 weights with
-   FP32 accumulation.  With params.learned = 1, hyb_solve follows every two-level cycle z = M(v)
-   with r' = v - S z, c = Gamma P^T r', s = rms(c), z += s P N(c / s); a non-finite network output
-   leaves z unchanged (counted in hyb_info.fallbacks).
+   FP32 accumulation.  With params.learned = 1, hyb_solve and hyb_precondition follow every
+   two-level cycle z = M(v) with r' = v - S z, c = Gamma P^T r', s = rms(c),
+   d = s P (N(c / s) / H_KK), and z += d only if ||r' - S d||_2 < learned_tau ||r'||_2 (FP64):
+   otherwise, or when the network output is not finite, z stays the plain cycle's output (counted in
+   hyb_info.fallbacks).
    Parameters (FP32, host arrays of hyb_nn_param_count() values): W1 [16][1][45], b1 [16],
    W2 [16][16][45], b2 [16], W3 [1][16][45], b3 [1], tap index = 5*h + (dk+2), h = centre, W, E,
-   S, N, SW, SE, NW, NE.  Cell fields x, t, y are DEVICE FP32 arrays [nsamp][nlev][ncol]. */
+   S, N, SW, SE, NW, NE.  Cell fields x, t, y are DEVICE FP32 arrays [nsamp][nlev][ncol].
+   Errors: HYB_ESTATE before hyb_nn_set_weights (or, for the energy calls, before hyb_condense);
+   HYB_EINVAL for NULL arrays, nsamp < 1, a wrong parameter count or non-finite weights. */
 int hyb_nn_param_count(void);
 int hyb_nn_set_weights(hyb_ctx *ctx, const float *weights, int64_t n);
 int hyb_nn_get_weights(hyb_ctx *ctx, float *weights, int64_t n);
@@ -198,8 +207,17 @@ int hyb_nn_forward(hyb_ctx *ctx, const float *x, float *y, int32_t nsamp);
 /* mean squared error of N(x) against t over all cells and samples; gradient (host, may be NULL)
    in the parameter layout above */
 int hyb_nn_loss_grad(hyb_ctx *ctx, const float *x, const float *t, int32_t nsamp, float *loss, float *grad);
-/* one Adam step (beta 0.9 / 0.999, eps 1e-8) on the FP32 master weights; loss (host) may be NULL */
+/* one Adam step (beta 0.9 / 0.999, eps 1e-8) on the mean squared error; loss (host) may be NULL */
 int hyb_nn_train_step(hyb_ctx *ctx, const float *x, const float *t, int32_t nsamp, float lr, float *loss);
+/* Error-energy loss of the stage's correction: for pairs x_i = c_i / s_i (FP32) and
+   rhat_i = P^T r'_i / s_i (DEVICE FP64 [nsamp][nlev][ncol]), with q_i = N(x_i) / H_KK and
+   G = P^T S P, loss = mean_i (q_i^T G q_i - 2 q_i^T rhat_i) * mean(H_KK) / ncell, which is the change
+   of (e'^T S e') / s_i^2 when S is symmetric (e' = S^-1 r'), up to that scale.  gradient (host, may be
+   NULL) as above; loss (host, may be NULL). */
+int hyb_nn_energy_grad(hyb_ctx *ctx, const float *x, const double *rhat, int32_t nsamp, double *loss, float *grad);
+/* one Adam step on the energy loss */
+int hyb_nn_energy_train_step(hyb_ctx *ctx, const float *x, const double *rhat, int32_t nsamp, float lr,
+                             double *loss);
 
 const char *hyb_last_error(const hyb_ctx *ctx);
 void hyb_destroy(hyb_ctx *ctx);

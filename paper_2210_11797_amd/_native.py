@@ -42,7 +42,7 @@ class _Params(ctypes.Structure):
                 ("omega", ctypes.c_double), ("n_pre", ctypes.c_int32), ("n_post", ctypes.c_int32),
                 ("omega_p", ctypes.c_double), ("mg_pre", ctypes.c_int32), ("mg_post", ctypes.c_int32),
                 ("mg_coarse_sweeps", ctypes.c_int32), ("restart", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("learned", ctypes.c_int32)]
+                ("learned", ctypes.c_int32), ("learned_tau", ctypes.c_double)]
 
 
 class _Info(ctypes.Structure):
@@ -72,6 +72,7 @@ class Params:
     restart: int = 30
     precision: int = PREC_FP64
     learned: int = 0
+    learned_tau: float = 3.0
 
     def to_c(self) -> _Params:
         return _Params(**{f.name: getattr(self, f.name) for f in fields(self)})
@@ -81,7 +82,8 @@ ABI_FUNCTIONS = [
     "hyb_create", "hyb_set_params", "hyb_assemble_local", "hyb_condense", "hyb_trace_apply",
     "hyb_precondition", "hyb_solve", "hyb_recover", "hyb_sizes", "hyb_profile", "hyb_profile_read",
     "hyb_restrict", "hyb_nn_param_count", "hyb_nn_set_weights", "hyb_nn_get_weights", "hyb_nn_forward",
-    "hyb_nn_loss_grad", "hyb_nn_train_step", "hyb_last_error", "hyb_destroy",
+    "hyb_nn_loss_grad", "hyb_nn_train_step", "hyb_nn_energy_grad", "hyb_nn_energy_train_step",
+    "hyb_last_error", "hyb_destroy",
 ]
 
 _lib = None
@@ -125,6 +127,9 @@ def declare(lib):
     lib.hyb_nn_forward.argtypes = [vp, vp, vp, ctypes.c_int32]
     lib.hyb_nn_loss_grad.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_float), vp]
     lib.hyb_nn_train_step.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.c_float, ctypes.POINTER(ctypes.c_float)]
+    lib.hyb_nn_energy_grad.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), vp]
+    lib.hyb_nn_energy_train_step.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.c_float,
+                                             ctypes.POINTER(ctypes.c_double)]
     lib.hyb_last_error.argtypes = [vp]
     lib.hyb_last_error.restype = ctypes.c_char_p
     lib.hyb_destroy.argtypes = [vp]
@@ -296,6 +301,24 @@ class HybSolver:
         loss = ctypes.c_float()
         self._check(self.lib.hyb_nn_train_step(self.h, _ptr(x, n, "x", "float32"), _ptr(t, n, "t", "float32"),
                                                int(nsamp), float(lr), ctypes.byref(loss)), "hyb_nn_train_step")
+        return loss.value
+
+    def nn_energy_grad(self, x, rhat, nsamp=1, want_grad=True):
+        n = self.ncell * nsamp
+        loss = ctypes.c_double()
+        g = np.empty(self.nn_param_count(), np.float32) if want_grad else None
+        self._check(self.lib.hyb_nn_energy_grad(self.h, _ptr(x, n, "x", "float32"), _ptr(rhat, n, "rhat"),
+                                                int(nsamp), ctypes.byref(loss),
+                                                g.ctypes.data_as(ctypes.c_void_p) if g is not None else None),
+                    "hyb_nn_energy_grad")
+        return loss.value, g
+
+    def nn_energy_train_step(self, x, rhat, nsamp, lr):
+        n = self.ncell * nsamp
+        loss = ctypes.c_double()
+        self._check(self.lib.hyb_nn_energy_train_step(self.h, _ptr(x, n, "x", "float32"), _ptr(rhat, n, "rhat"),
+                                                      int(nsamp), float(lr), ctypes.byref(loss)),
+                    "hyb_nn_energy_train_step")
         return loss.value
 
     def profile(self, enable: bool):

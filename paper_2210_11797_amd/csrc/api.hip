@@ -73,6 +73,7 @@ int check_params(hyb_ctx *c, const hyb_params *p) {
   if (p->precision != HYB_PREC_FP64 && p->precision != HYB_PREC_MIXED)
     return fail(c, HYB_EINVAL, "unknown precision mode");
   if (p->learned != 0 && p->learned != 1) return fail(c, HYB_EINVAL, "learned must be 0 or 1");
+  if (!(p->learned_tau > 0.0) || !std::isfinite(p->learned_tau)) return fail(c, HYB_EINVAL, "learned_tau must be > 0");
   return HYB_OK;
 }
 
@@ -370,14 +371,22 @@ int hyb_precondition(hyb_ctx *c, const double *r, double *z) {
   if (!c) return HYB_EINVAL;
   if (!c->condensed) return fail(c, HYB_ESTATE, "precondition before condense");
   if (!r || !z || r == z) return fail(c, HYB_EINVAL, "bad vectors");
+  if (c->p.learned && !c->nn.loaded) return fail(c, HYB_ESTATE, "learned stage requested without weights");
+  if (c->p.learned || c->p.precision != HYB_PREC_FP64) {
+    // the learned stage reduces into the Krylov scratch; the FP32 path uses the first basis slot of Z
+    int rc = alloc_krylov(c);
+    if (rc) return rc;
+  }
   if (c->p.precision == HYB_PREC_FP64) {
     CHECK_HIP(precondition<double>(c, r, z), "precondition");
+    if (c->p.learned) CHECK_HIP(learned_stage<double>(c, r, z), "learned stage");
   } else {
     size_t n = (size_t)c->ntrace;
     float *rf = (float *)c->tIn;
-    float *zf = (float *)c->Z;  // first basis slot as scratch
+    float *zf = (float *)c->Z;
     CHECK_HIP(launch_convert(c, r, rf, n), "convert");
     CHECK_HIP(precondition<float>(c, rf, zf), "precondition");
+    if (c->p.learned) CHECK_HIP(learned_stage<float>(c, r, zf), "learned stage");
     CHECK_HIP(launch_copy_widen(c, zf, z, n), "widen");
   }
   return HYB_OK;
@@ -614,7 +623,7 @@ int hyb_profile_read(hyb_ctx *c, const char *family, int64_t *launches, double *
 int hyb_restrict(hyb_ctx *c, const double *r, double *cells, int32_t mode) {
   if (!c) return HYB_EINVAL;
   if (!c->condensed) return fail(c, HYB_ESTATE, "restrict before condense");
-  if (!r || !cells || (mode != 0 && mode != 1)) return fail(c, HYB_EINVAL, "bad restrict arguments");
+  if (!r || !cells || mode < 0 || mode > 3) return fail(c, HYB_EINVAL, "bad restrict arguments");
   CHECK_HIP(launch_restrict_cells(c, r, cells, mode), "restrict");
   return HYB_OK;
 }
@@ -665,6 +674,29 @@ int hyb_nn_train_step(hyb_ctx *c, const float *x, const float *t, int32_t nsamp,
   if (!c->nn.loaded) return fail(c, HYB_ESTATE, "no weights");
   if (!x || !t || nsamp < 1 || !(lr > 0)) return fail(c, HYB_EINVAL, "bad train arguments");
   CHECK_HIP(nn_loss_grad(c, x, t, nsamp, loss), "nn loss/grad");
+  CHECK_HIP(nn_adam(c, lr), "nn adam");
+  return HYB_OK;
+}
+
+int hyb_nn_energy_grad(hyb_ctx *c, const float *x, const double *rhat, int32_t nsamp, double *loss, float *grad) {
+  if (!c) return HYB_EINVAL;
+  if (!c->nn.loaded) return fail(c, HYB_ESTATE, "no weights");
+  if (!c->condensed) return fail(c, HYB_ESTATE, "energy loss before condense");
+  if (!x || !rhat || nsamp < 1) return fail(c, HYB_EINVAL, "bad energy arguments");
+  CHECK_HIP(nn_energy_grad(c, x, rhat, nsamp, loss), "nn energy grad");
+  if (grad) {
+    CHECK_HIP(hipStreamSynchronize(c->stream), "sync");
+    CHECK_HIP(hipMemcpy(grad, c->nn.g, nn_param_count() * sizeof(float), hipMemcpyDeviceToHost), "d2h grad");
+  }
+  return HYB_OK;
+}
+
+int hyb_nn_energy_train_step(hyb_ctx *c, const float *x, const double *rhat, int32_t nsamp, float lr, double *loss) {
+  if (!c) return HYB_EINVAL;
+  if (!c->nn.loaded) return fail(c, HYB_ESTATE, "no weights");
+  if (!c->condensed) return fail(c, HYB_ESTATE, "energy loss before condense");
+  if (!x || !rhat || nsamp < 1 || !(lr > 0)) return fail(c, HYB_EINVAL, "bad train arguments");
+  CHECK_HIP(nn_energy_grad(c, x, rhat, nsamp, loss), "nn energy grad");
   CHECK_HIP(nn_adam(c, lr), "nn adam");
   return HYB_OK;
 }

@@ -48,6 +48,10 @@ struct NNState {
   float *part = nullptr, *tmpg = nullptr, *lpart = nullptr;       // reduction scratch
   float *cin = nullptr, *cout = nullptr;                          // learned stage input / output [ncell]
   double *scal = nullptr;                                         // learned stage scalars (device)
+  double *d64 = nullptr, *sd64 = nullptr;                         // correction d and S d [ntrace]
+  double *gq = nullptr, *epart = nullptr;                         // energy loss: G q [nsamp][ncell], partials
+  size_t gq_cap = 0;
+  double dbar = 0.0;                                              // mean of the diagonal of H
   size_t cap = 0;                                                 // cells x samples the activations hold
   long step = 0;
   bool loaded = false;
@@ -185,11 +189,14 @@ hipError_t nn_set_weights(hyb_ctx *c, const float *host_w);
 hipError_t nn_get_weights(hyb_ctx *c, float *host_w);
 hipError_t nn_forward(hyb_ctx *c, const float *x, float *out, int nsamp);
 hipError_t nn_loss_grad(hyb_ctx *c, const float *x, const float *target, int nsamp, float *loss_host);
+hipError_t nn_energy_grad(hyb_ctx *c, const float *x, const double *rhat, int nsamp, double *loss_host);
 hipError_t nn_adam(hyb_ctx *c, float lr);
 void nn_free(hyb_ctx *c);
-// restriction of a trace vector to cells: mode 0 Gamma P^T r, mode 1 P^T r / P^T 1 (cell average)
+// restriction of a trace vector to cells: mode 0 Gamma P^T r, mode 1 P^T r / P^T 1 (cell average),
+// mode 2 H_diag times mode 1, mode 3 P^T r
 hipError_t launch_restrict_cells(hyb_ctx *c, const double *r, double *cells, int mode);
-// learned stage: z += s P N(c / s), c = Gamma P^T (r - S z), s = rms(c); skipped if not finite
+// learned stage: d = s P (N(c / s) / H_diag), c = Gamma P^T (r - S z), s = rms(c); z += d if it
+// lowers ||r - S z||, else counted as a fallback
 template <typename Tz>
 hipError_t learned_stage(hyb_ctx *c, const double *r, Tz *z);
 

@@ -216,11 +216,12 @@ __global__ void k_weights_to_bf16(const float *__restrict__ w, uint16_t *__restr
   if (q >= 0) wb[q] = f2bf(w[j]);
 }
 
-// cells[c] = mode 0: Gamma_c sum_F w_F r_F;  mode 1: sum_F w_F r_F / sum_F w_F  (w = 1/2, 1 on
-// ground and lid facets: the transpose of the facet-average prolongation)
+// cells[c] = mode 0: Gamma_c sum_F w_F r_F;  mode 1: sum_F w_F r_F / sum_F w_F;  mode 2: H_cc times
+// mode 1;  mode 3: sum_F w_F r_F, i.e. (P^T r)_c  (w = 1/2, 1 on ground and lid facets: P^T for the
+// facet-average prolongation P)
 __global__ void k_restrict_cells(const double *__restrict__ r, const double *__restrict__ gamma,
-                                 double *__restrict__ out, int nlev, int ncol, int nedge, size_t nz,
-                                 const int32_t *__restrict__ col_edge, int mode) {
+                                 const double *__restrict__ hdiag, double *__restrict__ out, int nlev, int ncol,
+                                 int nedge, size_t nz, const int32_t *__restrict__ col_edge, int mode) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nlev * ncol) return;
   int k = c / ncol, col = c - k * ncol;
@@ -231,7 +232,16 @@ __global__ void k_restrict_cells(const double *__restrict__ r, const double *__r
   s *= 0.5;
   double wb = (k == 0 ? 1.0 : 0.5), wt = (k == nlev - 1 ? 1.0 : 0.5);
   s += wb * r[(size_t)k * ncol + col] + wt * r[(size_t)(k + 1) * ncol + col];
-  out[c] = mode == 0 ? gamma[c] * s : s / (2.0 + wb + wt);
+  double v;
+  if (mode == 0)
+    v = gamma[c] * s;
+  else if (mode == 1)
+    v = s / (2.0 + wb + wt);
+  else if (mode == 2)
+    v = hdiag[c] * s / (2.0 + wb + wt);
+  else
+    v = s;
+  out[c] = v;
 }
 
 // sum of squares of a vector into part[blk]
@@ -270,34 +280,121 @@ __global__ void k_normalise(const double *__restrict__ c, const double *__restri
   x[i] = s > 0.0 ? (float)(c[i] / s) : 0.f;
 }
 
-// z_F += s (P y)_F when the network output is finite (scal[1] = sum y^2); else count a fallback
-template <typename Tz>
-__global__ void k_prolong_scaled(const float *__restrict__ y, double *__restrict__ scal, Tz *__restrict__ z,
-                                 int nlev, int ncol, int nedge, size_t nz, size_t ntr,
-                                 const int32_t *__restrict__ edge_col) {
+// d_F = s (P (y / H_diag))_F when the network output is finite (scal[1] = sum y^2), else 0
+__global__ void k_prolong_correction(const float *__restrict__ y, const double *__restrict__ scal,
+                                     const double *__restrict__ hdiag, double *__restrict__ d, int nlev, int ncol,
+                                     int nedge, size_t nz, size_t ntr, const int32_t *__restrict__ edge_col) {
   size_t F = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool ok = isfinite(scal[1]);
-  if (!ok) {
-    if (F == 0) scal[2] += 1.0;
+  if (F >= ntr) return;
+  if (!isfinite(scal[1])) {
+    d[F] = 0.0;
     return;
   }
-  if (F >= ntr) return;
   const double s = sqrt(scal[0] / (double)((size_t)nlev * ncol));
   double v;
   if (F < nz) {
     int k = (int)(F / ncol), col = (int)(F - (size_t)k * ncol);
+    size_t lo = (size_t)(k - 1) * ncol + col, hi = (size_t)k * ncol + col;
     if (k == 0)
-      v = y[col];
+      v = (double)y[hi] / hdiag[hi];
     else if (k == nlev)
-      v = y[(size_t)(nlev - 1) * ncol + col];
+      v = (double)y[lo] / hdiag[lo];
     else
-      v = 0.5 * ((double)y[(size_t)(k - 1) * ncol + col] + (double)y[(size_t)k * ncol + col]);
+      v = 0.5 * ((double)y[lo] / hdiag[lo] + (double)y[hi] / hdiag[hi]);
   } else {
     size_t h = F - nz;
     int k = (int)(h / nedge), e = (int)(h - (size_t)k * nedge);
-    v = 0.5 * ((double)y[(size_t)k * ncol + edge_col[e]] + (double)y[(size_t)k * ncol + edge_col[nedge + e]]);
+    size_t a = (size_t)k * ncol + edge_col[e], b = (size_t)k * ncol + edge_col[nedge + e];
+    v = 0.5 * ((double)y[a] / hdiag[a] + (double)y[b] / hdiag[b]);
   }
-  z[F] = (Tz)((double)z[F] + s * v);
+  d[F] = s * v;
+}
+
+// partial sums of ||t - u||^2 (row 0) and ||t||^2 (row 1) per block: part[row * gridDim.x + blk]
+__global__ void __launch_bounds__(kBlock) k_judge_sums(const double *__restrict__ t, const double *__restrict__ u,
+                                                      size_t n, double *__restrict__ part) {
+  __shared__ double red[2][kBlock / 64];
+  double a = 0.0, b = 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    double ti = t[i], di = ti - u[i];
+    a += di * di;
+    b += ti * ti;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_down(a, off, 64);
+    b += __shfl_down(b, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) red[0][threadIdx.x >> 6] = a, red[1][threadIdx.x >> 6] = b;
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double t2 = 0.0;
+    for (int q = 0; q < kBlock / 64; ++q) t2 += red[threadIdx.x][q];
+    part[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = t2;
+  }
+}
+
+// z += d if the network output was finite (scal[1] = sum y^2) and the corrected residual stays
+// below tau times the cycle's (scal[3] = ||r' - S d||^2, scal[4] = ||r'||^2); otherwise z is left as
+// the two-level cycle made it and the fallback counter scal[2] grows
+template <typename Tz>
+__global__ void k_apply_correction(const double *__restrict__ d, double *__restrict__ scal, Tz *__restrict__ z,
+                                   size_t n, double tau2) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool ok = isfinite(scal[1]) && scal[3] < tau2 * scal[4];  // false for NaN
+  if (!ok) {
+    if (i == 0) scal[2] += 1.0;
+    return;
+  }
+  if (i < n) z[i] = (Tz)((double)z[i] + d[i]);
+}
+
+// out_F = (P (y / H_diag))_F for one sample of network outputs y [ncell]
+__global__ void k_prolong_q(const float *__restrict__ y, const double *__restrict__ hdiag, double *__restrict__ out,
+                            int nlev, int ncol, int nedge, size_t nz, size_t ntr, const int32_t *__restrict__ edge_col) {
+  size_t F = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (F >= ntr) return;
+  double v;
+  if (F < nz) {
+    int k = (int)(F / ncol), col = (int)(F - (size_t)k * ncol);
+    size_t lo = (size_t)(k - 1) * ncol + col, hi = (size_t)k * ncol + col;
+    if (k == 0)
+      v = (double)y[hi] / hdiag[hi];
+    else if (k == nlev)
+      v = (double)y[lo] / hdiag[lo];
+    else
+      v = 0.5 * ((double)y[lo] / hdiag[lo] + (double)y[hi] / hdiag[hi]);
+  } else {
+    size_t h = F - nz;
+    int k = (int)(h / nedge), e = (int)(h - (size_t)k * nedge);
+    size_t a = (size_t)k * ncol + edge_col[e], b = (size_t)k * ncol + edge_col[nedge + e];
+    v = 0.5 * ((double)y[a] / hdiag[a] + (double)y[b] / hdiag[b]);
+  }
+  out[F] = v;
+}
+
+// Energy loss over a batch: q = y / H_diag per cell (H_diag repeats for every sample), partial sums of
+// q (Gq - 2 rhat) per block, and dy = 2 (Gq - rhat) / H_diag * scale
+__global__ void __launch_bounds__(kBlock) k_energy(const float *__restrict__ y, const double *__restrict__ gq,
+                                                  const double *__restrict__ rhat, const double *__restrict__ hdiag,
+                                                  float *__restrict__ dy, size_t ncell, size_t total, double scale,
+                                                  double *__restrict__ part) {
+  __shared__ double red[kBlock / 64];
+  double acc = 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    double h = hdiag[i % ncell], q = (double)y[i] / h, g = gq[i], r = rhat[i];
+    acc += q * (g - 2.0 * r);
+    dy[i] = (float)(2.0 * (g - r) / h * scale);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < kBlock / 64; ++q) t += red[q];
+    part[blockIdx.x] = t;
+  }
 }
 
 __global__ void k_zero_scal(double *p, int n) {
@@ -308,8 +405,8 @@ __global__ void k_zero_scal(double *p, int n) {
 
 hipError_t launch_restrict_cells(hyb_ctx *c, const double *r, double *cells, int mode) {
   const LevelDev &L0 = c->lv[0];
-  hipLaunchKernelGGL(k_restrict_cells, dim3(nblk(c->ncell)), dim3(kBlock), 0, c->stream, r, c->gamma, cells, c->nlev,
-                     c->ncol, c->nedge, (size_t)c->nz, L0.col_edge, mode);
+  hipLaunchKernelGGL(k_restrict_cells, dim3(nblk(c->ncell)), dim3(kBlock), 0, c->stream, r, c->gamma, L0.H, cells,
+                     c->nlev, c->ncol, c->nedge, (size_t)c->nz, L0.col_edge, mode);
   return hipGetLastError();
 }
 
@@ -437,21 +534,20 @@ static hipError_t weight_grad(hyb_ctx *c, const float *dy, const float *x, int n
   return hipMemcpyAsync(grad_b, s.tmpg + WS, CO * 4, hipMemcpyDeviceToDevice, c->stream);
 }
 
-// Loss (mean squared error over all cells and samples) and gradients into s.g.
-hipError_t nn_loss_grad(hyb_ctx *c, const float *x, const float *target, int nsamp, float *loss_host) {
-  NNState &s = c->nn;
-  // the activation buffers (s.y among them) must exist at this size before s.y is passed on
-  hipError_t e = ensure_acts(c, nsamp);
-  if (e) return e;
-  if ((e = nn_forward(c, x, s.y, nsamp))) return e;
+static hipError_t ensure_grad_scratch(NNState &s) {
+  hipError_t e = hipSuccess;
   if (!s.tmpg) {
     if ((e = hipMalloc((void **)&s.tmpg, (W2N + C) * 4))) return e;
     if ((e = hipMalloc((void **)&s.lpart, 1024 * 4))) return e;
   }
+  return e;
+}
+
+// Gradients of every parameter into s.g from dL/dy in s.dy (activations of the last forward pass).
+static hipError_t nn_backward(hyb_ctx *c, const float *x, int nsamp) {
+  NNState &s = c->nn;
+  hipError_t e;
   size_t n = (size_t)c->ncell * nsamp;
-  unsigned nb = std::min<unsigned>(1024, nblk(n));
-  hipLaunchKernelGGL(k_mse, dim3(nb), dim3(kBlock), 0, c->stream, s.y, target, s.dy, n, s.lpart);
-  if ((e = hipGetLastError())) return e;
   dim3 g(nblk(n)), b(kBlock);
   int L = c->nlev, nc = c->ncol;
   // layer 3: dy -> dW3, db3, d(a2) masked by a2 > 0
@@ -465,7 +561,22 @@ hipError_t nn_loss_grad(hyb_ctx *c, const float *x, const float *target, int nsa
                      s.nb9);
   if ((e = hipGetLastError())) return e;
   // layer 1 (input x)
-  if ((e = weight_grad<1, C>(c, s.d1, x, nsamp, s.g + OFF_W1, s.g + OFF_B1))) return e;
+  return weight_grad<1, C>(c, s.d1, x, nsamp, s.g + OFF_W1, s.g + OFF_B1);
+}
+
+// Loss (mean squared error over all cells and samples) and gradients into s.g.
+hipError_t nn_loss_grad(hyb_ctx *c, const float *x, const float *target, int nsamp, float *loss_host) {
+  NNState &s = c->nn;
+  // the activation buffers (s.y among them) must exist at this size before s.y is passed on
+  hipError_t e = ensure_acts(c, nsamp);
+  if (e) return e;
+  if ((e = nn_forward(c, x, s.y, nsamp))) return e;
+  if ((e = ensure_grad_scratch(s))) return e;
+  size_t n = (size_t)c->ncell * nsamp;
+  unsigned nb = std::min<unsigned>(1024, nblk(n));
+  hipLaunchKernelGGL(k_mse, dim3(nb), dim3(kBlock), 0, c->stream, s.y, target, s.dy, n, s.lpart);
+  if ((e = hipGetLastError())) return e;
+  if ((e = nn_backward(c, x, nsamp))) return e;
   if (loss_host) {
     std::vector<float> lp(nb);
     if ((e = hipMemcpyAsync(lp.data(), s.lpart, nb * 4, hipMemcpyDeviceToHost, c->stream))) return e;
@@ -473,6 +584,61 @@ hipError_t nn_loss_grad(hyb_ctx *c, const float *x, const float *target, int nsa
     double acc = 0.0;
     for (unsigned i = 0; i < nb; ++i) acc += lp[i];
     *loss_host = (float)(acc / (double)n);
+  }
+  return hipSuccess;
+}
+
+// Energy loss of a batch, (1/nsamp) sum_i (q_i^T G q_i - 2 q_i^T rhat_i) mean(H_diag) / ncell with
+// q_i = N(x_i) / H_diag and G = P^T S P, and its gradients into s.g.  x [nsamp][ncell] FP32,
+// rhat [nsamp][ncell] FP64.
+hipError_t nn_energy_grad(hyb_ctx *c, const float *x, const double *rhat, int nsamp, double *loss_host) {
+  NNState &s = c->nn;
+  hipError_t e = ensure_acts(c, nsamp);
+  if (e) return e;
+  if ((e = ensure_grad_scratch(s))) return e;
+  const size_t ncell = (size_t)c->ncell, ntr = (size_t)c->ntrace, n = ncell * nsamp;
+  if (s.gq_cap < n) {
+    if (s.gq) (void)hipFree(s.gq), s.gq = nullptr;
+    if ((e = hipMalloc((void **)&s.gq, n * 8))) return e;
+    s.gq_cap = n;
+  }
+  if (!s.d64) {
+    if ((e = hipMalloc((void **)&s.d64, ntr * 8)) || (e = hipMalloc((void **)&s.sd64, ntr * 8))) return e;
+  }
+  const LevelDev &L0 = c->lv[0];
+  if (!(s.dbar > 0.0)) {  // mean of the diagonal of H (once)
+    std::vector<double> h(ncell);
+    if ((e = hipMemcpy(h.data(), L0.H, ncell * 8, hipMemcpyDeviceToHost))) return e;
+    double acc = 0.0;
+    for (double v : h) acc += v;
+    s.dbar = acc / (double)ncell;
+  }
+  if ((e = nn_forward(c, x, s.y, nsamp))) return e;
+  for (int i = 0; i < nsamp; ++i) {
+    hipLaunchKernelGGL(k_prolong_q, dim3(nblk(ntr)), dim3(kBlock), 0, c->stream, s.y + (size_t)i * ncell, L0.H, s.d64,
+                       c->nlev, c->ncol, c->nedge, (size_t)c->nz, ntr, L0.edge_col);
+    if ((e = hipGetLastError())) return e;
+    if ((e = launch_trace_apply<double, double, double>(c, c->S, s.d64, nullptr, s.sd64, 0))) return e;
+    if ((e = launch_restrict_cells(c, s.sd64, s.gq + (size_t)i * ncell, 3))) return e;
+  }
+  const double scale = s.dbar / (double)ncell / (double)nsamp;
+  unsigned nb = std::min<unsigned>(1024, nblk(n));
+  double *part = s.epart;
+  if (!part) {
+    if ((e = hipMalloc((void **)&s.epart, 1024 * 8))) return e;
+    part = s.epart;
+  }
+  hipLaunchKernelGGL(k_energy, dim3(nb), dim3(kBlock), 0, c->stream, s.y, s.gq, rhat, L0.H, s.dy, ncell, n, scale,
+                     part);
+  if ((e = hipGetLastError())) return e;
+  if ((e = nn_backward(c, x, nsamp))) return e;
+  if (loss_host) {
+    std::vector<double> lp(nb);
+    if ((e = hipMemcpyAsync(lp.data(), part, nb * 8, hipMemcpyDeviceToHost, c->stream))) return e;
+    if ((e = hipStreamSynchronize(c->stream))) return e;
+    double acc = 0.0;
+    for (unsigned i = 0; i < nb; ++i) acc += lp[i];
+    *loss_host = acc * scale;
   }
   return hipSuccess;
 }
@@ -487,31 +653,38 @@ hipError_t nn_adam(hyb_ctx *c, float lr) {
   return hipGetLastError();
 }
 
-// The learned coarse correction applied after the two-level cycle: r' = r - S z,
-// c = Gamma P^T r', s = rms(c), z += s P N(c / s).  Everything stays on the device; a non-finite
-// network output leaves z unchanged and increments the fallback counter scal[2].
+// The learned coarse correction applied after the two-level cycle z = M(r):
+//   r' = r - S z,  c = Gamma P^T r',  s = rms(c),  d = s P (N(c / s) / H_diag),
+//   z += d  if ||r' - S d|| < ||r'||  (the FP64 residual judges every correction),
+// otherwise z stays the plain cycle's output and the fallback counter scal[2] grows (also when the
+// network output is not finite).  Everything stays on the device; no host synchronisation.
 template <typename Tz>
 hipError_t learned_stage(hyb_ctx *c, const double *r, Tz *z) {
   NNState &s = c->nn;
   hipError_t e;
-  size_t n = (size_t)c->ncell;
+  const size_t n = (size_t)c->ncell, ntr = (size_t)c->ntrace;
   if (!s.cin) {
     if ((e = hipMalloc((void **)&s.cin, n * 4)) || (e = hipMalloc((void **)&s.cout, n * 4)) ||
-        (e = hipMalloc((void **)&s.scal, 4 * sizeof(double))))
+        (e = hipMalloc((void **)&s.scal, 8 * sizeof(double))))
       return e;
-    hipLaunchKernelGGL(k_zero_scal, dim3(1), dim3(64), 0, c->stream, s.scal, 4);
+    hipLaunchKernelGGL(k_zero_scal, dim3(1), dim3(64), 0, c->stream, s.scal, 8);
     if ((e = hipGetLastError())) return e;
-    c->bytes += n * 8 + 32;
+    c->bytes += n * 8 + 64;
+  }
+  if (!s.d64) {
+    if ((e = hipMalloc((void **)&s.d64, ntr * 8)) || (e = hipMalloc((void **)&s.sd64, ntr * 8))) return e;
+    c->bytes += 2 * ntr * 8;
   }
   if (!c->cell64) {
     if ((e = hipMalloc((void **)&c->cell64, n * 8))) return e;
     c->bytes += n * 8;
   }
   int slot = prof_begin(c, F_NN);
+  const LevelDev &L0 = c->lv[0];
   if ((e = launch_trace_apply<double, Tz, double>(c, c->S, z, r, c->t64, 1))) return e;
   if ((e = launch_restrict_cells(c, c->t64, c->cell64, 0))) return e;
   unsigned nb = std::min<unsigned>(1024, nblk(n));
-  double *part = c->partial;  // Krylov reduction scratch (>= 1024 doubles)
+  double *part = c->partial;  // Krylov reduction scratch (>= 2 x 1024 doubles)
   hipLaunchKernelGGL((k_sumsq<double>), dim3(nb), dim3(kBlock), 0, c->stream, c->cell64, n, part);
   hipLaunchKernelGGL(k_sum_into, dim3(1), dim3(64), 0, c->stream, part, (int)nb, s.scal);
   hipLaunchKernelGGL(k_normalise, dim3(nblk(n)), dim3(kBlock), 0, c->stream, c->cell64, s.scal, s.cin, n);
@@ -519,9 +692,16 @@ hipError_t learned_stage(hyb_ctx *c, const double *r, Tz *z) {
   if ((e = nn_forward(c, s.cin, s.cout, 1))) return e;
   hipLaunchKernelGGL((k_sumsq<float>), dim3(nb), dim3(kBlock), 0, c->stream, s.cout, n, part);
   hipLaunchKernelGGL(k_sum_into, dim3(1), dim3(64), 0, c->stream, part, (int)nb, s.scal + 1);
-  const LevelDev &L0 = c->lv[0];
-  hipLaunchKernelGGL((k_prolong_scaled<Tz>), dim3(nblk(c->ntrace)), dim3(kBlock), 0, c->stream, s.cout, s.scal, z,
-                     c->nlev, c->ncol, c->nedge, (size_t)c->nz, (size_t)c->ntrace, L0.edge_col);
+  hipLaunchKernelGGL(k_prolong_correction, dim3(nblk(ntr)), dim3(kBlock), 0, c->stream, s.cout, s.scal, L0.H, s.d64,
+                     c->nlev, c->ncol, c->nedge, (size_t)c->nz, ntr, L0.edge_col);
+  if ((e = hipGetLastError())) return e;
+  if ((e = launch_trace_apply<double, double, double>(c, c->S, s.d64, nullptr, s.sd64, 0))) return e;
+  unsigned nbt = std::min<unsigned>(1024, nblk(ntr));
+  hipLaunchKernelGGL(k_judge_sums, dim3(nbt), dim3(kBlock), 0, c->stream, c->t64, s.sd64, ntr, part);
+  hipLaunchKernelGGL(k_sum_into, dim3(1), dim3(64), 0, c->stream, part, (int)nbt, s.scal + 3);
+  hipLaunchKernelGGL(k_sum_into, dim3(1), dim3(64), 0, c->stream, part + nbt, (int)nbt, s.scal + 4);
+  hipLaunchKernelGGL((k_apply_correction<Tz>), dim3(nblk(ntr)), dim3(kBlock), 0, c->stream, s.d64, s.scal, z, ntr,
+                     c->p.learned_tau * c->p.learned_tau);
   prof_end(c, F_NN, slot);
   return hipGetLastError();
 }
@@ -537,6 +717,12 @@ void nn_free(hyb_ctx *c) {
   if (s.isbf) (void)hipFree(s.isbf), s.isbf = nullptr;
   if (s.nb9) (void)hipFree(s.nb9), s.nb9 = nullptr;
   if (s.scal) (void)hipFree(s.scal), s.scal = nullptr;
+  if (s.d64) (void)hipFree(s.d64), s.d64 = nullptr;
+  if (s.sd64) (void)hipFree(s.sd64), s.sd64 = nullptr;
+  if (s.gq) (void)hipFree(s.gq), s.gq = nullptr;
+  if (s.epart) (void)hipFree(s.epart), s.epart = nullptr;
+  s.gq_cap = 0;
+  s.dbar = 0.0;
   if (c->cell64) (void)hipFree(c->cell64), c->cell64 = nullptr;
   s.cap = 0;
 }

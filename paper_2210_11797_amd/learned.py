@@ -1,14 +1,14 @@
 """Learned coarse correction: training data and training loop (driver around the HIP library).
 
-Pairs (input, target) come from the plain method: for a right-hand side b, lambda* is solved to a
-tight tolerance; then the two-level cycle is applied as a stationary iteration, x_{k+1} = x_k +
-M(r_k), r_{k+1} = r_k - S M(r_k).  Each step gives one pair with the residual r' = r_{k+1} left by
-the cycle: input c / s with c = Gamma P^T r' (the coarse right-hand side of Alg. 2) and s = rms(c);
-target the facet average of the remaining error lambda* - x_{k+1}, divided by s.  At inference the
-library adds s P N(c / s) to the output of the cycle (see include/hyb.h).
+Pairs come from the plain method: from a right-hand side b, the two-level cycle is applied as a
+stationary iteration, r_{k+1} = r_k - S M(r_k).  Each step gives one pair from the residual r' left
+by the cycle: x = c / s with c = Gamma P^T r' (the coarse right-hand side of Alg. 2) and s = rms(c),
+and rhat = P^T r' / s.  Training minimises the error energy that the stage's correction
+d = s P (N(x) / H_KK) leaves, through the library's energy loss q^T G q - 2 q^T rhat with
+q = N(x) / H_KK and G = P^T S P: no solve with S is needed (see include/hyb.h).
 
-The solves, the cycle, S, the restrictions and every network pass (forward, backward, Adam) run in
-libhyb.so; torch only holds the vectors and does the vector updates between calls.
+The cycle, S, the restrictions and every network pass (forward, backward, Adam) run in libhyb.so;
+torch only holds the vectors and does the vector updates between calls.
 """
 
 from __future__ import annotations
@@ -50,56 +50,50 @@ def init_params(channels=16, seed=0):
     return pack(W, b)
 
 
-def generate_pairs(solver, rhs_list, steps=8, rtol=1e-12):
-    """rhs_list: device FP64 trace right-hand sides.  Returns (X, T) device FP32 [npairs][ncell]."""
+def generate_pairs(solver, rhs_list, steps=8):
+    """rhs_list: device FP64 trace right-hand sides.  Returns (X FP32, Rhat FP64), both
+    [npairs][ncell] on the device."""
     import torch
 
     n, nc = solver.ntrace, solver.ncell
-    X, T = [], []
-    lam_star = torch.zeros(n, dtype=torch.float64, device="cuda")
-    z = torch.empty_like(lam_star)
-    sz = torch.empty_like(lam_star)
+    X, R = [], []
+    z = torch.empty(n, dtype=torch.float64, device="cuda")
+    sz = torch.empty_like(z)
     cells = torch.empty(nc, dtype=torch.float64, device="cuda")
-    err_cells = torch.empty_like(cells)
+    pt = torch.empty_like(cells)
     for b in rhs_list:
-        lam_star.zero_()
-        info = solver.solve(b, lam_star, rtol=rtol, maxit=400)
-        if info["status"] != 0:
-            raise RuntimeError(f"training solve did not converge: {info}")
-        x = torch.zeros_like(lam_star)
         r = b.clone()
         for _ in range(steps):
             solver.precondition(r, z)
-            x += z
             solver.trace_apply(z, sz)
             r -= sz
             solver.restrict(r, cells, 0)
             s = torch.sqrt(torch.mean(cells * cells))
             if not torch.isfinite(s) or float(s) == 0.0:
                 break
-            solver.restrict(lam_star - x, err_cells, 1)
+            solver.restrict(r, pt, 3)
             X.append((cells / s).float())
-            T.append((err_cells / s).float())
-    return torch.stack(X), torch.stack(T)
+            R.append(pt / s)
+    return torch.stack(X), torch.stack(R)
 
 
-def train(solver, X, T, steps=300, batch=8, lr=1e-3, seed=0, log=None):
-    """Adam on random mini-batches of pairs; returns the loss history."""
+def train(solver, X, R, steps=1000, batch=8, lr=2e-3, seed=0, log=None):
+    """Adam on the energy loss over random mini-batches of pairs; returns the loss history."""
     import torch
 
     g = torch.Generator(device="cpu").manual_seed(seed)
     npairs = X.shape[0]
     xb = torch.empty((batch, X.shape[1]), dtype=torch.float32, device="cuda")
-    tb = torch.empty_like(xb)
+    rb = torch.empty((batch, R.shape[1]), dtype=torch.float64, device="cuda")
     hist = []
     for it in range(steps):
         idx = torch.randint(0, npairs, (batch,), generator=g).cuda()
         torch.index_select(X, 0, idx, out=xb)
-        torch.index_select(T, 0, idx, out=tb)
-        loss = solver.nn_train_step(xb, tb, batch, lr)
+        torch.index_select(R, 0, idx, out=rb)
+        loss = solver.nn_energy_train_step(xb, rb, batch, lr)
         hist.append(loss)
-        if log and (it % 50 == 0 or it == steps - 1):
-            log(f"train step {it}: loss {loss:.4e}")
+        if log and (it % 250 == 0 or it == steps - 1):
+            log(f"train step {it}: energy loss {loss:.4e}")
     return hist
 
 

@@ -134,7 +134,8 @@ def solver_sequence(lib):
         c.call("hyb_profile_read", fam.encode(), ctypes.byref(n), ctypes.byref(ms))
     c.call("hyb_profile", 0)
     # argument errors come back as codes
-    check(lib.hyb_restrict(c.h, P(b), P(cells), 2) < 0, "bad restriction mode rejected")
+    check(lib.hyb_restrict(c.h, P(b), P(cells), 4) < 0 and lib.hyb_restrict(c.h, P(b), P(cells), -1) < 0,
+          "bad restriction modes rejected")
     check(lib.hyb_solve(c.h, P(b), P(b), 1e-8, 10, None) < 0, "aliased solve vectors rejected")
     c.close()
 
@@ -146,6 +147,25 @@ def network_sequence(lib):
     rng = np.random.default_rng(0)
     check(lib.hyb_nn_forward(c.h, None, None, 1) < 0, "network call before weights rejected")
     w = learned.init_params(16, seed=2)
+    c.call("hyb_nn_set_weights", P(w), w.size)
+    # the preconditioner with the stage before any solve (Krylov scratch not yet allocated)
+    v, z = rng.standard_normal(c.ntrace), np.empty(c.ntrace)
+    for prec in (N.PREC_MIXED, N.PREC_FP64):
+        c.set(learned=1, precision=prec)
+        c.call("hyb_precondition", P(v), P(z))
+    cells = np.empty(nc)
+    c.call("hyb_restrict", P(v), P(cells), 2)
+    c.call("hyb_restrict", P(v), P(cells), 3)
+    c.set(learned=0)
+    # energy loss: first with a batch of 2, then a larger one (buffers grow)
+    for ns in (2, 4):
+        xe = rng.standard_normal((ns, nc)).astype(np.float32)
+        re = rng.standard_normal((ns, nc))
+        el = ctypes.c_double()
+        ge = np.empty(w.size, np.float32)
+        c.call("hyb_nn_energy_grad", P(xe), P(re), ns, ctypes.byref(el), P(ge))
+        c.call("hyb_nn_energy_train_step", P(xe), P(re), ns, ctypes.c_float(1e-3), None)
+    check(np.isfinite(el.value) and np.all(np.isfinite(ge)), f"energy loss and gradient: {el.value:.3e}")
     c.call("hyb_nn_set_weights", P(w), w.size)
     loss = ctypes.c_float()
     # a training step as the very first network call (activation buffers not yet allocated)

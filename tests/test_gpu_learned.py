@@ -82,13 +82,90 @@ def test_restriction_modes(small):
     say(f"[restrict] Gamma P^T r: {err:.2e} (tol {tol:.2e}, cancellation ratio {ratio:.2e})")
     assert err <= tol
     s.restrict(dev(r), c, 1)
-    assert rel_max(host(c), (P.T @ r) / (P.T @ np.ones(orc.mesh.ntrace))) <= 1e-12
+    avg = (P.T @ r) / (P.T @ np.ones(orc.mesh.ntrace))
+    assert rel_max(host(c), avg) <= 1e-12
+    s.restrict(dev(r), c, 2)
+    assert rel_max(host(c), orc.H.diagonal() * avg) <= 1e-12
+    s.restrict(dev(r), c, 3)
+    assert rel_max(host(c), P.T @ r) <= 1e-12
+
+
+@pytest.mark.gpu
+def test_energy_loss_gradients_match_oracle(small):
+    """The training loss of the stage (error energy after the correction) and its gradients against
+    the oracle's, with G = P^T S P and the oracle's S (which the GPU's matches to 1e-12)."""
+    prob, s = small
+    orc = OracleProblem(prob)
+    P, S = orc.pc.P, orc.pc.S
+    G = (P.T @ S @ P).tocsr()
+    hd = orc.H.diagonal().copy()
+    rng = np.random.default_rng(13)
+    vec = learned.init_params(16, seed=14)
+    vec[16 * 45 : 16 * 45 + 16] = rng.standard_normal(16) * 0.1
+    vec[-1] = 0.3
+    s.nn_set_weights(vec)
+    x = rng.standard_normal((2, prob.ncell)).astype(np.float32)
+    rhat = rng.standard_normal((2, prob.ncell))
+    loss, g = s.nn_energy_grad(_f32(x), dev(rhat), 2)
+    W, b = learned.unpack(vec)
+    Wr = [onn.bf16_round(w) for w in W]
+    nb = onn.neighbour_table(prob.nx, prob.ny)
+    refs = [onn.energy_loss_and_grads(x[i].astype(np.float64), rhat[i], Wr, b, nb, prob.nlev, G, hd) for i in range(2)]
+    lref = 0.5 * (refs[0][0] + refs[1][0])
+    gref = learned.pack([0.5 * (refs[0][1][j] + refs[1][1][j]) for j in range(3)],
+                        [0.5 * (refs[0][2][j] + refs[1][2][j]) for j in range(3)]).astype(np.float64)
+    errs, off = [], 0
+    for name, shp in learned.layout():
+        k = int(np.prod(shp))
+        errs.append(rel_max(g[off : off + k], gref[off : off + k]))
+        off += k
+    say(f"[energy] loss {loss:.6e} vs {lref:.6e}; grads {['%.1e' % e for e in errs]}")
+    assert abs(loss - lref) <= 1e-5 * abs(lref)
+    assert max(errs) <= 1e-4
+
+
+def _stage_reference(prob, orc, vec, v):
+    W, b = learned.unpack(vec)
+    Wr = [onn.bf16_round(w) for w in W]
+    z = orc.pc(v)
+    return onn.learned_correction(v, z, orc.pc.S, orc.pc.P, orc.pc.gamma, orc.H.diagonal(), Wr, b,
+                                  onn.neighbour_table(prob.nx, prob.ny), prob.nlev)
+
+
+@pytest.mark.gpu
+def test_precondition_with_learned_stage_matches_oracle(small):
+    """hyb_precondition with the stage against the oracle's cycle + stage: an exact identity network
+    (the correction is the closed form P H_KK^-1 Gamma P^T r') and a random one.  The network takes
+    c / s rounded to FP32 (relative 2^-24), so the correction agrees to about 1e-7 of its size."""
+    prob, s = small
+    import torch
+
+    orc = OracleProblem(prob)
+    Wi, bi = onn.identity_weights(16)
+    nets = {"identity": learned.pack(Wi, bi), "random": learned.init_params(16, seed=9)}
+    rng = np.random.default_rng(10)
+    p = s.params
+    for name, vec in nets.items():
+        s.nn_set_weights(vec)
+        for trial in range(3):
+            v = rng.standard_normal(orc.mesh.ntrace)
+            zref, acc = _stage_reference(prob, orc, vec, v)
+            z = torch.empty(s.ntrace, dtype=torch.float64, device="cuda")
+            p.learned = 1
+            s.set_params(p)
+            s.precondition(dev(v), z)
+            p.learned = 0
+            s.set_params(p)
+            err = rel_max(host(z), zref)
+            say(f"[stage] {name} trial {trial}: accepted {acc}, error {err:.2e}")
+            assert err <= 1e-6
 
 
 @pytest.mark.gpu
 def test_learned_stage_trains_and_gains():
-    """Train on pairs from the plain method on a 32x32x64 box (dx = 5 km, dz = 250 m), then compare
-    FGMRES iterations with and without the stage on held-out right-hand sides."""
+    """Train on the energy loss with pairs from the plain method on a 32x32x64 box (dx = 5 km,
+    dz = 250 m), then compare FGMRES iterations to 1e-8 with and without the stage on held-out
+    right-hand sides; every solve is checked with the oracle's S."""
     import torch
 
     prob = make_box(nx=32, ny=32, nlev=64, dx=5e3, dz=250.0, dt=600.0, mg_levels=4)
@@ -101,12 +178,12 @@ def test_learned_stage_trains_and_gains():
         s.condense(dev(r_ub), dev(r_pi), b)
         return b
 
-    X, T = learned.generate_pairs(s, [rhs(10000 + i) for i in range(48)], steps=8)
+    X, R = learned.generate_pairs(s, [rhs(10000 + i) for i in range(48)], steps=8)
     say(f"[learned] {X.shape[0]} pairs")
-    hist = learned.train(s, X, T, steps=400, batch=8, lr=2e-3, log=say)
-    assert np.mean(hist[-20:]) < 0.5 * np.mean(hist[:5])
+    hist = learned.train(s, X, R, steps=1500, batch=8, lr=2e-3, log=say)
+    assert np.mean(hist[-50:]) < np.mean(hist[:5])  # the energy loss starts near 0 and goes negative
     orc = OracleProblem(prob, with_precond=False)
-    plain, with_nn = [], []
+    plain, with_nn, used = [], [], []
     for seed in (1000, 1001, 1002):
         r_ub, r_pi = make_rhs(prob, seed)
         b = rhs(seed)
@@ -119,13 +196,17 @@ def test_learned_stage_trains_and_gains():
             ruc, rpc = cells_from_soa(r_ub, r_pi)
             B = orc.hyb.rhs(ruc, rpc)
             res = np.linalg.norm(B - orc.hyb.S @ host(lam)) / np.linalg.norm(B)
-            assert info["status"] == 0 and res <= 1.01e-8 and info["fallbacks"] == 0
+            assert info["status"] == 0 and res <= 1.01e-8
             out.append(info["iters"])
+            if flag:
+                used.append(info["iters"] - info["fallbacks"])
     p = s.params
     p.learned = 0
     s.set_params(p)
-    say(f"[learned] held-out iterations: plain {plain}, with learned stage {with_nn}")
-    assert sum(with_nn) <= sum(plain) + 3
+    say(f"[learned] held-out iterations: plain {plain}, with learned stage {with_nn} "
+        f"(corrections kept {used})")
+    assert sum(used) > 0
+    assert sum(with_nn) < sum(plain)
 
 
 @pytest.mark.gpu
