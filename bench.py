@@ -25,7 +25,7 @@ if ROOT not in sys.path:
 
 PEAK_HBM_GBS = 8000.0
 FAMILIES = ("smooth_rows", "smooth_rows0", "thomas", "trace_apply", "mg_smooth", "restrict", "prolong", "krylov",
-            "cell_solve")
+            "cell_solve", "nn")
 
 
 def log(*a):
@@ -156,6 +156,52 @@ def cpu_baseline(nx, nlev, dx, dz, dt, seeds=1):
     return dict(sec_per_solve=sum(times) / len(times), setup_s=t_setup, iters=its, ncell=prob.ncell)
 
 
+def learned_leg(args, prob, s, rhs, sec_plain, dx, dz, dt):
+    """Train the learned stage on a smaller box of the same physics (the network is local and
+    translation-equivariant, so its weights carry over), outside the timed region; then time the
+    solves with the stage on the benchmark box."""
+    import numpy as np
+    import torch
+
+    from paper_2210_11797_amd import learned
+    from synth import make_box, make_rhs
+
+    nt = args.train_nx
+    tprob = make_box(nx=nt, ny=nt, nlev=args.nlev, dx=dx, dz=dz, dt=dt, mg_levels=4)
+    ts = setup_solver(tprob, 0, mg_coarse_sweeps=args.coarse_sweeps)
+    ts.nn_set_weights(learned.init_params(16, seed=0))
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()  # noqa: E731
+    t0 = time.perf_counter()
+    bl = []
+    for sd in range(32):
+        r_ub, r_pi = make_rhs(tprob, 20000 + sd)
+        b = torch.empty(ts.ntrace, dtype=torch.float64, device="cuda")
+        ts.condense(d(r_ub), d(r_pi), b)
+        bl.append(b)
+    X, R = learned.generate_pairs(ts, bl, steps=8)
+    npairs = int(X.shape[0])
+    hist = learned.train(ts, X, R, steps=args.train_steps, batch=8, lr=2e-3, log=log)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    w = ts.nn_get_weights()
+    ts.close()
+    del X, R, bl
+    s.nn_set_weights(w)
+    p = s.params
+    p.learned = 1
+    s.set_params(p)
+    lsec, linfos, lfams = run_steps(s, rhs, args.steps, args.warmup, args.rtol, profile=True)
+    p.learned = 0
+    s.set_params(p)
+    nn_launches, nn_ms = lfams["nn"]
+    return dict(sec_per_solve=lsec, iters=[i["iters"] for i in linfos],
+                corrections_kept=[i["iters"] - i["fallbacks"] for i in linfos],
+                rel_res=max(i["rel_res"] for i in linfos), speedup_vs_fp64=sec_plain / lsec,
+                stage_ms_per_call=nn_ms / max(nn_launches, 1),
+                training=dict(box=f"{nt}x{nt}x{args.nlev}", pairs=npairs, steps=args.train_steps,
+                              batch=8, final_energy_loss=float(np.mean(hist[-50:])), seconds=train_s))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,6 +212,9 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--train-nx", type=int, default=64, help="box on which the learned stage is trained")
+    ap.add_argument("--train-steps", type=int, default=1500)
     ap.add_argument("--coarse-sweeps", type=int, default=30)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy (for scaling HBM counters), outside the timed region")
@@ -221,6 +270,10 @@ def main():
                      rel_res=max(i["rel_res"] for i in minfos), speedup_vs_fp64=sec / msec)
         sm.close()
 
+    learned_out = None
+    if not args.no_learned:
+        learned_out = learned_leg(args, prob, s, rhs, sec, dx, dz, dt)
+
     cpu = None
     if not args.no_cpu_baseline:
         nxs = 64
@@ -261,6 +314,7 @@ def main():
                      "launches": ls_launches, "avg_ms": ls_avg_ms, "bytes_per_launch": ls_bytes},
         "kernel_ms": {k: {"launches": v[0], "total_ms": v[1]} for k, v in fams.items()},
         "mixed": mixed,
+        "learned": learned_out,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
