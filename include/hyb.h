@@ -85,6 +85,7 @@ typedef struct {
   const hyb_level *levels;   /* [nlevels] */
   double dx, dy;
   const double *dz;          /* host [nlev] */
+  int32_t order;             /* 0: RT0 / Q0 / one trace dof per facet; 1: RT1 / DG1 / Q1 trace (below) */
 } hyb_mesh;
 
 typedef struct {
@@ -115,6 +116,17 @@ typedef struct {
   int32_t history_len;
   int32_t fallbacks;    /* learned corrections dropped (output not finite, or rejected by the residual test) */
 } hyb_info;
+
+/* Order 1 (the paper's p = 1 row of its table of unknowns; Sec. 2.2 forms with n = 4 point Gauss
+   rules and q32 / m3^rho / m3^Pi at the W3 nodes; Sec. 2.4 hybridisation): broken RT1 velocity, 36
+   dofs per cell ordered as the outward normal components at the 2x2 Gauss points of faces W, E, S,
+   N, B, T (24; face point i = 2 t1 + t2 in the face's tangential coordinates (y,z), (x,z), (x,y)),
+   then the mid-plane interior values (12); DG1 pressure nodal at the 2x2x2 Gauss points (8, index
+   4 i + 2 j + k); Q1 trace nodal at the 2x2 face Gauss points, trace dof 4 F + i for facet F in
+   the order-0 numbering.  Cell fields are the same inputs; right-hand sides and recovered fields
+   are r_ub / u_b [36][nlev][ncol] and r_pi / pi [8][nlev][ncol]; trace vectors have 4 x the
+   order-0 length (hyb_sizes).  Order 1 provides hyb_assemble_local, hyb_condense,
+   hyb_trace_apply and hyb_recover; the other calls return HYB_ESTATE for it. */
 
 /* Create a context for one mesh.  stream: a hipStream_t (NULL = default stream).
    Fails with HYB_EINVAL on inconsistent tables (every edge must appear on

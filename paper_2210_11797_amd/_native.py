@@ -33,7 +33,7 @@ class _Level(ctypes.Structure):
 
 class _Mesh(ctypes.Structure):
     _fields_ = [("nlev", ctypes.c_int32), ("nlevels", ctypes.c_int32), ("levels", ctypes.POINTER(_Level)),
-                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", _f64p)]
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", _f64p), ("order", ctypes.c_int32)]
 
 
 class _Params(ctypes.Structure):
@@ -159,10 +159,13 @@ class HybSolver:
     edge_lf [2, 2ncol] and, for coarse levels, parent [ncol of the finer level].
     """
 
-    def __init__(self, nlev, levels, dx, dy, dz, params: Params | None = None, stream=None):
+    def __init__(self, nlev, levels, dx, dy, dz, params: Params | None = None, stream=None, order: int = 0):
         import torch
 
         self.lib = load()
+        self.order = int(order)
+        # velocity and pressure dofs per cell
+        self.nu, self.npr = (6, 1) if self.order == 0 else (36, 8)
         self.params = params or Params()
         self.nlev = int(nlev)
         self._keep = []
@@ -181,7 +184,7 @@ class HybSolver:
             lv[i] = _Level(int(L["ncol"]), arrs["col_edge"], arrs["edge_col"], arrs["edge_lf"], par)
         dzh = np.ascontiguousarray(dz, dtype=np.float64)
         self._keep += [lv, dzh]
-        mesh = _Mesh(self.nlev, len(levels), lv, float(dx), float(dy), dzh.ctypes.data_as(_f64p))
+        mesh = _Mesh(self.nlev, len(levels), lv, float(dx), float(dy), dzh.ctypes.data_as(_f64p), self.order)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -237,7 +240,8 @@ class HybSolver:
         if r_ub is None:
             self._check(self.lib.hyb_condense(self.h, None, None, None), "hyb_condense")
             return
-        self._check(self.lib.hyb_condense(self.h, _ptr(r_ub, 6 * self.ncell, "r_ub"), _ptr(r_pi, self.ncell, "r_pi"),
+        self._check(self.lib.hyb_condense(self.h, _ptr(r_ub, self.nu * self.ncell, "r_ub"),
+                                          _ptr(r_pi, self.npr * self.ncell, "r_pi"),
                                           _ptr(b_lambda, self.ntrace, "b_lambda")), "hyb_condense")
 
     def trace_apply(self, x, y):
@@ -258,9 +262,10 @@ class HybSolver:
                     history=[hist[i] for i in range(info.history_len)], fallbacks=info.fallbacks)
 
     def recover(self, r_ub, r_pi, lam, u_b, pi):
-        self._check(self.lib.hyb_recover(self.h, _ptr(r_ub, 6 * self.ncell, "r_ub"), _ptr(r_pi, self.ncell, "r_pi"),
-                                         _ptr(lam, self.ntrace, "lambda"), _ptr(u_b, 6 * self.ncell, "u_b"),
-                                         _ptr(pi, self.ncell, "pi")), "hyb_recover")
+        self._check(self.lib.hyb_recover(self.h, _ptr(r_ub, self.nu * self.ncell, "r_ub"),
+                                         _ptr(r_pi, self.npr * self.ncell, "r_pi"), _ptr(lam, self.ntrace, "lambda"),
+                                         _ptr(u_b, self.nu * self.ncell, "u_b"), _ptr(pi, self.npr * self.ncell, "pi")),
+                    "hyb_recover")
 
     def restrict(self, r, cells, mode=0):
         self._check(self.lib.hyb_restrict(self.h, _ptr(r, self.ntrace, "r"), _ptr(cells, self.ncell, "cells"),

@@ -173,6 +173,7 @@ void free_all(hyb_ctx *c) {
     for (auto ev : f.ev) (void)hipEventDestroy(ev);
   c->fam.clear();
   nn_free(c);
+  p1_free(c);
 }
 
 int alloc_krylov(hyb_ctx *c) {
@@ -246,6 +247,12 @@ int hyb_create(const hyb_mesh *mesh, const hyb_params *params, void *stream, hyb
   c->ncell = c->nlev * c->ncol;
   c->nz = (c->nlev + 1) * c->ncol;
   c->ntrace = c->nz + c->nlev * c->nedge;
+  if (mesh->order != 0 && mesh->order != 1) {
+    delete c;
+    return HYB_EINVAL;
+  }
+  c->order = mesh->order;
+  if (c->order == 1) c->ntrace *= 4;
   c->dx = mesh->dx;
   c->dy = mesh->dy;
   c->dz.assign(mesh->dz, mesh->dz + c->nlev);
@@ -291,6 +298,7 @@ int hyb_set_params(hyb_ctx *c, const hyb_params *params) {
   if (rc) return rc;
   bool prec_change = params->precision != c->p.precision;
   c->p = *params;
+  if (c->order == 1) return HYB_OK;
   if (prec_change && c->condensed && c->p.precision == HYB_PREC_MIXED) {
     // FP32 copies are made at condensation; refresh them for the new mode
     CHECK_HIP(launch_to_float(c, c->S, c->Sf, (size_t)11 * c->ntrace), "to_float S");
@@ -310,6 +318,18 @@ int hyb_assemble_local(hyb_ctx *c, const double *theta_w, const double *exner_ha
   if (!c) return HYB_EINVAL;
   if (!theta_w || !exner_hat_w || !exner_c || !rho_c) return fail(c, HYB_EINVAL, "null field");
   int rc;
+  if (c->order == 1) {
+    hyb::P1State &s = c->p1;
+    const size_t nc = (size_t)c->ncell;
+    if ((rc = dalloc(c, &s.A, 44 * 44 * nc)) || (rc = dalloc(c, &s.cdiag, 24 * nc)) ||
+        (rc = dalloc(c, &s.kdiag, 24 * nc)) || (rc = dalloc(c, &s.SK, 24 * 24 * nc)) || (rc = dalloc(c, &s.bK, 24 * nc)))
+      return rc;
+    CHECK_HIP(p1_setup(c), "p1 tables");
+    CHECK_HIP(p1_assemble(c, theta_w, exner_hat_w, exner_c, rho_c), "p1 assemble_local");
+    c->assembled = true;
+    c->condensed = false;
+    return HYB_OK;
+  }
   if ((rc = dalloc(c, &c->A, (size_t)49 * c->ncell)) || (rc = dalloc(c, &c->kv, (size_t)6 * c->ncell))) return rc;
   CHECK_HIP(launch_assemble_box(c, theta_w, exner_hat_w, exner_c, rho_c), "assemble_local");
   c->assembled = true;
@@ -321,6 +341,20 @@ int hyb_condense(hyb_ctx *c, const double *r_ub, const double *r_pi, double *b_l
   if (!c) return HYB_EINVAL;
   if (!c->assembled) return fail(c, HYB_ESTATE, "condense before assemble_local");
   int rc;
+  if (c->order == 1) {
+    if (r_ub == nullptr) {
+      if (c->condensed) return HYB_OK;  // the LU factors replaced A_K
+      CHECK_HIP(p1_factor(c), "p1 factor");
+      CHECK_HIP(hipStreamSynchronize(c->stream), "condense sync");
+      c->condensed = true;
+      return HYB_OK;
+    }
+    if (!c->condensed) return fail(c, HYB_ESTATE, "condense the operator (r_ub = NULL) first");
+    if (!r_pi || !b_lambda) return fail(c, HYB_EINVAL, "null argument");
+    CHECK_HIP(p1_cell_solve(c, r_ub, r_pi, nullptr, 0, nullptr, nullptr), "p1 condense rhs");
+    CHECK_HIP(p1_rows(c, nullptr, b_lambda, 1), "p1 gather rhs");
+    return HYB_OK;
+  }
   if (r_ub == nullptr) {
     size_t ntr = (size_t)c->ntrace, nc = (size_t)c->ncell;
     if ((rc = dalloc(c, &c->LU, 49 * nc)) || (rc = dalloc(c, &c->Scell, 36 * nc)) || (rc = dalloc(c, &c->S, 11 * ntr)) ||
@@ -363,12 +397,17 @@ int hyb_trace_apply(hyb_ctx *c, const double *x, double *y) {
   if (!c) return HYB_EINVAL;
   if (!c->condensed) return fail(c, HYB_ESTATE, "trace_apply before condense");
   if (!x || !y || x == y) return fail(c, HYB_EINVAL, "bad vectors");
+  if (c->order == 1) {
+    CHECK_HIP(p1_rows(c, x, y, 0), "p1 trace_apply");
+    return HYB_OK;
+  }
   CHECK_HIP((launch_trace_apply<double, double, double>(c, c->S, x, nullptr, y, 0)), "trace_apply");
   return HYB_OK;
 }
 
 int hyb_precondition(hyb_ctx *c, const double *r, double *z) {
   if (!c) return HYB_EINVAL;
+  if (c->order == 1) return fail(c, HYB_ESTATE, "hyb_precondition is not available at order 1");
   if (!c->condensed) return fail(c, HYB_ESTATE, "precondition before condense");
   if (!r || !z || r == z) return fail(c, HYB_EINVAL, "bad vectors");
   if (c->p.learned && !c->nn.loaded) return fail(c, HYB_ESTATE, "learned stage requested without weights");
@@ -394,6 +433,7 @@ int hyb_precondition(hyb_ctx *c, const double *r, double *z) {
 
 int hyb_solve(hyb_ctx *c, const double *b, double *lam, double rtol, int32_t maxit, hyb_info *info) {
   if (!c) return HYB_EINVAL;
+  if (c->order == 1) return fail(c, HYB_ESTATE, "hyb_solve is not available at order 1");
   if (!c->condensed) return fail(c, HYB_ESTATE, "solve before condense");
   if (!b || !lam || b == lam || !(rtol >= 0) || maxit < 0) return fail(c, HYB_EINVAL, "bad solve arguments");
   int rc = alloc_krylov(c);
@@ -582,6 +622,10 @@ int hyb_recover(hyb_ctx *c, const double *r_ub, const double *r_pi, const double
   if (!c) return HYB_EINVAL;
   if (!c->condensed) return fail(c, HYB_ESTATE, "recover before condense");
   if (!r_ub || !r_pi || !lambda || !u_b || !pi) return fail(c, HYB_EINVAL, "null argument");
+  if (c->order == 1) {
+    CHECK_HIP(p1_cell_solve(c, r_ub, r_pi, lambda, 1, u_b, pi), "p1 recover");
+    return HYB_OK;
+  }
   CHECK_HIP(launch_recover(c, r_ub, r_pi, lambda, u_b, pi), "recover");
   return HYB_OK;
 }
@@ -622,6 +666,7 @@ int hyb_profile_read(hyb_ctx *c, const char *family, int64_t *launches, double *
 
 int hyb_restrict(hyb_ctx *c, const double *r, double *cells, int32_t mode) {
   if (!c) return HYB_EINVAL;
+  if (c->order == 1) return fail(c, HYB_ESTATE, "hyb_restrict is not available at order 1");
   if (!c->condensed) return fail(c, HYB_ESTATE, "restrict before condense");
   if (!r || !cells || mode < 0 || mode > 3) return fail(c, HYB_EINVAL, "bad restrict arguments");
   CHECK_HIP(launch_restrict_cells(c, r, cells, mode), "restrict");
@@ -632,6 +677,7 @@ int hyb_nn_param_count(void) { return nn_param_count(); }
 
 int hyb_nn_set_weights(hyb_ctx *c, const float *w, int64_t n) {
   if (!c) return HYB_EINVAL;
+  if (c->order == 1) return fail(c, HYB_ESTATE, "hyb_nn_set_weights is not available at order 1");
   if (!w || n != nn_param_count()) return fail(c, HYB_EINVAL, "weights: wrong size");
   for (int64_t i = 0; i < n; ++i)
     if (!std::isfinite(w[i])) return fail(c, HYB_EINVAL, "weights: not finite");

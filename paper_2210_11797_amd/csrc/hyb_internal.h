@@ -57,6 +57,16 @@ struct NNState {
   bool loaded = false;
 };
 
+// p = 1 system (p1.hip): cell data per cell (array of structures)
+struct P1State {
+  double *tbl = nullptr;    // reference tables of the assembly
+  double *A = nullptr;      // [ncell][44][44] A_K, then its LU factors (unit lower, no pivoting)
+  double *cdiag = nullptr;  // [ncell][24] diagonal of C_K on the face dofs
+  double *kdiag = nullptr;  // [ncell][24] diagonal of K_K
+  double *SK = nullptr;     // [ncell][24][24] S_K = C_K [A_K^-1]_ff K_K
+  double *bK = nullptr;     // [ncell][24] the cell's share of B_lambda
+};
+
 struct ProfFamily {
   std::string name;
   std::vector<hipEvent_t> ev;  // start/stop pairs
@@ -110,6 +120,9 @@ struct hyb_ctx {
 
   hyb::NNState nn;
   double *cell64 = nullptr;  // [ncell] scratch of the learned stage
+
+  int order = 0;             // 0: RT0 / Q0 / one trace dof per facet; 1: RT1 / DG1 / 4 per facet
+  hyb::P1State p1;
 };
 
 namespace hyb {
@@ -181,6 +194,18 @@ template <typename Tz>
 hipError_t launch_update_solution(hyb_ctx *c, const Tz *Z, size_t ldz, int nv, const double *y_dev,
                                   double *x, size_t n);
 hipError_t launch_scale(hyb_ctx *c, double *w, size_t n, double s);
+
+// ----- p = 1 (p1.hip) -----
+hipError_t p1_setup(hyb_ctx *c);
+hipError_t p1_assemble(hyb_ctx *c, const double *theta_w, const double *exner_hat_w, const double *exner_c,
+                       const double *rho_c);
+hipError_t p1_factor(hyb_ctx *c);
+// mode 0: the cells' shares of B_lambda into p1.bK; mode 1: recovery into u [36][ncell], pi [8][ncell]
+hipError_t p1_cell_solve(hyb_ctx *c, const double *r_u, const double *r_p, const double *lam, int mode, double *u,
+                         double *pi);
+// mode 0: y = S x; mode 1: y = gather of p1.bK (B_lambda)
+hipError_t p1_rows(hyb_ctx *c, const double *x, double *y, int mode);
+void p1_free(hyb_ctx *c);
 
 // ----- learned coarse correction (nn.hip) -----
 int nn_param_count();

@@ -1,0 +1,411 @@
+// Next-to-lowest-order (p = 1) hybridised system on the box: RT1 broken velocity (36 per cell),
+// DG1 pressure nodal at the 2x2x2 Gauss points (8), Q1 trace nodal at the 2x2 face Gauss points
+// (4 per facet, trace dof 4 F + i).  The paper states the method for general p (Sec. 2.2 forms,
+// n = p + 3 point Gauss rules, q32 / m3^rho / m3^Pi at the W3 nodes; Sec. 2.4 hybridisation) and
+// the p = 1 sizes in its table of unknowns (44 x 44 cell matrices, 24 x 24 condensed blocks).
+//
+// Every form is linear in the cell's coefficients (cell sizes, theta* and Pi-hat* at the bottom
+// and top facets, the cell values of Pi* and rho*), so the assembly multiplies reference tables --
+// integrals of products of the reference basis functions, computed once on the host with exact
+// Gauss rules -- by per-cell scalars.  Cell data are stored per cell (array of structures): one
+// wavefront owns one cell in the assembly, the factorisation and the cell solves, and reads or
+// writes its 44 x 44 block contiguously.
+//
+// Dof order per cell: velocity face dofs 4 f + i (f = W, E, S, N, B, T; face point i = 2 t1 + t2
+// in the face's tangential coordinates (y, z), (x, z) or (x, y)), velocity interior dofs
+// 24 + 4 d + (2 t1 + t2), then the 8 pressure dofs 36 + 4 i + 2 j + k.
+#include <cmath>
+#include <vector>
+
+#include "hyb_internal.h"
+
+namespace hyb {
+
+namespace {
+
+constexpr int NU = 36, NPR = 8, NF = 24, NX = 44, NA = NX * NX, NS = NF * NF;
+
+inline unsigned nblk(size_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
+
+// ---- reference tables (host) ------------------------------------------------------------------
+// tbl layout (doubles): Tm2[36][36], Tzz[36][36], TgB[36][8], TgT[36][8], Tgz[36][8], Td[8][36],
+// Uz[36][8], dir[36] (direction of each velocity function, as double)
+constexpr int OFF_M2 = 0, OFF_ZZ = OFF_M2 + NU * NU, OFF_GB = OFF_ZZ + NU * NU, OFF_GT = OFF_GB + NU * NPR,
+              OFF_GZ = OFF_GT + NU * NPR, OFF_TD = OFF_GZ + NU * NPR, OFF_UZ = OFF_TD + NPR * NU,
+              OFF_DIR = OFF_UZ + NU * NPR, TBL_LEN = OFF_DIR + NU;
+
+struct Basis1D {
+  // Lagrange polynomials on nodes; value and derivative
+  std::vector<double> nodes;
+  double val(int j, double x) const {
+    double v = 1.0;
+    for (size_t m = 0; m < nodes.size(); ++m)
+      if ((int)m != j) v *= (x - nodes[m]) / (nodes[j] - nodes[m]);
+    return v;
+  }
+  double der(int j, double x) const {
+    double d = 0.0;
+    for (size_t m = 0; m < nodes.size(); ++m) {
+      if ((int)m == j) continue;
+      double t = 1.0 / (nodes[j] - nodes[m]);
+      for (size_t q = 0; q < nodes.size(); ++q)
+        if ((int)q != j && q != m) t *= (x - nodes[q]) / (nodes[j] - nodes[q]);
+      d += t;
+    }
+    return d;
+  }
+};
+
+struct RT1Fn {
+  int d, a, t1, t2;
+  double sgn;
+};
+
+std::vector<RT1Fn> rt1_functions() {
+  const int fdir[6] = {0, 0, 1, 1, 2, 2};
+  const double fsgn[6] = {-1, 1, -1, 1, -1, 1};
+  std::vector<RT1Fn> out;
+  for (int f = 0; f < 6; ++f)
+    for (int i = 0; i < 4; ++i) out.push_back({fdir[f], fsgn[f] < 0 ? 0 : 2, i / 2, i % 2, fsgn[f]});
+  for (int d = 0; d < 3; ++d)
+    for (int i = 0; i < 4; ++i) out.push_back({d, 1, i / 2, i % 2, 1.0});
+  return out;
+}
+
+std::vector<double> build_tables() {
+  const double g0 = 0.5 - 0.5 / std::sqrt(3.0), g1 = 0.5 + 0.5 / std::sqrt(3.0);
+  Basis1D Lq{{0.0, 0.5, 1.0}}, Lg{{g0, g1}};
+  // 4-point Gauss-Legendre on [0, 1] (exact for the products below)
+  const double a = std::sqrt(3.0 / 7.0 - 2.0 / 7.0 * std::sqrt(6.0 / 5.0)),
+               b = std::sqrt(3.0 / 7.0 + 2.0 / 7.0 * std::sqrt(6.0 / 5.0));
+  const double xs[4] = {-b, -a, a, b};
+  const double wa = (18.0 + std::sqrt(30.0)) / 36.0, wb = (18.0 - std::sqrt(30.0)) / 36.0;
+  const double ws[4] = {wb, wa, wa, wb};
+  double X[4], W[4];
+  for (int i = 0; i < 4; ++i) X[i] = 0.5 * (xs[i] + 1.0), W[i] = 0.5 * ws[i];
+  auto fns = rt1_functions();
+  const int tang[3][2] = {{1, 2}, {0, 2}, {0, 1}};
+  auto uval = [&](const RT1Fn &f, const double p[3]) {
+    return f.sgn * Lq.val(f.a, p[f.d]) * Lg.val(f.t1, p[tang[f.d][0]]) * Lg.val(f.t2, p[tang[f.d][1]]);
+  };
+  auto udiv = [&](const RT1Fn &f, const double p[3]) {  // d/d(own reference coordinate)
+    return f.sgn * Lq.der(f.a, p[f.d]) * Lg.val(f.t1, p[tang[f.d][0]]) * Lg.val(f.t2, p[tang[f.d][1]]);
+  };
+  auto phi = [&](int q, const double p[3]) {
+    return Lg.val(q / 4, p[0]) * Lg.val((q / 2) % 2, p[1]) * Lg.val(q % 2, p[2]);
+  };
+  std::vector<double> T(TBL_LEN, 0.0);
+  for (int ix = 0; ix < 4; ++ix)
+    for (int iy = 0; iy < 4; ++iy)
+      for (int iz = 0; iz < 4; ++iz) {
+        const double p[3] = {X[ix], X[iy], X[iz]}, w = W[ix] * W[iy] * W[iz];
+        double u[NU], dv[NU], ph[NPR];
+        for (int j = 0; j < NU; ++j) u[j] = uval(fns[j], p), dv[j] = udiv(fns[j], p);
+        for (int q = 0; q < NPR; ++q) ph[q] = phi(q, p);
+        for (int i = 0; i < NU; ++i) {
+          for (int j = 0; j < NU; ++j) {
+            if (fns[i].d == fns[j].d) T[OFF_M2 + i * NU + j] += w * u[i] * u[j];
+            if (fns[i].d == 2 && fns[j].d == 2) T[OFF_ZZ + i * NU + j] += w * u[i] * u[j];
+          }
+          for (int q = 0; q < NPR; ++q) {
+            T[OFF_GB + i * NPR + q] += w * (1.0 - p[2]) * dv[i] * ph[q];
+            T[OFF_GT + i * NPR + q] += w * p[2] * dv[i] * ph[q];
+            if (fns[i].d == 2) T[OFF_GZ + i * NPR + q] += w * u[i] * ph[q];
+            T[OFF_TD + q * NU + i] += w * ph[q] * dv[i];
+          }
+        }
+      }
+  const double G[2] = {g0, g1};
+  for (int i = 0; i < NU; ++i) {
+    for (int q = 0; q < NPR; ++q) {
+      const double p[3] = {G[q / 4], G[(q / 2) % 2], G[q % 2]};
+      T[OFF_UZ + i * NPR + q] = fns[i].d == 2 ? uval(fns[i], p) : 0.0;
+    }
+    T[OFF_DIR + i] = fns[i].d;
+  }
+  return T;
+}
+
+// ---- kernels ----------------------------------------------------------------------------------
+
+struct CellCoef {
+  double hx, hy, hz, thB, thT, dpi, pic, rhoc;
+};
+
+__device__ __forceinline__ CellCoef cell_coef(int c, int ncol, const double *dz, double dx, double dy,
+                                              const double *theta_w, const double *exner_hat_w,
+                                              const double *exner_c, const double *rho_c) {
+  const int k = c / ncol, col = c - k * ncol;
+  CellCoef q;
+  q.hx = dx, q.hy = dy, q.hz = dz[k];
+  q.thB = theta_w[(size_t)k * ncol + col], q.thT = theta_w[(size_t)(k + 1) * ncol + col];
+  q.dpi = (exner_hat_w[(size_t)(k + 1) * ncol + col] - exner_hat_w[(size_t)k * ncol + col]) / q.hz;
+  q.pic = exner_c[c], q.rhoc = rho_c[c];
+  return q;
+}
+
+// One wavefront per cell writes A_K (44 x 44, row-major) and the diagonals of C_K and K_K.
+__global__ void __launch_bounds__(kBlock) k_p1_assemble(int ncell, int ncol, const double *__restrict__ dz, double dx,
+                                                        double dy, const double *__restrict__ theta_w,
+                                                        const double *__restrict__ exner_hat_w,
+                                                        const double *__restrict__ exner_c,
+                                                        const double *__restrict__ rho_c,
+                                                        const double *__restrict__ T, double dt, double tu,
+                                                        double tr, double tt, double cp, double kappa,
+                                                        double *__restrict__ A, double *__restrict__ cdiag,
+                                                        double *__restrict__ kdiag) {
+  const int lane = threadIdx.x & 63;
+  const int c = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (c >= ncell) return;
+  const CellCoef q = cell_coef(c, ncol, dz, dx, dy, theta_w, exner_hat_w, exner_c, rho_c);
+  const double vol = q.hx * q.hy * q.hz, dth = (q.thT - q.thB) / q.hz;
+  const double h[3] = {q.hx, q.hy, q.hz};
+  const double c22 = tu * tt * dt * dt * cp * q.dpi * dth * vol, cg = -tu * dt * cp * vol, cd = tr * dt * vol;
+  const double G0 = 0.5 - 0.5 / sqrt(3.0), G1 = 0.5 + 0.5 / sqrt(3.0);
+  double *Ac = A + (size_t)c * NA;
+  for (int e = lane; e < NA; e += 64) {
+    const int i = e / NX, j = e - i * NX;
+    double v;
+    if (i < NU && j < NU) {
+      v = vol * T[OFF_M2 + i * NU + j] - c22 * T[OFF_ZZ + i * NU + j];
+    } else if (i < NU) {  // g^b: velocity row i, pressure column
+      const int p = j - NU;
+      const double hi = h[(int)T[OFF_DIR + i]];
+      v = cg * ((q.thB * T[OFF_GB + i * NPR + p] + q.thT * T[OFF_GT + i * NPR + p]) / hi + dth * T[OFF_GZ + i * NPR + p]);
+    } else if (j < NU) {  // q32 + M3rho M3^-1 D: pressure row, velocity column
+      const int p = i - NU;
+      const double hj = h[(int)T[OFF_DIR + j]];
+      const double zp = (p % 2) ? G1 : G0;
+      const double thp = q.thB * (1.0 - zp) + q.thT * zp;
+      v = tt * dt * 0.125 * vol * T[OFF_UZ + j * NPR + p] * dth / thp + cd * T[OFF_TD + p * NU + j] / hj;
+    } else {
+      v = (i == j) ? (1.0 - kappa) / kappa * 0.125 * vol / q.pic : 0.0;
+    }
+    Ac[e] = v;
+  }
+  if (lane < NF) {
+    const int f = lane / 4, i = lane % 4;
+    const double area = (f < 2) ? q.hy * q.hz : (f < 4) ? q.hx * q.hz : q.hx * q.hy;
+    double th;
+    if (f < 4)
+      th = (i % 2) ? q.thB * (1.0 - G1) + q.thT * G1 : q.thB * (1.0 - G0) + q.thT * G0;
+    else
+      th = (f == 4) ? q.thB : q.thT;
+    cdiag[(size_t)c * NF + lane] = 0.25 * area;
+    kdiag[(size_t)c * NF + lane] = tu * dt * cp * 0.25 * area * th;
+  }
+}
+
+// One wavefront per cell: LU factorisation of A_K without pivoting (velocity block first; the
+// velocity block is a perturbed mass matrix and the pressure Schur complement is positive), in
+// place, then S_K[r][s] = c_r [A_K^-1]_{rs} k_s for the 24 face dofs.  A_K staged in LDS.
+constexpr int kP1Waves = 2;  // cells per workgroup (LDS: 2 x (44 x 44 + 44 x 24) doubles)
+__global__ void __launch_bounds__(64 * kP1Waves) k_p1_factor(int ncell, double *__restrict__ A,
+                                                            const double *__restrict__ cdiag,
+                                                            const double *__restrict__ kdiag, double *__restrict__ SK) {
+  __shared__ double sA[kP1Waves][NX * NX];
+  __shared__ double sX[kP1Waves][NX * NF];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int c = blockIdx.x * kP1Waves + wv;
+  const bool active = c < ncell;
+  double *a = sA[wv], *x = sX[wv];
+  if (active) {
+    const double *Ac = A + (size_t)c * NA;
+    for (int e = lane; e < NA; e += 64) a[e] = Ac[e];
+    for (int e = lane; e < NX * NF; e += 64) {
+      const int i = e / NF, j = e - i * NF;
+      x[e] = (i == j) ? kdiag[(size_t)c * NF + j] : 0.0;  // [K_K; 0]: K_K is diagonal on the face dofs
+    }
+  }
+  __syncthreads();
+  // right-looking elimination; lanes own rows
+  for (int k = 0; k < NX; ++k) {
+    if (active && lane > k && lane < NX) {
+      const double l = a[lane * NX + k] / a[k * NX + k];
+      a[lane * NX + k] = l;
+      for (int j = k + 1; j < NX; ++j) a[lane * NX + j] -= l * a[k * NX + j];
+      for (int j = 0; j < NF; ++j) x[lane * NF + j] -= l * x[k * NF + j];
+    }
+    __syncthreads();
+  }
+  // back substitution, lanes own right-hand-side columns
+  if (active && lane < NF) {
+    for (int i = NX - 1; i >= 0; --i) {
+      double s = x[i * NF + lane];
+      for (int m = i + 1; m < NX; ++m) s -= a[i * NX + m] * x[m * NF + lane];
+      x[i * NF + lane] = s / a[i * NX + i];
+    }
+  }
+  __syncthreads();
+  if (active) {
+    double *Ac = A + (size_t)c * NA;
+    for (int e = lane; e < NA; e += 64) Ac[e] = a[e];
+    for (int e = lane; e < NS; e += 64) {
+      const int r = e / NF, s = e - r * NF;
+      SK[(size_t)c * NS + e] = cdiag[(size_t)c * NF + r] * x[r * NF + s];
+    }
+  }
+}
+
+// Global trace dof of local face dof j of cell (k, col).
+__device__ __forceinline__ size_t p1_dof(int j, int k, int col, int ncol, int nedge, size_t nz,
+                                         const int32_t *__restrict__ col_edge) {
+  const int f = j >> 2;
+  size_t F;
+  if (f < 4)
+    F = nz + (size_t)k * nedge + col_edge[(size_t)f * ncol + col];
+  else
+    F = (size_t)(k + (f - 4)) * ncol + col;
+  return 4 * F + (j & 3);
+}
+
+// One wavefront per cell: X = LU^-1 (R - [K lambda; 0]) with the stored factors.  mode 0: b_K =
+// C_K [X]_face (the cell's share of B_lambda, lambda unused); mode 1: recovery, u_b = X_u, pi = X_p.
+__global__ void __launch_bounds__(64 * kP1Waves) k_p1_cell_solve(int ncell, int ncol, int nedge, size_t nz,
+                                                                const int32_t *__restrict__ col_edge,
+                                                                const double *__restrict__ LU,
+                                                                const double *__restrict__ cdiag,
+                                                                const double *__restrict__ kdiag,
+                                                                const double *__restrict__ r_u,
+                                                                const double *__restrict__ r_p,
+                                                                const double *__restrict__ lam, int mode,
+                                                                double *__restrict__ bK, double *__restrict__ u,
+                                                                double *__restrict__ pi) {
+  __shared__ double sx[kP1Waves][NX];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int c = blockIdx.x * kP1Waves + wv;
+  const bool active = c < ncell;
+  double *x = sx[wv];
+  const double *L = LU + (size_t)c * NA;
+  const int k = active ? c / ncol : 0, col = active ? c - k * ncol : 0;
+  if (active && lane < NX) {
+    // right-hand sides are [dof][nlev][ncol]
+    double v = lane < NU ? r_u[(size_t)lane * ncell + c] : r_p[(size_t)(lane - NU) * ncell + c];
+    if (mode == 1 && lane < NF) v -= kdiag[(size_t)c * NF + lane] * lam[p1_dof(lane, k, col, ncol, nedge, nz, col_edge)];
+    x[lane] = v;
+  }
+  __syncthreads();
+  for (int m = 0; m < NX; ++m) {  // forward substitution (unit lower)
+    if (active && lane > m && lane < NX) x[lane] -= L[lane * NX + m] * x[m];
+    __syncthreads();
+  }
+  for (int m = NX - 1; m >= 0; --m) {  // back substitution
+    if (active && lane == 0) x[m] /= L[m * NX + m];
+    __syncthreads();
+    if (active && lane < m) x[lane] -= L[lane * NX + m] * x[m];
+    __syncthreads();
+  }
+  if (!active || lane >= NX) return;
+  if (mode == 0) {
+    if (lane < NF) bK[(size_t)c * NF + lane] = cdiag[(size_t)c * NF + lane] * x[lane];
+  } else {
+    if (lane < NU)
+      u[(size_t)lane * ncell + c] = x[lane];
+    else
+      pi[(size_t)(lane - NU) * ncell + c] = x[lane];
+  }
+}
+
+// For trace row T = 4 F + i: the (up to two) cells of facet F and the facet's local face in each.
+__device__ __forceinline__ int p1_row_cells(size_t T, int nlev, int ncol, int nedge, size_t nz,
+                                            const int32_t *__restrict__ edge_col, const int32_t *__restrict__ edge_lf,
+                                            int cells[2], int faces[2]) {
+  const size_t F = T >> 2;
+  int n = 0;
+  if (F < nz) {
+    const int k = (int)(F / ncol), col = (int)(F - (size_t)k * ncol);
+    if (k > 0) cells[n] = (k - 1) * ncol + col, faces[n++] = 5;
+    if (k < nlev) cells[n] = k * ncol + col, faces[n++] = 4;
+  } else {
+    const size_t h = F - nz;
+    const int k = (int)(h / nedge), e = (int)(h - (size_t)k * nedge);
+    cells[0] = k * ncol + edge_col[e], faces[0] = edge_lf[e];
+    cells[1] = k * ncol + edge_col[nedge + e], faces[1] = edge_lf[nedge + e];
+    n = 2;
+  }
+  return n;
+}
+
+// y = S x (mode 0), or the gather of the cells' right-hand-side shares b_K into B (mode 1)
+__global__ void k_p1_rows(size_t ntr, int nlev, int ncol, int nedge, size_t nz, const int32_t *__restrict__ col_edge,
+                          const int32_t *__restrict__ edge_col, const int32_t *__restrict__ edge_lf,
+                          const double *__restrict__ SK, const double *__restrict__ x, const double *__restrict__ bK,
+                          double *__restrict__ y, int mode) {
+  const size_t T = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (T >= ntr) return;
+  int cells[2], faces[2];
+  const int n = p1_row_cells(T, nlev, ncol, nedge, nz, edge_col, edge_lf, cells, faces);
+  const int i = (int)(T & 3);
+  double s = 0.0;
+  for (int q = 0; q < n; ++q) {
+    const int c = cells[q], r = 4 * faces[q] + i;
+    if (mode == 1) {
+      s += bK[(size_t)c * NF + r];
+      continue;
+    }
+    const int k = c / ncol, col = c - k * ncol;
+    const double *row = SK + (size_t)c * NS + (size_t)r * NF;
+#pragma unroll 4
+    for (int j = 0; j < NF; ++j) s += row[j] * x[p1_dof(j, k, col, ncol, nedge, nz, col_edge)];
+  }
+  y[T] = s;
+}
+
+}  // namespace
+
+// ---- host ---------------------------------------------------------------------------------------
+
+hipError_t p1_setup(hyb_ctx *c) {
+  P1State &s = c->p1;
+  if (s.tbl) return hipSuccess;
+  std::vector<double> T = build_tables();
+  hipError_t e = hipMalloc((void **)&s.tbl, T.size() * 8);
+  if (e) return e;
+  c->bytes += T.size() * 8;
+  return hipMemcpy(s.tbl, T.data(), T.size() * 8, hipMemcpyHostToDevice);
+}
+
+hipError_t p1_assemble(hyb_ctx *c, const double *theta_w, const double *exner_hat_w, const double *exner_c,
+                       const double *rho_c) {
+  P1State &s = c->p1;
+  const hyb_params &p = c->p;
+  const double kappa = p.rd / p.cp;
+  hipLaunchKernelGGL(k_p1_assemble, dim3(nblk(c->ncell, kBlock / 64)), dim3(kBlock), 0, c->stream, c->ncell, c->ncol,
+                     c->dz_d, c->dx, c->dy, theta_w, exner_hat_w, exner_c, rho_c, s.tbl, p.dt, p.tau_u, p.tau_rho,
+                     p.tau_theta, p.cp, kappa, s.A, s.cdiag, s.kdiag);
+  return hipGetLastError();
+}
+
+hipError_t p1_factor(hyb_ctx *c) {
+  P1State &s = c->p1;
+  hipLaunchKernelGGL(k_p1_factor, dim3(nblk(c->ncell, kP1Waves)), dim3(64 * kP1Waves), 0, c->stream, c->ncell, s.A,
+                     s.cdiag, s.kdiag, s.SK);
+  return hipGetLastError();
+}
+
+hipError_t p1_cell_solve(hyb_ctx *c, const double *r_u, const double *r_p, const double *lam, int mode, double *u,
+                         double *pi) {
+  P1State &s = c->p1;
+  const LevelDev &L0 = c->lv[0];
+  hipLaunchKernelGGL(k_p1_cell_solve, dim3(nblk(c->ncell, kP1Waves)), dim3(64 * kP1Waves), 0, c->stream, c->ncell,
+                     c->ncol, c->nedge, (size_t)c->nz, L0.col_edge, s.A, s.cdiag, s.kdiag, r_u, r_p, lam, mode, s.bK,
+                     u, pi);
+  return hipGetLastError();
+}
+
+hipError_t p1_rows(hyb_ctx *c, const double *x, double *y, int mode) {
+  P1State &s = c->p1;
+  const LevelDev &L0 = c->lv[0];
+  const size_t ntr = (size_t)c->ntrace;
+  hipLaunchKernelGGL(k_p1_rows, dim3(nblk(ntr)), dim3(kBlock), 0, c->stream, ntr, c->nlev, c->ncol, c->nedge,
+                     (size_t)c->nz, L0.col_edge, L0.edge_col, L0.edge_lf, s.SK, x, s.bK, y, mode);
+  return hipGetLastError();
+}
+
+void p1_free(hyb_ctx *c) {
+  P1State &s = c->p1;
+  for (double **q : {&s.tbl, &s.A, &s.cdiag, &s.kdiag, &s.SK, &s.bK})
+    if (*q) (void)hipFree(*q), *q = nullptr;
+}
+
+}  // namespace hyb

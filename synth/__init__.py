@@ -7,4 +7,4 @@ random right-hand sides.  Both the CPU oracle and the HIP library consume
 what it produces; neither imports the other.
 """
 
-from .box import BoxProblem, make_box, make_rhs, config_box  # noqa: F401
+from .box import BoxProblem, make_box, make_rhs, make_rhs_p1, config_box  # noqa: F401

@@ -270,6 +270,15 @@ def make_rhs(prob: BoxProblem, seed: int):
     return np.ascontiguousarray(ru.transpose(2, 0, 1)), np.ascontiguousarray(rp)
 
 
+def make_rhs_p1(prob: BoxProblem, seed: int):
+    """Dual right-hand side of the order-1 system: broken RT1 velocity part [36][L][ncol] and DG1
+    pressure part [8][L][ncol].  Draw order: (L, ncol, 36) then (L, ncol, 8), standard normal."""
+    rng = np.random.default_rng(seed)
+    ru = rng.standard_normal((prob.nlev, prob.ncol, 36))
+    rp = rng.standard_normal((prob.nlev, prob.ncol, 8))
+    return np.ascontiguousarray(ru.transpose(2, 0, 1)), np.ascontiguousarray(rp.transpose(2, 0, 1))
+
+
 def config_box(name: str, **kw) -> BoxProblem:
     """Named workloads.
 

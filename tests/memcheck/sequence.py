@@ -32,8 +32,8 @@ def P(a):
 
 
 class Ctx:
-    def __init__(self, lib, prob, **kw):
-        self.lib, self.prob = lib, prob
+    def __init__(self, lib, prob, order=0, **kw):
+        self.lib, self.prob, self.order = lib, prob, order
         keep = []
         levels = N.levels_of(prob)
         lv = (N._Level * len(levels))()
@@ -50,7 +50,7 @@ class Ctx:
                 par = a.ctypes.data_as(N._i32p)
             lv[i] = N._Level(int(L["ncol"]), arr["col_edge"], arr["edge_col"], arr["edge_lf"], par)
         dz = np.ascontiguousarray(prob.dz, np.float64)
-        mesh = N._Mesh(prob.nlev, len(levels), lv, prob.dx, prob.dy, dz.ctypes.data_as(N._f64p))
+        mesh = N._Mesh(prob.nlev, len(levels), lv, prob.dx, prob.dy, dz.ctypes.data_as(N._f64p), order)
         base = dict(dt=prob.dt, tau_u=prob.tau_u, tau_rho=prob.tau_rho, tau_theta=prob.tau_theta, cp=prob.cp,
                     rd=prob.rd)
         base.update(kw)
@@ -204,13 +204,47 @@ def network_sequence(lib):
     c.close()
 
 
+def p1_sequence(lib):
+    """Order 1: assembly, condensation, S x, B_lambda and recovery against the oracle's p = 1 system
+    (a sanity check of the same code the GPU runs)."""
+    from oracle import p1 as op1
+    from oracle.mesh import BoxMesh
+
+    prob = make_box(nx=3, ny=2, nlev=3, dx=5e3, dz=250.0, mg_levels=1, perturb=0.05, seed=6)
+    c = Ctx(lib, prob, order=1)
+    mesh = BoxMesh(prob.nx, prob.ny, prob.nlev, prob.dx, prob.dy, prob.z)
+    h = op1.HybridP1(mesh, op1.local_matrices(mesh, prob))
+    check(c.ntrace == h.ntrace, f"order 1: {c.ntrace} trace unknowns")
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal(c.ntrace)
+    y = np.empty(c.ntrace)
+    c.call("hyb_trace_apply", P(x), P(y))
+    ref = h.S @ x
+    check(np.abs(y - ref).max() <= 1e-11 * np.abs(ref).max(), "order 1: S x matches the oracle")
+    r_u = rng.standard_normal((36, c.ncell))
+    r_p = rng.standard_normal((8, c.ncell))
+    b = np.empty(c.ntrace)
+    c.call("hyb_condense", P(r_u), P(r_p), P(b))
+    bref = h.rhs(r_u.T.copy(), r_p.T.copy())
+    check(np.abs(b - bref).max() <= 1e-11 * np.abs(bref).max(), "order 1: B_lambda matches the oracle")
+    u, pi = np.empty((36, c.ncell)), np.empty((8, c.ncell))
+    c.call("hyb_recover", P(r_u), P(r_p), P(x), P(u), P(pi))
+    uref, pref = h.recover(x, r_u.T.copy(), r_p.T.copy())
+    check(np.abs(u.T - uref).max() <= 1e-10 * np.abs(uref).max() and np.abs(pi.T - pref).max() <= 1e-10 * np.abs(pref).max(),
+          "order 1: recovery matches the oracle")
+    check(lib.hyb_precondition(c.h, P(b), P(y)) < 0, "order 1: calls it does not provide are rejected")
+    c.close()
+
+
 def main():
     lib = N.declare(ctypes.CDLL(sys.argv[1]))
-    which = sys.argv[2:] or ["solver", "network"]
+    which = sys.argv[2:] or ["solver", "network", "p1"]
     if "solver" in which:
         solver_sequence(lib)
     if "network" in which:
         network_sequence(lib)
+    if "p1" in which:
+        p1_sequence(lib)
     print("sequence complete", flush=True)
 
 

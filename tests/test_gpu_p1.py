@@ -1,0 +1,112 @@
+"""Order 1 (RT1 / DG1 / Q1 trace) on the GPU against the p = 1 oracle: the trace operator, the
+condensed right-hand side and the recovery on small boxes (element by element), and sampled rows
+and cells on the 128x128x32 box (dx = 10 km, dz = 500 m) in the launch configuration of the
+benchmark."""
+
+import numpy as np
+import pytest
+
+from gpu_common import dev, host, params_for, rel_max, say
+from oracle import p1 as op1
+from oracle.mesh import BoxMesh
+from paper_2210_11797_amd import HybSolver, levels_of
+from synth import make_box, make_rhs_p1
+
+CASES = {
+    "3x2x3": dict(nx=3, ny=2, nlev=3, dx=5e3, dz=250.0, perturb=0.05),
+    "8x6x5": dict(nx=8, ny=6, nlev=5, dx=5e3, dz=250.0, perturb=0.1, theta_col_perturb=0.02),
+    "stretched": dict(nx=4, ny=4, nlev=9, dx=10e3, dz=None, stretch="quadratic", ztop=16e3),
+}
+
+
+def make_p1_solver(prob):
+    s = HybSolver(prob.nlev, levels_of(prob), prob.dx, prob.dy, prob.dz, params_for(prob), order=1)
+    s.assemble_local(dev(prob.theta_w), dev(prob.exner_hat_w), dev(prob.exner_c), dev(prob.rho_c))
+    s.condense()
+    return s
+
+
+def _box(kw):
+    kw = dict(kw)
+    if kw.get("dz") is None:
+        kw.pop("dz")
+    return make_box(mg_levels=1, **kw)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("case", list(CASES))
+def test_p1_operators_match_oracle(case):
+    prob = _box(CASES[case])
+    say(f"[p1] case {case}: {prob.nx}x{prob.ny}x{prob.nlev}")
+    s = make_p1_solver(prob)
+    mesh = BoxMesh(prob.nx, prob.ny, prob.nlev, prob.dx, prob.dy, prob.z)
+    h = op1.HybridP1(mesh, op1.local_matrices(mesh, prob))
+    assert s.ntrace == h.ntrace
+    import torch
+
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal(s.ntrace)
+    y = torch.empty(s.ntrace, dtype=torch.float64, device="cuda")
+    s.trace_apply(dev(x), y)
+    e_s = rel_max(host(y), h.S @ x)
+    r_u, r_p = make_rhs_p1(prob, 2)
+    b = torch.empty_like(y)
+    s.condense(dev(r_u), dev(r_p), b)
+    ruc, rpc = r_u.reshape(36, -1).T.copy(), r_p.reshape(8, -1).T.copy()
+    e_b = rel_max(host(b), h.rhs(ruc, rpc))
+    u = torch.empty(36 * s.ncell, dtype=torch.float64, device="cuda")
+    pi = torch.empty(8 * s.ncell, dtype=torch.float64, device="cuda")
+    s.recover(dev(r_u), dev(r_p), dev(x), u, pi)
+    uref, pref = h.recover(x, ruc, rpc)
+    e_u = rel_max(host(u).reshape(36, -1).T, uref)
+    e_p = rel_max(host(pi).reshape(8, -1).T, pref)
+    say(f"[p1] {case}: S x {e_s:.1e}, B {e_b:.1e}, u {e_u:.1e}, pi {e_p:.1e}")
+    assert max(e_s, e_b) <= 1e-11 and max(e_u, e_p) <= 1e-10
+
+
+@pytest.mark.gpu
+def test_p1_fullsize_sampled_rows():
+    """128x128x32: 2000 sampled rows of S x and 500 sampled cells of the recovery against the oracle's
+    own cell matrices for the cells involved."""
+    import torch
+
+    prob = make_box(nx=128, ny=128, nlev=32, dx=10e3, dz=500.0, mg_levels=1)
+    s = make_p1_solver(prob)
+    mesh = BoxMesh(prob.nx, prob.ny, prob.nlev, prob.dx, prob.dy, prob.z)
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(s.ntrace)
+    y = torch.empty(s.ntrace, dtype=torch.float64, device="cuda")
+    s.trace_apply(dev(x), y)
+    yh = host(y)
+    rows = rng.choice(s.ntrace, 2000, replace=False)
+    facets = rows // 4
+    # the (cell, local face) pairs of each sampled facet
+    owner = {}
+    sel = np.isin(mesh.cell_faces, facets)
+    for c_, f_ in zip(*np.nonzero(sel)):
+        owner.setdefault(int(mesh.cell_faces[c_, f_]), []).append((int(c_), int(f_)))
+    need = sorted({c_ for v in owner.values() for c_, _ in v})
+    loc = op1.local_matrices(mesh, prob, cells=np.array(need))
+    SK = dict(zip(need, op1.cell_trace_operator(loc)))
+    dofs = op1.cell_dofs(mesh)
+    ref = np.zeros(len(rows))
+    for n_, T in enumerate(rows):
+        for c_, f_ in owner[int(T // 4)]:
+            ref[n_] += SK[c_][4 * f_ + T % 4] @ x[dofs[c_]]
+    e_s = np.abs(yh[rows] - ref).max() / np.abs(ref).max()
+    r_u, r_p = make_rhs_p1(prob, 4)
+    u = torch.empty(36 * s.ncell, dtype=torch.float64, device="cuda")
+    pi = torch.empty(8 * s.ncell, dtype=torch.float64, device="cuda")
+    s.recover(dev(r_u), dev(r_p), dev(x), u, pi)
+    cs = rng.choice(s.ncell, 500, replace=False)
+    locc = op1.local_matrices(mesh, prob, cells=cs)
+    ruc, rpc = r_u.reshape(36, -1).T[cs], r_p.reshape(8, -1).T[cs]
+    R = np.concatenate([ruc, rpc], axis=1)
+    R[:, :36] -= np.einsum("caf,cf->ca", locc["K"], x[dofs[cs]])
+    X = np.linalg.solve(locc["A"], R[:, :, None])[:, :, 0]
+    uh = host(u).reshape(36, -1).T[cs]
+    ph = host(pi).reshape(8, -1).T[cs]
+    e_u = np.abs(uh - X[:, :36]).max() / np.abs(X[:, :36]).max()
+    e_p = np.abs(ph - X[:, 36:]).max() / np.abs(X[:, 36:]).max()
+    say(f"[p1] 128x128x32 sampled: S x {e_s:.1e}, u {e_u:.1e}, pi {e_p:.1e}")
+    assert e_s <= 1e-11 and max(e_u, e_p) <= 1e-10
