@@ -63,6 +63,8 @@ extern "C" {
 
 #define HYB_PREC_FP64 0        /* every step in FP64 */
 #define HYB_PREC_MIXED 1       /* FP32 preconditioner and preconditioned basis, FP64 outer Krylov */
+#define HYB_PREC_MFMA_FP32 2   /* order 1 only: S_K condensed on FP32 MFMA (FP32 accumulation) */
+#define HYB_PREC_MFMA_BF16X 3  /* order 1 only: S_K condensed on BF16 MFMA, operands split hi + lo */
 
 typedef struct hyb_ctx hyb_ctx;
 

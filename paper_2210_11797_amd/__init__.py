@@ -12,6 +12,8 @@ from ._native import (  # noqa: F401
     HYB_OK,
     LIB_PATH,
     PREC_FP64,
+    PREC_MFMA_BF16X,
+    PREC_MFMA_FP32,
     PREC_MIXED,
     HybSolver,
     Params,

@@ -21,6 +21,8 @@ HYB_NOT_CONVERGED = 1
 HYB_BREAKDOWN = 2
 PREC_FP64 = 0
 PREC_MIXED = 1
+PREC_MFMA_FP32 = 2
+PREC_MFMA_BF16X = 3
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _f64p = ctypes.POINTER(ctypes.c_double)

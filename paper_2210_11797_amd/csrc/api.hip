@@ -20,8 +20,9 @@ int reduction_blocks();
 
 namespace {
 
-const char *kFamilyNames[F_COUNT] = {"smooth_rows", "smooth_rows0", "thomas", "trace_apply", "mg_smooth",
-                                     "restrict",    "prolong",      "krylov", "cell_solve",  "nn"};
+const char *kFamilyNames[F_COUNT] = {"smooth_rows", "smooth_rows0", "thomas",      "trace_apply", "mg_smooth",
+                                     "restrict",    "prolong",      "krylov",      "cell_solve",  "nn",
+                                     "p1_condense", "p1_factor"};
 
 int fail(hyb_ctx *c, int code, const std::string &msg) {
   if (c) c->err = msg;
@@ -70,7 +71,8 @@ int check_params(hyb_ctx *c, const hyb_params *p) {
   if (p->n_pre < 0 || p->n_post < 0 || p->mg_pre < 0 || p->mg_post < 0 || p->mg_coarse_sweeps < 1)
     return fail(c, HYB_EINVAL, "sweep counts must be >= 0 (coarse sweeps >= 1)");
   if (p->restart < 1 || p->restart > 200) return fail(c, HYB_EINVAL, "restart must be in [1, 200]");
-  if (p->precision != HYB_PREC_FP64 && p->precision != HYB_PREC_MIXED)
+  if (p->precision != HYB_PREC_FP64 && p->precision != HYB_PREC_MIXED && p->precision != HYB_PREC_MFMA_FP32 &&
+      p->precision != HYB_PREC_MFMA_BF16X)
     return fail(c, HYB_EINVAL, "unknown precision mode");
   if (p->learned != 0 && p->learned != 1) return fail(c, HYB_EINVAL, "learned must be 0 or 1");
   if (!(p->learned_tau > 0.0) || !std::isfinite(p->learned_tau)) return fail(c, HYB_EINVAL, "learned_tau must be > 0");
@@ -253,6 +255,14 @@ int hyb_create(const hyb_mesh *mesh, const hyb_params *params, void *stream, hyb
   }
   c->order = mesh->order;
   if (c->order == 1) c->ntrace *= 4;
+  {
+    const bool mfma = params->precision == HYB_PREC_MFMA_FP32 || params->precision == HYB_PREC_MFMA_BF16X;
+    // MFMA condensation is an order-1 mode; order 1 has no mixed-precision solve
+    if ((c->order == 0 && mfma) || (c->order == 1 && params->precision == HYB_PREC_MIXED)) {
+      delete c;
+      return HYB_EINVAL;
+    }
+  }
   c->dx = mesh->dx;
   c->dy = mesh->dy;
   c->dz.assign(mesh->dz, mesh->dz + c->nlev);
@@ -297,8 +307,16 @@ int hyb_set_params(hyb_ctx *c, const hyb_params *params) {
   int rc = check_params(c, params);
   if (rc) return rc;
   bool prec_change = params->precision != c->p.precision;
+  if (c->order == 1) {
+    if (params->precision == HYB_PREC_MIXED) return fail(c, HYB_EINVAL, "order 1 has no mixed-precision solve");
+    c->p = *params;
+    // the condensation arithmetic changed: A_K has been replaced by its factors, so assemble again
+    if (prec_change) c->assembled = c->condensed = false;
+    return HYB_OK;
+  }
+  if (params->precision == HYB_PREC_MFMA_FP32 || params->precision == HYB_PREC_MFMA_BF16X)
+    return fail(c, HYB_EINVAL, "MFMA condensation is an order-1 mode");
   c->p = *params;
-  if (c->order == 1) return HYB_OK;
   if (prec_change && c->condensed && c->p.precision == HYB_PREC_MIXED) {
     // FP32 copies are made at condensation; refresh them for the new mode
     CHECK_HIP(launch_to_float(c, c->S, c->Sf, (size_t)11 * c->ntrace), "to_float S");

@@ -144,6 +144,8 @@ enum Family {
   F_KRYLOV,
   F_CELL,
   F_NN,               // learned coarse-correction stage
+  F_P1_CONDENSE,      // order 1: S_K on MFMA
+  F_P1_FACTOR,        // order 1: FP64 LU of A_K (and S_K in the FP64 mode)
   F_COUNT
 };
 

@@ -202,7 +202,8 @@ __global__ void __launch_bounds__(kBlock) k_p1_assemble(int ncell, int ncol, con
 constexpr int kP1Waves = 2;  // cells per workgroup (LDS: 2 x (44 x 44 + 44 x 24) doubles)
 __global__ void __launch_bounds__(64 * kP1Waves) k_p1_factor(int ncell, double *__restrict__ A,
                                                             const double *__restrict__ cdiag,
-                                                            const double *__restrict__ kdiag, double *__restrict__ SK) {
+                                                            const double *__restrict__ kdiag, double *__restrict__ SK,
+                                                            int write_sk) {
   __shared__ double sA[kP1Waves][NX * NX];
   __shared__ double sX[kP1Waves][NX * NF];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -240,11 +241,133 @@ __global__ void __launch_bounds__(64 * kP1Waves) k_p1_factor(int ncell, double *
   if (active) {
     double *Ac = A + (size_t)c * NA;
     for (int e = lane; e < NA; e += 64) Ac[e] = a[e];
-    for (int e = lane; e < NS; e += 64) {
-      const int r = e / NF, s = e - r * NF;
-      SK[(size_t)c * NS + e] = cdiag[(size_t)c * NF + r] * x[r * NF + s];
+    if (write_sk)
+      for (int e = lane; e < NS; e += 64) {
+        const int r = e / NF, s = e - r * NF;
+        SK[(size_t)c * NS + e] = cdiag[(size_t)c * NF + r] * x[r * NF + s];
+      }
+  }
+}
+
+// ---- condensation on MFMA ------------------------------------------------------------------------
+// S_K from A_K and K_K with matrix cores: one wavefront per cell; [A_K | [K_K; 0]] padded to 48 rows,
+// 48 + 32 columns (identity on the padding), FP32 in LDS.  Blocked right-looking elimination without
+// pivoting, block 16: the 16-column panel (and the 16-row block to its right) by the lanes, the
+// trailing update A22 -= L21 U12 as 16x16 tiles on MFMA; then the blocked back substitution with U,
+// whose off-diagonal block products are MFMA tiles too.  SPLIT: each FP32 operand is split into
+// BF16 hi + lo and a tile product is hi*lo + lo*hi + hi*hi (FP32 accumulation), else FP32 MFMA.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+constexpr int MP = 48, MW = 80, LDM = 81;  // padded size, augmented width, LDS row stride (odd)
+constexpr int kMW = 4;                     // cells (wavefronts) per workgroup
+
+__device__ __forceinline__ short bf16_rne(float f) {
+  const unsigned u = __float_as_uint(f);
+  return (short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_val(short h) { return __uint_as_float(((unsigned)(unsigned short)h) << 16); }
+
+// P = M[r0:r0+16, k0:k0+16] M[k0:k0+16, c0:c0+16]; lane layouts of the two instructions: FP32 16x16x4:
+// a = A[l%16][l/16], b = B[l/16][l%16]; BF16 16x16x16: a[j] = A[l%16][4(l/16)+j], b[j] = B[4(l/16)+j][l%16];
+// result: d[j] = P[4(l/16)+j][l%16]
+template <bool SPLIT>
+__device__ __forceinline__ f32x4 tile_product(const float *M, int r0, int k0, int c0, int lane) {
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  const int lr = lane & 15, lk = lane >> 4;
+  if constexpr (!SPLIT) {
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const float a = M[(r0 + lr) * LDM + k0 + 4 * kk + lk];
+      const float b = M[(k0 + 4 * kk + lk) * LDM + c0 + lr];
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+    }
+  } else {
+    bf16x4 ah, al, bh, bl;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float a = M[(r0 + lr) * LDM + k0 + 4 * lk + j];
+      const float b = M[(k0 + 4 * lk + j) * LDM + c0 + lr];
+      const short a1 = bf16_rne(a), b1 = bf16_rne(b);
+      ah[j] = a1, al[j] = bf16_rne(a - bf16_val(a1));
+      bh[j] = b1, bl[j] = bf16_rne(b - bf16_val(b1));
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+template <bool SPLIT>
+__global__ void __launch_bounds__(64 * kMW) k_p1_condense_mfma(int ncell, const double *__restrict__ A,
+                                                              const double *__restrict__ cdiag,
+                                                              const double *__restrict__ kdiag,
+                                                              double *__restrict__ SK) {
+  __shared__ float sM[kMW][MP * LDM];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int c = blockIdx.x * kMW + wv;
+  const bool active = c < ncell;  // uniform within a wavefront
+  float *M = sM[wv];
+  if (active) {
+    const double *Ac = A + (size_t)c * NA;
+    for (int e = lane; e < MP * MW; e += 64) {
+      const int i = e / MW, j = e - i * MW;
+      float v;
+      if (j < MP) {
+        v = (i < NX && j < NX) ? (float)Ac[i * NX + j] : (i == j ? 1.f : 0.f);
+      } else {
+        const int q = j - MP;
+        v = (i == q && q < NF) ? (float)kdiag[(size_t)c * NF + q] : 0.f;
+      }
+      M[i * LDM + j] = v;
     }
   }
+  __syncthreads();
+  for (int kb = 0; kb < 3; ++kb) {
+    const int r0 = 16 * kb, rend = r0 + 16;
+    for (int k = r0; k < rend; ++k) {
+      if (active && lane > k && lane < MP) {
+        const float l = M[lane * LDM + k] / M[k * LDM + k];
+        M[lane * LDM + k] = l;
+        const int jend = lane < rend ? MW : rend;  // block rows: whole row (U12, RHS); below: the panel
+        for (int j = k + 1; j < jend; ++j) M[lane * LDM + j] -= l * M[k * LDM + j];
+      }
+      __syncthreads();
+    }
+    for (int tr = kb + 1; tr < 3; ++tr)
+      for (int tc = kb + 1; tc < 5; ++tc) {
+        if (!active) continue;
+        const f32x4 p = tile_product<SPLIT>(M, 16 * tr, r0, 16 * tc, lane);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) M[(16 * tr + 4 * (lane >> 4) + j) * LDM + 16 * tc + (lane & 15)] -= p[j];
+      }
+    __syncthreads();
+  }
+  for (int kb = 2; kb >= 0; --kb) {
+    const int r0 = 16 * kb;
+    if (active && lane < 32) {
+      const int col = MP + lane;
+      for (int i = r0 + 15; i >= r0; --i) {
+        float sum = M[i * LDM + col];
+        for (int m = i + 1; m < r0 + 16; ++m) sum -= M[i * LDM + m] * M[m * LDM + col];
+        M[i * LDM + col] = sum / M[i * LDM + i];
+      }
+    }
+    __syncthreads();
+    for (int tr = 0; tr < kb; ++tr)
+      for (int tc = 3; tc < 5; ++tc) {
+        if (!active) continue;
+        const f32x4 p = tile_product<SPLIT>(M, 16 * tr, r0, 16 * tc, lane);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) M[(16 * tr + 4 * (lane >> 4) + j) * LDM + 16 * tc + (lane & 15)] -= p[j];
+      }
+    __syncthreads();
+  }
+  if (active)
+    for (int e = lane; e < NS; e += 64) {
+      const int r = e / NF, q = e - r * NF;
+      SK[(size_t)c * NS + e] = cdiag[(size_t)c * NF + r] * (double)M[r * LDM + MP + q];
+    }
 }
 
 // Global trace dof of local face dof j of cell (k, col).
@@ -376,10 +499,25 @@ hipError_t p1_assemble(hyb_ctx *c, const double *theta_w, const double *exner_ha
   return hipGetLastError();
 }
 
+// S_K in the arithmetic of params.precision (FP64, FP32 MFMA or BF16-split MFMA), then the FP64
+// LU factors of A_K in place (used by the per-solve cell solves: B_lambda and the recovery).
 hipError_t p1_factor(hyb_ctx *c) {
   P1State &s = c->p1;
+  const int prec = c->p.precision;
+  int slot = prof_begin(c, F_P1_CONDENSE);
+  if (prec == HYB_PREC_MFMA_FP32)
+    hipLaunchKernelGGL((k_p1_condense_mfma<false>), dim3(nblk(c->ncell, kMW)), dim3(64 * kMW), 0, c->stream, c->ncell,
+                       s.A, s.cdiag, s.kdiag, s.SK);
+  else if (prec == HYB_PREC_MFMA_BF16X)
+    hipLaunchKernelGGL((k_p1_condense_mfma<true>), dim3(nblk(c->ncell, kMW)), dim3(64 * kMW), 0, c->stream, c->ncell,
+                       s.A, s.cdiag, s.kdiag, s.SK);
+  prof_end(c, F_P1_CONDENSE, slot);
+  hipError_t e = hipGetLastError();
+  if (e) return e;
+  slot = prof_begin(c, F_P1_FACTOR);
   hipLaunchKernelGGL(k_p1_factor, dim3(nblk(c->ncell, kP1Waves)), dim3(64 * kP1Waves), 0, c->stream, c->ncell, s.A,
-                     s.cdiag, s.kdiag, s.SK);
+                     s.cdiag, s.kdiag, s.SK, prec == HYB_PREC_FP64 ? 1 : 0);
+  prof_end(c, F_P1_FACTOR, slot);
   return hipGetLastError();
 }
 

@@ -1,8 +1,9 @@
 """Build the library's own sources for the CPU stand-in of the HIP runtime, with AddressSanitizer.
 
-Test harness only.  The sources are taken unchanged from paper_2210_11797_amd/csrc except for two
-textual substitutions that g++ needs (the dynamic LDS array becomes the stand-in's per-launch
-buffer; the header include gets an absolute path); the result is a separate shared object in a
+Test harness only.  The sources are taken unchanged from paper_2210_11797_amd/csrc except for textual
+substitutions that g++ needs (the dynamic LDS array becomes the stand-in's per-launch buffer; the
+header include gets an absolute path; clang's vector types used as matrix-core operands become the
+stand-in's structs); the result is a separate shared object in a
 scratch directory, never the product library.
 """
 
@@ -36,6 +37,8 @@ def _prepare(outdir: str) -> list[str]:
         text = text.replace('"../../include/hyb.h"', f'"{hdr}"')
         text = text.replace("extern __shared__ unsigned char smem_raw[];",
                             "unsigned char *smem_raw = emu::dyn_smem();")
+        text = text.replace("typedef float f32x4 __attribute__((ext_vector_type(4)));", "typedef emu_f32x4 f32x4;")
+        text = text.replace("typedef short bf16x4 __attribute__((ext_vector_type(4)));", "typedef emu_bf16x4 bf16x4;")
         dst = os.path.join(outdir, name if name.endswith(".h") else name.replace(".hip", ".cpp"))
         with open(dst, "w") as f:
             f.write(text)

@@ -45,14 +45,14 @@ dim3 threadIdx_, blockIdx_, blockDim_, gridDim_;
 
 namespace {
 constexpr size_t kStack = 256 * 1024;
-enum State { READY, WAIT, DONE };
+enum State { READY, WAIT, WAVE_WAIT, DONE };
 struct Fiber {
   void *sp = nullptr;
   char *stack = nullptr;
   void *fake = nullptr;
   State st = READY;
   unsigned tid = 0;
-  uint64_t xchg = 0;
+  alignas(16) unsigned char xchg[64];
 };
 std::vector<Fiber> fibers;
 Fiber *cur = nullptr;
@@ -106,9 +106,13 @@ void barrier() {
   cur->st = WAIT;
   to_main(false);
 }
+void wave_barrier() {
+  if (!cur) { std::fprintf(stderr, "wavefront barrier outside a kernel\n"); std::abort(); }
+  cur->st = WAVE_WAIT;
+  to_main(false);
+}
 unsigned char *dyn_smem() { return dyn.data(); }
-void *xchg_slot() { return &cur->xchg; }
-void *xchg_slot_of(unsigned tid) { return &fibers[tid].xchg; }
+void *xchg(unsigned tid) { return fibers[tid].xchg; }
 unsigned cur_tid() { return cur->tid; }
 
 void launch(dim3 g, dim3 b, size_t shm, const std::function<void()> &k) {
@@ -139,11 +143,29 @@ void launch(dim3 g, dim3 b, size_t shm, const std::function<void()> &k) {
             __sanitizer_finish_switch_fiber(main_fake, nullptr, nullptr);
           }
           cur = nullptr;
-          unsigned waiting = 0;
-          for (unsigned t = 0; t < nt; ++t) waiting += fibers[t].st == WAIT;
-          if (!waiting) break;
+          // a wavefront whose live threads all wait at a wavefront barrier goes on first; then a
+          // workgroup barrier once every live thread waits at one
+          bool released = false;
+          for (unsigned w0 = 0; w0 < nt; w0 += 64) {
+            unsigned live = 0, wwait = 0;
+            for (unsigned t = w0; t < nt && t < w0 + 64; ++t)
+              if (fibers[t].st != DONE) ++live, wwait += fibers[t].st == WAVE_WAIT;
+            if (live && wwait == live) {
+              for (unsigned t = w0; t < nt && t < w0 + 64; ++t) fibers[t].st = READY;
+              released = true;
+            }
+          }
+          if (released) continue;
+          unsigned live = 0, waiting = 0;
           for (unsigned t = 0; t < nt; ++t)
-            if (fibers[t].st == WAIT) fibers[t].st = READY;
+            if (fibers[t].st != DONE) ++live, waiting += fibers[t].st == WAIT;
+          if (!live) break;
+          if (waiting != live) {
+            std::fprintf(stderr, "EMU: threads of a workgroup wait at different barriers (kernel launch %zu)\n",
+                         launches);
+            std::abort();
+          }
+          for (unsigned t = 0; t < nt; ++t) fibers[t].st = READY;
         }
       }
 }

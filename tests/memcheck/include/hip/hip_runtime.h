@@ -31,8 +31,8 @@ extern dim3 threadIdx_, blockIdx_, blockDim_, gridDim_;
 void launch(dim3 g, dim3 b, size_t shm, const std::function<void()> &body);
 void barrier();
 unsigned char *dyn_smem();
-void *xchg_slot();  // 8-byte exchange slot of the current thread
-void *xchg_slot_of(unsigned tid);
+void wave_barrier();  // barrier among the fibers of the current wavefront (64 threads)
+void *xchg(unsigned tid);  // 64-byte exchange slot of a thread of the current workgroup
 unsigned cur_tid();
 }  // namespace emu
 #define threadIdx emu::threadIdx_
@@ -55,15 +55,77 @@ unsigned cur_tid();
 template <typename T>
 inline T __shfl_down(T v, unsigned off, int width = 64) {
   static_assert(sizeof(T) <= 8, "shfl of a large type");
-  std::memcpy(emu::xchg_slot(), &v, sizeof(T));
-  emu::barrier();
-  unsigned tid = emu::cur_tid();
+  const unsigned tid = emu::cur_tid();
+  std::memcpy(emu::xchg(tid), &v, sizeof(T));
+  emu::wave_barrier();
   unsigned lane = tid % (unsigned)width, src = lane + off;
   T r = v;
-  if (src < (unsigned)width) std::memcpy(&r, emu::xchg_slot_of(tid - lane + src), sizeof(T));
-  emu::barrier();
+  if (src < (unsigned)width) std::memcpy(&r, emu::xchg(tid - lane + src), sizeof(T));
+  emu::wave_barrier();
   return r;
 }
+
+// Matrix-core instructions used by the library, with their lane layouts (wavefront of 64):
+// f32 16x16x4: a = A[l%16][l/16], b = B[l/16][l%16]; bf16 16x16x16: a[j] = A[l%16][4(l/16)+j],
+// b[j] = B[4(l/16)+j][l%16]; result d[j] = D[4(l/16)+j][l%16].
+struct emu_f32x4 {
+  float v[4];
+  float &operator[](int i) { return v[i]; }
+  float operator[](int i) const { return v[i]; }
+};
+struct emu_bf16x4 {
+  short v[4];
+  short &operator[](int i) { return v[i]; }
+  short operator[](int i) const { return v[i]; }
+};
+inline float emu_bf16_to_f32(short h) {
+  uint32_t u = ((uint32_t)(uint16_t)h) << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+inline emu_f32x4 emu_mfma_f32_16x16x4f32(float a, float b, emu_f32x4 c, int, int, int) {
+  const unsigned tid = emu::cur_tid(), lane = tid % 64, base = tid - lane;
+  float ab[2] = {a, b};
+  std::memcpy(emu::xchg(tid), ab, 8);
+  emu::wave_barrier();
+  for (int j = 0; j < 4; ++j) {
+    const unsigned row = 4 * (lane / 16) + j, col = lane % 16;
+    float acc = 0.f;
+    for (unsigned k = 0; k < 4; ++k) {
+      float A[2], B[2];
+      std::memcpy(A, emu::xchg(base + k * 16 + row), 8);
+      std::memcpy(B, emu::xchg(base + k * 16 + col), 8);
+      acc += A[0] * B[1];
+    }
+    c[j] += acc;
+  }
+  emu::wave_barrier();
+  return c;
+}
+inline emu_f32x4 emu_mfma_f32_16x16x16bf16_1k(emu_bf16x4 a, emu_bf16x4 b, emu_f32x4 c, int, int, int) {
+  const unsigned tid = emu::cur_tid(), lane = tid % 64, base = tid - lane;
+  short ab[8];
+  for (int j = 0; j < 4; ++j) ab[j] = a[j], ab[4 + j] = b[j];
+  std::memcpy(emu::xchg(tid), ab, 16);
+  emu::wave_barrier();
+  for (int j = 0; j < 4; ++j) {
+    const unsigned row = 4 * (lane / 16) + j, col = lane % 16;
+    float acc = 0.f;
+    for (unsigned k = 0; k < 16; ++k) {
+      short A[8], B[8];
+      std::memcpy(A, emu::xchg(base + (k / 4) * 16 + row), 16);
+      std::memcpy(B, emu::xchg(base + (k / 4) * 16 + col), 16);
+      acc += emu_bf16_to_f32(A[k % 4]) * emu_bf16_to_f32(B[4 + k % 4]);
+    }
+    c[j] += acc;
+  }
+  emu::wave_barrier();
+  return c;
+}
+#define __builtin_amdgcn_mfma_f32_16x16x4f32 emu_mfma_f32_16x16x4f32
+#define __builtin_amdgcn_mfma_f32_16x16x16bf16_1k emu_mfma_f32_16x16x16bf16_1k
+
 inline float __uint_as_float(uint32_t u) { float f; std::memcpy(&f, &u, 4); return f; }
 inline uint32_t __float_as_uint(float f) { uint32_t u; std::memcpy(&u, &f, 4); return u; }
 template <class A, class B> inline auto min(A a, B b) -> typename std::common_type<A, B>::type { return a < b ? a : b; }

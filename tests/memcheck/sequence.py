@@ -234,6 +234,14 @@ def p1_sequence(lib):
           "order 1: recovery matches the oracle")
     check(lib.hyb_precondition(c.h, P(b), P(y)) < 0, "order 1: calls it does not provide are rejected")
     c.close()
+    # S_K condensed on matrix cores (FP32, and BF16 split into hi + lo) against the FP64 operator
+    for prec, tol in ((N.PREC_MFMA_FP32, 1e-5), (N.PREC_MFMA_BF16X, 1e-4)):
+        cm = Ctx(lib, prob, order=1, precision=prec)
+        ym = np.empty(cm.ntrace)
+        cm.call("hyb_trace_apply", P(x), P(ym))
+        err = np.abs(ym - ref).max() / np.abs(ref).max()
+        check(err <= tol, f"order 1, condensation mode {prec}: S x error vs FP64 {err:.1e}")
+        cm.close()
 
 
 def main():

@@ -110,3 +110,37 @@ def test_p1_fullsize_sampled_rows():
     e_p = np.abs(ph - X[:, 36:]).max() / np.abs(X[:, 36:]).max()
     say(f"[p1] 128x128x32 sampled: S x {e_s:.1e}, u {e_u:.1e}, pi {e_p:.1e}")
     assert e_s <= 1e-11 and max(e_u, e_p) <= 1e-10
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("size", ["8x6x5", "128x128x32"])
+def test_p1_mfma_condensation_error_vs_fp64(size):
+    """S_K condensed on matrix cores against the FP64 condensation: FP32 MFMA to 1e-5 and BF16 split
+    hi + lo (three products, FP32 accumulation) to 1e-4 of the largest entry of S x; the elimination
+    without pivoting in FP32 loses about cond(A_K) * 2^-24 on A_K, far less on the condensed block
+    (~1e-6 measured)."""
+    import torch
+
+    from paper_2210_11797_amd import PREC_FP64, PREC_MFMA_BF16X, PREC_MFMA_FP32
+
+    if size == "8x6x5":
+        prob = _box(CASES["8x6x5"])
+    else:
+        prob = make_box(nx=128, ny=128, nlev=32, dx=10e3, dz=500.0, mg_levels=1)
+    rng = np.random.default_rng(8)
+    x = dev(rng.standard_normal(4 * (prob.ncol * (prob.nlev + 1) + 2 * prob.ncol * prob.nlev)))
+    out = {}
+    for prec in (PREC_FP64, PREC_MFMA_FP32, PREC_MFMA_BF16X):
+        s = HybSolver(prob.nlev, levels_of(prob), prob.dx, prob.dy, prob.dz, params_for(prob, precision=prec), order=1)
+        s.assemble_local(dev(prob.theta_w), dev(prob.exner_hat_w), dev(prob.exner_c), dev(prob.rho_c))
+        s.condense()
+        y = torch.empty(s.ntrace, dtype=torch.float64, device="cuda")
+        s.trace_apply(x, y)
+        out[prec] = host(y)
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    e32 = rel_max(out[PREC_MFMA_FP32], out[PREC_FP64])
+    ebf = rel_max(out[PREC_MFMA_BF16X], out[PREC_FP64])
+    say(f"[p1] {size}: S x error vs FP64 condensation: FP32 MFMA {e32:.1e}, BF16 split MFMA {ebf:.1e}")
+    assert e32 <= 1e-5 and ebf <= 1e-4
