@@ -306,3 +306,63 @@ class MixedP1:
         """Broken (outward) velocity (ncell, 36) and pressure (ncell, 8) of a mixed solution."""
         x = np.where(self.full >= 0, sol[np.maximum(self.full, 0)], 0.0) * self.fsign
         return x[:, :NU], x[:, NU:]
+
+
+# ---- the two-level preconditioner at order 1 (Alg. 1 and Alg. 2 with the DG0 coarse space) ----
+
+def trace_prolongation(mesh: BoxMesh):
+    """P: DG0 cells -> order-1 trace, every dof of a facet = the average of its two cells (its one
+    cell on the lid and the ground)."""
+    rows, cols, vals = [], [], []
+    cf = mesh.cell_faces
+    for f in range(6):
+        F = cf[:, f]
+        w = np.where(mesh.boundary[F], 1.0, 0.5)
+        for i in range(4):
+            rows.append(4 * F + i)
+            cols.append(np.arange(mesh.ncell))
+            vals.append(w)
+    cat = np.concatenate
+    return sp.csr_matrix((cat(vals), (cat(rows), cat(cols))), shape=(4 * mesh.ntrace, mesh.ncell))
+
+
+def line_smoother_matrix(mesh: BoxMesh, S):
+    """D of LineSmooth at order 1: S restricted to the couplings between dofs of horizontal facets
+    of the same column (block tridiagonal with 4x4 blocks), and the diagonal of S on the dofs of
+    vertical facets (point Jacobi)."""
+    S = sp.coo_matrix(S)
+    nz = mesh.n_zface
+    Fr, Fc = S.row // 4, S.col // 4
+    zr, zc = Fr < nz, Fc < nz
+    same_col = zr & zc & ((Fr % mesh.ncol) == (Fc % mesh.ncol))
+    keep = same_col | (~zr & (S.row == S.col))
+    return sp.csr_matrix((S.data[keep], (S.row[keep], S.col[keep])), shape=S.shape)
+
+
+class TwoLevelP1:
+    """Alg. 2 at order 1: LineSmooth (n_pre) from zero, residual, B = Gamma P^T R, one pressure
+    multigrid V-cycle on the order-0 H of the same mesh, lambda += P dPi, LineSmooth (n_post)."""
+
+    def __init__(self, mesh: BoxMesh, S, H, omega=0.6, n_pre=1, n_post=2, mg_levels=4, omega_p=0.9, mg_pre=1,
+                 mg_post=2, mg_coarse_sweeps=30):
+        from .precond import PressureMultigrid
+
+        self.mesh, self.S = mesh, sp.csr_matrix(S)
+        self.omega, self.n_pre, self.n_post = omega, n_pre, n_post
+        self.D = line_smoother_matrix(mesh, self.S)
+        self.D_lu = spla.splu(self.D.tocsc())
+        self.P = trace_prolongation(mesh)
+        self.mg = PressureMultigrid(H, mesh.nx, mesh.ny, mesh.nlev, mg_levels, omega_p, mg_pre, mg_post,
+                                    mg_coarse_sweeps)
+        ones = np.ones(mesh.ncell)
+        self.gamma = (H @ ones) / (self.P.T @ (self.S @ (self.P @ ones)))
+
+    def line_smooth(self, lam, B, sweeps):
+        for _ in range(sweeps):
+            lam = lam + self.omega * self.D_lu.solve(B - self.S @ lam)
+        return lam
+
+    def __call__(self, B):
+        lam = self.line_smooth(np.zeros_like(B), B, self.n_pre)
+        dpi = self.mg.vcycle(self.gamma * (self.P.T @ (B - self.S @ lam)))
+        return self.line_smooth(lam + self.P @ dpi, B, self.n_post)
