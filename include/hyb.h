@@ -127,8 +127,13 @@ typedef struct {
    4 i + 2 j + k); Q1 trace nodal at the 2x2 face Gauss points, trace dof 4 F + i for facet F in
    the order-0 numbering.  Cell fields are the same inputs; right-hand sides and recovered fields
    are r_ub / u_b [36][nlev][ncol] and r_pi / pi [8][nlev][ncol]; trace vectors have 4 x the
-   order-0 length (hyb_sizes).  Order 1 provides hyb_assemble_local, hyb_condense,
-   hyb_trace_apply and hyb_recover; the other calls return HYB_ESTATE for it. */
+   order-0 length (hyb_sizes).  The two-level preconditioner at order 1 uses the DG0 coarse space
+   with the order-0 pressure operator H on the same mesh (an internal order-0 context), P setting
+   the 4 dofs of a facet to the average of its cells, Gamma = H 1 / (P^T S P 1), and LineSmooth
+   with 4x4 block-tridiagonal column solves on the horizontal facets and point Jacobi on the
+   vertical ones; hyb_solve is FGMRES with it (FP64).  params.precision chooses the arithmetic of
+   the condensation of S_K (HYB_PREC_FP64 or the MFMA modes); changing it needs a new
+   hyb_assemble_local.  hyb_restrict and the learned stage return HYB_ESTATE at order 1. */
 
 /* Create a context for one mesh.  stream: a hipStream_t (NULL = default stream).
    Fails with HYB_EINVAL on inconsistent tables (every edge must appear on

@@ -176,6 +176,7 @@ void free_all(hyb_ctx *c) {
   c->fam.clear();
   nn_free(c);
   p1_free(c);
+  if (c->coarse) hyb_destroy(c->coarse), c->coarse = nullptr;
 }
 
 int alloc_krylov(hyb_ctx *c) {
@@ -298,6 +299,21 @@ int hyb_create(const hyb_mesh *mesh, const hyb_params *params, void *stream, hyb
     delete c;
     return rc;
   }
+  if (c->order == 1) {
+    // the DG0 coarse space: an order-0 context on the same mesh (its pressure operator H, the
+    // multigrid hierarchy and its V-cycle)
+    hyb_mesh m0 = *mesh;
+    m0.order = 0;
+    hyb_params p0 = *params;
+    p0.precision = HYB_PREC_FP64;
+    p0.learned = 0;
+    rc = hyb_create(&m0, &p0, stream, &c->coarse);
+    if (rc != HYB_OK) {
+      free_all(c);
+      delete c;
+      return rc;
+    }
+  }
   *out = c;
   return HYB_OK;
 }
@@ -309,6 +325,10 @@ int hyb_set_params(hyb_ctx *c, const hyb_params *params) {
   bool prec_change = params->precision != c->p.precision;
   if (c->order == 1) {
     if (params->precision == HYB_PREC_MIXED) return fail(c, HYB_EINVAL, "order 1 has no mixed-precision solve");
+    if (params->learned) return fail(c, HYB_EINVAL, "order 1 has no learned stage");
+    hyb_params p0 = *params;
+    p0.precision = HYB_PREC_FP64;
+    if ((rc = hyb_set_params(c->coarse, &p0))) return fail(c, rc, std::string("coarse space: ") + hyb_last_error(c->coarse));
     c->p = *params;
     // the condensation arithmetic changed: A_K has been replaced by its factors, so assemble again
     if (prec_change) c->assembled = c->condensed = false;
@@ -344,6 +364,8 @@ int hyb_assemble_local(hyb_ctx *c, const double *theta_w, const double *exner_ha
       return rc;
     CHECK_HIP(p1_setup(c), "p1 tables");
     CHECK_HIP(p1_assemble(c, theta_w, exner_hat_w, exner_c, rho_c), "p1 assemble_local");
+    if ((rc = hyb_assemble_local(c->coarse, theta_w, exner_hat_w, exner_c, rho_c)))
+      return fail(c, rc, std::string("coarse space: ") + hyb_last_error(c->coarse));
     c->assembled = true;
     c->condensed = false;
     return HYB_OK;
@@ -362,7 +384,17 @@ int hyb_condense(hyb_ctx *c, const double *r_ub, const double *r_pi, double *b_l
   if (c->order == 1) {
     if (r_ub == nullptr) {
       if (c->condensed) return HYB_OK;  // the LU factors replaced A_K
+      if ((rc = hyb_condense(c->coarse, nullptr, nullptr, nullptr)))
+        return fail(c, rc, std::string("coarse space: ") + hyb_last_error(c->coarse));
       CHECK_HIP(p1_factor(c), "p1 factor");
+      hyb::P1State &s = c->p1;
+      const size_t ntr = (size_t)c->ntrace, nc = (size_t)c->ncell;
+      if ((rc = dalloc(c, &s.dS, ntr)) || (rc = dalloc(c, &s.zf, 48 * (size_t)c->nz)) ||
+          (rc = dalloc(c, &s.gamma, nc)) || (rc = dalloc(c, &s.den, nc)) || (rc = dalloc(c, &s.t1, ntr)) ||
+          (rc = dalloc(c, &s.t2, ntr)) || (rc = dalloc(c, &s.t3, ntr)))
+        return rc;
+      CHECK_HIP(p1_precond_setup(c), "p1 preconditioner setup");
+      if ((rc = alloc_krylov(c))) return rc;
       CHECK_HIP(hipStreamSynchronize(c->stream), "condense sync");
       c->condensed = true;
       return HYB_OK;
@@ -370,7 +402,7 @@ int hyb_condense(hyb_ctx *c, const double *r_ub, const double *r_pi, double *b_l
     if (!c->condensed) return fail(c, HYB_ESTATE, "condense the operator (r_ub = NULL) first");
     if (!r_pi || !b_lambda) return fail(c, HYB_EINVAL, "null argument");
     CHECK_HIP(p1_cell_solve(c, r_ub, r_pi, nullptr, 0, nullptr, nullptr), "p1 condense rhs");
-    CHECK_HIP(p1_rows(c, nullptr, b_lambda, 1), "p1 gather rhs");
+    CHECK_HIP(p1_rows(c, nullptr, b_lambda, 1, nullptr), "p1 gather rhs");
     return HYB_OK;
   }
   if (r_ub == nullptr) {
@@ -416,7 +448,7 @@ int hyb_trace_apply(hyb_ctx *c, const double *x, double *y) {
   if (!c->condensed) return fail(c, HYB_ESTATE, "trace_apply before condense");
   if (!x || !y || x == y) return fail(c, HYB_EINVAL, "bad vectors");
   if (c->order == 1) {
-    CHECK_HIP(p1_rows(c, x, y, 0), "p1 trace_apply");
+    CHECK_HIP(p1_rows(c, x, y, 0, nullptr), "p1 trace_apply");
     return HYB_OK;
   }
   CHECK_HIP((launch_trace_apply<double, double, double>(c, c->S, x, nullptr, y, 0)), "trace_apply");
@@ -425,7 +457,12 @@ int hyb_trace_apply(hyb_ctx *c, const double *x, double *y) {
 
 int hyb_precondition(hyb_ctx *c, const double *r, double *z) {
   if (!c) return HYB_EINVAL;
-  if (c->order == 1) return fail(c, HYB_ESTATE, "hyb_precondition is not available at order 1");
+  if (c->order == 1) {
+    if (!c->condensed) return fail(c, HYB_ESTATE, "precondition before condense");
+    if (!r || !z || r == z) return fail(c, HYB_EINVAL, "bad vectors");
+    CHECK_HIP(p1_precondition(c, r, z), "p1 precondition");
+    return HYB_OK;
+  }
   if (!c->condensed) return fail(c, HYB_ESTATE, "precondition before condense");
   if (!r || !z || r == z) return fail(c, HYB_EINVAL, "bad vectors");
   if (c->p.learned && !c->nn.loaded) return fail(c, HYB_ESTATE, "learned stage requested without weights");
@@ -451,7 +488,6 @@ int hyb_precondition(hyb_ctx *c, const double *r, double *z) {
 
 int hyb_solve(hyb_ctx *c, const double *b, double *lam, double rtol, int32_t maxit, hyb_info *info) {
   if (!c) return HYB_EINVAL;
-  if (c->order == 1) return fail(c, HYB_ESTATE, "hyb_solve is not available at order 1");
   if (!c->condensed) return fail(c, HYB_ESTATE, "solve before condense");
   if (!b || !lam || b == lam || !(rtol >= 0) || maxit < 0) return fail(c, HYB_EINVAL, "bad solve arguments");
   int rc = alloc_krylov(c);
@@ -487,7 +523,10 @@ int hyb_solve(hyb_ctx *c, const double *b, double *lam, double rtol, int32_t max
   }
   for (;;) {
     // true residual r = b - S lam into V_0
-    CHECK_HIP((launch_trace_apply<double, double, double>(c, c->S, lam, b, V, 1)), "residual");
+    if (c->order == 1)
+      CHECK_HIP(p1_rows(c, lam, V, 2, b), "residual");
+    else
+      CHECK_HIP((launch_trace_apply<double, double, double>(c, c->S, lam, b, V, 1)), "residual");
     CHECK_HIP(launch_multidot(c, V, 0, 0, V, n, nrm, true), "norm r");
     CHECK_HIP(hipMemcpyAsync(hh, nrm, sizeof(double), hipMemcpyDeviceToHost, c->stream), "d2h");
     CHECK_HIP(hipStreamSynchronize(c->stream), "sync");
@@ -516,6 +555,10 @@ int hyb_solve(hyb_ctx *c, const double *b, double *lam, double rtol, int32_t max
         CHECK_HIP(precondition<float>(c, (const float *)c->tIn, zf), "precondition");
         if (learned) CHECK_HIP(learned_stage<float>(c, vj, zf), "learned stage");
         CHECK_HIP((launch_trace_apply<double, float, double>(c, c->S, zf, nullptr, w, 0)), "matvec");
+      } else if (c->order == 1) {
+        double *zj = (double *)c->Z + (size_t)j * n;
+        CHECK_HIP(p1_precondition(c, vj, zj), "precondition");
+        CHECK_HIP(p1_rows(c, zj, w, 0, nullptr), "matvec");
       } else {
         double *zj = (double *)c->Z + (size_t)j * n;
         CHECK_HIP(precondition<double>(c, vj, zj), "precondition");

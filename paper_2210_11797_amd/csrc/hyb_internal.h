@@ -65,6 +65,12 @@ struct P1State {
   double *kdiag = nullptr;  // [ncell][24] diagonal of K_K
   double *SK = nullptr;     // [ncell][24][24] S_K = C_K [A_K^-1]_ff K_K
   double *bK = nullptr;     // [ncell][24] the cell's share of B_lambda
+  // two-level preconditioner
+  double *dS = nullptr;     // [ntrace] diagonal of S
+  double *zf = nullptr;     // [nz][48] block LU factors of the column systems: Dinv, W, U (4x4 each)
+  double *gamma = nullptr;  // [ncell] Gamma = H 1 / (P^T S P 1)
+  double *den = nullptr;    // [ncell]
+  double *t1 = nullptr, *t2 = nullptr, *t3 = nullptr;  // [ntrace] work vectors
 };
 
 struct ProfFamily {
@@ -123,6 +129,7 @@ struct hyb_ctx {
 
   int order = 0;             // 0: RT0 / Q0 / one trace dof per facet; 1: RT1 / DG1 / 4 per facet
   hyb::P1State p1;
+  hyb_ctx *coarse = nullptr;  // order 1: order-0 context on the same mesh (the DG0 coarse space)
 };
 
 namespace hyb {
@@ -205,9 +212,13 @@ hipError_t p1_factor(hyb_ctx *c);
 // mode 0: the cells' shares of B_lambda into p1.bK; mode 1: recovery into u [36][ncell], pi [8][ncell]
 hipError_t p1_cell_solve(hyb_ctx *c, const double *r_u, const double *r_p, const double *lam, int mode, double *u,
                          double *pi);
-// mode 0: y = S x; mode 1: y = gather of p1.bK (B_lambda)
-hipError_t p1_rows(hyb_ctx *c, const double *x, double *y, int mode);
+// mode 0: y = S x; mode 1: y = gather of p1.bK (B_lambda); mode 2: y = b - S x; mode 3: y = diag(S)
+hipError_t p1_rows(hyb_ctx *c, const double *x, double *y, int mode, const double *b);
+hipError_t p1_precond_setup(hyb_ctx *c);
+hipError_t p1_precondition(hyb_ctx *c, const double *r, double *z);
 void p1_free(hyb_ctx *c);
+// one FP64 pressure multigrid V-cycle on level 0: lv[0].b -> lv[0].x (solve.hip)
+hipError_t coarse_vcycle(hyb_ctx *c);
 
 // ----- learned coarse correction (nn.hip) -----
 int nn_param_count();

@@ -449,7 +449,8 @@ __device__ __forceinline__ int p1_row_cells(size_t T, int nlev, int ncol, int ne
   return n;
 }
 
-// y = S x (mode 0), or the gather of the cells' right-hand-side shares b_K into B (mode 1)
+// mode 0: y = S x; mode 1: the gather of the cells' right-hand-side shares b_K into B; mode 2:
+// y = b - S x; mode 3: y = diag(S)
 __global__ void k_p1_rows(size_t ntr, int nlev, int ncol, int nedge, size_t nz, const int32_t *__restrict__ col_edge,
                           const int32_t *__restrict__ edge_col, const int32_t *__restrict__ edge_lf,
                           const double *__restrict__ SK, const double *__restrict__ x, const double *__restrict__ bK,
@@ -466,12 +467,176 @@ __global__ void k_p1_rows(size_t ntr, int nlev, int ncol, int nedge, size_t nz, 
       s += bK[(size_t)c * NF + r];
       continue;
     }
-    const int k = c / ncol, col = c - k * ncol;
     const double *row = SK + (size_t)c * NS + (size_t)r * NF;
+    if (mode == 3) {
+      s += row[r];
+      continue;
+    }
+    const int k = c / ncol, col = c - k * ncol;
 #pragma unroll 4
     for (int j = 0; j < NF; ++j) s += row[j] * x[p1_dof(j, k, col, ncol, nedge, nz, col_edge)];
   }
-  y[T] = s;
+  y[T] = (mode == 2) ? bK[T] - s : s;  // mode 2 passes b through the bK argument
+}
+
+// ---- two-level preconditioner at order 1 ------------------------------------------------------
+// Per column, the horizontal-facet dofs (4 per facet, facets k = 0..L) form a block-tridiagonal
+// system with 4x4 blocks: facet k couples to itself through the cells below (its T face) and above
+// (its B face), and to facets k -/+ 1 through those cells.  Block LU (Thomas) factors per facet:
+// Dinv_k = (D_k - W_k U_{k-1})^-1, W_k = Lo_k Dinv_{k-1}, and U_k; 48 doubles per facet.
+__device__ __forceinline__ void inv4(const double *a, double *o) {
+  // 4x4 inverse by Gauss-Jordan without pivoting (diagonal blocks of an S^zz that is dominant)
+  double m[4][8];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) m[i][j] = a[4 * i + j], m[i][4 + j] = (i == j) ? 1.0 : 0.0;
+  for (int k = 0; k < 4; ++k) {
+    const double p = 1.0 / m[k][k];
+    for (int j = 0; j < 8; ++j) m[k][j] *= p;
+    for (int i = 0; i < 4; ++i)
+      if (i != k) {
+        const double f = m[i][k];
+        for (int j = 0; j < 8; ++j) m[i][j] -= f * m[k][j];
+      }
+  }
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) o[4 * i + j] = m[i][4 + j];
+}
+
+// block of S_K between local faces fa (rows) and fb (columns)
+__device__ __forceinline__ void sk_block(const double *SK, int c, int fa, int fb, double *o) {
+  const double *b = SK + (size_t)c * NS;
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) o[4 * i + j] = b[(4 * fa + i) * NF + 4 * fb + j];
+}
+
+__global__ void k_p1_zfactor(int nlev, int ncol, const double *__restrict__ SK, double *__restrict__ zf) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= ncol) return;
+  double Dinv[16], Up[16];
+  for (int k = 0; k <= nlev; ++k) {
+    double D[16] = {0}, t[16];
+    if (k > 0) {
+      sk_block(SK, (k - 1) * ncol + col, 5, 5, t);
+      for (int q = 0; q < 16; ++q) D[q] += t[q];
+    }
+    if (k < nlev) {
+      sk_block(SK, k * ncol + col, 4, 4, t);
+      for (int q = 0; q < 16; ++q) D[q] += t[q];
+    }
+    double W[16] = {0};
+    if (k > 0) {
+      double Lo[16];
+      sk_block(SK, (k - 1) * ncol + col, 5, 4, Lo);  // facet k's rows, facet k-1's columns
+      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+          double a = 0.0;
+          for (int m = 0; m < 4; ++m) a += Lo[4 * i + m] * Dinv[4 * m + j];
+          W[4 * i + j] = a;
+        }
+      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+          double a = 0.0;
+          for (int m = 0; m < 4; ++m) a += W[4 * i + m] * Up[4 * m + j];
+          D[4 * i + j] -= a;
+        }
+    }
+    inv4(D, Dinv);
+    if (k < nlev)
+      sk_block(SK, k * ncol + col, 4, 5, Up);  // facet k's rows, facet k+1's columns
+    else
+      for (int q = 0; q < 16; ++q) Up[q] = 0.0;
+    double *o = zf + ((size_t)k * ncol + col) * 48;
+    for (int q = 0; q < 16; ++q) o[q] = Dinv[q], o[16 + q] = W[q], o[32 + q] = Up[q];
+  }
+}
+
+// LineSmooth (Alg. 1) at order 1, given the residual R: horizontal facets by the block-tridiagonal
+// column solve, vertical facets by point Jacobi; lambda_out = lambda_in + omega delta.
+__global__ void k_p1_zsolve(int nlev, int ncol, const double *__restrict__ zf, const double *__restrict__ R,
+                            const double *__restrict__ lin, double *__restrict__ lout, double omega) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= ncol) return;
+  double y[4], prev[4] = {0, 0, 0, 0};
+  for (int k = 0; k <= nlev; ++k) {  // forward: y_k = R_k - W_k y_{k-1}, kept in lout
+    const size_t F = (size_t)k * ncol + col;
+    const double *W = zf + F * 48 + 16;
+    for (int i = 0; i < 4; ++i) {
+      double a = R[4 * F + i];
+      for (int m = 0; m < 4; ++m) a -= W[4 * i + m] * prev[m];
+      y[i] = a;
+    }
+    for (int i = 0; i < 4; ++i) lout[4 * F + i] = prev[i] = y[i];
+  }
+  double next[4] = {0, 0, 0, 0};
+  for (int k = nlev; k >= 0; --k) {  // backward: x_k = Dinv_k (y_k - U_k x_{k+1})
+    const size_t F = (size_t)k * ncol + col;
+    const double *Dinv = zf + F * 48, *Up = zf + F * 48 + 32;
+    double t[4], x[4];
+    for (int i = 0; i < 4; ++i) {
+      double a = lout[4 * F + i];
+      for (int m = 0; m < 4; ++m) a -= Up[4 * i + m] * next[m];
+      t[i] = a;
+    }
+    for (int i = 0; i < 4; ++i) {
+      double a = 0.0;
+      for (int m = 0; m < 4; ++m) a += Dinv[4 * i + m] * t[m];
+      x[i] = a;
+    }
+    for (int i = 0; i < 4; ++i) {
+      next[i] = x[i];
+      lout[4 * F + i] = (lin ? lin[4 * F + i] : 0.0) + omega * x[i];
+    }
+  }
+}
+
+__global__ void k_p1_hjacobi(size_t nz4, size_t ntr, const double *__restrict__ dS, const double *__restrict__ R,
+                             const double *__restrict__ lin, double *__restrict__ lout, double omega) {
+  const size_t T = nz4 + (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (T >= ntr) return;
+  lout[T] = (lin ? lin[T] : 0.0) + omega * R[T] / dS[T];
+}
+
+// Restriction to the DG0 coarse space with scaling: out_c = g_c (P^T r)_c; P sets every dof of a
+// facet to the average of its two cells (to the one cell at ground and lid), so P^T weights the 24
+// dofs of a cell by 1/2, by 1 on ground and lid facets.  g = NULL: no scaling.
+__global__ void k_p1_restrict(int nlev, int ncol, int nedge, size_t nz, const int32_t *__restrict__ col_edge,
+                              const double *__restrict__ r, const double *__restrict__ g, double *__restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nlev * ncol) return;
+  const int k = c / ncol, col = c - k * ncol;
+  double s = 0.0;
+  for (int j = 0; j < NF; ++j) {
+    const int f = j >> 2;
+    const double w = (f == 4 && k == 0) || (f == 5 && k == nlev - 1) ? 1.0 : 0.5;
+    s += w * r[p1_dof(j, k, col, ncol, nedge, nz, col_edge)];
+  }
+  out[c] = g ? g[c] * s : s;
+}
+
+// lambda_T += (P x)_T
+__global__ void k_p1_prolong(size_t ntr, int nlev, int ncol, int nedge, size_t nz, const int32_t *__restrict__ edge_col,
+                             const int32_t *__restrict__ edge_lf, const double *__restrict__ x, double *__restrict__ lam) {
+  const size_t T = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (T >= ntr) return;
+  int cells[2], faces[2];
+  const int n = p1_row_cells(T, nlev, ncol, nedge, nz, edge_col, edge_lf, cells, faces);
+  const double v = n == 1 ? x[cells[0]] : 0.5 * (x[cells[0]] + x[cells[1]]);
+  lam[T] += v;
+}
+
+// Gamma_c = (H 1)_c / (P^T S P 1)_c with the coarse operator H (7-entry stencil rows)
+__global__ void k_p1_gamma(int ncell, const double *__restrict__ H, const double *__restrict__ den,
+                           double *__restrict__ g) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  double h1 = 0.0;
+  for (int s = 0; s < 7; ++s) h1 += H[(size_t)s * ncell + c];
+  g[c] = h1 / den[c];
+}
+
+__global__ void k_p1_fill(double *x, size_t n, double v) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
 }
 
 }  // namespace
@@ -531,18 +696,96 @@ hipError_t p1_cell_solve(hyb_ctx *c, const double *r_u, const double *r_p, const
   return hipGetLastError();
 }
 
-hipError_t p1_rows(hyb_ctx *c, const double *x, double *y, int mode) {
+hipError_t p1_rows(hyb_ctx *c, const double *x, double *y, int mode, const double *b) {
   P1State &s = c->p1;
   const LevelDev &L0 = c->lv[0];
   const size_t ntr = (size_t)c->ntrace;
+  int slot = prof_begin(c, F_TRACE_APPLY);
   hipLaunchKernelGGL(k_p1_rows, dim3(nblk(ntr)), dim3(kBlock), 0, c->stream, ntr, c->nlev, c->ncol, c->nedge,
-                     (size_t)c->nz, L0.col_edge, L0.edge_col, L0.edge_lf, s.SK, x, s.bK, y, mode);
+                     (size_t)c->nz, L0.col_edge, L0.edge_col, L0.edge_lf, s.SK, x, mode == 2 ? b : s.bK, y, mode);
+  prof_end(c, F_TRACE_APPLY, slot);
   return hipGetLastError();
+}
+
+// Setup of the two-level preconditioner at order 1 (after the condensation): diag(S), the block
+// factors of the column systems, and Gamma with the coarse context's H.
+hipError_t p1_precond_setup(hyb_ctx *c) {
+  P1State &s = c->p1;
+  hyb_ctx *cc = c->coarse;
+  const LevelDev &L0 = c->lv[0];
+  const size_t ntr = (size_t)c->ntrace, nc = (size_t)c->ncell;
+  hipError_t e;
+  if ((e = p1_rows(c, nullptr, s.dS, 3, nullptr))) return e;
+  hipLaunchKernelGGL(k_p1_zfactor, dim3(nblk(c->ncol)), dim3(kBlock), 0, c->stream, c->nlev, c->ncol, s.SK, s.zf);
+  if ((e = hipGetLastError())) return e;
+  // P 1 = 1 on every dof; den = P^T S 1
+  hipLaunchKernelGGL(k_p1_fill, dim3(nblk(ntr)), dim3(kBlock), 0, c->stream, s.t1, ntr, 1.0);
+  if ((e = p1_rows(c, s.t1, s.t2, 0, nullptr))) return e;
+  hipLaunchKernelGGL(k_p1_restrict, dim3(nblk(nc)), dim3(kBlock), 0, c->stream, c->nlev, c->ncol, c->nedge,
+                     (size_t)c->nz, L0.col_edge, s.t2, (const double *)nullptr, s.den);
+  hipLaunchKernelGGL(k_p1_gamma, dim3(nblk(nc)), dim3(kBlock), 0, c->stream, c->ncell, cc->lv[0].H, s.den, s.gamma);
+  return hipGetLastError();
+}
+
+// z = M(r): Alg. 2 at order 1 (LineSmooth n_pre sweeps from zero, residual, restriction to DG0 with
+// Gamma, one V-cycle of the coarse context's pressure multigrid, prolongation, n_post sweeps).
+hipError_t p1_precondition(hyb_ctx *c, const double *r, double *z) {
+  P1State &s = c->p1;
+  hyb_ctx *cc = c->coarse;
+  const hyb_params &p = c->p;
+  const LevelDev &L0 = c->lv[0];
+  const size_t ntr = (size_t)c->ntrace, nc = (size_t)c->ncell, nz4 = 4 * (size_t)c->nz;
+  double *lam = s.t1, *tmp = s.t2, *R = s.t3;
+  hipError_t e;
+  auto sweep = [&](const double *lin, double *lout) -> hipError_t {
+    hipError_t q;
+    if (lin) {
+      if ((q = p1_rows(c, lin, R, 2, r))) return q;
+    }
+    const double *res = lin ? R : r;
+    int slot = prof_begin(c, F_THOMAS);
+    hipLaunchKernelGGL(k_p1_zsolve, dim3(nblk(c->ncol, 64)), dim3(64), 0, c->stream, c->nlev, c->ncol, s.zf, res, lin,
+                       lout, p.omega);
+    hipLaunchKernelGGL(k_p1_hjacobi, dim3(nblk(ntr - nz4)), dim3(kBlock), 0, c->stream, nz4, ntr, s.dS, res, lin, lout,
+                       p.omega);
+    prof_end(c, F_THOMAS, slot);
+    return hipGetLastError();
+  };
+  bool have = false;
+  for (int k = 0; k < p.n_pre; ++k) {
+    if ((e = sweep(have ? lam : nullptr, have ? tmp : lam))) return e;
+    if (have) std::swap(lam, tmp);
+    have = true;
+  }
+  if (!have) {
+    hipLaunchKernelGGL(k_p1_fill, dim3(nblk(ntr)), dim3(kBlock), 0, c->stream, lam, ntr, 0.0);
+    if ((e = hipGetLastError())) return e;
+  }
+  if ((e = p1_rows(c, lam, R, 2, r))) return e;
+  int slot = prof_begin(c, F_RESTRICT);
+  hipLaunchKernelGGL(k_p1_restrict, dim3(nblk(nc)), dim3(kBlock), 0, c->stream, c->nlev, c->ncol, c->nedge,
+                     (size_t)c->nz, L0.col_edge, R, s.gamma, (double *)cc->lv[0].b);
+  prof_end(c, F_RESTRICT, slot);
+  if ((e = hipGetLastError())) return e;
+  if ((e = coarse_vcycle(cc))) return e;
+  slot = prof_begin(c, F_PROLONG);
+  hipLaunchKernelGGL(k_p1_prolong, dim3(nblk(ntr)), dim3(kBlock), 0, c->stream, ntr, c->nlev, c->ncol, c->nedge,
+                     (size_t)c->nz, L0.edge_col, L0.edge_lf, (const double *)cc->lv[0].x, lam);
+  prof_end(c, F_PROLONG, slot);
+  if ((e = hipGetLastError())) return e;
+  for (int k = 0; k < p.n_post; ++k) {
+    double *dst = (k == p.n_post - 1) ? z : tmp;
+    if ((e = sweep(lam, dst))) return e;
+    if (dst == tmp) std::swap(lam, tmp);
+  }
+  if (p.n_post <= 0) return hipMemcpyAsync(z, lam, ntr * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+  return hipSuccess;
 }
 
 void p1_free(hyb_ctx *c) {
   P1State &s = c->p1;
-  for (double **q : {&s.tbl, &s.A, &s.cdiag, &s.kdiag, &s.SK, &s.bK})
+  for (double **q : {&s.tbl, &s.A, &s.cdiag, &s.kdiag, &s.SK, &s.bK, &s.dS, &s.zf, &s.gamma, &s.den, &s.t1, &s.t2,
+                     &s.t3})
     if (*q) (void)hipFree(*q), *q = nullptr;
 }
 

@@ -579,4 +579,7 @@ hipError_t launch_thomas_factor(hyb_ctx *c) {
   return hipGetLastError();
 }
 
+// FP64 V-cycle on level 0 (lv[0].b -> lv[0].x), for a context used as another's coarse space
+hipError_t coarse_vcycle(hyb_ctx *c) { return vcycle<double>(c, 0); }
+
 }  // namespace hyb

@@ -232,7 +232,20 @@ def p1_sequence(lib):
     uref, pref = h.recover(x, r_u.T.copy(), r_p.T.copy())
     check(np.abs(u.T - uref).max() <= 1e-10 * np.abs(uref).max() and np.abs(pi.T - pref).max() <= 1e-10 * np.abs(pref).max(),
           "order 1: recovery matches the oracle")
-    check(lib.hyb_precondition(c.h, P(b), P(y)) < 0, "order 1: calls it does not provide are rejected")
+    # the two-level preconditioner and the solve against the oracle's
+    from oracle.problem import OracleProblem
+
+    tl = op1.TwoLevelP1(mesh, h.S, OracleProblem(prob).H, mg_levels=1)
+    z = np.empty(c.ntrace)
+    c.call("hyb_precondition", P(b), P(z))
+    zref = tl(b)
+    check(np.abs(z - zref).max() <= 1e-9 * np.abs(zref).max(), "order 1: preconditioner matches the oracle")
+    rc, info, lam = c.solve(b, 1e-12)
+    lref = op1.spla.splu(h.S.tocsc()).solve(b)
+    check(rc == 0 and np.abs(lam - lref).max() <= 1e-9 * np.abs(lref).max(),
+          f"order 1: FGMRES solve matches the direct solution ({info.iters} iterations)")
+    cells = np.empty(c.ncell)
+    check(lib.hyb_restrict(c.h, P(b), P(cells), 0) < 0, "order 1: calls it does not provide are rejected")
     c.close()
     # S_K condensed on matrix cores (FP32, and BF16 split into hi + lo) against the FP64 operator
     for prec, tol in ((N.PREC_MFMA_FP32, 1e-5), (N.PREC_MFMA_BF16X, 1e-4)):

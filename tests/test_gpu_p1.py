@@ -144,3 +144,46 @@ def test_p1_mfma_condensation_error_vs_fp64(size):
     ebf = rel_max(out[PREC_MFMA_BF16X], out[PREC_FP64])
     say(f"[p1] {size}: S x error vs FP64 condensation: FP32 MFMA {e32:.1e}, BF16 split MFMA {ebf:.1e}")
     assert e32 <= 1e-5 and ebf <= 1e-4
+
+
+PRECOND_CASES = {
+    "4x4x4": dict(nx=4, ny=4, nlev=4, dx=5e3, dz=250.0, perturb=0.05, mg_levels=2),
+    "8x6x5": dict(nx=8, ny=6, nlev=5, dx=5e3, dz=250.0, perturb=0.1, mg_levels=2),
+    "stretched": dict(nx=8, ny=8, nlev=9, dx=10e3, ztop=16e3, stretch="quadratic", mg_levels=3),
+}
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("case", list(PRECOND_CASES))
+def test_p1_precondition_and_solve_match_oracle(case):
+    """The order-1 two-level preconditioner against the oracle's (a fixed linear map of ~50 column
+    solves and a V-cycle: compared to 1e-9), and FGMRES to rtol 1e-12 against the direct solution
+    (1e-9), with the oracle's FGMRES iteration count (+-1)."""
+    import torch
+    import scipy.sparse.linalg as spla
+
+    from oracle.krylov import fgmres
+    from oracle.problem import OracleProblem
+
+    prob = make_box(**PRECOND_CASES[case])
+    say(f"[p1] precondition/solve case {case}")
+    s = make_p1_solver(prob)
+    mesh = BoxMesh(prob.nx, prob.ny, prob.nlev, prob.dx, prob.dy, prob.z)
+    h = op1.HybridP1(mesh, op1.local_matrices(mesh, prob))
+    tl = op1.TwoLevelP1(mesh, h.S, OracleProblem(prob).H, mg_levels=len(prob.levels))
+    r_u, r_p = make_rhs_p1(prob, 5)
+    B = h.rhs(r_u.reshape(36, -1).T.copy(), r_p.reshape(8, -1).T.copy())
+    z = torch.empty(s.ntrace, dtype=torch.float64, device="cuda")
+    s.precondition(dev(B), z)
+    zref = tl(B)
+    e_m = rel_max(host(z), zref)
+    b = torch.empty_like(z)
+    s.condense(dev(r_u), dev(r_p), b)
+    lam = torch.zeros_like(z)
+    info = s.solve(b, lam, rtol=1e-12, maxit=500)
+    lref = spla.splu(h.S.tocsc()).solve(B)
+    e_l = rel_max(host(lam), lref)
+    its_ref = fgmres(lambda v: h.S @ v, tl, B, rtol=1e-12, restart=30, maxit=500)[2]
+    say(f"[p1] {case}: M(B) {e_m:.1e}; solve {info['iters']} its (oracle {its_ref}), lambda {e_l:.1e}")
+    assert e_m <= 1e-9
+    assert info["status"] == 0 and e_l <= 1e-9 and abs(info["iters"] - its_ref) <= 1
