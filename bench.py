@@ -26,6 +26,10 @@ if ROOT not in sys.path:
 PEAK_HBM_GBS = 8000.0
 FAMILIES = ("smooth_rows", "smooth_rows0", "thomas", "trace_apply", "mg_smooth", "restrict", "prolong", "krylov",
             "cell_solve", "nn")
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
+# algorithmic flops of the order-1 condensation per cell: elimination of the 44 x 44 block without
+# pivoting (2/3 n^3) and of its 24 right-hand sides (forward and back substitution, 2 n^2 each)
+P1_CONDENSE_FLOPS = 2.0 / 3.0 * 44**3 + 2 * 44**2 * 24
 
 
 def log(*a):
@@ -202,6 +206,84 @@ def learned_leg(args, prob, s, rhs, sec_plain, dx, dz, dt):
                               batch=8, final_energy_loss=float(np.mean(hist[-50:])), seconds=train_s))
 
 
+def p1_leg(args):
+    """Order 1 (RT1 / DG1 / Q1 trace, 44 x 44 cell blocks) on the 128 x 128 x 32 box (dx = 10 km,
+    dz = 500 m): the condensation in FP64 and on MFMA (FP32, BF16 split), and time-to-1e-8 of FGMRES
+    with the order-1 two-level preconditioner for each condensed operator."""
+    import numpy as np
+    import torch
+
+    from paper_2210_11797_amd import HybSolver, Params, PREC_FP64, PREC_MFMA_BF16X, PREC_MFMA_FP32, levels_of
+    from synth import make_box, make_rhs_p1
+
+    prob = make_box(nx=args.p1_nx, ny=args.p1_nx, nlev=args.p1_nlev, dx=10e3, dz=500.0, dt=600.0, mg_levels=4)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()  # noqa: E731
+    rhs = [tuple(d(a) for a in make_rhs_p1(prob, sd)) for sd in range(3)]
+    x = d(np.random.default_rng(0).standard_normal(4 * (prob.ncol * (prob.nlev + 1) + 2 * prob.ncol * prob.nlev)))
+    out, y64 = {}, None
+    for name, prec, dtype in (("fp64", PREC_FP64, "fp64"), ("mfma_fp32", PREC_MFMA_FP32, "fp32"),
+                              ("mfma_bf16x", PREC_MFMA_BF16X, "bf16")):
+        params = Params(dt=prob.dt, tau_u=prob.tau_u, tau_rho=prob.tau_rho, tau_theta=prob.tau_theta, cp=prob.cp,
+                        rd=prob.rd, precision=prec, mg_coarse_sweeps=args.coarse_sweeps)
+        s = HybSolver(prob.nlev, levels_of(prob), prob.dx, prob.dy, prob.dz, params, order=1)
+        s.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.assemble_local(d(prob.theta_w), d(prob.exner_hat_w), d(prob.exner_c), d(prob.rho_c))
+        s.condense()
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - t0
+        ncond, cond_ms = s.profile_read("p1_condense")
+        nfac, fac_ms = s.profile_read("p1_factor")
+        s.profile(False)
+        y = torch.empty(s.ntrace, dtype=torch.float64, device="cuda")
+        s.trace_apply(x, y)
+        if y64 is None:
+            y64 = y.clone()
+        err = float((y - y64).abs().max() / y64.abs().max())
+        b = torch.empty_like(y)
+        lam = torch.empty_like(y)
+        u = torch.empty(36 * s.ncell, dtype=torch.float64, device="cuda")
+        pi = torch.empty(8 * s.ncell, dtype=torch.float64, device="cuda")
+        its, res = [], []
+
+        def step(i):
+            r_u, r_p = rhs[i % len(rhs)]
+            s.condense(r_u, r_p, b)
+            lam.zero_()
+            info = s.solve(b, lam, rtol=args.rtol, maxit=500)
+            s.recover(r_u, r_p, lam, u, pi)
+            return info
+
+        step(0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(3):
+            info = step(i)
+            its.append(info["iters"])
+            res.append(info["rel_res"])
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / 3
+        kern_ms = cond_ms if ncond else fac_ms
+        flops = P1_CONDENSE_FLOPS * s.ncell
+        achieved = flops / (kern_ms * 1e-3) / 1e12
+        out[name] = dict(sec_per_solve=sec, iters=its, rel_res=max(res), setup_s=setup, condense_kernel_ms=kern_ms,
+                         fp64_factor_ms=fac_ms, s_x_error_vs_fp64=err,
+                         roofline={"bound": "mfma" if ncond else "alu", "achieved": achieved,
+                                   "peak": PEAK_TFLOPS[dtype], "unit": "TFLOP/s",
+                                   "frac": achieved / PEAK_TFLOPS[dtype],
+                                   "kernel": "k_p1_condense_mfma" if ncond else "k_p1_factor"})
+        log(f"p1 {name}: condense kernel {kern_ms:.2f} ms ({achieved:.2f} TFLOP/s), fp64 factor {fac_ms:.2f} ms, "
+            f"solve {sec * 1e3:.1f} ms, iters {its}, S x error vs fp64 {err:.1e}")
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    return dict(workload=f"periodic box {args.p1_nx}x{args.p1_nx}x{args.p1_nlev}, dx=10km, dz=500m, RT1/DG1/Q1 "
+                         f"trace (44x44 cell blocks), FGMRES(30)+two-level (DG0 coarse space), rtol {args.rtol}",
+                ncell=prob.ncell, ntrace=4 * (prob.ncol * (prob.nlev + 1) + 2 * prob.ncol * prob.nlev),
+                condense_flops_per_cell=P1_CONDENSE_FLOPS, modes=out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -213,6 +295,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-p1", action="store_true")
+    ap.add_argument("--p1-nx", type=int, default=128)
+    ap.add_argument("--p1-nlev", type=int, default=32)
     ap.add_argument("--train-nx", type=int, default=64, help="box on which the learned stage is trained")
     ap.add_argument("--train-steps", type=int, default=1500)
     ap.add_argument("--coarse-sweeps", type=int, default=30)
@@ -274,6 +359,13 @@ def main():
     if not args.no_learned:
         learned_out = learned_leg(args, prob, s, rhs, sec, dx, dz, dt)
 
+    p1_out = None
+    if not args.no_p1:
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+        p1_out = p1_leg(args)
+
     cpu = None
     if not args.no_cpu_baseline:
         nxs = 64
@@ -315,6 +407,7 @@ def main():
         "kernel_ms": {k: {"launches": v[0], "total_ms": v[1]} for k, v in fams.items()},
         "mixed": mixed,
         "learned": learned_out,
+        "p1": p1_out,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

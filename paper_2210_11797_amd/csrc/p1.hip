@@ -669,17 +669,19 @@ hipError_t p1_assemble(hyb_ctx *c, const double *theta_w, const double *exner_ha
 hipError_t p1_factor(hyb_ctx *c) {
   P1State &s = c->p1;
   const int prec = c->p.precision;
-  int slot = prof_begin(c, F_P1_CONDENSE);
-  if (prec == HYB_PREC_MFMA_FP32)
-    hipLaunchKernelGGL((k_p1_condense_mfma<false>), dim3(nblk(c->ncell, kMW)), dim3(64 * kMW), 0, c->stream, c->ncell,
-                       s.A, s.cdiag, s.kdiag, s.SK);
-  else if (prec == HYB_PREC_MFMA_BF16X)
-    hipLaunchKernelGGL((k_p1_condense_mfma<true>), dim3(nblk(c->ncell, kMW)), dim3(64 * kMW), 0, c->stream, c->ncell,
-                       s.A, s.cdiag, s.kdiag, s.SK);
-  prof_end(c, F_P1_CONDENSE, slot);
-  hipError_t e = hipGetLastError();
-  if (e) return e;
-  slot = prof_begin(c, F_P1_FACTOR);
+  if (prec == HYB_PREC_MFMA_FP32 || prec == HYB_PREC_MFMA_BF16X) {
+    const int slot = prof_begin(c, F_P1_CONDENSE);
+    if (prec == HYB_PREC_MFMA_FP32)
+      hipLaunchKernelGGL((k_p1_condense_mfma<false>), dim3(nblk(c->ncell, kMW)), dim3(64 * kMW), 0, c->stream,
+                         c->ncell, s.A, s.cdiag, s.kdiag, s.SK);
+    else
+      hipLaunchKernelGGL((k_p1_condense_mfma<true>), dim3(nblk(c->ncell, kMW)), dim3(64 * kMW), 0, c->stream,
+                         c->ncell, s.A, s.cdiag, s.kdiag, s.SK);
+    prof_end(c, F_P1_CONDENSE, slot);
+    hipError_t e = hipGetLastError();
+    if (e) return e;
+  }
+  const int slot = prof_begin(c, F_P1_FACTOR);
   hipLaunchKernelGGL(k_p1_factor, dim3(nblk(c->ncell, kP1Waves)), dim3(64 * kP1Waves), 0, c->stream, c->ncell, s.A,
                      s.cdiag, s.kdiag, s.SK, prec == HYB_PREC_FP64 ? 1 : 0);
   prof_end(c, F_P1_FACTOR, slot);
