@@ -63,7 +63,7 @@ struct P1State {
   double *A = nullptr;      // [ncell][44][44] A_K, then its LU factors (unit lower, no pivoting)
   double *cdiag = nullptr;  // [ncell][24] diagonal of C_K on the face dofs
   double *kdiag = nullptr;  // [ncell][24] diagonal of K_K
-  double *SK = nullptr;     // [ncell][24][24] S_K = C_K [A_K^-1]_ff K_K
+  double *SK = nullptr;     // [24 x 24][ncell] S_K = C_K [A_K^-1]_ff K_K, entry (r, j) at (r * 24 + j) * ncell
   double *bK = nullptr;     // [ncell][24] the cell's share of B_lambda
   // two-level preconditioner
   double *dS = nullptr;     // [ntrace] diagonal of S

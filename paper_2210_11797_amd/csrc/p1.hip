@@ -9,7 +9,8 @@
 // integrals of products of the reference basis functions, computed once on the host with exact
 // Gauss rules -- by per-cell scalars.  Cell data are stored per cell (array of structures): one
 // wavefront owns one cell in the assembly, the factorisation and the cell solves, and reads or
-// writes its 44 x 44 block contiguously.
+// writes its 44 x 44 block contiguously.  The condensed blocks S_K are stored entry by entry over
+// the cells ([24 x 24][ncell]): the trace rows of consecutive cells then read consecutive addresses.
 //
 // Dof order per cell: velocity face dofs 4 f + i (f = W, E, S, N, B, T; face point i = 2 t1 + t2
 // in the face's tangential coordinates (y, z), (x, z) or (x, y)), velocity interior dofs
@@ -244,7 +245,7 @@ __global__ void __launch_bounds__(64 * kP1Waves) k_p1_factor(int ncell, double *
     if (write_sk)
       for (int e = lane; e < NS; e += 64) {
         const int r = e / NF, s = e - r * NF;
-        SK[(size_t)c * NS + e] = cdiag[(size_t)c * NF + r] * x[r * NF + s];
+        SK[(size_t)e * ncell + c] = cdiag[(size_t)c * NF + r] * x[r * NF + s];
       }
   }
 }
@@ -366,7 +367,7 @@ __global__ void __launch_bounds__(64 * kMW) k_p1_condense_mfma(int ncell, const 
   if (active)
     for (int e = lane; e < NS; e += 64) {
       const int r = e / NF, q = e - r * NF;
-      SK[(size_t)c * NS + e] = cdiag[(size_t)c * NF + r] * (double)M[r * LDM + MP + q];
+      SK[(size_t)e * ncell + c] = cdiag[(size_t)c * NF + r] * (double)M[r * LDM + MP + q];
     }
 }
 
@@ -467,14 +468,15 @@ __global__ void k_p1_rows(size_t ntr, int nlev, int ncol, int nedge, size_t nz, 
       s += bK[(size_t)c * NF + r];
       continue;
     }
-    const double *row = SK + (size_t)c * NS + (size_t)r * NF;
+    const size_t ncell = (size_t)nlev * ncol;
+    const double *row = SK + (size_t)r * NF * ncell + c;  // entry (r, j) of cell c at row[j * ncell]
     if (mode == 3) {
-      s += row[r];
+      s += row[(size_t)r * ncell];
       continue;
     }
     const int k = c / ncol, col = c - k * ncol;
 #pragma unroll 4
-    for (int j = 0; j < NF; ++j) s += row[j] * x[p1_dof(j, k, col, ncol, nedge, nz, col_edge)];
+    for (int j = 0; j < NF; ++j) s += row[(size_t)j * ncell] * x[p1_dof(j, k, col, ncol, nedge, nz, col_edge)];
   }
   y[T] = (mode == 2) ? bK[T] - s : s;  // mode 2 passes b through the bK argument
 }
@@ -503,30 +505,30 @@ __device__ __forceinline__ void inv4(const double *a, double *o) {
 }
 
 // block of S_K between local faces fa (rows) and fb (columns)
-__device__ __forceinline__ void sk_block(const double *SK, int c, int fa, int fb, double *o) {
-  const double *b = SK + (size_t)c * NS;
+__device__ __forceinline__ void sk_block(const double *SK, size_t ncell, int c, int fa, int fb, double *o) {
   for (int i = 0; i < 4; ++i)
-    for (int j = 0; j < 4; ++j) o[4 * i + j] = b[(4 * fa + i) * NF + 4 * fb + j];
+    for (int j = 0; j < 4; ++j) o[4 * i + j] = SK[(size_t)((4 * fa + i) * NF + 4 * fb + j) * ncell + c];
 }
 
 __global__ void k_p1_zfactor(int nlev, int ncol, const double *__restrict__ SK, double *__restrict__ zf) {
   const int col = blockIdx.x * blockDim.x + threadIdx.x;
   if (col >= ncol) return;
+  const size_t ncell = (size_t)nlev * ncol;
   double Dinv[16], Up[16];
   for (int k = 0; k <= nlev; ++k) {
     double D[16] = {0}, t[16];
     if (k > 0) {
-      sk_block(SK, (k - 1) * ncol + col, 5, 5, t);
+      sk_block(SK, ncell, (k - 1) * ncol + col, 5, 5, t);
       for (int q = 0; q < 16; ++q) D[q] += t[q];
     }
     if (k < nlev) {
-      sk_block(SK, k * ncol + col, 4, 4, t);
+      sk_block(SK, ncell, k * ncol + col, 4, 4, t);
       for (int q = 0; q < 16; ++q) D[q] += t[q];
     }
     double W[16] = {0};
     if (k > 0) {
       double Lo[16];
-      sk_block(SK, (k - 1) * ncol + col, 5, 4, Lo);  // facet k's rows, facet k-1's columns
+      sk_block(SK, ncell, (k - 1) * ncol + col, 5, 4, Lo);  // facet k's rows, facet k-1's columns
       for (int i = 0; i < 4; ++i)
         for (int j = 0; j < 4; ++j) {
           double a = 0.0;
@@ -542,7 +544,7 @@ __global__ void k_p1_zfactor(int nlev, int ncol, const double *__restrict__ SK, 
     }
     inv4(D, Dinv);
     if (k < nlev)
-      sk_block(SK, k * ncol + col, 4, 5, Up);  // facet k's rows, facet k+1's columns
+      sk_block(SK, ncell, k * ncol + col, 4, 5, Up);  // facet k's rows, facet k+1's columns
     else
       for (int q = 0; q < 16; ++q) Up[q] = 0.0;
     double *o = zf + ((size_t)k * ncol + col) * 48;
