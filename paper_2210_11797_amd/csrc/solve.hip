@@ -400,6 +400,64 @@ hipError_t line_smooth(hyb_ctx *c, const T *S, const T *B, const T *lin, T *lout
   return hipGetLastError();
 }
 
+constexpr int kPcrMaxColumns = 4096;
+
+// One block-Jacobi sweep of the pressure multigrid, fused: x_out = base + omega H_z^-1 (b - H X) with
+// X = 0 (MODE 0), xin (MODE 1) or xin plus the injected coarse correction xc[parent] (MODE 2), base = X.
+// One wavefront per column, lane k = level k (nlev <= 64): the vertical neighbours of the residual
+// come from the adjacent lanes, and the tridiagonal column system (entries below / diagonal / above
+// = H slots 5, 0, 6) is solved by parallel cyclic reduction: at stride s every row eliminates its
+// couplings to rows k -/+ s, so after ceil(log2 nlev) steps it is diagonal.  Lanes k >= nlev carry
+// the identity row.
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kBlock) k_mg_sweep_pcr(const T *__restrict__ H, const T *__restrict__ b,
+                                                        const T *__restrict__ xin, const T *__restrict__ xc,
+                                                        T *__restrict__ xout, int nlev, int ncol, int ncolc,
+                                                        const int32_t *__restrict__ nbr,
+                                                        const int32_t *__restrict__ parent, T omega) {
+  const int k = threadIdx.x & 63;
+  const int col = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (col >= ncol) return;  // the whole wavefront
+  const bool on = k < nlev;
+  const size_t n = (size_t)nlev * ncol, c = (size_t)k * ncol + col;
+  auto X = [&](int cc) -> T {
+    T v = xin[(size_t)k * ncol + cc];
+    if (MODE == 2) v += xc[(size_t)k * ncolc + parent[cc]];
+    return v;
+  };
+  T am = 0, bm = 1, cm = 0, dm = 0, xk = 0;
+  if (on) {
+    am = k > 0 ? H[5 * n + c] : T(0);
+    bm = H[c];
+    cm = k < nlev - 1 ? H[6 * n + c] : T(0);
+    dm = b[c];
+    if (MODE != 0) {
+      xk = X(col);
+      T hx = bm * xk;
+#pragma unroll
+      for (int f = 0; f < 4; ++f) hx += H[(1 + f) * n + c] * X(nbr[(size_t)f * ncol + col]);
+      dm -= hx;
+    }
+  }
+  if (MODE != 0) {
+    const T xdn = __shfl_up(xk, 1, 64), xup = __shfl_down(xk, 1, 64);
+    if (on) dm -= am * xdn + cm * xup;  // am = 0 at the ground, cm = 0 at the lid
+  }
+  for (int st = 1; st < nlev; st <<= 1) {
+    const T a1 = __shfl_up(am, st, 64), b1 = __shfl_up(bm, st, 64), c1 = __shfl_up(cm, st, 64),
+            d1 = __shfl_up(dm, st, 64);
+    const T a2 = __shfl_down(am, st, 64), b2 = __shfl_down(bm, st, 64), c2 = __shfl_down(cm, st, 64),
+            d2 = __shfl_down(dm, st, 64);
+    const bool lo = k >= st, hi = k + st < nlev;
+    const T al = (on && lo) ? -am / b1 : T(0), ga = (on && hi) ? -cm / b2 : T(0);
+    const T an = lo ? al * a1 : T(0), cn = hi ? ga * c2 : T(0);
+    const T bn = bm + (lo ? al * c1 : T(0)) + (hi ? ga * a2 : T(0));
+    const T dn = dm + (lo ? al * d1 : T(0)) + (hi ? ga * d2 : T(0));
+    if (on) am = an, bm = bn, cm = cn, dm = dn;
+  }
+  if (on) xout[c] = (MODE == 0 ? T(0) : xk) + omega * (dm / bm);
+}
+
 template <typename T>
 hipError_t mg_smooth(hyb_ctx *c, int l, const T *b, const T *xin, const T *xc, T *xout, int mode) {
   const LevelDev &Lv = c->lv[l];
@@ -412,7 +470,21 @@ hipError_t mg_smooth(hyb_ctx *c, int l, const T *b, const T *xin, const T *xc, T
   T om = (T)c->p.omega_p;
   dim3 gc(nblk(Lv.ncol, kColBlock)), bc(kColBlock), gr(nblk(n)), br(kBlock);
   int slot = prof_begin(c, F_MG_SMOOTH);
-  if (mode == 0) {
+  // the fused sweep with cyclic reduction pays on small levels, where the Thomas recurrence of the
+  // two-kernel path is latency bound (1024 columns: 5.9 us against 4.4 + 12.1 us); on large levels
+  // its shuffles and divisions make it compute bound (65536 columns: 305 us against 69 + 35 us)
+  if (c->nlev <= 64 && Lv.ncol <= kPcrMaxColumns) {
+    const dim3 gw(nblk(Lv.ncol, kBlock / 64)), bw(kBlock);
+    if (mode == 0)
+      hipLaunchKernelGGL((k_mg_sweep_pcr<T, 0>), gw, bw, 0, c->stream, H, b, xin, xc, xout, c->nlev, Lv.ncol, ncolc,
+                         Lv.nbr, Lv.parent, om);
+    else if (mode == 1)
+      hipLaunchKernelGGL((k_mg_sweep_pcr<T, 1>), gw, bw, 0, c->stream, H, b, xin, xc, xout, c->nlev, Lv.ncol, ncolc,
+                         Lv.nbr, Lv.parent, om);
+    else
+      hipLaunchKernelGGL((k_mg_sweep_pcr<T, 2>), gw, bw, 0, c->stream, H, b, xin, xc, xout, c->nlev, Lv.ncol, ncolc,
+                         Lv.nbr, Lv.parent, om);
+  } else if (mode == 0) {
     hipLaunchKernelGGL((k_column_solve<T, true, false>), gc, bc, shm, c->stream, b, fac, n, xin, xc, xout, c->nlev,
                        Lv.ncol, ncolc, Lv.parent, om);
   } else if (mode == 1) {

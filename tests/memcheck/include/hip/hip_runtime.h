@@ -65,6 +65,19 @@ inline T __shfl_down(T v, unsigned off, int width = 64) {
   return r;
 }
 
+template <typename T>
+inline T __shfl_up(T v, unsigned off, int width = 64) {
+  static_assert(sizeof(T) <= 8, "shfl of a large type");
+  const unsigned tid = emu::cur_tid();
+  std::memcpy(emu::xchg(tid), &v, sizeof(T));
+  emu::wave_barrier();
+  unsigned lane = tid % (unsigned)width;
+  T r = v;
+  if (lane >= off) std::memcpy(&r, emu::xchg(tid - off), sizeof(T));
+  emu::wave_barrier();
+  return r;
+}
+
 // Matrix-core instructions used by the library, with their lane layouts (wavefront of 64):
 // f32 16x16x4: a = A[l%16][l/16], b = B[l/16][l%16]; bf16 16x16x16: a[j] = A[l%16][4(l/16)+j],
 // b[j] = B[4(l/16)+j][l%16]; result d[j] = D[4(l/16)+j][l%16].

@@ -133,6 +133,11 @@ def solver_sequence(lib):
                 "krylov", "cell_solve", "nn"):
         c.call("hyb_profile_read", fam.encode(), ctypes.byref(n), ctypes.byref(ms))
     c.call("hyb_profile", 0)
+    c2 = Ctx(lib, make_box(nx=4, ny=4, nlev=66, dx=5e3, dz=150.0, mg_levels=2, seed=8))  # nlev > 64: Thomas path
+    _, _, b2 = c2.rhs(3)
+    rc2, info2, lam2 = c2.solve(b2, 1e-10)
+    check(rc2 == 0 and c2.residual(b2, lam2) <= 1.01e-10, f"66 levels (two-kernel smoother): {info2.iters} iterations")
+    c2.close()
     # argument errors come back as codes
     check(lib.hyb_restrict(c.h, P(b), P(cells), 4) < 0 and lib.hyb_restrict(c.h, P(b), P(cells), -1) < 0,
           "bad restriction modes rejected")
