@@ -48,6 +48,7 @@ struct NNState {
   float *part = nullptr, *tmpg = nullptr, *lpart = nullptr;       // reduction scratch
   float *cin = nullptr, *cout = nullptr;                          // learned stage input / output [ncell]
   double *scal = nullptr;                                         // learned stage scalars (device)
+  uint16_t *a1h = nullptr, *a2h = nullptr;                        // stage activations [ncell][16] BF16
   double *d64 = nullptr, *sd64 = nullptr;                         // correction d and S d [ntrace]
   double *gq = nullptr, *epart = nullptr;                         // energy loss: G q [nsamp][ncell], partials
   size_t gq_cap = 0;

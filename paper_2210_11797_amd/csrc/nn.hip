@@ -15,6 +15,7 @@ namespace hyb {
 namespace {
 
 constexpr int NHT = 9, NVT = 5, NTAP = NHT * NVT;
+constexpr int C1 = 16;  // hidden channels (the inference kernels are written for 16)
 // opposite horizontal direction of each tap (centre, W, E, S, N, SW, SE, NW, NE)
 __constant__ int kOpp[NHT] = {0, 2, 1, 4, 3, 8, 7, 6, 5};
 
@@ -397,6 +398,116 @@ __global__ void __launch_bounds__(kBlock) k_energy(const float *__restrict__ y, 
   }
 }
 
+// ---- inference path of the stage (one sample): BF16 activations on matrix cores -------------------
+// a1 = bf16(relu(conv1(x))) by the lanes (FP32 accumulation), a2 = bf16(relu(conv2(a1))) as an implicit
+// GEMM on BF16 MFMA (FP32 accumulation): for 16 cells and one tap, A = a1 of the 16 tapped cells x 16
+// input channels, B = W2[:, :, tap]^T (16 x 16), 45 taps accumulate into the 16 cells x 16 outputs;
+// y = conv3(a2) by the lanes.  Activations are stored per cell, 16 BF16 channels contiguous.
+typedef float nn_f32x4 __attribute__((ext_vector_type(4)));
+typedef short nn_bf16x4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(kBlock) k_inf_layer1(const float *__restrict__ x, const uint16_t *__restrict__ wb,
+                                                      const float *__restrict__ bias, uint16_t *__restrict__ a1,
+                                                      int nlev, int ncol, const int32_t *__restrict__ nb9) {
+  __shared__ float w[C1 * NTAP];
+  for (int i = threadIdx.x; i < C1 * NTAP; i += blockDim.x) w[i] = bf2f(wb[i]);
+  __syncthreads();
+  const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= nlev * ncol) return;
+  const int k = cell / ncol, col = cell - k * ncol;
+  float acc[C1];
+#pragma unroll
+  for (int co = 0; co < C1; ++co) acc[co] = bias[co];
+  for (int h = 0; h < NHT; ++h) {
+    const int c2 = nb9[(size_t)h * ncol + col];
+#pragma unroll
+    for (int v = 0; v < NVT; ++v) {
+      const int kk = k + v - 2;
+      if (kk < 0 || kk >= nlev) continue;
+      const float xv = x[(size_t)kk * ncol + c2];
+#pragma unroll
+      for (int co = 0; co < C1; ++co) acc[co] += w[co * NTAP + h * NVT + v] * xv;
+    }
+  }
+#pragma unroll
+  for (int co = 0; co < C1; ++co) a1[(size_t)cell * C1 + co] = f2bf(fmaxf(acc[co], 0.f));
+}
+
+constexpr int kInfTiles = 8;  // 16-cell tiles per wavefront
+__global__ void __launch_bounds__(kBlock) k_inf_layer2_mfma(const uint16_t *__restrict__ a1,
+                                                           const uint16_t *__restrict__ wb2,
+                                                           const float *__restrict__ bias, uint16_t *__restrict__ a2,
+                                                           int nlev, int ncol, const int32_t *__restrict__ nb9) {
+  const int lane = threadIdx.x & 63;
+  const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int ncell = nlev * ncol;
+  const int r = lane & 15, q = lane >> 4;  // operand row / k-quarter
+  // B operands of all taps: lane holds W2[co = r][ci = 4 q + j][t], j = 0..3
+  nn_bf16x4 B[NTAP];
+#pragma unroll
+  for (int t = 0; t < NTAP; ++t)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) B[t][j] = (short)wb2[(r * C1 + 4 * q + j) * NTAP + t];
+  const float bco = bias[r];
+  for (int tile = 0; tile < kInfTiles; ++tile) {
+    const int base = (wave * kInfTiles + tile) * 16;
+    if (base >= ncell) break;  // uniform over the wavefront
+    const int cell = base + r;  // the cell whose tapped values this lane loads
+    const bool live = cell < ncell;
+    const int k = live ? cell / ncol : 0, col = live ? cell - k * ncol : 0;
+    nn_f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int h = 0; h < NHT; ++h) {
+      const int c2 = live ? nb9[(size_t)h * ncol + col] : 0;
+#pragma unroll
+      for (int v = 0; v < NVT; ++v) {
+        const int kk = k + v - 2;
+        nn_bf16x4 A = {0, 0, 0, 0};
+        if (live && kk >= 0 && kk < nlev) {
+          const uint2 u = *reinterpret_cast<const uint2 *>(a1 + ((size_t)kk * ncol + c2) * C1 + 4 * q);
+          A[0] = (short)(u.x & 0xFFFFu), A[1] = (short)(u.x >> 16), A[2] = (short)(u.y & 0xFFFFu), A[3] = (short)(u.y >> 16);
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, B[h * NVT + v], acc, 0, 0, 0);
+      }
+    }
+    // acc[j] = output channel r of cell base + 4 q + j
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int oc = base + 4 * q + j;
+      if (oc < ncell) a2[(size_t)oc * C1 + r] = f2bf(fmaxf(acc[j] + bco, 0.f));
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_inf_layer3(const uint16_t *__restrict__ a2, const uint16_t *__restrict__ wb3,
+                                                      const float *__restrict__ bias, float *__restrict__ y, int nlev,
+                                                      int ncol, const int32_t *__restrict__ nb9) {
+  __shared__ float w[C1 * NTAP];
+  for (int i = threadIdx.x; i < C1 * NTAP; i += blockDim.x) w[i] = bf2f(wb3[i]);
+  __syncthreads();
+  const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= nlev * ncol) return;
+  const int k = cell / ncol, col = cell - k * ncol;
+  float acc = bias[0];
+  for (int h = 0; h < NHT; ++h) {
+    const int c2 = nb9[(size_t)h * ncol + col];
+#pragma unroll
+    for (int v = 0; v < NVT; ++v) {
+      const int kk = k + v - 2;
+      if (kk < 0 || kk >= nlev) continue;
+      const uint4 *src = reinterpret_cast<const uint4 *>(a2 + ((size_t)kk * ncol + c2) * C1);
+      const uint4 u0 = src[0], u1 = src[1];
+      const uint32_t words[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+#pragma unroll
+      for (int ci = 0; ci < C1; ++ci) {
+        const uint16_t hv = (uint16_t)((ci & 1) ? (words[ci >> 1] >> 16) : (words[ci >> 1] & 0xFFFFu));
+        acc += w[ci * NTAP + h * NVT + v] * bf2f(hv);
+      }
+    }
+  }
+  y[cell] = acc;
+}
+
 __global__ void k_zero_scal(double *p, int n) {
   if (threadIdx.x < n) p[threadIdx.x] = 0.0;
 }
@@ -512,6 +623,27 @@ hipError_t nn_forward(hyb_ctx *c, const float *x, float *out, int nsamp) {
                      s.nb9);
   hipLaunchKernelGGL((k_conv_fwd<C, 1, false>), g, b, 0, c->stream, s.a2, s.wb + W1N + W2N, s.w + OFF_B3, out, L, nc,
                      nsamp, s.nb9);
+  return hipGetLastError();
+}
+
+// Forward pass of one field for the stage inside the solve: BF16 activations, middle layer on MFMA.
+static hipError_t nn_forward_inference(hyb_ctx *c, const float *x, float *out) {
+  NNState &s = c->nn;
+  static_assert(C == C1, "the inference kernels are written for 16 hidden channels");
+  const size_t n = (size_t)c->ncell;
+  hipError_t e;
+  if (!s.a1h) {
+    if ((e = hipMalloc((void **)&s.a1h, n * C * 2)) || (e = hipMalloc((void **)&s.a2h, n * C * 2))) return e;
+    c->bytes += 2 * n * C * 2;
+  }
+  const int L = c->nlev, nc = c->ncol;
+  hipLaunchKernelGGL(k_inf_layer1, dim3(nblk(n)), dim3(kBlock), 0, c->stream, x, s.wb, s.w + OFF_B1, s.a1h, L, nc,
+                     s.nb9);
+  const size_t waves = (n + 16 * kInfTiles - 1) / (16 * kInfTiles);
+  hipLaunchKernelGGL(k_inf_layer2_mfma, dim3(nblk(waves, kBlock / 64)), dim3(kBlock), 0, c->stream, s.a1h, s.wb + W1N,
+                     s.w + OFF_B2, s.a2h, L, nc, s.nb9);
+  hipLaunchKernelGGL(k_inf_layer3, dim3(nblk(n)), dim3(kBlock), 0, c->stream, s.a2h, s.wb + W1N + W2N, s.w + OFF_B3,
+                     out, L, nc, s.nb9);
   return hipGetLastError();
 }
 
@@ -689,7 +821,7 @@ hipError_t learned_stage(hyb_ctx *c, const double *r, Tz *z) {
   hipLaunchKernelGGL(k_sum_into, dim3(1), dim3(64), 0, c->stream, part, (int)nb, s.scal);
   hipLaunchKernelGGL(k_normalise, dim3(nblk(n)), dim3(kBlock), 0, c->stream, c->cell64, s.scal, s.cin, n);
   if ((e = hipGetLastError())) return e;
-  if ((e = nn_forward(c, s.cin, s.cout, 1))) return e;
+  if ((e = nn_forward_inference(c, s.cin, s.cout))) return e;
   hipLaunchKernelGGL((k_sumsq<float>), dim3(nb), dim3(kBlock), 0, c->stream, s.cout, n, part);
   hipLaunchKernelGGL(k_sum_into, dim3(1), dim3(64), 0, c->stream, part, (int)nb, s.scal + 1);
   hipLaunchKernelGGL(k_prolong_correction, dim3(nblk(ntr)), dim3(kBlock), 0, c->stream, s.cout, s.scal, L0.H, s.d64,
@@ -717,6 +849,8 @@ void nn_free(hyb_ctx *c) {
   if (s.isbf) (void)hipFree(s.isbf), s.isbf = nullptr;
   if (s.nb9) (void)hipFree(s.nb9), s.nb9 = nullptr;
   if (s.scal) (void)hipFree(s.scal), s.scal = nullptr;
+  if (s.a1h) (void)hipFree(s.a1h), s.a1h = nullptr;
+  if (s.a2h) (void)hipFree(s.a2h), s.a2h = nullptr;
   if (s.d64) (void)hipFree(s.d64), s.d64 = nullptr;
   if (s.sd64) (void)hipFree(s.sd64), s.sd64 = nullptr;
   if (s.gq) (void)hipFree(s.gq), s.gq = nullptr;

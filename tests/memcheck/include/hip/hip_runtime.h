@@ -17,6 +17,8 @@ struct dim3 {
   dim3() = default;
   dim3(unsigned a, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}
 };
+struct uint2 { uint32_t x, y; };
+struct uint4 { uint32_t x, y, z, w; };
 typedef enum hipError_t { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorOutOfMemory = 2,
                           hipErrorIllegalAddress = 700 } hipError_t;
 typedef void *hipStream_t;

@@ -125,18 +125,22 @@ def test_energy_loss_gradients_match_oracle(small):
 
 
 def _stage_reference(prob, orc, vec, v):
+    """The stage inside the solve runs the network with BF16 weights and BF16 hidden activations
+    (FP32 accumulation); the input is the FP32 c / s."""
     W, b = learned.unpack(vec)
     Wr = [onn.bf16_round(w) for w in W]
     z = orc.pc(v)
     return onn.learned_correction(v, z, orc.pc.S, orc.pc.P, orc.pc.gamma, orc.H.diagonal(), Wr, b,
-                                  onn.neighbour_table(prob.nx, prob.ny), prob.nlev)
+                                  onn.neighbour_table(prob.nx, prob.ny), prob.nlev, round_act=onn.bf16_round)
 
 
 @pytest.mark.gpu
 def test_precondition_with_learned_stage_matches_oracle(small):
     """hyb_precondition with the stage against the oracle's cycle + stage: an exact identity network
-    (the correction is the closed form P H_KK^-1 Gamma P^T r') and a random one.  The network takes
-    c / s rounded to FP32 (relative 2^-24), so the correction agrees to about 1e-7 of its size."""
+    (every product is exact in BF16 / FP32, so the correction is the closed form with c / s rounded
+    to BF16 on both sides; to 1e-6) and a random one (to 1e-4: where the FP32 accumulation on the GPU
+    and the FP64 one in the oracle straddle a BF16 rounding boundary, a hidden activation differs by
+    one BF16 ulp, 2^-8 of itself)."""
     prob, s = small
     import torch
 
@@ -158,7 +162,7 @@ def test_precondition_with_learned_stage_matches_oracle(small):
             s.set_params(p)
             err = rel_max(host(z), zref)
             say(f"[stage] {name} trial {trial}: accepted {acc}, error {err:.2e}")
-            assert err <= 1e-6
+            assert err <= (1e-6 if name == "identity" else 1e-4)
 
 
 @pytest.mark.gpu
