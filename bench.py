@@ -30,6 +30,10 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
 # algorithmic flops of the order-1 condensation per cell: elimination of the 44 x 44 block without
 # pivoting (2/3 n^3) and of its 24 right-hand sides (forward and back substitution, 2 n^2 each)
 P1_CONDENSE_FLOPS = 2.0 / 3.0 * 44**3 + 2 * 44**2 * 24
+# algorithmic HBM bytes of the FP64 condensation by the block structure per cell: the 748 entries
+# of A_K it uses (twelve 3x3 velocity blocks, G, D, P), C_F and K_F (24 + 24), S_K written (576)
+# and the 748 cell factors written
+P1_STRUCT_BYTES = 8 * (748 + 48 + 576 + 748)
 
 
 def log(*a):
@@ -264,16 +268,20 @@ def p1_leg(args):
             res.append(info["rel_res"])
         torch.cuda.synchronize()
         sec = (time.perf_counter() - t0) / 3
-        kern_ms = cond_ms if ncond else fac_ms
-        flops = P1_CONDENSE_FLOPS * s.ncell
-        achieved = flops / (kern_ms * 1e-3) / 1e12
+        if ncond:  # dense elimination on matrix cores
+            kern_ms = cond_ms
+            achieved = P1_CONDENSE_FLOPS * s.ncell / (kern_ms * 1e-3) / 1e12
+            roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[dtype], "unit": "TFLOP/s",
+                    "frac": achieved / PEAK_TFLOPS[dtype], "kernel": "k_p1_condense_mfma"}
+        else:  # FP64 by the block structure, bound by HBM
+            kern_ms = fac_ms
+            achieved = P1_STRUCT_BYTES * s.ncell / (kern_ms * 1e-3) / 1e9
+            roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": achieved / PEAK_HBM_GBS, "kernel": "k_p1_condense_struct"}
         out[name] = dict(sec_per_solve=sec, iters=its, rel_res=max(res), setup_s=setup, condense_kernel_ms=kern_ms,
-                         fp64_factor_ms=fac_ms, s_x_error_vs_fp64=err,
-                         roofline={"bound": "mfma" if ncond else "alu", "achieved": achieved,
-                                   "peak": PEAK_TFLOPS[dtype], "unit": "TFLOP/s",
-                                   "frac": achieved / PEAK_TFLOPS[dtype],
-                                   "kernel": "k_p1_condense_mfma" if ncond else "k_p1_factor"})
-        log(f"p1 {name}: condense kernel {kern_ms:.2f} ms ({achieved:.2f} TFLOP/s), fp64 factor {fac_ms:.2f} ms, "
+                         fp64_factor_ms=fac_ms, s_x_error_vs_fp64=err, roofline=roof)
+        unit = roof["unit"]
+        log(f"p1 {name}: condense kernel {kern_ms:.2f} ms ({achieved:.2f} {unit}), fp64 factors {fac_ms:.2f} ms, "
             f"solve {sec * 1e3:.1f} ms, iters {its}, S x error vs fp64 {err:.1e}")
         s.close()
         del s
@@ -281,7 +289,7 @@ def p1_leg(args):
     return dict(workload=f"periodic box {args.p1_nx}x{args.p1_nx}x{args.p1_nlev}, dx=10km, dz=500m, RT1/DG1/Q1 "
                          f"trace (44x44 cell blocks), FGMRES(30)+two-level (DG0 coarse space), rtol {args.rtol}",
                 ncell=prob.ncell, ntrace=4 * (prob.ncol * (prob.nlev + 1) + 2 * prob.ncol * prob.nlev),
-                condense_flops_per_cell=P1_CONDENSE_FLOPS, modes=out)
+                condense_flops_per_cell=P1_CONDENSE_FLOPS, struct_bytes_per_cell=P1_STRUCT_BYTES, modes=out)
 
 
 def main():

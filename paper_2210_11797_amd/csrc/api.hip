@@ -330,8 +330,7 @@ int hyb_set_params(hyb_ctx *c, const hyb_params *params) {
     p0.precision = HYB_PREC_FP64;
     if ((rc = hyb_set_params(c->coarse, &p0))) return fail(c, rc, std::string("coarse space: ") + hyb_last_error(c->coarse));
     c->p = *params;
-    // the condensation arithmetic changed: A_K has been replaced by its factors, so assemble again
-    if (prec_change) c->assembled = c->condensed = false;
+    if (prec_change) c->condensed = false;  // condense again in the new arithmetic
     return HYB_OK;
   }
   if (params->precision == HYB_PREC_MFMA_FP32 || params->precision == HYB_PREC_MFMA_BF16X)
@@ -360,7 +359,8 @@ int hyb_assemble_local(hyb_ctx *c, const double *theta_w, const double *exner_ha
     hyb::P1State &s = c->p1;
     const size_t nc = (size_t)c->ncell;
     if ((rc = dalloc(c, &s.A, 44 * 44 * nc)) || (rc = dalloc(c, &s.cdiag, 24 * nc)) ||
-        (rc = dalloc(c, &s.kdiag, 24 * nc)) || (rc = dalloc(c, &s.SK, 24 * 24 * nc)) || (rc = dalloc(c, &s.bK, 24 * nc)))
+        (rc = dalloc(c, &s.kdiag, 24 * nc)) || (rc = dalloc(c, &s.SK, 24 * 24 * nc)) || (rc = dalloc(c, &s.bK, 24 * nc)) ||
+        (rc = dalloc(c, &s.fac, 748 * nc)))
       return rc;
     CHECK_HIP(p1_setup(c), "p1 tables");
     CHECK_HIP(p1_assemble(c, theta_w, exner_hat_w, exner_c, rho_c), "p1 assemble_local");
@@ -383,7 +383,7 @@ int hyb_condense(hyb_ctx *c, const double *r_ub, const double *r_pi, double *b_l
   int rc;
   if (c->order == 1) {
     if (r_ub == nullptr) {
-      if (c->condensed) return HYB_OK;  // the LU factors replaced A_K
+      if (c->condensed) return HYB_OK;
       if ((rc = hyb_condense(c->coarse, nullptr, nullptr, nullptr)))
         return fail(c, rc, std::string("coarse space: ") + hyb_last_error(c->coarse));
       CHECK_HIP(p1_factor(c), "p1 factor");

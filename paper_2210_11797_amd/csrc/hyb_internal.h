@@ -61,11 +61,12 @@ struct NNState {
 // p = 1 system (p1.hip): cell data per cell (array of structures)
 struct P1State {
   double *tbl = nullptr;    // reference tables of the assembly
-  double *A = nullptr;      // [ncell][44][44] A_K, then its LU factors (unit lower, no pivoting)
+  double *A = nullptr;      // [ncell][44][44] A_K
   double *cdiag = nullptr;  // [ncell][24] diagonal of C_K on the face dofs
   double *kdiag = nullptr;  // [ncell][24] diagonal of K_K
   double *SK = nullptr;     // [24 x 24][ncell] S_K = C_K [A_K^-1]_ff K_K, entry (r, j) at (r * 24 + j) * ncell
-  double *bK = nullptr;     // [ncell][24] the cell's share of B_lambda
+  double *bK = nullptr;     // [24][ncell] the cells' shares of B_lambda, or of S x on its way to the rows
+  double *fac = nullptr;    // [748][ncell] factors of A_K by its block structure: M^-1, M^-1 G, Dr, Sg^-1
   // two-level preconditioner
   double *dS = nullptr;     // [ntrace] diagonal of S
   double *zf = nullptr;     // [nz][48] block LU factors of the column systems: Dinv, W, U (4x4 each)

@@ -8,8 +8,8 @@
 // and top facets, the cell values of Pi* and rho*), so the assembly multiplies reference tables --
 // integrals of products of the reference basis functions, computed once on the host with exact
 // Gauss rules -- by per-cell scalars.  Cell data are stored per cell (array of structures): one
-// wavefront owns one cell in the assembly, the factorisation and the cell solves, and reads or
-// writes its 44 x 44 block contiguously.  The condensed blocks S_K are stored entry by entry over
+// wavefront owns one cell in the assembly and the condensation, and reads its 44 x 44 block
+// contiguously.  The condensed blocks S_K are stored entry by entry over
 // the cells ([24 x 24][ncell]): the trace rows of consecutive cells then read consecutive addresses.
 //
 // Dof order per cell: velocity face dofs 4 f + i (f = W, E, S, N, B, T; face point i = 2 t1 + t2
@@ -145,6 +145,16 @@ __device__ __forceinline__ CellCoef cell_coef(int c, int ncol, const double *dz,
   return q;
 }
 
+// Workgroups go to the 8 XCDs in turn (workgroup b to XCD b mod 8), each with its own L2.  Kernels
+// that write entry by entry over the cells renumber their workgroups so that each XCD owns one
+// contiguous range of cells: neighbouring cells, whose values share cache lines, are then written
+// through the same L2 and leave it as whole lines.
+__device__ __forceinline__ int xcd_block() {
+  constexpr int kXcd = 8;
+  const int b = blockIdx.x, n = gridDim.x, x = b % kXcd, base = n / kXcd, rem = n % kXcd;
+  return x * base + (x < rem ? x : rem) + b / kXcd;
+}
+
 // One wavefront per cell writes A_K (44 x 44, row-major) and the diagonals of C_K and K_K.
 __global__ void __launch_bounds__(kBlock) k_p1_assemble(int ncell, int ncol, const double *__restrict__ dz, double dx,
                                                         double dy, const double *__restrict__ theta_w,
@@ -194,59 +204,6 @@ __global__ void __launch_bounds__(kBlock) k_p1_assemble(int ncell, int ncol, con
       th = (f == 4) ? q.thB : q.thT;
     cdiag[(size_t)c * NF + lane] = 0.25 * area;
     kdiag[(size_t)c * NF + lane] = tu * dt * cp * 0.25 * area * th;
-  }
-}
-
-// One wavefront per cell: LU factorisation of A_K without pivoting (velocity block first; the
-// velocity block is a perturbed mass matrix and the pressure Schur complement is positive), in
-// place, then S_K[r][s] = c_r [A_K^-1]_{rs} k_s for the 24 face dofs.  A_K staged in LDS.
-constexpr int kP1Waves = 2;  // cells per workgroup (LDS: 2 x (44 x 44 + 44 x 24) doubles)
-__global__ void __launch_bounds__(64 * kP1Waves) k_p1_factor(int ncell, double *__restrict__ A,
-                                                            const double *__restrict__ cdiag,
-                                                            const double *__restrict__ kdiag, double *__restrict__ SK,
-                                                            int write_sk) {
-  __shared__ double sA[kP1Waves][NX * NX];
-  __shared__ double sX[kP1Waves][NX * NF];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int c = blockIdx.x * kP1Waves + wv;
-  const bool active = c < ncell;
-  double *a = sA[wv], *x = sX[wv];
-  if (active) {
-    const double *Ac = A + (size_t)c * NA;
-    for (int e = lane; e < NA; e += 64) a[e] = Ac[e];
-    for (int e = lane; e < NX * NF; e += 64) {
-      const int i = e / NF, j = e - i * NF;
-      x[e] = (i == j) ? kdiag[(size_t)c * NF + j] : 0.0;  // [K_K; 0]: K_K is diagonal on the face dofs
-    }
-  }
-  __syncthreads();
-  // right-looking elimination; lanes own rows
-  for (int k = 0; k < NX; ++k) {
-    if (active && lane > k && lane < NX) {
-      const double l = a[lane * NX + k] / a[k * NX + k];
-      a[lane * NX + k] = l;
-      for (int j = k + 1; j < NX; ++j) a[lane * NX + j] -= l * a[k * NX + j];
-      for (int j = 0; j < NF; ++j) x[lane * NF + j] -= l * x[k * NF + j];
-    }
-    __syncthreads();
-  }
-  // back substitution, lanes own right-hand-side columns
-  if (active && lane < NF) {
-    for (int i = NX - 1; i >= 0; --i) {
-      double s = x[i * NF + lane];
-      for (int m = i + 1; m < NX; ++m) s -= a[i * NX + m] * x[m * NF + lane];
-      x[i * NF + lane] = s / a[i * NX + i];
-    }
-  }
-  __syncthreads();
-  if (active) {
-    double *Ac = A + (size_t)c * NA;
-    for (int e = lane; e < NA; e += 64) Ac[e] = a[e];
-    if (write_sk)
-      for (int e = lane; e < NS; e += 64) {
-        const int r = e / NF, s = e - r * NF;
-        SK[(size_t)e * ncell + c] = cdiag[(size_t)c * NF + r] * x[r * NF + s];
-      }
   }
 }
 
@@ -306,7 +263,7 @@ __global__ void __launch_bounds__(64 * kMW) k_p1_condense_mfma(int ncell, const 
                                                               double *__restrict__ SK) {
   __shared__ float sM[kMW][MP * LDM];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int c = blockIdx.x * kMW + wv;
+  const int c = xcd_block() * kMW + wv;
   const bool active = c < ncell;  // uniform within a wavefront
   float *M = sM[wv];
   if (active) {
@@ -383,53 +340,6 @@ __device__ __forceinline__ size_t p1_dof(int j, int k, int col, int ncol, int ne
   return 4 * F + (j & 3);
 }
 
-// One wavefront per cell: X = LU^-1 (R - [K lambda; 0]) with the stored factors.  mode 0: b_K =
-// C_K [X]_face (the cell's share of B_lambda, lambda unused); mode 1: recovery, u_b = X_u, pi = X_p.
-__global__ void __launch_bounds__(64 * kP1Waves) k_p1_cell_solve(int ncell, int ncol, int nedge, size_t nz,
-                                                                const int32_t *__restrict__ col_edge,
-                                                                const double *__restrict__ LU,
-                                                                const double *__restrict__ cdiag,
-                                                                const double *__restrict__ kdiag,
-                                                                const double *__restrict__ r_u,
-                                                                const double *__restrict__ r_p,
-                                                                const double *__restrict__ lam, int mode,
-                                                                double *__restrict__ bK, double *__restrict__ u,
-                                                                double *__restrict__ pi) {
-  __shared__ double sx[kP1Waves][NX];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int c = blockIdx.x * kP1Waves + wv;
-  const bool active = c < ncell;
-  double *x = sx[wv];
-  const double *L = LU + (size_t)c * NA;
-  const int k = active ? c / ncol : 0, col = active ? c - k * ncol : 0;
-  if (active && lane < NX) {
-    // right-hand sides are [dof][nlev][ncol]
-    double v = lane < NU ? r_u[(size_t)lane * ncell + c] : r_p[(size_t)(lane - NU) * ncell + c];
-    if (mode == 1 && lane < NF) v -= kdiag[(size_t)c * NF + lane] * lam[p1_dof(lane, k, col, ncol, nedge, nz, col_edge)];
-    x[lane] = v;
-  }
-  __syncthreads();
-  for (int m = 0; m < NX; ++m) {  // forward substitution (unit lower)
-    if (active && lane > m && lane < NX) x[lane] -= L[lane * NX + m] * x[m];
-    __syncthreads();
-  }
-  for (int m = NX - 1; m >= 0; --m) {  // back substitution
-    if (active && lane == 0) x[m] /= L[m * NX + m];
-    __syncthreads();
-    if (active && lane < m) x[lane] -= L[lane * NX + m] * x[m];
-    __syncthreads();
-  }
-  if (!active || lane >= NX) return;
-  if (mode == 0) {
-    if (lane < NF) bK[(size_t)c * NF + lane] = cdiag[(size_t)c * NF + lane] * x[lane];
-  } else {
-    if (lane < NU)
-      u[(size_t)lane * ncell + c] = x[lane];
-    else
-      pi[(size_t)(lane - NU) * ncell + c] = x[lane];
-  }
-}
-
 // For trace row T = 4 F + i: the (up to two) cells of facet F and the facet's local face in each.
 __device__ __forceinline__ int p1_row_cells(size_t T, int nlev, int ncol, int nedge, size_t nz,
                                             const int32_t *__restrict__ edge_col, const int32_t *__restrict__ edge_lf,
@@ -450,35 +360,247 @@ __device__ __forceinline__ int p1_row_cells(size_t T, int nlev, int ncol, int ne
   return n;
 }
 
-// mode 0: y = S x; mode 1: the gather of the cells' right-hand-side shares b_K into B; mode 2:
-// y = b - S x; mode 3: y = diag(S)
-__global__ void k_p1_rows(size_t ntr, int nlev, int ncol, int nedge, size_t nz, const int32_t *__restrict__ col_edge,
-                          const int32_t *__restrict__ edge_col, const int32_t *__restrict__ edge_lf,
-                          const double *__restrict__ SK, const double *__restrict__ x, const double *__restrict__ bK,
-                          double *__restrict__ y, int mode) {
+// ---- condensation by the block structure of A_K --------------------------------------------------
+// On an axis-aligned cell the velocity block M = m2 - q22 is block diagonal: every RT1 function is a
+// Lagrange function on the Gauss points in its two tangential directions, and those are orthogonal,
+// so a function couples only to the two others of its direction and tangential point -- twelve 3x3
+// blocks {4 (2d) + i, 4 (2d + 1) + i, 24 + 4 d + i} (d direction, i tangential point).  With
+// Mi = M^-1 and the pressure Schur complement Sg = P - Dr Mi G (8x8),
+//   [A^-1]_uu = Mi + (Mi G) Sg^-1 (Dr Mi),   S_K = C_F ([Mi]_FF + [Mi G]_F Sg^-1 [Dr Mi]_F) K_F,
+// and the cell solves X = A^-1 R are y = Mi R_u, x_p = Sg^-1 (R_p - Dr y), x_u = y - (Mi G) x_p.
+// Factors kept per cell (entry by entry over the cells): Mi (12 x 9), Mi G (36 x 8), Dr (8 x 36),
+// Sg^-1 (8 x 8).
+constexpr int FO_MI = 0, FO_MIG = 108, FO_DR = FO_MIG + 288, FO_SGI = FO_DR + 288, NFAC = FO_SGI + 64;
+
+__device__ __forceinline__ int blk_dof(int blk, int r) {  // dof of position r (0: "-" face, 1: "+" face, 2: interior)
+  const int d = blk >> 2, i = blk & 3;
+  return r == 0 ? 8 * d + i : (r == 1 ? 8 * d + 4 + i : 24 + 4 * d + i);
+}
+__device__ __forceinline__ void dof_blk(int a, int &blk, int &r) {
+  if (a < 24) {
+    const int f = a >> 2, i = a & 3;
+    blk = 4 * (f >> 1) + i, r = f & 1;
+  } else {
+    blk = a - 24, r = 2;  // 24 + 4 d + i  ->  block 4 d + i
+  }
+}
+
+constexpr int kSW = 4;  // cells (wavefronts) per workgroup
+__global__ void __launch_bounds__(64 * kSW) k_p1_condense_struct(int ncell, const double *__restrict__ A,
+                                                                const double *__restrict__ cdiag,
+                                                                const double *__restrict__ kdiag,
+                                                                double *__restrict__ SK, double *__restrict__ fac,
+                                                                int write_sk) {
+  __shared__ double sMi[kSW][108], sG[kSW][288], sDr[kSW][288], sMiG[kSW][288], sDrMi[kSW][288], sSg[kSW][64],
+      sT[kSW][192];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int c = xcd_block() * kSW + wv;
+  const bool active = c < ncell;
+  double *Mi = sMi[wv], *G = sG[wv], *Dr = sDr[wv], *MiG = sMiG[wv], *DrMi = sDrMi[wv], *Sg = sSg[wv], *T = sT[wv];
+  const double *Ac = A + (size_t)c * NA;
+  if (active) {
+    for (int e = lane; e < 288; e += 64) {
+      const int a = e >> 3, p = e & 7;
+      G[e] = Ac[a * NX + NU + p];              // G[a][p]
+      Dr[p * NU + a] = Ac[(NU + p) * NX + a];  // Dr[p][a]
+    }
+    Sg[lane] = Ac[(NU + (lane >> 3)) * NX + NU + (lane & 7)];  // P
+    if (lane < 12) {  // invert the 3x3 block by cofactors
+      double m[3][3];
+      for (int r = 0; r < 3; ++r)
+        for (int q = 0; q < 3; ++q) m[r][q] = Ac[blk_dof(lane, r) * NX + blk_dof(lane, q)];
+      const double c00 = m[1][1] * m[2][2] - m[1][2] * m[2][1], c01 = m[1][2] * m[2][0] - m[1][0] * m[2][2],
+                   c02 = m[1][0] * m[2][1] - m[1][1] * m[2][0];
+      const double inv = 1.0 / (m[0][0] * c00 + m[0][1] * c01 + m[0][2] * c02);
+      double *o = Mi + 9 * lane;
+      o[0] = c00 * inv, o[3] = c01 * inv, o[6] = c02 * inv;
+      o[1] = (m[0][2] * m[2][1] - m[0][1] * m[2][2]) * inv, o[4] = (m[0][0] * m[2][2] - m[0][2] * m[2][0]) * inv,
+      o[7] = (m[0][1] * m[2][0] - m[0][0] * m[2][1]) * inv;
+      o[2] = (m[0][1] * m[1][2] - m[0][2] * m[1][1]) * inv, o[5] = (m[0][2] * m[1][0] - m[0][0] * m[1][2]) * inv,
+      o[8] = (m[0][0] * m[1][1] - m[0][1] * m[1][0]) * inv;
+    }
+  }
+  __syncthreads();
+  if (active)
+    for (int e = lane; e < 288; e += 64) {
+      int blk, r;
+      // (Mi G)[a][p]
+      const int a = e >> 3, p = e & 7;
+      dof_blk(a, blk, r);
+      double s1 = 0.0;
+      for (int q = 0; q < 3; ++q) s1 += Mi[9 * blk + 3 * r + q] * G[blk_dof(blk, q) * 8 + p];
+      MiG[e] = s1;
+      // (Dr Mi)[p2][a2] stored at p2 * 36 + a2
+      const int p2 = e / NU, a2 = e - p2 * NU;
+      dof_blk(a2, blk, r);
+      double s2 = 0.0;
+      for (int q = 0; q < 3; ++q) s2 += Dr[p2 * NU + blk_dof(blk, q)] * Mi[9 * blk + 3 * q + r];
+      DrMi[e] = s2;
+    }
+  __syncthreads();
+  if (active) {  // Sg = P - Dr (Mi G)
+    const int p = lane >> 3, q = lane & 7;
+    double s = 0.0;
+    for (int a = 0; a < NU; ++a) s += Dr[p * NU + a] * MiG[a * 8 + q];
+    Sg[lane] -= s;
+  }
+  __syncthreads();
+  if (active) {
+    // Sg^-1 in place by Gauss-Jordan without pivoting (Sg is dominated by its positive diagonal):
+    // lane 8 i + j holds entry (i, j); each step reads the pivot row and column across lanes
+    const int i = lane >> 3, j = lane & 7;
+    double a = Sg[lane];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const double akk = __shfl(a, 9 * k), aik = __shfl(a, 8 * i + k), akj = __shfl(a, 8 * k + j);
+      const double p = 1.0 / akk;
+      if (i == k && j == k) a = p;
+      else if (i == k) a = akj * p;
+      else if (j == k) a = -aik * p;
+      else a -= aik * akj * p;
+    }
+    Sg[lane] = a;
+  }
+  __syncthreads();
+  if (active)
+    for (int e = lane; e < 192; e += 64) {  // T = Sg^-1 [Dr Mi]_F
+      const int p = e / NF, f = e - p * NF;
+      double s = 0.0;
+      for (int q = 0; q < 8; ++q) s += Sg[8 * p + q] * DrMi[q * NU + f];
+      T[e] = s;
+    }
+  __syncthreads();
+  // Writes: thread t takes cell w = t mod kSW of the workgroup, so each store covers kSW consecutive
+  // cells of 64 / kSW entries (32-byte pieces) instead of 64 scattered doubles.
+  const int w = threadIdx.x % kSW, c0 = c - wv;
+  if (c0 + w >= ncell) return;
+  const double *wMi = sMi[w], *wMiG = sMiG[w], *wT = sT[w], *wDr = sDr[w], *wSg = sSg[w];
+  const size_t cw = (size_t)c0 + w;
+  if (write_sk)
+    for (int e = threadIdx.x / kSW; e < NS; e += 64) {
+      const int r = e / NF, f = e - r * NF;
+      int br, pr, bf, pf;
+      dof_blk(r, br, pr);
+      dof_blk(f, bf, pf);
+      double v = (br == bf) ? wMi[9 * br + 3 * pr + pf] : 0.0;
+      for (int p = 0; p < 8; ++p) v += wMiG[r * 8 + p] * wT[p * NF + f];
+      SK[(size_t)e * ncell + cw] = cdiag[cw * NF + r] * v * kdiag[cw * NF + f];
+    }
+  for (int e = threadIdx.x / kSW; e < NFAC; e += 64) {
+    double v;
+    if (e < FO_MIG) v = wMi[e];
+    else if (e < FO_DR) v = wMiG[e - FO_MIG];
+    else if (e < FO_SGI) v = wDr[e - FO_DR];
+    else v = wSg[e - FO_SGI];
+    fac[(size_t)e * ncell + cw] = v;
+  }
+}
+
+// Thread per cell: X = A_K^-1 (R - [K lambda; 0]) from the structured factors.  mode 0: the cell's
+// share C_F [X_u]_F of B_lambda into bK [24][ncell]; mode 1: recovery into u [36][ncell], pi [8][ncell].
+__global__ void __launch_bounds__(kBlock) k_p1_cell_struct(int ncell, int ncol, int nedge, size_t nz,
+                                                          const int32_t *__restrict__ col_edge,
+                                                          const double *__restrict__ fac,
+                                                          const double *__restrict__ cdiag,
+                                                          const double *__restrict__ kdiag,
+                                                          const double *__restrict__ r_u,
+                                                          const double *__restrict__ r_p,
+                                                          const double *__restrict__ lam, int mode,
+                                                          double *__restrict__ bK, double *__restrict__ u,
+                                                          double *__restrict__ pi) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  const int k = c / ncol, col = c - k * ncol;
+  auto F = [&](int e) { return fac[(size_t)e * ncell + c]; };
+  double R[NU], y[NU], g[NPR], xp[NPR];
+#pragma unroll
+  for (int a = 0; a < NU; ++a) R[a] = r_u[(size_t)a * ncell + c];
+  if (mode == 1)
+#pragma unroll
+    for (int f = 0; f < NF; ++f) R[f] -= kdiag[(size_t)c * NF + f] * lam[p1_dof(f, k, col, ncol, nedge, nz, col_edge)];
+#pragma unroll
+  for (int blk = 0; blk < 12; ++blk) {
+    const int d0 = blk_dof(blk, 0), d1 = blk_dof(blk, 1), d2 = blk_dof(blk, 2);
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+      y[blk_dof(blk, r)] = F(FO_MI + 9 * blk + 3 * r) * R[d0] + F(FO_MI + 9 * blk + 3 * r + 1) * R[d1] +
+                           F(FO_MI + 9 * blk + 3 * r + 2) * R[d2];
+  }
+#pragma unroll
+  for (int p = 0; p < NPR; ++p) {
+    double s = r_p[(size_t)p * ncell + c];
+#pragma unroll
+    for (int a = 0; a < NU; ++a) s -= F(FO_DR + p * NU + a) * y[a];
+    g[p] = s;
+  }
+#pragma unroll
+  for (int p = 0; p < NPR; ++p) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < NPR; ++q) s += F(FO_SGI + 8 * p + q) * g[q];
+    xp[p] = s;
+  }
+#pragma unroll
+  for (int a = 0; a < NU; ++a) {
+    double s = y[a];
+#pragma unroll
+    for (int p = 0; p < NPR; ++p) s -= F(FO_MIG + 8 * a + p) * xp[p];
+    y[a] = s;
+  }
+  if (mode == 0) {
+#pragma unroll
+    for (int f = 0; f < NF; ++f) bK[(size_t)f * ncell + c] = cdiag[(size_t)c * NF + f] * y[f];
+  } else {
+#pragma unroll
+    for (int a = 0; a < NU; ++a) u[(size_t)a * ncell + c] = y[a];
+#pragma unroll
+    for (int p = 0; p < NPR; ++p) pi[(size_t)p * ncell + c] = xp[p];
+  }
+}
+
+// S x in two passes.  Thread per cell: t_K = S_K x_K into t [24][ncell] (mode 0), or the diagonal of
+// S_K (mode 1).  Each cell gathers its 24 trace values once and reads its S_K entry by entry over
+// the cells, so both the matrix and t stream coalesced.
+__global__ void __launch_bounds__(kBlock) k_p1_cell_mv(int ncell, int ncol, int nedge, size_t nz,
+                                                      const int32_t *__restrict__ col_edge,
+                                                      const double *__restrict__ SK, const double *__restrict__ x,
+                                                      int mode, double *__restrict__ t) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  if (mode == 1) {
+#pragma unroll 4
+    for (int r = 0; r < NF; ++r) t[(size_t)r * ncell + c] = SK[(size_t)(r * NF + r) * ncell + c];
+    return;
+  }
+  const int k = c / ncol, col = c - k * ncol;
+  double xk[NF];
+#pragma unroll
+  for (int j = 0; j < NF; ++j) xk[j] = x[p1_dof(j, k, col, ncol, nedge, nz, col_edge)];
+#pragma unroll 2
+  for (int r = 0; r < NF; ++r) {
+    const double *row = SK + (size_t)r * NF * ncell + c;
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < NF; ++j) s += row[(size_t)j * ncell] * xk[j];
+    t[(size_t)r * ncell + c] = s;
+  }
+}
+
+// Thread per trace row T = 4 F + i: the sum of the shares t_K of the (up to two) cells of facet F,
+// y = sum (sub = 0) or y = b - sum (sub = 1).  t is [24][ncell] (the cells' shares of S x, of
+// diag(S), or of B_lambda).
+__global__ void k_p1_gather(size_t ntr, int nlev, int ncol, int nedge, size_t nz, const int32_t *__restrict__ edge_col,
+                            const int32_t *__restrict__ edge_lf, const double *__restrict__ t,
+                            const double *__restrict__ b, double *__restrict__ y, int sub) {
   const size_t T = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (T >= ntr) return;
   int cells[2], faces[2];
   const int n = p1_row_cells(T, nlev, ncol, nedge, nz, edge_col, edge_lf, cells, faces);
+  const size_t ncell = (size_t)nlev * ncol;
   const int i = (int)(T & 3);
   double s = 0.0;
-  for (int q = 0; q < n; ++q) {
-    const int c = cells[q], r = 4 * faces[q] + i;
-    if (mode == 1) {
-      s += bK[(size_t)c * NF + r];
-      continue;
-    }
-    const size_t ncell = (size_t)nlev * ncol;
-    const double *row = SK + (size_t)r * NF * ncell + c;  // entry (r, j) of cell c at row[j * ncell]
-    if (mode == 3) {
-      s += row[(size_t)r * ncell];
-      continue;
-    }
-    const int k = c / ncol, col = c - k * ncol;
-#pragma unroll 4
-    for (int j = 0; j < NF; ++j) s += row[(size_t)j * ncell] * x[p1_dof(j, k, col, ncol, nedge, nz, col_edge)];
-  }
-  y[T] = (mode == 2) ? bK[T] - s : s;  // mode 2 passes b through the bK argument
+  for (int q = 0; q < n; ++q) s += t[(size_t)(4 * faces[q] + i) * ncell + cells[q]];
+  y[T] = sub ? b[T] - s : s;
 }
 
 // ---- two-level preconditioner at order 1 ------------------------------------------------------
@@ -666,8 +788,8 @@ hipError_t p1_assemble(hyb_ctx *c, const double *theta_w, const double *exner_ha
   return hipGetLastError();
 }
 
-// S_K in the arithmetic of params.precision (FP64, FP32 MFMA or BF16-split MFMA), then the FP64
-// LU factors of A_K in place (used by the per-solve cell solves: B_lambda and the recovery).
+// S_K in the arithmetic of params.precision: FP64 from the block structure, or the dense elimination
+// of A_K on MFMA (FP32, BF16 split); the per-solve cell factors always in FP64 from the structure.
 hipError_t p1_factor(hyb_ctx *c) {
   P1State &s = c->p1;
   const int prec = c->p.precision;
@@ -684,8 +806,8 @@ hipError_t p1_factor(hyb_ctx *c) {
     if (e) return e;
   }
   const int slot = prof_begin(c, F_P1_FACTOR);
-  hipLaunchKernelGGL(k_p1_factor, dim3(nblk(c->ncell, kP1Waves)), dim3(64 * kP1Waves), 0, c->stream, c->ncell, s.A,
-                     s.cdiag, s.kdiag, s.SK, prec == HYB_PREC_FP64 ? 1 : 0);
+  hipLaunchKernelGGL(k_p1_condense_struct, dim3(nblk(c->ncell, kSW)), dim3(64 * kSW), 0, c->stream, c->ncell, s.A,
+                     s.cdiag, s.kdiag, s.SK, s.fac, prec == HYB_PREC_FP64 ? 1 : 0);
   prof_end(c, F_P1_FACTOR, slot);
   return hipGetLastError();
 }
@@ -694,9 +816,10 @@ hipError_t p1_cell_solve(hyb_ctx *c, const double *r_u, const double *r_p, const
                          double *pi) {
   P1State &s = c->p1;
   const LevelDev &L0 = c->lv[0];
-  hipLaunchKernelGGL(k_p1_cell_solve, dim3(nblk(c->ncell, kP1Waves)), dim3(64 * kP1Waves), 0, c->stream, c->ncell,
-                     c->ncol, c->nedge, (size_t)c->nz, L0.col_edge, s.A, s.cdiag, s.kdiag, r_u, r_p, lam, mode, s.bK,
-                     u, pi);
+  const int slot = prof_begin(c, F_CELL);
+  hipLaunchKernelGGL(k_p1_cell_struct, dim3(nblk(c->ncell)), dim3(kBlock), 0, c->stream, c->ncell, c->ncol, c->nedge,
+                     (size_t)c->nz, L0.col_edge, s.fac, s.cdiag, s.kdiag, r_u, r_p, lam, mode, s.bK, u, pi);
+  prof_end(c, F_CELL, slot);
   return hipGetLastError();
 }
 
@@ -705,8 +828,12 @@ hipError_t p1_rows(hyb_ctx *c, const double *x, double *y, int mode, const doubl
   const LevelDev &L0 = c->lv[0];
   const size_t ntr = (size_t)c->ntrace;
   int slot = prof_begin(c, F_TRACE_APPLY);
-  hipLaunchKernelGGL(k_p1_rows, dim3(nblk(ntr)), dim3(kBlock), 0, c->stream, ntr, c->nlev, c->ncol, c->nedge,
-                     (size_t)c->nz, L0.col_edge, L0.edge_col, L0.edge_lf, s.SK, x, mode == 2 ? b : s.bK, y, mode);
+  if (mode != 1) {  // mode 1 gathers the shares already in bK
+    hipLaunchKernelGGL(k_p1_cell_mv, dim3(nblk(c->ncell)), dim3(kBlock), 0, c->stream, c->ncell, c->ncol, c->nedge,
+                       (size_t)c->nz, L0.col_edge, s.SK, x, mode == 3 ? 1 : 0, s.bK);
+  }
+  hipLaunchKernelGGL(k_p1_gather, dim3(nblk(ntr)), dim3(kBlock), 0, c->stream, ntr, c->nlev, c->ncol, c->nedge,
+                     (size_t)c->nz, L0.edge_col, L0.edge_lf, s.bK, b, y, mode == 2 ? 1 : 0);
   prof_end(c, F_TRACE_APPLY, slot);
   return hipGetLastError();
 }
@@ -788,8 +915,8 @@ hipError_t p1_precondition(hyb_ctx *c, const double *r, double *z) {
 
 void p1_free(hyb_ctx *c) {
   P1State &s = c->p1;
-  for (double **q : {&s.tbl, &s.A, &s.cdiag, &s.kdiag, &s.SK, &s.bK, &s.dS, &s.zf, &s.gamma, &s.den, &s.t1, &s.t2,
-                     &s.t3})
+  for (double **q : {&s.tbl, &s.A, &s.cdiag, &s.kdiag, &s.SK, &s.bK, &s.fac, &s.dS, &s.zf, &s.gamma, &s.den, &s.t1,
+                     &s.t2, &s.t3})
     if (*q) (void)hipFree(*q), *q = nullptr;
 }
 

@@ -259,6 +259,12 @@ def p1_sequence(lib):
         cm.call("hyb_trace_apply", P(x), P(ym))
         err = np.abs(ym - ref).max() / np.abs(ref).max()
         check(err <= tol, f"order 1, condensation mode {prec}: S x error vs FP64 {err:.1e}")
+        # a change of arithmetic asks for the condensation again, and FP64 restores the exact operator
+        cm.set(precision=N.PREC_FP64)
+        check(lib.hyb_trace_apply(cm.h, P(x), P(ym)) < 0, "order 1: a new precision rejects S x until condensed")
+        cm.call("hyb_condense", None, None, None)
+        cm.call("hyb_trace_apply", P(x), P(ym))
+        check(np.abs(ym - ref).max() <= 1e-11 * np.abs(ref).max(), "order 1: FP64 condensation after a switch")
         cm.close()
 
 
