@@ -57,6 +57,8 @@ def setup_solver(prob, precision, **kw):
 
 
 def run_steps(s, rhs, steps, warmup, rtol, profile=False):
+    """Times `steps` solves after `warmup`.  profile: False (no events), True (events around
+    every kernel family) or a family name (events around that family's launches only)."""
     import torch
 
     b = torch.empty(s.ntrace, dtype=torch.float64, device="cuda")
@@ -76,7 +78,9 @@ def run_steps(s, rhs, steps, warmup, rtol, profile=False):
     for i in range(warmup):
         step(i)
     torch.cuda.synchronize()
-    if profile:
+    if isinstance(profile, str):
+        s.profile_family(profile)
+    elif profile:
         s.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -87,7 +91,7 @@ def run_steps(s, rhs, steps, warmup, rtol, profile=False):
     t1 = time.perf_counter()
     fams = {}
     if profile:
-        for f in FAMILIES:
+        for f in ([profile] if isinstance(profile, str) else FAMILIES):
             fams[f] = s.profile_read(f)
         s.profile(False)
     return (t1 - t0) / steps, infos, fams
@@ -198,7 +202,7 @@ def learned_leg(args, prob, s, rhs, sec_plain, dx, dz, dt):
     p = s.params
     p.learned = 1
     s.set_params(p)
-    lsec, linfos, lfams = run_steps(s, rhs, args.steps, args.warmup, args.rtol, profile=True)
+    lsec, linfos, lfams = run_steps(s, rhs, args.steps, args.warmup, args.rtol, profile="nn")
     p.learned = 0
     s.set_params(p)
     nn_launches, nn_ms = lfams["nn"]
@@ -343,14 +347,17 @@ def main():
     setup_s = time.perf_counter() - t0
     log(f"setup (assemble + condense + preconditioner) {setup_s * 1e3:.1f} ms, workspace {s.workspace_bytes() / 1e9:.2f} GB")
 
-    sec, infos, fams = run_steps(s, rhs, args.steps, args.warmup, args.rtol, profile=True)
+    # timed solves with HIP events around the dominant kernel only; then the same solves again,
+    # untimed, with events around every family for the breakdown and the launch counts
+    sec, infos, dom = run_steps(s, rhs, args.steps, args.warmup, args.rtol, profile="smooth_rows")
+    _, _, fams = run_steps(s, rhs, args.steps, 0, args.rtol, profile=True)
     its = [i["iters"] for i in infos]
     ntr, ncell = s.ntrace, s.ncell
     # algorithmic bytes of the dominant kernel: one LineSmooth sweep reads the 11-entry row of S,
     # B and lambda_in and writes lambda_out for every trace row (8 bytes each, FP64)
     # dominant kernel: the LineSmooth residual rows (k_smooth_rows<double,false>), which read the
     # 11-entry row of S, B and lambda_in and write R or lambda_out for every trace row
-    ls_launches, ls_ms = fams["smooth_rows"]
+    ls_launches, ls_ms = dom["smooth_rows"]
     ls_bytes = 14 * 8 * ntr
     ls_avg_ms = ls_ms / max(ls_launches, 1)
     ls_gbs = ls_bytes / (ls_avg_ms * 1e-3) / 1e9
@@ -413,6 +420,7 @@ def main():
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated)",
                      "launches": ls_launches, "avg_ms": ls_avg_ms, "bytes_per_launch": ls_bytes},
         "kernel_ms": {k: {"launches": v[0], "total_ms": v[1]} for k, v in fams.items()},
+        "kernel_ms_note": "from a second, untimed run of the same solves with events around every family",
         "mixed": mixed,
         "learned": learned_out,
         "p1": p1_out,

@@ -198,6 +198,10 @@ int hyb_sizes(const hyb_ctx *ctx, int64_t *ntrace, int64_t *ncell, int64_t *work
    "thomas" (LineSmooth column solves), "trace_apply", "mg_smooth",
    "restrict", "prolong", "krylov", "cell_solve". */
 int hyb_profile(hyb_ctx *ctx, int32_t enable);
+/* As hyb_profile(ctx, 1), but recording one family only (the others launch without
+   events, so the timing of the rest of the path is not disturbed).  HYB_EINVAL for an
+   unknown family name. */
+int hyb_profile_family(hyb_ctx *ctx, const char *family);
 int hyb_profile_read(hyb_ctx *ctx, const char *family, int64_t *launches, double *total_ms);
 
 /* Restriction of a trace vector r [ntrace] to cells [nlev][ncol] (device FP64 arrays): mode 0

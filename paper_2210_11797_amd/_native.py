@@ -82,7 +82,7 @@ class Params:
 
 ABI_FUNCTIONS = [
     "hyb_create", "hyb_set_params", "hyb_assemble_local", "hyb_condense", "hyb_trace_apply",
-    "hyb_precondition", "hyb_solve", "hyb_recover", "hyb_sizes", "hyb_profile", "hyb_profile_read",
+    "hyb_precondition", "hyb_solve", "hyb_recover", "hyb_sizes", "hyb_profile", "hyb_profile_family", "hyb_profile_read",
     "hyb_restrict", "hyb_nn_param_count", "hyb_nn_set_weights", "hyb_nn_get_weights", "hyb_nn_forward",
     "hyb_nn_loss_grad", "hyb_nn_train_step", "hyb_nn_energy_grad", "hyb_nn_energy_train_step",
     "hyb_last_error", "hyb_destroy",
@@ -120,6 +120,7 @@ def declare(lib):
     lib.hyb_sizes.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                               ctypes.POINTER(ctypes.c_int64)]
     lib.hyb_profile.argtypes = [vp, ctypes.c_int32]
+    lib.hyb_profile_family.argtypes = [vp, ctypes.c_char_p]
     lib.hyb_profile_read.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
                                      ctypes.POINTER(ctypes.c_double)]
     lib.hyb_restrict.argtypes = [vp, vp, vp, ctypes.c_int32]
@@ -330,6 +331,10 @@ class HybSolver:
 
     def profile(self, enable: bool):
         self._check(self.lib.hyb_profile(self.h, 1 if enable else 0), "hyb_profile")
+
+    def profile_family(self, family: str):
+        """Record HIP events around the launches of one kernel family only."""
+        self._check(self.lib.hyb_profile_family(self.h, family.encode()), "hyb_profile_family")
 
     def profile_read(self, family: str):
         n, ms = ctypes.c_int64(), ctypes.c_double()

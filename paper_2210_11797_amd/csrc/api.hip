@@ -202,7 +202,7 @@ int alloc_krylov(hyb_ctx *c) {
 namespace hyb {
 
 int prof_begin(hyb_ctx *c, int fam) {
-  if (!c->prof) return -1;
+  if (!c->prof || !((c->prof_mask >> fam) & 1)) return -1;
   ProfFamily &f = c->fam[fam];
   if (f.used + 2 > f.ev.size()) {
     for (int i = 0; i < 64; ++i) {
@@ -704,7 +704,21 @@ int hyb_profile(hyb_ctx *c, int32_t enable) {
   CHECK_HIP(hipStreamSynchronize(c->stream), "profile sync");
   for (auto &f : c->fam) f.used = 0;
   c->prof = enable != 0;
+  c->prof_mask = ~0ull;
   return HYB_OK;
+}
+
+int hyb_profile_family(hyb_ctx *c, const char *family) {
+  if (!c || !family) return HYB_EINVAL;
+  for (size_t i = 0; i < c->fam.size(); ++i) {
+    if (c->fam[i].name != family) continue;
+    CHECK_HIP(hipStreamSynchronize(c->stream), "profile sync");
+    for (auto &f : c->fam) f.used = 0;
+    c->prof = true;
+    c->prof_mask = 1ull << i;
+    return HYB_OK;
+  }
+  return fail(c, HYB_EINVAL, std::string("unknown kernel family ") + family);
 }
 
 int hyb_profile_read(hyb_ctx *c, const char *family, int64_t *launches, double *total_ms) {

@@ -124,6 +124,7 @@ struct hyb_ctx {
   size_t bytes = 0;
 
   bool prof = false;
+  uint64_t prof_mask = ~0ull;  // families recorded while prof is on
   std::vector<hyb::ProfFamily> fam;
 
   hyb::NNState nn;
