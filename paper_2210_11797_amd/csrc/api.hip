@@ -190,7 +190,7 @@ int alloc_krylov(hyb_ctx *c) {
   int rc;
   c->nblk_red = reduction_blocks();
   if ((rc = dalloc(c, &c->V, (size_t)(m + 1) * n)) || (rc = dalloc(c, (double **)&c->Z, (size_t)m * n)) ||
-      (rc = dalloc(c, &c->partial, (size_t)c->nblk_red * (m + 2))) || (rc = dalloc(c, &c->hdev, 4 * (size_t)(m + 2))))
+      (rc = dalloc(c, &c->partial, (size_t)c->nblk_red * 2 * (m + 2))) || (rc = dalloc(c, &c->hdev, 4 * (size_t)(m + 2))))
     return rc;
   CHECK_HIP(hipHostMalloc((void **)&c->hhost, 4 * (size_t)(m + 2) * sizeof(double), hipHostMallocDefault),
             "hipHostMalloc");
@@ -547,7 +547,8 @@ int hyb_solve(hyb_ctx *c, const double *b, double *lam, double rtol, int32_t max
     g[0] = beta;
     int jend = 0;
     bool breakdown = false;
-    for (int j = 0; j < m; ++j) {
+    // z_j = M(V_j) into Z, w = S z_j into V_{j+1}
+    auto apply_op = [&](int j) -> int {
       double *vj = V + (size_t)j * n, *w = V + (size_t)(j + 1) * n;
       if (mixed) {
         float *zf = (float *)c->Z + (size_t)j * n;
@@ -565,6 +566,94 @@ int hyb_solve(hyb_ctx *c, const double *b, double *lam, double rtol, int32_t max
         if (learned) CHECK_HIP(learned_stage<double>(c, vj, zj), "learned stage");
         CHECK_HIP((launch_trace_apply<double, double, double>(c, c->S, zj, nullptr, w, 0)), "matvec");
       }
+      return HYB_OK;
+    };
+    if (m <= kDgsMax) {
+      // Arnoldi with classical Gram-Schmidt and delayed reorthogonalisation: step j applies the
+      // operator to V_j as orthogonalised once in step j - 1 (scaled by the estimated norm eta),
+      // then one reduction pass gives the dots that finish V_j (second orthogonalisation, exact
+      // norm rho) and orthogonalise w once, and one update pass writes both.  Column j - 1 of the
+      // Hessenberg matrix is completed with eta_j a and eta_j rho; the Givens QR of the columns
+      // so far is redone every step from the unrotated matrix Hr.
+      std::vector<double> Hr((size_t)(m + 1) * m, 0.0), ca(m), cb(m);
+      double eta_prev = 1.0, g0 = beta;
+      for (int j = 0; j < m; ++j) {
+        if ((rc = apply_op(j))) return rc;
+        CHECK_HIP(launch_dgs_dots(c, V, n, j, c->hdev), "gram-schmidt dots");
+        CHECK_HIP(hipMemcpyAsync(hh, c->hdev, (2 * (size_t)j + 3) * sizeof(double), hipMemcpyDeviceToHost, c->stream),
+                  "d2h");
+        CHECK_HIP(hipStreamSynchronize(c->stream), "sync");
+        double a2 = 0.0, ab = 0.0, b2 = 0.0;
+        for (int k = 0; k < j; ++k) {
+          ca[k] = hh[k], cb[k] = hh[j + 1 + k];
+          a2 += ca[k] * ca[k], ab += ca[k] * cb[k], b2 += cb[k] * cb[k];
+        }
+        const double rho2 = hh[j] - a2;
+        if (!(rho2 > 0.0) || !std::isfinite(rho2)) {
+          breakdown = true;
+          break;
+        }
+        const double rho = std::sqrt(rho2);
+        if (j == 0) {
+          g0 = beta * rho;  // r = beta V_0 (as scaled) = beta rho v_0
+        } else {
+          double *prev = &Hr[(size_t)(j - 1) * (m + 1)];
+          for (int k = 0; k < j; ++k) prev[k] += eta_prev * ca[k];
+          prev[j] = eta_prev * rho;
+        }
+        double *col = &Hr[(size_t)j * (m + 1)];
+        const double hjj = (hh[2 * j + 1] - ab) / rho;
+        for (int k = 0; k < j; ++k) col[k] = cb[k];
+        col[j] = hjj;
+        const double eta2 = hh[2 * j + 2] - b2 - hjj * hjj;
+        const double eta = (eta2 > 0.0 && std::isfinite(eta2)) ? std::sqrt(eta2) : 0.0;
+        col[j + 1] = eta;
+        CHECK_HIP(launch_dgs_update(c, V, n, j, ca.data(), cb.data(), 1.0 / rho, hjj, eta > 0.0 ? 1.0 / eta : 0.0),
+                  "gram-schmidt update");
+        eta_prev = eta;
+        // Givens QR of columns 0..j
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = g0;
+        bool bad = false;
+        for (int q = 0; q <= j; ++q) {
+          double *rq = &R[(size_t)q * (m + 1)];
+          const double *hq = &Hr[(size_t)q * (m + 1)];
+          for (int i = 0; i <= q + 1; ++i) rq[i] = hq[i];
+          for (int i = 0; i < q; ++i) {
+            const double x = rq[i], z = rq[i + 1];
+            rq[i] = cs[i] * x + sn[i] * z;
+            rq[i + 1] = -sn[i] * x + cs[i] * z;
+          }
+          const double rr = std::hypot(rq[q], rq[q + 1]);
+          if (!(rr > 0) || !std::isfinite(rr)) {
+            bad = true;
+            break;
+          }
+          cs[q] = rq[q] / rr;
+          sn[q] = rq[q + 1] / rr;
+          rq[q] = rr;
+          rq[q + 1] = 0.0;
+          g[q + 1] = -sn[q] * g[q];
+          g[q] = cs[q] * g[q];
+        }
+        if (bad) {
+          breakdown = true;
+          break;
+        }
+        its++;
+        jend = j + 1;
+        const double est = std::fabs(g[j + 1]) / bnorm;
+        if (info && info->history && info->history_len < info->history_cap) info->history[info->history_len++] = est;
+        if (!std::isfinite(est)) {
+          breakdown = true;
+          break;
+        }
+        if (est <= rtol || its >= maxit || eta == 0.0) break;
+      }
+    } else
+    for (int j = 0; j < m; ++j) {
+      double *w = V + (size_t)(j + 1) * n;
+      if ((rc = apply_op(j))) return rc;
       double *col = &R[(size_t)j * (m + 1)];
       double hn;
       bool scaled = false;

@@ -195,6 +195,77 @@ __global__ void __launch_bounds__(kBlock) k_gs_update_scale(const double *__rest
   w[i] = v * s;
 }
 
+// Gram-Schmidt with delayed reorthogonalisation: one reduction pass and one update pass over the
+// basis per step.  u = a_j was orthogonalised once in the previous step; w = a_{j+1} is the new
+// vector.  Outputs (in partial, then summed): a_k . u for k <= j at [k], a_k . w for k <= j at
+// [j + 1 + k], and w . w at [2 j + 2].  The waves of a workgroup share the elements and split the
+// basis vectors (wave q takes k = q, q + 4, ...), so each thread holds 2 KW accumulators.
+template <int KW>
+__global__ void __launch_bounds__(kBlock) k_dgs_dots(const double *__restrict__ a, size_t lda, int j, size_t n,
+                                                     double *__restrict__ partial) {
+  constexpr int NW = kBlock / 64;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double au[KW], aw[KW], ww = 0.0;
+#pragma unroll
+  for (int q = 0; q < KW; ++q) au[q] = aw[q] = 0.0;
+  const double *u = a + (size_t)j * lda, *w = a + (size_t)(j + 1) * lda;
+  const size_t stride = (size_t)gridDim.x * 64;
+  for (size_t i = (size_t)blockIdx.x * 64 + lane; i < n; i += stride) {
+    const double ui = u[i], wi = w[i];
+#pragma unroll
+    for (int q = 0; q < KW; ++q) {
+      const int k = wv + NW * q;
+      if (k < j) {
+        const double v = a[(size_t)k * lda + i];
+        au[q] += v * ui;
+        aw[q] += v * wi;
+      } else if (k == j) {
+        au[q] += ui * ui;
+        aw[q] += ui * wi;
+      }
+    }
+    if (wv == 0) ww += wi * wi;
+  }
+  const size_t nb = gridDim.x;
+#pragma unroll
+  for (int q = 0; q < KW; ++q) {
+    const int k = wv + NW * q;
+    if (k <= j) {
+      const double x = wave_sum(au[q]), y = wave_sum(aw[q]);
+      if (lane == 0) partial[(size_t)k * nb + blockIdx.x] = x, partial[(size_t)(j + 1 + k) * nb + blockIdx.x] = y;
+    }
+  }
+  if (wv == 0) {
+    const double z = wave_sum(ww);
+    if (lane == 0) partial[(size_t)(2 * j + 2) * nb + blockIdx.x] = z;
+  }
+}
+
+struct DgsCoef {
+  double a[32], b[32];
+};
+
+// The update pass: a_j <- (u - sum_{k<j} ca_k a_k) rinv (the reorthogonalised, normalised u) and
+// a_{j+1} <- (w - sum_{k<j} cb_k a_k - hjj a_j) einv (w orthogonalised once and scaled).
+template <int NV>
+__global__ void __launch_bounds__(kBlock) k_dgs_update(double *__restrict__ a, size_t lda, int j, DgsCoef cf,
+                                                       double rinv, double hjj, double einv, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double su = 0.0, sw = 0.0;
+#pragma unroll
+  for (int k = 0; k < NV; ++k)
+    if (k < j) {
+      const double v = a[(size_t)k * lda + i];
+      su += cf.a[k] * v;
+      sw += cf.b[k] * v;
+    }
+  double *u = a + (size_t)j * lda, *w = a + (size_t)(j + 1) * lda;
+  const double vj = (u[i] - su) * rinv;
+  u[i] = vj;
+  w[i] = (w[i] - sw - hjj * vj) * einv;
+}
+
 template <typename Tz>
 __global__ void k_update_solution(const Tz *__restrict__ Z, size_t ldz, int nv, const double *__restrict__ y,
                                   double *__restrict__ x, size_t n) {
@@ -291,6 +362,38 @@ hipError_t launch_gs_finish(hyb_ctx *c, const double *V, size_t n, int nv, const
     hipLaunchKernelGGL((k_gs_update_scale<16>), dim3(nblk(n)), dim3(kBlock), 0, c->stream, V, n, nv, h2, w, n, s);
   else
     hipLaunchKernelGGL((k_gs_update_scale<32>), dim3(nblk(n)), dim3(kBlock), 0, c->stream, V, n, nv, h2, w, n, s);
+  prof_end(c, F_KRYLOV, slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_dgs_dots(hyb_ctx *c, const double *V, size_t n, int j, double *out_dev) {
+  if (j < 0 || j >= kDgsMax || 2 * j + 3 > 2 * (c->m + 2)) return hipErrorInvalidValue;
+  int slot = prof_begin(c, F_KRYLOV);
+  const unsigned nb = std::min<unsigned>(kRedBlocks, nblk(n, 64));  // 64 elements per workgroup and step
+  static_assert(kBlock == 256, "four waves split the basis vectors");
+  if (j < 8)
+    hipLaunchKernelGGL((k_dgs_dots<2>), dim3(nb), dim3(kBlock), 0, c->stream, V, n, j, n, c->partial);
+  else if (j < 16)
+    hipLaunchKernelGGL((k_dgs_dots<4>), dim3(nb), dim3(kBlock), 0, c->stream, V, n, j, n, c->partial);
+  else
+    hipLaunchKernelGGL((k_dgs_dots<8>), dim3(nb), dim3(kBlock), 0, c->stream, V, n, j, n, c->partial);
+  hipLaunchKernelGGL(k_multidot_final, dim3(2 * j + 3), dim3(kBlock), 0, c->stream, c->partial, (int)nb, out_dev);
+  prof_end(c, F_KRYLOV, slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_dgs_update(hyb_ctx *c, double *V, size_t n, int j, const double *ca, const double *cb, double rinv,
+                             double hjj, double einv) {
+  if (j < 0 || j >= kDgsMax) return hipErrorInvalidValue;
+  DgsCoef cf{};
+  for (int k = 0; k < j; ++k) cf.a[k] = ca[k], cf.b[k] = cb[k];
+  int slot = prof_begin(c, F_KRYLOV);
+  if (j < 8)
+    hipLaunchKernelGGL((k_dgs_update<8>), dim3(nblk(n)), dim3(kBlock), 0, c->stream, V, n, j, cf, rinv, hjj, einv, n);
+  else if (j < 16)
+    hipLaunchKernelGGL((k_dgs_update<16>), dim3(nblk(n)), dim3(kBlock), 0, c->stream, V, n, j, cf, rinv, hjj, einv, n);
+  else
+    hipLaunchKernelGGL((k_dgs_update<32>), dim3(nblk(n)), dim3(kBlock), 0, c->stream, V, n, j, cf, rinv, hjj, einv, n);
   prof_end(c, F_KRYLOV, slot);
   return hipGetLastError();
 }

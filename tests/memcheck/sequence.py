@@ -133,6 +133,20 @@ def solver_sequence(lib):
                 "krylov", "cell_solve", "nn"):
         c.call("hyb_profile_read", fam.encode(), ctypes.byref(n), ctypes.byref(ms))
     c.call("hyb_profile", 0)
+    c.call("hyb_profile_family", b"krylov")
+    c.solve(b, 1e-6)
+    c.call("hyb_profile_read", b"krylov", ctypes.byref(n), ctypes.byref(ms))
+    check(n.value > 0 and lib.hyb_profile_read(c.h, b"smooth_rows", ctypes.byref(n), ctypes.byref(ms)) == 0
+          and n.value == 0, "single-family profiling records that family only")
+    check(lib.hyb_profile_family(c.h, b"nonsense") < 0, "unknown profiling family rejected")
+    c.call("hyb_profile", 0)
+    # restart cycles longer than the delayed-reorthogonalisation limit take the three-pass and
+    # the conditional second-pass Gram-Schmidt paths
+    c.set(precision=N.PREC_FP64, restart=40)
+    rc, info, lam = c.solve(b, 0.0, maxit=36)
+    res = c.residual(b, lam)
+    check(info.iters == 36 and res <= 1e-12, f"fp64 FGMRES(40), 36 steps without a tolerance: residual {res:.1e}")
+    c.set(restart=30)
     c2 = Ctx(lib, make_box(nx=4, ny=4, nlev=66, dx=5e3, dz=150.0, mg_levels=2, seed=8))  # nlev > 64: Thomas path
     _, _, b2 = c2.rhs(3)
     rc2, info2, lam2 = c2.solve(b2, 1e-10)

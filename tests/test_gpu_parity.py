@@ -208,6 +208,16 @@ def test_edge_cases():
     lam.zero_()
     info3 = s.solve(b, lam, rtol=1e-8, maxit=400)
     assert info3["status"] == 0 and info3["restarts"] >= 1
+    # cycles longer than 31 steps use three-pass Gram-Schmidt (and a conditional second pass from
+    # step 32 on) instead of the delayed reorthogonalisation: run 36 steps without a tolerance
+    s.set_params(params_for(prob, restart=40))
+    lam.zero_()
+    info4 = s.solve(b, lam, rtol=0.0, maxit=36)
+    y = torch.empty_like(b)
+    s.trace_apply(lam, y)
+    res4 = float(torch.linalg.norm(b - y) / torch.linalg.norm(b))
+    say(f"[restart 40] 36 steps: true residual {res4:.1e}")
+    assert info4["iters"] == 36 and res4 <= 1e-11
     s.set_params(params_for(prob))
     # bad arguments are rejected, not crashed on
     with pytest.raises(RuntimeError):
