@@ -262,33 +262,61 @@ __global__ void __launch_bounds__(64 * kMW) k_p1_condense_mfma(int ncell, const 
                                                               const double *__restrict__ kdiag,
                                                               double *__restrict__ SK) {
   __shared__ float sM[kMW][MP * LDM];
+  __shared__ double sC[kMW][NF];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int c = xcd_block() * kMW + wv;
   const bool active = c < ncell;  // uniform within a wavefront
   float *M = sM[wv];
   if (active) {
+    // A_K (contiguous per cell) in batches of 8 loads per lane, all in flight together; then the
+    // padding (identity), the right-hand sides [K; 0] and C_F
     const double *Ac = A + (size_t)c * NA;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int idx = (8 * b + q) * 64 + lane;
+        v[q] = idx < NA ? Ac[idx] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int idx = (8 * b + q) * 64 + lane;
+        if (idx < NA) {
+          const int i = idx / NX, j = idx - i * NX;
+          M[i * LDM + j] = (float)v[q];
+        }
+      }
+    }
     for (int e = lane; e < MP * MW; e += 64) {
       const int i = e / MW, j = e - i * MW;
-      float v;
-      if (j < MP) {
-        v = (i < NX && j < NX) ? (float)Ac[i * NX + j] : (i == j ? 1.f : 0.f);
-      } else {
-        const int q = j - MP;
-        v = (i == q && q < NF) ? (float)kdiag[(size_t)c * NF + q] : 0.f;
-      }
+      if (i < NX && j < NX) continue;
+      float v = (j < MP && i == j) ? 1.f : 0.f;
+      if (j - MP == i && i < NF) v = (float)kdiag[(size_t)c * NF + i];
       M[i * LDM + j] = v;
     }
+    if (lane < NF) sC[wv][lane] = cdiag[(size_t)c * NF + lane];
   }
   __syncthreads();
+  const int rr = lane >> 4, cc = lane & 15;  // panel steps: 4 rows x 16 columns of lanes
   for (int kb = 0; kb < 3; ++kb) {
     const int r0 = 16 * kb, rend = r0 + 16;
-    for (int k = r0; k < rend; ++k) {
-      if (active && lane > k && lane < MP) {
-        const float l = M[lane * LDM + k] / M[k * LDM + k];
-        M[lane * LDM + k] = l;
-        const int jend = lane < rend ? MW : rend;  // block rows: whole row (U12, RHS); below: the panel
-        for (int j = k + 1; j < jend; ++j) M[lane * LDM + j] -= l * M[k * LDM + j];
+    for (int k = r0; k <= rend; ++k) {
+      if (active) {
+        // the multipliers of column k - 1 for the rows below the block (L21, read by the MFMA
+        // update), stored one step late so that no lane overwrites an entry another lane reads
+        if (k > r0)
+          for (int r = rend + lane; r < MP; r += 64) M[r * LDM + k - 1] /= M[(k - 1) * LDM + k - 1];
+        if (k < rend) {
+          // rows of the block below the pivot: whole rows (U12 and the right-hand sides); rows
+          // below the block: the panel columns only (their trailing part is the MFMA update)
+          const float inv = 1.f / M[k * LDM + k];
+          for (int r = k + 1 + rr; r < MP; r += 4) {
+            const float l = M[r * LDM + k] * inv;
+            const int jend = r < rend ? MW : rend;
+            for (int j = k + 1 + cc; j < jend; j += 16) M[r * LDM + j] -= l * M[k * LDM + j];
+          }
+        }
       }
       __syncthreads();
     }
@@ -303,12 +331,15 @@ __global__ void __launch_bounds__(64 * kMW) k_p1_condense_mfma(int ncell, const 
   }
   for (int kb = 2; kb >= 0; --kb) {
     const int r0 = 16 * kb;
-    if (active && lane < 32) {
-      const int col = MP + lane;
+    if (active) {
+      // back substitution in the diagonal block: lane l takes right-hand side l mod 32 and every
+      // other term of the row sum (l / 32), the halves are combined across the wavefront
+      const int col = MP + (lane & 31), half = lane >> 5;
       for (int i = r0 + 15; i >= r0; --i) {
-        float sum = M[i * LDM + col];
-        for (int m = i + 1; m < r0 + 16; ++m) sum -= M[i * LDM + m] * M[m * LDM + col];
-        M[i * LDM + col] = sum / M[i * LDM + i];
+        float part = 0.f;
+        for (int m = i + 1 + half; m < r0 + 16; m += 2) part += M[i * LDM + m] * M[m * LDM + col];
+        const float sum = part + __shfl_xor(part, 32);
+        if (half == 0) M[i * LDM + col] = (M[i * LDM + col] - sum) / M[i * LDM + i];
       }
     }
     __syncthreads();
@@ -321,11 +352,15 @@ __global__ void __launch_bounds__(64 * kMW) k_p1_condense_mfma(int ncell, const 
       }
     __syncthreads();
   }
-  if (active)
-    for (int e = lane; e < NS; e += 64) {
+  // thread t writes cell t mod kMW of the workgroup: each store covers kMW consecutive cells
+  const int w = threadIdx.x % kMW, cw = c - wv + w;
+  if (cw < ncell) {
+    const float *Mw = sM[w];
+    for (int e = threadIdx.x / kMW; e < NS; e += 64) {
       const int r = e / NF, q = e - r * NF;
-      SK[(size_t)e * ncell + c] = cdiag[(size_t)c * NF + r] * (double)M[r * LDM + MP + q];
+      SK[(size_t)e * ncell + cw] = sC[w][r] * (double)Mw[r * LDM + MP + q];
     }
+  }
 }
 
 // Global trace dof of local face dof j of cell (k, col).
@@ -392,18 +427,21 @@ __global__ void __launch_bounds__(64 * kSW) k_p1_condense_struct(int ncell, cons
                                                                 double *__restrict__ SK, double *__restrict__ fac,
                                                                 int write_sk) {
   __shared__ double sMi[kSW][108], sG[kSW][288], sDr[kSW][288], sMiG[kSW][288], sDrMi[kSW][288], sSg[kSW][64],
-      sT[kSW][192];
+      sT[kSW][192], sCK[kSW][2 * NF];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int c = xcd_block() * kSW + wv;
   const bool active = c < ncell;
   double *Mi = sMi[wv], *G = sG[wv], *Dr = sDr[wv], *MiG = sMiG[wv], *DrMi = sDrMi[wv], *Sg = sSg[wv], *T = sT[wv];
   const double *Ac = A + (size_t)c * NA;
   if (active) {
+#pragma unroll
     for (int e = lane; e < 288; e += 64) {
       const int a = e >> 3, p = e & 7;
       G[e] = Ac[a * NX + NU + p];              // G[a][p]
       Dr[p * NU + a] = Ac[(NU + p) * NX + a];  // Dr[p][a]
     }
+    if (lane < NF) sCK[wv][lane] = cdiag[(size_t)c * NF + lane];
+    else if (lane < 2 * NF) sCK[wv][lane] = kdiag[(size_t)c * NF + lane - NF];
     Sg[lane] = Ac[(NU + (lane >> 3)) * NX + NU + (lane & 7)];  // P
     if (lane < 12) {  // invert the 3x3 block by cofactors
       double m[3][3];
@@ -484,7 +522,7 @@ __global__ void __launch_bounds__(64 * kSW) k_p1_condense_struct(int ncell, cons
       dof_blk(f, bf, pf);
       double v = (br == bf) ? wMi[9 * br + 3 * pr + pf] : 0.0;
       for (int p = 0; p < 8; ++p) v += wMiG[r * 8 + p] * wT[p * NF + f];
-      SK[(size_t)e * ncell + cw] = cdiag[cw * NF + r] * v * kdiag[cw * NF + f];
+      SK[(size_t)e * ncell + cw] = sCK[w][r] * v * sCK[w][NF + f];
     }
   for (int e = threadIdx.x / kSW; e < NFAC; e += 64) {
     double v;

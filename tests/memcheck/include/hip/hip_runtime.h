@@ -81,6 +81,20 @@ inline T __shfl(T v, int src, int width = 64) {
 }
 
 template <typename T>
+inline T __shfl_xor(T v, int mask, int width = 64) {
+  static_assert(sizeof(T) <= 8, "shfl of a large type");
+  const unsigned tid = emu::cur_tid();
+  std::memcpy(emu::xchg(tid), &v, sizeof(T));
+  emu::wave_barrier();
+  const unsigned lane = tid % 64u, seg = lane - lane % (unsigned)width;
+  const unsigned src = lane ^ (unsigned)mask;
+  T r = v;
+  if (src >= seg && src < seg + (unsigned)width) std::memcpy(&r, emu::xchg(tid - lane + src), sizeof(T));
+  emu::wave_barrier();
+  return r;
+}
+
+template <typename T>
 inline T __shfl_up(T v, unsigned off, int width = 64) {
   static_assert(sizeof(T) <= 8, "shfl of a large type");
   const unsigned tid = emu::cur_tid();
