@@ -209,15 +209,19 @@ __global__ void __launch_bounds__(kBlock) k_p1_assemble(int ncell, int ncol, con
 
 // ---- condensation on MFMA ------------------------------------------------------------------------
 // S_K from A_K and K_K with matrix cores: one wavefront per cell; [A_K | [K_K; 0]] padded to 48 rows,
-// 48 + 32 columns (identity on the padding), FP32 in LDS.  Blocked right-looking elimination without
-// pivoting, block 16: the 16-column panel (and the 16-row block to its right) by the lanes, the
-// trailing update A22 -= L21 U12 as 16x16 tiles on MFMA; then the blocked back substitution with U,
-// whose off-diagonal block products are MFMA tiles too.  SPLIT: each FP32 operand is split into
-// BF16 hi + lo and a tile product is hi*lo + lo*hi + hi*hi (FP32 accumulation), else FP32 MFMA.
+// 48 + 32 columns (identity on the padding), FP32, held in registers as 3 x 5 tiles of 16 x 16 in the
+// accumulator layout of the 16x16 MFMA (lane l: rows 4 (l / 16) .. + 3, column l mod 16 of every
+// tile).  Blocked right-looking elimination without pivoting, block 16: within a block each pivot
+// row and column is shuffled across the lanes and the lanes update their own entries; after the block
+// the trailing update A22 -= L21 U12 runs on MFMA straight into the accumulators (L21 and U12
+// staged through LDS into the operand layouts).  Then the blocked back substitution: the diagonal
+// blocks row by row, the blocks above by MFMA.  SPLIT: each FP32 operand is split into BF16 hi + lo
+// and a tile product is hi*lo + lo*hi + hi*hi (FP32 accumulation), else FP32 MFMA.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
-constexpr int MP = 48, MW = 80, LDM = 81;  // padded size, augmented width, LDS row stride (odd)
-constexpr int kMW = 4;                     // cells (wavefronts) per workgroup
+constexpr int MP = 48, MW = 80;  // padded size, augmented width
+constexpr int TS = 17;           // row stride of a 16 x 16 tile staged in LDS
+constexpr int kMW = 4;           // cells (wavefronts) per workgroup
 
 __device__ __forceinline__ short bf16_rne(float f) {
   const unsigned u = __float_as_uint(f);
@@ -225,26 +229,31 @@ __device__ __forceinline__ short bf16_rne(float f) {
 }
 __device__ __forceinline__ float bf16_val(short h) { return __uint_as_float(((unsigned)(unsigned short)h) << 16); }
 
-// P = M[r0:r0+16, k0:k0+16] M[k0:k0+16, c0:c0+16]; lane layouts of the two instructions: FP32 16x16x4:
+// entry q of an accumulator with q known only at run time (no dynamic register indexing)
+__device__ __forceinline__ float f4_get(const f32x4 &v, int q) {
+  return q == 0 ? v[0] : (q == 1 ? v[1] : (q == 2 ? v[2] : v[3]));
+}
+__device__ __forceinline__ void f4_set(f32x4 &v, int q, float x) {
+  if (q == 0) v[0] = x;
+  else if (q == 1) v[1] = x;
+  else if (q == 2) v[2] = x;
+  else v[3] = x;
+}
+
+// acc - L U for 16 x 16 tiles L, U staged row-major in LDS.  Operand layouts: FP32 16x16x4:
 // a = A[l%16][l/16], b = B[l/16][l%16]; BF16 16x16x16: a[j] = A[l%16][4(l/16)+j], b[j] = B[4(l/16)+j][l%16];
-// result: d[j] = P[4(l/16)+j][l%16]
+// result d[j] = D[4(l/16)+j][l%16], the layout of acc.
 template <bool SPLIT>
-__device__ __forceinline__ f32x4 tile_product(const float *M, int r0, int k0, int c0, int lane) {
-  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-  const int lr = lane & 15, lk = lane >> 4;
+__device__ __forceinline__ f32x4 tile_msub(const float *L, const float *U, f32x4 acc, int lc, int lg) {
   if constexpr (!SPLIT) {
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      const float a = M[(r0 + lr) * LDM + k0 + 4 * kk + lk];
-      const float b = M[(k0 + 4 * kk + lk) * LDM + c0 + lr];
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
-    }
+    for (int s = 0; s < 4; ++s)
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(-L[lc * TS + 4 * s + lg], U[(4 * s + lg) * TS + lc], acc, 0, 0, 0);
   } else {
     bf16x4 ah, al, bh, bl;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const float a = M[(r0 + lr) * LDM + k0 + 4 * lk + j];
-      const float b = M[(k0 + 4 * lk + j) * LDM + c0 + lr];
+      const float a = -L[lc * TS + 4 * lg + j], b = U[(4 * lg + j) * TS + lc];
       const short a1 = bf16_rne(a), b1 = bf16_rne(b);
       ah[j] = a1, al[j] = bf16_rne(a - bf16_val(a1));
       bh[j] = b1, bl[j] = bf16_rne(b - bf16_val(b1));
@@ -256,109 +265,182 @@ __device__ __forceinline__ f32x4 tile_product(const float *M, int r0, int k0, in
   return acc;
 }
 
+struct MfmaLds {
+  float stg[6][16 * TS];  // tiles staged for MFMA operands; at the end the 24 x 24 result
+};
+
+// The 16 pivots of block KB.  Lane l holds column 16 tj + l mod 16 of rows 16 ti + 4 (l / 16) + q,
+// so the pivot row's entry of a lane's column comes from lane 16 (kk / 4) + l mod 16 and the pivot
+// column's entry of a lane's row from lane 16 (l / 16) + kk: shuffles, no barriers.
+template <int KB>
+__device__ __forceinline__ void mf_elim_block(f32x4 (&acc)[3][5], int lc, int lg) {
+  for (int kk = 0; kk < 16; ++kk) {
+    const int k = 16 * KB + kk, qk = kk & 3, src_row = 16 * (kk >> 2) + lc, src_col = 16 * lg + kk;
+    float prow[5], pcol[3][4];
+#pragma unroll
+    for (int tj = KB; tj < 5; ++tj) prow[tj] = __shfl(f4_get(acc[KB][tj], qk), src_row);
+    const float inv = 1.f / __shfl(prow[KB], kk);  // lane kk holds column k of the pivot row
+#pragma unroll
+    for (int ti = KB; ti < 3; ++ti)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) pcol[ti][q] = __shfl(acc[ti][KB][q], src_col);
+    // rows of the block below the pivot: every column right of it (U12 and the right-hand sides)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (16 * KB + 4 * lg + q > k) {
+        const float l = pcol[KB][q] * inv;
+#pragma unroll
+        for (int tj = KB; tj < 5; ++tj)
+          if (16 * tj + lc > k) acc[KB][tj][q] -= l * prow[tj];
+      }
+    }
+    // rows below the block: the panel columns right of the pivot; the multiplier into column k
+#pragma unroll
+    for (int ti = KB + 1; ti < 3; ++ti)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float l = pcol[ti][q] * inv;
+        const int j = 16 * KB + lc;
+        if (j > k) acc[ti][KB][q] -= l * prow[KB];
+        else if (j == k) acc[ti][KB][q] = l;
+      }
+  }
+}
+
+// A22 -= L21 U12 after block KB (KB < 2); every wavefront of the workgroup reaches the barriers
+template <int KB, bool SPLIT>
+__device__ __forceinline__ void mf_trailing(f32x4 (&acc)[3][5], MfmaLds &S, bool active, int lc, int lg) {
+  if (active) {
+#pragma unroll
+    for (int ti = KB + 1; ti < 3; ++ti)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) S.stg[ti - KB - 1][(4 * lg + q) * TS + lc] = acc[ti][KB][q];
+#pragma unroll
+    for (int tj = KB + 1; tj < 5; ++tj)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) S.stg[2 + tj - KB - 1][(4 * lg + q) * TS + lc] = acc[KB][tj][q];
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int ti = KB + 1; ti < 3; ++ti)
+#pragma unroll
+      for (int tj = KB + 1; tj < 5; ++tj)
+        acc[ti][tj] = tile_msub<SPLIT>(S.stg[ti - KB - 1], S.stg[2 + tj - KB - 1], acc[ti][tj], lc, lg);
+  }
+  __syncthreads();
+}
+
+// Back substitution of block row KB for the right-hand-side tiles 3 and 4 (row by row, the solved
+// row and the U column shuffled across the lanes), then their update in the block rows above (MFMA)
+template <int KB, bool SPLIT>
+__device__ __forceinline__ void mf_back_block(f32x4 (&acc)[3][5], MfmaLds &S, bool active, int lc, int lg) {
+  if (active)
+    for (int ii = 15; ii >= 0; --ii) {
+      const int qi = ii & 3, src_row = 16 * (ii >> 2) + lc, src_col = 16 * lg + ii;
+      const float d = 1.f / __shfl(f4_get(acc[KB][KB], qi), 16 * (ii >> 2) + ii);
+      const float x3 = __shfl(f4_get(acc[KB][3], qi), src_row) * d;
+      const float x4 = __shfl(f4_get(acc[KB][4], qi), src_row) * d;
+      if (lg == (ii >> 2)) {
+        f4_set(acc[KB][3], qi, x3);
+        f4_set(acc[KB][4], qi, x4);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float u = __shfl(acc[KB][KB][q], src_col);
+        if (4 * lg + q < ii) {
+          acc[KB][3][q] -= u * x3;
+          acc[KB][4][q] -= u * x4;
+        }
+      }
+    }
+  if constexpr (KB > 0) {
+    if (active) {
+#pragma unroll
+      for (int ti = 0; ti < KB; ++ti)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) S.stg[1 + ti][(4 * lg + q) * TS + lc] = acc[ti][KB][q];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        S.stg[3][(4 * lg + q) * TS + lc] = acc[KB][3][q];
+        S.stg[4][(4 * lg + q) * TS + lc] = acc[KB][4][q];
+      }
+    }
+    __syncthreads();
+    if (active)
+#pragma unroll
+      for (int ti = 0; ti < KB; ++ti) {
+        acc[ti][3] = tile_msub<SPLIT>(S.stg[1 + ti], S.stg[3], acc[ti][3], lc, lg);
+        acc[ti][4] = tile_msub<SPLIT>(S.stg[1 + ti], S.stg[4], acc[ti][4], lc, lg);
+      }
+    __syncthreads();
+  }
+}
+
 template <bool SPLIT>
 __global__ void __launch_bounds__(64 * kMW) k_p1_condense_mfma(int ncell, const double *__restrict__ A,
                                                               const double *__restrict__ cdiag,
                                                               const double *__restrict__ kdiag,
                                                               double *__restrict__ SK) {
-  __shared__ float sM[kMW][MP * LDM];
+  __shared__ MfmaLds sL[kMW];
   __shared__ double sC[kMW][NF];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lc = lane & 15, lg = lane >> 4;
   const int c = xcd_block() * kMW + wv;
   const bool active = c < ncell;  // uniform within a wavefront
-  float *M = sM[wv];
+  MfmaLds &S = sL[wv];
+  f32x4 acc[3][5];
   if (active) {
-    // A_K (contiguous per cell) in batches of 8 loads per lane, all in flight together; then the
-    // padding (identity), the right-hand sides [K; 0] and C_F
     const double *Ac = A + (size_t)c * NA;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      double v[8];
+    for (int ti = 0; ti < 3; ++ti)
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int idx = (8 * b + q) * 64 + lane;
-        v[q] = idx < NA ? Ac[idx] : 0.0;
-      }
+      for (int tj = 0; tj < 5; ++tj)
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int idx = (8 * b + q) * 64 + lane;
-        if (idx < NA) {
-          const int i = idx / NX, j = idx - i * NX;
-          M[i * LDM + j] = (float)v[q];
+        for (int q = 0; q < 4; ++q) {
+          const int r = 16 * ti + 4 * lg + q, j = 16 * tj + lc;
+          float v;
+          if (r < NX && j < NX) v = (float)Ac[r * NX + j];
+          else if (j < MP) v = (r == j) ? 1.f : 0.f;
+          else v = (j - MP == r && r < NF) ? (float)kdiag[(size_t)c * NF + r] : 0.f;
+          acc[ti][tj][q] = v;
         }
-      }
-    }
-    for (int e = lane; e < MP * MW; e += 64) {
-      const int i = e / MW, j = e - i * MW;
-      if (i < NX && j < NX) continue;
-      float v = (j < MP && i == j) ? 1.f : 0.f;
-      if (j - MP == i && i < NF) v = (float)kdiag[(size_t)c * NF + i];
-      M[i * LDM + j] = v;
-    }
     if (lane < NF) sC[wv][lane] = cdiag[(size_t)c * NF + lane];
+  } else {
+#pragma unroll
+    for (int ti = 0; ti < 3; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 5; ++tj) acc[ti][tj] = f32x4{0.f, 0.f, 0.f, 0.f};
   }
-  __syncthreads();
-  const int rr = lane >> 4, cc = lane & 15;  // panel steps: 4 rows x 16 columns of lanes
-  for (int kb = 0; kb < 3; ++kb) {
-    const int r0 = 16 * kb, rend = r0 + 16;
-    for (int k = r0; k <= rend; ++k) {
-      if (active) {
-        // the multipliers of column k - 1 for the rows below the block (L21, read by the MFMA
-        // update), stored one step late so that no lane overwrites an entry another lane reads
-        if (k > r0)
-          for (int r = rend + lane; r < MP; r += 64) M[r * LDM + k - 1] /= M[(k - 1) * LDM + k - 1];
-        if (k < rend) {
-          // rows of the block below the pivot: whole rows (U12 and the right-hand sides); rows
-          // below the block: the panel columns only (their trailing part is the MFMA update)
-          const float inv = 1.f / M[k * LDM + k];
-          for (int r = k + 1 + rr; r < MP; r += 4) {
-            const float l = M[r * LDM + k] * inv;
-            const int jend = r < rend ? MW : rend;
-            for (int j = k + 1 + cc; j < jend; j += 16) M[r * LDM + j] -= l * M[k * LDM + j];
-          }
+  if (active) mf_elim_block<0>(acc, lc, lg);
+  mf_trailing<0, SPLIT>(acc, S, active, lc, lg);
+  if (active) mf_elim_block<1>(acc, lc, lg);
+  mf_trailing<1, SPLIT>(acc, S, active, lc, lg);
+  if (active) mf_elim_block<2>(acc, lc, lg);
+  mf_back_block<2, SPLIT>(acc, S, active, lc, lg);
+  mf_back_block<1, SPLIT>(acc, S, active, lc, lg);
+  mf_back_block<0, SPLIT>(acc, S, active, lc, lg);
+  // X = the rows 0..23 of the solution in the right-hand-side columns 0..23 -> LDS, then S_K = C X
+  float *X = &S.stg[0][0];
+  if (active)
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = 16 * ti + 4 * lg + q;
+        if (r < NF) {
+          X[r * NF + lc] = acc[ti][3][q];
+          if (lc < NF - 16) X[r * NF + 16 + lc] = acc[ti][4][q];
         }
       }
-      __syncthreads();
-    }
-    for (int tr = kb + 1; tr < 3; ++tr)
-      for (int tc = kb + 1; tc < 5; ++tc) {
-        if (!active) continue;
-        const f32x4 p = tile_product<SPLIT>(M, 16 * tr, r0, 16 * tc, lane);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) M[(16 * tr + 4 * (lane >> 4) + j) * LDM + 16 * tc + (lane & 15)] -= p[j];
-      }
-    __syncthreads();
-  }
-  for (int kb = 2; kb >= 0; --kb) {
-    const int r0 = 16 * kb;
-    if (active) {
-      // back substitution in the diagonal block: lane l takes right-hand side l mod 32 and every
-      // other term of the row sum (l / 32), the halves are combined across the wavefront
-      const int col = MP + (lane & 31), half = lane >> 5;
-      for (int i = r0 + 15; i >= r0; --i) {
-        float part = 0.f;
-        for (int m = i + 1 + half; m < r0 + 16; m += 2) part += M[i * LDM + m] * M[m * LDM + col];
-        const float sum = part + __shfl_xor(part, 32);
-        if (half == 0) M[i * LDM + col] = (M[i * LDM + col] - sum) / M[i * LDM + i];
-      }
-    }
-    __syncthreads();
-    for (int tr = 0; tr < kb; ++tr)
-      for (int tc = 3; tc < 5; ++tc) {
-        if (!active) continue;
-        const f32x4 p = tile_product<SPLIT>(M, 16 * tr, r0, 16 * tc, lane);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) M[(16 * tr + 4 * (lane >> 4) + j) * LDM + 16 * tc + (lane & 15)] -= p[j];
-      }
-    __syncthreads();
-  }
+  __syncthreads();
   // thread t writes cell t mod kMW of the workgroup: each store covers kMW consecutive cells
   const int w = threadIdx.x % kMW, cw = c - wv + w;
   if (cw < ncell) {
-    const float *Mw = sM[w];
+    const float *Xw = &sL[w].stg[0][0];
     for (int e = threadIdx.x / kMW; e < NS; e += 64) {
-      const int r = e / NF, q = e - r * NF;
-      SK[(size_t)e * ncell + cw] = sC[w][r] * (double)Mw[r * LDM + MP + q];
+      const int r = e / NF;
+      SK[(size_t)e * ncell + cw] = sC[w][r] * (double)Xw[e];
     }
   }
 }
