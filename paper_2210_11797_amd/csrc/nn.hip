@@ -438,16 +438,19 @@ __global__ void __launch_bounds__(kBlock) k_inf_layer2_mfma(const uint16_t *__re
                                                            const uint16_t *__restrict__ wb2,
                                                            const float *__restrict__ bias, uint16_t *__restrict__ a2,
                                                            int nlev, int ncol, const int32_t *__restrict__ nb9) {
+  // the B operands of every tap in LDS, [tap][co][ci], so a lane reads its 4 input channels at once
+  __shared__ uint2 sB[NTAP][C1][C1 / 4];
+  for (int i = threadIdx.x; i < NTAP * C1 * (C1 / 4); i += blockDim.x) {
+    const int t = i / (C1 * C1 / 4), rem = i - t * (C1 * C1 / 4), co = rem / (C1 / 4), c4 = rem - co * (C1 / 4);
+    const unsigned w0 = wb2[(co * C1 + 4 * c4) * NTAP + t], w1 = wb2[(co * C1 + 4 * c4 + 1) * NTAP + t];
+    const unsigned w2 = wb2[(co * C1 + 4 * c4 + 2) * NTAP + t], w3 = wb2[(co * C1 + 4 * c4 + 3) * NTAP + t];
+    sB[t][co][c4] = make_uint2(w0 | (w1 << 16), w2 | (w3 << 16));
+  }
+  __syncthreads();
   const int lane = threadIdx.x & 63;
   const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const int ncell = nlev * ncol;
   const int r = lane & 15, q = lane >> 4;  // operand row / k-quarter
-  // B operands of all taps: lane holds W2[co = r][ci = 4 q + j][t], j = 0..3
-  nn_bf16x4 B[NTAP];
-#pragma unroll
-  for (int t = 0; t < NTAP; ++t)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) B[t][j] = (short)wb2[(r * C1 + 4 * q + j) * NTAP + t];
   const float bco = bias[r];
   for (int tile = 0; tile < kInfTiles; ++tile) {
     const int base = (wave * kInfTiles + tile) * 16;
@@ -467,7 +470,11 @@ __global__ void __launch_bounds__(kBlock) k_inf_layer2_mfma(const uint16_t *__re
           const uint2 u = *reinterpret_cast<const uint2 *>(a1 + ((size_t)kk * ncol + c2) * C1 + 4 * q);
           A[0] = (short)(u.x & 0xFFFFu), A[1] = (short)(u.x >> 16), A[2] = (short)(u.y & 0xFFFFu), A[3] = (short)(u.y >> 16);
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, B[h * NVT + v], acc, 0, 0, 0);
+        // B: lane holds W2[co = r][ci = 4 q + j][tap], j = 0..3
+        const uint2 w = sB[h * NVT + v][r][q];
+        nn_bf16x4 B;
+        B[0] = (short)(w.x & 0xFFFFu), B[1] = (short)(w.x >> 16), B[2] = (short)(w.y & 0xFFFFu), B[3] = (short)(w.y >> 16);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, B, acc, 0, 0, 0);
       }
     }
     // acc[j] = output channel r of cell base + 4 q + j
