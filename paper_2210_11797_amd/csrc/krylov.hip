@@ -198,33 +198,45 @@ __global__ void __launch_bounds__(kBlock) k_gs_update_scale(const double *__rest
 // Gram-Schmidt with delayed reorthogonalisation: one reduction pass and one update pass over the
 // basis per step.  u = a_j was orthogonalised once in the previous step; w = a_{j+1} is the new
 // vector.  Outputs (in partial, then summed): a_k . u for k <= j at [k], a_k . w for k <= j at
-// [j + 1 + k], and w . w at [2 j + 2].  The waves of a workgroup share the elements and split the
-// basis vectors (wave q takes k = q, q + 4, ...), so each thread holds 2 KW accumulators.
+// [j + 1 + k], and w . w at [2 j + 2].  A workgroup stages 256 entries of u and w in LDS; its waves
+// split the basis vectors (wave q takes k = q, q + 4, ...) and each runs over all 256 entries, so
+// every vector entry is loaded once and a thread keeps at most 2 KW accumulators.
 template <int KW>
 __global__ void __launch_bounds__(kBlock) k_dgs_dots(const double *__restrict__ a, size_t lda, int j, size_t n,
                                                      double *__restrict__ partial) {
   constexpr int NW = kBlock / 64;
+  __shared__ double su[kBlock], sw[kBlock], red[NW];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double au[KW], aw[KW], ww = 0.0;
 #pragma unroll
   for (int q = 0; q < KW; ++q) au[q] = aw[q] = 0.0;
   const double *u = a + (size_t)j * lda, *w = a + (size_t)(j + 1) * lda;
-  const size_t stride = (size_t)gridDim.x * 64;
-  for (size_t i = (size_t)blockIdx.x * 64 + lane; i < n; i += stride) {
-    const double ui = u[i], wi = w[i];
+  const size_t stride = (size_t)gridDim.x * kBlock;
+  for (size_t base = (size_t)blockIdx.x * kBlock; base < n; base += stride) {
+    const size_t i = base + threadIdx.x;
+    const double ui = i < n ? u[i] : 0.0, wi = i < n ? w[i] : 0.0;
+    ww += wi * wi;
+    __syncthreads();  // the previous entries are no longer read
+    su[threadIdx.x] = ui;
+    sw[threadIdx.x] = wi;
+    __syncthreads();
 #pragma unroll
-    for (int q = 0; q < KW; ++q) {
-      const int k = wv + NW * q;
-      if (k < j) {
-        const double v = a[(size_t)k * lda + i];
-        au[q] += v * ui;
-        aw[q] += v * wi;
-      } else if (k == j) {
-        au[q] += ui * ui;
-        aw[q] += ui * wi;
+    for (int g = 0; g < NW; ++g) {
+      const size_t ii = base + 64 * g + lane;
+      const double us = su[64 * g + lane], ws = sw[64 * g + lane];
+#pragma unroll
+      for (int q = 0; q < KW; ++q) {
+        const int k = wv + NW * q;
+        if (k < j) {
+          const double v = ii < n ? a[(size_t)k * lda + ii] : 0.0;
+          au[q] += v * us;
+          aw[q] += v * ws;
+        } else if (k == j) {
+          au[q] += us * us;
+          aw[q] += us * ws;
+        }
       }
     }
-    if (wv == 0) ww += wi * wi;
   }
   const size_t nb = gridDim.x;
 #pragma unroll
@@ -235,9 +247,14 @@ __global__ void __launch_bounds__(kBlock) k_dgs_dots(const double *__restrict__ 
       if (lane == 0) partial[(size_t)k * nb + blockIdx.x] = x, partial[(size_t)(j + 1 + k) * nb + blockIdx.x] = y;
     }
   }
-  if (wv == 0) {
-    const double z = wave_sum(ww);
-    if (lane == 0) partial[(size_t)(2 * j + 2) * nb + blockIdx.x] = z;
+  const double z = wave_sum(ww);
+  if (lane == 0) red[wv] = z;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) t += red[q];
+    partial[(size_t)(2 * j + 2) * nb + blockIdx.x] = t;
   }
 }
 
@@ -369,7 +386,7 @@ hipError_t launch_gs_finish(hyb_ctx *c, const double *V, size_t n, int nv, const
 hipError_t launch_dgs_dots(hyb_ctx *c, const double *V, size_t n, int j, double *out_dev) {
   if (j < 0 || j >= kDgsMax || 2 * j + 3 > 2 * (c->m + 2)) return hipErrorInvalidValue;
   int slot = prof_begin(c, F_KRYLOV);
-  const unsigned nb = std::min<unsigned>(kRedBlocks, nblk(n, 64));  // 64 elements per workgroup and step
+  const unsigned nb = std::min<unsigned>(kRedBlocks, nblk(n));
   static_assert(kBlock == 256, "four waves split the basis vectors");
   if (j < 8)
     hipLaunchKernelGGL((k_dgs_dots<2>), dim3(nb), dim3(kBlock), 0, c->stream, V, n, j, n, c->partial);
