@@ -36,6 +36,11 @@ P1_CONDENSE_FLOPS = 2.0 / 3.0 * 44**3 + 2 * 44**2 * 24
 P1_STRUCT_BYTES = 8 * (748 + 48 + 576 + 748)
 
 
+def coarsest_desc(args):
+    kind = "block-Jacobi sweeps" if args.coarse_jacobi else "Chebyshev steps over block Jacobi on [0.02, 2]"
+    return f"{args.coarse_sweeps} {kind}"
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -143,7 +148,7 @@ def algorithmic_bytes(ntr, ncell, ncol, nlev, its, fams, steps):
     return total
 
 
-def cpu_baseline(nx, nlev, dx, dz, dt, seeds=1):
+def cpu_baseline(nx, nlev, dx, dz, dt, coarse_sweeps, coarse_jacobi, seeds=1):
     """The oracle's hybridised FGMRES solve (condense RHS + FGMRES + recover) on a smaller box
     of the same physics, one BLAS thread; returns seconds per solve of the sample."""
     from threadpoolctl import threadpool_limits
@@ -154,7 +159,8 @@ def cpu_baseline(nx, nlev, dx, dz, dt, seeds=1):
     with threadpool_limits(limits=1):
         prob = make_box(nx=nx, ny=nx, nlev=nlev, dx=dx, dz=dz, dt=dt, mg_levels=4)
         t0 = time.perf_counter()
-        orc = OracleProblem(prob)
+        orc = OracleProblem(prob, mg_coarse_sweeps=coarse_sweeps,
+                            mg_coarse_cheb=None if coarse_jacobi else (0.02, 2.0))
         t_setup = time.perf_counter() - t0
         times, its = [], []
         for sd in range(seeds):
@@ -180,7 +186,7 @@ def learned_leg(args, prob, s, rhs, sec_plain, dx, dz, dt):
 
     nt = args.train_nx
     tprob = make_box(nx=nt, ny=nt, nlev=args.nlev, dx=dx, dz=dz, dt=dt, mg_levels=4)
-    ts = setup_solver(tprob, 0, mg_coarse_sweeps=args.coarse_sweeps)
+    ts = setup_solver(tprob, 0, mg_coarse_sweeps=args.coarse_sweeps, mg_coarse_cheb=0 if args.coarse_jacobi else 1)
     ts.nn_set_weights(learned.init_params(16, seed=0))
     d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()  # noqa: E731
     t0 = time.perf_counter()
@@ -232,7 +238,8 @@ def p1_leg(args):
     for name, prec, dtype in (("fp64", PREC_FP64, "fp64"), ("mfma_fp32", PREC_MFMA_FP32, "fp32"),
                               ("mfma_bf16x", PREC_MFMA_BF16X, "bf16")):
         params = Params(dt=prob.dt, tau_u=prob.tau_u, tau_rho=prob.tau_rho, tau_theta=prob.tau_theta, cp=prob.cp,
-                        rd=prob.rd, precision=prec, mg_coarse_sweeps=args.coarse_sweeps)
+                        rd=prob.rd, precision=prec, mg_coarse_sweeps=args.coarse_sweeps,
+                        mg_coarse_cheb=0 if args.coarse_jacobi else 1)
         s = HybSolver(prob.nlev, levels_of(prob), prob.dx, prob.dy, prob.dz, params, order=1)
         s.profile(True)
         torch.cuda.synchronize()
@@ -312,7 +319,10 @@ def main():
     ap.add_argument("--p1-nlev", type=int, default=32)
     ap.add_argument("--train-nx", type=int, default=64, help="box on which the learned stage is trained")
     ap.add_argument("--train-steps", type=int, default=1500)
-    ap.add_argument("--coarse-sweeps", type=int, default=30)
+    ap.add_argument("--coarse-sweeps", type=int, default=6,
+                    help="steps of the coarsest multigrid solve (Chebyshev semi-iteration, or block Jacobi)")
+    ap.add_argument("--coarse-jacobi", action="store_true",
+                    help="damped block-Jacobi sweeps on the coarsest level instead of the Chebyshev semi-iteration")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy (for scaling HBM counters), outside the timed region")
     args = ap.parse_args()
@@ -343,7 +353,7 @@ def main():
         log("copy calibration: 1073741824 bytes read, 1073741824 bytes written")
         del src, dst
     t0 = time.perf_counter()
-    s = setup_solver(prob, 0, mg_coarse_sweeps=args.coarse_sweeps)
+    s = setup_solver(prob, 0, mg_coarse_sweeps=args.coarse_sweeps, mg_coarse_cheb=0 if args.coarse_jacobi else 1)
     setup_s = time.perf_counter() - t0
     log(f"setup (assemble + condense + preconditioner) {setup_s * 1e3:.1f} ms, workspace {s.workspace_bytes() / 1e9:.2f} GB")
 
@@ -364,7 +374,7 @@ def main():
     per_solve_bytes = algorithmic_bytes(ntr, s.ncell, s.ncol, args.nlev, its, fams, args.steps)
     mixed = None
     if not args.no_mixed:
-        sm = setup_solver(prob, 1, mg_coarse_sweeps=args.coarse_sweeps)
+        sm = setup_solver(prob, 1, mg_coarse_sweeps=args.coarse_sweeps, mg_coarse_cheb=0 if args.coarse_jacobi else 1)
         msec, minfos, _ = run_steps(sm, rhs, args.steps, args.warmup, args.rtol, profile=False)
         mixed = dict(sec_per_solve=msec, iters=[i["iters"] for i in minfos],
                      rel_res=max(i["rel_res"] for i in minfos), speedup_vs_fp64=sec / msec)
@@ -385,7 +395,7 @@ def main():
     if not args.no_cpu_baseline:
         nxs = 64
         log(f"cpu baseline: oracle on a {nxs}x{nxs}x{args.nlev} sample ...")
-        cb = cpu_baseline(nxs, args.nlev, dx, dz, dt)
+        cb = cpu_baseline(nxs, args.nlev, dx, dz, dt, args.coarse_sweeps, args.coarse_jacobi)
         scale = prob.ncell / cb["ncell"]
         cpu = {"value": cb["sec_per_solve"] * scale, "unit": "s", "cores": 1, "kind": "oracle",
                "sample": (f"oracle FGMRES+two-level solve (condense RHS, solve to 1e-8, recover) on a "
@@ -407,7 +417,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"periodic box {args.nx}x{args.nx}x{args.nlev}, dx=5km, dz=250m, dt=600s, "
-                               f"RT0/Q0/trace, FGMRES(30)+two-level (1 pre/2 post, 4-level V-cycle), rtol 1e-8",
+                               f"RT0/Q0/trace, FGMRES(30)+two-level (1 pre/2 post, 4-level V-cycle, coarsest "
+                               f"{coarsest_desc(args)}), rtol 1e-8",
                    "ncell": ncell, "ntrace": ntr},
         "solves_per_s": 1.0 / sec,
         "iters": its,

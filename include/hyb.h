@@ -106,6 +106,13 @@ typedef struct {
      two-level cycle; learned_tau > 0: a correction d is kept only if ||r' - S d|| < learned_tau ||r'|| */
   int32_t learned;
   double learned_tau;
+  /* coarsest multigrid level: 0 = mg_coarse_sweeps damped block-Jacobi sweeps (omega_p); 1 = the
+     Chebyshev semi-iteration with mg_coarse_sweeps steps (one column solve each), preconditioned by
+     the same column operator H_z and tuned to eigenvalues of H_z^-1 H in [cheb_lo, cheb_hi]
+     (0 < cheb_lo < cheb_hi; eigenvalues stay below 2 when H has non-positive couplings and positive
+     row sums, as the pressure operators here do) */
+  int32_t mg_coarse_cheb;
+  double cheb_lo, cheb_hi;
 } hyb_params;
 
 typedef struct {

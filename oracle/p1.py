@@ -344,7 +344,7 @@ class TwoLevelP1:
     multigrid V-cycle on the order-0 H of the same mesh, lambda += P dPi, LineSmooth (n_post)."""
 
     def __init__(self, mesh: BoxMesh, S, H, omega=0.6, n_pre=1, n_post=2, mg_levels=4, omega_p=0.9, mg_pre=1,
-                 mg_post=2, mg_coarse_sweeps=30):
+                 mg_post=2, mg_coarse_sweeps=6, mg_coarse_cheb=(0.02, 2.0)):
         from .precond import PressureMultigrid
 
         self.mesh, self.S = mesh, sp.csr_matrix(S)
@@ -353,7 +353,7 @@ class TwoLevelP1:
         self.D_lu = spla.splu(self.D.tocsc())
         self.P = trace_prolongation(mesh)
         self.mg = PressureMultigrid(H, mesh.nx, mesh.ny, mesh.nlev, mg_levels, omega_p, mg_pre, mg_post,
-                                    mg_coarse_sweeps)
+                                    mg_coarse_sweeps, mg_coarse_cheb)
         ones = np.ones(mesh.ncell)
         self.gamma = (H @ ones) / (self.P.T @ (self.S @ (self.P @ ones)))
 

@@ -24,8 +24,15 @@ details to earlier work and prints one sign that diverges):
   i.e. one tridiagonal block per column.
 * Multigrid levels: 2x2 horizontal agglomeration, no vertical coarsening;
   restriction = sum over the four children, prolongation = injection, coarse
-  operators by the Galerkin product R H P; the coarsest level is smoothed
-  with a fixed number of block-Jacobi sweeps.
+  operators by the Galerkin product R H P; the coarsest level is solved
+  approximately with a fixed number of steps: either damped block-Jacobi
+  sweeps, or (the default) the Chebyshev semi-iteration preconditioned by
+  the same column operator H_z, tuned to eigenvalues of H_z^-1 H in
+  [lo, hi] = [0.02, 2].  The upper end holds for every level: H has
+  non-positive couplings and positive row sums (H 1 = M3^Pi 1), so
+  2 H_z - H, which flips the sign of the horizontal couplings, is
+  diagonally dominant and positive definite; the modes below lo are few
+  and are left to the Krylov method.
 * Prolongation to a facet on the ground or lid is one sided (the value of the
   single adjacent cell), so the restriction weight there is 1 (1/2 elsewhere).
 
@@ -78,9 +85,17 @@ def agglomeration(nx, ny, nlev):
     return sp.csr_matrix((np.ones(nf), (fine, coarse)), shape=(nf, nc))
 
 
+COARSE_CHEB = (0.02, 2.0)  # default interval of the Chebyshev coarsest solve
+
+
 class PressureMultigrid:
-    def __init__(self, H, nx, ny, nlev, levels=4, omega=0.9, pre=1, post=2, coarse_sweeps=30):
+    """coarse_cheb: (lo, hi) for the Chebyshev coarsest solve, or None for damped block-Jacobi
+    sweeps; coarse_sweeps: the number of steps either way."""
+
+    def __init__(self, H, nx, ny, nlev, levels=4, omega=0.9, pre=1, post=2, coarse_sweeps=6,
+                 coarse_cheb=COARSE_CHEB):
         self.omega, self.pre, self.post, self.coarse_sweeps = omega, pre, post, coarse_sweeps
+        self.coarse_cheb = coarse_cheb
         self.H = [sp.csr_matrix(H)]
         self.P = []
         self.ncol = [nx * ny]
@@ -105,12 +120,35 @@ class PressureMultigrid:
     def vcycle(self, b, level=0):
         x = np.zeros_like(b)
         if level == self.nlevels - 1:
+            if self.coarse_cheb is not None:
+                lo, hi = self.coarse_cheb
+                return chebyshev_solve(lambda v: self.H[level] @ v, self.Hz_lu[level].solve, b,
+                                       self.coarse_sweeps, lo, hi)
             return self.smooth(level, x, b, self.coarse_sweeps)
         x = self.smooth(level, x, b, self.pre)
         r = b - self.H[level] @ x
         xc = self.vcycle(self.P[level].T @ r, level + 1)
         x = x + self.P[level] @ xc
         return self.smooth(level, x, b, self.post)
+
+
+def chebyshev_solve(apply_A, apply_Minv, b, steps, lo, hi):
+    """Chebyshev semi-iteration (Golub and Varga, 1961) for A x = b from x = 0, preconditioned by M,
+    tuned to eigenvalues of M^-1 A in [lo, hi]; the three-term recurrence of the shifted and scaled
+    Chebyshev polynomials (as in Saad, Iterative Methods for Sparse Linear Systems, Alg. 12.1).
+    After `steps` preconditioner applications the error is p(M^-1 A) x with
+    p(t) = T_steps((theta - t) / delta) / T_steps(theta / delta), theta and delta the centre and
+    half-width of the interval."""
+    theta, delta = 0.5 * (hi + lo), 0.5 * (hi - lo)
+    sigma = theta / delta
+    rho = 1.0 / sigma
+    x_prev = np.zeros_like(b)
+    x = apply_Minv(b) / theta
+    for _ in range(steps - 1):
+        rho_next = 1.0 / (2.0 * sigma - rho)
+        x_next = x + rho_next * rho * (x - x_prev) + (2.0 * rho_next / delta) * apply_Minv(b - apply_A(x))
+        x_prev, x, rho = x, x_next, rho_next
+    return x
 
 
 def trace_prolongation(mesh: BoxMesh):
@@ -134,14 +172,15 @@ class TwoLevel:
     """Alg. 2 with LineSmooth (Alg. 1) and a pressure multigrid V-cycle coarse solve."""
 
     def __init__(self, mesh: BoxMesh, S, H, omega=0.6, n_pre=1, n_post=2, mg_levels=4,
-                 omega_p=0.9, mg_pre=1, mg_post=2, mg_coarse_sweeps=30, sign=+1.0):
+                 omega_p=0.9, mg_pre=1, mg_post=2, mg_coarse_sweeps=6, sign=+1.0,
+                 mg_coarse_cheb=COARSE_CHEB):
         self.mesh, self.S = mesh, sp.csr_matrix(S)
         self.omega, self.n_pre, self.n_post, self.sign = omega, n_pre, n_post, sign
         self.D = line_smoother_matrix(mesh, self.S)
         self.D_lu = spla.splu(self.D.tocsc())
         self.P = trace_prolongation(mesh)
         self.mg = PressureMultigrid(H, mesh.nx, mesh.ny, mesh.nlev, mg_levels, omega_p, mg_pre,
-                                    mg_post, mg_coarse_sweeps)
+                                    mg_post, mg_coarse_sweeps, mg_coarse_cheb)
         ones_c = np.ones(mesh.ncell)
         self.gamma = (H @ ones_c) / (self.P.T @ (self.S @ (self.P @ ones_c)))
 

@@ -9,7 +9,7 @@ from .krylov import fgmres
 from .local import local_matrices
 from .mesh import BoxMesh
 from .mixed import MixedSystem
-from .precond import TwoLevel, pressure_operator
+from .precond import COARSE_CHEB, TwoLevel, pressure_operator
 
 
 def cells_from_soa(r_ub, r_pi):
@@ -20,7 +20,8 @@ def cells_from_soa(r_ub, r_pi):
 
 class OracleProblem:
     def __init__(self, prob, *, with_mixed=True, with_precond=True, omega=0.6, n_pre=1,
-                 n_post=2, mg_levels=None, omega_p=0.9, mg_pre=1, mg_post=2, mg_coarse_sweeps=30):
+                 n_post=2, mg_levels=None, omega_p=0.9, mg_pre=1, mg_post=2, mg_coarse_sweeps=6,
+                 mg_coarse_cheb=COARSE_CHEB):
         self.prob = prob
         self.mesh = BoxMesh(prob.nx, prob.ny, prob.nlev, prob.dx, prob.dy, prob.z)
         self.loc = local_matrices(self.mesh, prob)
@@ -33,7 +34,8 @@ class OracleProblem:
                 mg_levels = len(prob.levels)
             self.pc = TwoLevel(self.mesh, self.hyb.S, self.H, omega=omega, n_pre=n_pre,
                                n_post=n_post, mg_levels=mg_levels, omega_p=omega_p, mg_pre=mg_pre,
-                               mg_post=mg_post, mg_coarse_sweeps=mg_coarse_sweeps)
+                               mg_post=mg_post, mg_coarse_sweeps=mg_coarse_sweeps,
+                               mg_coarse_cheb=mg_coarse_cheb)
 
     def solve_fgmres(self, B, rtol=1e-8, restart=30, maxit=500, precondition=True):
         M = self.pc if precondition else (lambda r: r)

@@ -44,7 +44,8 @@ class _Params(ctypes.Structure):
                 ("omega", ctypes.c_double), ("n_pre", ctypes.c_int32), ("n_post", ctypes.c_int32),
                 ("omega_p", ctypes.c_double), ("mg_pre", ctypes.c_int32), ("mg_post", ctypes.c_int32),
                 ("mg_coarse_sweeps", ctypes.c_int32), ("restart", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("learned", ctypes.c_int32), ("learned_tau", ctypes.c_double)]
+                ("learned", ctypes.c_int32), ("learned_tau", ctypes.c_double),
+                ("mg_coarse_cheb", ctypes.c_int32), ("cheb_lo", ctypes.c_double), ("cheb_hi", ctypes.c_double)]
 
 
 class _Info(ctypes.Structure):
@@ -70,11 +71,14 @@ class Params:
     omega_p: float = 0.9
     mg_pre: int = 1
     mg_post: int = 2
-    mg_coarse_sweeps: int = 30
+    mg_coarse_sweeps: int = 6
     restart: int = 30
     precision: int = PREC_FP64
     learned: int = 0
     learned_tau: float = 3.0
+    mg_coarse_cheb: int = 1
+    cheb_lo: float = 0.02
+    cheb_hi: float = 2.0
 
     def to_c(self) -> _Params:
         return _Params(**{f.name: getattr(self, f.name) for f in fields(self)})

@@ -76,6 +76,9 @@ int check_params(hyb_ctx *c, const hyb_params *p) {
     return fail(c, HYB_EINVAL, "unknown precision mode");
   if (p->learned != 0 && p->learned != 1) return fail(c, HYB_EINVAL, "learned must be 0 or 1");
   if (!(p->learned_tau > 0.0) || !std::isfinite(p->learned_tau)) return fail(c, HYB_EINVAL, "learned_tau must be > 0");
+  if (p->mg_coarse_cheb != 0 && p->mg_coarse_cheb != 1) return fail(c, HYB_EINVAL, "mg_coarse_cheb must be 0 or 1");
+  if (p->mg_coarse_cheb && !(p->cheb_lo > 0.0 && p->cheb_hi > p->cheb_lo && std::isfinite(p->cheb_hi)))
+    return fail(c, HYB_EINVAL, "the Chebyshev interval needs 0 < cheb_lo < cheb_hi");
   return HYB_OK;
 }
 
@@ -156,6 +159,7 @@ int setup_level(hyb_ctx *c, const hyb_mesh *mesh, int l) {
   double **vecs[4] = {(double **)&L.b, (double **)&L.x, (double **)&L.y, (double **)&L.r};
   for (auto v : vecs)
     if ((rc = dalloc(c, v, n))) return rc;
+  if (l == mesh->nlevels - 1 && (rc = dalloc(c, (double **)&L.w, n))) return rc;  // third Chebyshev iterate
   return HYB_OK;
 }
 
@@ -163,7 +167,7 @@ void free_all(hyb_ctx *c) {
   for (auto &L : c->lv) {
     dfree(L.col_edge), dfree(L.edge_col), dfree(L.edge_lf), dfree(L.nbr), dfree(L.nlf), dfree(L.own);
     dfree(L.est), dfree(L.parent), dfree(L.children), dfree(L.H), dfree(L.Hf);
-    dfree(L.zf), dfree(L.zff), dfree(L.b), dfree(L.x), dfree(L.y), dfree(L.r);
+    dfree(L.zf), dfree(L.zff), dfree(L.b), dfree(L.x), dfree(L.y), dfree(L.r), dfree(L.w);
   }
   dfree(c->dz_d), dfree(c->A), dfree(c->LU), dfree(c->kv), dfree(c->Scell), dfree(c->bcell);
   dfree(c->S), dfree(c->Sf), dfree(c->m2l), dfree(c->gamma), dfree(c->gammaf), dfree(c->zfac), dfree(c->zfacf);

@@ -33,6 +33,7 @@ struct LevelDev {
   double *zf = nullptr;         // [3][nlev*ncol] LU factors of the column part H_z: l, 1/u, c/u
   float *zff = nullptr;
   void *b = nullptr, *x = nullptr, *y = nullptr, *r = nullptr;  // [nlev*ncol] work vectors
+  void *w = nullptr;  // coarsest level only: the third iterate of the Chebyshev coarsest solve
 };
 
 constexpr int kNNChannels = 16;

@@ -403,7 +403,8 @@ hipError_t line_smooth(hyb_ctx *c, const T *S, const T *B, const T *lin, T *lout
 constexpr int kPcrMaxColumns = 4096;
 
 // One block-Jacobi sweep of the pressure multigrid, fused: x_out = base + omega H_z^-1 (b - H X) with
-// X = 0 (MODE 0), xin (MODE 1) or xin plus the injected coarse correction xc[parent] (MODE 2), base = X.
+// X = 0 (MODE 0), xin (MODE 1) or xin plus the injected coarse correction xc[parent] (MODE 2), base = X;
+// MODE 3 is a step of the Chebyshev semi-iteration, base = X + c1 (X - xprev).
 // One wavefront per column, lane k = level k (nlev <= 64): the vertical neighbours of the residual
 // come from the adjacent lanes, and the tridiagonal column system (entries below / diagonal / above
 // = H slots 5, 0, 6) is solved by parallel cyclic reduction: at stride s every row eliminates its
@@ -414,7 +415,8 @@ __global__ void __launch_bounds__(kBlock) k_mg_sweep_pcr(const T *__restrict__ H
                                                         const T *__restrict__ xin, const T *__restrict__ xc,
                                                         T *__restrict__ xout, int nlev, int ncol, int ncolc,
                                                         const int32_t *__restrict__ nbr,
-                                                        const int32_t *__restrict__ parent, T omega) {
+                                                        const int32_t *__restrict__ parent, T omega,
+                                                        const T *__restrict__ xprev, T c1) {
   const int k = threadIdx.x & 63;
   const int col = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (col >= ncol) return;  // the whole wavefront
@@ -455,11 +457,25 @@ __global__ void __launch_bounds__(kBlock) k_mg_sweep_pcr(const T *__restrict__ H
     const T dn = dm + (lo ? al * d1 : T(0)) + (hi ? ga * d2 : T(0));
     if (on) am = an, bm = bn, cm = cn, dm = dn;
   }
-  if (on) xout[c] = (MODE == 0 ? T(0) : xk) + omega * (dm / bm);
+  if (on) {
+    T base = MODE == 0 ? T(0) : xk;
+    if (MODE == 3) base += c1 * (xk - (xprev ? xprev[c] : T(0)));  // a null xprev is the zero vector
+    xout[c] = base + omega * (dm / bm);
+  }
+}
+
+// x_out = x + c1 (x - xprev) + c2 x_out (a Chebyshev step on levels without the fused sweep; x_out holds
+// H_z^-1 (b - H x) on entry; a null xprev is the zero vector)
+template <typename T>
+__global__ void k_cheb_update(const T *__restrict__ x, const T *__restrict__ xprev, T *__restrict__ xout, size_t n,
+                              T c1, T c2) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) xout[i] = x[i] + c1 * (x[i] - (xprev ? xprev[i] : T(0))) + c2 * xout[i];
 }
 
 template <typename T>
-hipError_t mg_smooth(hyb_ctx *c, int l, const T *b, const T *xin, const T *xc, T *xout, int mode) {
+hipError_t mg_smooth(hyb_ctx *c, int l, const T *b, const T *xin, const T *xc, T *xout, int mode, T om,
+                     const T *xprev = nullptr, T c1 = 0) {
   const LevelDev &Lv = c->lv[l];
   const T *H = pick<T>(Lv.H, Lv.Hf);
   const T *fac = pick<T>(Lv.zf, Lv.zff);
@@ -467,7 +483,6 @@ hipError_t mg_smooth(hyb_ctx *c, int l, const T *b, const T *xin, const T *xc, T
   size_t n = (size_t)c->nlev * Lv.ncol;
   size_t shm = sizeof(T) * (size_t)c->nlev * kColBlock;
   int ncolc = (l + 1 < c->nlevels) ? c->lv[l + 1].ncol : 1;
-  T om = (T)c->p.omega_p;
   dim3 gc(nblk(Lv.ncol, kColBlock)), bc(kColBlock), gr(nblk(n)), br(kBlock);
   int slot = prof_begin(c, F_MG_SMOOTH);
   // the fused sweep with cyclic reduction pays on small levels, where the Thomas recurrence of the
@@ -477,13 +492,16 @@ hipError_t mg_smooth(hyb_ctx *c, int l, const T *b, const T *xin, const T *xc, T
     const dim3 gw(nblk(Lv.ncol, kBlock / 64)), bw(kBlock);
     if (mode == 0)
       hipLaunchKernelGGL((k_mg_sweep_pcr<T, 0>), gw, bw, 0, c->stream, H, b, xin, xc, xout, c->nlev, Lv.ncol, ncolc,
-                         Lv.nbr, Lv.parent, om);
+                         Lv.nbr, Lv.parent, om, xprev, c1);
     else if (mode == 1)
       hipLaunchKernelGGL((k_mg_sweep_pcr<T, 1>), gw, bw, 0, c->stream, H, b, xin, xc, xout, c->nlev, Lv.ncol, ncolc,
-                         Lv.nbr, Lv.parent, om);
-    else
+                         Lv.nbr, Lv.parent, om, xprev, c1);
+    else if (mode == 2)
       hipLaunchKernelGGL((k_mg_sweep_pcr<T, 2>), gw, bw, 0, c->stream, H, b, xin, xc, xout, c->nlev, Lv.ncol, ncolc,
-                         Lv.nbr, Lv.parent, om);
+                         Lv.nbr, Lv.parent, om, xprev, c1);
+    else
+      hipLaunchKernelGGL((k_mg_sweep_pcr<T, 3>), gw, bw, 0, c->stream, H, b, xin, xc, xout, c->nlev, Lv.ncol, ncolc,
+                         Lv.nbr, Lv.parent, om, xprev, c1);
   } else if (mode == 0) {
     hipLaunchKernelGGL((k_column_solve<T, true, false>), gc, bc, shm, c->stream, b, fac, n, xin, xc, xout, c->nlev,
                        Lv.ncol, ncolc, Lv.parent, om);
@@ -492,6 +510,13 @@ hipError_t mg_smooth(hyb_ctx *c, int l, const T *b, const T *xin, const T *xc, T
                        Lv.nbr, Lv.parent);
     hipLaunchKernelGGL((k_column_solve<T, false, false>), gc, bc, shm, c->stream, (const T *)r, fac, n, xin, xc, xout,
                        c->nlev, Lv.ncol, ncolc, Lv.parent, om);
+  } else if (mode == 3) {
+    // residual, its column solve into xout, then the three-term update in place
+    hipLaunchKernelGGL((k_mg_residual<T, false>), gr, br, 0, c->stream, H, b, xin, xc, r, c->nlev, Lv.ncol, ncolc,
+                       Lv.nbr, Lv.parent);
+    hipLaunchKernelGGL((k_column_solve<T, true, false>), gc, bc, shm, c->stream, (const T *)r, fac, n, xin, xc, xout,
+                       c->nlev, Lv.ncol, ncolc, Lv.parent, T(1));
+    hipLaunchKernelGGL((k_cheb_update<T>), gr, br, 0, c->stream, xin, xprev, xout, n, c1, om);
   } else {
     hipLaunchKernelGGL((k_mg_residual<T, true>), gr, br, 0, c->stream, H, b, xin, xc, r, c->nlev, Lv.ncol, ncolc,
                        Lv.nbr, Lv.parent);
@@ -510,14 +535,36 @@ hipError_t vcycle(hyb_ctx *c, int l) {
   T *b = (T *)Lv.b;
   const hyb_params &p = c->p;
   bool coarsest = (l == c->nlevels - 1);
+  const T om = (T)p.omega_p;
+  if (coarsest && p.mg_coarse_cheb) {
+    // Chebyshev semi-iteration from x = 0 for H x = b, preconditioned by H_z, tuned to eigenvalues of
+    // H_z^-1 H in [lo, hi]: x_1 = H_z^-1 b / theta, then
+    // x_{k+1} = x_k + rho_k rho_{k-1} (x_k - x_{k-1}) + (2 rho_k / delta) H_z^-1 (b - H x_k),
+    // rho_0 = delta / theta, rho_k = 1 / (2 theta / delta - rho_{k-1})
+    const double theta = 0.5 * (p.cheb_hi + p.cheb_lo), delta = 0.5 * (p.cheb_hi - p.cheb_lo);
+    const double sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    void *buf[3] = {Lv.x, Lv.y, Lv.w};
+    int cur = 0, prv = -1, nxt = 1;  // x_0 = 0 is passed as a null pointer
+    HYB_TRY(mg_smooth<T>(c, l, b, nullptr, nullptr, (T *)buf[cur], 0, (T)(1.0 / theta)));
+    for (int s = 1; s < p.mg_coarse_sweeps; ++s) {
+      const double rho_next = 1.0 / (2.0 * sigma - rho);
+      HYB_TRY(mg_smooth<T>(c, l, b, (const T *)buf[cur], nullptr, (T *)buf[nxt], 3, (T)(2.0 * rho_next / delta),
+                           prv < 0 ? (const T *)nullptr : (const T *)buf[prv], (T)(rho_next * rho)));
+      rho = rho_next;
+      prv = cur, cur = nxt, nxt = 3 - prv - cur;
+    }
+    Lv.x = buf[cur], Lv.y = buf[(cur + 1) % 3], Lv.w = buf[(cur + 2) % 3];
+    return hipSuccess;
+  }
   int pre = coarsest ? p.mg_coarse_sweeps : p.mg_pre;
   if (pre <= 0) {
     hipLaunchKernelGGL((k_zero<T>), dim3(nblk(n)), dim3(kBlock), 0, c->stream, (T *)Lv.x, n);
     HYB_TRY(hipGetLastError());
   } else {
-    HYB_TRY(mg_smooth<T>(c, l, b, nullptr, nullptr, (T *)Lv.x, 0));
+    HYB_TRY(mg_smooth<T>(c, l, b, nullptr, nullptr, (T *)Lv.x, 0, om));
     for (int s = 1; s < pre; ++s) {
-      HYB_TRY(mg_smooth<T>(c, l, b, (T *)Lv.x, nullptr, (T *)Lv.y, 1));
+      HYB_TRY(mg_smooth<T>(c, l, b, (T *)Lv.x, nullptr, (T *)Lv.y, 1, om));
       std::swap(Lv.x, Lv.y);
     }
   }
@@ -537,10 +584,10 @@ hipError_t vcycle(hyb_ctx *c, int l) {
                        (const T *)Lc.x, c->nlev, Lv.ncol, Lc.ncol, Lv.parent);
     return hipGetLastError();
   }
-  HYB_TRY(mg_smooth<T>(c, l, b, (T *)Lv.x, (const T *)Lc.x, (T *)Lv.y, 2));
+  HYB_TRY(mg_smooth<T>(c, l, b, (T *)Lv.x, (const T *)Lc.x, (T *)Lv.y, 2, om));
   std::swap(Lv.x, Lv.y);
   for (int s = 1; s < p.mg_post; ++s) {
-    HYB_TRY(mg_smooth<T>(c, l, b, (T *)Lv.x, nullptr, (T *)Lv.y, 1));
+    HYB_TRY(mg_smooth<T>(c, l, b, (T *)Lv.x, nullptr, (T *)Lv.y, 1, om));
     std::swap(Lv.x, Lv.y);
   }
   return hipSuccess;

@@ -81,7 +81,7 @@ def test_vcycle_and_two_level_contract(box):
     wide = make_box(nx=4, ny=4, nlev=6, dx=1e11, dz=1250.0, mg_levels=1)
     ow = OracleProblem(wide)
     bw = rng.standard_normal(ow.H.shape[0])
-    mg1 = PressureMultigrid(ow.H, 4, 4, 6, levels=1, omega=1.0, coarse_sweeps=1)
+    mg1 = PressureMultigrid(ow.H, 4, 4, 6, levels=1, omega=1.0, coarse_sweeps=1, coarse_cheb=None)
     y = mg1.vcycle(bw)
     assert np.linalg.norm(bw - ow.H @ y) < 1e-10 * np.linalg.norm(bw)
     # the two-level cycle is a linear map
@@ -135,3 +135,57 @@ def test_preconditioned_solve_reaches_tolerance(box):
     assert all(h2 <= h1 * (1 + 1e-12) for h1, h2 in zip(hist, hist[1:]))
     xu, hu, itu, cu = o.solve_fgmres(B, rtol=1e-10, precondition=False, maxit=2000)
     assert itu > 2 * its
+
+
+def test_chebyshev_semi_iteration_closed_form():
+    """After d steps from x = 0 the error of the Chebyshev semi-iteration is p_d(M^-1 A) x with
+    p_d(t) = T_d((theta - t) / delta) / T_d(theta / delta): checked on a diagonal A (M = I) with
+    eigenvalues inside and outside the interval, T_d from numpy's Chebyshev series."""
+    from numpy.polynomial import chebyshev as C
+
+    from oracle.precond import chebyshev_solve
+
+    rng = np.random.default_rng(3)
+    lam = np.concatenate([np.linspace(0.02, 2.0, 9), [0.005, 0.5, 1.3, 2.2]])
+    x_true = rng.standard_normal(lam.size)
+    b = lam * x_true
+    lo, hi = 0.02, 2.0
+    theta, delta = (hi + lo) / 2, (hi - lo) / 2
+    for d in (1, 2, 3, 6, 11):
+        x = chebyshev_solve(lambda v: lam * v, lambda v: v, b, d, lo, hi)
+        Td = C.Chebyshev.basis(d)
+        p = Td((theta - lam) / delta) / Td(theta / delta)
+        np.testing.assert_allclose(x_true - x, p * x_true, rtol=1e-10, atol=1e-12)
+        # inside the interval the error factor is at most 1 / T_d(theta / delta)
+        inside = (lam >= lo) & (lam <= hi)
+        assert np.all(np.abs(p[inside]) <= 1.0 / Td(theta / delta) * (1 + 1e-12))
+
+
+def test_chebyshev_coarsest_solve(box):
+    """The eigenvalues of H_z^-1 H lie in (0, 2) on every level (the upper end of the default
+    interval), and with the exact interval and enough steps the Chebyshev coarsest solve reaches
+    the direct solution within its error bound."""
+    from numpy.polynomial import chebyshev as C
+
+    from oracle.precond import chebyshev_solve
+
+    prob, o = box
+    mg = o.pc.mg
+    for lev in range(mg.nlevels):
+        Hd, Hz = mg.H[lev].toarray(), mg.Hz[lev].toarray()
+        ev = np.linalg.eigvals(np.linalg.solve(Hz, Hd)).real
+        assert ev.min() > 0 and ev.max() < 2.0, (lev, ev.min(), ev.max())
+    L = mg.nlevels - 1
+    Hd, Hz = mg.H[L].toarray(), mg.Hz[L].toarray()
+    ev = np.linalg.eigvals(np.linalg.solve(Hz, Hd)).real
+    lo, hi = ev.min(), ev.max()
+    rng = np.random.default_rng(8)
+    b = rng.standard_normal(Hd.shape[0])
+    x_ref = np.linalg.solve(Hd, b)
+    d = 40
+    x = chebyshev_solve(lambda v: mg.H[L] @ v, mg.Hz_lu[L].solve, b, d, lo, hi)
+    theta, delta = (hi + lo) / 2, (hi - lo) / 2
+    bound = 1.0 / C.Chebyshev.basis(d)(theta / delta)
+    # error in the H-norm (H_z^-1 H is self-adjoint there) shrinks by at most the bound
+    e, e0 = x_ref - x, x_ref
+    assert np.sqrt(e @ Hd @ e) <= bound * np.sqrt(e0 @ Hd @ e0) * (1 + 1e-8)
