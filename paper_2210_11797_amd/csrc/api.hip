@@ -509,11 +509,13 @@ int hyb_solve(hyb_ctx *c, const double *b, double *lam, double rtol, int32_t max
   }
   const bool learned = c->p.learned && c->nn.loaded;
   if (c->p.learned && !c->nn.loaded) return fail(c, HYB_ESTATE, "learned stage requested without weights");
-  // ||b||
+  // ||b|| and ||lambda_0||^2: from a zero initial guess the first residual is b itself
   CHECK_HIP(launch_multidot(c, b, 0, 0, b, n, nrm, true), "norm b");
-  CHECK_HIP(hipMemcpyAsync(hh, nrm, sizeof(double), hipMemcpyDeviceToHost, c->stream), "d2h");
+  CHECK_HIP(launch_multidot(c, lam, 0, 0, lam, n, nrm + 1, true), "norm lambda");
+  CHECK_HIP(hipMemcpyAsync(hh, nrm, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream), "d2h");
   CHECK_HIP(hipStreamSynchronize(c->stream), "sync");
   double bnorm = std::sqrt(hh[0]);
+  bool lam_zero = hh[1] == 0.0;
   if (!std::isfinite(bnorm)) return fail(c, HYB_EINVAL, "right-hand side is not finite");
   if (bnorm == 0.0) {
     CHECK_HIP(launch_fill(c, lam, n, 0.0), "zero");
@@ -527,10 +529,13 @@ int hyb_solve(hyb_ctx *c, const double *b, double *lam, double rtol, int32_t max
   }
   for (;;) {
     // true residual r = b - S lam into V_0
-    if (c->order == 1)
+    if (lam_zero)
+      CHECK_HIP(hipMemcpyAsync(V, b, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream), "residual");
+    else if (c->order == 1)
       CHECK_HIP(p1_rows(c, lam, V, 2, b), "residual");
     else
       CHECK_HIP((launch_trace_apply<double, double, double>(c, c->S, lam, b, V, 1)), "residual");
+    lam_zero = false;
     CHECK_HIP(launch_multidot(c, V, 0, 0, V, n, nrm, true), "norm r");
     CHECK_HIP(hipMemcpyAsync(hh, nrm, sizeof(double), hipMemcpyDeviceToHost, c->stream), "d2h");
     CHECK_HIP(hipStreamSynchronize(c->stream), "sync");
