@@ -364,7 +364,7 @@ int hyb_assemble_local(hyb_ctx *c, const double *theta_w, const double *exner_ha
     const size_t nc = (size_t)c->ncell;
     if ((rc = dalloc(c, &s.A, 44 * 44 * nc)) || (rc = dalloc(c, &s.cdiag, 24 * nc)) ||
         (rc = dalloc(c, &s.kdiag, 24 * nc)) || (rc = dalloc(c, &s.SK, 24 * 24 * nc)) || (rc = dalloc(c, &s.bK, 24 * nc)) ||
-        (rc = dalloc(c, &s.fac, 748 * nc)))
+        (rc = dalloc(c, &s.fac, 748 * nc)) || (rc = dalloc(c, &s.SKf, 24 * 24 * nc)))
       return rc;
     CHECK_HIP(p1_setup(c), "p1 tables");
     CHECK_HIP(p1_assemble(c, theta_w, exner_hat_w, exner_c, rho_c), "p1 assemble_local");

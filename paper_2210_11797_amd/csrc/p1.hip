@@ -381,7 +381,7 @@ template <bool SPLIT>
 __global__ void __launch_bounds__(64 * kMW) k_p1_condense_mfma(int ncell, const double *__restrict__ A,
                                                               const double *__restrict__ cdiag,
                                                               const double *__restrict__ kdiag,
-                                                              double *__restrict__ SK) {
+                                                              float *__restrict__ SK) {
   __shared__ MfmaLds sL[kMW];
   __shared__ double sC[kMW][NF];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -440,7 +440,7 @@ __global__ void __launch_bounds__(64 * kMW) k_p1_condense_mfma(int ncell, const 
     const float *Xw = &sL[w].stg[0][0];
     for (int e = threadIdx.x / kMW; e < NS; e += 64) {
       const int r = e / NF;
-      SK[(size_t)e * ncell + cw] = sC[w][r] * (double)Xw[e];
+      SK[(size_t)e * ncell + cw] = (float)(sC[w][r] * (double)Xw[e]);
     }
   }
 }
@@ -681,9 +681,10 @@ __global__ void __launch_bounds__(kBlock) k_p1_cell_struct(int ncell, int ncol, 
 // S x in two passes.  Thread per cell: t_K = S_K x_K into t [24][ncell] (mode 0), or the diagonal of
 // S_K (mode 1).  Each cell gathers its 24 trace values once and reads its S_K entry by entry over
 // the cells, so both the matrix and t stream coalesced.
+template <typename TS>
 __global__ void __launch_bounds__(kBlock) k_p1_cell_mv(int ncell, int ncol, int nedge, size_t nz,
                                                       const int32_t *__restrict__ col_edge,
-                                                      const double *__restrict__ SK, const double *__restrict__ x,
+                                                      const TS *__restrict__ SK, const double *__restrict__ x,
                                                       int mode, double *__restrict__ t) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncell) return;
@@ -698,10 +699,10 @@ __global__ void __launch_bounds__(kBlock) k_p1_cell_mv(int ncell, int ncol, int 
   for (int j = 0; j < NF; ++j) xk[j] = x[p1_dof(j, k, col, ncol, nedge, nz, col_edge)];
 #pragma unroll 2
   for (int r = 0; r < NF; ++r) {
-    const double *row = SK + (size_t)r * NF * ncell + c;
+    const TS *row = SK + (size_t)r * NF * ncell + c;
     double s = 0.0;
 #pragma unroll
-    for (int j = 0; j < NF; ++j) s += row[(size_t)j * ncell] * xk[j];
+    for (int j = 0; j < NF; ++j) s += (double)row[(size_t)j * ncell] * xk[j];
     t[(size_t)r * ncell + c] = s;
   }
 }
@@ -747,12 +748,14 @@ __device__ __forceinline__ void inv4(const double *a, double *o) {
 }
 
 // block of S_K between local faces fa (rows) and fb (columns)
-__device__ __forceinline__ void sk_block(const double *SK, size_t ncell, int c, int fa, int fb, double *o) {
+template <typename TS>
+__device__ __forceinline__ void sk_block(const TS *SK, size_t ncell, int c, int fa, int fb, double *o) {
   for (int i = 0; i < 4; ++i)
     for (int j = 0; j < 4; ++j) o[4 * i + j] = SK[(size_t)((4 * fa + i) * NF + 4 * fb + j) * ncell + c];
 }
 
-__global__ void k_p1_zfactor(int nlev, int ncol, const double *__restrict__ SK, double *__restrict__ zf) {
+template <typename TS>
+__global__ void k_p1_zfactor(int nlev, int ncol, const TS *__restrict__ SK, double *__restrict__ zf) {
   const int col = blockIdx.x * blockDim.x + threadIdx.x;
   if (col >= ncol) return;
   const size_t ncell = (size_t)nlev * ncol;
@@ -910,6 +913,11 @@ hipError_t p1_assemble(hyb_ctx *c, const double *theta_w, const double *exner_ha
 
 // S_K in the arithmetic of params.precision: FP64 from the block structure, or the dense elimination
 // of A_K on MFMA (FP32, BF16 split); the per-solve cell factors always in FP64 from the structure.
+// S_K is held in FP32 when the matrix cores condensed it (FP32-accurate there), else in FP64
+bool p1_sk_fp32(const hyb_ctx *c) {
+  return c->p.precision == HYB_PREC_MFMA_FP32 || c->p.precision == HYB_PREC_MFMA_BF16X;
+}
+
 hipError_t p1_factor(hyb_ctx *c) {
   P1State &s = c->p1;
   const int prec = c->p.precision;
@@ -917,10 +925,10 @@ hipError_t p1_factor(hyb_ctx *c) {
     const int slot = prof_begin(c, F_P1_CONDENSE);
     if (prec == HYB_PREC_MFMA_FP32)
       hipLaunchKernelGGL((k_p1_condense_mfma<false>), dim3(nblk(c->ncell, kMW)), dim3(64 * kMW), 0, c->stream,
-                         c->ncell, s.A, s.cdiag, s.kdiag, s.SK);
+                         c->ncell, s.A, s.cdiag, s.kdiag, s.SKf);
     else
       hipLaunchKernelGGL((k_p1_condense_mfma<true>), dim3(nblk(c->ncell, kMW)), dim3(64 * kMW), 0, c->stream,
-                         c->ncell, s.A, s.cdiag, s.kdiag, s.SK);
+                         c->ncell, s.A, s.cdiag, s.kdiag, s.SKf);
     prof_end(c, F_P1_CONDENSE, slot);
     hipError_t e = hipGetLastError();
     if (e) return e;
@@ -949,8 +957,12 @@ hipError_t p1_rows(hyb_ctx *c, const double *x, double *y, int mode, const doubl
   const size_t ntr = (size_t)c->ntrace;
   int slot = prof_begin(c, F_TRACE_APPLY);
   if (mode != 1) {  // mode 1 gathers the shares already in bK
-    hipLaunchKernelGGL(k_p1_cell_mv, dim3(nblk(c->ncell)), dim3(kBlock), 0, c->stream, c->ncell, c->ncol, c->nedge,
-                       (size_t)c->nz, L0.col_edge, s.SK, x, mode == 3 ? 1 : 0, s.bK);
+    if (p1_sk_fp32(c))
+      hipLaunchKernelGGL(k_p1_cell_mv<float>, dim3(nblk(c->ncell)), dim3(kBlock), 0, c->stream, c->ncell, c->ncol,
+                         c->nedge, (size_t)c->nz, L0.col_edge, (const float *)s.SKf, x, mode == 3 ? 1 : 0, s.bK);
+    else
+      hipLaunchKernelGGL(k_p1_cell_mv<double>, dim3(nblk(c->ncell)), dim3(kBlock), 0, c->stream, c->ncell, c->ncol,
+                         c->nedge, (size_t)c->nz, L0.col_edge, (const double *)s.SK, x, mode == 3 ? 1 : 0, s.bK);
   }
   hipLaunchKernelGGL(k_p1_gather, dim3(nblk(ntr)), dim3(kBlock), 0, c->stream, ntr, c->nlev, c->ncol, c->nedge,
                      (size_t)c->nz, L0.edge_col, L0.edge_lf, s.bK, b, y, mode == 2 ? 1 : 0);
@@ -967,7 +979,12 @@ hipError_t p1_precond_setup(hyb_ctx *c) {
   const size_t ntr = (size_t)c->ntrace, nc = (size_t)c->ncell;
   hipError_t e;
   if ((e = p1_rows(c, nullptr, s.dS, 3, nullptr))) return e;
-  hipLaunchKernelGGL(k_p1_zfactor, dim3(nblk(c->ncol)), dim3(kBlock), 0, c->stream, c->nlev, c->ncol, s.SK, s.zf);
+  if (p1_sk_fp32(c))
+    hipLaunchKernelGGL(k_p1_zfactor<float>, dim3(nblk(c->ncol)), dim3(kBlock), 0, c->stream, c->nlev, c->ncol,
+                       (const float *)s.SKf, s.zf);
+  else
+    hipLaunchKernelGGL(k_p1_zfactor<double>, dim3(nblk(c->ncol)), dim3(kBlock), 0, c->stream, c->nlev, c->ncol,
+                       (const double *)s.SK, s.zf);
   if ((e = hipGetLastError())) return e;
   // P 1 = 1 on every dof; den = P^T S 1
   hipLaunchKernelGGL(k_p1_fill, dim3(nblk(ntr)), dim3(kBlock), 0, c->stream, s.t1, ntr, 1.0);
@@ -1035,6 +1052,8 @@ hipError_t p1_precondition(hyb_ctx *c, const double *r, double *z) {
 
 void p1_free(hyb_ctx *c) {
   P1State &s = c->p1;
+  if (s.SKf) (void)hipFree(s.SKf);
+  s.SKf = nullptr;
   for (double **q : {&s.tbl, &s.A, &s.cdiag, &s.kdiag, &s.SK, &s.bK, &s.fac, &s.dS, &s.zf, &s.gamma, &s.den, &s.t1,
                      &s.t2, &s.t3})
     if (*q) (void)hipFree(*q), *q = nullptr;

@@ -273,6 +273,9 @@ def p1_sequence(lib):
         cm.call("hyb_trace_apply", P(x), P(ym))
         err = np.abs(ym - ref).max() / np.abs(ref).max()
         check(err <= tol, f"order 1, condensation mode {prec}: S x error vs FP64 {err:.1e}")
+        rc, info, lam_m = cm.solve(b, 1e-8)
+        check(rc == 0 and cm.residual(b, lam_m) <= 1.01e-8,
+              f"order 1, condensation mode {prec}: FGMRES on the FP32 S_K ({info.iters} iterations)")
         # a change of arithmetic asks for the condensation again, and FP64 restores the exact operator
         cm.set(precision=N.PREC_FP64)
         check(lib.hyb_trace_apply(cm.h, P(x), P(ym)) < 0, "order 1: a new precision rejects S x until condensed")
