@@ -141,8 +141,11 @@ def algorithmic_bytes(ntr, ncell, ncol, nlev, its, fams, steps):
     total += cycles * vcycle
     for it_count in its:
         for j in range(it_count):
-            total += 8 * ntr * ((j + 3) + (j + 4) + 2) / len(its)  # dots + norm, update + norm, scale
+            # Gram-Schmidt with delayed reorthogonalisation: the reduction pass reads V_0..V_{j+1},
+            # the update pass reads them and writes V_j and V_{j+1}
+            total += 8 * ntr * ((j + 2) + (j + 4)) / len(its)
         total += 8 * ntr * (it_count + 2) / len(its)                # solution update
+        total += 8 * ntr * 5 / len(its)                             # ||b||, ||lambda_0||, r_0 = b, ||r_0||
     total += ncell * 8 * (49 + 7 + 6) + 8 * 9 * ntr / 3            # condense RHS + facet gather
     total += ncell * 8 * (49 + 7 + 6 + 6 + 7)                      # recover
     return total
