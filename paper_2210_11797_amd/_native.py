@@ -57,7 +57,10 @@ class _Info(ctypes.Structure):
 @dataclass
 class Params:
     """Solver parameters; defaults are the paper's (Sec. 3.3): omega = 0.6 with 1 pre- and 2
-    post-smoothing sweeps, a 4-level pressure multigrid with omega_p = 0.9, 1 pre / 2 post sweeps."""
+    post-smoothing sweeps, a 4-level pressure multigrid with omega_p = 0.9, 1 pre / 2 post sweeps.
+    The paper leaves the coarsest level open: by default 6 steps of the Chebyshev semi-iteration
+    over block Jacobi on [cheb_lo, cheb_hi] = [0.02, 2] (mg_coarse_cheb = 0: mg_coarse_sweeps
+    damped block-Jacobi sweeps instead)."""
 
     dt: float = 600.0
     tau_u: float = 0.5
