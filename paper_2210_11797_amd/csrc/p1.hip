@@ -799,40 +799,44 @@ __global__ void k_p1_zfactor(int nlev, int ncol, const TS *__restrict__ SK, doub
 
 // LineSmooth (Alg. 1) at order 1, given the residual R: horizontal facets by the block-tridiagonal
 // column solve, vertical facets by point Jacobi; lambda_out = lambda_in + omega delta.
-__global__ void k_p1_zsolve(int nlev, int ncol, const double *__restrict__ zf, const double *__restrict__ R,
-                            const double *__restrict__ lin, double *__restrict__ lout, double omega) {
-  const int col = blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= ncol) return;
-  double y[4], prev[4] = {0, 0, 0, 0};
+// Four lanes per column, lane i holding dof row i of every facet's 4-vector; the 4x4 products take
+// the other rows of the vector from the group's lanes by shuffles, so the loads of a level do not
+// wait on the recurrence and a column's rows are read as one 128-byte piece.
+__global__ void __launch_bounds__(kBlock) k_p1_zsolve(int nlev, int ncol, const double *__restrict__ zf,
+                                                     const double *__restrict__ R, const double *__restrict__ lin,
+                                                     double *__restrict__ lout, double omega) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int col = t >> 2, i = t & 3, lane = threadIdx.x & 63, g0 = lane & ~3;
+  const bool on = col < ncol;  // uniform over a group of four; every lane takes part in the shuffles
+  const int cl = on ? col : ncol - 1;  // lanes past the last column read (and discard) the last one's
+  double prev = 0.0;
+#pragma unroll 4
   for (int k = 0; k <= nlev; ++k) {  // forward: y_k = R_k - W_k y_{k-1}, kept in lout
-    const size_t F = (size_t)k * ncol + col;
-    const double *W = zf + F * 48 + 16;
-    for (int i = 0; i < 4; ++i) {
-      double a = R[4 * F + i];
-      for (int m = 0; m < 4; ++m) a -= W[4 * i + m] * prev[m];
-      y[i] = a;
-    }
-    for (int i = 0; i < 4; ++i) lout[4 * F + i] = prev[i] = y[i];
+    const size_t F = (size_t)k * ncol + cl;
+    double w[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) w[m] = zf[F * 48 + 16 + 4 * i + m];
+    double y = R[4 * F + i];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) y -= w[m] * __shfl(prev, g0 + m, 64);
+    if (on) lout[4 * F + i] = y;
+    prev = y;
   }
-  double next[4] = {0, 0, 0, 0};
+  double next = 0.0;
+#pragma unroll 4
   for (int k = nlev; k >= 0; --k) {  // backward: x_k = Dinv_k (y_k - U_k x_{k+1})
-    const size_t F = (size_t)k * ncol + col;
-    const double *Dinv = zf + F * 48, *Up = zf + F * 48 + 32;
-    double t[4], x[4];
-    for (int i = 0; i < 4; ++i) {
-      double a = lout[4 * F + i];
-      for (int m = 0; m < 4; ++m) a -= Up[4 * i + m] * next[m];
-      t[i] = a;
-    }
-    for (int i = 0; i < 4; ++i) {
-      double a = 0.0;
-      for (int m = 0; m < 4; ++m) a += Dinv[4 * i + m] * t[m];
-      x[i] = a;
-    }
-    for (int i = 0; i < 4; ++i) {
-      next[i] = x[i];
-      lout[4 * F + i] = (lin ? lin[4 * F + i] : 0.0) + omega * x[i];
-    }
+    const size_t F = (size_t)k * ncol + cl;
+    double dv[4], up[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) dv[m] = zf[F * 48 + 4 * i + m], up[m] = zf[F * 48 + 32 + 4 * i + m];
+    double tt = lout[4 * F + i];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) tt -= up[m] * __shfl(next, g0 + m, 64);
+    double x = 0.0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) x += dv[m] * __shfl(tt, g0 + m, 64);
+    next = x;
+    if (on) lout[4 * F + i] = (lin ? lin[4 * F + i] : 0.0) + omega * x;
   }
 }
 
@@ -1012,7 +1016,8 @@ hipError_t p1_precondition(hyb_ctx *c, const double *r, double *z) {
     }
     const double *res = lin ? R : r;
     int slot = prof_begin(c, F_THOMAS);
-    hipLaunchKernelGGL(k_p1_zsolve, dim3(nblk(c->ncol, 64)), dim3(64), 0, c->stream, c->nlev, c->ncol, s.zf, res, lin,
+    hipLaunchKernelGGL(k_p1_zsolve, dim3(nblk(4 * (size_t)c->ncol)), dim3(kBlock), 0, c->stream, c->nlev, c->ncol, s.zf,
+                       res, lin,
                        lout, p.omega);
     hipLaunchKernelGGL(k_p1_hjacobi, dim3(nblk(ntr - nz4)), dim3(kBlock), 0, c->stream, nz4, ntr, s.dS, res, lin, lout,
                        p.omega);
