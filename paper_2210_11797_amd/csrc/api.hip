@@ -342,7 +342,7 @@ int hyb_set_params(hyb_ctx *c, const hyb_params *params) {
   c->p = *params;
   if (prec_change && c->condensed && c->p.precision == HYB_PREC_MIXED) {
     // FP32 copies are made at condensation; refresh them for the new mode
-    CHECK_HIP(launch_to_float(c, c->S, c->Sf, (size_t)11 * c->ntrace), "to_float S");
+    CHECK_HIP(launch_to_float(c, c->S, c->Sf, s_entries(c->ntrace)), "to_float S");
     CHECK_HIP(launch_to_float(c, c->gamma, c->gammaf, (size_t)c->ncell), "to_float gamma");
     CHECK_HIP(launch_to_float(c, c->zfac, c->zfacf, 3 * (size_t)c->nz), "to_float zfac");
     for (int l = 0; l < c->nlevels; ++l)
@@ -411,8 +411,8 @@ int hyb_condense(hyb_ctx *c, const double *r_ub, const double *r_pi, double *b_l
   }
   if (r_ub == nullptr) {
     size_t ntr = (size_t)c->ntrace, nc = (size_t)c->ncell;
-    if ((rc = dalloc(c, &c->LU, 49 * nc)) || (rc = dalloc(c, &c->Scell, 36 * nc)) || (rc = dalloc(c, &c->S, 11 * ntr)) ||
-        (rc = dalloc(c, &c->Sf, 11 * ntr)) || (rc = dalloc(c, &c->m2l, ntr)) || (rc = dalloc(c, &c->gamma, nc)) ||
+    if ((rc = dalloc(c, &c->LU, 49 * nc)) || (rc = dalloc(c, &c->Scell, 36 * nc)) || (rc = dalloc(c, &c->S, s_entries(ntr))) ||
+        (rc = dalloc(c, &c->Sf, s_entries(ntr))) || (rc = dalloc(c, &c->m2l, ntr)) || (rc = dalloc(c, &c->gamma, nc)) ||
         (rc = dalloc(c, &c->zfac, 3 * (size_t)c->nz)) || (rc = dalloc(c, &c->zfacf, 3 * (size_t)c->nz)) ||
         (rc = dalloc(c, &c->gammaf, nc)) || (rc = dalloc(c, &c->bcell, 6 * nc)) ||
         (rc = dalloc(c, (double **)&c->tIn, ntr)) || (rc = dalloc(c, (double **)&c->tA, ntr)) ||
@@ -428,7 +428,7 @@ int hyb_condense(hyb_ctx *c, const double *r_ub, const double *r_pi, double *b_l
     for (int l = 1; l < c->nlevels; ++l) CHECK_HIP(launch_galerkin(c, l), "galerkin");
     for (int l = 0; l < c->nlevels; ++l) CHECK_HIP(launch_mg_factor(c, l), "mg_factor");
     CHECK_HIP(launch_gamma(c), "gamma");
-    CHECK_HIP(launch_to_float(c, c->S, c->Sf, 11 * ntr), "to_float S");
+    CHECK_HIP(launch_to_float(c, c->S, c->Sf, s_entries(ntr)), "to_float S");
     CHECK_HIP(launch_to_float(c, c->gamma, c->gammaf, nc), "to_float gamma");
     CHECK_HIP(launch_to_float(c, c->zfac, c->zfacf, 3 * (size_t)c->nz), "to_float zfac");
     for (int l = 0; l < c->nlevels; ++l)

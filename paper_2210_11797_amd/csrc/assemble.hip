@@ -165,7 +165,7 @@ __global__ void k_build_stencil(int nlev, int ncol, int nedge, int ncell, size_t
     }
   }
 #pragma unroll
-  for (int i = 0; i < 11; ++i) S[i * ntr + F] = s[i];
+  for (int i = 0; i < 11; ++i) S[s_idx(F, i)] = s[i];
 }
 
 // Sign of local face f of a cell relative to the global facet orientation: +1 when the facet

@@ -36,6 +36,15 @@ struct LevelDev {
   void *w = nullptr;  // coarsest level only: the third iterate of the Chebyshev coarsest solve
 };
 
+// The 11-entry trace stencil S (and its FP32 copy) is stored in tiles of 64 rows: entry j of row F
+// at ((F / 64) * 11 + j) * 64 + F mod 64, so the entries a wavefront reads for 64 consecutive rows lie
+// in one contiguous 5.5 KB block (one stream from HBM instead of eleven).
+constexpr int kSTile = 64;
+__host__ __device__ __forceinline__ size_t s_idx(size_t F, int j) {
+  return ((F / kSTile) * 11 + (size_t)j) * kSTile + F % kSTile;
+}
+__host__ __device__ __forceinline__ size_t s_entries(size_t ntr) { return 11 * ((ntr + kSTile - 1) / kSTile) * kSTile; }
+
 constexpr int kNNChannels = 16;
 
 // Learned coarse-correction network state (device buffers).

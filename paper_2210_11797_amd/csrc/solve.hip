@@ -28,18 +28,18 @@ struct Acc {
 template <typename A, typename Tm, typename Tx>
 __device__ __forceinline__ A row_z(const Tm *__restrict__ S, size_t ntr, const Tx *__restrict__ x, size_t F,
                                    int k, int nlev, int ncol, int nedge, size_t nz, const int ce[4]) {
-  A acc = (A)S[F] * (A)x[F];
+  A acc = (A)S[s_idx(F, 0)] * (A)x[F];
   if (k > 0) {
     size_t hb = nz + (size_t)(k - 1) * nedge;
-    acc += (A)S[ntr + F] * (A)x[F - ncol];
+    acc += (A)S[s_idx(F, 1)] * (A)x[F - ncol];
 #pragma unroll
-    for (int f = 0; f < 4; ++f) acc += (A)S[(3 + f) * ntr + F] * (A)x[hb + ce[f]];
+    for (int f = 0; f < 4; ++f) acc += (A)S[s_idx(F, 3 + f)] * (A)x[hb + ce[f]];
   }
   if (k < nlev) {
     size_t hb = nz + (size_t)k * nedge;
-    acc += (A)S[2 * ntr + F] * (A)x[F + ncol];
+    acc += (A)S[s_idx(F, 2)] * (A)x[F + ncol];
 #pragma unroll
-    for (int f = 0; f < 4; ++f) acc += (A)S[(7 + f) * ntr + F] * (A)x[hb + ce[f]];
+    for (int f = 0; f < 4; ++f) acc += (A)S[s_idx(F, 7 + f)] * (A)x[hb + ce[f]];
   }
   return acc;
 }
@@ -50,17 +50,17 @@ __device__ __forceinline__ A row_h(const Tm *__restrict__ S, size_t ntr, const T
                                    int k, int ncol, int nedge, size_t nz, const int t[8]) {
   size_t hb = nz + (size_t)k * nedge;
   size_t zb = (size_t)k * ncol;
-  A acc = (A)S[F] * (A)x[F];
-  acc += (A)S[ntr + F] * (A)x[zb + t[0]];
-  acc += (A)S[2 * ntr + F] * (A)x[zb + ncol + t[0]];
-  acc += (A)S[3 * ntr + F] * (A)x[hb + t[2]];
-  acc += (A)S[4 * ntr + F] * (A)x[hb + t[3]];
-  acc += (A)S[5 * ntr + F] * (A)x[hb + t[4]];
-  acc += (A)S[6 * ntr + F] * (A)x[zb + t[1]];
-  acc += (A)S[7 * ntr + F] * (A)x[zb + ncol + t[1]];
-  acc += (A)S[8 * ntr + F] * (A)x[hb + t[5]];
-  acc += (A)S[9 * ntr + F] * (A)x[hb + t[6]];
-  acc += (A)S[10 * ntr + F] * (A)x[hb + t[7]];
+  A acc = (A)S[s_idx(F, 0)] * (A)x[F];
+  acc += (A)S[s_idx(F, 1)] * (A)x[zb + t[0]];
+  acc += (A)S[s_idx(F, 2)] * (A)x[zb + ncol + t[0]];
+  acc += (A)S[s_idx(F, 3)] * (A)x[hb + t[2]];
+  acc += (A)S[s_idx(F, 4)] * (A)x[hb + t[3]];
+  acc += (A)S[s_idx(F, 5)] * (A)x[hb + t[4]];
+  acc += (A)S[s_idx(F, 6)] * (A)x[zb + t[1]];
+  acc += (A)S[s_idx(F, 7)] * (A)x[zb + ncol + t[1]];
+  acc += (A)S[s_idx(F, 8)] * (A)x[hb + t[5]];
+  acc += (A)S[s_idx(F, 9)] * (A)x[hb + t[6]];
+  acc += (A)S[s_idx(F, 10)] * (A)x[hb + t[7]];
   return acc;
 }
 
@@ -91,12 +91,12 @@ __device__ __forceinline__ void hrow_op(const Tm *__restrict__ S, const Tx *__re
   using A = typename Acc<Ty>::type;
   size_t F = nz + (size_t)k * nedge + e;
   if (OP == OP_SMOOTH0) {
-    lout[F] = omega * b[F] / (Ty)S[F];
+    lout[F] = omega * b[F] / (Ty)S[s_idx(F, 0)];
   } else {
     A v = row_h<A>(S, ntr, x, F, k, ncol, nedge, nz, t);
     if (OP != OP_APPLY) v = (A)b[F] - v;
     if (OP == OP_SMOOTH)
-      lout[F] = (Ty)x[F] + omega * (Ty)v / (Ty)S[F];
+      lout[F] = (Ty)x[F] + omega * (Ty)v / (Ty)S[s_idx(F, 0)];
     else
       y[F] = (Ty)v;
   }
@@ -226,7 +226,7 @@ __global__ void k_thomas_factor(const double *__restrict__ S, double *__restrict
   double up = 1.0, cprev = 0.0;
   for (int k = 0; k <= nlev; ++k) {
     size_t F = (size_t)k * ncol + col;
-    double a = S[ntr + F], b = S[F], c = S[2 * ntr + F];
+    double a = S[s_idx(F, 1)], b = S[s_idx(F, 0)], c = S[s_idx(F, 2)];
     double l = (k == 0) ? 0.0 : a / up;
     double u = b - l * cprev;
     fac[F] = l;
