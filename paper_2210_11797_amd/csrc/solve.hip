@@ -71,7 +71,7 @@ __device__ __forceinline__ A row_h(const Tm *__restrict__ S, size_t ntr, const T
 //             facets lout = x + omega (b - S x) / diag(S^hh) (point Jacobi)
 //   OP_SMOOTH0 the same from x = 0 on vertical facets only: lout = omega b / diag(S^hh)
 enum { OP_APPLY = 0, OP_RESID = 1, OP_SMOOTH = 2, OP_SMOOTH0 = 3 };
-constexpr int kRowChunk = 8;
+constexpr int kRowChunk = 2;  // layers per thread (swept 1-32 at 256x256x64: 2 is fastest)
 
 template <typename Tm, typename Tx, typename Ty, int OP>
 __device__ __forceinline__ void zrow_op(const Tm *__restrict__ S, const Tx *__restrict__ x, const Ty *__restrict__ b,
