@@ -226,11 +226,12 @@ def learned_leg(args, prob, s, rhs, sec_plain, dx, dz, dt):
 def p1_leg(args):
     """Order 1 (RT1 / DG1 / Q1 trace, 44 x 44 cell blocks) on the 128 x 128 x 32 box (dx = 10 km,
     dz = 500 m): the condensation in FP64 and on MFMA (FP32, BF16 split), and time-to-1e-8 of FGMRES
-    with the order-1 two-level preconditioner for each condensed operator."""
+    with the order-1 two-level preconditioner for each condensed operator, and for the mixed form
+    (FP64 operator, FP32 copy of S_K in the preconditioner)."""
     import numpy as np
     import torch
 
-    from paper_2210_11797_amd import HybSolver, Params, PREC_FP64, PREC_MFMA_BF16X, PREC_MFMA_FP32, levels_of
+    from paper_2210_11797_amd import HybSolver, Params, PREC_FP64, PREC_MFMA_BF16X, PREC_MFMA_FP32, PREC_MIXED, levels_of
     from synth import make_box, make_rhs_p1
 
     prob = make_box(nx=args.p1_nx, ny=args.p1_nx, nlev=args.p1_nlev, dx=10e3, dz=500.0, dt=600.0, mg_levels=4)
@@ -238,8 +239,8 @@ def p1_leg(args):
     rhs = [tuple(d(a) for a in make_rhs_p1(prob, sd)) for sd in range(3)]
     x = d(np.random.default_rng(0).standard_normal(4 * (prob.ncol * (prob.nlev + 1) + 2 * prob.ncol * prob.nlev)))
     out, y64 = {}, None
-    for name, prec, dtype in (("fp64", PREC_FP64, "fp64"), ("mfma_fp32", PREC_MFMA_FP32, "fp32"),
-                              ("mfma_bf16x", PREC_MFMA_BF16X, "bf16")):
+    for name, prec, dtype in (("fp64", PREC_FP64, "fp64"), ("mixed", PREC_MIXED, "fp64"),
+                              ("mfma_fp32", PREC_MFMA_FP32, "fp32"), ("mfma_bf16x", PREC_MFMA_BF16X, "bf16")):
         params = Params(dt=prob.dt, tau_u=prob.tau_u, tau_rho=prob.tau_rho, tau_theta=prob.tau_theta, cp=prob.cp,
                         rd=prob.rd, precision=prec, mg_coarse_sweeps=args.coarse_sweeps,
                         mg_coarse_cheb=0 if args.coarse_jacobi else 1)

@@ -139,8 +139,9 @@ typedef struct {
    the 4 dofs of a facet to the average of its cells, Gamma = H 1 / (P^T S P 1), and LineSmooth
    with 4x4 block-tridiagonal column solves on the horizontal facets and point Jacobi on the
    vertical ones; hyb_solve is FGMRES with it (FP64).  params.precision chooses the arithmetic of
-   the condensation of S_K (HYB_PREC_FP64 or the MFMA modes); after changing it call
-   hyb_condense(ctx, NULL, ...) again.  hyb_restrict and the learned stage return HYB_ESTATE at order 1. */
+   the condensation of S_K (HYB_PREC_FP64 or the MFMA modes, whose S_K is stored in FP32) or the
+   mixed form (HYB_PREC_MIXED: S_K condensed in FP64 for the outer operator, its FP32 copy in the
+   preconditioner's applications of S); after changing it call hyb_condense(ctx, NULL, ...) again.  hyb_restrict and the learned stage return HYB_ESTATE at order 1. */
 
 /* Create a context for one mesh.  stream: a hipStream_t (NULL = default stream).
    Fails with HYB_EINVAL on inconsistent tables (every edge must appear on

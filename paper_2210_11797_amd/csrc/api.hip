@@ -262,8 +262,8 @@ int hyb_create(const hyb_mesh *mesh, const hyb_params *params, void *stream, hyb
   if (c->order == 1) c->ntrace *= 4;
   {
     const bool mfma = params->precision == HYB_PREC_MFMA_FP32 || params->precision == HYB_PREC_MFMA_BF16X;
-    // MFMA condensation is an order-1 mode; order 1 has no mixed-precision solve
-    if ((c->order == 0 && mfma) || (c->order == 1 && params->precision == HYB_PREC_MIXED)) {
+    // MFMA condensation is an order-1 mode
+    if (c->order == 0 && mfma) {
       delete c;
       return HYB_EINVAL;
     }
@@ -328,7 +328,6 @@ int hyb_set_params(hyb_ctx *c, const hyb_params *params) {
   if (rc) return rc;
   bool prec_change = params->precision != c->p.precision;
   if (c->order == 1) {
-    if (params->precision == HYB_PREC_MIXED) return fail(c, HYB_EINVAL, "order 1 has no mixed-precision solve");
     if (params->learned) return fail(c, HYB_EINVAL, "order 1 has no learned stage");
     hyb_params p0 = *params;
     p0.precision = HYB_PREC_FP64;
@@ -498,7 +497,9 @@ int hyb_solve(hyb_ctx *c, const double *b, double *lam, double rtol, int32_t max
   if (rc) return rc;
   const size_t n = (size_t)c->ntrace;
   const int m = c->m;
-  const bool mixed = c->p.precision == HYB_PREC_MIXED;
+  // the order-0 mixed form keeps the preconditioned basis Z in FP32 (at order 1 the mixed form only
+  // changes the preconditioner's copy of S_K, and Z stays FP64)
+  const bool mixed = c->p.precision == HYB_PREC_MIXED && c->order == 0;
   double *V = c->V;
   double *h1 = c->hdev, *h2 = c->hdev + (m + 2), *nrm = c->hdev + 2 * (m + 2);
   double *hh = c->hhost;

@@ -75,7 +75,7 @@ struct P1State {
   double *cdiag = nullptr;  // [ncell][24] diagonal of C_K on the face dofs
   double *kdiag = nullptr;  // [ncell][24] diagonal of K_K
   double *SK = nullptr;     // [24 x 24][ncell] S_K = C_K [A_K^-1]_ff K_K, entry (r, j) at (r * 24 + j) * ncell
-  float *SKf = nullptr;     // [576][ncell] S_K in FP32 (the MFMA condensation modes)
+  float *SKf = nullptr;     // [576][ncell] S_K in FP32 (the MFMA modes; the preconditioner's copy when mixed)
   double *bK = nullptr;     // [24][ncell] the cells' shares of B_lambda, or of S x on its way to the rows
   double *fac = nullptr;    // [748][ncell] factors of A_K by its block structure: M^-1, M^-1 G, Dr, Sg^-1
   // two-level preconditioner
@@ -235,8 +235,9 @@ bool p1_sk_fp32(const hyb_ctx *c);
 // mode 0: the cells' shares of B_lambda into p1.bK; mode 1: recovery into u [36][ncell], pi [8][ncell]
 hipError_t p1_cell_solve(hyb_ctx *c, const double *r_u, const double *r_p, const double *lam, int mode, double *u,
                          double *pi);
-// mode 0: y = S x; mode 1: y = gather of p1.bK (B_lambda); mode 2: y = b - S x; mode 3: y = diag(S)
-hipError_t p1_rows(hyb_ctx *c, const double *x, double *y, int mode, const double *b);
+// mode 0: y = S x; mode 1: y = gather of p1.bK (B_lambda); mode 2: y = b - S x; mode 3: y = diag(S);
+// precond: an application inside the preconditioner (the FP32 copy of S_K in the mixed form)
+hipError_t p1_rows(hyb_ctx *c, const double *x, double *y, int mode, const double *b, bool precond = false);
 hipError_t p1_precond_setup(hyb_ctx *c);
 hipError_t p1_precondition(hyb_ctx *c, const double *r, double *z);
 void p1_free(hyb_ctx *c);

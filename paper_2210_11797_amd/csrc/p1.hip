@@ -917,7 +917,8 @@ hipError_t p1_assemble(hyb_ctx *c, const double *theta_w, const double *exner_ha
 
 // S_K in the arithmetic of params.precision: FP64 from the block structure, or the dense elimination
 // of A_K on MFMA (FP32, BF16 split); the per-solve cell factors always in FP64 from the structure.
-// S_K is held in FP32 when the matrix cores condensed it (FP32-accurate there), else in FP64
+// S_K is held in FP32 when the matrix cores condensed it (FP32-accurate there), else in FP64; the
+// mixed form keeps an FP32 copy of the FP64 S_K for the preconditioner
 bool p1_sk_fp32(const hyb_ctx *c) {
   return c->p.precision == HYB_PREC_MFMA_FP32 || c->p.precision == HYB_PREC_MFMA_BF16X;
 }
@@ -939,9 +940,11 @@ hipError_t p1_factor(hyb_ctx *c) {
   }
   const int slot = prof_begin(c, F_P1_FACTOR);
   hipLaunchKernelGGL(k_p1_condense_struct, dim3(nblk(c->ncell, kSW)), dim3(64 * kSW), 0, c->stream, c->ncell, s.A,
-                     s.cdiag, s.kdiag, s.SK, s.fac, prec == HYB_PREC_FP64 ? 1 : 0);
+                     s.cdiag, s.kdiag, s.SK, s.fac, p1_sk_fp32(c) ? 0 : 1);
   prof_end(c, F_P1_FACTOR, slot);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e || prec != HYB_PREC_MIXED) return e;
+  return launch_to_float(c, s.SK, s.SKf, (size_t)NS * c->ncell);
 }
 
 hipError_t p1_cell_solve(hyb_ctx *c, const double *r_u, const double *r_p, const double *lam, int mode, double *u,
@@ -955,13 +958,13 @@ hipError_t p1_cell_solve(hyb_ctx *c, const double *r_u, const double *r_p, const
   return hipGetLastError();
 }
 
-hipError_t p1_rows(hyb_ctx *c, const double *x, double *y, int mode, const double *b) {
+hipError_t p1_rows(hyb_ctx *c, const double *x, double *y, int mode, const double *b, bool precond) {
   P1State &s = c->p1;
   const LevelDev &L0 = c->lv[0];
   const size_t ntr = (size_t)c->ntrace;
   int slot = prof_begin(c, F_TRACE_APPLY);
   if (mode != 1) {  // mode 1 gathers the shares already in bK
-    if (p1_sk_fp32(c))
+    if (p1_sk_fp32(c) || (precond && c->p.precision == HYB_PREC_MIXED))
       hipLaunchKernelGGL(k_p1_cell_mv<float>, dim3(nblk(c->ncell)), dim3(kBlock), 0, c->stream, c->ncell, c->ncol,
                          c->nedge, (size_t)c->nz, L0.col_edge, (const float *)s.SKf, x, mode == 3 ? 1 : 0, s.bK);
     else
@@ -1012,7 +1015,7 @@ hipError_t p1_precondition(hyb_ctx *c, const double *r, double *z) {
   auto sweep = [&](const double *lin, double *lout) -> hipError_t {
     hipError_t q;
     if (lin) {
-      if ((q = p1_rows(c, lin, R, 2, r))) return q;
+      if ((q = p1_rows(c, lin, R, 2, r, true))) return q;
     }
     const double *res = lin ? R : r;
     int slot = prof_begin(c, F_THOMAS);
@@ -1034,7 +1037,7 @@ hipError_t p1_precondition(hyb_ctx *c, const double *r, double *z) {
     hipLaunchKernelGGL(k_p1_fill, dim3(nblk(ntr)), dim3(kBlock), 0, c->stream, lam, ntr, 0.0);
     if ((e = hipGetLastError())) return e;
   }
-  if ((e = p1_rows(c, lam, R, 2, r))) return e;
+  if ((e = p1_rows(c, lam, R, 2, r, true))) return e;
   int slot = prof_begin(c, F_RESTRICT);
   hipLaunchKernelGGL(k_p1_restrict, dim3(nblk(nc)), dim3(kBlock), 0, c->stream, c->nlev, c->ncol, c->nedge,
                      (size_t)c->nz, L0.col_edge, R, s.gamma, (double *)cc->lv[0].b);

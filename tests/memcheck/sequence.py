@@ -266,6 +266,15 @@ def p1_sequence(lib):
     cells = np.empty(c.ncell)
     check(lib.hyb_restrict(c.h, P(b), P(cells), 0) < 0, "order 1: calls it does not provide are rejected")
     c.close()
+    # the mixed form: FP64 outer operator, FP32 copy of S_K inside the preconditioner
+    cx = Ctx(lib, prob, order=1, precision=N.PREC_MIXED)
+    zx = np.empty(cx.ntrace)
+    cx.call("hyb_precondition", P(b), P(zx))
+    ez = np.abs(zx - z).max() / np.abs(z).max()
+    rc, info, lam_x = cx.solve(b, 1e-10)
+    check(0 < ez <= 1e-5 and rc == 0 and cx.residual(b, lam_x) <= 1.01e-10,
+          f"order 1, mixed form: preconditioner vs FP64 {ez:.1e}, FGMRES {info.iters} iterations")
+    cx.close()
     # S_K condensed on matrix cores (FP32, and BF16 split into hi + lo) against the FP64 operator
     for prec, tol in ((N.PREC_MFMA_FP32, 1e-5), (N.PREC_MFMA_BF16X, 1e-4)):
         cm = Ctx(lib, prob, order=1, precision=prec)

@@ -19,8 +19,8 @@ CASES = {
 }
 
 
-def make_p1_solver(prob):
-    s = HybSolver(prob.nlev, levels_of(prob), prob.dx, prob.dy, prob.dz, params_for(prob), order=1)
+def make_p1_solver(prob, **kw):
+    s = HybSolver(prob.nlev, levels_of(prob), prob.dx, prob.dy, prob.dz, params_for(prob, **kw), order=1)
     s.assemble_local(dev(prob.theta_w), dev(prob.exner_hat_w), dev(prob.exner_c), dev(prob.rho_c))
     s.condense()
     return s
@@ -187,3 +187,38 @@ def test_p1_precondition_and_solve_match_oracle(case):
     say(f"[p1] {case}: M(B) {e_m:.1e}; solve {info['iters']} its (oracle {its_ref}), lambda {e_l:.1e}")
     assert e_m <= 1e-9
     assert info["status"] == 0 and e_l <= 1e-9 and abs(info["iters"] - its_ref) <= 1
+
+
+@pytest.mark.gpu
+def test_p1_mixed_form_reaches_fp64_tolerance():
+    """The mixed form at order 1 (S_K condensed in FP64 for the outer operator, its FP32 copy in the
+    preconditioner): the preconditioner differs from the FP64 one by FP32 rounding, FGMRES reaches
+    the FP64 tolerance on the FP64 operator (measured by the oracle), and the solution agrees with
+    the direct solution as that tolerance allows."""
+    import torch
+    import scipy.sparse.linalg as spla
+
+    from paper_2210_11797_amd import PREC_MIXED
+
+    prob = make_box(**PRECOND_CASES["8x6x5"])
+    say("[p1] mixed form 8x6x5")
+    s64 = make_p1_solver(prob)
+    smx = make_p1_solver(prob, precision=PREC_MIXED)
+    mesh = BoxMesh(prob.nx, prob.ny, prob.nlev, prob.dx, prob.dy, prob.z)
+    h = op1.HybridP1(mesh, op1.local_matrices(mesh, prob))
+    r_u, r_p = make_rhs_p1(prob, 6)
+    B = h.rhs(r_u.reshape(36, -1).T.copy(), r_p.reshape(8, -1).T.copy())
+    z64, zmx = (torch.empty(s64.ntrace, dtype=torch.float64, device="cuda") for _ in range(2))
+    s64.precondition(dev(B), z64)
+    smx.precondition(dev(B), zmx)
+    e_z = rel_max(host(zmx), host(z64))
+    b = torch.empty_like(z64)
+    smx.condense(dev(r_u), dev(r_p), b)
+    lam = torch.zeros_like(z64)
+    info = smx.solve(b, lam, rtol=1e-8, maxit=500)
+    res = np.linalg.norm(B - h.S @ host(lam)) / np.linalg.norm(B)
+    lref = spla.splu(h.S.tocsc()).solve(B)
+    e_l = np.linalg.norm(host(lam) - lref) / np.linalg.norm(lref)
+    say(f"[p1 mixed] M(B) vs FP64 {e_z:.1e}; {info['iters']} its, oracle residual {res:.1e}, lambda {e_l:.1e}")
+    assert 0 < e_z <= 1e-5
+    assert info["status"] == 0 and res <= 1e-8 and e_l <= 1e-5
