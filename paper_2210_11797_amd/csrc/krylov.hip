@@ -9,6 +9,7 @@ namespace {
 
 constexpr int kChunk = 8;  // dot products accumulated per pass over w
 constexpr int kRedBlocks = 2048;
+constexpr int kDgsStage = 1;  // kBlock-entry chunks staged per reduction step (swept 1, 2, 4 with 1024-8192 blocks)
 
 inline unsigned nblk(size_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
 
@@ -198,13 +199,13 @@ __global__ void __launch_bounds__(kBlock) k_gs_update_scale(const double *__rest
 // Gram-Schmidt with delayed reorthogonalisation: one reduction pass and one update pass over the
 // basis per step.  u = a_j was orthogonalised once in the previous step; w = a_{j+1} is the new
 // vector.  Outputs (in partial, then summed): a_k . u for k <= j at [k], a_k . w for k <= j at
-// [j + 1 + k], and w . w at [2 j + 2].  A workgroup stages 512 entries of u and w in LDS; its waves
-// split the basis vectors (wave q takes k = q, q + 4, ...) and each runs over all 512 entries, so
+// [j + 1 + k], and w . w at [2 j + 2].  A workgroup stages kDgsStage x 256 entries of u and w in LDS; its
+// waves split the basis vectors (wave q takes k = q, q + 4, ...) and each runs over all of them, so
 // every vector entry is loaded once and a thread keeps at most 2 KW accumulators.
 template <int KW>
 __global__ void __launch_bounds__(kBlock) k_dgs_dots(const double *__restrict__ a, size_t lda, int j, size_t n,
                                                      double *__restrict__ partial) {
-  constexpr int NW = kBlock / 64, NE = 2 * kBlock;  // entries staged per step
+  constexpr int NW = kBlock / 64, RS = kDgsStage, NE = RS * kBlock;  // entries staged per step
   __shared__ double su[NE], sw[NE], red[NW];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double au[KW], aw[KW], ww = 0.0;
@@ -213,13 +214,16 @@ __global__ void __launch_bounds__(kBlock) k_dgs_dots(const double *__restrict__ 
   const double *u = a + (size_t)j * lda, *w = a + (size_t)(j + 1) * lda;
   const size_t stride = (size_t)gridDim.x * NE;
   for (size_t base = (size_t)blockIdx.x * NE; base < n; base += stride) {
-    const size_t i0 = base + threadIdx.x, i1 = i0 + kBlock;
-    const double u0 = i0 < n ? u[i0] : 0.0, w0 = i0 < n ? w[i0] : 0.0;
-    const double u1 = i1 < n ? u[i1] : 0.0, w1 = i1 < n ? w[i1] : 0.0;
-    ww += w0 * w0 + w1 * w1;
+    double ur[RS], wr[RS];
+#pragma unroll
+    for (int q = 0; q < RS; ++q) {
+      const size_t i = base + q * kBlock + threadIdx.x;
+      ur[q] = i < n ? u[i] : 0.0, wr[q] = i < n ? w[i] : 0.0;
+      ww += wr[q] * wr[q];
+    }
     __syncthreads();  // the previous entries are no longer read
-    su[threadIdx.x] = u0, su[kBlock + threadIdx.x] = u1;
-    sw[threadIdx.x] = w0, sw[kBlock + threadIdx.x] = w1;
+#pragma unroll
+    for (int q = 0; q < RS; ++q) su[q * kBlock + threadIdx.x] = ur[q], sw[q * kBlock + threadIdx.x] = wr[q];
     __syncthreads();
 #pragma unroll
     for (int g = 0; g < NE / 64; ++g) {
@@ -387,7 +391,7 @@ hipError_t launch_gs_finish(hyb_ctx *c, const double *V, size_t n, int nv, const
 hipError_t launch_dgs_dots(hyb_ctx *c, const double *V, size_t n, int j, double *out_dev) {
   if (j < 0 || j >= kDgsMax || 2 * j + 3 > 2 * (c->m + 2)) return hipErrorInvalidValue;
   int slot = prof_begin(c, F_KRYLOV);
-  const unsigned nb = std::min<unsigned>(kRedBlocks, nblk(n, 2 * kBlock));
+  const unsigned nb = std::min<unsigned>(kRedBlocks, nblk(n, kDgsStage * kBlock));
   static_assert(kBlock == 256, "four waves split the basis vectors");
   if (j < 8)
     hipLaunchKernelGGL((k_dgs_dots<2>), dim3(nb), dim3(kBlock), 0, c->stream, V, n, j, n, c->partial);
