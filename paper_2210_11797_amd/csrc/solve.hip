@@ -71,6 +71,7 @@ __device__ __forceinline__ A row_h(const Tm *__restrict__ S, size_t ntr, const T
 //             facets lout = x + omega (b - S x) / diag(S^hh) (point Jacobi)
 //   OP_SMOOTH0 the same from x = 0 on vertical facets only: lout = omega b / diag(S^hh)
 enum { OP_APPLY = 0, OP_RESID = 1, OP_SMOOTH = 2, OP_SMOOTH0 = 3 };
+constexpr int kRowBlock = 256;  // threads per workgroup of the row kernels (swept 64-512)
 constexpr int kRowChunk = 2;  // layers per thread (swept 1-32 at 256x256x64: 2 is fastest)
 
 template <typename Tm, typename Tx, typename Ty, int OP>
@@ -108,7 +109,7 @@ __device__ __forceinline__ void hrow_op(const Tm *__restrict__ S, const Tx *__re
 // round-robin placement over the XCDs: measured, it spreads the streams over the HBM channels
 // better than giving each XCD a contiguous range (which would raise L2 reuse of the gathers).
 template <typename Tm, typename Tx, typename Ty, int OP>
-__global__ void __launch_bounds__(kBlock) k_rows(const Tm *__restrict__ S, const Tx *__restrict__ x,
+__global__ void __launch_bounds__(kRowBlock) k_rows(const Tm *__restrict__ S, const Tx *__restrict__ x,
                                                  const Ty *__restrict__ b, Ty *__restrict__ y,
                                                  Ty *__restrict__ lout, int nlev, int ncol, int nedge, size_t nz,
                                                  size_t ntr, int ent0, const int32_t *__restrict__ col_edge,
@@ -144,7 +145,7 @@ __global__ void __launch_bounds__(kBlock) k_rows(const Tm *__restrict__ S, const
 // grid of the row kernels: entities (columns, plus edges unless column-owned) x layer chunks
 inline dim3 row_grid(const hyb_ctx *c, bool edges_only) {
   int ents = edges_only ? c->nedge : c->ncol + c->nedge;
-  return dim3(nblk(ents), (c->nlev + kRowChunk) / kRowChunk);
+  return dim3(nblk(ents, kRowBlock), (c->nlev + kRowChunk) / kRowChunk);
 }
 inline int row_ent0(const hyb_ctx *c, bool edges_only) { return edges_only ? c->ncol : 0; }
 
@@ -380,10 +381,10 @@ hipError_t line_smooth(hyb_ctx *c, const T *S, const T *B, const T *lin, T *lout
   int slot = prof_begin(c, fam);
   dim3 grid = row_grid(c, zero);
   if (zero)
-    hipLaunchKernelGGL((k_rows<T, T, T, OP_SMOOTH0>), grid, dim3(kBlock), 0, c->stream, S, lin, B, R, lout, c->nlev,
+    hipLaunchKernelGGL((k_rows<T, T, T, OP_SMOOTH0>), grid, dim3(kRowBlock), 0, c->stream, S, lin, B, R, lout, c->nlev,
                        c->ncol, c->nedge, nz, ntr, row_ent0(c, true), L0.col_edge, L0.est, om);
   else
-    hipLaunchKernelGGL((k_rows<T, T, T, OP_SMOOTH>), grid, dim3(kBlock), 0, c->stream, S, lin, B, R, lout, c->nlev,
+    hipLaunchKernelGGL((k_rows<T, T, T, OP_SMOOTH>), grid, dim3(kRowBlock), 0, c->stream, S, lin, B, R, lout, c->nlev,
                        c->ncol, c->nedge, nz, ntr, 0, L0.col_edge, L0.est, om);
   prof_end(c, fam, slot);
   HYB_TRY(hipGetLastError());
@@ -601,10 +602,10 @@ hipError_t launch_trace_apply(hyb_ctx *c, const Tm *S, const Tx *x, const Ty *b,
   int slot = prof_begin(c, F_TRACE_APPLY);
   dim3 grid = row_grid(c, false);
   if (mode == 0)
-    hipLaunchKernelGGL((k_rows<Tm, Tx, Ty, OP_APPLY>), grid, dim3(kBlock), 0, c->stream, S, x, b, y, (Ty *)nullptr,
+    hipLaunchKernelGGL((k_rows<Tm, Tx, Ty, OP_APPLY>), grid, dim3(kRowBlock), 0, c->stream, S, x, b, y, (Ty *)nullptr,
                        c->nlev, c->ncol, c->nedge, (size_t)c->nz, (size_t)c->ntrace, 0, L0.col_edge, L0.est, (Ty)0);
   else
-    hipLaunchKernelGGL((k_rows<Tm, Tx, Ty, OP_RESID>), grid, dim3(kBlock), 0, c->stream, S, x, b, y, (Ty *)nullptr,
+    hipLaunchKernelGGL((k_rows<Tm, Tx, Ty, OP_RESID>), grid, dim3(kRowBlock), 0, c->stream, S, x, b, y, (Ty *)nullptr,
                        c->nlev, c->ncol, c->nedge, (size_t)c->nz, (size_t)c->ntrace, 0, L0.col_edge, L0.est, (Ty)0);
   prof_end(c, F_TRACE_APPLY, slot);
   return hipGetLastError();
