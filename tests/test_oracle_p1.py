@@ -270,3 +270,23 @@ def test_fgmres_with_two_level_p1_reaches_the_direct_solution():
     lam = spla_solve(h.S, B)
     assert ok and its < 60
     assert np.abs(x - lam).max() <= 1e-9 * np.abs(lam).max()
+
+
+def test_velocity_block_is_twelve_3x3_blocks():
+    """On an axis-aligned cell the RT1 functions are Lagrange functions on the Gauss points in their
+    tangential directions, which are orthogonal under the Gauss rule, so M = m2 - q22 couples a
+    function only to the two others of its direction and tangential point: twelve 3x3 blocks
+    {4 (2 d) + i, 4 (2 d + 1) + i, 24 + 4 d + i}.  The FP64 condensation of the library relies on it;
+    checked on a stretched, perturbed box (every entry outside the blocks below 1e-14 of the largest)."""
+    prob, mesh = _mesh(nx=3, ny=2, nlev=4, perturb=0.1, dx=6e3, ztop=9e3, stretch="quadratic")
+    A = p1.local_matrices(mesh, prob)["A"]
+    M = A[:, :36, :36]
+    mask = np.zeros((36, 36), bool)
+    for d in range(3):
+        for i in range(4):
+            idx = [8 * d + i, 8 * d + 4 + i, 24 + 4 * d + i]
+            mask[np.ix_(idx, idx)] = True
+    outside = np.abs(M[:, ~mask]).max()
+    assert outside <= 1e-14 * np.abs(M).max(), outside
+    # and the blocks themselves are full (no further structure assumed)
+    assert np.abs(M[:, mask]).min() > 0
