@@ -573,8 +573,10 @@ int hyb_solve(hyb_ctx *c, const double *b, double *lam, double rtol, int32_t max
       } else {
         double *zj = (double *)c->Z + (size_t)j * n;
         CHECK_HIP(precondition<double>(c, vj, zj), "precondition");
-        if (learned) CHECK_HIP(learned_stage<double>(c, vj, zj), "learned stage");
-        CHECK_HIP((launch_trace_apply<double, double, double>(c, c->S, zj, nullptr, w, 0)), "matvec");
+        if (learned)  // the stage's own applications of S give w = S z (no separate matvec)
+          CHECK_HIP(learned_stage<double>(c, vj, zj, w), "learned stage");
+        else
+          CHECK_HIP((launch_trace_apply<double, double, double>(c, c->S, zj, nullptr, w, 0)), "matvec");
       }
       return HYB_OK;
     };

@@ -110,8 +110,8 @@ struct hyb_ctx {
   double *Scell = nullptr;  // [36][ncell] S_K = [A_K^-1]_uu diag(k)  (setup only)
   double *bcell = nullptr;  // [6][ncell] [A_K^-1 R_K]_u
   // trace operator
-  double *S = nullptr;      // [11][ntrace]
-  float *Sf = nullptr;      // [11][ntrace] FP32 copy
+  double *S = nullptr;      // 11-entry rows in tiles of 64 rows (s_idx)
+  float *Sf = nullptr;      // FP32 copy, same layout
   double *m2l = nullptr;    // [ntrace] lumped velocity mass (interior facets)
   double *zfac = nullptr;   // [3][nz] LU factors of S^zz per column: l, 1/u, c/u
   float *zfacf = nullptr;
@@ -260,6 +260,6 @@ hipError_t launch_restrict_cells(hyb_ctx *c, const double *r, double *cells, int
 // learned stage: d = s P (N(c / s) / H_diag), c = Gamma P^T (r - S z), s = rms(c); z += d if it
 // lowers ||r - S z||, else counted as a fallback
 template <typename Tz>
-hipError_t learned_stage(hyb_ctx *c, const double *r, Tz *z);
+hipError_t learned_stage(hyb_ctx *c, const double *r, Tz *z, double *Sz = nullptr);
 
 }  // namespace hyb

@@ -350,6 +350,16 @@ __global__ void k_apply_correction(const double *__restrict__ d, double *__restr
   if (i < n) z[i] = (Tz)((double)z[i] + d[i]);
 }
 
+// w = S z after the stage from the applications it already made: r - r' + S d if the correction
+// was kept (r' = r - S z of the plain z), else r - r'
+__global__ void k_stage_matvec(const double *__restrict__ r, const double *__restrict__ rp,
+                               const double *__restrict__ sd, const double *__restrict__ scal, double *__restrict__ w,
+                               size_t n, double tau2) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool ok = isfinite(scal[1]) && scal[3] < tau2 * scal[4];  // the same decision as the apply
+  if (i < n) w[i] = r[i] - rp[i] + (ok ? sd[i] : 0.0);
+}
+
 // out_F = (P (y / H_diag))_F for one sample of network outputs y [ncell]
 __global__ void k_prolong_q(const float *__restrict__ y, const double *__restrict__ hdiag, double *__restrict__ out,
                             int nlev, int ncol, int nedge, size_t nz, size_t ntr, const int32_t *__restrict__ edge_col) {
@@ -798,7 +808,7 @@ hipError_t nn_adam(hyb_ctx *c, float lr) {
 // otherwise z stays the plain cycle's output and the fallback counter scal[2] grows (also when the
 // network output is not finite).  Everything stays on the device; no host synchronisation.
 template <typename Tz>
-hipError_t learned_stage(hyb_ctx *c, const double *r, Tz *z) {
+hipError_t learned_stage(hyb_ctx *c, const double *r, Tz *z, double *Sz) {
   NNState &s = c->nn;
   hipError_t e;
   const size_t n = (size_t)c->ncell, ntr = (size_t)c->ntrace;
@@ -839,13 +849,16 @@ hipError_t learned_stage(hyb_ctx *c, const double *r, Tz *z) {
   hipLaunchKernelGGL(k_judge_sums, dim3(nbt), dim3(kBlock), 0, c->stream, c->t64, s.sd64, ntr, part);
   hipLaunchKernelGGL(k_sum_into, dim3(1), dim3(64), 0, c->stream, part, (int)nbt, s.scal + 3);
   hipLaunchKernelGGL(k_sum_into, dim3(1), dim3(64), 0, c->stream, part + nbt, (int)nbt, s.scal + 4);
+  if (Sz)  // before the apply, which counts a rejected correction in scal[2] (not read here)
+    hipLaunchKernelGGL(k_stage_matvec, dim3(nblk(ntr)), dim3(kBlock), 0, c->stream, r, c->t64, s.sd64, s.scal, Sz, ntr,
+                       c->p.learned_tau * c->p.learned_tau);
   hipLaunchKernelGGL((k_apply_correction<Tz>), dim3(nblk(ntr)), dim3(kBlock), 0, c->stream, s.d64, s.scal, z, ntr,
                      c->p.learned_tau * c->p.learned_tau);
   prof_end(c, F_NN, slot);
   return hipGetLastError();
 }
-template hipError_t learned_stage<double>(hyb_ctx *, const double *, double *);
-template hipError_t learned_stage<float>(hyb_ctx *, const double *, float *);
+template hipError_t learned_stage<double>(hyb_ctx *, const double *, double *, double *);
+template hipError_t learned_stage<float>(hyb_ctx *, const double *, float *, double *);
 
 void nn_free(hyb_ctx *c) {
   NNState &s = c->nn;
