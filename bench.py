@@ -322,7 +322,8 @@ def main():
     ap.add_argument("--p1-nx", type=int, default=128)
     ap.add_argument("--p1-nlev", type=int, default=32)
     ap.add_argument("--train-nx", type=int, default=64, help="box on which the learned stage is trained")
-    ap.add_argument("--train-steps", type=int, default=1500)
+    ap.add_argument("--train-steps", type=int, default=300,
+                    help="Adam steps of the learned stage (300 generalised better to the 256x256x64 box than 1500)")
     ap.add_argument("--coarse-sweeps", type=int, default=6,
                     help="steps of the coarsest multigrid solve (Chebyshev semi-iteration, or block Jacobi)")
     ap.add_argument("--coarse-jacobi", action="store_true",
