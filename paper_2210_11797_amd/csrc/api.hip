@@ -562,7 +562,8 @@ int hyb_solve(hyb_ctx *c, const double *b, double *lam, double rtol, int32_t max
       double *vj = V + (size_t)j * n, *w = V + (size_t)(j + 1) * n;
       if (mixed) {
         float *zf = (float *)c->Z + (size_t)j * n;
-        CHECK_HIP(launch_convert(c, vj, (float *)c->tIn, n), "convert");
+        // the two-pass Gram-Schmidt writes the FP32 copy of V_j with V_j itself (steps j > 0)
+        if (j == 0 || m > kDgsMax) CHECK_HIP(launch_convert(c, vj, (float *)c->tIn, n), "convert");
         CHECK_HIP(precondition<float>(c, (const float *)c->tIn, zf), "precondition");
         if (learned) CHECK_HIP(learned_stage<float>(c, vj, zf), "learned stage");
         CHECK_HIP((launch_trace_apply<double, float, double>(c, c->S, zf, nullptr, w, 0)), "matvec");
@@ -620,7 +621,8 @@ int hyb_solve(hyb_ctx *c, const double *b, double *lam, double rtol, int32_t max
         const double eta2 = hh[2 * j + 2] - b2 - hjj * hjj;
         const double eta = (eta2 > 0.0 && std::isfinite(eta2)) ? std::sqrt(eta2) : 0.0;
         col[j + 1] = eta;
-        CHECK_HIP(launch_dgs_update(c, V, n, j, ca.data(), cb.data(), 1.0 / rho, hjj, eta > 0.0 ? 1.0 / eta : 0.0),
+        CHECK_HIP(launch_dgs_update(c, V, n, j, ca.data(), cb.data(), 1.0 / rho, hjj, eta > 0.0 ? 1.0 / eta : 0.0,
+                                    mixed ? (float *)c->tIn : nullptr),
                   "gram-schmidt update");
         eta_prev = eta;
         // Givens QR of columns 0..j

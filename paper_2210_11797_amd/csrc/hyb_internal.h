@@ -213,11 +213,12 @@ hipError_t launch_gs_finish(hyb_ctx *c, const double *V, size_t n, int nv, const
 // Gram-Schmidt with delayed reorthogonalisation (steps j < kDgsMax): dots of V_j and V_{j+1}
 // against V_0..V_j and ||V_{j+1}||^2 (2 j + 3 values into out_dev: [V_k . V_j], [V_k . V_{j+1}],
 // ||V_{j+1}||^2); then V_j <- (V_j - sum_{k<j} ca_k V_k) rinv and
-// V_{j+1} <- (V_{j+1} - sum_{k<j} cb_k V_k - hjj V_j) einv in one pass.
+// V_{j+1} <- (V_{j+1} - sum_{k<j} cb_k V_k - hjj V_j) einv in one pass (and its FP32 copy into wf
+// if wf is not null).
 constexpr int kDgsMax = 31;
 hipError_t launch_dgs_dots(hyb_ctx *c, const double *V, size_t n, int j, double *out_dev);
 hipError_t launch_dgs_update(hyb_ctx *c, double *V, size_t n, int j, const double *ca, const double *cb, double rinv,
-                             double hjj, double einv);
+                             double hjj, double einv, float *wf = nullptr);
 // w -= sum_k h[k] a[k], then nrm_dev[0] = ||w||^2
 hipError_t launch_axpy_norm(hyb_ctx *c, const double *a, size_t lda, int nv, const double *h_dev, double *w,
                             size_t n, double *nrm_dev);

@@ -271,7 +271,8 @@ struct DgsCoef {
 // a_{j+1} <- (w - sum_{k<j} cb_k a_k - hjj a_j) einv (w orthogonalised once and scaled).
 template <int NV>
 __global__ void __launch_bounds__(kBlock) k_dgs_update(double *__restrict__ a, size_t lda, int j, DgsCoef cf,
-                                                       double rinv, double hjj, double einv, size_t n) {
+                                                       double rinv, double hjj, double einv, size_t n,
+                                                       float *__restrict__ wf) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double su = 0.0, sw = 0.0;
@@ -285,7 +286,9 @@ __global__ void __launch_bounds__(kBlock) k_dgs_update(double *__restrict__ a, s
   double *u = a + (size_t)j * lda, *w = a + (size_t)(j + 1) * lda;
   const double vj = (u[i] - su) * rinv;
   u[i] = vj;
-  w[i] = (w[i] - sw - hjj * vj) * einv;
+  const double wn = (w[i] - sw - hjj * vj) * einv;
+  w[i] = wn;
+  if (wf) wf[i] = (float)wn;  // the FP32 input of the next preconditioner application (mixed form)
 }
 
 template <typename Tz>
@@ -405,17 +408,20 @@ hipError_t launch_dgs_dots(hyb_ctx *c, const double *V, size_t n, int j, double 
 }
 
 hipError_t launch_dgs_update(hyb_ctx *c, double *V, size_t n, int j, const double *ca, const double *cb, double rinv,
-                             double hjj, double einv) {
+                             double hjj, double einv, float *wf) {
   if (j < 0 || j >= kDgsMax) return hipErrorInvalidValue;
   DgsCoef cf{};
   for (int k = 0; k < j; ++k) cf.a[k] = ca[k], cf.b[k] = cb[k];
   int slot = prof_begin(c, F_KRYLOV);
   if (j < 8)
-    hipLaunchKernelGGL((k_dgs_update<8>), dim3(nblk(n)), dim3(kBlock), 0, c->stream, V, n, j, cf, rinv, hjj, einv, n);
+    hipLaunchKernelGGL((k_dgs_update<8>), dim3(nblk(n)), dim3(kBlock), 0, c->stream, V, n, j, cf, rinv, hjj, einv, n,
+                       wf);
   else if (j < 16)
-    hipLaunchKernelGGL((k_dgs_update<16>), dim3(nblk(n)), dim3(kBlock), 0, c->stream, V, n, j, cf, rinv, hjj, einv, n);
+    hipLaunchKernelGGL((k_dgs_update<16>), dim3(nblk(n)), dim3(kBlock), 0, c->stream, V, n, j, cf, rinv, hjj, einv, n,
+                       wf);
   else
-    hipLaunchKernelGGL((k_dgs_update<32>), dim3(nblk(n)), dim3(kBlock), 0, c->stream, V, n, j, cf, rinv, hjj, einv, n);
+    hipLaunchKernelGGL((k_dgs_update<32>), dim3(nblk(n)), dim3(kBlock), 0, c->stream, V, n, j, cf, rinv, hjj, einv, n,
+                       wf);
   prof_end(c, F_KRYLOV, slot);
   return hipGetLastError();
 }
