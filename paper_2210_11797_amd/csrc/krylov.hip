@@ -233,7 +233,7 @@ __global__ void __launch_bounds__(kBlock) k_dgs_dots(const double *__restrict__ 
       for (int q = 0; q < KW; ++q) {
         const int k = wv + NW * q;
         if (k < j) {
-          const double v = ii < n ? a[(size_t)k * lda + ii] : 0.0;
+          const double v = ii < n ? __builtin_nontemporal_load(&a[(size_t)k * lda + ii]) : 0.0;  // streamed
           au[q] += v * us;
           aw[q] += v * ws;
         } else if (k == j) {
@@ -279,7 +279,7 @@ __global__ void __launch_bounds__(kBlock) k_dgs_update(double *__restrict__ a, s
 #pragma unroll
   for (int k = 0; k < NV; ++k)
     if (k < j) {
-      const double v = a[(size_t)k * lda + i];
+      const double v = __builtin_nontemporal_load(&a[(size_t)k * lda + i]);  // streamed
       su += cf.a[k] * v;
       sw += cf.b[k] * v;
     }

@@ -702,7 +702,7 @@ __global__ void __launch_bounds__(kBlock) k_p1_cell_mv(int ncell, int ncol, int 
     const TS *row = SK + (size_t)r * NF * ncell + c;
     double s = 0.0;
 #pragma unroll
-    for (int j = 0; j < NF; ++j) s += (double)row[(size_t)j * ncell] * xk[j];
+    for (int j = 0; j < NF; ++j) s += (double)__builtin_nontemporal_load(&row[(size_t)j * ncell]) * xk[j];
     t[(size_t)r * ncell + c] = s;
   }
 }

@@ -51,6 +51,7 @@ unsigned cur_tid();
 #define __constant__
 #define __shared__ static
 #define __syncthreads() emu::barrier()
+#define __builtin_nontemporal_load(p) (*(p))
 
 #define hipLaunchKernelGGL(K, G, B, SH, ST, ...) \
   emu::launch(dim3(G), dim3(B), (size_t)(SH), [&]() { K(__VA_ARGS__); })
