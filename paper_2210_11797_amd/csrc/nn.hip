@@ -469,17 +469,22 @@ __global__ void __launch_bounds__(kBlock) k_inf_layer2_mfma(const uint16_t *__re
     const bool live = cell < ncell;
     const int k = live ? cell / ncol : 0, col = live ? cell - k * ncol : 0;
     nn_f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    int cn[NHT];  // the 3x3 neighbourhood first, so that the 45 activation loads do not wait on it
+#pragma unroll
+    for (int h = 0; h < NHT; ++h) cn[h] = live ? nb9[(size_t)h * ncol + col] : 0;
 #pragma unroll
     for (int h = 0; h < NHT; ++h) {
-      const int c2 = live ? nb9[(size_t)h * ncol + col] : 0;
+      const int c2 = cn[h];
 #pragma unroll
       for (int v = 0; v < NVT; ++v) {
-        const int kk = k + v - 2;
-        nn_bf16x4 A = {0, 0, 0, 0};
-        if (live && kk >= 0 && kk < nlev) {
-          const uint2 u = *reinterpret_cast<const uint2 *>(a1 + ((size_t)kk * ncol + c2) * C1 + 4 * q);
-          A[0] = (short)(u.x & 0xFFFFu), A[1] = (short)(u.x >> 16), A[2] = (short)(u.y & 0xFFFFu), A[3] = (short)(u.y >> 16);
-        }
+        // unconditional load from a clamped level (the value is discarded outside the column), so
+        // the loads of all taps can be issued ahead of the products
+        const int kk = k + v - 2, kc = kk < 0 ? 0 : (kk >= nlev ? nlev - 1 : kk);
+        const uint2 u = *reinterpret_cast<const uint2 *>(a1 + ((size_t)kc * ncol + c2) * C1 + 4 * q);
+        const bool in = live && kk == kc;
+        nn_bf16x4 A;
+        A[0] = in ? (short)(u.x & 0xFFFFu) : (short)0, A[1] = in ? (short)(u.x >> 16) : (short)0;
+        A[2] = in ? (short)(u.y & 0xFFFFu) : (short)0, A[3] = in ? (short)(u.y >> 16) : (short)0;
         // B: lane holds W2[co = r][ci = 4 q + j][tap], j = 0..3
         const uint2 w = sB[h * NVT + v][r][q];
         nn_bf16x4 B;
