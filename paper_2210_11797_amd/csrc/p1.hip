@@ -274,6 +274,7 @@ struct MfmaLds {
 // column's entry of a lane's row from lane 16 (l / 16) + kk: shuffles, no barriers.
 template <int KB>
 __device__ __forceinline__ void mf_elim_block(f32x4 (&acc)[3][5], int lc, int lg) {
+#pragma unroll
   for (int kk = 0; kk < 16; ++kk) {
     const int k = 16 * KB + kk, qk = kk & 3, src_row = 16 * (kk >> 2) + lc, src_col = 16 * lg + kk;
     float prow[5], pcol[3][4];
@@ -336,6 +337,7 @@ __device__ __forceinline__ void mf_trailing(f32x4 (&acc)[3][5], MfmaLds &S, bool
 template <int KB, bool SPLIT>
 __device__ __forceinline__ void mf_back_block(f32x4 (&acc)[3][5], MfmaLds &S, bool active, int lc, int lg) {
   if (active)
+#pragma unroll
     for (int ii = 15; ii >= 0; --ii) {
       const int qi = ii & 3, src_row = 16 * (ii >> 2) + lc, src_col = 16 * lg + ii;
       const float d = 1.f / __shfl(f4_get(acc[KB][KB], qi), 16 * (ii >> 2) + ii);
