@@ -185,3 +185,191 @@ def local_matrices(mesh: BoxMesh, prob, chunk: int = 8192, cells=None):
                          ("thF", thF)):
             out[key][sl] = val
     return out
+
+
+# ---------------------------------------------------------------------------------------------
+# Curved cells (the extruded cubed sphere): the same forms under a general cell map
+# ---------------------------------------------------------------------------------------------
+
+
+def trilinear(xi, eta, zeta):
+    """Trilinear shape functions of the 8 corners q = I + 2 J + 4 K at reference points and their
+    reference gradients: arrays (nq, 8) and (nq, 8, 3)."""
+    p = np.stack([xi, eta, zeta], axis=1)  # (nq, 3)
+    N = np.ones((p.shape[0], 8))
+    dN = np.ones((p.shape[0], 8, 3))
+    for q in range(8):
+        bits = (q & 1, (q >> 1) & 1, (q >> 2) & 1)
+        for d in range(3):
+            f = p[:, d] if bits[d] else 1.0 - p[:, d]
+            df = 1.0 if bits[d] else -1.0
+            N[:, q] *= f
+            for e in range(3):
+                dN[:, q, e] *= df if e == d else f
+    return N, dN
+
+
+def trilinear_map(X):
+    """The trilinear cell map through corners X (nc, 8, 3): returns map(xi, eta, zeta) -> (x, J)
+    with x (nc, nq, 3) and J[..., d, e] = d x_d / d xi_e."""
+    X = np.asarray(X, np.float64)
+
+    def m(xi, eta, zeta):
+        N, dN = trilinear(xi, eta, zeta)
+        return np.einsum("qa,cad->cqd", N, X), np.einsum("qae,cad->cqde", dN, X)
+
+    return m
+
+
+def shell_map(U, r0, r1):
+    """The cell map of an extruded cubed-sphere cell: x = r(zeta) u(xi, eta) with
+    r = r0 + zeta (r1 - r0) and u = p / |p|, p the bilinear interpolation of the column's corner
+    unit vectors U (nc, 4, 3) (corner I + 2 J at (xi, eta) = (I, J)).  Bottom and top faces lie on
+    spheres, the side faces in planes through the centre (great-circle edges), and the vertical
+    direction d x / d zeta is radial, orthogonal to the two horizontal ones."""
+    U = np.asarray(U, np.float64)
+    r0, r1 = np.asarray(r0, np.float64), np.asarray(r1, np.float64)
+
+    def m(xi, eta, zeta):
+        w = np.stack([(1 - xi) * (1 - eta), xi * (1 - eta), (1 - xi) * eta, xi * eta], axis=1)  # (nq, 4)
+        dwx = np.stack([-(1 - eta), 1 - eta, -eta, eta], axis=1)
+        dwy = np.stack([-(1 - xi), -xi, 1 - xi, xi], axis=1)
+        p = np.einsum("qa,cad->cqd", w, U)
+        px = np.einsum("qa,cad->cqd", dwx, U)
+        py = np.einsum("qa,cad->cqd", dwy, U)
+        npn = np.linalg.norm(p, axis=-1, keepdims=True)
+        u = p / npn
+        ux = (px - u * np.einsum("cqd,cqd->cq", u, px)[..., None]) / npn
+        uy = (py - u * np.einsum("cqd,cqd->cq", u, py)[..., None]) / npn
+        r = r0[:, None] + zeta[None, :] * (r1 - r0)[:, None]
+        x = r[..., None] * u
+        J = np.stack([r[..., None] * ux, r[..., None] * uy, (r1 - r0)[:, None, None] * u], axis=-1)
+        return x, J
+
+    return m
+
+
+def local_matrices_mapped(cmap, fields, consts, omega_vec=None, radial=True):
+    """Cell matrices of the hybridised system on cells given by a cell map ``cmap`` of the unit
+    cube (``trilinear_map`` or ``shell_map``).
+
+    The lowest-order broken Raviart-Thomas functions are the reference ones (unit outward flux
+    through their own face of the unit cube) mapped by the contravariant Piola transform
+    v = J v_hat / det J, so every velocity dof is still the flux through its face.  W_theta fields
+    are linear in the vertical reference coordinate; W3 functions are constant.  The vertical unit
+    vector z_hat is the radial direction x / |x| (``radial``) or +z.  Forms of Sec. 2.2: the
+    velocity mass with the Coriolis term tau_u dt <w . 2 Omega x u> (``omega_vec``, the rotation
+    vector; the mu term is read as zero), q22 with z_hat and d/dz = z_hat . grad, g^b, d, m3 by
+    the 3-point Gauss rule in each direction (weights det J); q32, m3^rho and m3^Pi by the
+    one-point rule at the reference centre (weight det J there); k and c over the faces with the
+    3x3 rule and the physical surface element (cross product of the face's tangent vectors).
+
+    fields: dict of (nc,) arrays thB, thT, piB, piT (theta* and the projected Exner pressure at
+    the bottom / top faces), pic, rhoc; consts: dict dt, tau_u, tau_rho, tau_theta, cp, kappa.
+    Returns the same dict as ``local_matrices`` plus ``cor`` (the Coriolis block, included in A)
+    and ``vol``.
+    """
+    dt, tu, tr, tt = consts["dt"], consts["tau_u"], consts["tau_rho"], consts["tau_theta"]
+    cp, kappa = consts["cp"], consts["kappa"]
+    thB, thT, piB, piT = fields["thB"], fields["thT"], fields["piB"], fields["piT"]
+    pic, rhoc = fields["pic"], fields["rhoc"]
+    nc = thB.shape[0]
+    Om = np.zeros(3) if omega_vec is None else np.asarray(omega_vec, np.float64)
+
+    def geometry(xi, eta, zeta):
+        x, J = cmap(xi, eta, zeta)
+        det = np.linalg.det(J)
+        Jinv = np.linalg.inv(J)
+        vhat = rt0_values(xi, eta, zeta, np.ones(1), np.ones(1), np.ones(1))[0]  # (nq, 6, 3)
+        v = np.einsum("cqde,qae->cqad", J, vhat) / det[:, :, None, None]
+        if radial:
+            zh = x / np.linalg.norm(x, axis=-1, keepdims=True)
+        else:
+            zh = np.broadcast_to(np.array([0.0, 0.0, 1.0]), x.shape)
+        gzeta = Jinv[:, :, 2, :]  # grad of the vertical reference coordinate
+        return J, det, v, zh, gzeta
+
+    qx, qy, qz, qw = volume_rule()
+    J, det, v, zh, gz = geometry(qx, qy, qz)
+    wq = qw[None, :] * det  # (nc, nq)
+    div = 1.0 / det  # (nc, nq), the same for all six functions
+    th_q = thB[:, None] * (1.0 - qz)[None, :] + thT[:, None] * qz[None, :]
+    grad_th = (thT - thB)[:, None, None] * gz  # (nc, nq, 3)
+    dzth = np.einsum("cqd,cqd->cq", zh, grad_th)
+    dzpi = np.einsum("cqd,cqd->cq", zh, (piT - piB)[:, None, None] * gz)
+    vz = np.einsum("cqad,cqd->cqa", v, zh)
+    m2 = np.einsum("cq,cqad,cqbd->cab", wq, v, v)
+    cv = 2.0 * np.cross(np.broadcast_to(Om, v.shape), v)  # 2 Omega x v_b
+    cor = tu * dt * np.einsum("cq,cqad,cqbd->cab", wq, v, cv)
+    q22 = tu * tt * dt * dt * cp * np.einsum("cq,cqa,cqb->cab", wq * dzpi * dzth, vz, vz)
+    divthw = th_q[:, :, None] * div[:, :, None] + np.einsum("cqad,cqd->cqa", v, grad_th)
+    gb = -tu * dt * cp * np.einsum("cq,cqa->ca", wq, divthw)
+    dD = tr * dt * rhoc[:, None] * np.einsum("cq,cq->c", wq, div)[:, None] * np.ones((1, 6))
+    m3 = wq.sum(axis=1)
+    # one-point rule at the reference centre
+    h = np.array([0.5])
+    _, detc, vc, zc, gzc = geometry(h, h, h)
+    detc, vc, zc, gzc = detc[:, 0], vc[:, 0], zc[:, 0], gzc[:, 0]
+    thc = 0.5 * (thB + thT)
+    dzth_c = (thT - thB) * np.einsum("cd,cd->c", zc, gzc)
+    q32 = tt * dt * (dzth_c / thc)[:, None] * np.einsum("cad,cd->ca", vc, zc) * detc[:, None]
+    m3rho = detc / rhoc
+    m3pi = (1.0 - kappa) / kappa * detc / pic
+    Kmat = np.zeros((nc, 6, 6))
+    Cmat = np.zeros((nc, 6, 6))
+    thF = np.zeros((nc, 6))
+    tang = {0: (1, 2), 1: (1, 2), 2: (2, 0), 3: (2, 0), 4: (0, 1), 5: (0, 1)}
+    for f in range(6):
+        fx, fy, fz, fw = face_rule(f)
+        Jf, _, vf, _, _ = geometry(fx, fy, fz)
+        t1, t2 = tang[f]
+        nds = np.cross(Jf[:, :, :, t1], Jf[:, :, :, t2]) * (1.0 if f % 2 else -1.0)  # outward
+        flux = np.einsum("cqad,cqd->cqa", vf, nds) * fw[None, :, None]
+        th_f = thB[:, None] * (1.0 - fz)[None, :] + thT[:, None] * fz[None, :]
+        Kmat[:, :, f] = tu * dt * cp * np.einsum("cq,cqa->ca", th_f, flux)
+        Cmat[:, :, f] = flux.sum(axis=1)
+        thF[:, f] = Kmat[:, f, f] / (tu * dt * cp)
+    drow = q32 + (m3rho / m3)[:, None] * dD
+    A = np.zeros((nc, 7, 7))
+    A[:, :6, :6] = m2 + cor - q22
+    A[:, :6, 6] = gb
+    A[:, 6, :6] = drow
+    A[:, 6, 6] = m3pi
+    return dict(A=A, K=Kmat, C=Cmat, m2=m2, q22=q22, cor=cor, gb=gb, d=drow, q32=q32, m3=m3,
+                m3rho=m3rho, m3pi=m3pi, thF=thF, vol=m3)
+
+
+def shell_cells(mesh, prob, cells=None):
+    """Corner unit vectors (nc, 4, 3), bottom and top radii (nc,) of cells of a cubed sphere."""
+    sel = slice(None) if cells is None else np.asarray(cells)
+    k = mesh.cell_layer[sel]
+    col = mesh.cell_col[sel]
+    U = np.stack([prob.corners[q][:, col].T for q in range(4)], axis=1)
+    return U, prob.radius[k], prob.radius[k + 1]
+
+
+def shell_fields(mesh, prob, cells=None):
+    sel = slice(None) if cells is None else np.asarray(cells)
+    k = mesh.cell_layer[sel]
+    col = mesh.cell_col[sel]
+    return dict(thB=prob.theta_w[k, col], thT=prob.theta_w[k + 1, col], piB=prob.exner_hat_w[k, col],
+                piT=prob.exner_hat_w[k + 1, col], pic=prob.exner_c[k, col], rhoc=prob.rho_c[k, col])
+
+
+def shell_local_matrices(mesh, prob, cells=None, chunk=4096):
+    """Cell matrices of every cell (or of ``cells``) of an extruded cubed sphere (``shell_map``),
+    rotating about the polar (+z) axis at prob.omega_rot."""
+    idx = np.arange(mesh.ncell) if cells is None else np.asarray(cells)
+    consts = dict(dt=prob.dt, tau_u=prob.tau_u, tau_rho=prob.tau_rho, tau_theta=prob.tau_theta, cp=prob.cp,
+                  kappa=prob.kappa)
+    out = None
+    for s0 in range(0, idx.shape[0], chunk):
+        sel = idx[s0 : s0 + chunk]
+        U, r0, r1 = shell_cells(mesh, prob, sel)
+        part = local_matrices_mapped(shell_map(U, r0, r1), shell_fields(mesh, prob, sel), consts,
+                                     omega_vec=np.array([0.0, 0.0, prob.omega_rot]))
+        if out is None:
+            out = {k: np.zeros((idx.shape[0],) + v.shape[1:]) for k, v in part.items()}
+        for k, v in part.items():
+            out[k][s0 : s0 + sel.shape[0]] = v
+    return out

@@ -89,3 +89,57 @@ class BoxMesh:
 
     def is_zface(self, f):
         return f < self.n_zface
+
+
+class TableMesh:
+    """The dof maps of an extruded mesh given by its horizontal connectivity tables (the cubed
+    sphere; the periodic box gives the same maps as ``BoxMesh``).
+
+    Same numbering as the box: cells ``k * ncol + col``; horizontal facets ``k * ncol + col``;
+    vertical facets ``(L + 1) * ncol + k * nedge + e``; local faces W, E, S, N, B, T in the
+    column's own frame.  The global normal of edge e leaves ``edge_col[0][e]``; +z on B / T.
+    ``parents`` (optional): for each multigrid level below the finest, the coarse column of every
+    column of the level above it.
+    """
+
+    def __init__(self, nlev, col_edge, edge_col, edge_lf, parents=()):
+        self.nlev = int(nlev)
+        self.col_edge = np.asarray(col_edge, np.int64)
+        self.edge_col = np.asarray(edge_col, np.int64)
+        self.edge_lf = np.asarray(edge_lf, np.int64)
+        self.ncol = self.col_edge.shape[1]
+        self.nedge = self.edge_col.shape[1]
+        self.ncell = self.ncol * self.nlev
+        self.n_zface = self.ncol * (self.nlev + 1)
+        self.n_hface = self.nedge * self.nlev
+        self.ntrace = self.n_zface + self.n_hface
+        self.parents = [np.asarray(p, np.int64) for p in parents]
+        L, ncol = self.nlev, self.ncol
+        c = np.arange(self.ncell)
+        k, col = c // ncol, c % ncol
+        faces = np.empty((self.ncell, 6), np.int64)
+        sign = np.empty((self.ncell, 6))
+        for f in range(4):
+            e = self.col_edge[f, col]
+            faces[:, f] = self.n_zface + k * self.nedge + e
+            leaves = (self.edge_col[0, e] == col) & (self.edge_lf[0, e] == f)
+            sign[:, f] = np.where(leaves, 1.0, -1.0)
+        faces[:, 4] = k * ncol + col
+        faces[:, 5] = (k + 1) * ncol + col
+        sign[:, 4], sign[:, 5] = -1.0, 1.0
+        self.cell_faces = faces
+        self.cell_sign = sign
+        self.cell_layer = k
+        self.cell_col = col
+        bnd = np.zeros(self.ntrace, bool)
+        bnd[:ncol] = True
+        bnd[L * ncol : (L + 1) * ncol] = True
+        self.boundary = bnd
+
+    face_cells = BoxMesh.face_cells
+
+    def column_of_zface(self, f):
+        return f % self.ncol
+
+    def is_zface(self, f):
+        return f < self.n_zface

@@ -7,7 +7,10 @@ ground facets carry no velocity dof (u . n = 0 there).  The matrix is
 assembled from the cell matrices of ``local`` by the sign map between
 outward-flux broken dofs and globally oriented dofs.  The velocity-pressure
 block includes the facet term <[[theta* w]] {{Pi}}> of the form g, which
-vanishes when theta* is single valued on every facet.
+vanishes when theta* is single valued on every facet.  On the cubed sphere the
+global orientation of a vertical facet is that of its edge (the normal leaves
+the first column of the edge); the velocity block then carries the Coriolis
+term, which the lumped mass leaves out.
 
 The right-hand side of the continuous problem is obtained from the broken one
 by R_u(F) = sum over the two cells K of F of s_{K,F} r^b_{K,F}, the
@@ -37,8 +40,9 @@ class MixedSystem:
         self.nu = int(interior.sum())
         self.np_ = mesh.ncell
         A = loc["A"]
+        cor = loc.get("cor")
         cf, cs = mesh.cell_faces, mesh.cell_sign
-        rows_uu, cols_uu, vals_uu = [], [], []
+        rows_uu, cols_uu, vals_uu, vals_lump = [], [], [], []
         rows_up, cols_up, vals_up = [], [], []
         rows_pu, cols_pu, vals_pu = [], [], []
         cells = np.arange(mesh.ncell)
@@ -51,6 +55,8 @@ class MixedSystem:
                 rows_uu.append(ua[ok])
                 cols_uu.append(ub[ok])
                 vals_uu.append((cs[:, a] * cs[:, b] * A[:, a, b])[ok])
+                m = A[:, a, b] if cor is None else A[:, a, b] - cor[:, a, b]
+                vals_lump.append((cs[:, a] * cs[:, b] * m)[ok])
             rows_up.append(ua[ok_a])
             cols_up.append(cells[ok_a])
             vals_up.append((cs[:, a] * A[:, a, 6])[ok_a])
@@ -71,6 +77,8 @@ class MixedSystem:
             vals_up.append(0.5 * coef * jump[cf[:, a]][ok])
         cat = np.concatenate
         self.Muu = sp.csr_matrix((cat(vals_uu), (cat(rows_uu), cat(cols_uu))), shape=(self.nu, self.nu))
+        # the velocity block without the Coriolis term, whose row sums give the lumped mass
+        self.Muu_nocor = sp.csr_matrix((cat(vals_lump), (cat(rows_uu), cat(cols_uu))), shape=(self.nu, self.nu))
         self.G = sp.csr_matrix((cat(vals_up), (cat(rows_up), cat(cols_up))), shape=(self.nu, self.np_))
         self.Bp = sp.csr_matrix((cat(vals_pu), (cat(rows_pu), cat(cols_pu))), shape=(self.np_, self.nu))
         self.M3pi = sp.diags(A[:, 6, 6])

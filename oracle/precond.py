@@ -22,7 +22,8 @@ details to earlier work and prints one sign that diverges):
   (M2 - Q22) in global orientation, over the interior (non-lid) dofs.
 * H_z: the diagonal of H plus its couplings to the cells above and below,
   i.e. one tridiagonal block per column.
-* Multigrid levels: 2x2 horizontal agglomeration, no vertical coarsening;
+* Multigrid levels: 2x2 horizontal agglomeration (inside each panel on the
+  cubed sphere), no vertical coarsening;
   restriction = sum over the four children, prolongation = injection, coarse
   operators by the Galerkin product R H P; the coarsest level is solved
   approximately with a fixed number of steps: either damped block-Jacobi
@@ -54,8 +55,9 @@ from .mesh import BoxMesh
 
 
 def lumped_velocity_mass(mixed):
-    """Row sums of the assembled continuous (M2 - Q22) over interior dofs."""
-    return np.asarray(mixed.Muu.sum(axis=1)).ravel()
+    """Row sums of the assembled continuous (M2 - Q22) over interior dofs (without the Coriolis
+    term, which has no place in a lumped mass: its rows sum to the rotation of a uniform flow)."""
+    return np.asarray(mixed.Muu_nocor.sum(axis=1)).ravel()
 
 
 def pressure_operator(mixed, m2lumped=None):
@@ -85,6 +87,16 @@ def agglomeration(nx, ny, nlev):
     return sp.csr_matrix((np.ones(nf), (fine, coarse)), shape=(nf, nc))
 
 
+def agglomeration_from_parent(parent, ncol_coarse, nlev):
+    """Injection P (fine cells x coarse cells) given the coarse column of every fine column."""
+    parent = np.asarray(parent, np.int64)
+    ncf = parent.shape[0]
+    fine = np.arange(ncf * nlev)
+    k, col = fine // ncf, fine % ncf
+    coarse = k * ncol_coarse + parent[col]
+    return sp.csr_matrix((np.ones(fine.shape[0]), (fine, coarse)), shape=(fine.shape[0], ncol_coarse * nlev))
+
+
 COARSE_CHEB = (0.02, 2.0)  # default interval of the Chebyshev coarsest solve
 
 
@@ -93,18 +105,26 @@ class PressureMultigrid:
     sweeps; coarse_sweeps: the number of steps either way."""
 
     def __init__(self, H, nx, ny, nlev, levels=4, omega=0.9, pre=1, post=2, coarse_sweeps=6,
-                 coarse_cheb=COARSE_CHEB):
+                 coarse_cheb=COARSE_CHEB, parents=None):
+        """nx, ny: the periodic box's columns; or ``parents`` (then nx, ny are unused): the coarse
+        column of every column, one array per coarsening."""
         self.omega, self.pre, self.post, self.coarse_sweeps = omega, pre, post, coarse_sweeps
         self.coarse_cheb = coarse_cheb
         self.H = [sp.csr_matrix(H)]
         self.P = []
-        self.ncol = [nx * ny]
-        for _ in range(1, levels):
-            P = agglomeration(nx, ny, nlev)
+        self.ncol = [H.shape[0] // nlev]
+        for lvl in range(1, levels):
+            if parents is not None:
+                par = parents[lvl - 1]
+                nc = int(par.max()) + 1
+                P = agglomeration_from_parent(par, nc, nlev)
+            else:
+                P = agglomeration(nx, ny, nlev)
+                nx, ny = nx // 2, ny // 2
+                nc = nx * ny
             self.P.append(P)
             self.H.append(sp.csr_matrix(P.T @ self.H[-1] @ P))
-            nx, ny = nx // 2, ny // 2
-            self.ncol.append(nx * ny)
+            self.ncol.append(nc)
         self.Hz = [column_part(h, n) for h, n in zip(self.H, self.ncol)]
         self.Hz_lu = [spla.splu(h.tocsc()) for h in self.Hz]
 
@@ -179,8 +199,10 @@ class TwoLevel:
         self.D = line_smoother_matrix(mesh, self.S)
         self.D_lu = spla.splu(self.D.tocsc())
         self.P = trace_prolongation(mesh)
-        self.mg = PressureMultigrid(H, mesh.nx, mesh.ny, mesh.nlev, mg_levels, omega_p, mg_pre,
-                                    mg_post, mg_coarse_sweeps, mg_coarse_cheb)
+        parents = getattr(mesh, "parents", None)
+        self.mg = PressureMultigrid(H, getattr(mesh, "nx", 0), getattr(mesh, "ny", 0), mesh.nlev, mg_levels,
+                                    omega_p, mg_pre, mg_post, mg_coarse_sweeps, mg_coarse_cheb,
+                                    parents=parents if parents else None)
         ones_c = np.ones(mesh.ncell)
         self.gamma = (H @ ones_c) / (self.P.T @ (self.S @ (self.P @ ones_c)))
 

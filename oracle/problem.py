@@ -1,4 +1,5 @@
-"""Glue: build every oracle object for one synthetic box problem (test infrastructure)."""
+"""Glue: build every oracle object for one synthetic problem, periodic box or extruded cubed
+sphere (test infrastructure)."""
 
 from __future__ import annotations
 
@@ -6,8 +7,8 @@ import numpy as np
 
 from .hybrid import HybridSystem
 from .krylov import fgmres
-from .local import local_matrices
-from .mesh import BoxMesh
+from .local import local_matrices, shell_local_matrices
+from .mesh import BoxMesh, TableMesh
 from .mixed import MixedSystem
 from .precond import COARSE_CHEB, TwoLevel, pressure_operator
 
@@ -23,8 +24,13 @@ class OracleProblem:
                  n_post=2, mg_levels=None, omega_p=0.9, mg_pre=1, mg_post=2, mg_coarse_sweeps=6,
                  mg_coarse_cheb=COARSE_CHEB):
         self.prob = prob
-        self.mesh = BoxMesh(prob.nx, prob.ny, prob.nlev, prob.dx, prob.dy, prob.z)
-        self.loc = local_matrices(self.mesh, prob)
+        if getattr(prob, "geom", "box") == "shell":
+            self.mesh = TableMesh(prob.nlev, prob.col_edge, prob.edge_col, prob.edge_lf,
+                                  parents=[L.parent for L in prob.levels[1:]])
+            self.loc = shell_local_matrices(self.mesh, prob)
+        else:
+            self.mesh = BoxMesh(prob.nx, prob.ny, prob.nlev, prob.dx, prob.dy, prob.z)
+            self.loc = local_matrices(self.mesh, prob)
         self.hyb = HybridSystem(self.mesh, self.loc)
         self.mixed = MixedSystem(self.mesh, self.loc, prob) if (with_mixed or with_precond) else None
         self.pc = None

@@ -8,3 +8,4 @@ what it produces; neither imports the other.
 """
 
 from .box import BoxProblem, make_box, make_rhs, make_rhs_p1, config_box  # noqa: F401
+from .sphere import SphereProblem, make_sphere, make_rhs_sphere, config_sphere  # noqa: F401,E402
