@@ -223,6 +223,59 @@ def learned_leg(args, prob, s, rhs, sec_plain, dx, dz, dt):
                               batch=8, final_energy_loss=float(np.mean(hist[-50:])), seconds=train_s))
 
 
+def sphere_leg(args):
+    """The extruded cubed sphere (C192 x 30 quadratic layers to 30 km, dt = 1800 s, rotating, the
+    Gaussian pressure bump): time-to-1e-8 of the plain FP64 solve and of the mixed form, their
+    iterations, and the error of the mixed solution against the FP64 one."""
+    import numpy as np
+    import torch
+
+    from paper_2210_11797_amd import PREC_FP64, PREC_MIXED, Params, solver_for
+    from synth import make_rhs_sphere, make_sphere
+
+    prob = make_sphere(args.sphere_n, args.sphere_nlev, dt=args.sphere_dt, mg_levels=4)
+    log(f"sphere: C{args.sphere_n} x {args.sphere_nlev}, {prob.ncell} cells, {prob.ntrace} trace unknowns")
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()  # noqa: E731
+    rhs = [tuple(d(a) for a in make_rhs_sphere(prob, sd)) for sd in range(3)]
+    out, lam0 = {}, {}
+    for name, prec in (("fp64", PREC_FP64), ("mixed", PREC_MIXED)):
+        params = Params(dt=prob.dt, tau_u=prob.tau_u, tau_rho=prob.tau_rho, tau_theta=prob.tau_theta, cp=prob.cp,
+                        rd=prob.rd, precision=prec, omega_rot=prob.omega_rot, mg_coarse_sweeps=args.coarse_sweeps,
+                        mg_coarse_cheb=0 if args.coarse_jacobi else 1)
+        s = solver_for(prob, params)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.assemble_local(d(prob.theta_w), d(prob.exner_hat_w), d(prob.exner_c), d(prob.rho_c))
+        s.condense()
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - t0
+        sec, infos, _ = run_steps(s, rhs, 3, 1, args.rtol, profile=False)
+        rec = dict(sec_per_solve=sec, iters=[i["iters"] for i in infos], rel_res=max(i["rel_res"] for i in infos),
+                   setup_s=setup)
+        if prec == PREC_FP64:
+            _, _, fams = run_steps(s, rhs, 3, 0, args.rtol, profile=True)
+            nbytes = algorithmic_bytes(s.ntrace, s.ncell, s.ncol, prob.nlev, rec["iters"], fams, 3)
+            rec["hbm_gbs_algorithmic"] = nbytes / sec / 1e9
+            rec["bytes_per_solve"] = nbytes
+        b = torch.empty(s.ntrace, dtype=torch.float64, device="cuda")
+        lam = torch.zeros_like(b)
+        s.condense(rhs[0][0], rhs[0][1], b)
+        s.solve(b, lam, rtol=args.rtol, maxit=500)
+        lam0[name] = lam
+        out[name] = rec
+        log(f"sphere {name}: {sec * 1e3:.1f} ms per solve, iters {rec['iters']}, setup {setup * 1e3:.0f} ms")
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    err = float(torch.linalg.norm(lam0["mixed"] - lam0["fp64"]) / torch.linalg.norm(lam0["fp64"]))
+    out["mixed"]["speedup_vs_fp64"] = out["fp64"]["sec_per_solve"] / out["mixed"]["sec_per_solve"]
+    out["mixed"]["lambda_error_vs_fp64"] = err
+    return dict(workload=f"cubed sphere C{args.sphere_n} x {args.sphere_nlev} quadratic layers to 30 km, radius "
+                         f"6371 km, Omega 7.292e-5/s, dt={args.sphere_dt:.0f}s, RT0/Q0/trace, seeded N(0,1) RHS plus "
+                         f"the Gaussian pressure bump, FGMRES(30)+two-level, rtol {args.rtol}",
+                ncell=prob.ncell, ntrace=prob.ntrace, forms=out)
+
+
 def p1_leg(args):
     """Order 1 (RT1 / DG1 / Q1 trace, 44 x 44 cell blocks) on the 128 x 128 x 32 box (dx = 10 km,
     dz = 500 m): the condensation in FP64 and on MFMA (FP32, BF16 split), and time-to-1e-8 of FGMRES
@@ -319,6 +372,10 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-p1", action="store_true")
+    ap.add_argument("--no-sphere", action="store_true")
+    ap.add_argument("--sphere-n", type=int, default=192)
+    ap.add_argument("--sphere-nlev", type=int, default=30)
+    ap.add_argument("--sphere-dt", type=float, default=1800.0)
     ap.add_argument("--p1-nx", type=int, default=128)
     ap.add_argument("--p1-nlev", type=int, default=32)
     ap.add_argument("--train-nx", type=int, default=64, help="box on which the learned stage is trained")
@@ -389,6 +446,10 @@ def main():
     if not args.no_learned:
         learned_out = learned_leg(args, prob, s, rhs, sec, dx, dz, dt)
 
+    sphere_out = None
+    if not args.no_sphere:
+        sphere_out = sphere_leg(args)
+
     p1_out = None
     if not args.no_p1:
         s.close()
@@ -439,6 +500,7 @@ def main():
         "kernel_ms_note": "from a second, untimed run of the same solves with events around every family",
         "mixed": mixed,
         "learned": learned_out,
+        "sphere": sphere_out,
         "p1": p1_out,
         "cpu_baseline": cpu,
     }

@@ -66,6 +66,9 @@ extern "C" {
 #define HYB_PREC_MFMA_FP32 2   /* order 1 only: S_K condensed on FP32 MFMA (FP32 accumulation) */
 #define HYB_PREC_MFMA_BF16X 3  /* order 1 only: S_K condensed on BF16 MFMA, operands split hi + lo */
 
+#define HYB_GEOM_BOX 0         /* periodic box of axis-aligned cells dx x dy x dz[k] */
+#define HYB_GEOM_SHELL 1       /* extruded cubed sphere: curved cells between spheres (below) */
+
 typedef struct hyb_ctx hyb_ctx;
 
 /* Horizontal mesh of one multigrid level (host arrays). */
@@ -77,10 +80,16 @@ typedef struct {
   const int32_t *parent;     /* [ncol of the next finer level]; NULL on level 0 */
 } hyb_level;
 
-/* Extruded mesh: a periodic box of nx*ny columns with cell sizes dx, dy and
-   layer thicknesses dz[nlev] (host), plus the 2x2-agglomerated multigrid
-   levels (levels[0] = the mesh itself; each coarser level keeps the local
-   face orientation of its children; no vertical coarsening). */
+/* Extruded mesh plus its 2x2-agglomerated multigrid levels (levels[0] = the mesh itself; each
+   coarser level keeps the local face orientation of its children; no vertical coarsening).
+   geom = HYB_GEOM_BOX: a periodic box, cells dx x dy x dz[k] (dz host [nlev]).
+   geom = HYB_GEOM_SHELL (order 0 only): an extruded cubed sphere.  corners (host [4][3][ncol]) are
+   the unit vectors of the column corners, corner q = I + 2 J at the column's local coordinates
+   (I, J) in {0, 1}^2 (local faces W at I = 0, E at I = 1, S at J = 0, N at J = 1, the frame
+   right-handed seen from outside); radius (host [nlev + 1]) the radii of the layer interfaces.
+   A cell is the image of the unit cube under x = r(zeta) p / |p|, r(zeta) = radius[k] +
+   zeta (radius[k+1] - radius[k]), p the bilinear interpolation of the corners: the vertical is
+   radial, the side faces lie on great-circle planes.  dx, dy and dz are ignored. */
 typedef struct {
   int32_t nlev;
   int32_t nlevels;           /* multigrid levels, >= 1 */
@@ -88,6 +97,9 @@ typedef struct {
   double dx, dy;
   const double *dz;          /* host [nlev] */
   int32_t order;             /* 0: RT0 / Q0 / one trace dof per facet; 1: RT1 / DG1 / Q1 trace (below) */
+  int32_t geom;              /* HYB_GEOM_BOX or HYB_GEOM_SHELL */
+  const double *corners;     /* HYB_GEOM_SHELL: host [4][3][ncol] */
+  const double *radius;      /* HYB_GEOM_SHELL: host [nlev + 1], increasing */
 } hyb_mesh;
 
 typedef struct {
@@ -113,6 +125,10 @@ typedef struct {
      row sums, as the pressure operators here do) */
   int32_t mg_coarse_cheb;
   double cheb_lo, cheb_hi;
+  /* rotation rate about the +z axis (1/s): the Coriolis term tau_u dt <w . 2 Omega x u> of the
+     velocity mass form (Sec. 2.2), on HYB_GEOM_SHELL meshes (0 on the box); read at
+     hyb_assemble_local.  The lumped velocity mass of the preconditioner leaves it out. */
+  double omega_rot;
 } hyb_params;
 
 typedef struct {

@@ -7,6 +7,8 @@ raises if it has not been built.
 
 from ._native import (  # noqa: F401
     ABI_FUNCTIONS,
+    GEOM_BOX,
+    GEOM_SHELL,
     HYB_BREAKDOWN,
     HYB_NOT_CONVERGED,
     HYB_OK,
@@ -18,5 +20,6 @@ from ._native import (  # noqa: F401
     HybSolver,
     Params,
     levels_of,
+    solver_for,
     load,
 )

@@ -23,6 +23,8 @@ PREC_FP64 = 0
 PREC_MIXED = 1
 PREC_MFMA_FP32 = 2
 PREC_MFMA_BF16X = 3
+GEOM_BOX = 0
+GEOM_SHELL = 1
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _f64p = ctypes.POINTER(ctypes.c_double)
@@ -35,7 +37,8 @@ class _Level(ctypes.Structure):
 
 class _Mesh(ctypes.Structure):
     _fields_ = [("nlev", ctypes.c_int32), ("nlevels", ctypes.c_int32), ("levels", ctypes.POINTER(_Level)),
-                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", _f64p), ("order", ctypes.c_int32)]
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", _f64p), ("order", ctypes.c_int32),
+                ("geom", ctypes.c_int32), ("corners", _f64p), ("radius", _f64p)]
 
 
 class _Params(ctypes.Structure):
@@ -45,7 +48,8 @@ class _Params(ctypes.Structure):
                 ("omega_p", ctypes.c_double), ("mg_pre", ctypes.c_int32), ("mg_post", ctypes.c_int32),
                 ("mg_coarse_sweeps", ctypes.c_int32), ("restart", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("learned", ctypes.c_int32), ("learned_tau", ctypes.c_double),
-                ("mg_coarse_cheb", ctypes.c_int32), ("cheb_lo", ctypes.c_double), ("cheb_hi", ctypes.c_double)]
+                ("mg_coarse_cheb", ctypes.c_int32), ("cheb_lo", ctypes.c_double), ("cheb_hi", ctypes.c_double),
+                ("omega_rot", ctypes.c_double)]
 
 
 class _Info(ctypes.Structure):
@@ -82,6 +86,7 @@ class Params:
     mg_coarse_cheb: int = 1
     cheb_lo: float = 0.02
     cheb_hi: float = 2.0
+    omega_rot: float = 0.0
 
     def to_c(self) -> _Params:
         return _Params(**{f.name: getattr(self, f.name) for f in fields(self)})
@@ -169,7 +174,8 @@ class HybSolver:
     edge_lf [2, 2ncol] and, for coarse levels, parent [ncol of the finer level].
     """
 
-    def __init__(self, nlev, levels, dx, dy, dz, params: Params | None = None, stream=None, order: int = 0):
+    def __init__(self, nlev, levels, dx, dy, dz, params: Params | None = None, stream=None, order: int = 0,
+                 corners=None, radius=None):
         import torch
 
         self.lib = load()
@@ -194,7 +200,15 @@ class HybSolver:
             lv[i] = _Level(int(L["ncol"]), arrs["col_edge"], arrs["edge_col"], arrs["edge_lf"], par)
         dzh = np.ascontiguousarray(dz, dtype=np.float64)
         self._keep += [lv, dzh]
-        mesh = _Mesh(self.nlev, len(levels), lv, float(dx), float(dy), dzh.ctypes.data_as(_f64p), self.order)
+        geom, cptr, rptr = GEOM_BOX, None, None
+        if corners is not None:
+            geom = GEOM_SHELL
+            ch = np.ascontiguousarray(corners, dtype=np.float64)
+            rh = np.ascontiguousarray(radius, dtype=np.float64)
+            self._keep += [ch, rh]
+            cptr, rptr = ch.ctypes.data_as(_f64p), rh.ctypes.data_as(_f64p)
+        mesh = _Mesh(self.nlev, len(levels), lv, float(dx), float(dy), dzh.ctypes.data_as(_f64p), self.order,
+                     geom, cptr, rptr)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -350,8 +364,17 @@ class HybSolver:
         return n.value, ms.value
 
 
+def solver_for(prob, params: Params | None = None, order: int = 0, stream=None) -> "HybSolver":
+    """A HybSolver for a synthetic problem: the periodic box, or the extruded cubed sphere (its
+    corner unit vectors and interface radii as the shell geometry)."""
+    if getattr(prob, "geom", "box") == "shell":
+        return HybSolver(prob.nlev, levels_of(prob), 0.0, 0.0, prob.dz, params, stream=stream, order=order,
+                         corners=prob.corners, radius=prob.radius)
+    return HybSolver(prob.nlev, levels_of(prob), prob.dx, prob.dy, prob.dz, params, stream=stream, order=order)
+
+
 def levels_of(prob):
-    """Mesh hierarchy of a synthetic box problem as the dicts HybSolver takes."""
+    """Mesh hierarchy of a synthetic problem as the dicts HybSolver takes."""
     out = []
     for i, L in enumerate(prob.levels):
         out.append(dict(ncol=L.ncol, col_edge=L.col_edge, edge_col=L.edge_col, edge_lf=L.edge_lf,

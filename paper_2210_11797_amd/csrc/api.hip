@@ -79,6 +79,9 @@ int check_params(hyb_ctx *c, const hyb_params *p) {
   if (p->mg_coarse_cheb != 0 && p->mg_coarse_cheb != 1) return fail(c, HYB_EINVAL, "mg_coarse_cheb must be 0 or 1");
   if (p->mg_coarse_cheb && !(p->cheb_lo > 0.0 && p->cheb_hi > p->cheb_lo && std::isfinite(p->cheb_hi)))
     return fail(c, HYB_EINVAL, "the Chebyshev interval needs 0 < cheb_lo < cheb_hi");
+  if (!std::isfinite(p->omega_rot)) return fail(c, HYB_EINVAL, "omega_rot must be finite");
+  if (p->omega_rot != 0.0 && c->geom != HYB_GEOM_SHELL)
+    return fail(c, HYB_EINVAL, "rotation (omega_rot) is defined on HYB_GEOM_SHELL meshes only");
   return HYB_OK;
 }
 
@@ -169,7 +172,7 @@ void free_all(hyb_ctx *c) {
     dfree(L.est), dfree(L.parent), dfree(L.children), dfree(L.H), dfree(L.Hf);
     dfree(L.zf), dfree(L.zff), dfree(L.b), dfree(L.x), dfree(L.y), dfree(L.r), dfree(L.w);
   }
-  dfree(c->dz_d), dfree(c->A), dfree(c->LU), dfree(c->kv), dfree(c->Scell), dfree(c->bcell);
+  dfree(c->dz_d), dfree(c->corners_d), dfree(c->radius_d), dfree(c->A), dfree(c->LU), dfree(c->kv), dfree(c->Scell), dfree(c->bcell);
   dfree(c->S), dfree(c->Sf), dfree(c->m2l), dfree(c->gamma), dfree(c->gammaf), dfree(c->zfac), dfree(c->zfacf);
   dfree(c->tIn), dfree(c->tA), dfree(c->tB), dfree(c->tR), dfree(c->t64);
   dfree(c->V), dfree(c->Z), dfree(c->partial), dfree(c->hdev);
@@ -235,13 +238,25 @@ int hyb_create(const hyb_mesh *mesh, const hyb_params *params, void *stream, hyb
   *out = nullptr;
   hyb_ctx *c = new (std::nothrow) hyb_ctx();
   if (!c) return HYB_ENOMEM;
+  if (!mesh || mesh->nlev < 1 || mesh->nlevels < 1 || !mesh->levels) {
+    delete c;
+    return HYB_EINVAL;
+  }
+  c->geom = mesh->geom;
   int rc = check_params(c, params);
   if (rc) {
     delete c;
     return rc;
   }
-  if (!mesh || mesh->nlev < 1 || mesh->nlevels < 1 || !mesh->levels || !mesh->dz || !(mesh->dx > 0) ||
-      !(mesh->dy > 0)) {
+  bool geom_ok = false;
+  if (mesh->geom == HYB_GEOM_BOX) {
+    geom_ok = mesh->dz && mesh->dx > 0 && mesh->dy > 0;
+  } else if (mesh->geom == HYB_GEOM_SHELL) {
+    geom_ok = mesh->corners && mesh->radius && mesh->order == 0 && mesh->radius[0] > 0;
+    for (int k = 0; geom_ok && k < mesh->nlev; ++k) geom_ok = mesh->radius[k + 1] > mesh->radius[k];
+    for (size_t i = 0; geom_ok && i < (size_t)12 * mesh->levels[0].ncol; ++i) geom_ok = std::isfinite(mesh->corners[i]);
+  }
+  if (!geom_ok) {
     delete c;
     return HYB_EINVAL;
   }
@@ -270,7 +285,12 @@ int hyb_create(const hyb_mesh *mesh, const hyb_params *params, void *stream, hyb
   }
   c->dx = mesh->dx;
   c->dy = mesh->dy;
-  c->dz.assign(mesh->dz, mesh->dz + c->nlev);
+  if (c->geom == HYB_GEOM_SHELL) {
+    c->dz.resize(c->nlev);
+    for (int k = 0; k < c->nlev; ++k) c->dz[k] = mesh->radius[k + 1] - mesh->radius[k];
+  } else {
+    c->dz.assign(mesh->dz, mesh->dz + c->nlev);
+  }
   for (double d : c->dz)
     if (!(d > 0)) {
       delete c;
@@ -296,6 +316,14 @@ int hyb_create(const hyb_mesh *mesh, const hyb_params *params, void *stream, hyb
     rc = dalloc(c, &c->dz_d, c->nlev);
     if (rc == HYB_OK && hipMemcpy(c->dz_d, c->dz.data(), c->nlev * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
       rc = HYB_EHIP;
+  }
+  if (rc == HYB_OK && c->geom == HYB_GEOM_SHELL) {
+    const size_t nco = (size_t)12 * c->ncol;
+    rc = dalloc(c, &c->corners_d, nco);
+    if (rc == HYB_OK) rc = dalloc(c, &c->radius_d, (size_t)c->nlev + 1);
+    if (rc == HYB_OK && (hipMemcpy(c->corners_d, mesh->corners, nco * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+                         hipMemcpy(c->radius_d, mesh->radius, (c->nlev + 1) * sizeof(double), hipMemcpyHostToDevice) != hipSuccess))
+      rc = fail(c, HYB_EHIP, "upload of the shell geometry");
   }
   if (rc != HYB_OK) {
     fprintf(stderr, "hyb_create: %s\n", c->err.c_str());
@@ -373,8 +401,20 @@ int hyb_assemble_local(hyb_ctx *c, const double *theta_w, const double *exner_ha
     c->condensed = false;
     return HYB_OK;
   }
-  if ((rc = dalloc(c, &c->A, (size_t)49 * c->ncell)) || (rc = dalloc(c, &c->kv, (size_t)6 * c->ncell))) return rc;
-  CHECK_HIP(launch_assemble_box(c, theta_w, exner_hat_w, exner_c, rho_c), "assemble_local");
+  if ((rc = dalloc(c, &c->A, (size_t)49 * c->ncell)) || (rc = dalloc(c, &c->kv, (size_t)6 * c->ncell)) ||
+      (rc = dalloc(c, &c->m2l, (size_t)c->ntrace)))
+    return rc;
+  // the lumped velocity mass (Sec. 2.3) is taken from the cell matrices without the Coriolis term,
+  // which is added afterwards on the sphere
+  if (c->geom == HYB_GEOM_SHELL) {
+    CHECK_HIP(launch_assemble_shell(c, theta_w, exner_hat_w, exner_c, false), "assemble_local");
+    CHECK_HIP(launch_lumped_mass(c), "lumped_mass");
+    if (c->p.omega_rot != 0.0)
+      CHECK_HIP(launch_assemble_shell(c, theta_w, exner_hat_w, exner_c, true), "assemble_local (Coriolis)");
+  } else {
+    CHECK_HIP(launch_assemble_box(c, theta_w, exner_hat_w, exner_c, rho_c), "assemble_local");
+    CHECK_HIP(launch_lumped_mass(c), "lumped_mass");
+  }
   c->assembled = true;
   c->condensed = false;
   return HYB_OK;
@@ -411,7 +451,7 @@ int hyb_condense(hyb_ctx *c, const double *r_ub, const double *r_pi, double *b_l
   if (r_ub == nullptr) {
     size_t ntr = (size_t)c->ntrace, nc = (size_t)c->ncell;
     if ((rc = dalloc(c, &c->LU, 49 * nc)) || (rc = dalloc(c, &c->Scell, 36 * nc)) || (rc = dalloc(c, &c->S, s_entries(ntr))) ||
-        (rc = dalloc(c, &c->Sf, s_entries(ntr))) || (rc = dalloc(c, &c->m2l, ntr)) || (rc = dalloc(c, &c->gamma, nc)) ||
+        (rc = dalloc(c, &c->Sf, s_entries(ntr))) || (rc = dalloc(c, &c->gamma, nc)) ||
         (rc = dalloc(c, &c->zfac, 3 * (size_t)c->nz)) || (rc = dalloc(c, &c->zfacf, 3 * (size_t)c->nz)) ||
         (rc = dalloc(c, &c->gammaf, nc)) || (rc = dalloc(c, &c->bcell, 6 * nc)) ||
         (rc = dalloc(c, (double **)&c->tIn, ntr)) || (rc = dalloc(c, (double **)&c->tA, ntr)) ||
@@ -422,7 +462,6 @@ int hyb_condense(hyb_ctx *c, const double *r_ub, const double *r_pi, double *b_l
     CHECK_HIP(launch_factor_cells(c), "factor_cells");
     CHECK_HIP(launch_build_stencil(c), "build_stencil");
     CHECK_HIP(launch_thomas_factor(c), "thomas_factor");
-    CHECK_HIP(launch_lumped_mass(c), "lumped_mass");
     CHECK_HIP(launch_pressure_stencil(c), "pressure_stencil");
     for (int l = 1; l < c->nlevels; ++l) CHECK_HIP(launch_galerkin(c, l), "galerkin");
     for (int l = 0; l < c->nlevels; ++l) CHECK_HIP(launch_mg_factor(c, l), "mg_factor");
@@ -856,6 +895,7 @@ int hyb_nn_param_count(void) { return nn_param_count(); }
 int hyb_nn_set_weights(hyb_ctx *c, const float *w, int64_t n) {
   if (!c) return HYB_EINVAL;
   if (c->order == 1) return fail(c, HYB_ESTATE, "hyb_nn_set_weights is not available at order 1");
+  if (c->geom != HYB_GEOM_BOX) return fail(c, HYB_ESTATE, "the learned stage needs the periodic box");
   if (!w || n != nn_param_count()) return fail(c, HYB_EINVAL, "weights: wrong size");
   for (int64_t i = 0; i < n; ++i)
     if (!std::isfinite(w[i])) return fail(c, HYB_EINVAL, "weights: not finite");

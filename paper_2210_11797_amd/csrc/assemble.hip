@@ -1,4 +1,5 @@
-// Cell matrices, static condensation and preconditioner setup (lowest order, extruded box).
+// Cell matrices, static condensation and preconditioner setup (lowest order; periodic box or
+// extruded cubed sphere).
 //
 // Every kernel here is owner-computes: one thread writes each output entry and gathers what it
 // needs, so there are no atomics and results are bitwise reproducible.
@@ -57,6 +58,164 @@ __global__ void k_assemble_box(int ncell, int ncol, double dx, double dy, const 
     kv[at(f, ncell, c)] = cc * thF[f];
   }
   a[48] = (1.0 - kappa) / kappa * vol / pic[c];
+#pragma unroll
+  for (int i = 0; i < 49; ++i) A[at(i, ncell, c)] = a[i];
+}
+
+// Cell matrix A_K and the diagonal of K_K on the extruded cubed sphere (Sec. 2.2 forms, Sec. 2.4
+// g^b and k) for the cell map x = r(zeta) u(xi, eta), u = p / |p|, p the bilinear interpolation of
+// the column's corner unit vectors, r = r0 + zeta dr.  The reference RT0 functions (unit outward
+// flux) are mapped by the contravariant Piola transform v_a = phi_a J_d(a) / det J with J_x = r u_xi,
+// J_y = r u_eta, J_z = dr u, so that:
+//   - the mass form is sum_q w phi_a phi_b (J_d(a) . J_d(b)) / det over the 3x3x3 Gauss rule; J_z is
+//     orthogonal to J_x and J_y, so the vertical and horizontal functions do not couple;
+//   - the Coriolis form tau_u dt <v_a . 2 Omega x v_b> (Omega along +z) is
+//     tau_u dt sum_q w phi_a phi_b 2 Omega e_z . (J_d(b) x J_d(a)) / det (with_coriolis);
+//   - z_hat = u, so d/dz of a W_theta field is its jump over the cell divided by dr, z_hat . v_a is
+//     nonzero only for B and T, and q22 scales the vertical block by (1 + beta) as on the box;
+//   - g^b and k follow from the divergence theorem in reference coordinates: minus / plus
+//     tau_u dt cp times the mean of theta* over the face, as on the box;
+//   - the pressure row is d = tau_rho dt rho* (unit flux) times M3^rho / M3 = (det_c / rho*) / |K|
+//     (det_c: det J at the centre, the one-point rule), so rho* cancels again, plus q32 from the
+//     centre rule (-/+ tau_theta dt (thT - thB) / (thT + thB) on B / T); M3^Pi = (1-kappa)/kappa
+//     det_c / Pi*.
+__device__ __forceinline__ void shell_point(const double U[12], double xi, double eta, double u[3],
+                                            double ux[3], double uy[3]) {
+  double w0 = (1 - xi) * (1 - eta), w1 = xi * (1 - eta), w2 = (1 - xi) * eta, w3 = xi * eta;
+  double p[3], px[3], py[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double c0 = U[d], c1 = U[3 + d], c2 = U[6 + d], c3 = U[9 + d];
+    p[d] = w0 * c0 + w1 * c1 + w2 * c2 + w3 * c3;
+    px[d] = (1 - eta) * (c1 - c0) + eta * (c3 - c2);
+    py[d] = (1 - xi) * (c2 - c0) + xi * (c3 - c1);
+  }
+  double inv = 1.0 / sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) u[d] = p[d] * inv;
+  double ax = u[0] * px[0] + u[1] * px[1] + u[2] * px[2];
+  double ay = u[0] * py[0] + u[1] * py[1] + u[2] * py[2];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    ux[d] = (px[d] - ax * u[d]) * inv;
+    uy[d] = (py[d] - ay * u[d]) * inv;
+  }
+}
+
+__global__ void k_assemble_shell(int ncell, int ncol, const double *__restrict__ corners,
+                                 const double *__restrict__ radius, const double *__restrict__ thw,
+                                 const double *__restrict__ piw, const double *__restrict__ pic, double dt,
+                                 double tu, double tr, double tt, double cp, double kappa, double two_omega,
+                                 double *__restrict__ A, double *__restrict__ kv) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  int k = c / ncol, col = c - k * ncol;
+  double U[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) U[i] = corners[(size_t)i * ncol + col];
+  const double r0 = radius[k], dr = radius[k + 1] - r0;
+  double thB = thw[(size_t)k * ncol + col], thT = thw[(size_t)(k + 1) * ncol + col];
+  double piB = piw[(size_t)k * ncol + col], piT = piw[(size_t)(k + 1) * ncol + col];
+  const double gx[3] = {0.1127016653792583, 0.5, 0.8872983346207417};
+  const double gw[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+  // horizontal block over (W, E, S, N), vertical block over (B, T), Coriolis couplings
+  double mh[4][4], mv[2][2], cr[6][6], vol = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) mh[i][j] = 0.0;
+  mv[0][0] = mv[0][1] = mv[1][0] = mv[1][1] = 0.0;
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = 0; j < 6; ++j) cr[i][j] = 0.0;
+  for (int qi = 0; qi < 3; ++qi)
+    for (int qj = 0; qj < 3; ++qj) {
+      const double xi = gx[qi], eta = gx[qj];
+      double u[3], ux[3], uy[3];
+      shell_point(U, xi, eta, u, ux, uy);
+      // area element of the unit sphere and the horizontal Gram matrix, per r^2
+      const double s = u[0] * (ux[1] * uy[2] - ux[2] * uy[1]) + u[1] * (ux[2] * uy[0] - ux[0] * uy[2]) +
+                       u[2] * (ux[0] * uy[1] - ux[1] * uy[0]);
+      const double gxx = ux[0] * ux[0] + ux[1] * ux[1] + ux[2] * ux[2];
+      const double gxy = ux[0] * uy[0] + ux[1] * uy[1] + ux[2] * uy[2];
+      const double gyy = uy[0] * uy[0] + uy[1] * uy[1] + uy[2] * uy[2];
+      // e_z . (J_e x J_d) per r^2 (horizontal pair) and per r dr (with the vertical)
+      const double cyx = uy[0] * ux[1] - uy[1] * ux[0];  // e = y, d = x
+      const double czx = u[0] * ux[1] - u[1] * ux[0];    // e = z, d = x
+      const double czy = u[0] * uy[1] - u[1] * uy[0];    // e = z, d = y
+      const double phx[2] = {-(1 - xi), xi}, phy[2] = {-(1 - eta), eta};
+      for (int qk = 0; qk < 3; ++qk) {
+        const double zeta = gx[qk], w = gw[qi] * gw[qj] * gw[qk];
+        const double r = r0 + zeta * dr;
+        const double det = r * r * dr * s;
+        const double wd = w / det;
+        vol += w * det;
+        const double phz[2] = {-(1 - zeta), zeta};
+        double ph[6] = {phx[0], phx[1], phy[0], phy[1], phz[0], phz[1]};
+        // (J_d . J_e) for the horizontal pairs: r^2 g
+        const double hxx = r * r * gxx, hxy = r * r * gxy, hyy = r * r * gyy;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const double g = (a < 2) ? ((b < 2) ? hxx : hxy) : ((b < 2) ? hxy : hyy);
+            mh[a][b] += wd * ph[a] * ph[b] * g;
+          }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) mv[a][b] += wd * phz[a] * phz[b] * dr * dr;
+        if (two_omega != 0.0) {
+          // C[d][e] = 2 Omega e_z . (J_e x J_d) for d = direction of the test, e = of the trial
+          const double Cxy = two_omega * r * r * cyx, Cyx = -Cxy;
+          const double Cxz = two_omega * r * dr * czx, Czx = -Cxz;
+          const double Cyz = two_omega * r * dr * czy, Czy = -Cyz;
+          const double Cm[3][3] = {{0.0, Cxy, Cxz}, {Cyx, 0.0, Cyz}, {Czx, Czy, 0.0}};
+#pragma unroll
+          for (int a = 0; a < 6; ++a)
+#pragma unroll
+            for (int b = 0; b < 6; ++b) cr[a][b] += wd * ph[a] * ph[b] * Cm[a / 2][b / 2];
+        }
+      }
+    }
+  // centre: det_c for the one-point rules
+  double uc[3], uxc[3], uyc[3];
+  shell_point(U, 0.5, 0.5, uc, uxc, uyc);
+  const double sc = uc[0] * (uxc[1] * uyc[2] - uxc[2] * uyc[1]) + uc[1] * (uxc[2] * uyc[0] - uxc[0] * uyc[2]) +
+                    uc[2] * (uxc[0] * uyc[1] - uxc[1] * uyc[0]);
+  const double rc = r0 + 0.5 * dr;
+  const double detc = rc * rc * dr * sc;
+  double a[49];
+#pragma unroll
+  for (int i = 0; i < 49; ++i) a[i] = 0.0;
+  const double beta = -tu * tt * dt * dt * cp * (piT - piB) * (thT - thB) / (dr * dr);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) a[i * 7 + j] = mh[i][j];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) a[(4 + i) * 7 + 4 + j] = (1.0 + beta) * mv[i][j];
+  const double tud = tu * dt;
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = 0; j < 6; ++j) a[i * 7 + j] += tud * cr[i][j];
+  const double cc = tu * dt * cp;
+  const double thH = 0.5 * (thB + thT);
+  const double thF[6] = {thH, thH, thH, thH, thB, thT};
+  const double q = tt * dt * (thT - thB) / (thT + thB);
+  const double dd = tr * dt * detc / vol;
+  const double dF[6] = {dd, dd, dd, dd, dd - q, dd + q};
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    a[f * 7 + 6] = -cc * thF[f];
+    a[6 * 7 + f] = dF[f];
+    kv[at(f, ncell, c)] = cc * thF[f];
+  }
+  a[48] = (1.0 - kappa) / kappa * detc / pic[c];
 #pragma unroll
   for (int i = 0; i < 49; ++i) A[at(i, ncell, c)] = a[i];
 }
@@ -414,6 +573,16 @@ hipError_t launch_assemble_box(hyb_ctx *c, const double *thw, const double *piw,
   hipLaunchKernelGGL(k_assemble_box, dim3(nblk(c->ncell)), dim3(kBlock), 0, c->stream, c->ncell, c->ncol,
                      c->dx, c->dy, c->dz_d, thw, piw, pic, p.dt, p.tau_u, p.tau_rho, p.tau_theta, p.cp, kappa,
                      c->A, c->kv);
+  return hipGetLastError();
+}
+
+hipError_t launch_assemble_shell(hyb_ctx *c, const double *thw, const double *piw, const double *pic,
+                                 bool with_coriolis) {
+  const hyb_params &p = c->p;
+  double kappa = p.rd / p.cp;
+  hipLaunchKernelGGL(k_assemble_shell, dim3(nblk(c->ncell, 64)), dim3(64), 0, c->stream, c->ncell, c->ncol,
+                     c->corners_d, c->radius_d, thw, piw, pic, p.dt, p.tau_u, p.tau_rho, p.tau_theta, p.cp, kappa,
+                     with_coriolis ? 2.0 * p.omega_rot : 0.0, c->A, c->kv);
   return hipGetLastError();
 }
 

@@ -101,6 +101,9 @@ struct hyb_ctx {
   double dx = 0, dy = 0;
   std::vector<double> dz;
   double *dz_d = nullptr;
+  int geom = HYB_GEOM_BOX;
+  double *corners_d = nullptr;  // HYB_GEOM_SHELL: [4][3][ncol] corner unit vectors
+  double *radius_d = nullptr;   // HYB_GEOM_SHELL: [nlev + 1]
   std::vector<hyb::LevelDev> lv;
 
   // cell data
@@ -175,6 +178,8 @@ hipError_t launch_assemble_box(hyb_ctx *c, const double *theta_w, const double *
                                const double *exner_c, const double *rho_c);
 hipError_t launch_factor_cells(hyb_ctx *c);
 hipError_t launch_build_stencil(hyb_ctx *c);
+hipError_t launch_assemble_shell(hyb_ctx *c, const double *theta_w, const double *exner_hat_w,
+                                 const double *exner_c, bool with_coriolis);
 hipError_t launch_lumped_mass(hyb_ctx *c);
 hipError_t launch_pressure_stencil(hyb_ctx *c);
 hipError_t launch_galerkin(hyb_ctx *c, int coarse_level);

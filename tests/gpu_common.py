@@ -6,7 +6,7 @@ import sys
 
 import numpy as np
 
-from paper_2210_11797_amd import HybSolver, Params, levels_of
+from paper_2210_11797_amd import HybSolver, Params, levels_of, solver_for  # noqa: F401
 
 
 def say(*a):
@@ -26,13 +26,13 @@ def host(t):
 
 def params_for(prob, **kw):
     base = dict(dt=prob.dt, tau_u=prob.tau_u, tau_rho=prob.tau_rho, tau_theta=prob.tau_theta, cp=prob.cp,
-                rd=prob.rd)
+                rd=prob.rd, omega_rot=getattr(prob, "omega_rot", 0.0))
     base.update(kw)
     return Params(**base)
 
 
 def make_solver(prob, **kw):
-    s = HybSolver(prob.nlev, levels_of(prob), prob.dx, prob.dy, prob.dz, params_for(prob, **kw))
+    s = solver_for(prob, params_for(prob, **kw))
     s.assemble_local(dev(prob.theta_w), dev(prob.exner_hat_w), dev(prob.exner_c), dev(prob.rho_c))
     s.condense()
     return s

@@ -22,7 +22,8 @@ sys.path.insert(0, ROOT)
 from oracle import nn as onn  # noqa: E402
 from paper_2210_11797_amd import _native as N  # noqa: E402
 from paper_2210_11797_amd import learned  # noqa: E402
-from synth import make_box, make_rhs  # noqa: E402
+from oracle.problem import OracleProblem, cells_from_soa  # noqa: E402
+from synth import make_box, make_rhs, make_rhs_sphere, make_sphere  # noqa: E402
 
 vp = ctypes.c_void_p
 
@@ -50,7 +51,16 @@ class Ctx:
                 par = a.ctypes.data_as(N._i32p)
             lv[i] = N._Level(int(L["ncol"]), arr["col_edge"], arr["edge_col"], arr["edge_lf"], par)
         dz = np.ascontiguousarray(prob.dz, np.float64)
-        mesh = N._Mesh(prob.nlev, len(levels), lv, prob.dx, prob.dy, dz.ctypes.data_as(N._f64p), order)
+        self.shell = getattr(prob, "geom", "box") == "shell"
+        geom, cptr, rptr = N.GEOM_BOX, None, None
+        if self.shell:
+            ch = np.ascontiguousarray(prob.corners, np.float64)
+            rh = np.ascontiguousarray(prob.radius, np.float64)
+            keep += [ch, rh]
+            geom, cptr, rptr = N.GEOM_SHELL, ch.ctypes.data_as(N._f64p), rh.ctypes.data_as(N._f64p)
+        self._keep = keep
+        mesh = N._Mesh(prob.nlev, len(levels), lv, prob.dx, prob.dy, dz.ctypes.data_as(N._f64p), order, geom, cptr,
+                       rptr)
         base = dict(dt=prob.dt, tau_u=prob.tau_u, tau_rho=prob.tau_rho, tau_theta=prob.tau_theta, cp=prob.cp,
                     rd=prob.rd)
         base.update(kw)
@@ -80,7 +90,7 @@ class Ctx:
         self.call("hyb_set_params", ctypes.byref(cp))
 
     def rhs(self, seed):
-        r_ub, r_pi = make_rhs(self.prob, seed)
+        r_ub, r_pi = make_rhs_sphere(self.prob, seed) if self.shell else make_rhs(self.prob, seed)
         r_ub, r_pi = np.ascontiguousarray(r_ub, np.float64), np.ascontiguousarray(r_pi, np.float64)
         b = np.empty(self.ntrace)
         self.call("hyb_condense", P(r_ub), P(r_pi), P(b))
@@ -294,15 +304,48 @@ def p1_sequence(lib):
         cm.close()
 
 
+def sphere_sequence(lib):
+    # the extruded cubed sphere with rotation: shell assembly (twice: without and with the Coriolis
+    # term), condensation, S x, B_lambda, the preconditioner, FGMRES in both precisions, recovery;
+    # S x and the recovery against the oracle
+    prob = make_sphere(4, 5, mg_levels=2, perturb=0.05, seed=3)
+    c = Ctx(lib, prob, omega_rot=prob.omega_rot)
+    o = OracleProblem(prob, with_precond=False)
+    r_ub, r_pi, b = c.rhs(2)
+    ruc, rpc = cells_from_soa(r_ub, r_pi)
+    bref = o.hyb.rhs(ruc, rpc)
+    check(np.abs(b - bref).max() <= 1e-11 * np.abs(bref).max(), "sphere: B_lambda against the oracle")
+    x = np.random.default_rng(0).standard_normal(c.ntrace)
+    y, z = np.empty(c.ntrace), np.empty(c.ntrace)
+    c.call("hyb_trace_apply", P(x), P(y))
+    ref = o.hyb.S @ x
+    check(np.abs(y - ref).max() <= 1e-11 * np.abs(ref).max(), "sphere: S x against the oracle")
+    c.call("hyb_precondition", P(b), P(z))
+    rc, info, lam = c.solve(b, 1e-10)
+    check(rc == 0 and c.residual(b, lam) <= 1.01e-10, f"sphere: fp64 FGMRES {info.iters} iterations")
+    u_b, pi = np.empty(6 * c.ncell), np.empty(c.ncell)
+    c.call("hyb_recover", P(r_ub), P(r_pi), P(lam), P(u_b), P(pi))
+    _, pref = o.hyb.recover(lam, ruc, rpc)
+    check(np.abs(pi - pref).max() <= 1e-9 * np.abs(pref).max(), "sphere: recovery against the oracle")
+    c.set(precision=N.PREC_MIXED)
+    rc, info, lam = c.solve(b, 1e-8)
+    check(rc == 0 and c.residual(b, lam) <= 1.01e-8, f"sphere: mixed FGMRES {info.iters} iterations")
+    w = np.zeros(N.Params and lib.hyb_nn_param_count(), np.float32)
+    check(lib.hyb_nn_set_weights(c.h, P(w), w.size) < 0, "sphere: the learned stage is rejected")
+    c.close()
+
+
 def main():
     lib = N.declare(ctypes.CDLL(sys.argv[1]))
-    which = sys.argv[2:] or ["solver", "network", "p1"]
+    which = sys.argv[2:] or ["solver", "network", "p1", "sphere"]
     if "solver" in which:
         solver_sequence(lib)
     if "network" in which:
         network_sequence(lib)
     if "p1" in which:
         p1_sequence(lib)
+    if "sphere" in which:
+        sphere_sequence(lib)
     print("sequence complete", flush=True)
 
 

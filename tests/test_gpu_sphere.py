@@ -1,0 +1,253 @@
+"""Parity on the extruded cubed sphere with rotation (GPU).
+
+Small spheres (several column tiles, odd coarse levels) against the full oracle: S x, B_lambda and
+the recovery (1e-11 of the largest entry: the cell matrices come from two different quadrature
+codes), the preconditioner (100 eps cond(H)), solves to rtol 1e-13 against the sparse direct
+solution (the forward error the measured residual implies), FGMRES histories, the mixed form.
+
+The C192 x 30 mesh of the mixed-precision workload (quadratic layers to 30 km, dt = 1800 s, the
+Gaussian pressure bump): sampled rows of S x and B_lambda and sampled recovered cells against the
+oracle's own cell matrices of those cells (1e-11), and solves in FP64 and in the mixed form whose
+continuity defects, evaluated by the oracle, match the reported residuals; the error of the mixed
+solution against the FP64 one is reported.
+"""
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from gpu_common import dev, host, make_solver, rel_max, rel_norm, say
+from oracle.hybrid import cell_recover, cell_rhs, cell_trace_operator
+from oracle.local import shell_local_matrices
+from oracle.mesh import TableMesh
+from oracle.problem import OracleProblem, cells_from_soa
+from synth import make_rhs_sphere, make_sphere
+
+CASES = {
+    "c8": dict(n=8, nlev=6, mg_levels=3, perturb=0.05, dt=1800.0),
+    "c6": dict(n=6, nlev=4, mg_levels=2, dt=1200.0),
+    "c16": dict(n=16, nlev=8, mg_levels=4, dt=1800.0),
+}
+TOL_OP = 1e-11
+_cache = {}
+
+
+def setup(name):
+    if name not in _cache:
+        say(f"[sphere setup] case {name}: {CASES[name]}")
+        prob = make_sphere(**CASES[name])
+        orc = OracleProblem(prob, with_mixed=True, with_precond=True)
+        s = make_solver(prob)
+        _cache[name] = (prob, orc, s)
+    return _cache[name]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name", ["c8", "c6", "c16"])
+def test_sphere_operators(name):
+    prob, orc, s = setup(name)
+    import torch
+
+    n = orc.mesh.ntrace
+    x = np.random.default_rng(1).standard_normal(n)
+    y = torch.empty(n, dtype=torch.float64, device="cuda")
+    s.trace_apply(dev(x), y)
+    err_s = rel_max(host(y), orc.hyb.S @ x)
+    r_ub, r_pi = make_rhs_sphere(prob, 3)
+    ruc, rpc = cells_from_soa(r_ub, r_pi)
+    b = torch.empty(n, dtype=torch.float64, device="cuda")
+    s.condense(dev(r_ub), dev(r_pi), b)
+    err_b = rel_max(host(b), orc.hyb.rhs(ruc, rpc))
+    lam = np.random.default_rng(2).standard_normal(n)
+    ub = torch.empty(6 * orc.mesh.ncell, dtype=torch.float64, device="cuda")
+    pi = torch.empty(orc.mesh.ncell, dtype=torch.float64, device="cuda")
+    s.recover(dev(r_ub), dev(r_pi), dev(lam), ub, pi)
+    u_ref, p_ref = orc.hyb.recover(lam, ruc, rpc)
+    err_u = rel_max(host(ub).reshape(6, -1).T, u_ref)
+    err_p = rel_max(host(pi), p_ref)
+    say(f"[sphere operators] {name}: S x {err_s:.2e} B {err_b:.2e} u {err_u:.2e} pi {err_p:.2e}")
+    assert max(err_s, err_b, err_u, err_p) <= TOL_OP
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name", ["c8", "c6", "c16"])
+def test_sphere_precondition(name):
+    prob, orc, s = setup(name)
+    import torch
+
+    r = np.random.default_rng(7).standard_normal(orc.mesh.ntrace)
+    z = torch.empty(orc.mesh.ntrace, dtype=torch.float64, device="cuda")
+    s.precondition(dev(r), z)
+    err = rel_max(host(z), orc.pc(r))
+    cond_h = np.linalg.cond(orc.H.toarray()) if orc.mesh.ncell <= 4000 else 1e4
+    tol = max(1e-11, 100 * np.finfo(float).eps * cond_h)
+    say(f"[sphere precondition] {name}: rel err {err:.2e} (tol {tol:.1e})")
+    assert err <= tol
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name", ["c8", "c6", "c16"])
+def test_sphere_solve_matches_direct(name):
+    prob, orc, s = setup(name)
+    import torch
+
+    r_ub, r_pi = make_rhs_sphere(prob, 0)
+    ruc, rpc = cells_from_soa(r_ub, r_pi)
+    lam_ref, ub_ref, pi_ref, Bref = orc.hyb.solve_direct(ruc, rpc)
+    u_mixed, pi_mixed = orc.mixed.solve(ruc, rpc)
+    b = torch.empty(orc.mesh.ntrace, dtype=torch.float64, device="cuda")
+    lam = torch.zeros(orc.mesh.ntrace, dtype=torch.float64, device="cuda")
+    s.condense(dev(r_ub), dev(r_pi), b)
+    info = s.solve(b, lam, rtol=1e-13, maxit=300)
+    ub = torch.empty(6 * orc.mesh.ncell, dtype=torch.float64, device="cuda")
+    pi = torch.empty(orc.mesh.ncell, dtype=torch.float64, device="cuda")
+    s.recover(dev(r_ub), dev(r_pi), lam, ub, pi)
+    e_l = rel_norm(host(lam), lam_ref)
+    e_p = rel_norm(host(pi), pi_mixed)
+    e_u = rel_norm(host(ub).reshape(6, -1).T, orc.mixed.broken_from_continuous(u_mixed))
+    res = np.linalg.norm(Bref - orc.hyb.S @ host(lam)) / np.linalg.norm(Bref)
+    dl = spla.splu(orc.hyb.S.tocsc()).solve(Bref - orc.hyb.S @ host(lam))
+    pred_l = np.linalg.norm(dl) / np.linalg.norm(lam_ref)
+    ub_h, pi_h = orc.hyb.recover(host(lam), ruc, rpc)
+    pred_p, pred_u = rel_norm(pi_h, pi_ref), rel_norm(ub_h, ub_ref)
+    say(f"[sphere solve] {name}: its {info['iters']} res {info['rel_res']:.2e} oracle res {res:.2e} "
+        f"lam {e_l:.2e} pi {e_p:.2e} u {e_u:.2e} (implied {pred_l:.2e} {pred_p:.2e} {pred_u:.2e})")
+    assert info["status"] == 0 and info["rel_res"] <= 1e-13 and res <= 2e-13
+    assert e_l <= 2 * pred_l + 1e-11 and e_p <= 2 * pred_p + 1e-11 and e_u <= 2 * pred_u + 1e-11
+    assert pred_l <= 1e-9 and pred_p <= 1e-9 and pred_u <= 1e-9
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name", ["c8", "c16"])
+def test_sphere_iterations_match_oracle(name):
+    prob, orc, s = setup(name)
+    import torch
+
+    r_ub, r_pi = make_rhs_sphere(prob, 4)
+    ruc, rpc = cells_from_soa(r_ub, r_pi)
+    Bref = orc.hyb.rhs(ruc, rpc)
+    _, hist, its, conv = orc.solve_fgmres(Bref, rtol=1e-8)
+    b = dev(Bref)
+    lam = torch.zeros_like(b)
+    info = s.solve(b, lam, rtol=1e-8, maxit=200)
+    say(f"[sphere iterations] {name}: gpu {info['iters']} oracle {its}")
+    assert abs(info["iters"] - its) <= 1
+    n = min(len(info["history"]), len(hist) - 1)
+    np.testing.assert_allclose(info["history"][:n], hist[1 : n + 1], rtol=1e-6)
+
+
+@pytest.mark.gpu
+def test_sphere_mixed_precision():
+    prob, orc, s = setup("c16")
+    import torch
+
+    sm = make_solver(prob, precision=1)
+    r_ub, r_pi = make_rhs_sphere(prob, 5)
+    ruc, rpc = cells_from_soa(r_ub, r_pi)
+    lam_ref, _, _, Bref = orc.hyb.solve_direct(ruc, rpc)
+    b = dev(Bref)
+    lam = torch.zeros_like(b)
+    info = sm.solve(b, lam, rtol=1e-8, maxit=200)
+    true_res = np.linalg.norm(Bref - orc.hyb.S @ host(lam)) / np.linalg.norm(Bref)
+    err = rel_norm(host(lam), lam_ref)
+    say(f"[sphere mixed] its {info['iters']} reported {info['rel_res']:.2e} oracle residual {true_res:.2e} "
+        f"err vs FP64 {err:.2e}")
+    assert info["status"] == 0 and true_res <= 1e-8 and err <= 1e-5
+    sm.close()
+
+
+# ------------------------------------------------------------------------------------------------
+# C192 x 30
+# ------------------------------------------------------------------------------------------------
+
+NSAMPLE = 3000
+_big = {}
+
+
+def big():
+    if not _big:
+        say("[c192] building the C192 x 30 problem")
+        prob = make_sphere(192, 30, dt=1800.0, mg_levels=4)
+        mesh = TableMesh(prob.nlev, prob.col_edge, prob.edge_col, prob.edge_lf)
+        fc, flf = mesh.face_cells()
+        s = make_solver(prob)
+        rng = np.random.default_rng(2025)
+        # sampled facets: random ones, and the facets around a cube corner (column 0 of panel 0)
+        faces = np.concatenate([rng.integers(0, mesh.n_zface, NSAMPLE // 2),
+                                rng.integers(mesh.n_zface, mesh.ntrace, NSAMPLE // 2),
+                                mesh.cell_faces[[0, mesh.ncol * (prob.nlev - 1)]].ravel(), [0, mesh.ntrace - 1]])
+        cells = np.unique(np.concatenate([fc[faces][fc[faces] >= 0], rng.integers(0, mesh.ncell, NSAMPLE),
+                                          [0, mesh.ncell - 1]]))
+        loc = shell_local_matrices(mesh, prob, cells=cells)
+        _big.update(prob=prob, mesh=mesh, fc=fc, flf=flf, s=s, faces=faces, cells=cells, loc=loc,
+                    pos={c: i for i, c in enumerate(cells)})
+    return _big
+
+
+def _rows(st, cellvals):
+    out = np.zeros(len(st["faces"]))
+    for j, F in enumerate(st["faces"]):
+        for side in range(2):
+            c = st["fc"][F, side]
+            if c >= 0:
+                out[j] += cellvals(st["pos"][c], st["flf"][F, side])
+    return out
+
+
+@pytest.mark.gpu
+def test_c192_sampled_operators():
+    st = big()
+    import torch
+
+    prob, mesh, s, cells = st["prob"], st["mesh"], st["s"], st["cells"]
+    x = np.random.default_rng(11).standard_normal(mesh.ntrace)
+    y = torch.empty(mesh.ntrace, dtype=torch.float64, device="cuda")
+    s.trace_apply(dev(x), y)
+    Sc = cell_trace_operator(st["loc"])
+    xc = x[mesh.cell_faces[cells]]
+    err_s = rel_max(host(y)[st["faces"]], _rows(st, lambda i, a: Sc[i, a] @ xc[i]))
+    r_ub, r_pi = make_rhs_sphere(prob, 0)
+    ruc, rpc = cells_from_soa(r_ub, r_pi)
+    b = torch.empty(mesh.ntrace, dtype=torch.float64, device="cuda")
+    s.condense(dev(r_ub), dev(r_pi), b)
+    bc = cell_rhs(st["loc"], ruc[cells], rpc[cells])
+    err_b = rel_max(host(b)[st["faces"]], _rows(st, lambda i, a: bc[i, a]))
+    lam = np.random.default_rng(5).standard_normal(mesh.ntrace)
+    ub = torch.empty(6 * mesh.ncell, dtype=torch.float64, device="cuda")
+    pi = torch.empty(mesh.ncell, dtype=torch.float64, device="cuda")
+    s.recover(dev(r_ub), dev(r_pi), dev(lam), ub, pi)
+    u_ref, p_ref = cell_recover(st["loc"], lam[mesh.cell_faces[cells]], ruc[cells], rpc[cells])
+    err_u = rel_max(host(ub).reshape(6, -1)[:, cells].T, u_ref)
+    err_p = rel_max(host(pi)[cells], p_ref)
+    say(f"[c192 sampled] S x {err_s:.2e} B {err_b:.2e} u {err_u:.2e} pi {err_p:.2e}")
+    assert max(err_s, err_b, err_u, err_p) <= TOL_OP
+
+
+@pytest.mark.gpu
+def test_c192_solves_fp64_and_mixed():
+    st = big()
+    import torch
+
+    prob, mesh, cells = st["prob"], st["mesh"], st["cells"]
+    r_ub, r_pi = make_rhs_sphere(prob, 1)
+    ruc, rpc = cells_from_soa(r_ub, r_pi)
+    lams = {}
+    for precision in (0, 1):
+        s = st["s"] if precision == 0 else make_solver(prob, precision=1)
+        b = torch.empty(mesh.ntrace, dtype=torch.float64, device="cuda")
+        lam = torch.zeros(mesh.ntrace, dtype=torch.float64, device="cuda")
+        s.condense(dev(r_ub), dev(r_pi), b)
+        info = s.solve(b, lam, rtol=1e-8, maxit=500)
+        lams[precision] = host(lam)
+        u_ref, _ = cell_recover(st["loc"], lams[precision][mesh.cell_faces[cells]], ruc[cells], rpc[cells])
+        defect = _rows(st, lambda i, a: u_ref[i, a])
+        worst = np.abs(defect).max() / float(torch.linalg.norm(b))
+        say(f"[c192 solve p{precision}] its {info['iters']} rel_res {info['rel_res']:.2e} "
+            f"max sampled continuity defect / ||B|| {worst:.2e}")
+        assert info["status"] == 0 and info["rel_res"] <= 1e-8
+        assert worst <= 1.0001 * info["rel_res"]
+        if precision:
+            s.close()
+    err = rel_norm(lams[1], lams[0])
+    say(f"[c192] mixed vs FP64 solution: rel 2-norm difference {err:.2e}")
+    assert err <= 1e-5
