@@ -3,7 +3,9 @@
 The network maps a DG0 field (one value per cell, [L][ncol]) to a DG0 field through three 3D
 convolutions, 1 -> C -> C -> 1 channels, each tap set being the 3 x 3 horizontal neighbourhood of a
 column (the column, its four edge neighbours and four corner neighbours) times 5 vertical offsets
-(-2..2, zero padded above the lid and below the ground); ReLU after the first two layers.
+(-2..2, zero padded above the lid and below the ground); ReLU after the first two layers.  On the
+cubed sphere the neighbourhood follows each column's frame across panel edges, and the corner
+neighbour that does not exist at a cube vertex is zero padded.
 
 The stage (not part of the paper) follows the two-level cycle z = M(v) of Alg. 2: with the residual
 r' = v - S z it left, the coarse right-hand side c = Gamma P^T r' of Alg. 2 and s = rms(c), the
@@ -45,6 +47,43 @@ def neighbour_table(nx, ny):
     return np.stack([((iy + dy) % ny) * nx + (ix + dx) % nx for (dx, dy) in H_OFFSETS]).astype(np.int64)
 
 
+# directions counter-clockwise in a column's frame (E, N, W, S) and the local faces W, E, S, N
+_DIR_OF_FACE = np.array([2, 0, 3, 1])
+_FACE_OF_DIR = np.array([1, 3, 0, 2])
+
+
+def neighbour_table_from_tables(col_edge, edge_col, edge_lf):
+    """nb[h][col] for any quadrilateral mesh whose column frames turn the same way (the cubed
+    sphere): the edge neighbours across W, E, S, N, and the corner neighbour at offset (dx, dy)
+    reached by one step along y and then one along x, the x direction carried into the
+    neighbour's frame by the quarter turn that maps the step's direction onto the neighbour's
+    face pointing away from the column.  Where the two orders of the steps disagree (the three
+    columns at a cube vertex have no corner neighbour there) the entry is -1 (zero padded)."""
+    ce, ec, el = (np.asarray(a, np.int64) for a in (col_edge, edge_col, edge_lf))
+    ncol = ce.shape[1]
+    col = np.arange(ncol)
+    nbr = np.empty((4, ncol), np.int64)
+    nlf = np.empty((4, ncol), np.int64)
+    for f in range(4):
+        e = ce[f]
+        side = np.where((ec[0, e] == col) & (el[0, e] == f), 0, 1)
+        nbr[f] = ec[1 - side, e]
+        nlf[f] = el[1 - side, e]
+
+    def route(f1, f2):
+        n = nbr[f1]
+        turn = (_DIR_OF_FACE[nlf[f1]] + 2 - _DIR_OF_FACE[f1]) % 4
+        return nbr[_FACE_OF_DIR[(_DIR_OF_FACE[f2] + turn) % 4], n]
+
+    def corner(fx, fy):
+        a, b = route(fy, fx), route(fx, fy)
+        return np.where(a == b, a, -1)
+
+    W, E, S, N = 0, 1, 2, 3
+    return np.stack([col, nbr[W], nbr[E], nbr[S], nbr[N], corner(W, S), corner(E, S), corner(W, N),
+                     corner(E, N)]).astype(np.int64)
+
+
 def init_weights(channels=16, seed=0):
     rng = np.random.default_rng(seed)
     shapes = [(channels, 1), (channels, channels), (1, channels)]
@@ -65,7 +104,8 @@ def conv(x, W, bias, nb, nlev):
     xr = x.reshape(ci, nlev, ncol)
     y = np.repeat(bias[:, None], n, axis=1).reshape(co, nlev, ncol).copy()
     for h in range(NH):
-        xh = xr[:, :, nb[h]]  # (ci, L, ncol): value at the neighbour column
+        ok = nb[h] >= 0  # a missing neighbour (cube vertex) reads zeros
+        xh = xr[:, :, np.where(ok, nb[h], 0)] * ok  # (ci, L, ncol): value at the neighbour column
         for v in range(NV):
             dk = v - 2
             shifted = np.zeros_like(xh)
@@ -87,7 +127,8 @@ def conv_grads(x, W, dy, nb, nlev):
     dW = np.zeros_like(W)
     dx = np.zeros((ci, nlev, ncol))
     for h in range(NH):
-        xh = xr[:, :, nb[h]]
+        ok = nb[h] >= 0
+        xh = xr[:, :, np.where(ok, nb[h], 0)] * ok
         for v in range(NV):
             dk = v - 2
             shifted = np.zeros_like(xh)
@@ -103,7 +144,7 @@ def conv_grads(x, W, dy, nb, nlev):
                 back[:, dk:] = g[:, : nlev - dk]
             else:
                 back[:, : nlev + dk] = g[:, -dk:]
-            np.add.at(dx, (slice(None), slice(None), nb[h]), back)
+            np.add.at(dx, (slice(None), slice(None), nb[h][ok]), back[:, :, ok])
     return dx.reshape(ci, n), dW, dyr.sum(axis=(1, 2))
 
 

@@ -215,3 +215,71 @@ def test_energy_gradients_match_central_differences():
         bm[layer][0] -= h
         fd = (f(W, bp)[0] - f(W, bm)[0]) / (2 * h)
         assert abs(fd - db[layer][0]) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_neighbour_table_from_tables_on_the_box():
+    from synth import make_box
+
+    p = make_box(nx=5, ny=4, nlev=1, dx=1e3, dz=1e3, mg_levels=1)
+    np.testing.assert_array_equal(nn.neighbour_table_from_tables(p.col_edge, p.edge_col, p.edge_lf),
+                                  nn.neighbour_table(5, 4))
+
+
+def test_neighbour_table_on_the_cubed_sphere():
+    # edge neighbours share two corner points with the column, corner neighbours exactly one, and
+    # the tap's direction agrees with the geometry: the neighbour's centre lies on the side of the
+    # offset (dx, dy) in the column's frame; only the 3 columns at each of the 8 cube vertices lack
+    # the corner neighbour there
+    from synth import make_sphere
+
+    p = make_sphere(6, 1, mg_levels=1)
+    nb = nn.neighbour_table_from_tables(p.col_edge, p.edge_col, p.edge_lf)
+    U = np.round(p.corners, 12)
+    ncol = p.ncol
+    pts = [set(map(tuple, U[:, :, c])) for c in range(ncol)]
+    assert (nb < 0).sum() == 24
+    cen = p.column_centres()
+    ex = (U[1] + U[3] - U[0] - U[2])  # the frame's x and y directions at the column
+    ey = (U[2] + U[3] - U[0] - U[1])
+    for h, (dx, dy) in enumerate(nn.H_OFFSETS[1:], start=1):
+        for c in range(ncol):
+            n = nb[h, c]
+            if n < 0:
+                continue
+            shared = len(pts[c] & pts[n])
+            assert shared == (2 if h <= 4 else 1), (h, c, n)
+            d = cen[:, n] - cen[:, c]
+            assert dx * (d @ ex[:, c]) >= 0 and dy * (d @ ey[:, c]) >= 0
+            if dx:
+                assert dx * (d @ ex[:, c]) > 0
+            if dy:
+                assert dy * (d @ ey[:, c]) > 0
+
+
+def test_gradients_with_missing_neighbours():
+    from synth import make_sphere
+
+    p = make_sphere(2, 4, mg_levels=1)
+    nb = nn.neighbour_table_from_tables(p.col_edge, p.edge_col, p.edge_lf)
+    assert (nb < 0).any()
+    nlev, n = 4, p.ncell
+    W, b = nn.init_weights(3, 5)
+    rng = np.random.default_rng(6)
+    x, t = rng.standard_normal(n), rng.standard_normal(n)
+    loss, dW, db, dx = nn.loss_and_grads(x, t, W, b, nb, nlev)
+    h = 1e-6
+    for layer in range(3):
+        for _ in range(4):
+            idx = tuple(rng.integers(0, s) for s in W[layer].shape)
+            Wp = [w.copy() for w in W]
+            Wm = [w.copy() for w in W]
+            Wp[layer][idx] += h
+            Wm[layer][idx] -= h
+            fd = (nn.loss_and_grads(x, t, Wp, b, nb, nlev)[0] - nn.loss_and_grads(x, t, Wm, b, nb, nlev)[0]) / (2 * h)
+            assert abs(fd - dW[layer][idx]) <= 1e-6 * max(1.0, abs(fd))
+    for i in rng.integers(0, n, 10):
+        xp, xm = x.copy(), x.copy()
+        xp[i] += h
+        xm[i] -= h
+        fd = (nn.loss_and_grads(xp, t, W, b, nb, nlev)[0] - nn.loss_and_grads(xm, t, W, b, nb, nlev)[0]) / (2 * h)
+        assert abs(fd - dx[i]) <= 1e-6 * max(1.0, abs(fd))
