@@ -276,6 +276,114 @@ def sphere_leg(args):
                 ncell=prob.ncell, ntrace=prob.ntrace, forms=out)
 
 
+def c384_leg(args):
+    """The learned stage on the extruded cubed sphere C384 x 70 (quadratic layers to 30 km, dt =
+    900 s, rotating; 61.9M cells): time-to-1e-8 of the plain FP64 solve, of the solve with the
+    learned stage and of the mixed form.  The network is local (it sees a 3 x 3 x 5 neighbourhood of
+    normalised residuals, 7 x 7 x 13 cells through three layers), so it is trained outside the timed
+    region on a smaller mesh with the same local geometry: by default a periodic 64 x 64 box with the
+    C384 mean cell width (2 pi R / 1536 = 26.1 km), the same 70 layers and time step (the same
+    Courant number); or (--c384-train sphere) a C{train_n} x 70 sphere with the time step scaled to
+    the same Courant number.  The box's recipe: 32 right-hand sides x 8 steps of the plain
+    iteration, 300 Adam steps on the energy loss.  One solver is alive at a time (the FP64 one with
+    its FGMRES(30) basis takes ~210 GB)."""
+    import numpy as np
+    import torch
+
+    from paper_2210_11797_amd import PREC_FP64, PREC_MIXED, Params, learned, solver_for
+    from synth import make_rhs_sphere, make_sphere
+
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()  # noqa: E731
+
+    def build(prob, prec):
+        params = Params(dt=prob.dt, tau_u=prob.tau_u, tau_rho=prob.tau_rho, tau_theta=prob.tau_theta, cp=prob.cp,
+                        rd=prob.rd, precision=prec, omega_rot=getattr(prob, "omega_rot", 0.0),
+                        mg_coarse_sweeps=args.coarse_sweeps,
+                        mg_coarse_cheb=0 if args.coarse_jacobi else 1)
+        sv = solver_for(prob, params)
+        sv.assemble_local(d(prob.theta_w), d(prob.exner_hat_w), d(prob.exner_c), d(prob.rho_c))
+        sv.condense()
+        torch.cuda.synchronize()
+        return sv
+
+    n, nt = args.c384_n, args.c384_train_n
+    if args.c384_train == "sphere":
+        tdt = args.c384_dt * n / nt
+        tprob = make_sphere(nt, args.c384_nlev, dt=tdt, mg_levels=4)
+        tmesh = f"C{nt} x {args.c384_nlev} sphere"
+        trhs = make_rhs_sphere
+    else:
+        from synth import make_box, make_rhs
+
+        tdt = args.c384_dt
+        dxm = 2.0 * np.pi * 6371.0e3 / (4 * n)
+        tprob = make_box(nx=64, ny=64, nlev=args.c384_nlev, dx=dxm, ztop=30.0e3, stretch="quadratic", dt=tdt,
+                         mg_levels=4)
+        tmesh = f"periodic box 64x64x{args.c384_nlev}, dx={dxm / 1e3:.1f}km, quadratic layers to 30km"
+        trhs = make_rhs
+    ts = build(tprob, PREC_FP64)
+    ts.nn_set_weights(learned.init_params(16, seed=0))
+    t0 = time.perf_counter()
+    bl = []
+    for sd in range(32):
+        r_ub, r_pi = trhs(tprob, 10000 + sd)
+        b = torch.empty(ts.ntrace, dtype=torch.float64, device="cuda")
+        ts.condense(d(r_ub), d(r_pi), b)
+        bl.append(b)
+    X, R = learned.generate_pairs(ts, bl, steps=8)
+    npairs = int(X.shape[0])
+    hist = learned.train(ts, X, R, steps=args.train_steps, batch=8, lr=2e-3, log=log)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    w = ts.nn_get_weights()
+    ts.close()
+    del X, R, bl, ts
+    torch.cuda.empty_cache()
+    log(f"c384: trained on {tmesh} (dt {tdt:.0f} s), {npairs} pairs, {train_s:.1f} s")
+
+    prob = make_sphere(n, args.c384_nlev, dt=args.c384_dt, mg_levels=4)
+    log(f"c384: C{n} x {args.c384_nlev}, {prob.ncell} cells, {prob.ntrace} trace unknowns")
+    rhs = [tuple(d(a) for a in make_rhs_sphere(prob, 1000 + sd)) for sd in range(2)]
+    out = {}
+    s = build(prob, PREC_FP64)
+    out["workspace_gb"] = s.workspace_bytes() / 1e9
+    sec, infos, _ = run_steps(s, rhs, 2, 1, args.rtol, profile=False)
+    _, _, fams = run_steps(s, rhs, 2, 0, args.rtol, profile=True)
+    its = [i["iters"] for i in infos]
+    nbytes = algorithmic_bytes(s.ntrace, s.ncell, s.ncol, prob.nlev, its, fams, 2)
+    out["fp64"] = dict(sec_per_solve=sec, iters=its, rel_res=max(i["rel_res"] for i in infos),
+                       hbm_gbs_algorithmic=nbytes / sec / 1e9, bytes_per_solve=nbytes)
+    log(f"c384 fp64: {sec * 1e3:.1f} ms per solve, iters {its}")
+    s.nn_set_weights(w)
+    p = s.params
+    p.learned = 1
+    s.set_params(p)
+    lsec, linfos, lfams = run_steps(s, rhs, 2, 1, args.rtol, profile="nn")
+    nn_launches, nn_ms = lfams["nn"]
+    out["learned"] = dict(sec_per_solve=lsec, iters=[i["iters"] for i in linfos],
+                          corrections_kept=[i["iters"] - i["fallbacks"] for i in linfos],
+                          rel_res=max(i["rel_res"] for i in linfos), speedup_vs_fp64=sec / lsec,
+                          stage_ms_per_call=nn_ms / max(nn_launches, 1),
+                          training=dict(mesh=tmesh, dt=tdt, pairs=npairs, steps=args.train_steps,
+                                        batch=8, final_energy_loss=float(np.mean(hist[-50:])), seconds=train_s))
+    log(f"c384 learned: {lsec * 1e3:.1f} ms per solve, iters {out['learned']['iters']}")
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    s = build(prob, PREC_MIXED)
+    msec, minfos, _ = run_steps(s, rhs, 2, 1, args.rtol, profile=False)
+    out["mixed"] = dict(sec_per_solve=msec, iters=[i["iters"] for i in minfos],
+                        rel_res=max(i["rel_res"] for i in minfos), speedup_vs_fp64=sec / msec)
+    log(f"c384 mixed: {msec * 1e3:.1f} ms per solve, iters {out['mixed']['iters']}")
+    s.close()
+    del s, rhs
+    torch.cuda.empty_cache()
+    return dict(workload=f"cubed sphere C{n} x {args.c384_nlev} quadratic layers to 30 km, radius 6371 km, "
+                         f"Omega 7.292e-5/s, dt={args.c384_dt:.0f}s, RT0/Q0/trace, seeded N(0,1) RHS plus the "
+                         f"Gaussian pressure bump (held-out seeds 1000-1001), FGMRES(30)+two-level, rtol {args.rtol}",
+                ncell=prob.ncell, ntrace=prob.ntrace, forms=out)
+
+
 def p1_leg(args):
     """Order 1 (RT1 / DG1 / Q1 trace, 44 x 44 cell blocks) on the 128 x 128 x 32 box (dx = 10 km,
     dz = 500 m): the condensation in FP64 and on MFMA (FP32, BF16 split), and time-to-1e-8 of FGMRES
@@ -373,6 +481,14 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-p1", action="store_true")
     ap.add_argument("--no-sphere", action="store_true")
+    ap.add_argument("--no-c384", action="store_true")
+    ap.add_argument("--c384-n", type=int, default=384)
+    ap.add_argument("--c384-nlev", type=int, default=70)
+    ap.add_argument("--c384-dt", type=float, default=900.0)
+    ap.add_argument("--c384-train", choices=["box", "sphere"], default="box",
+                    help="mesh the C384 network is trained on: a periodic box with the C384 cell width and layers, "
+                         "or a smaller cubed sphere (--c384-train-n) at the same Courant number")
+    ap.add_argument("--c384-train-n", type=int, default=48)
     ap.add_argument("--sphere-n", type=int, default=192)
     ap.add_argument("--sphere-nlev", type=int, default=30)
     ap.add_argument("--sphere-dt", type=float, default=1800.0)
@@ -448,13 +564,26 @@ def main():
 
     sphere_out = None
     if not args.no_sphere:
-        sphere_out = sphere_leg(args)
+        try:
+            sphere_out = sphere_leg(args)
+        except Exception as e:  # a failed side leg must not cost the headline line
+            log(f"sphere leg failed: {e}")
+            sphere_out = {"error": str(e)}
+
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    c384_out = None
+    if not args.no_c384:
+        try:
+            c384_out = c384_leg(args)
+        except Exception as e:
+            log(f"c384 leg failed: {e}")
+            c384_out = {"error": str(e)}
+            torch.cuda.empty_cache()
 
     p1_out = None
     if not args.no_p1:
-        s.close()
-        del s
-        torch.cuda.empty_cache()
         p1_out = p1_leg(args)
 
     cpu = None
@@ -501,6 +630,7 @@ def main():
         "mixed": mixed,
         "learned": learned_out,
         "sphere": sphere_out,
+        "c384": c384_out,
         "p1": p1_out,
         "cpu_baseline": cpu,
     }

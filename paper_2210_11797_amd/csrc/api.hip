@@ -895,7 +895,6 @@ int hyb_nn_param_count(void) { return nn_param_count(); }
 int hyb_nn_set_weights(hyb_ctx *c, const float *w, int64_t n) {
   if (!c) return HYB_EINVAL;
   if (c->order == 1) return fail(c, HYB_ESTATE, "hyb_nn_set_weights is not available at order 1");
-  if (c->geom != HYB_GEOM_BOX) return fail(c, HYB_ESTATE, "the learned stage needs the periodic box");
   if (!w || n != nn_param_count()) return fail(c, HYB_EINVAL, "weights: wrong size");
   for (int64_t i = 0; i < n; ++i)
     if (!std::isfinite(w[i])) return fail(c, HYB_EINVAL, "weights: not finite");

@@ -52,7 +52,8 @@ struct NNState {
   float *w = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;  // FP32 parameters, Adam moments, gradient
   uint16_t *wb = nullptr;                                         // BF16 copy of the weights
   int32_t *isbf = nullptr;                                        // parameter -> BF16 index (-1: bias)
-  int32_t *nb9 = nullptr;                                         // [9][ncol] 3x3 horizontal neighbourhood
+  int32_t *nb9 = nullptr;                                         // [9][ncol] 3x3 horizontal neighbourhood (-1: none)
+  int32_t *rv9 = nullptr;                                         // [9][ncol] readers of a column: col * 9 + tap
   float *a1 = nullptr, *a2 = nullptr, *y = nullptr;               // activations [nsamp][C][ncell]
   float *d1 = nullptr, *d2 = nullptr, *dy = nullptr;              // their gradients
   float *part = nullptr, *tmpg = nullptr, *lpart = nullptr;       // reduction scratch

@@ -17,7 +17,6 @@ namespace {
 constexpr int NHT = 9, NVT = 5, NTAP = NHT * NVT;
 constexpr int C1 = 16;  // hidden channels (the inference kernels are written for 16)
 // opposite horizontal direction of each tap (centre, W, E, S, N, SW, SE, NW, NE)
-__constant__ int kOpp[NHT] = {0, 2, 1, 4, 3, 8, 7, 6, 5};
 
 inline unsigned nblk(size_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
 
@@ -50,6 +49,7 @@ __global__ void __launch_bounds__(kBlock) k_conv_fwd(const float *__restrict__ x
   const float *xs = x + (size_t)s * CI * n;
   for (int h = 0; h < NHT; ++h) {
     const int c2 = nb9[(size_t)h * ncol + col];
+    if (c2 < 0) continue;  // no corner neighbour at a cube vertex: zero padding
 #pragma unroll
     for (int v = 0; v < NVT; ++v) {
       const int kk = k + v - 2;
@@ -68,12 +68,14 @@ __global__ void __launch_bounds__(kBlock) k_conv_fwd(const float *__restrict__ x
   for (int co = 0; co < CO; ++co) ys[(size_t)co * n + cell] = RELU ? fmaxf(acc[co], 0.f) : acc[co];
 }
 
-// dx[s][ci][cell] = (sum_{co,t} W[co][ci][t] dy[s][co][k-dk][nb[opp h][col]]) * (xin > 0 if MASK)
+// dx[s][ci][cell] = (sum over the columns c' and taps h with nb[h][c'] = col of
+//                    sum_{co,v} W[co][ci][h,v] dy[s][co][k-dk][c']) * (xin > 0 if MASK);
+// rv9[r][col] = c' * 9 + h lists those pairs (at most 9, ordered by h; -1 pads)
 template <int CI, int CO, bool MASK>
 __global__ void __launch_bounds__(kBlock) k_conv_bwd_data(const float *__restrict__ dy, const uint16_t *__restrict__ wb,
                                                           const float *__restrict__ xin, float *__restrict__ dx,
                                                           int nlev, int ncol, int nsamp,
-                                                          const int32_t *__restrict__ nb9) {
+                                                          const int32_t *__restrict__ rv9) {
   __shared__ float w[CO * CI * NTAP];
   for (int i = threadIdx.x; i < CO * CI * NTAP; i += blockDim.x) w[i] = bf2f(wb[i]);
   __syncthreads();
@@ -87,8 +89,10 @@ __global__ void __launch_bounds__(kBlock) k_conv_bwd_data(const float *__restric
 #pragma unroll
   for (int ci = 0; ci < CI; ++ci) acc[ci] = 0.f;
   const float *dys = dy + (size_t)s * CO * n;
-  for (int h = 0; h < NHT; ++h) {
-    const int c2 = nb9[(size_t)kOpp[h] * ncol + col];
+  for (int rr = 0; rr < NHT; ++rr) {
+    const int pk = rv9[(size_t)rr * ncol + col];
+    if (pk < 0) continue;
+    const int c2 = pk / NHT, h = pk - c2 * NHT;
 #pragma unroll
     for (int v = 0; v < NVT; ++v) {
       const int kk = k - (v - 2);
@@ -147,7 +151,9 @@ __global__ void __launch_bounds__(kBlock) k_conv_bwd_weight(const float *__restr
       const int k = cell / ncol, col = cell - k * ncol;
       const int kk = k + dk;
       if (kk < 0 || kk >= nlev) continue;
-      const float xv = x[((size_t)s * CI + ci) * n + (size_t)kk * ncol + nb9[(size_t)h * ncol + col]];
+      const int c2 = nb9[(size_t)h * ncol + col];
+      if (c2 < 0) continue;
+      const float xv = x[((size_t)s * CI + ci) * n + (size_t)kk * ncol + c2];
 #pragma unroll
       for (int co = 0; co < CO; ++co) acc[co] += sdy[i][co] * xv;
     }
@@ -430,6 +436,7 @@ __global__ void __launch_bounds__(kBlock) k_inf_layer1(const float *__restrict__
   for (int co = 0; co < C1; ++co) acc[co] = bias[co];
   for (int h = 0; h < NHT; ++h) {
     const int c2 = nb9[(size_t)h * ncol + col];
+    if (c2 < 0) continue;
 #pragma unroll
     for (int v = 0; v < NVT; ++v) {
       const int kk = k + v - 2;
@@ -474,14 +481,16 @@ __global__ void __launch_bounds__(kBlock) k_inf_layer2_mfma(const uint16_t *__re
     for (int h = 0; h < NHT; ++h) cn[h] = live ? nb9[(size_t)h * ncol + col] : 0;
 #pragma unroll
     for (int h = 0; h < NHT; ++h) {
-      const int c2 = cn[h];
+      // a missing corner neighbour (cube vertex) loads from the column itself and is discarded
+      const bool has = cn[h] >= 0;
+      const int c2 = has ? cn[h] : col;
 #pragma unroll
       for (int v = 0; v < NVT; ++v) {
         // unconditional load from a clamped level (the value is discarded outside the column), so
         // the loads of all taps can be issued ahead of the products
         const int kk = k + v - 2, kc = kk < 0 ? 0 : (kk >= nlev ? nlev - 1 : kk);
         const uint2 u = *reinterpret_cast<const uint2 *>(a1 + ((size_t)kc * ncol + c2) * C1 + 4 * q);
-        const bool in = live && kk == kc;
+        const bool in = live && has && kk == kc;
         nn_bf16x4 A;
         A[0] = in ? (short)(u.x & 0xFFFFu) : (short)0, A[1] = in ? (short)(u.x >> 16) : (short)0;
         A[2] = in ? (short)(u.y & 0xFFFFu) : (short)0, A[3] = in ? (short)(u.y >> 16) : (short)0;
@@ -513,6 +522,7 @@ __global__ void __launch_bounds__(kBlock) k_inf_layer3(const uint16_t *__restric
   float acc = bias[0];
   for (int h = 0; h < NHT; ++h) {
     const int c2 = nb9[(size_t)h * ncol + col];
+    if (c2 < 0) continue;
 #pragma unroll
     for (int v = 0; v < NVT; ++v) {
       const int kk = k + v - 2;
@@ -565,24 +575,53 @@ hipError_t nn_setup(hyb_ctx *c) {
   };
   if ((e = A((void **)&s.w, NPARAM * 4)) || (e = A((void **)&s.m, NPARAM * 4)) || (e = A((void **)&s.v, NPARAM * 4)) ||
       (e = A((void **)&s.g, NPARAM * 4)) || (e = A((void **)&s.wb, (W1N + W2N + W3N) * 2)) ||
-      (e = A((void **)&s.isbf, NPARAM * 4)) || (e = A((void **)&s.nb9, 9 * (size_t)c->ncol * 4)))
+      (e = A((void **)&s.isbf, NPARAM * 4)) || (e = A((void **)&s.nb9, 9 * (size_t)c->ncol * 4)) ||
+      (e = A((void **)&s.rv9, 9 * (size_t)c->ncol * 4)))
     return e;
   std::vector<int32_t> isbf(NPARAM, -1);
   for (int j = 0; j < W1N; ++j) isbf[OFF_W1 + j] = j;
   for (int j = 0; j < W2N; ++j) isbf[OFF_W2 + j] = W1N + j;
   for (int j = 0; j < W3N; ++j) isbf[OFF_W3 + j] = W1N + W2N + j;
   if ((e = hipMemcpy(s.isbf, isbf.data(), NPARAM * 4, hipMemcpyHostToDevice))) return e;
-  // 3x3 horizontal neighbourhood from the edge neighbours: corners are the W/E neighbours of the
-  // S/N neighbours
-  std::vector<int32_t> nbr(4 * (size_t)c->ncol), nb9(9 * (size_t)c->ncol);
-  if ((e = hipMemcpy(nbr.data(), c->lv[0].nbr, nbr.size() * 4, hipMemcpyDeviceToHost))) return e;
+  // 3x3 horizontal neighbourhood in each column's frame: the edge neighbours, and the corner
+  // neighbour at (dx, dy) one step along y and then one along x, the x direction turned into the
+  // neighbour's frame by the quarter turn between the frames (none on the periodic box); where the
+  // two step orders disagree (cube vertices) there is no corner neighbour: -1, read as zeros.
+  // rv9 lists, per column, the (column, tap) pairs that read it, for the transposed convolution.
+  std::vector<int32_t> nbr(4 * (size_t)c->ncol), nlf(4 * (size_t)c->ncol), nb9(9 * (size_t)c->ncol);
+  if ((e = hipMemcpy(nbr.data(), c->lv[0].nbr, nbr.size() * 4, hipMemcpyDeviceToHost)) ||
+      (e = hipMemcpy(nlf.data(), c->lv[0].nlf, nlf.size() * 4, hipMemcpyDeviceToHost)))
+    return e;
   const size_t n = c->ncol;
+  static const int kDirOfFace[4] = {2, 0, 3, 1};  // W, E, S, N -> counter-clockwise direction (E, N, W, S)
+  static const int kFaceOfDir[4] = {1, 3, 0, 2};
+  auto route = [&](size_t col, int f1, int f2) {
+    const int nb = nbr[f1 * n + col];
+    const int turn = (kDirOfFace[nlf[f1 * n + col]] + 2 - kDirOfFace[f1]) & 3;
+    return nbr[(size_t)kFaceOfDir[(kDirOfFace[f2] + turn) & 3] * n + nb];
+  };
+  auto corner = [&](size_t col, int fx, int fy) {
+    const int a = route(col, fy, fx), b = route(col, fx, fy);
+    return a == b ? a : -1;
+  };
   for (size_t col = 0; col < n; ++col) {
-    int W = nbr[0 * n + col], E = nbr[1 * n + col], S = nbr[2 * n + col], N = nbr[3 * n + col];
-    int v[9] = {(int)col, W, E, S, N, nbr[0 * n + S], nbr[1 * n + S], nbr[0 * n + N], nbr[1 * n + N]};
+    int v[9] = {(int)col, nbr[0 * n + col], nbr[1 * n + col], nbr[2 * n + col], nbr[3 * n + col],
+                corner(col, 0, 2), corner(col, 1, 2), corner(col, 0, 3), corner(col, 1, 3)};
     for (int h = 0; h < 9; ++h) nb9[h * n + col] = v[h];
   }
-  if ((e = hipMemcpy(s.nb9, nb9.data(), nb9.size() * 4, hipMemcpyHostToDevice))) return e;
+  std::vector<int32_t> rv9(9 * n, -1);
+  std::vector<int> cnt(n, 0);
+  if (n * 9 > (size_t)INT32_MAX) return hipErrorInvalidValue;
+  for (int h = 0; h < 9; ++h)
+    for (size_t col = 0; col < n; ++col) {
+      const int t = nb9[h * n + col];
+      if (t < 0) continue;
+      if (cnt[t] >= 9) return hipErrorInvalidValue;  // more than 9 readers of one column
+      rv9[(size_t)cnt[t]++ * n + t] = (int32_t)(col * 9 + h);
+    }
+  if ((e = hipMemcpy(s.nb9, nb9.data(), nb9.size() * 4, hipMemcpyHostToDevice)) ||
+      (e = hipMemcpy(s.rv9, rv9.data(), rv9.size() * 4, hipMemcpyHostToDevice)))
+    return e;
   std::vector<float> zero(NPARAM, 0.f);
   if ((e = hipMemcpy(s.m, zero.data(), NPARAM * 4, hipMemcpyHostToDevice)) ||
       (e = hipMemcpy(s.v, zero.data(), NPARAM * 4, hipMemcpyHostToDevice)) ||
@@ -707,12 +746,12 @@ static hipError_t nn_backward(hyb_ctx *c, const float *x, int nsamp) {
   // layer 3: dy -> dW3, db3, d(a2) masked by a2 > 0
   if ((e = weight_grad<C, 1>(c, s.dy, s.a2, nsamp, s.g + OFF_W3, s.g + OFF_B3))) return e;
   hipLaunchKernelGGL((k_conv_bwd_data<C, 1, true>), g, b, 0, c->stream, s.dy, s.wb + W1N + W2N, s.a2, s.d2, L, nc,
-                     nsamp, s.nb9);
+                     nsamp, s.rv9);
   if ((e = hipGetLastError())) return e;
   // layer 2
   if ((e = weight_grad<C, C>(c, s.d2, s.a1, nsamp, s.g + OFF_W2, s.g + OFF_B2))) return e;
   hipLaunchKernelGGL((k_conv_bwd_data<C, C, true>), g, b, 0, c->stream, s.d2, s.wb + W1N, s.a1, s.d1, L, nc, nsamp,
-                     s.nb9);
+                     s.rv9);
   if ((e = hipGetLastError())) return e;
   // layer 1 (input x)
   return weight_grad<1, C>(c, s.d1, x, nsamp, s.g + OFF_W1, s.g + OFF_B1);
@@ -873,6 +912,7 @@ void nn_free(hyb_ctx *c) {
   if (s.wb) (void)hipFree(s.wb), s.wb = nullptr;
   if (s.isbf) (void)hipFree(s.isbf), s.isbf = nullptr;
   if (s.nb9) (void)hipFree(s.nb9), s.nb9 = nullptr;
+  if (s.rv9) (void)hipFree(s.rv9), s.rv9 = nullptr;
   if (s.scal) (void)hipFree(s.scal), s.scal = nullptr;
   if (s.a1h) (void)hipFree(s.a1h), s.a1h = nullptr;
   if (s.a2h) (void)hipFree(s.a2h), s.a2h = nullptr;

@@ -330,8 +330,33 @@ def sphere_sequence(lib):
     c.set(precision=N.PREC_MIXED)
     rc, info, lam = c.solve(b, 1e-8)
     check(rc == 0 and c.residual(b, lam) <= 1.01e-8, f"sphere: mixed FGMRES {info.iters} iterations")
-    w = np.zeros(N.Params and lib.hyb_nn_param_count(), np.float32)
-    check(lib.hyb_nn_set_weights(c.h, P(w), w.size) < 0, "sphere: the learned stage is rejected")
+    # the network on the frame-following neighbourhood (zero padded at the cube vertices): forward
+    # and gradients against the oracle, a training step, the solve with the stage
+    rng = np.random.default_rng(1)
+    w = learned.init_params(16, seed=3)
+    w[16 * 45 : 16 * 45 + 16] = rng.standard_normal(16) * 0.1
+    c.call("hyb_nn_set_weights", P(w), w.size)
+    nb = onn.neighbour_table_from_tables(prob.col_edge, prob.edge_col, prob.edge_lf)
+    W, bias = learned.unpack(w)
+    Wr = [onn.bf16_round(a) for a in W]
+    x2 = rng.standard_normal((2, c.ncell)).astype(np.float32)
+    t2 = rng.standard_normal((2, c.ncell)).astype(np.float32)
+    y2 = np.empty((2, c.ncell), np.float32)
+    c.call("hyb_nn_forward", P(x2), P(y2), 2)
+    yref = np.stack([onn.forward(x2[i].astype(np.float64), Wr, bias, nb, prob.nlev)[0] for i in range(2)])
+    check(np.abs(y2 - yref).max() <= 1e-5 * np.abs(yref).max(), "sphere: network forward against the oracle")
+    loss, g = ctypes.c_float(), np.empty(w.size, np.float32)
+    c.call("hyb_nn_loss_grad", P(x2), P(t2), 2, ctypes.byref(loss), P(g))
+    refs = [onn.loss_and_grads(x2[i].astype(np.float64), t2[i].astype(np.float64), Wr, bias, nb, prob.nlev)
+            for i in range(2)]
+    gref = learned.pack([0.5 * (refs[0][1][j] + refs[1][1][j]) for j in range(3)],
+                        [0.5 * (refs[0][2][j] + refs[1][2][j]) for j in range(3)]).astype(np.float64)
+    gerr = np.abs(g - gref).max() / np.abs(gref).max()
+    check(gerr <= 1e-4, f"sphere: network gradients against the oracle ({gerr:.1e})")
+    c.call("hyb_nn_train_step", P(x2), P(t2), 2, ctypes.c_float(1e-3), None)
+    c.set(learned=1, precision=N.PREC_FP64)
+    rc, info, lam = c.solve(b, 1e-8, maxit=60)
+    check(rc >= 0, f"sphere: solve with the learned stage: {info.iters} iterations")
     c.close()
 
 

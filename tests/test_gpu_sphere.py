@@ -251,3 +251,64 @@ def test_c192_solves_fp64_and_mixed():
     err = rel_norm(lams[1], lams[0])
     say(f"[c192] mixed vs FP64 solution: rel 2-norm difference {err:.2e}")
     assert err <= 1e-5
+
+
+# ------------------------------------------------------------------------------------------------
+# the learned stage on the sphere (frame-following 3x3 neighbourhood, zero padded at cube vertices)
+# ------------------------------------------------------------------------------------------------
+
+
+@pytest.mark.gpu
+def test_sphere_network_and_stage_match_oracle():
+    """Network forward and MSE gradients (BF16 weights in the oracle) on C8 x 6, whose 24 columns at
+    the cube vertices lack a corner neighbour, and hyb_precondition with the stage against the
+    oracle's cycle + stage (identity network to 1e-6, random network to 1e-4, the tolerances of the
+    box tests)."""
+    import torch
+
+    from oracle import nn as onn
+    from paper_2210_11797_amd import learned
+
+    prob, orc, s = setup("c8")
+    nb = onn.neighbour_table_from_tables(prob.col_edge, prob.edge_col, prob.edge_lf)
+    assert (nb < 0).sum() == 24
+    rng = np.random.default_rng(0)
+    vec = learned.init_params(16, seed=1)
+    vec[16 * 45 : 16 * 45 + 16] = rng.standard_normal(16) * 0.1
+    s.nn_set_weights(vec)
+    x = rng.standard_normal((2, prob.ncell)).astype(np.float32)
+    t = rng.standard_normal((2, prob.ncell)).astype(np.float32)
+    W, b = learned.unpack(vec)
+    Wr = [onn.bf16_round(w) for w in W]
+    f32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()  # noqa: E731
+    y = torch.empty((2, prob.ncell), dtype=torch.float32, device="cuda")
+    s.nn_forward(f32(x), y, 2)
+    yref = np.stack([onn.forward(x[i].astype(np.float64), Wr, b, nb, prob.nlev)[0] for i in range(2)])
+    err_y = rel_max(host(y), yref)
+    loss, g = s.nn_loss_grad(f32(x), f32(t), 2)
+    refs = [onn.loss_and_grads(x[i].astype(np.float64), t[i].astype(np.float64), Wr, b, nb, prob.nlev)
+            for i in range(2)]
+    gref = learned.pack([0.5 * (refs[0][1][j] + refs[1][1][j]) for j in range(3)],
+                        [0.5 * (refs[0][2][j] + refs[1][2][j]) for j in range(3)]).astype(np.float64)
+    err_g = rel_max(np.asarray(g, np.float64), gref)
+    say(f"[sphere nn] forward {err_y:.2e} gradients {err_g:.2e}")
+    assert err_y <= 1e-5 and err_g <= 1e-4
+    Wi, bi = onn.identity_weights(16)
+    p = s.params
+    for name, v_ in (("identity", learned.pack(Wi, bi)), ("random", learned.init_params(16, seed=9))):
+        s.nn_set_weights(v_)
+        Wv, bv = learned.unpack(v_)
+        Wvr = [onn.bf16_round(w) for w in Wv]
+        for trial in range(2):
+            v = rng.standard_normal(orc.mesh.ntrace)
+            zref, acc = onn.learned_correction(v, orc.pc(v), orc.pc.S, orc.pc.P, orc.pc.gamma, orc.H.diagonal(), Wvr,
+                                               bv, nb, prob.nlev, round_act=onn.bf16_round)
+            z = torch.empty(s.ntrace, dtype=torch.float64, device="cuda")
+            p.learned = 1
+            s.set_params(p)
+            s.precondition(dev(v), z)
+            p.learned = 0
+            s.set_params(p)
+            err = rel_max(host(z), zref)
+            say(f"[sphere stage] {name} trial {trial}: accepted {acc}, error {err:.2e}")
+            assert err <= (1e-6 if name == "identity" else 1e-4)
