@@ -312,3 +312,131 @@ def test_sphere_network_and_stage_match_oracle():
             err = rel_max(host(z), zref)
             say(f"[sphere stage] {name} trial {trial}: accepted {acc}, error {err:.2e}")
             assert err <= (1e-6 if name == "identity" else 1e-4)
+
+
+# ------------------------------------------------------------------------------------------------
+# C384 x 70 (the learned-stage workload): sampled parity in the benchmark's configuration
+# ------------------------------------------------------------------------------------------------
+
+
+class _Cells:
+    """cell_layer / cell_col of every cell of an extruded mesh (what the oracle's cell matrices
+    need), without the full dof maps."""
+
+    def __init__(self, ncol, nlev):
+        c = np.arange(ncol * nlev, dtype=np.int64)
+        self.cell_layer, self.cell_col = c // ncol, c % ncol
+
+
+def _faces_of_cells(prob, cells):
+    """(ncell_sampled, 6) trace facets of the given cells (numbering of the library's header)."""
+    ncol, nlev = prob.ncol, prob.nlev
+    k, col = cells // ncol, cells % ncol
+    nz = (nlev + 1) * ncol
+    out = np.empty((cells.shape[0], 6), np.int64)
+    for f in range(4):
+        out[:, f] = nz + k * (2 * ncol) + prob.col_edge[f, col]
+    out[:, 4] = k * ncol + col
+    out[:, 5] = (k + 1) * ncol + col
+    return out
+
+
+def _cells_of_faces(prob, faces):
+    """For each facet its (cell, local face) pairs, -1 where absent."""
+    ncol, nlev = prob.ncol, prob.nlev
+    nz = (nlev + 1) * ncol
+    cells = np.full((faces.shape[0], 2), -1, np.int64)
+    lfs = np.full((faces.shape[0], 2), -1, np.int64)
+    for j, F in enumerate(faces):
+        if F < nz:
+            k, col = divmod(int(F), ncol)
+            if k > 0:
+                cells[j, 0], lfs[j, 0] = (k - 1) * ncol + col, 5
+            if k < nlev:
+                cells[j, 1], lfs[j, 1] = k * ncol + col, 4
+        else:
+            k, e = divmod(int(F) - nz, 2 * ncol)
+            for sd in range(2):
+                cells[j, sd], lfs[j, sd] = k * ncol + prob.edge_col[sd, e], prob.edge_lf[sd, e]
+    return cells, lfs
+
+
+@pytest.mark.gpu
+def test_c384_sampled_operators_and_solves():
+    import torch
+
+    from paper_2210_11797_amd import learned
+
+    if _big.get("s") is not None:  # release the C192 context first (one large context at a time)
+        _big["s"].close()
+        _big.clear()
+    torch.cuda.empty_cache()
+    say("[c384] building the C384 x 70 problem")
+    prob = make_sphere(384, 70, dt=900.0, mg_levels=4)
+    ncol, ncell = prob.ncol, prob.ncell
+    ntrace = prob.ntrace
+    rng = np.random.default_rng(2026)
+    nz = (prob.nlev + 1) * ncol
+    faces = np.concatenate([rng.integers(0, nz, 800), rng.integers(nz, ntrace, 800),
+                            _faces_of_cells(prob, np.array([0, ncell - 1])).ravel(), [0, ntrace - 1]])
+    fcell, flf = _cells_of_faces(prob, faces)
+    cells = np.unique(np.concatenate([fcell[fcell >= 0], rng.integers(0, ncell, 1500), [0, ncell - 1]]))
+    pos = {c: i for i, c in enumerate(cells)}
+    loc = shell_local_matrices(_Cells(ncol, prob.nlev), prob, cells=cells)
+    cf = _faces_of_cells(prob, cells)
+
+    def rows(cellvals):
+        out = np.zeros(faces.shape[0])
+        for j in range(faces.shape[0]):
+            for sd in range(2):
+                if fcell[j, sd] >= 0:
+                    out[j] += cellvals(pos[fcell[j, sd]], flf[j, sd])
+        return out
+
+    s = make_solver(prob)
+    say(f"[c384] context {s.workspace_bytes() / 1e9:.1f} GB")
+    x = np.random.default_rng(11).standard_normal(ntrace)
+    y = torch.empty(ntrace, dtype=torch.float64, device="cuda")
+    s.trace_apply(dev(x), y)
+    Sc = cell_trace_operator(loc)
+    xc = x[cf]
+    err_s = rel_max(host(y)[faces], rows(lambda i, a: Sc[i, a] @ xc[i]))
+    del y
+    r_ub, r_pi = make_rhs_sphere(prob, 1000)
+    ruc = np.ascontiguousarray(r_ub.reshape(6, -1)[:, cells].T)
+    rpc = r_pi.reshape(-1)[cells]
+    b = torch.empty(ntrace, dtype=torch.float64, device="cuda")
+    s.condense(dev(r_ub), dev(r_pi), b)
+    bc = cell_rhs(loc, ruc, rpc)
+    err_b = rel_max(host(b)[faces], rows(lambda i, a: bc[i, a]))
+    say(f"[c384 sampled] S x {err_s:.2e} B {err_b:.2e}")
+    assert err_s <= TOL_OP and err_b <= TOL_OP
+    bnorm = float(torch.linalg.norm(b))
+    for learned_on in (0, 1):
+        if learned_on:
+            s.nn_set_weights(learned.init_params(16, seed=0))
+            p = s.params
+            p.learned = 1
+            s.set_params(p)
+        lam = torch.zeros(ntrace, dtype=torch.float64, device="cuda")
+        info = s.solve(b, lam, rtol=1e-8, maxit=300)
+        lam_h = host(lam)
+        u_ref, _ = cell_recover(loc, lam_h[cf], ruc, rpc)
+        worst = np.abs(rows(lambda i, a: u_ref[i, a])).max() / bnorm
+        say(f"[c384 solve learned={learned_on}] its {info['iters']} rel_res {info['rel_res']:.2e} kept "
+            f"{info['iters'] - info['fallbacks']} max sampled continuity defect / ||B|| {worst:.2e}")
+        assert info["status"] == 0 and info["rel_res"] <= 1e-8
+        assert worst <= 1.0001 * info["rel_res"]
+        del lam
+    ub = torch.empty(6 * ncell, dtype=torch.float64, device="cuda")
+    pi = torch.empty(ncell, dtype=torch.float64, device="cuda")
+    lam_r = np.random.default_rng(5).standard_normal(ntrace)
+    s.recover(dev(r_ub), dev(r_pi), dev(lam_r), ub, pi)
+    u_ref, p_ref = cell_recover(loc, lam_r[cf], ruc, rpc)
+    err_u = rel_max(host(ub).reshape(6, -1)[:, cells].T, u_ref)
+    err_p = rel_max(host(pi)[cells], p_ref)
+    say(f"[c384 recover] u {err_u:.2e} pi {err_p:.2e}")
+    assert err_u <= TOL_OP and err_p <= TOL_OP
+    s.close()
+    del s, b, ub, pi
+    torch.cuda.empty_cache()
