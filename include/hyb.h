@@ -235,14 +235,17 @@ int hyb_profile_read(hyb_ctx *ctx, const char *family, int64_t *launches, double
 int hyb_restrict(hyb_ctx *ctx, const double *r, double *cells, int32_t mode);
 
 /* Learned coarse correction (not part of the paper): a network of three 3D convolutions on cell
-   fields (1 -> 16 -> 16 -> 1 channels; taps = the 3x3 horizontal neighbourhood of a column times
-   5 vertical offsets, zero padded at ground and lid; ReLU after the first two), BF16 weights with
-   FP32 accumulation.  With params.learned = 1, hyb_solve and hyb_precondition follow every
+   fields (3 -> 16 -> 16 -> 1 channels; taps = the 3x3 horizontal neighbourhood of a column in its
+   own frame times 5 vertical offsets, zero padded at ground and lid and where a cube vertex leaves
+   no corner neighbour; ReLU after the first two), BF16 weights with FP32 accumulation.  Input
+   channel 0 is the field x; channels 1 and 2 are static fields of the assembled mesh, the same for
+   every sample: log(h / dz) with h = sqrt(|K| / dz) the cell's horizontal size, and the height of
+   the cell centre over the height of the lid (network calls need hyb_assemble_local first).  With params.learned = 1, hyb_solve and hyb_precondition follow every
    two-level cycle z = M(v) with r' = v - S z, c = Gamma P^T r', s = rms(c),
    d = s P (N(c / s) / H_KK), and z += d only if ||r' - S d||_2 < learned_tau ||r'||_2 (FP64):
    otherwise, or when the network output is not finite, z stays the plain cycle's output (counted in
    hyb_info.fallbacks).
-   Parameters (FP32, host arrays of hyb_nn_param_count() values): W1 [16][1][45], b1 [16],
+   Parameters (FP32, host arrays of hyb_nn_param_count() values): W1 [16][3][45], b1 [16],
    W2 [16][16][45], b2 [16], W3 [1][16][45], b3 [1], tap index = 5*h + (dk+2), h = centre, W, E,
    S, N, SW, SE, NW, NE.  Cell fields x, t, y are DEVICE FP32 arrays [nsamp][nlev][ncol].
    Errors: HYB_ESTATE before hyb_nn_set_weights (or, for the energy calls, before hyb_condense);

@@ -1,7 +1,8 @@
 """Learned coarse correction network and stage (test infrastructure, FP64 NumPy reference).
 
-The network maps a DG0 field (one value per cell, [L][ncol]) to a DG0 field through three 3D
-convolutions, 1 -> C -> C -> 1 channels, each tap set being the 3 x 3 horizontal neighbourhood of a
+The network maps a DG0 field (one value per cell, [L][ncol]), with two static fields of the mesh
+beside it (log(h / dz), h = sqrt(|K| / dz) the cell's horizontal size, and the cell-centre height
+over the lid's), to a DG0 field through three 3D convolutions, 3 -> C -> C -> 1 channels, each tap set being the 3 x 3 horizontal neighbourhood of a
 column (the column, its four edge neighbours and four corner neighbours) times 5 vertical offsets
 (-2..2, zero padded above the lid and below the ground); ReLU after the first two layers.  On the
 cubed sphere the neighbourhood follows each column's frame across panel edges, and the corner
@@ -84,9 +85,25 @@ def neighbour_table_from_tables(col_edge, edge_col, edge_lf):
                      corner(E, N)]).astype(np.int64)
 
 
+NIN = 3  # input channels: the normalised coarse residual, log(h / dz), z / z_top
+
+
+def static_inputs(vol, z, ncol):
+    """The two static input channels (2, L*ncol) of the network: log(h / dz) with h = sqrt(|K| / dz)
+    the cell's horizontal size, and the height of the cell centre over that of the lid.
+    vol: cell volumes (L*ncol,); z: interface heights (L+1,)."""
+    z = np.asarray(z, np.float64)
+    nlev = z.shape[0] - 1
+    k = np.arange(nlev * ncol) // ncol
+    dz = (z[1:] - z[:-1])[k]
+    h = np.sqrt(np.asarray(vol, np.float64) / dz)
+    zc = (0.5 * (z[1:] + z[:-1]) - z[0])[k] / (z[-1] - z[0])
+    return np.stack([np.log(h / dz), zc])
+
+
 def init_weights(channels=16, seed=0):
     rng = np.random.default_rng(seed)
-    shapes = [(channels, 1), (channels, channels), (1, channels)]
+    shapes = [(channels, NIN), (channels, channels), (1, channels)]
     W, b = [], []
     for co, ci in shapes:
         fan_in = ci * NT
@@ -148,11 +165,18 @@ def conv_grads(x, W, dy, nb, nlev):
     return dx.reshape(ci, n), dW, dyr.sum(axis=(1, 2))
 
 
-def forward(x, W, b, nb, nlev, round_act=None):
+def forward(x, W, b, nb, nlev, round_act=None, static=None):
     """Returns the output and the post-activation values of every layer (x is (L*ncol,)).
     round_act: applied to the hidden activations after the ReLU (e.g. ``bf16_round`` for networks
-    whose hidden activations are stored in BF16)."""
-    acts = [x[None, :]]
+    whose hidden activations are stored in BF16); static: the static input channels (zeros if
+    None)."""
+    nst = W[0].shape[1] - 1
+    if nst == 0:
+        acts = [x[None, :]]
+    else:
+        if static is None:
+            static = np.zeros((nst, x.shape[0]))
+        acts = [np.vstack([x[None, :], np.asarray(static, np.float64).reshape(nst, -1)])]
     h = acts[0]
     for i in range(3):
         h = conv(h, W[i], b[i], nb, nlev)
@@ -164,9 +188,9 @@ def forward(x, W, b, nb, nlev, round_act=None):
     return h[0], acts
 
 
-def loss_and_grads(x, target, W, b, nb, nlev):
+def loss_and_grads(x, target, W, b, nb, nlev, static=None):
     """Mean squared error over cells and its gradients (dW list, db list, dx)."""
-    y, acts = forward(x, W, b, nb, nlev)
+    y, acts = forward(x, W, b, nb, nlev, static=static)
     n = y.shape[0]
     diff = y - target
     loss = float(np.mean(diff * diff))
@@ -189,13 +213,13 @@ def bf16_round(a):
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
-def learned_correction(v, z, S, P, gamma, hdiag, W, b, nb, nlev, tau=3.0, round_act=None):
+def learned_correction(v, z, S, P, gamma, hdiag, W, b, nb, nlev, tau=3.0, round_act=None, static=None):
     """The learned stage after z = M(v).  Returns (z_new, accepted)."""
     rp = v - S @ z
     c = gamma * (P.T @ rp)
     s = float(np.sqrt(np.mean(c * c)))
     x = c / s if s > 0.0 else np.zeros_like(c)
-    y, _ = forward(x, W, b, nb, nlev, round_act)
+    y, _ = forward(x, W, b, nb, nlev, round_act, static=static)
     if not np.all(np.isfinite(y)):
         return z, False
     d = s * (P @ (y / hdiag))
@@ -207,7 +231,7 @@ def learned_correction(v, z, S, P, gamma, hdiag, W, b, nb, nlev, tau=3.0, round_
 def identity_weights(channels=16):
     """Weights for which the network is exactly the identity: channel 0 carries relu(x), channel 1
     relu(-x), the last layer returns their difference (centre tap, dk = 0, zero biases)."""
-    W = [np.zeros((channels, 1, NT)), np.zeros((channels, channels, NT)), np.zeros((1, channels, NT))]
+    W = [np.zeros((channels, NIN, NT)), np.zeros((channels, channels, NT)), np.zeros((1, channels, NT))]
     centre = 0 * NV + 2
     W[0][0, 0, centre], W[0][1, 0, centre] = 1.0, -1.0
     W[1][0, 0, centre], W[1][1, 1, centre] = 1.0, 1.0
@@ -215,12 +239,12 @@ def identity_weights(channels=16):
     return W, [np.zeros(channels), np.zeros(channels), np.zeros(1)]
 
 
-def energy_loss_and_grads(x, rhat, W, b, nb, nlev, G, hdiag):
+def energy_loss_and_grads(x, rhat, W, b, nb, nlev, G, hdiag, static=None):
     """Energy loss of one pair and its gradients (dW list, db list).
 
     q = N(x) / H_KK,  loss = (q^T G q - 2 q^T rhat) * mean(H_KK) / ncell  (the scale makes the loss
     dimensionless and of order one; averaging over a batch is the caller's)."""
-    y, acts = forward(x, W, b, nb, nlev)
+    y, acts = forward(x, W, b, nb, nlev, static=static)
     n = y.shape[0]
     scale = float(np.mean(hdiag)) / n
     q = y / hdiag

@@ -172,7 +172,7 @@ void free_all(hyb_ctx *c) {
     dfree(L.est), dfree(L.parent), dfree(L.children), dfree(L.H), dfree(L.Hf);
     dfree(L.zf), dfree(L.zff), dfree(L.b), dfree(L.x), dfree(L.y), dfree(L.r), dfree(L.w);
   }
-  dfree(c->dz_d), dfree(c->corners_d), dfree(c->radius_d), dfree(c->A), dfree(c->LU), dfree(c->kv), dfree(c->Scell), dfree(c->bcell);
+  dfree(c->dz_d), dfree(c->corners_d), dfree(c->radius_d), dfree(c->vol), dfree(c->A), dfree(c->LU), dfree(c->kv), dfree(c->Scell), dfree(c->bcell);
   dfree(c->S), dfree(c->Sf), dfree(c->m2l), dfree(c->gamma), dfree(c->gammaf), dfree(c->zfac), dfree(c->zfacf);
   dfree(c->tIn), dfree(c->tA), dfree(c->tB), dfree(c->tR), dfree(c->t64);
   dfree(c->V), dfree(c->Z), dfree(c->partial), dfree(c->hdev);
@@ -402,8 +402,9 @@ int hyb_assemble_local(hyb_ctx *c, const double *theta_w, const double *exner_ha
     return HYB_OK;
   }
   if ((rc = dalloc(c, &c->A, (size_t)49 * c->ncell)) || (rc = dalloc(c, &c->kv, (size_t)6 * c->ncell)) ||
-      (rc = dalloc(c, &c->m2l, (size_t)c->ntrace)))
+      (rc = dalloc(c, &c->m2l, (size_t)c->ntrace)) || (rc = dalloc(c, &c->vol, (size_t)c->ncell)))
     return rc;
+  c->nn.st_ready = false;  // the network's static inputs follow the cell volumes
   // the lumped velocity mass (Sec. 2.3) is taken from the cell matrices without the Coriolis term,
   // which is added afterwards on the sphere
   if (c->geom == HYB_GEOM_SHELL) {

@@ -24,12 +24,13 @@ __global__ void k_assemble_box(int ncell, int ncol, double dx, double dy, const 
                                const double *__restrict__ thw, const double *__restrict__ piw,
                                const double *__restrict__ pic, double dt, double tu, double tr,
                                double tt, double cp, double kappa, double *__restrict__ A,
-                               double *__restrict__ kv) {
+                               double *__restrict__ kv, double *__restrict__ volc) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncell) return;
   int k = c / ncol, col = c - k * ncol;
   double hx = dx, hy = dy, hz = dz[k];
   double vol = hx * hy * hz;
+  volc[c] = vol;
   double thB = thw[(size_t)k * ncol + col], thT = thw[(size_t)(k + 1) * ncol + col];
   double piB = piw[(size_t)k * ncol + col], piT = piw[(size_t)(k + 1) * ncol + col];
   double a[49];
@@ -106,7 +107,7 @@ __global__ void k_assemble_shell(int ncell, int ncol, const double *__restrict__
                                  const double *__restrict__ radius, const double *__restrict__ thw,
                                  const double *__restrict__ piw, const double *__restrict__ pic, double dt,
                                  double tu, double tr, double tt, double cp, double kappa, double two_omega,
-                                 double *__restrict__ A, double *__restrict__ kv) {
+                                 double *__restrict__ A, double *__restrict__ kv, double *__restrict__ volc) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncell) return;
   int k = c / ncol, col = c - k * ncol;
@@ -218,6 +219,7 @@ __global__ void k_assemble_shell(int ncell, int ncol, const double *__restrict__
   a[48] = (1.0 - kappa) / kappa * detc / pic[c];
 #pragma unroll
   for (int i = 0; i < 49; ++i) A[at(i, ncell, c)] = a[i];
+  volc[c] = vol;
 }
 
 // In-register LU (no pivoting) of a 7x7 matrix: the velocity block is symmetric positive
@@ -572,7 +574,7 @@ hipError_t launch_assemble_box(hyb_ctx *c, const double *thw, const double *piw,
   double kappa = p.rd / p.cp;
   hipLaunchKernelGGL(k_assemble_box, dim3(nblk(c->ncell)), dim3(kBlock), 0, c->stream, c->ncell, c->ncol,
                      c->dx, c->dy, c->dz_d, thw, piw, pic, p.dt, p.tau_u, p.tau_rho, p.tau_theta, p.cp, kappa,
-                     c->A, c->kv);
+                     c->A, c->kv, c->vol);
   return hipGetLastError();
 }
 
@@ -582,7 +584,7 @@ hipError_t launch_assemble_shell(hyb_ctx *c, const double *thw, const double *pi
   double kappa = p.rd / p.cp;
   hipLaunchKernelGGL(k_assemble_shell, dim3(nblk(c->ncell, 64)), dim3(64), 0, c->stream, c->ncell, c->ncol,
                      c->corners_d, c->radius_d, thw, piw, pic, p.dt, p.tau_u, p.tau_rho, p.tau_theta, p.cp, kappa,
-                     with_coriolis ? 2.0 * p.omega_rot : 0.0, c->A, c->kv);
+                     with_coriolis ? 2.0 * p.omega_rot : 0.0, c->A, c->kv, c->vol);
   return hipGetLastError();
 }
 

@@ -46,6 +46,10 @@ __host__ __device__ __forceinline__ size_t s_idx(size_t F, int j) {
 __host__ __device__ __forceinline__ size_t s_entries(size_t ntr) { return 11 * ((ntr + kSTile - 1) / kSTile) * kSTile; }
 
 constexpr int kNNChannels = 16;
+// network input channels: the normalised coarse residual, then two static fields of the mesh,
+// log(h / dz) (h = sqrt(|K| / dz), the cell's horizontal size) and the cell-centre height over the
+// height of the lid
+constexpr int kNNInputs = 3;
 
 // Learned coarse-correction network state (device buffers).
 struct NNState {
@@ -54,6 +58,9 @@ struct NNState {
   int32_t *isbf = nullptr;                                        // parameter -> BF16 index (-1: bias)
   int32_t *nb9 = nullptr;                                         // [9][ncol] 3x3 horizontal neighbourhood (-1: none)
   int32_t *rv9 = nullptr;                                         // [9][ncol] readers of a column: col * 9 + tap
+  float *st = nullptr;                                            // [2][ncell] static input channels
+  double *layer = nullptr;                                        // [2][nlev] log(dz), centre height / lid
+  bool st_ready = false;
   float *a1 = nullptr, *a2 = nullptr, *y = nullptr;               // activations [nsamp][C][ncell]
   float *d1 = nullptr, *d2 = nullptr, *dy = nullptr;              // their gradients
   float *part = nullptr, *tmpg = nullptr, *lpart = nullptr;       // reduction scratch
@@ -111,6 +118,7 @@ struct hyb_ctx {
   double *A = nullptr;      // [49][ncell] A_K row-major (i*7+j)
   double *LU = nullptr;     // [49][ncell] LU factors of A_K (unit lower, no pivoting)
   double *kv = nullptr;     // [6][ncell] diagonal of K_K
+  double *vol = nullptr;    // [ncell] cell volumes (the Gauss rule of the mass forms)
   double *Scell = nullptr;  // [36][ncell] S_K = [A_K^-1]_uu diag(k)  (setup only)
   double *bcell = nullptr;  // [6][ncell] [A_K^-1 R_K]_u
   // trace operator

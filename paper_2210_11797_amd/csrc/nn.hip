@@ -29,11 +29,14 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
   return (uint16_t)((u + 0x7FFFu + lsb) >> 16);
 }
 
-// y[s][co][cell] = bias[co] + sum_{ci,t} W[co][ci][t] x[s][ci][k+dk][nb[h][col]]   (RELU: max(.,0))
-template <int CI, int CO, bool RELU>
+// y[s][co][cell] = bias[co] + sum_{ci,t} W[co][ci][t] x[s][ci][k+dk][nb[h][col]]   (RELU: max(.,0));
+// the last CS of the CI input channels are static fields xst[CS][cell], the same for every sample
+template <int CI, int CO, bool RELU, int CS = 0>
 __global__ void __launch_bounds__(kBlock) k_conv_fwd(const float *__restrict__ x, const uint16_t *__restrict__ wb,
                                                      const float *__restrict__ bias, float *__restrict__ y, int nlev,
-                                                     int ncol, int nsamp, const int32_t *__restrict__ nb9) {
+                                                     int ncol, int nsamp, const int32_t *__restrict__ nb9,
+                                                     const float *__restrict__ xst = nullptr) {
+  constexpr int CD = CI - CS;  // per-sample channels
   __shared__ float w[CO * CI * NTAP];
   for (int i = threadIdx.x; i < CO * CI * NTAP; i += blockDim.x) w[i] = bf2f(wb[i]);
   __syncthreads();
@@ -46,7 +49,7 @@ __global__ void __launch_bounds__(kBlock) k_conv_fwd(const float *__restrict__ x
   float acc[CO];
 #pragma unroll
   for (int co = 0; co < CO; ++co) acc[co] = bias[co];
-  const float *xs = x + (size_t)s * CI * n;
+  const float *xs = x + (size_t)s * CD * n;
   for (int h = 0; h < NHT; ++h) {
     const int c2 = nb9[(size_t)h * ncol + col];
     if (c2 < 0) continue;  // no corner neighbour at a cube vertex: zero padding
@@ -57,7 +60,8 @@ __global__ void __launch_bounds__(kBlock) k_conv_fwd(const float *__restrict__ x
       const int t = h * NVT + v;
 #pragma unroll
       for (int ci = 0; ci < CI; ++ci) {
-        const float xv = xs[(size_t)ci * n + (size_t)kk * ncol + c2];
+        const float *src = ci < CD ? xs + (size_t)ci * n : xst + (size_t)(ci - CD) * n;
+        const float xv = src[(size_t)kk * ncol + c2];
 #pragma unroll
         for (int co = 0; co < CO; ++co) acc[co] += w[(co * CI + ci) * NTAP + t] * xv;
       }
@@ -119,11 +123,12 @@ __global__ void __launch_bounds__(kBlock) k_conv_bwd_data(const float *__restric
 // Per-workgroup partial weight gradients over a tile of cells:
 //   part[blk][co][ci][t] = sum_cells dy[co][cell] x[ci][k+dk][nb[h][col]],  part[blk][wsize+co] = sum dy[co]
 constexpr int kTile = 512;
-template <int CI, int CO>
+template <int CI, int CO, int CS = 0>
 __global__ void __launch_bounds__(kBlock) k_conv_bwd_weight(const float *__restrict__ dy, const float *__restrict__ x,
                                                             float *__restrict__ part, int nlev, int ncol, int nsamp,
-                                                            const int32_t *__restrict__ nb9) {
-  constexpr int WS = CO * CI * NTAP;
+                                                            const int32_t *__restrict__ nb9,
+                                                            const float *__restrict__ xst = nullptr) {
+  constexpr int WS = CO * CI * NTAP, CD = CI - CS;
   __shared__ float sdy[kTile][CO];
   __shared__ int scell[kTile];
   const size_t n = (size_t)nlev * ncol, total = n * nsamp;
@@ -153,7 +158,8 @@ __global__ void __launch_bounds__(kBlock) k_conv_bwd_weight(const float *__restr
       if (kk < 0 || kk >= nlev) continue;
       const int c2 = nb9[(size_t)h * ncol + col];
       if (c2 < 0) continue;
-      const float xv = x[((size_t)s * CI + ci) * n + (size_t)kk * ncol + c2];
+      const float xv = ci < CD ? x[((size_t)s * CD + ci) * n + (size_t)kk * ncol + c2]
+                               : xst[(size_t)(ci - CD) * n + (size_t)kk * ncol + c2];
 #pragma unroll
       for (int co = 0; co < CO; ++co) acc[co] += sdy[i][co] * xv;
     }
@@ -424,9 +430,11 @@ typedef short nn_bf16x4 __attribute__((ext_vector_type(4)));
 
 __global__ void __launch_bounds__(kBlock) k_inf_layer1(const float *__restrict__ x, const uint16_t *__restrict__ wb,
                                                       const float *__restrict__ bias, uint16_t *__restrict__ a1,
-                                                      int nlev, int ncol, const int32_t *__restrict__ nb9) {
-  __shared__ float w[C1 * NTAP];
-  for (int i = threadIdx.x; i < C1 * NTAP; i += blockDim.x) w[i] = bf2f(wb[i]);
+                                                      int nlev, int ncol, const int32_t *__restrict__ nb9,
+                                                      const float *__restrict__ xst) {
+  constexpr int CIN = kNNInputs;  // x, then the static fields xst[CIN - 1][cell]
+  __shared__ float w[C1 * CIN * NTAP];
+  for (int i = threadIdx.x; i < C1 * CIN * NTAP; i += blockDim.x) w[i] = bf2f(wb[i]);
   __syncthreads();
   const int cell = blockIdx.x * blockDim.x + threadIdx.x;
   if (cell >= nlev * ncol) return;
@@ -441,9 +449,15 @@ __global__ void __launch_bounds__(kBlock) k_inf_layer1(const float *__restrict__
     for (int v = 0; v < NVT; ++v) {
       const int kk = k + v - 2;
       if (kk < 0 || kk >= nlev) continue;
-      const float xv = x[(size_t)kk * ncol + c2];
+      const size_t at2 = (size_t)kk * ncol + c2;
+      float xv[CIN];
+      xv[0] = x[at2];
 #pragma unroll
-      for (int co = 0; co < C1; ++co) acc[co] += w[co * NTAP + h * NVT + v] * xv;
+      for (int ci = 1; ci < CIN; ++ci) xv[ci] = xst[(size_t)(ci - 1) * nlev * ncol + at2];
+#pragma unroll
+      for (int co = 0; co < C1; ++co)
+#pragma unroll
+        for (int ci = 0; ci < CIN; ++ci) acc[co] += w[(co * CIN + ci) * NTAP + h * NVT + v] * xv[ci];
     }
   }
 #pragma unroll
@@ -540,6 +554,18 @@ __global__ void __launch_bounds__(kBlock) k_inf_layer3(const uint16_t *__restric
   y[cell] = acc;
 }
 
+// Static input channels of the network: st[0] = log(h / dz) with h = sqrt(|K| / dz) the cell's
+// horizontal size (0.5 log |K| - 1.5 log dz), st[1] = height of the cell centre over the lid's;
+// layer[0][k] = log dz_k, layer[1][k] = centre height / lid height
+__global__ void k_static_inputs(int ncell, int ncol, const double *__restrict__ vol, const double *__restrict__ layer,
+                                int nlev, float *__restrict__ st) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  const int k = c / ncol;
+  st[c] = (float)(0.5 * log(vol[c]) - 1.5 * layer[k]);
+  st[(size_t)ncell + c] = (float)layer[nlev + k];
+}
+
 __global__ void k_zero_scal(double *p, int n) {
   if (threadIdx.x < n) p[threadIdx.x] = 0.0;
 }
@@ -558,7 +584,8 @@ hipError_t launch_restrict_cells(hyb_ctx *c, const double *r, double *cells, int
 // W3 [1][C][45], b3 [1].  The BF16 copy holds W1, W2, W3 back to back.
 // ---------------------------------------------------------------------------------------------
 static constexpr int C = kNNChannels;
-static constexpr int W1N = C * 1 * NTAP, W2N = C * C * NTAP, W3N = 1 * C * NTAP;
+static constexpr int CIN = kNNInputs;
+static constexpr int W1N = C * CIN * NTAP, W2N = C * C * NTAP, W3N = 1 * C * NTAP;
 static constexpr int OFF_W1 = 0, OFF_B1 = W1N, OFF_W2 = OFF_B1 + C, OFF_B2 = OFF_W2 + W2N, OFF_W3 = OFF_B2 + C,
                      OFF_B3 = OFF_W3 + W3N, NPARAM = OFF_B3 + 1;
 
@@ -671,6 +698,36 @@ static hipError_t ensure_acts(hyb_ctx *c, int nsamp) {
   return hipSuccess;
 }
 
+// The static input channels from the cell volumes of the last assembly and the layer thicknesses.
+static hipError_t nn_static(hyb_ctx *c) {
+  NNState &s = c->nn;
+  if (s.st_ready) return hipSuccess;
+  if (!c->vol || !c->assembled) return hipErrorInvalidValue;  // the network needs the assembled mesh
+  hipError_t e;
+  const size_t n = (size_t)c->ncell;
+  if (!s.st) {
+    if ((e = hipMalloc((void **)&s.st, 2 * n * 4)) || (e = hipMalloc((void **)&s.layer, 2 * (size_t)c->nlev * 8)))
+      return e;
+    c->bytes += 2 * n * 4 + 2 * (size_t)c->nlev * 8;
+  }
+  std::vector<double> layer(2 * (size_t)c->nlev);
+  double top = 0.0;
+  for (double d : c->dz) top += d;
+  double z = 0.0;
+  for (int k = 0; k < c->nlev; ++k) {
+    layer[k] = std::log(c->dz[k]);
+    layer[c->nlev + k] = (z + 0.5 * c->dz[k]) / top;
+    z += c->dz[k];
+  }
+  if ((e = hipMemcpyAsync(s.layer, layer.data(), layer.size() * 8, hipMemcpyHostToDevice, c->stream))) return e;
+  hipLaunchKernelGGL(k_static_inputs, dim3(nblk(n)), dim3(kBlock), 0, c->stream, c->ncell, c->ncol, c->vol, s.layer,
+                     c->nlev, s.st);
+  if ((e = hipGetLastError())) return e;
+  if ((e = hipStreamSynchronize(c->stream))) return e;  // the host array goes out of scope
+  s.st_ready = true;
+  return hipSuccess;
+}
+
 // Forward pass of nsamp fields x [nsamp][ncell] -> out [nsamp][ncell] (activations kept for backward).
 hipError_t nn_forward(hyb_ctx *c, const float *x, float *out, int nsamp) {
   NNState &s = c->nn;
@@ -679,7 +736,9 @@ hipError_t nn_forward(hyb_ctx *c, const float *x, float *out, int nsamp) {
   size_t n = (size_t)c->ncell * nsamp;
   dim3 g(nblk(n)), b(kBlock);
   int L = c->nlev, nc = c->ncol;
-  hipLaunchKernelGGL((k_conv_fwd<1, C, true>), g, b, 0, c->stream, x, s.wb, s.w + OFF_B1, s.a1, L, nc, nsamp, s.nb9);
+  if ((e = nn_static(c))) return e;
+  hipLaunchKernelGGL((k_conv_fwd<CIN, C, true, CIN - 1>), g, b, 0, c->stream, x, s.wb, s.w + OFF_B1, s.a1, L, nc,
+                     nsamp, s.nb9, (const float *)s.st);
   hipLaunchKernelGGL((k_conv_fwd<C, C, true>), g, b, 0, c->stream, s.a1, s.wb + W1N, s.w + OFF_B2, s.a2, L, nc, nsamp,
                      s.nb9);
   hipLaunchKernelGGL((k_conv_fwd<C, 1, false>), g, b, 0, c->stream, s.a2, s.wb + W1N + W2N, s.w + OFF_B3, out, L, nc,
@@ -697,9 +756,10 @@ static hipError_t nn_forward_inference(hyb_ctx *c, const float *x, float *out) {
     if ((e = hipMalloc((void **)&s.a1h, n * C * 2)) || (e = hipMalloc((void **)&s.a2h, n * C * 2))) return e;
     c->bytes += 2 * n * C * 2;
   }
+  if ((e = nn_static(c))) return e;
   const int L = c->nlev, nc = c->ncol;
   hipLaunchKernelGGL(k_inf_layer1, dim3(nblk(n)), dim3(kBlock), 0, c->stream, x, s.wb, s.w + OFF_B1, s.a1h, L, nc,
-                     s.nb9);
+                     s.nb9, (const float *)s.st);
   const size_t waves = (n + 16 * kInfTiles - 1) / (16 * kInfTiles);
   hipLaunchKernelGGL(k_inf_layer2_mfma, dim3(nblk(waves, kBlock / 64)), dim3(kBlock), 0, c->stream, s.a1h, s.wb + W1N,
                      s.w + OFF_B2, s.a2h, L, nc, s.nb9);
@@ -708,14 +768,14 @@ static hipError_t nn_forward_inference(hyb_ctx *c, const float *x, float *out) {
   return hipGetLastError();
 }
 
-template <int CI, int CO>
+template <int CI, int CO, int CS = 0>
 static hipError_t weight_grad(hyb_ctx *c, const float *dy, const float *x, int nsamp, float *grad_w, float *grad_b) {
   NNState &s = c->nn;
   size_t n = (size_t)c->ncell * nsamp;
   int nparts = (int)((n + kTile - 1) / kTile);
   constexpr int WS = CO * CI * NTAP;
-  hipLaunchKernelGGL((k_conv_bwd_weight<CI, CO>), dim3(nparts), dim3(kBlock), 0, c->stream, dy, x, s.part, c->nlev,
-                     c->ncol, nsamp, s.nb9);
+  hipLaunchKernelGGL((k_conv_bwd_weight<CI, CO, CS>), dim3(nparts), dim3(kBlock), 0, c->stream, dy, x, s.part,
+                     c->nlev, c->ncol, nsamp, s.nb9, (const float *)s.st);
   hipError_t e = hipGetLastError();
   if (e) return e;
   // sum: weights then biases (contiguous WS + CO per part; the grad layout keeps W and b apart)
@@ -753,8 +813,8 @@ static hipError_t nn_backward(hyb_ctx *c, const float *x, int nsamp) {
   hipLaunchKernelGGL((k_conv_bwd_data<C, C, true>), g, b, 0, c->stream, s.d2, s.wb + W1N, s.a1, s.d1, L, nc, nsamp,
                      s.rv9);
   if ((e = hipGetLastError())) return e;
-  // layer 1 (input x)
-  return weight_grad<1, C>(c, s.d1, x, nsamp, s.g + OFF_W1, s.g + OFF_B1);
+  // layer 1 (input x and the static fields)
+  return weight_grad<CIN, C, CIN - 1>(c, s.d1, x, nsamp, s.g + OFF_W1, s.g + OFF_B1);
 }
 
 // Loss (mean squared error over all cells and samples) and gradients into s.g.
@@ -913,6 +973,9 @@ void nn_free(hyb_ctx *c) {
   if (s.isbf) (void)hipFree(s.isbf), s.isbf = nullptr;
   if (s.nb9) (void)hipFree(s.nb9), s.nb9 = nullptr;
   if (s.rv9) (void)hipFree(s.rv9), s.rv9 = nullptr;
+  if (s.st) (void)hipFree(s.st), s.st = nullptr;
+  if (s.layer) (void)hipFree(s.layer), s.layer = nullptr;
+  s.st_ready = false;
   if (s.scal) (void)hipFree(s.scal), s.scal = nullptr;
   if (s.a1h) (void)hipFree(s.a1h), s.a1h = nullptr;
   if (s.a2h) (void)hipFree(s.a2h), s.a2h = nullptr;

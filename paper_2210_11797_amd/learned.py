@@ -18,12 +18,14 @@ import json
 import numpy as np
 
 NTAP = 45
+NIN = 3  # input channels: c / s, then the static fields log(h / dz) and z / z_top
 
 
 def layout(channels=16):
     """(name, shape) of the parameter vector blocks, in order."""
     c = channels
-    return [("W1", (c, 1, NTAP)), ("b1", (c,)), ("W2", (c, c, NTAP)), ("b2", (c,)), ("W3", (1, c, NTAP)), ("b3", (1,))]
+    return [("W1", (c, NIN, NTAP)), ("b1", (c,)), ("W2", (c, c, NTAP)), ("b2", (c,)), ("W3", (1, c, NTAP)),
+            ("b3", (1,))]
 
 
 def pack(W, b):
@@ -43,7 +45,7 @@ def init_params(channels=16, seed=0):
     """He-scaled random weights, zero biases, a small last layer (FP32 vector)."""
     rng = np.random.default_rng(seed)
     W, b = [], []
-    for co, ci in ((channels, 1), (channels, channels), (1, channels)):
+    for co, ci in ((channels, NIN), (channels, channels), (1, channels)):
         W.append(rng.standard_normal((co, ci, NTAP)) * np.sqrt(2.0 / (ci * NTAP)))
         b.append(np.zeros(co))
     W[2] *= 0.1

@@ -46,3 +46,19 @@ def rel_max(a, ref):
 def rel_norm(a, ref):
     ref = np.asarray(ref)
     return float(np.linalg.norm(np.asarray(a) - ref) / max(np.linalg.norm(ref), 1e-300))
+
+
+def static_for(prob, orc=None):
+    """The network's static input channels for a synthetic problem, computed by the oracle (cell
+    volumes of its own cell matrices on the sphere, dx dy dz on the box)."""
+    from oracle import nn as onn
+
+    if getattr(prob, "geom", "box") == "shell":
+        if orc is None:
+            from oracle.problem import OracleProblem
+
+            orc = OracleProblem(prob, with_mixed=False, with_precond=False)
+        vol = orc.loc["m3"]
+    else:
+        vol = prob.dx * prob.dy * np.repeat(np.diff(prob.z), prob.ncol)
+    return onn.static_inputs(vol, prob.z, prob.ncol)

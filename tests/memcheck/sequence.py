@@ -214,8 +214,9 @@ def network_sequence(lib):
     wc = np.empty(w.size, np.float32)
     c.call("hyb_nn_get_weights", P(wc), wc.size)
     W, bias = learned.unpack(wc)
+    st = onn.static_inputs(prob.dx * prob.dy * np.repeat(np.diff(prob.z), prob.ncol), prob.z, prob.ncol)
     ref = onn.forward(x1[0].astype(np.float64), [onn.bf16_round(a) for a in W], bias,
-                      onn.neighbour_table(prob.nx, prob.ny), prob.nlev)[0]
+                      onn.neighbour_table(prob.nx, prob.ny), prob.nlev, static=st)[0]
     err = float(np.abs(y1[0] - ref).max() / np.abs(ref).max())
     check(err <= 1e-5, f"forward after training matches the oracle's formula: {err:.1e}")
     _, _, b = c.rhs(2)
@@ -224,8 +225,8 @@ def network_sequence(lib):
         rc, info, lam = c.solve(b, 1e-8, maxit=40)
         check(rc >= 0, f"solve with the learned stage (precision {prec}): {info.iters} iterations")
     wo = w.copy()
-    wo[: 16 * 45] = np.repeat(np.where(np.arange(16) % 2 == 0, 1e30, -1e30), 45)
-    wo[16 * 45 + 16: 16 * 45 + 16 + 16 * 16 * 45] = 1e30
+    wo[: 16 * learned.NIN * 45] = np.repeat(np.where(np.arange(16) % 2 == 0, 1e30, -1e30), learned.NIN * 45)
+    wo[16 * learned.NIN * 45 + 16: 16 * learned.NIN * 45 + 16 + 16 * 16 * 45] = 1e30
     c.call("hyb_nn_set_weights", P(wo), wo.size)
     c.set(precision=N.PREC_FP64)
     rc, info, lam = c.solve(b, 1e-8)
@@ -334,7 +335,7 @@ def sphere_sequence(lib):
     # and gradients against the oracle, a training step, the solve with the stage
     rng = np.random.default_rng(1)
     w = learned.init_params(16, seed=3)
-    w[16 * 45 : 16 * 45 + 16] = rng.standard_normal(16) * 0.1
+    w[16 * learned.NIN * 45 : 16 * learned.NIN * 45 + 16] = rng.standard_normal(16) * 0.1
     c.call("hyb_nn_set_weights", P(w), w.size)
     nb = onn.neighbour_table_from_tables(prob.col_edge, prob.edge_col, prob.edge_lf)
     W, bias = learned.unpack(w)
@@ -343,11 +344,12 @@ def sphere_sequence(lib):
     t2 = rng.standard_normal((2, c.ncell)).astype(np.float32)
     y2 = np.empty((2, c.ncell), np.float32)
     c.call("hyb_nn_forward", P(x2), P(y2), 2)
-    yref = np.stack([onn.forward(x2[i].astype(np.float64), Wr, bias, nb, prob.nlev)[0] for i in range(2)])
+    st = onn.static_inputs(o.loc["m3"], prob.z, prob.ncol)
+    yref = np.stack([onn.forward(x2[i].astype(np.float64), Wr, bias, nb, prob.nlev, static=st)[0] for i in range(2)])
     check(np.abs(y2 - yref).max() <= 1e-5 * np.abs(yref).max(), "sphere: network forward against the oracle")
     loss, g = ctypes.c_float(), np.empty(w.size, np.float32)
     c.call("hyb_nn_loss_grad", P(x2), P(t2), 2, ctypes.byref(loss), P(g))
-    refs = [onn.loss_and_grads(x2[i].astype(np.float64), t2[i].astype(np.float64), Wr, bias, nb, prob.nlev)
+    refs = [onn.loss_and_grads(x2[i].astype(np.float64), t2[i].astype(np.float64), Wr, bias, nb, prob.nlev, static=st)
             for i in range(2)]
     gref = learned.pack([0.5 * (refs[0][1][j] + refs[1][1][j]) for j in range(3)],
                         [0.5 * (refs[0][2][j] + refs[1][2][j]) for j in range(3)]).astype(np.float64)

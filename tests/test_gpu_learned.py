@@ -4,7 +4,7 @@ restriction, training, the solve with the stage, its fallback, and what it gains
 import numpy as np
 import pytest
 
-from gpu_common import dev, host, make_solver, rel_max, say
+from gpu_common import dev, host, make_solver, rel_max, say, static_for
 from oracle import nn as onn
 from oracle.problem import OracleProblem, cells_from_soa
 from paper_2210_11797_amd import learned
@@ -29,7 +29,7 @@ def test_network_forward_and_gradients_match_oracle(small):
     prob, s = small
     rng = np.random.default_rng(0)
     vec = learned.init_params(16, seed=1)
-    vec[16 * 45 : 16 * 45 + 16] = rng.standard_normal(16) * 0.1  # b1
+    vec[16 * learned.NIN * 45 : 16 * learned.NIN * 45 + 16] = rng.standard_normal(16) * 0.1  # b1
     s.nn_set_weights(vec)
     x = rng.standard_normal((2, prob.ncell)).astype(np.float32)
     t = rng.standard_normal((2, prob.ncell)).astype(np.float32)
@@ -40,11 +40,12 @@ def test_network_forward_and_gradients_match_oracle(small):
 
     y = torch.empty((2, prob.ncell), dtype=torch.float32, device="cuda")
     s.nn_forward(_f32(x), y, 2)
-    yref = np.stack([onn.forward(x[i].astype(np.float64), Wr, b, nb, prob.nlev)[0] for i in range(2)])
+    st = static_for(prob)
+    yref = np.stack([onn.forward(x[i].astype(np.float64), Wr, b, nb, prob.nlev, static=st)[0] for i in range(2)])
     err_y = rel_max(host(y), yref)
     loss, g = s.nn_loss_grad(_f32(x), _f32(t), 2)
     # oracle: mean over both samples = average of the per-sample means
-    refs = [onn.loss_and_grads(x[i].astype(np.float64), t[i].astype(np.float64), Wr, b, nb, prob.nlev)
+    refs = [onn.loss_and_grads(x[i].astype(np.float64), t[i].astype(np.float64), Wr, b, nb, prob.nlev, static=st)
             for i in range(2)]
     lref = 0.5 * (refs[0][0] + refs[1][0])
     gW = [0.5 * (refs[0][1][j] + refs[1][1][j]) for j in range(3)]
@@ -101,7 +102,7 @@ def test_energy_loss_gradients_match_oracle(small):
     hd = orc.H.diagonal().copy()
     rng = np.random.default_rng(13)
     vec = learned.init_params(16, seed=14)
-    vec[16 * 45 : 16 * 45 + 16] = rng.standard_normal(16) * 0.1
+    vec[16 * learned.NIN * 45 : 16 * learned.NIN * 45 + 16] = rng.standard_normal(16) * 0.1
     vec[-1] = 0.3
     s.nn_set_weights(vec)
     x = rng.standard_normal((2, prob.ncell)).astype(np.float32)
@@ -110,7 +111,9 @@ def test_energy_loss_gradients_match_oracle(small):
     W, b = learned.unpack(vec)
     Wr = [onn.bf16_round(w) for w in W]
     nb = onn.neighbour_table(prob.nx, prob.ny)
-    refs = [onn.energy_loss_and_grads(x[i].astype(np.float64), rhat[i], Wr, b, nb, prob.nlev, G, hd) for i in range(2)]
+    st = static_for(prob)
+    refs = [onn.energy_loss_and_grads(x[i].astype(np.float64), rhat[i], Wr, b, nb, prob.nlev, G, hd, static=st)
+            for i in range(2)]
     lref = 0.5 * (refs[0][0] + refs[1][0])
     gref = learned.pack([0.5 * (refs[0][1][j] + refs[1][1][j]) for j in range(3)],
                         [0.5 * (refs[0][2][j] + refs[1][2][j]) for j in range(3)]).astype(np.float64)
@@ -131,7 +134,8 @@ def _stage_reference(prob, orc, vec, v):
     Wr = [onn.bf16_round(w) for w in W]
     z = orc.pc(v)
     return onn.learned_correction(v, z, orc.pc.S, orc.pc.P, orc.pc.gamma, orc.H.diagonal(), Wr, b,
-                                  onn.neighbour_table(prob.nx, prob.ny), prob.nlev, round_act=onn.bf16_round)
+                                  onn.neighbour_table(prob.nx, prob.ny), prob.nlev, round_act=onn.bf16_round,
+                                  static=static_for(prob))
 
 
 @pytest.mark.gpu
@@ -223,8 +227,8 @@ def test_learned_stage_falls_back_on_overflow(small):
     # the input's 3x3x5 box sum is nonzero; layer 2 (all 1e30) then overflows to inf, and layer 3
     # (mixed signs) gives inf or NaN.  (All-positive weights would give an exactly zero, finite
     # output for inputs whose box sums are all negative.)
-    vec[: 16 * 45] = np.repeat(np.where(np.arange(16) % 2 == 0, 1e30, -1e30), 45)
-    vec[16 * 45 + 16 : 16 * 45 + 16 + 16 * 16 * 45] = 1e30
+    vec[: 16 * learned.NIN * 45] = np.repeat(np.where(np.arange(16) % 2 == 0, 1e30, -1e30), learned.NIN * 45)
+    vec[16 * learned.NIN * 45 + 16 : 16 * learned.NIN * 45 + 16 + 16 * 16 * 45] = 1e30
     s.nn_set_weights(vec)
     p = s.params
     p.learned = 1

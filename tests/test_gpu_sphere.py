@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 import scipy.sparse.linalg as spla
 
-from gpu_common import dev, host, make_solver, rel_max, rel_norm, say
+from gpu_common import dev, host, make_solver, rel_max, rel_norm, say, static_for
 from oracle.hybrid import cell_recover, cell_rhs, cell_trace_operator
 from oracle.local import shell_local_matrices
 from oracle.mesh import TableMesh
@@ -274,7 +274,7 @@ def test_sphere_network_and_stage_match_oracle():
     assert (nb < 0).sum() == 24
     rng = np.random.default_rng(0)
     vec = learned.init_params(16, seed=1)
-    vec[16 * 45 : 16 * 45 + 16] = rng.standard_normal(16) * 0.1
+    vec[16 * learned.NIN * 45 : 16 * learned.NIN * 45 + 16] = rng.standard_normal(16) * 0.1
     s.nn_set_weights(vec)
     x = rng.standard_normal((2, prob.ncell)).astype(np.float32)
     t = rng.standard_normal((2, prob.ncell)).astype(np.float32)
@@ -283,10 +283,11 @@ def test_sphere_network_and_stage_match_oracle():
     f32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()  # noqa: E731
     y = torch.empty((2, prob.ncell), dtype=torch.float32, device="cuda")
     s.nn_forward(f32(x), y, 2)
-    yref = np.stack([onn.forward(x[i].astype(np.float64), Wr, b, nb, prob.nlev)[0] for i in range(2)])
+    st = static_for(prob, orc)
+    yref = np.stack([onn.forward(x[i].astype(np.float64), Wr, b, nb, prob.nlev, static=st)[0] for i in range(2)])
     err_y = rel_max(host(y), yref)
     loss, g = s.nn_loss_grad(f32(x), f32(t), 2)
-    refs = [onn.loss_and_grads(x[i].astype(np.float64), t[i].astype(np.float64), Wr, b, nb, prob.nlev)
+    refs = [onn.loss_and_grads(x[i].astype(np.float64), t[i].astype(np.float64), Wr, b, nb, prob.nlev, static=st)
             for i in range(2)]
     gref = learned.pack([0.5 * (refs[0][1][j] + refs[1][1][j]) for j in range(3)],
                         [0.5 * (refs[0][2][j] + refs[1][2][j]) for j in range(3)]).astype(np.float64)
@@ -302,7 +303,7 @@ def test_sphere_network_and_stage_match_oracle():
         for trial in range(2):
             v = rng.standard_normal(orc.mesh.ntrace)
             zref, acc = onn.learned_correction(v, orc.pc(v), orc.pc.S, orc.pc.P, orc.pc.gamma, orc.H.diagonal(), Wvr,
-                                               bv, nb, prob.nlev, round_act=onn.bf16_round)
+                                               bv, nb, prob.nlev, round_act=onn.bf16_round, static=st)
             z = torch.empty(s.ntrace, dtype=torch.float64, device="cuda")
             p.learned = 1
             s.set_params(p)

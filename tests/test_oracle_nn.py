@@ -138,7 +138,7 @@ def test_stage_rejects_useless_and_harmful_corrections():
     S, P, gam = orc.hyb.S, orc.pc.P, orc.pc.gamma
     v = np.random.default_rng(7).standard_normal(S.shape[0])
     z = orc.pc(v)
-    W0 = [np.zeros((16, 1, nn.NT)), np.zeros((16, 16, nn.NT)), np.zeros((1, 16, nn.NT))]
+    W0 = [np.zeros((16, nn.NIN, nn.NT)), np.zeros((16, 16, nn.NT)), np.zeros((1, 16, nn.NT))]
     b0 = [np.zeros(16), np.zeros(16), np.zeros(1)]
     zn, acc = nn.learned_correction(v, z, S, P, gam, hd, W0, b0, nb, prob.nlev)
     assert np.array_equal(zn, z)  # a zero correction leaves z as it is, accepted or not
@@ -283,3 +283,38 @@ def test_gradients_with_missing_neighbours():
         xm[i] -= h
         fd = (nn.loss_and_grads(xp, t, W, b, nb, nlev)[0] - nn.loss_and_grads(xm, t, W, b, nb, nlev)[0]) / (2 * h)
         assert abs(fd - dx[i]) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_static_inputs():
+    # log(h / dz) and the centre height over the lid's, from volumes and interface heights
+    z = np.array([0.0, 10.0, 40.0, 100.0])
+    ncol = 2
+    dz = np.repeat(np.diff(z), ncol)
+    vol = np.repeat([4e4, 9e4, 16e4], ncol) * dz  # h = 200, 300, 400
+    st = nn.static_inputs(vol, z, ncol)
+    np.testing.assert_allclose(st[0], np.log(np.repeat([200 / 10, 300 / 30, 400 / 60], ncol)), rtol=1e-14)
+    np.testing.assert_allclose(st[1], np.repeat([5 / 100, 25 / 100, 70 / 100], ncol), rtol=1e-14)
+
+
+def test_gradients_with_static_inputs():
+    # the static channels enter the first layer like the residual channel (finite differences)
+    nb, W, b, x, t = _setup()
+    nlev = 6
+    st = np.random.default_rng(9).standard_normal((2, x.shape[0]))
+    loss, dW, db, _ = nn.loss_and_grads(x, t, W, b, nb, nlev, static=st)
+    h = 1e-6
+    rng = np.random.default_rng(4)
+    for _ in range(6):
+        idx = (rng.integers(0, W[0].shape[0]), rng.integers(1, 3), rng.integers(0, nn.NT))
+        Wp = [w.copy() for w in W]
+        Wm = [w.copy() for w in W]
+        Wp[0][idx] += h
+        Wm[0][idx] -= h
+        fd = (nn.loss_and_grads(x, t, Wp, b, nb, nlev, static=st)[0]
+              - nn.loss_and_grads(x, t, Wm, b, nb, nlev, static=st)[0]) / (2 * h)
+        assert abs(fd - dW[0][idx]) <= 1e-6 * max(1.0, abs(fd))
+    # a network reading only a static channel through its centre tap is the identity on it
+    Wi, bi = nn.identity_weights(16)
+    Wi[0][:, [0, 1], :] = Wi[0][:, [1, 0], :]  # route static channel 1 instead of the residual
+    y, _ = nn.forward(x, Wi, bi, nb, nlev, static=st)
+    np.testing.assert_allclose(y, st[0], atol=1e-14)
