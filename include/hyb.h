@@ -89,7 +89,9 @@ typedef struct {
    right-handed seen from outside); radius (host [nlev + 1]) the radii of the layer interfaces.
    A cell is the image of the unit cube under x = r(zeta) p / |p|, r(zeta) = radius[k] +
    zeta (radius[k+1] - radius[k]), p the bilinear interpolation of the corners: the vertical is
-   radial, the side faces lie on great-circle planes.  dx, dy and dz are ignored. */
+   radial, the side faces lie on great-circle planes.  dx, dy and dz are ignored.  hyb_create returns
+   HYB_EINVAL for non-finite corners, radii that do not increase, order 1, or a column whose frame
+   turns the other way ((c1 - c0) x (c2 - c0) pointing inwards). */
 typedef struct {
   int32_t nlev;
   int32_t nlevels;           /* multigrid levels, >= 1 */

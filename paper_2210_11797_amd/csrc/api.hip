@@ -255,6 +255,18 @@ int hyb_create(const hyb_mesh *mesh, const hyb_params *params, void *stream, hyb
     geom_ok = mesh->corners && mesh->radius && mesh->order == 0 && mesh->radius[0] > 0;
     for (int k = 0; geom_ok && k < mesh->nlev; ++k) geom_ok = mesh->radius[k + 1] > mesh->radius[k];
     for (size_t i = 0; geom_ok && i < (size_t)12 * mesh->levels[0].ncol; ++i) geom_ok = std::isfinite(mesh->corners[i]);
+    // every column frame must turn the same way seen from outside (a positive cell Jacobian):
+    // (c1 - c0) x (c2 - c0) points outwards, along the sum of the corners
+    const size_t nc = mesh->levels[0].ncol;
+    for (size_t col = 0; geom_ok && col < nc; ++col) {
+      double q[4][3];
+      for (int a = 0; a < 4; ++a)
+        for (int d = 0; d < 3; ++d) q[a][d] = mesh->corners[((size_t)a * 3 + d) * nc + col];
+      double u[3], v[3], m[3];
+      for (int d = 0; d < 3; ++d) u[d] = q[1][d] - q[0][d], v[d] = q[2][d] - q[0][d], m[d] = q[0][d] + q[1][d] + q[2][d] + q[3][d];
+      const double nx = u[1] * v[2] - u[2] * v[1], ny = u[2] * v[0] - u[0] * v[2], nz = u[0] * v[1] - u[1] * v[0];
+      geom_ok = nx * m[0] + ny * m[1] + nz * m[2] > 0.0;
+    }
   }
   if (!geom_ok) {
     delete c;

@@ -310,6 +310,16 @@ def sphere_sequence(lib):
     # term), condensation, S x, B_lambda, the preconditioner, FGMRES in both precisions, recovery;
     # S x and the recovery against the oracle
     prob = make_sphere(4, 5, mg_levels=2, perturb=0.05, seed=3)
+    # a column frame turned the wrong way (corners 1 and 2 swapped) is rejected at create
+    bad = make_sphere(4, 5, mg_levels=2, seed=3)
+    bad.corners = np.ascontiguousarray(bad.corners.copy())
+    bad.corners[[1, 2], :, 7] = bad.corners[[2, 1], :, 7]
+    try:
+        Ctx(lib, bad, omega_rot=bad.omega_rot)
+        rejected = False
+    except AssertionError:
+        rejected = True
+    check(rejected, "sphere: a left-handed column frame is rejected")
     c = Ctx(lib, prob, omega_rot=prob.omega_rot)
     o = OracleProblem(prob, with_precond=False)
     r_ub, r_pi, b = c.rhs(2)
