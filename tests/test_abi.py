@@ -40,3 +40,38 @@ def test_null_arguments_are_rejected_without_a_device():
         fn.restype = ctypes.c_int
     assert lib.hyb_trace_apply(None, None, None) == -1
     assert lib.hyb_condense(None, None, None, None) == -1
+
+
+def _struct_fields(src, name):
+    """Field names, in order, of `typedef struct { ... } name;` in the header."""
+    blocks = dict((n, b) for b, n in re.findall(r"typedef struct \{([^{}]*)\}\s*(\w+);", src))
+    assert name in blocks, name
+    body = re.sub(r"/\*.*?\*/", "", blocks[name], flags=re.S)
+    names = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        decl = re.sub(r"^(const\s+)?[A-Za-z_0-9]+\s*", "", decl)  # the type
+        for part in decl.split(","):
+            names.append(part.strip().lstrip("*").strip())
+    return names
+
+
+def test_structs_match_the_binding():
+    from paper_2210_11797_amd import _native as N
+
+    src = open(os.path.join(ROOT, "include", "hyb.h")).read()
+    for cname, ctype in (("hyb_level", N._Level), ("hyb_mesh", N._Mesh), ("hyb_params", N._Params),
+                         ("hyb_info", N._Info)):
+        assert _struct_fields(src, cname) == [f[0] for f in ctype._fields_], cname
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+
+    res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                         text=True, timeout=120)
+    assert res.returncode == 2
+    assert "one GPU" in res.stderr
