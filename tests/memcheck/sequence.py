@@ -370,6 +370,20 @@ def sphere_sequence(lib):
     rc, info, lam = c.solve(b, 1e-8, maxit=60)
     check(rc >= 0, f"sphere: solve with the learned stage: {info.iters} iterations")
     c.close()
+    # degenerate spheres: one column per panel, one layer
+    for kw in (dict(n=1, nlev=2, mg_levels=1), dict(n=2, nlev=1, mg_levels=2)):
+        pr = make_sphere(**kw)
+        cd = Ctx(lib, pr, omega_rot=pr.omega_rot)
+        od = OracleProblem(pr, with_precond=False)
+        r_ub, r_pi, b = cd.rhs(4)
+        x = np.random.default_rng(2).standard_normal(cd.ntrace)
+        y = np.empty(cd.ntrace)
+        cd.call("hyb_trace_apply", P(x), P(y))
+        ref = od.hyb.S @ x
+        rc, info, lam = cd.solve(b, 1e-10)
+        check(np.abs(y - ref).max() <= 1e-11 * np.abs(ref).max() and rc == 0 and cd.residual(b, lam) <= 1.01e-10,
+              f"sphere C{kw['n']} x {kw['nlev']}: S x against the oracle, FGMRES {info.iters} iterations")
+        cd.close()
 
 
 def main():

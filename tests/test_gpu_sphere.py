@@ -1,6 +1,7 @@
 """Parity on the extruded cubed sphere with rotation (GPU).
 
-Small spheres (several column tiles, odd coarse levels) against the full oracle: S x, B_lambda and
+Small spheres (several column tiles, odd coarse levels, one column per panel, one layer) against
+the full oracle: S x, B_lambda and
 the recovery (1e-11 of the largest entry: the cell matrices come from two different quadrature
 codes), the preconditioner (100 eps cond(H)), solves to rtol 1e-13 against the sparse direct
 solution (the forward error the measured residual implies), FGMRES histories, the mixed form.
@@ -27,6 +28,8 @@ CASES = {
     "c8": dict(n=8, nlev=6, mg_levels=3, perturb=0.05, dt=1800.0),
     "c6": dict(n=6, nlev=4, mg_levels=2, dt=1200.0),
     "c16": dict(n=16, nlev=8, mg_levels=4, dt=1800.0),
+    "c1": dict(n=1, nlev=2, mg_levels=1),  # one column per panel
+    "c2x1": dict(n=2, nlev=1, mg_levels=2),  # one layer; a coarse level of one column per panel
 }
 TOL_OP = 1e-11
 _cache = {}
@@ -43,7 +46,7 @@ def setup(name):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("name", ["c8", "c6", "c16"])
+@pytest.mark.parametrize("name", ["c8", "c6", "c16", "c1", "c2x1"])
 def test_sphere_operators(name):
     prob, orc, s = setup(name)
     import torch
@@ -70,7 +73,7 @@ def test_sphere_operators(name):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("name", ["c8", "c6", "c16"])
+@pytest.mark.parametrize("name", ["c8", "c6", "c16", "c1", "c2x1"])
 def test_sphere_precondition(name):
     prob, orc, s = setup(name)
     import torch
@@ -86,7 +89,7 @@ def test_sphere_precondition(name):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("name", ["c8", "c6", "c16"])
+@pytest.mark.parametrize("name", ["c8", "c6", "c16", "c1", "c2x1"])
 def test_sphere_solve_matches_direct(name):
     prob, orc, s = setup(name)
     import torch
