@@ -417,13 +417,17 @@ int hyb_assemble_local(hyb_ctx *c, const double *theta_w, const double *exner_ha
       (rc = dalloc(c, &c->m2l, (size_t)c->ntrace)) || (rc = dalloc(c, &c->vol, (size_t)c->ncell)))
     return rc;
   c->nn.st_ready = false;  // the network's static inputs follow the cell volumes
-  // the lumped velocity mass (Sec. 2.3) is taken from the cell matrices without the Coriolis term,
-  // which is added afterwards on the sphere
+  // the lumped velocity mass (Sec. 2.3) leaves the Coriolis term out: on the sphere the assembly
+  // writes each cell's share of it (row sums before the term is added) to a temporary array
   if (c->geom == HYB_GEOM_SHELL) {
-    CHECK_HIP(launch_assemble_shell(c, theta_w, exner_hat_w, exner_c, false), "assemble_local");
-    CHECK_HIP(launch_lumped_mass(c), "lumped_mass");
-    if (c->p.omega_rot != 0.0)
-      CHECK_HIP(launch_assemble_shell(c, theta_w, exner_hat_w, exner_c, true), "assemble_local (Coriolis)");
+    double *rs = nullptr;
+    if ((rc = dalloc(c, &rs, (size_t)6 * c->ncell))) return rc;
+    hipError_t e = launch_assemble_shell(c, theta_w, exner_hat_w, exner_c, rs);
+    if (e == hipSuccess) e = launch_lumped_mass(c, rs);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // before the temporary is freed
+    c->bytes -= (size_t)6 * c->ncell * sizeof(double);
+    dfree(rs);
+    CHECK_HIP(e, "assemble_local");
   } else {
     CHECK_HIP(launch_assemble_box(c, theta_w, exner_hat_w, exner_c, rho_c), "assemble_local");
     CHECK_HIP(launch_lumped_mass(c), "lumped_mass");

@@ -71,7 +71,7 @@ __global__ void k_assemble_box(int ncell, int ncol, double dx, double dy, const 
 //   - the mass form is sum_q w phi_a phi_b (J_d(a) . J_d(b)) / det over the 3x3x3 Gauss rule; J_z is
 //     orthogonal to J_x and J_y, so the vertical and horizontal functions do not couple;
 //   - the Coriolis form tau_u dt <v_a . 2 Omega x v_b> (Omega along +z) is
-//     tau_u dt sum_q w phi_a phi_b 2 Omega e_z . (J_d(b) x J_d(a)) / det (with_coriolis);
+//     tau_u dt sum_q w phi_a phi_b 2 Omega e_z . (J_d(b) x J_d(a)) / det;
 //   - z_hat = u, so d/dz of a W_theta field is its jump over the cell divided by dr, z_hat . v_a is
 //     nonzero only for B and T, and q22 scales the vertical block by (1 + beta) as on the box;
 //   - g^b and k follow from the divergence theorem in reference coordinates: minus / plus
@@ -80,6 +80,14 @@ __global__ void k_assemble_box(int ncell, int ncol, double dx, double dy, const 
 //     (det_c: det J at the centre, the one-point rule), so rho* cancels again, plus q32 from the
 //     centre rule (-/+ tau_theta dt (thT - thB) / (thT + thB) on B / T); M3^Pi = (1-kappa)/kappa
 //     det_c / Pi*.
+// Sign of local face f of a cell relative to the global facet orientation: +1 when the facet
+// normal leaves the cell.  Vertical facets: the normal of edge e leaves edge_col[0][e].
+__device__ __forceinline__ double hsign(const int32_t *edge_col, const int32_t *edge_lf, int nedge,
+                                        const int32_t *col_edge, int ncol, int col, int f) {
+  int e = col_edge[(size_t)f * ncol + col];
+  return (edge_col[e] == col && edge_lf[e] == f) ? 1.0 : -1.0;
+}
+
 __device__ __forceinline__ void shell_point(const double U[12], double xi, double eta, double u[3],
                                             double ux[3], double uy[3]) {
   double w0 = (1 - xi) * (1 - eta), w1 = xi * (1 - eta), w2 = (1 - xi) * eta, w3 = xi * eta;
@@ -107,7 +115,10 @@ __global__ void k_assemble_shell(int ncell, int ncol, const double *__restrict__
                                  const double *__restrict__ radius, const double *__restrict__ thw,
                                  const double *__restrict__ piw, const double *__restrict__ pic, double dt,
                                  double tu, double tr, double tt, double cp, double kappa, double two_omega,
-                                 double *__restrict__ A, double *__restrict__ kv, double *__restrict__ volc) {
+                                 double *__restrict__ A, double *__restrict__ kv, double *__restrict__ volc,
+                                 int nlev, int nedge, const int32_t *__restrict__ col_edge,
+                                 const int32_t *__restrict__ edge_col, const int32_t *__restrict__ edge_lf,
+                                 double *__restrict__ rs) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncell) return;
   int k = c / ncol, col = c - k * ncol;
@@ -199,6 +210,21 @@ __global__ void k_assemble_shell(int ncell, int ncol, const double *__restrict__
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) a[(4 + i) * 7 + 4 + j] = (1.0 + beta) * mv[i][j];
+  // the cell's share of the lumped velocity mass, before the Coriolis term: rs_a = sum over the
+  // kept faces b of s_b (M2 - Q22)_ab, s_b the sign of face b against the global orientation (the
+  // lumped mass of a facet is rs_a of the cell its normal leaves minus rs_b of the other)
+  double sb[6];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) sb[b] = hsign(edge_col, edge_lf, nedge, col_edge, ncol, col, b);
+  sb[4] = k == 0 ? 0.0 : -1.0;  // no velocity dof on the ground or the lid
+  sb[5] = k == nlev - 1 ? 0.0 : 1.0;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) acc += sb[j] * a[i * 7 + j];
+    rs[at(i, ncell, c)] = acc;
+  }
   const double tud = tu * dt;
 #pragma unroll
   for (int i = 0; i < 6; ++i)
@@ -329,20 +355,13 @@ __global__ void k_build_stencil(int nlev, int ncol, int nedge, int ncell, size_t
   for (int i = 0; i < 11; ++i) S[s_idx(F, i)] = s[i];
 }
 
-// Sign of local face f of a cell relative to the global facet orientation: +1 when the facet
-// normal leaves the cell.  Vertical facets: the normal of edge e leaves edge_col[0][e].
-__device__ __forceinline__ double hsign(const int32_t *edge_col, const int32_t *edge_lf, int nedge,
-                                        const int32_t *col_edge, int ncol, int col, int f) {
-  int e = col_edge[(size_t)f * ncol + col];
-  return (edge_col[e] == col && edge_lf[e] == f) ? 1.0 : -1.0;
-}
 
 // Lumped velocity mass (Sec. 2.3): row sum, in global orientation, of the assembled continuous
 // (M2 - Q22) over the dofs kept in the mixed system (every facet except ground and lid).
 __global__ void k_lumped_mass(int nlev, int ncol, int nedge, int ncell, size_t ntr,
                               const int32_t *__restrict__ col_edge, const int32_t *__restrict__ edge_col,
                               const int32_t *__restrict__ edge_lf, const double *__restrict__ A,
-                              double *__restrict__ m2l) {
+                              const double *__restrict__ rs, double *__restrict__ m2l) {
   size_t F = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (F >= ntr) return;
   size_t nz = (size_t)(nlev + 1) * ncol;
@@ -367,6 +386,10 @@ __global__ void k_lumped_mass(int nlev, int ncol, int nedge, int ncell, size_t n
     lfs[0] = edge_lf[e];
     cells[1] = k * ncol + edge_col[nedge + e];
     lfs[1] = edge_lf[nedge + e];
+  }
+  if (rs) {  // the cells' row sums, written by the assembly
+    m2l[F] = rs[at(lfs[0], ncell, cells[0])] - rs[at(lfs[1], ncell, cells[1])];
+    return;
   }
   double sum = 0.0;
   for (int s = 0; s < 2; ++s) {
@@ -579,12 +602,14 @@ hipError_t launch_assemble_box(hyb_ctx *c, const double *thw, const double *piw,
 }
 
 hipError_t launch_assemble_shell(hyb_ctx *c, const double *thw, const double *piw, const double *pic,
-                                 bool with_coriolis) {
+                                 double *rs) {
   const hyb_params &p = c->p;
   double kappa = p.rd / p.cp;
+  const LevelDev &L0 = c->lv[0];
   hipLaunchKernelGGL(k_assemble_shell, dim3(nblk(c->ncell, 64)), dim3(64), 0, c->stream, c->ncell, c->ncol,
                      c->corners_d, c->radius_d, thw, piw, pic, p.dt, p.tau_u, p.tau_rho, p.tau_theta, p.cp, kappa,
-                     with_coriolis ? 2.0 * p.omega_rot : 0.0, c->A, c->kv, c->vol);
+                     2.0 * p.omega_rot, c->A, c->kv, c->vol, c->nlev, c->nedge, L0.col_edge, L0.edge_col, L0.edge_lf,
+                     rs);
   return hipGetLastError();
 }
 
@@ -601,10 +626,10 @@ hipError_t launch_build_stencil(hyb_ctx *c) {
   return hipGetLastError();
 }
 
-hipError_t launch_lumped_mass(hyb_ctx *c) {
+hipError_t launch_lumped_mass(hyb_ctx *c, const double *rs) {
   const LevelDev &L0 = c->lv[0];
   hipLaunchKernelGGL(k_lumped_mass, dim3(nblk(c->ntrace)), dim3(kBlock), 0, c->stream, c->nlev, c->ncol,
-                     c->nedge, c->ncell, (size_t)c->ntrace, L0.col_edge, L0.edge_col, L0.edge_lf, c->A, c->m2l);
+                     c->nedge, c->ncell, (size_t)c->ntrace, L0.col_edge, L0.edge_col, L0.edge_lf, c->A, rs, c->m2l);
   return hipGetLastError();
 }
 

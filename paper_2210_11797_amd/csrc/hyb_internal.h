@@ -188,8 +188,8 @@ hipError_t launch_assemble_box(hyb_ctx *c, const double *theta_w, const double *
 hipError_t launch_factor_cells(hyb_ctx *c);
 hipError_t launch_build_stencil(hyb_ctx *c);
 hipError_t launch_assemble_shell(hyb_ctx *c, const double *theta_w, const double *exner_hat_w,
-                                 const double *exner_c, bool with_coriolis);
-hipError_t launch_lumped_mass(hyb_ctx *c);
+                                 const double *exner_c, double *rs);
+hipError_t launch_lumped_mass(hyb_ctx *c, const double *rs = nullptr);
 hipError_t launch_pressure_stencil(hyb_ctx *c);
 hipError_t launch_galerkin(hyb_ctx *c, int coarse_level);
 hipError_t launch_gamma(hyb_ctx *c);

@@ -321,7 +321,7 @@ def sphere_sequence(lib):
         rejected = True
     check(rejected, "sphere: a left-handed column frame is rejected")
     c = Ctx(lib, prob, omega_rot=prob.omega_rot)
-    o = OracleProblem(prob, with_precond=False)
+    o = OracleProblem(prob)
     r_ub, r_pi, b = c.rhs(2)
     ruc, rpc = cells_from_soa(r_ub, r_pi)
     bref = o.hyb.rhs(ruc, rpc)
@@ -332,6 +332,9 @@ def sphere_sequence(lib):
     ref = o.hyb.S @ x
     check(np.abs(y - ref).max() <= 1e-11 * np.abs(ref).max(), "sphere: S x against the oracle")
     c.call("hyb_precondition", P(b), P(z))
+    zref = o.pc(b)
+    check(np.abs(z - zref).max() <= 1e-9 * np.abs(zref).max(),
+          "sphere: preconditioner (lumped mass without the Coriolis term) against the oracle")
     rc, info, lam = c.solve(b, 1e-10)
     check(rc == 0 and c.residual(b, lam) <= 1.01e-10, f"sphere: fp64 FGMRES {info.iters} iterations")
     u_b, pi = np.empty(6 * c.ncell), np.empty(c.ncell)
