@@ -223,6 +223,43 @@ def learned_leg(args, prob, s, rhs, sec_plain, dx, dz, dt):
                               batch=8, final_energy_loss=float(np.mean(hist[-50:])), seconds=train_s))
 
 
+def configs_leg(args, prob, rhs):
+    """The paper's solver configurations on the benchmark box, by time-to-1e-8 and iterations: the
+    hybridised single-level method (Configuration 2: FGMRES preconditioned by 1, 2 or 3 LineSmooth
+    sweeps) against the two-level cycle (Configuration 3c, the headline form), and the relaxation
+    factor omega of the two-level cycle from 0.3 to 0.9 (the paper's parameter study)."""
+    import torch
+
+    out = {"single_level": {}, "omega_two_level": {}}
+
+    def one(s, maxit):
+        b = torch.empty(s.ntrace, dtype=torch.float64, device="cuda")
+        lam = torch.zeros_like(b)
+        s.condense(rhs[0][0], rhs[0][1], b)
+        s.solve(b, lam, rtol=args.rtol, maxit=maxit)  # warm-up
+        lam.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = s.solve(b, lam, rtol=args.rtol, maxit=maxit)
+        torch.cuda.synchronize()
+        return dict(sec_per_solve=time.perf_counter() - t0, iters=info["iters"], rel_res=info["rel_res"],
+                    status=info["status"])
+
+    for n in (1, 2, 3):
+        s = setup_solver(prob, 0, coarse_mode=1, n_pre=n, n_post=0, mg_coarse_sweeps=args.coarse_sweeps)
+        out["single_level"][f"{n}_sweeps"] = r = one(s, 6000)
+        log(f"configuration 2 ({n} sweeps): {r['sec_per_solve'] * 1e3:.0f} ms, {r['iters']} iterations")
+        s.close()
+    for om in (0.3, 0.5, 0.6, 0.7, 0.8, 0.9):
+        s = setup_solver(prob, 0, omega=om, mg_coarse_sweeps=args.coarse_sweeps)
+        out["omega_two_level"][f"{om:.1f}"] = r = one(s, 1000)
+        log(f"configuration 3c, omega {om:.1f}: {r['sec_per_solve'] * 1e3:.1f} ms, {r['iters']} iterations, "
+            f"status {r['status']}")
+        s.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def sphere_leg(args):
     """The extruded cubed sphere (C192 x 30 quadratic layers to 30 km, dt = 1800 s, rotating, the
     Gaussian pressure bump): time-to-1e-8 of the plain FP64 solve and of the mixed form, their
@@ -481,6 +518,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-p1", action="store_true")
     ap.add_argument("--no-sphere", action="store_true")
+    ap.add_argument("--no-configs", action="store_true")
     ap.add_argument("--no-c384", action="store_true")
     ap.add_argument("--c384-n", type=int, default=384)
     ap.add_argument("--c384-nlev", type=int, default=70)
@@ -562,6 +600,14 @@ def main():
     if not args.no_learned:
         learned_out = learned_leg(args, prob, s, rhs, sec, dx, dz, dt)
 
+    configs_out = None
+    if not args.no_configs:
+        try:
+            configs_out = configs_leg(args, prob, rhs)
+        except Exception as e:
+            log(f"configs leg failed: {e}")
+            configs_out = {"error": str(e)}
+
     sphere_out = None
     if not args.no_sphere:
         try:
@@ -629,6 +675,7 @@ def main():
         "kernel_ms_note": "from a second, untimed run of the same solves with events around every family",
         "mixed": mixed,
         "learned": learned_out,
+        "configurations": configs_out,
         "sphere": sphere_out,
         "c384": c384_out,
         "p1": p1_out,

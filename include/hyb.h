@@ -131,6 +131,10 @@ typedef struct {
      velocity mass form (Sec. 2.2), on HYB_GEOM_SHELL meshes (0 on the box); read at
      hyb_assemble_local.  The lumped velocity mass of the preconditioner leaves it out. */
   double omega_rot;
+  /* coarse correction of the two-level cycle (Alg. 2): 0 = one pressure-multigrid V-cycle (the
+     paper's Configuration 3c, the default); 1 = none: the preconditioner is n_pre + n_post
+     LineSmooth sweeps from zero (Alg. 1 alone, the paper's hybridised single-level Configuration 2) */
+  int32_t coarse_mode;
 } hyb_params;
 
 typedef struct {

@@ -344,11 +344,11 @@ class TwoLevelP1:
     multigrid V-cycle on the order-0 H of the same mesh, lambda += P dPi, LineSmooth (n_post)."""
 
     def __init__(self, mesh: BoxMesh, S, H, omega=0.6, n_pre=1, n_post=2, mg_levels=4, omega_p=0.9, mg_pre=1,
-                 mg_post=2, mg_coarse_sweeps=6, mg_coarse_cheb=(0.02, 2.0)):
+                 mg_post=2, mg_coarse_sweeps=6, mg_coarse_cheb=(0.02, 2.0), coarse=True):
         from .precond import PressureMultigrid
 
         self.mesh, self.S = mesh, sp.csr_matrix(S)
-        self.omega, self.n_pre, self.n_post = omega, n_pre, n_post
+        self.omega, self.n_pre, self.n_post, self.coarse = omega, n_pre, n_post, coarse
         self.D = line_smoother_matrix(mesh, self.S)
         self.D_lu = spla.splu(self.D.tocsc())
         self.P = trace_prolongation(mesh)
@@ -364,5 +364,7 @@ class TwoLevelP1:
 
     def __call__(self, B):
         lam = self.line_smooth(np.zeros_like(B), B, self.n_pre)
+        if not self.coarse:  # LineSmooth alone (the single-level configuration)
+            return self.line_smooth(lam, B, self.n_post)
         dpi = self.mg.vcycle(self.gamma * (self.P.T @ (B - self.S @ lam)))
         return self.line_smooth(lam + self.P @ dpi, B, self.n_post)

@@ -193,9 +193,12 @@ class TwoLevel:
 
     def __init__(self, mesh: BoxMesh, S, H, omega=0.6, n_pre=1, n_post=2, mg_levels=4,
                  omega_p=0.9, mg_pre=1, mg_post=2, mg_coarse_sweeps=6, sign=+1.0,
-                 mg_coarse_cheb=COARSE_CHEB):
+                 mg_coarse_cheb=COARSE_CHEB, coarse=True):
+        """coarse=False: no coarse correction, the preconditioner is n_pre + n_post LineSmooth
+        sweeps from zero (the paper's hybridised single-level Configuration 2)."""
         self.mesh, self.S = mesh, sp.csr_matrix(S)
         self.omega, self.n_pre, self.n_post, self.sign = omega, n_pre, n_post, sign
+        self.coarse = coarse
         self.D = line_smoother_matrix(mesh, self.S)
         self.D_lu = spla.splu(self.D.tocsc())
         self.P = trace_prolongation(mesh)
@@ -215,6 +218,8 @@ class TwoLevel:
     def __call__(self, B):
         lam = np.zeros_like(B)
         lam = self.line_smooth(lam, B, self.n_pre)
+        if not self.coarse:
+            return self.line_smooth(lam, B, self.n_post)
         R = B - self.S @ lam
         Bbar = self.gamma * (self.P.T @ R)
         dpi = self.mg.vcycle(Bbar)

@@ -80,6 +80,7 @@ int check_params(hyb_ctx *c, const hyb_params *p) {
   if (p->mg_coarse_cheb && !(p->cheb_lo > 0.0 && p->cheb_hi > p->cheb_lo && std::isfinite(p->cheb_hi)))
     return fail(c, HYB_EINVAL, "the Chebyshev interval needs 0 < cheb_lo < cheb_hi");
   if (!std::isfinite(p->omega_rot)) return fail(c, HYB_EINVAL, "omega_rot must be finite");
+  if (p->coarse_mode != 0 && p->coarse_mode != 1) return fail(c, HYB_EINVAL, "coarse_mode must be 0 or 1");
   if (p->omega_rot != 0.0 && c->geom != HYB_GEOM_SHELL)
     return fail(c, HYB_EINVAL, "rotation (omega_rot) is defined on HYB_GEOM_SHELL meshes only");
   return HYB_OK;

@@ -1039,18 +1039,20 @@ hipError_t p1_precondition(hyb_ctx *c, const double *r, double *z) {
     hipLaunchKernelGGL(k_p1_fill, dim3(nblk(ntr)), dim3(kBlock), 0, c->stream, lam, ntr, 0.0);
     if ((e = hipGetLastError())) return e;
   }
-  if ((e = p1_rows(c, lam, R, 2, r, true))) return e;
-  int slot = prof_begin(c, F_RESTRICT);
-  hipLaunchKernelGGL(k_p1_restrict, dim3(nblk(nc)), dim3(kBlock), 0, c->stream, c->nlev, c->ncol, c->nedge,
-                     (size_t)c->nz, L0.col_edge, R, s.gamma, (double *)cc->lv[0].b);
-  prof_end(c, F_RESTRICT, slot);
-  if ((e = hipGetLastError())) return e;
-  if ((e = coarse_vcycle(cc))) return e;
-  slot = prof_begin(c, F_PROLONG);
-  hipLaunchKernelGGL(k_p1_prolong, dim3(nblk(ntr)), dim3(kBlock), 0, c->stream, ntr, c->nlev, c->ncol, c->nedge,
-                     (size_t)c->nz, L0.edge_col, L0.edge_lf, (const double *)cc->lv[0].x, lam);
-  prof_end(c, F_PROLONG, slot);
-  if ((e = hipGetLastError())) return e;
+  if (p.coarse_mode == 0) {  // the DG0 coarse correction (coarse_mode 1: LineSmooth alone)
+    if ((e = p1_rows(c, lam, R, 2, r, true))) return e;
+    int slot = prof_begin(c, F_RESTRICT);
+    hipLaunchKernelGGL(k_p1_restrict, dim3(nblk(nc)), dim3(kBlock), 0, c->stream, c->nlev, c->ncol, c->nedge,
+                       (size_t)c->nz, L0.col_edge, R, s.gamma, (double *)cc->lv[0].b);
+    prof_end(c, F_RESTRICT, slot);
+    if ((e = hipGetLastError())) return e;
+    if ((e = coarse_vcycle(cc))) return e;
+    slot = prof_begin(c, F_PROLONG);
+    hipLaunchKernelGGL(k_p1_prolong, dim3(nblk(ntr)), dim3(kBlock), 0, c->stream, ntr, c->nlev, c->ncol, c->nedge,
+                       (size_t)c->nz, L0.edge_col, L0.edge_lf, (const double *)cc->lv[0].x, lam);
+    prof_end(c, F_PROLONG, slot);
+    if ((e = hipGetLastError())) return e;
+  }
   for (int k = 0; k < p.n_post; ++k) {
     double *dst = (k == p.n_post - 1) ? z : tmp;
     if ((e = sweep(lam, dst))) return e;

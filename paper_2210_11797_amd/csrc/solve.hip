@@ -620,7 +620,7 @@ template hipError_t launch_trace_apply<double, float, double>(hyb_ctx *, const d
 template hipError_t launch_trace_apply<float, float, float>(hyb_ctx *, const float *, const float *, const float *,
                                                             float *, int);
 
-// Alg. 2 from a zero initial guess: z = M(r).
+// Alg. 2 from a zero initial guess: z = M(r) (with coarse_mode 1, the LineSmooth sweeps alone).
 template <typename T>
 hipError_t precondition(hyb_ctx *c, const T *r, T *z) {
   const hyb_params &p = c->p;
@@ -640,21 +640,23 @@ hipError_t precondition(hyb_ctx *c, const T *r, T *z) {
       std::swap(tA, tB);
     }
   }
-  // residual, restriction and scaling
-  HYB_TRY((launch_trace_apply<T, T, T>(c, S, tA, r, tR, 1)));
-  int slot = prof_begin(c, F_RESTRICT);
-  hipLaunchKernelGGL((k_restrict<T>), dim3(nblk(c->ncell)), dim3(kBlock), 0, c->stream, tR, gam, (T *)c->lv[0].b,
-                     c->nlev, c->ncol, c->nedge, (size_t)c->nz, L0.col_edge);
-  prof_end(c, F_RESTRICT, slot);
-  HYB_TRY(hipGetLastError());
-  // coarse solve: one pressure multigrid V-cycle
-  HYB_TRY(vcycle<T>(c, 0));
-  // prolongation and update
-  slot = prof_begin(c, F_PROLONG);
-  hipLaunchKernelGGL((k_prolong<T>), dim3(nblk(ntr)), dim3(kBlock), 0, c->stream, (const T *)c->lv[0].x, tA,
-                     c->nlev, c->ncol, c->nedge, (size_t)c->nz, ntr, L0.edge_col);
-  prof_end(c, F_PROLONG, slot);
-  HYB_TRY(hipGetLastError());
+  if (p.coarse_mode == 0) {
+    // residual, restriction and scaling
+    HYB_TRY((launch_trace_apply<T, T, T>(c, S, tA, r, tR, 1)));
+    int slot = prof_begin(c, F_RESTRICT);
+    hipLaunchKernelGGL((k_restrict<T>), dim3(nblk(c->ncell)), dim3(kBlock), 0, c->stream, tR, gam, (T *)c->lv[0].b,
+                       c->nlev, c->ncol, c->nedge, (size_t)c->nz, L0.col_edge);
+    prof_end(c, F_RESTRICT, slot);
+    HYB_TRY(hipGetLastError());
+    // coarse solve: one pressure multigrid V-cycle
+    HYB_TRY(vcycle<T>(c, 0));
+    // prolongation and update
+    slot = prof_begin(c, F_PROLONG);
+    hipLaunchKernelGGL((k_prolong<T>), dim3(nblk(ntr)), dim3(kBlock), 0, c->stream, (const T *)c->lv[0].x, tA,
+                       c->nlev, c->ncol, c->nedge, (size_t)c->nz, ntr, L0.edge_col);
+    prof_end(c, F_PROLONG, slot);
+    HYB_TRY(hipGetLastError());
+  }  // coarse_mode 1: LineSmooth alone (no coarse correction)
   // postsmoothing, the last sweep writes z
   if (p.n_post <= 0) {
     hipLaunchKernelGGL((k_copy<T>), dim3(nblk(ntr)), dim3(kBlock), 0, c->stream, (const T *)tA, z, ntr);

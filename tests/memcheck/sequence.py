@@ -132,6 +132,11 @@ def solver_sequence(lib):
           f"fp64 FGMRES(5): {info.iters} iterations, {info.restarts} restarts")
     u_b, pi = np.empty(6 * c.ncell), np.empty(c.ncell)
     c.call("hyb_recover", P(r_ub), P(r_pi), P(lam), P(u_b), P(pi))
+    c.set(coarse_mode=1, n_pre=2, n_post=1)  # LineSmooth alone (single-level configuration)
+    c.call("hyb_precondition", P(b), P(z))
+    rc, info, lam = c.solve(b, 1e-8, maxit=2000)
+    check(rc == 0 and c.residual(b, lam) <= 1.01e-8, f"single-level FGMRES(5): {info.iters} iterations")
+    c.set(coarse_mode=0, n_pre=1, n_post=2)
     c.set(precision=N.PREC_MIXED, restart=30)
     c.call("hyb_precondition", P(b), P(z))
     rc, info, lam = c.solve(b, 1e-8)

@@ -1,0 +1,109 @@
+"""The paper's hybridised single-level configuration (Configuration 2: FGMRES preconditioned by
+LineSmooth alone, coarse_mode = 1) against the oracle (GPU): the preconditioner, a fixed linear map
+of the sweeps, to 1e-12 of its largest entry (order 0, box and sphere) and 1e-9 (order 1, as the
+two-level map there); FGMRES iteration counts and the first residual estimates against the
+oracle's FGMRES; and the paper's ordering of the configurations in iterations."""
+
+import numpy as np
+import pytest
+
+from gpu_common import dev, host, make_solver, params_for, rel_max, say
+from oracle.problem import OracleProblem, cells_from_soa
+from synth import make_box, make_rhs, make_rhs_sphere, make_sphere
+
+BOX = dict(nx=16, ny=16, nlev=8, dx=10e3, dz=1250.0, mg_levels=4, perturb=0.05)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n_pre,n_post", [(1, 0), (2, 0), (3, 0), (1, 2)])
+def test_single_level_precondition_box(n_pre, n_post):
+    import torch
+
+    prob = make_box(**BOX)
+    s = make_solver(prob, coarse_mode=1, n_pre=n_pre, n_post=n_post)
+    orc = OracleProblem(prob, n_pre=n_pre, n_post=n_post, coarse=False)
+    r = np.random.default_rng(3).standard_normal(orc.mesh.ntrace)
+    z = torch.empty(orc.mesh.ntrace, dtype=torch.float64, device="cuda")
+    s.precondition(dev(r), z)
+    err = rel_max(host(z), orc.pc(r))
+    say(f"[single-level] box n_pre {n_pre} n_post {n_post}: rel err {err:.2e}")
+    assert err <= 1e-12
+    s.close()
+
+
+@pytest.mark.gpu
+def test_single_level_precondition_sphere():
+    import torch
+
+    prob = make_sphere(8, 6, mg_levels=3, perturb=0.05)
+    s = make_solver(prob, coarse_mode=1, n_pre=2, n_post=0)
+    orc = OracleProblem(prob, n_pre=2, n_post=0, coarse=False)
+    r = np.random.default_rng(4).standard_normal(orc.mesh.ntrace)
+    z = torch.empty(orc.mesh.ntrace, dtype=torch.float64, device="cuda")
+    s.precondition(dev(r), z)
+    err = rel_max(host(z), orc.pc(r))
+    say(f"[single-level] sphere C8 x 6: rel err {err:.2e}")
+    assert err <= 1e-12
+    s.close()
+
+
+@pytest.mark.gpu
+def test_single_level_precondition_order1():
+    import torch
+
+    from oracle import p1 as op1
+    from oracle.mesh import BoxMesh
+    from paper_2210_11797_amd import HybSolver, levels_of
+    from synth import make_rhs_p1
+
+    prob = make_box(nx=8, ny=6, nlev=5, dx=5e3, dz=250.0, perturb=0.1, mg_levels=2)
+    s = HybSolver(prob.nlev, levels_of(prob), prob.dx, prob.dy, prob.dz,
+                  params_for(prob, coarse_mode=1, n_pre=1, n_post=2), order=1)
+    s.assemble_local(dev(prob.theta_w), dev(prob.exner_hat_w), dev(prob.exner_c), dev(prob.rho_c))
+    s.condense()
+    mesh = BoxMesh(prob.nx, prob.ny, prob.nlev, prob.dx, prob.dy, prob.z)
+    h = op1.HybridP1(mesh, op1.local_matrices(mesh, prob))
+    tl = op1.TwoLevelP1(mesh, h.S, OracleProblem(prob).H, mg_levels=len(prob.levels), coarse=False)
+    r_u, r_p = make_rhs_p1(prob, 5)
+    B = h.rhs(r_u.reshape(36, -1).T.copy(), r_p.reshape(8, -1).T.copy())
+    z = torch.empty(s.ntrace, dtype=torch.float64, device="cuda")
+    s.precondition(dev(B), z)
+    err = rel_max(host(z), tl(B))
+    say(f"[single-level] order 1: rel err {err:.2e}")
+    assert err <= 1e-9
+    s.close()
+
+
+@pytest.mark.gpu
+def test_single_level_iterations_and_ordering():
+    """FGMRES with LineSmooth alone (1, 2, 3 sweeps) against the oracle's iteration counts, and
+    the paper's ordering: the two-level cycle needs far fewer iterations than any of them."""
+    import torch
+
+    prob = make_box(**BOX)
+    r_ub, r_pi = make_rhs(prob, 2)
+    ruc, rpc = cells_from_soa(r_ub, r_pi)
+    its = {}
+    for n in (1, 2, 3):
+        orc = OracleProblem(prob, n_pre=n, n_post=0, coarse=False)
+        B = orc.hyb.rhs(ruc, rpc)
+        _, hist, oits, conv = orc.solve_fgmres(B, rtol=1e-8, maxit=3000)
+        s = make_solver(prob, coarse_mode=1, n_pre=n, n_post=0)
+        b = dev(B)
+        lam = torch.zeros_like(b)
+        info = s.solve(b, lam, rtol=1e-8, maxit=3000)
+        res = np.linalg.norm(B - orc.hyb.S @ host(lam)) / np.linalg.norm(B)
+        say(f"[single-level] {n} sweep(s): gpu {info['iters']} oracle {oits} iterations, residual {res:.1e}")
+        assert info["status"] == 0 and res <= 1.01e-8
+        # rounding separates the two Krylov sequences slowly over hundreds of steps
+        assert abs(info["iters"] - oits) <= max(2, oits // 50)
+        k = min(20, len(info["history"]), len(hist) - 1)
+        np.testing.assert_allclose(info["history"][:k], hist[1 : k + 1], rtol=1e-6)
+        its[n] = info["iters"]
+        s.close()
+    s = make_solver(prob)
+    lam = torch.zeros_like(b)
+    its["3c"] = s.solve(b, lam, rtol=1e-8)["iters"]
+    say(f"[single-level] iterations {its}")
+    assert its["3c"] < min(its[1], its[2], its[3])
+    assert its[3] < its[1]

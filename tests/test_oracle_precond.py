@@ -189,3 +189,33 @@ def test_chebyshev_coarsest_solve(box):
     # error in the H-norm (H_z^-1 H is self-adjoint there) shrinks by at most the bound
     e, e0 = x_ref - x, x_ref
     assert np.sqrt(e @ Hd @ e) <= bound * np.sqrt(e0 @ Hd @ e0) * (1 + 1e-8)
+
+
+def test_single_level_configuration():
+    """The paper's hybridised single-level configuration: the preconditioner is LineSmooth alone.
+    One sweep from zero is omega D^-1 B (D: the column blocks of S^zz and diag(S^hh)); two sweeps
+    add omega D^-1 of the new residual; FGMRES needs more iterations with it than with the
+    two-level cycle, and fewer with more sweeps (the paper's ordering of its configurations)."""
+    import scipy.sparse.linalg as spla
+
+    from oracle.precond import line_smoother_matrix
+    from oracle.problem import OracleProblem, cells_from_soa
+    from synth import make_box, make_rhs
+
+    prob = make_box(nx=12, ny=12, nlev=8, dx=10e3, dz=1250.0, mg_levels=3)
+    o1 = OracleProblem(prob, n_pre=1, n_post=0, coarse=False)
+    S = o1.hyb.S
+    D = line_smoother_matrix(o1.mesh, S).tocsc()
+    B = cells_from_soa(*make_rhs(prob, 0))
+    B = o1.hyb.rhs(*B)
+    z1 = spla.spsolve(D, B) * 0.6
+    np.testing.assert_allclose(o1.pc(B), z1, rtol=1e-12, atol=1e-12 * np.abs(z1).max())
+    o2 = OracleProblem(prob, n_pre=1, n_post=1, coarse=False)
+    z2 = z1 + 0.6 * spla.spsolve(D, B - S @ z1)
+    np.testing.assert_allclose(o2.pc(B), z2, rtol=1e-11, atol=1e-12 * np.abs(z2).max())
+    its = {}
+    for n in (1, 3):
+        o = OracleProblem(prob, n_pre=n, n_post=0, coarse=False)
+        its[n] = o.solve_fgmres(B, rtol=1e-8, maxit=2000)[2]
+    its["3c"] = OracleProblem(prob).solve_fgmres(B, rtol=1e-8)[2]
+    assert its["3c"] < its[3] < its[1]
