@@ -133,8 +133,12 @@ typedef struct {
   double omega_rot;
   /* coarse correction of the two-level cycle (Alg. 2): 0 = one pressure-multigrid V-cycle (the
      paper's Configuration 3c, the default); 1 = none: the preconditioner is n_pre + n_post
-     LineSmooth sweeps from zero (Alg. 1 alone, the paper's hybridised single-level Configuration 2) */
+     LineSmooth sweeps from zero (Alg. 1 alone, the paper's hybridised single-level Configuration 2);
+     2 = BiCGStab on the coarse pressure system, preconditioned by one V-cycle, from zero until the
+     coarse residual drops by coarse_rtol (at most 200 steps; the paper's Configurations 3a with
+     1e-14 and 3b with 1e-2; order 0 and HYB_PREC_FP64 only, HYB_EINVAL otherwise) */
   int32_t coarse_mode;
+  double coarse_rtol;
 } hyb_params;
 
 typedef struct {

@@ -58,3 +58,43 @@ def fgmres(apply_A, apply_M, b, x0=None, rtol=1e-8, restart=30, maxit=500):
         if beta / bnorm <= rtol:
             return x, hist, its, True
     return x, hist, its, beta / bnorm <= rtol
+
+
+def bicgstab(apply_A, apply_M, b, rtol, maxit=200):
+    """BiCGStab (van der Vorst, 1992) with right preconditioning M (Saad, Iterative Methods for Sparse
+    Linear Systems, Sec. 9.3), from x = 0 until ||b - A x|| <= rtol ||b|| or maxit steps; a breakdown
+    (a zero inner product) returns the current iterate.  The coarse solve of the paper's
+    Configurations 3a / 3b."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    rh = b.copy()
+    p = np.zeros_like(b)
+    v = np.zeros_like(b)
+    bn = np.linalg.norm(b)
+    rho = alpha = omega = 1.0
+    rho1 = rh @ r
+    for it in range(maxit):
+        if bn == 0.0 or rho1 == 0.0 or omega == 0.0:
+            break
+        beta = (rho1 / rho) * (alpha / omega)
+        p = r + (beta if it else 0.0) * (p - omega * v)
+        ph = apply_M(p)
+        v = apply_A(ph)
+        den = rh @ v
+        if den == 0.0:
+            break
+        alpha = rho1 / den
+        s = r - alpha * v
+        if np.linalg.norm(s) <= rtol * bn:
+            x = x + alpha * ph
+            break
+        sh = apply_M(s)
+        t = apply_A(sh)
+        tt = t @ t
+        omega = (t @ s) / tt if tt > 0.0 else 0.0
+        x = x + alpha * ph + omega * sh
+        r = s - omega * t
+        rho, rho1 = rho1, rh @ r
+        if np.linalg.norm(r) <= rtol * bn:
+            break
+    return x

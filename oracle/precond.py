@@ -195,7 +195,9 @@ class TwoLevel:
                  omega_p=0.9, mg_pre=1, mg_post=2, mg_coarse_sweeps=6, sign=+1.0,
                  mg_coarse_cheb=COARSE_CHEB, coarse=True):
         """coarse=False: no coarse correction, the preconditioner is n_pre + n_post LineSmooth
-        sweeps from zero (the paper's hybridised single-level Configuration 2)."""
+        sweeps from zero (the paper's hybridised single-level Configuration 2); coarse=("bicgstab",
+        rtol): the coarse pressure system solved by BiCGStab preconditioned by the V-cycle to rtol
+        (the paper's Configurations 3a and 3b)."""
         self.mesh, self.S = mesh, sp.csr_matrix(S)
         self.omega, self.n_pre, self.n_post, self.sign = omega, n_pre, n_post, sign
         self.coarse = coarse
@@ -222,6 +224,12 @@ class TwoLevel:
             return self.line_smooth(lam, B, self.n_post)
         R = B - self.S @ lam
         Bbar = self.gamma * (self.P.T @ R)
-        dpi = self.mg.vcycle(Bbar)
+        if isinstance(self.coarse, tuple) and self.coarse[0] == "bicgstab":
+            from .krylov import bicgstab
+
+            H0 = self.mg.H[0]
+            dpi = bicgstab(lambda v: H0 @ v, self.mg.vcycle, Bbar, self.coarse[1])
+        else:
+            dpi = self.mg.vcycle(Bbar)
         lam = lam + self.P @ dpi
         return self.line_smooth(lam, B, self.n_post)

@@ -49,7 +49,7 @@ class _Params(ctypes.Structure):
                 ("mg_coarse_sweeps", ctypes.c_int32), ("restart", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("learned", ctypes.c_int32), ("learned_tau", ctypes.c_double),
                 ("mg_coarse_cheb", ctypes.c_int32), ("cheb_lo", ctypes.c_double), ("cheb_hi", ctypes.c_double),
-                ("omega_rot", ctypes.c_double), ("coarse_mode", ctypes.c_int32)]
+                ("omega_rot", ctypes.c_double), ("coarse_mode", ctypes.c_int32), ("coarse_rtol", ctypes.c_double)]
 
 
 class _Info(ctypes.Structure):
@@ -88,6 +88,7 @@ class Params:
     cheb_hi: float = 2.0
     omega_rot: float = 0.0
     coarse_mode: int = 0
+    coarse_rtol: float = 1e-2
 
     def to_c(self) -> _Params:
         return _Params(**{f.name: getattr(self, f.name) for f in fields(self)})

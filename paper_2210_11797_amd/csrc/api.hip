@@ -80,7 +80,11 @@ int check_params(hyb_ctx *c, const hyb_params *p) {
   if (p->mg_coarse_cheb && !(p->cheb_lo > 0.0 && p->cheb_hi > p->cheb_lo && std::isfinite(p->cheb_hi)))
     return fail(c, HYB_EINVAL, "the Chebyshev interval needs 0 < cheb_lo < cheb_hi");
   if (!std::isfinite(p->omega_rot)) return fail(c, HYB_EINVAL, "omega_rot must be finite");
-  if (p->coarse_mode != 0 && p->coarse_mode != 1) return fail(c, HYB_EINVAL, "coarse_mode must be 0 or 1");
+  if (p->coarse_mode < 0 || p->coarse_mode > 2) return fail(c, HYB_EINVAL, "coarse_mode must be 0, 1 or 2");
+  if (p->coarse_mode == 2 && (p->precision != HYB_PREC_FP64 || c->order != 0))
+    return fail(c, HYB_EINVAL, "the Krylov coarse solve (coarse_mode 2) is an order-0 FP64 mode");
+  if (p->coarse_mode == 2 && !(p->coarse_rtol > 0.0 && p->coarse_rtol < 1.0))
+    return fail(c, HYB_EINVAL, "coarse_rtol must be in (0, 1)");
   if (p->omega_rot != 0.0 && c->geom != HYB_GEOM_SHELL)
     return fail(c, HYB_EINVAL, "rotation (omega_rot) is defined on HYB_GEOM_SHELL meshes only");
   return HYB_OK;
@@ -173,7 +177,7 @@ void free_all(hyb_ctx *c) {
     dfree(L.est), dfree(L.parent), dfree(L.children), dfree(L.H), dfree(L.Hf);
     dfree(L.zf), dfree(L.zff), dfree(L.b), dfree(L.x), dfree(L.y), dfree(L.r), dfree(L.w);
   }
-  dfree(c->dz_d), dfree(c->corners_d), dfree(c->radius_d), dfree(c->vol), dfree(c->A), dfree(c->LU), dfree(c->kv), dfree(c->Scell), dfree(c->bcell);
+  dfree(c->dz_d), dfree(c->corners_d), dfree(c->radius_d), dfree(c->vol), dfree(c->ck), dfree(c->A), dfree(c->LU), dfree(c->kv), dfree(c->Scell), dfree(c->bcell);
   dfree(c->S), dfree(c->Sf), dfree(c->m2l), dfree(c->gamma), dfree(c->gammaf), dfree(c->zfac), dfree(c->zfacf);
   dfree(c->tIn), dfree(c->tA), dfree(c->tB), dfree(c->tR), dfree(c->t64);
   dfree(c->V), dfree(c->Z), dfree(c->partial), dfree(c->hdev);
@@ -288,6 +292,10 @@ int hyb_create(const hyb_mesh *mesh, const hyb_params *params, void *stream, hyb
   }
   c->order = mesh->order;
   if (c->order == 1) c->ntrace *= 4;
+  if (c->order == 1 && params->coarse_mode == 2) {
+    delete c;
+    return HYB_EINVAL;  // the Krylov coarse solve is an order-0 FP64 mode
+  }
   {
     const bool mfma = params->precision == HYB_PREC_MFMA_FP32 || params->precision == HYB_PREC_MFMA_BF16X;
     // MFMA condensation is an order-1 mode

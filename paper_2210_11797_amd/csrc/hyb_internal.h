@@ -119,6 +119,7 @@ struct hyb_ctx {
   double *LU = nullptr;     // [49][ncell] LU factors of A_K (unit lower, no pivoting)
   double *kv = nullptr;     // [6][ncell] diagonal of K_K
   double *vol = nullptr;    // [ncell] cell volumes (the Gauss rule of the mass forms)
+  double *ck = nullptr;     // [10][ncell] vectors of the Krylov coarse solve (coarse_mode 2)
   double *Scell = nullptr;  // [36][ncell] S_K = [A_K^-1]_uu diag(k)  (setup only)
   double *bcell = nullptr;  // [6][ncell] [A_K^-1 R_K]_u
   // trace operator

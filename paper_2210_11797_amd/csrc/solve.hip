@@ -4,6 +4,10 @@
 // Column kernels put one column per lane (64 consecutive columns per wavefront, so every access
 // to a [k][col] array is coalesced) and walk up the column: the tridiagonal Thomas solve keeps its
 // forward-elimination coefficients in LDS and runs the back substitution from there.
+#include <algorithm>
+#include <cmath>
+#include <type_traits>
+
 #include "hyb_internal.h"
 
 namespace hyb {
@@ -596,6 +600,164 @@ hipError_t vcycle(hyb_ctx *c, int l) {
   return hipSuccess;
 }
 
+// ---- Krylov coarse solve of the paper's Configurations 3a / 3b (coarse_mode 2, FP64) ----
+
+// y = H x on multigrid level 0 (the 7-point pressure operator)
+__global__ void k_h_apply(const double *__restrict__ H, const double *__restrict__ x, double *__restrict__ y,
+                          int nlev, int ncol, const int32_t *__restrict__ nbr) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t n = (size_t)nlev * ncol;
+  if (c >= (int)n) return;
+  const int k = c / ncol, col = c - k * ncol;
+  double hx = H[c] * x[c];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) hx += H[(1 + f) * n + c] * x[(size_t)k * ncol + nbr[(size_t)f * ncol + col]];
+  if (k > 0) hx += H[5 * n + c] * x[c - ncol];
+  if (k < nlev - 1) hx += H[6 * n + c] * x[c + ncol];
+  y[c] = hx;
+}
+
+// up to three dot products at once: per-workgroup partial sums part[blk][j] (fixed order)
+__global__ void __launch_bounds__(kBlock) k_dots3(const double *__restrict__ a0, const double *__restrict__ b0,
+                                                  const double *__restrict__ a1, const double *__restrict__ b1,
+                                                  const double *__restrict__ a2, const double *__restrict__ b2,
+                                                  int k, size_t n, double *__restrict__ part) {
+  __shared__ double sm[3][kBlock / 64];
+  double v[3] = {0.0, 0.0, 0.0};
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    v[0] += a0[i] * b0[i];
+    if (k > 1) v[1] += a1[i] * b1[i];
+    if (k > 2) v[2] += a2[i] * b2[i];
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    for (int off = 32; off > 0; off >>= 1) v[j] += __shfl_down(v[j], off, 64);
+    if (lane == 0) sm[j][wave] = v[j];
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double t = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) t += sm[threadIdx.x][w];
+    part[(size_t)blockIdx.x * 3 + threadIdx.x] = t;
+  }
+}
+
+__global__ void k_reduce3(const double *__restrict__ part, int nb, double *__restrict__ out) {
+  if (threadIdx.x < 3) {
+    double t = 0.0;
+    for (int b = 0; b < nb; ++b) t += part[(size_t)b * 3 + threadIdx.x];
+    out[threadIdx.x] = t;
+  }
+}
+
+// p = r + beta (p - omega v)
+__global__ void k_bicg_dir(const double *__restrict__ r, const double *__restrict__ v, double *__restrict__ p,
+                           double beta, double omega, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+}
+
+// y = x + a z
+__global__ void k_axpy_to(const double *__restrict__ x, double a, const double *__restrict__ z, double *__restrict__ y,
+                          size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = x[i] + a * z[i];
+}
+
+// x += a u + w q
+__global__ void k_axpy2(double *__restrict__ x, double a, const double *__restrict__ u, double w,
+                        const double *__restrict__ q, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] += a * u[i] + w * q[i];
+}
+
+// (a_j, b_j) for j < k, summed on the device and read by the host
+hipError_t dots(hyb_ctx *c, int k, const double *a0, const double *b0, const double *a1, const double *b1,
+                const double *a2, const double *b2, size_t n, double *out) {
+  const unsigned nb = std::min<unsigned>(1024, nblk(n));
+  hipLaunchKernelGGL(k_dots3, dim3(nb), dim3(kBlock), 0, c->stream, a0, b0, a1 ? a1 : a0, b1 ? b1 : b0,
+                     a2 ? a2 : a0, b2 ? b2 : b0, k, n, c->partial);
+  hipLaunchKernelGGL(k_reduce3, dim3(1), dim3(64), 0, c->stream, (const double *)c->partial, (int)nb, c->hdev);
+  HYB_TRY(hipGetLastError());
+  HYB_TRY(hipMemcpyAsync(c->hhost, c->hdev, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HYB_TRY(hipStreamSynchronize(c->stream));
+  for (int j = 0; j < k; ++j) out[j] = c->hhost[j];
+  return hipSuccess;
+}
+
+// H x = b on level 0 (b in lv[0].b, x to lv[0].x) by BiCGStab (van der Vorst 1992; the right-preconditioned
+// form of Saad, Iterative Methods for Sparse Linear Systems, Sec. 9.3) with one V-cycle as the
+// preconditioner, from x = 0 until ||b - H x|| <= coarse_rtol ||b|| (at most kCoarseKrylovMax steps)
+constexpr int kCoarseKrylovMax = 200;
+hipError_t coarse_bicgstab(hyb_ctx *c) {
+  LevelDev &L = c->lv[0];
+  const size_t n = (size_t)c->nlev * L.ncol;
+  if (!c->ck) {
+    HYB_TRY(hipMalloc((void **)&c->ck, 10 * n * sizeof(double)));
+    c->bytes += 10 * n * sizeof(double);
+  }
+  double *b = c->ck, *x = b + n, *r = x + n, *rh = r + n, *p = rh + n, *v = p + n, *sv = v + n, *t = sv + n,
+         *ph = t + n, *sh = ph + n;
+  double *Lb = (double *)L.b, *Lx = (double *)L.x;
+  const dim3 g(nblk(n)), bl(kBlock);
+  auto copy = [&](const double *src, double *dst) {
+    hipLaunchKernelGGL((k_copy<double>), g, bl, 0, c->stream, src, dst, n);
+    return hipGetLastError();
+  };
+  auto precond = [&](const double *y, double *yh) -> hipError_t {  // yh = V-cycle applied to y
+    HYB_TRY(copy(y, Lb));
+    HYB_TRY(vcycle<double>(c, 0));
+    return copy(Lx, yh);
+  };
+  auto happly = [&](const double *y, double *Hy) {
+    hipLaunchKernelGGL(k_h_apply, g, bl, 0, c->stream, (const double *)L.H, y, Hy, c->nlev, L.ncol, L.nbr);
+    return hipGetLastError();
+  };
+  HYB_TRY(copy(Lb, b));
+  HYB_TRY(copy(Lb, r));
+  HYB_TRY(copy(Lb, rh));
+  hipLaunchKernelGGL((k_zero<double>), g, bl, 0, c->stream, x, n);
+  hipLaunchKernelGGL((k_zero<double>), g, bl, 0, c->stream, p, n);
+  hipLaunchKernelGGL((k_zero<double>), g, bl, 0, c->stream, v, n);
+  HYB_TRY(hipGetLastError());
+  double d[3];
+  HYB_TRY(dots(c, 1, b, b, nullptr, nullptr, nullptr, nullptr, n, d));
+  const double bn = std::sqrt(d[0]), tol = c->p.coarse_rtol * bn;
+  double rho = 1.0, alpha = 1.0, omega = 1.0, rho1 = d[0];  // rh = r = b at the start
+  for (int it = 0; it < kCoarseKrylovMax && bn > 0.0; ++it) {
+    if (rho1 == 0.0 || omega == 0.0) break;  // breakdown: keep the current iterate
+    const double beta = (rho1 / rho) * (alpha / omega);
+    hipLaunchKernelGGL(k_bicg_dir, g, bl, 0, c->stream, r, v, p, it == 0 ? 0.0 : beta, omega, n);
+    HYB_TRY(hipGetLastError());
+    HYB_TRY(precond(p, ph));
+    HYB_TRY(happly(ph, v));
+    HYB_TRY(dots(c, 1, rh, v, nullptr, nullptr, nullptr, nullptr, n, d));
+    if (d[0] == 0.0) break;
+    alpha = rho1 / d[0];
+    hipLaunchKernelGGL(k_axpy_to, g, bl, 0, c->stream, r, -alpha, v, sv, n);
+    HYB_TRY(hipGetLastError());
+    HYB_TRY(dots(c, 1, sv, sv, nullptr, nullptr, nullptr, nullptr, n, d));
+    if (std::sqrt(d[0]) <= tol) {
+      hipLaunchKernelGGL(k_axpy2, g, bl, 0, c->stream, x, alpha, ph, 0.0, ph, n);
+      HYB_TRY(hipGetLastError());
+      break;
+    }
+    HYB_TRY(precond(sv, sh));
+    HYB_TRY(happly(sh, t));
+    HYB_TRY(dots(c, 2, t, sv, t, t, nullptr, nullptr, n, d));
+    omega = d[1] > 0.0 ? d[0] / d[1] : 0.0;
+    hipLaunchKernelGGL(k_axpy2, g, bl, 0, c->stream, x, alpha, ph, omega, sh, n);
+    hipLaunchKernelGGL(k_axpy_to, g, bl, 0, c->stream, sv, -omega, t, r, n);
+    HYB_TRY(hipGetLastError());
+    rho = rho1;
+    HYB_TRY(dots(c, 2, r, r, rh, r, nullptr, nullptr, n, d));
+    rho1 = d[1];
+    if (std::sqrt(d[0]) <= tol) break;
+  }
+  return copy(x, Lx);
+}
+
 }  // namespace
 
 template <typename Tm, typename Tx, typename Ty>
@@ -640,7 +802,7 @@ hipError_t precondition(hyb_ctx *c, const T *r, T *z) {
       std::swap(tA, tB);
     }
   }
-  if (p.coarse_mode == 0) {
+  if (p.coarse_mode != 1) {
     // residual, restriction and scaling
     HYB_TRY((launch_trace_apply<T, T, T>(c, S, tA, r, tR, 1)));
     int slot = prof_begin(c, F_RESTRICT);
@@ -648,8 +810,15 @@ hipError_t precondition(hyb_ctx *c, const T *r, T *z) {
                        c->nlev, c->ncol, c->nedge, (size_t)c->nz, L0.col_edge);
     prof_end(c, F_RESTRICT, slot);
     HYB_TRY(hipGetLastError());
-    // coarse solve: one pressure multigrid V-cycle
-    HYB_TRY(vcycle<T>(c, 0));
+    // coarse solve: one pressure multigrid V-cycle, or (coarse_mode 2, FP64) BiCGStab preconditioned by it
+    if (p.coarse_mode == 2) {
+      if constexpr (std::is_same<T, double>::value)
+        HYB_TRY(coarse_bicgstab(c));
+      else
+        return hipErrorInvalidValue;  // rejected by the parameter check
+    } else {
+      HYB_TRY(vcycle<T>(c, 0));
+    }
     // prolongation and update
     slot = prof_begin(c, F_PROLONG);
     hipLaunchKernelGGL((k_prolong<T>), dim3(nblk(ntr)), dim3(kBlock), 0, c->stream, (const T *)c->lv[0].x, tA,

@@ -137,6 +137,16 @@ def solver_sequence(lib):
     rc, info, lam = c.solve(b, 1e-8, maxit=2000)
     check(rc == 0 and c.residual(b, lam) <= 1.01e-8, f"single-level FGMRES(5): {info.iters} iterations")
     c.set(coarse_mode=0, n_pre=1, n_post=2)
+    # the Krylov coarse solve (BiCGStab + V-cycle on the coarse pressure system): loose and tight
+    for crt in (1e-2, 1e-14):
+        c.set(coarse_mode=2, coarse_rtol=crt)
+        c.call("hyb_precondition", P(b), P(z))
+        rc, info, lam = c.solve(b, 1e-8)
+        check(rc == 0 and c.residual(b, lam) <= 1.01e-8, f"Krylov coarse solve to {crt:.0e}: {info.iters} iterations")
+    bad = N.Params(**{**c.params.__dict__, "precision": N.PREC_MIXED})
+    cp_bad = bad.to_c()
+    check(lib.hyb_set_params(c.h, ctypes.byref(cp_bad)) < 0, "the Krylov coarse solve in the mixed form is rejected")
+    c.set(coarse_mode=0)
     c.set(precision=N.PREC_MIXED, restart=30)
     c.call("hyb_precondition", P(b), P(z))
     rc, info, lam = c.solve(b, 1e-8)

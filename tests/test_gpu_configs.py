@@ -107,3 +107,41 @@ def test_single_level_iterations_and_ordering():
     say(f"[single-level] iterations {its}")
     assert its["3c"] < min(its[1], its[2], its[3])
     assert its[3] < its[1]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("rtol", [1e-14, 1e-2])
+def test_krylov_coarse_solve(rtol):
+    """The paper's Configurations 3a (rtol 1e-14) and 3b (1e-2): the two-level cycle whose coarse
+    pressure system is solved by BiCGStab preconditioned by the V-cycle.  The preconditioner against
+    the oracle's (the same BiCGStab steps; 1e-9 of the largest entry), and for 3a against the cycle
+    with an exact coarse solve; FGMRES iteration counts against the oracle's (+-1)."""
+    import scipy.sparse.linalg as spla
+    import torch
+
+    prob = make_box(**BOX)
+    s = make_solver(prob, coarse_mode=2, coarse_rtol=rtol)
+    orc = OracleProblem(prob, coarse=("bicgstab", rtol))
+    r = np.random.default_rng(6).standard_normal(orc.mesh.ntrace)
+    z = torch.empty(orc.mesh.ntrace, dtype=torch.float64, device="cuda")
+    s.precondition(dev(r), z)
+    zref = orc.pc(r)
+    err = rel_max(host(z), zref)
+    pc = orc.pc
+    lam = pc.line_smooth(np.zeros_like(r), r, pc.n_pre)
+    Bbar = pc.gamma * (pc.P.T @ (r - pc.S @ lam))
+    zexact = pc.line_smooth(lam + pc.P @ spla.spsolve(pc.mg.H[0].tocsc(), Bbar), r, pc.n_post)
+    err_exact = rel_max(host(z), zexact)
+    r_ub, r_pi = make_rhs(prob, 2)
+    B = orc.hyb.rhs(*cells_from_soa(r_ub, r_pi))
+    _, _, oits, _ = orc.solve_fgmres(B, rtol=1e-8)
+    b = dev(B)
+    lam_d = torch.zeros_like(b)
+    info = s.solve(b, lam_d, rtol=1e-8)
+    say(f"[krylov coarse {rtol:.0e}] precondition err {err:.2e} (vs exact coarse solve {err_exact:.2e}); "
+        f"FGMRES gpu {info['iters']} oracle {oits}")
+    assert err <= 1e-9
+    if rtol < 1e-12:
+        assert err_exact <= 1e-9
+    assert info["status"] == 0 and abs(info["iters"] - oits) <= 1
+    s.close()

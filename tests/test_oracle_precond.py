@@ -219,3 +219,43 @@ def test_single_level_configuration():
         its[n] = o.solve_fgmres(B, rtol=1e-8, maxit=2000)[2]
     its["3c"] = OracleProblem(prob).solve_fgmres(B, rtol=1e-8)[2]
     assert its["3c"] < its[3] < its[1]
+
+
+def test_bicgstab_and_krylov_coarse_solve():
+    """BiCGStab reaches its tolerance and the sparse direct solution; with the exact inverse as the
+    preconditioner it stops after one half step; the two-level cycle with the coarse system solved
+    to 1e-14 by BiCGStab + V-cycle (the paper's Configuration 3a) is the cycle with an exact coarse
+    solve, and 1e-2 (3b) leaves at most that coarse residual."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+
+    from oracle.krylov import bicgstab
+    from oracle.problem import OracleProblem, cells_from_soa
+    from synth import make_box, make_rhs
+
+    rng = np.random.default_rng(5)
+    n = 60
+    A = sp.random(n, n, density=0.1, random_state=5) + sp.diags(4.0 + rng.random(n))
+    A = A.tocsr()
+    b = rng.standard_normal(n)
+    xd = spla.spsolve(A.tocsc(), b)
+    x = bicgstab(lambda v: A @ v, lambda v: v, b, 1e-12)
+    assert np.linalg.norm(b - A @ x) <= 1e-12 * np.linalg.norm(b)
+    assert np.linalg.norm(x - xd) <= 1e-10 * np.linalg.norm(xd)
+    lu = spla.splu(A.tocsc())
+    calls = []
+    x1 = bicgstab(lambda v: (calls.append(1), A @ v)[1], lu.solve, b, 1e-12)
+    assert len(calls) == 1 and np.linalg.norm(x1 - xd) <= 1e-12 * np.linalg.norm(xd)
+
+    prob = make_box(nx=12, ny=12, nlev=8, dx=10e3, dz=1250.0, mg_levels=3, perturb=0.05)
+    o = OracleProblem(prob)
+    B = o.hyb.rhs(*cells_from_soa(*make_rhs(prob, 1)))
+    pc = o.pc
+    lam = pc.line_smooth(np.zeros_like(B), B, pc.n_pre)
+    Bbar = pc.gamma * (pc.P.T @ (B - pc.S @ lam))
+    H0 = pc.mg.H[0]
+    zexact = pc.line_smooth(lam + pc.P @ spla.spsolve(H0.tocsc(), Bbar), B, pc.n_post)
+    o3a = OracleProblem(prob, coarse=("bicgstab", 1e-14))
+    np.testing.assert_allclose(o3a.pc(B), zexact, rtol=0, atol=1e-10 * np.abs(zexact).max())
+    dpi = bicgstab(lambda v: H0 @ v, pc.mg.vcycle, Bbar, 1e-2)
+    assert np.linalg.norm(Bbar - H0 @ dpi) <= 1e-2 * np.linalg.norm(Bbar)
