@@ -268,6 +268,54 @@ def configs_leg(args, prob, rhs):
     return out
 
 
+def appendix_b_leg(args, prob, rhs):
+    """The paper's solver-parameter study (its appendix on solver parameters) on the benchmark box:
+    time-to-1e-8 and iterations of the hybridised single-level method (Configuration 2) over the
+    smoother's relaxation factor omega = 0.3 ... 1.0 and 1, 2, 3 sweeps, and of the two-level cycle
+    (Configuration 3c; pressure V-cycle fixed) over omega and 1-3 pre- / 1-2 post-smoothing steps.
+    A run that has not reached the tolerance within its iteration cap (3000 for Configuration 2,
+    300 for 3c) counts as not converged (status 1)."""
+    import torch
+
+    omegas = (0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9, 1.0)
+    out = {"configuration_2": {}, "configuration_3c": {}}
+
+    def one(s, maxit):
+        b = torch.empty(s.ntrace, dtype=torch.float64, device="cuda")
+        lam = torch.zeros_like(b)
+        s.condense(rhs[0][0], rhs[0][1], b)
+        s.solve(b, lam, rtol=args.rtol, maxit=2)  # allocates the Krylov basis outside the timing
+        lam.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = s.solve(b, lam, rtol=args.rtol, maxit=maxit)
+        torch.cuda.synchronize()
+        return dict(sec_per_solve=time.perf_counter() - t0, iters=info["iters"], rel_res=info["rel_res"],
+                    status=info["status"])
+
+    for n in (1, 2, 3):
+        row = out["configuration_2"][f"{n}_sweeps"] = {}
+        for om in omegas:
+            s = setup_solver(prob, 0, coarse_mode=1, n_pre=n, n_post=0, omega=om,
+                             mg_coarse_sweeps=args.coarse_sweeps)
+            row[f"{om:.1f}"] = r = one(s, 3000)
+            s.close()
+            log(f"appendix B, configuration 2, {n} sweep(s), omega {om:.1f}: {r['sec_per_solve'] * 1e3:.0f} ms, "
+                f"{r['iters']} iterations, status {r['status']}")
+    for n_pre in (1, 2, 3):
+        for n_post in (1, 2):
+            row = out["configuration_3c"][f"{n_pre}_pre_{n_post}_post"] = {}
+            for om in omegas:
+                s = setup_solver(prob, 0, n_pre=n_pre, n_post=n_post, omega=om,
+                                 mg_coarse_sweeps=args.coarse_sweeps)
+                row[f"{om:.1f}"] = r = one(s, 300)
+                s.close()
+                log(f"appendix B, configuration 3c, {n_pre} pre {n_post} post, omega {om:.1f}: "
+                    f"{r['sec_per_solve'] * 1e3:.1f} ms, {r['iters']} iterations, status {r['status']}")
+    torch.cuda.empty_cache()
+    return out
+
+
 def sphere_leg(args):
     """The extruded cubed sphere (C192 x 30 quadratic layers to 30 km, dt = 1800 s, rotating, the
     Gaussian pressure bump): time-to-1e-8 of the plain FP64 solve and of the mixed form, their
@@ -528,6 +576,8 @@ def main():
     ap.add_argument("--no-sphere", action="store_true")
     ap.add_argument("--no-configs", action="store_true")
     ap.add_argument("--no-c384", action="store_true")
+    ap.add_argument("--appendix-b", action="store_true",
+                    help="also run the solver-parameter sweep (Configurations 2 and 3c over omega and smoothing steps)")
     ap.add_argument("--c384-n", type=int, default=384)
     ap.add_argument("--c384-nlev", type=int, default=70)
     ap.add_argument("--c384-dt", type=float, default=900.0)
@@ -616,6 +666,14 @@ def main():
             log(f"configs leg failed: {e}")
             configs_out = {"error": str(e)}
 
+    appb_out = None
+    if args.appendix_b:
+        try:
+            appb_out = appendix_b_leg(args, prob, rhs)
+        except Exception as e:
+            log(f"appendix B leg failed: {e}")
+            appb_out = {"error": str(e)}
+
     sphere_out = None
     if not args.no_sphere:
         try:
@@ -684,6 +742,7 @@ def main():
         "mixed": mixed,
         "learned": learned_out,
         "configurations": configs_out,
+        "appendix_b": appb_out,
         "sphere": sphere_out,
         "c384": c384_out,
         "p1": p1_out,

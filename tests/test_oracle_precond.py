@@ -221,6 +221,43 @@ def test_single_level_configuration():
     assert its["3c"] < its[3] < its[1]
 
 
+def test_line_smooth_error_propagation():
+    """k LineSmooth sweeps from zero are a preconditioner M_k with I - M_k S = (I - omega D^-1 S)^k
+    (Alg. 1 is a damped block-Jacobi iteration).  Consequences the solver-parameter study relies on:
+    one sweep is omega D^-1, a scalar multiple of a fixed map, so FGMRES takes the same iterations
+    for every omega; and where omega mu > 2 for an eigenvalue mu of D^-1 S, an even k makes the
+    eigenvalue 1 - (1 - omega mu)^k of M_k S negative (an indefinite preconditioned operator)."""
+    import scipy.sparse.linalg as spla
+
+    from oracle.precond import line_smoother_matrix
+    from oracle.problem import OracleProblem, cells_from_soa
+    from synth import make_box, make_rhs
+
+    prob = make_box(nx=8, ny=8, nlev=8, dx=10e3, dz=1250.0, mg_levels=2, perturb=0.05)
+    x = np.random.default_rng(9).standard_normal(OracleProblem(prob, with_precond=False).mesh.ntrace)
+    for om in (0.6, 0.9):
+        for k in (1, 2, 3):
+            o = OracleProblem(prob, omega=om, n_pre=k, n_post=0, coarse=False)
+            S = o.hyb.S
+            lu = spla.splu(line_smoother_matrix(o.mesh, S).tocsc())
+            e = x.copy()
+            for _ in range(k):
+                e = e - om * lu.solve(S @ e)
+            np.testing.assert_allclose(x - o.pc(S @ x), e, rtol=1e-10, atol=1e-10 * np.abs(x).max())
+    B = cells_from_soa(*make_rhs(prob, 0))
+    its = []
+    for om in (0.3, 0.9):
+        o = OracleProblem(prob, omega=om, n_pre=1, n_post=0, coarse=False)
+        its.append(o.solve_fgmres(o.hyb.rhs(*B), rtol=1e-8, maxit=2000)[2])
+    assert its[0] == its[1]
+    mu = np.linalg.eigvals(spla.splu(line_smoother_matrix(o.mesh, S).tocsc()).solve(S.toarray())).real
+    om = 2.2 / mu.max()
+    lam2 = 1.0 - (1.0 - om * mu) ** 2
+    assert lam2.min() < 0 < lam2.max()
+    lam3 = 1.0 - (1.0 - om * mu) ** 3
+    assert lam3.min() > 0
+
+
 def test_bicgstab_and_krylov_coarse_solve():
     """BiCGStab reaches its tolerance and the sparse direct solution; with the exact inverse as the
     preconditioner it stops after one half step; the two-level cycle with the coarse system solved
