@@ -220,6 +220,43 @@ int hyb_solve(hyb_ctx *ctx, const double *b_lambda, double *lambda, double rtol,
 int hyb_recover(hyb_ctx *ctx, const double *r_ub, const double *r_pi, const double *lambda,
                 double *u_b, double *pi);
 
+/* ----- Configuration 1 of the paper: the unhybridised system (Sec. 2.2, 2.3) -----
+   The velocity / Exner-pressure system of Sec. 2.2 on the same assembled cells (order 0 only;
+   HYB_EINVAL otherwise; HYB_ESTATE before hyb_condense, whose setup it uses: the lumped
+   velocity mass and the pressure multigrid hierarchy).  A mixed vector has ntrace + ncell FP64
+   entries in device memory: first the velocity on every facet of the trace numbering in the
+   facet's global orientation (+z for horizontal facets; for vertical facets the normal leaving
+   the first column of the edge), the ground and lid facets, which carry no velocity dof, held
+   at zero; then the Exner pressure of every cell ([nlev][ncol]).  These calls are FP64 whatever
+   hyb_params.precision says, and do not use the learned stage. */
+
+/* b = the mixed right-hand side from the broken one: R_u on facet F is the sum over the two
+   cells of F of the orientation sign times r_ub of that cell face (Sec. 2.4), R_Pi = r_pi.
+   r_ub [6][nlev][ncol], r_pi [nlev][ncol] as for hyb_condense; b [ntrace + ncell]. */
+int hyb_mixed_rhs(hyb_ctx *ctx, const double *r_ub, const double *r_pi, double *b);
+
+/* y = the mixed operator of Sec. 2.2 (velocity block M2 - Q22 with the Coriolis term on a
+   rotating sphere, gradient G including the facet term of the form g, divergence rows
+   Q32 + M3rho M3^-1 D, M3Pi) applied to x; y is zero on the ground and lid facets.  x and y
+   [ntrace + ncell], distinct. */
+int hyb_mixed_apply(hyb_ctx *ctx, const double *x, double *y);
+
+/* z = the approximate-Schur preconditioner of Sec. 2.3 applied to r: Step 1 the pressure
+   right-hand side with the lumped velocity mass, Step 2 one pressure multigrid V-cycle from
+   zero (the same cycle and parameters as the coarse step of Alg. 2), Step 3 the velocity from
+   the lumped mass.  r and z [ntrace + ncell], distinct; z is zero on the ground and lid.
+   Uses the level-0 multigrid work vectors, like hyb_precondition. */
+int hyb_mixed_precondition(hyb_ctx *ctx, const double *r, double *z);
+
+/* Flexible GMRES(restart) on the mixed system, right preconditioned by hyb_mixed_precondition
+   (the paper's Configuration 1).  x [ntrace + ncell] is the initial guess on entry and the
+   solution on exit.  Stops when ||b - A x|| / ||b|| <= rtol (the unweighted 2-norm of the
+   mixed residual) or after maxit iterations; returns as hyb_solve.  Allocates on its first
+   call a second Krylov basis of (2 restart + 1) (ntrace + ncell) doubles, kept until
+   hyb_destroy. */
+int hyb_mixed_solve(hyb_ctx *ctx, const double *b, double *x, double rtol, int32_t maxit,
+                    hyb_info *info);
+
 /* Sizes of the trace system: ntrace, and the bytes of device workspace held. */
 int hyb_sizes(const hyb_ctx *ctx, int64_t *ntrace, int64_t *ncell, int64_t *workspace_bytes);
 

@@ -99,6 +99,7 @@ ABI_FUNCTIONS = [
     "hyb_precondition", "hyb_solve", "hyb_recover", "hyb_sizes", "hyb_profile", "hyb_profile_family", "hyb_profile_read",
     "hyb_restrict", "hyb_nn_param_count", "hyb_nn_set_weights", "hyb_nn_get_weights", "hyb_nn_forward",
     "hyb_nn_loss_grad", "hyb_nn_train_step", "hyb_nn_energy_grad", "hyb_nn_energy_train_step",
+    "hyb_mixed_rhs", "hyb_mixed_apply", "hyb_mixed_precondition", "hyb_mixed_solve",
     "hyb_last_error", "hyb_destroy",
 ]
 
@@ -147,6 +148,10 @@ def declare(lib):
     lib.hyb_nn_energy_grad.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), vp]
     lib.hyb_nn_energy_train_step.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.c_float,
                                              ctypes.POINTER(ctypes.c_double)]
+    lib.hyb_mixed_rhs.argtypes = [vp, vp, vp, vp]
+    lib.hyb_mixed_apply.argtypes = [vp, vp, vp]
+    lib.hyb_mixed_precondition.argtypes = [vp, vp, vp]
+    lib.hyb_mixed_solve.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(_Info)]
     lib.hyb_last_error.argtypes = [vp]
     lib.hyb_last_error.restype = ctypes.c_char_p
     lib.hyb_destroy.argtypes = [vp]
@@ -277,6 +282,31 @@ class HybSolver:
     def precondition(self, r, z):
         self._check(self.lib.hyb_precondition(self.h, _ptr(r, self.ntrace, "r"), _ptr(z, self.ntrace, "z")),
                     "hyb_precondition")
+
+    # the unhybridised system (the paper's Configuration 1): vectors of ntrace + ncell doubles
+    @property
+    def nmixed(self):
+        return self.ntrace + self.ncell
+
+    def mixed_rhs(self, r_ub, r_pi, b):
+        self._check(self.lib.hyb_mixed_rhs(self.h, _ptr(r_ub, 6 * self.ncell, "r_ub"), _ptr(r_pi, self.ncell, "r_pi"),
+                                           _ptr(b, self.nmixed, "b")), "hyb_mixed_rhs")
+
+    def mixed_apply(self, x, y):
+        self._check(self.lib.hyb_mixed_apply(self.h, _ptr(x, self.nmixed, "x"), _ptr(y, self.nmixed, "y")),
+                    "hyb_mixed_apply")
+
+    def mixed_precondition(self, r, z):
+        self._check(self.lib.hyb_mixed_precondition(self.h, _ptr(r, self.nmixed, "r"), _ptr(z, self.nmixed, "z")),
+                    "hyb_mixed_precondition")
+
+    def mixed_solve(self, b, x, rtol=1e-8, maxit=500, history=256):
+        hist = (ctypes.c_double * max(1, history))()
+        info = _Info(0, 0, 0, 0.0, ctypes.cast(hist, _f64p), history, 0)
+        rc = self._check(self.lib.hyb_mixed_solve(self.h, _ptr(b, self.nmixed, "b"), _ptr(x, self.nmixed, "x"),
+                                                  float(rtol), int(maxit), ctypes.byref(info)), "hyb_mixed_solve")
+        return dict(status=rc, iters=info.iters, restarts=info.restarts, rel_res=info.rel_res,
+                    history=[hist[i] for i in range(info.history_len)])
 
     def solve(self, b_lambda, lam, rtol=1e-8, maxit=500, history=256):
         hist = (ctypes.c_double * max(1, history))()

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhyb.so")
-SOURCES = ["api.hip", "assemble.hip", "solve.hip", "krylov.hip", "nn.hip", "p1.hip"]
+SOURCES = ["api.hip", "assemble.hip", "solve.hip", "krylov.hip", "nn.hip", "p1.hip", "schur.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

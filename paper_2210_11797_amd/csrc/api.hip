@@ -180,7 +180,7 @@ void free_all(hyb_ctx *c) {
   dfree(c->dz_d), dfree(c->corners_d), dfree(c->radius_d), dfree(c->vol), dfree(c->ck), dfree(c->A), dfree(c->LU), dfree(c->kv), dfree(c->Scell), dfree(c->bcell);
   dfree(c->S), dfree(c->Sf), dfree(c->m2l), dfree(c->gamma), dfree(c->gammaf), dfree(c->zfac), dfree(c->zfacf);
   dfree(c->tIn), dfree(c->tA), dfree(c->tB), dfree(c->tR), dfree(c->t64);
-  dfree(c->V), dfree(c->Z), dfree(c->partial), dfree(c->hdev);
+  dfree(c->V), dfree(c->Z), dfree(c->Vm), dfree(c->Zm), dfree(c->partial), dfree(c->hdev);
   if (c->hhost) (void)hipHostFree(c->hhost);
   c->hhost = nullptr;
   for (auto &f : c->fam)
@@ -207,6 +207,258 @@ int alloc_krylov(hyb_ctx *c) {
   CHECK_HIP(hipHostMalloc((void **)&c->hhost, 4 * (size_t)(m + 2) * sizeof(double), hipHostMallocDefault),
             "hipHostMalloc");
   return HYB_OK;
+}
+
+// Flexible GMRES(m) from x on n-vectors, right preconditioned, FP64 basis V [(m+1)][n] and
+// preconditioned basis Z [m][n] (FP32 when zf32).  resid(V0) writes b - A x into V0 (not called
+// while x is zero); apply(j) writes Z_j = M V_j and V_{j+1} = A Z_j.  Returns the status
+// (HYB_OK, HYB_NOT_CONVERGED, HYB_BREAKDOWN) or a negative error code.
+template <typename Resid, typename Apply>
+int fgmres(hyb_ctx *c, size_t n, double *V, void *Zbuf, bool zf32, const double *b, double *x, double rtol,
+           int32_t maxit, hyb_info *info, Resid resid, Apply apply_op) {
+  const int m = c->m;
+  int rc = 0;
+  double *h1 = c->hdev, *h2 = c->hdev + (m + 2), *nrm = c->hdev + 2 * (m + 2);
+  double *hh = c->hhost;
+  std::vector<double> R((size_t)(m + 1) * m, 0.0), g(m + 1), cs(m), sn(m), y(m);
+  if (info) {
+    info->iters = 0, info->restarts = 0, info->history_len = 0, info->rel_res = 0, info->status = HYB_OK;
+    info->fallbacks = 0;
+  }
+  // ||b|| and ||lambda_0||^2: from a zero initial guess the first residual is b itself
+  CHECK_HIP(launch_multidot(c, b, 0, 0, b, n, nrm, true), "norm b");
+  CHECK_HIP(launch_multidot(c, x, 0, 0, x, n, nrm + 1, true), "norm x");
+  CHECK_HIP(hipMemcpyAsync(hh, nrm, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream), "d2h");
+  CHECK_HIP(hipStreamSynchronize(c->stream), "sync");
+  double bnorm = std::sqrt(hh[0]);
+  bool x_zero = hh[1] == 0.0;
+  if (!std::isfinite(bnorm)) return fail(c, HYB_EINVAL, "right-hand side is not finite");
+  if (bnorm == 0.0) {
+    CHECK_HIP(launch_fill(c, x, n, 0.0), "zero");
+    return HYB_OK;
+  }
+  int its = 0, restarts = 0, status = HYB_NOT_CONVERGED;
+  double rel = 0.0;
+  for (;;) {
+    // true residual r = b - S lam into V_0
+    if (x_zero)
+      CHECK_HIP(hipMemcpyAsync(V, b, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream), "residual");
+    else if ((rc = resid(V)))
+      return rc;
+    x_zero = false;
+    CHECK_HIP(launch_multidot(c, V, 0, 0, V, n, nrm, true), "norm r");
+    CHECK_HIP(hipMemcpyAsync(hh, nrm, sizeof(double), hipMemcpyDeviceToHost, c->stream), "d2h");
+    CHECK_HIP(hipStreamSynchronize(c->stream), "sync");
+    double beta = std::sqrt(hh[0]);
+    rel = beta / bnorm;
+    if (!std::isfinite(rel)) {
+      status = HYB_BREAKDOWN;
+      break;
+    }
+    if (rel <= rtol) {
+      status = HYB_OK;
+      break;
+    }
+    if (its >= maxit) break;
+    if (its > 0) restarts++;
+    CHECK_HIP(launch_scale(c, V, n, 1.0 / beta), "scale");
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int jend = 0;
+    bool breakdown = false;
+    if (m <= kDgsMax) {
+      // Arnoldi with classical Gram-Schmidt and delayed reorthogonalisation: step j applies the
+      // operator to V_j as orthogonalised once in step j - 1 (scaled by the estimated norm eta),
+      // then one reduction pass gives the dots that finish V_j (second orthogonalisation, exact
+      // norm rho) and orthogonalise w once, and one update pass writes both.  Column j - 1 of the
+      // Hessenberg matrix is completed with eta_j a and eta_j rho; the Givens QR of the columns
+      // so far is redone every step from the unrotated matrix Hr.
+      std::vector<double> Hr((size_t)(m + 1) * m, 0.0), ca(m), cb(m);
+      double eta_prev = 1.0, g0 = beta;
+      for (int j = 0; j < m; ++j) {
+        if ((rc = apply_op(j))) return rc;
+        CHECK_HIP(launch_dgs_dots(c, V, n, j, c->hdev), "gram-schmidt dots");
+        CHECK_HIP(hipMemcpyAsync(hh, c->hdev, (2 * (size_t)j + 3) * sizeof(double), hipMemcpyDeviceToHost, c->stream),
+                  "d2h");
+        CHECK_HIP(hipStreamSynchronize(c->stream), "sync");
+        double a2 = 0.0, ab = 0.0, b2 = 0.0;
+        for (int k = 0; k < j; ++k) {
+          ca[k] = hh[k], cb[k] = hh[j + 1 + k];
+          a2 += ca[k] * ca[k], ab += ca[k] * cb[k], b2 += cb[k] * cb[k];
+        }
+        const double rho2 = hh[j] - a2;
+        if (!(rho2 > 0.0) || !std::isfinite(rho2)) {
+          breakdown = true;
+          break;
+        }
+        const double rho = std::sqrt(rho2);
+        if (j == 0) {
+          g0 = beta * rho;  // r = beta V_0 (as scaled) = beta rho v_0
+        } else {
+          double *prev = &Hr[(size_t)(j - 1) * (m + 1)];
+          for (int k = 0; k < j; ++k) prev[k] += eta_prev * ca[k];
+          prev[j] = eta_prev * rho;
+        }
+        double *col = &Hr[(size_t)j * (m + 1)];
+        const double hjj = (hh[2 * j + 1] - ab) / rho;
+        for (int k = 0; k < j; ++k) col[k] = cb[k];
+        col[j] = hjj;
+        const double eta2 = hh[2 * j + 2] - b2 - hjj * hjj;
+        const double eta = (eta2 > 0.0 && std::isfinite(eta2)) ? std::sqrt(eta2) : 0.0;
+        col[j + 1] = eta;
+        CHECK_HIP(launch_dgs_update(c, V, n, j, ca.data(), cb.data(), 1.0 / rho, hjj, eta > 0.0 ? 1.0 / eta : 0.0,
+                                    zf32 ? (float *)c->tIn : nullptr),
+                  "gram-schmidt update");
+        eta_prev = eta;
+        // Givens QR of columns 0..j
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = g0;
+        bool bad = false;
+        for (int q = 0; q <= j; ++q) {
+          double *rq = &R[(size_t)q * (m + 1)];
+          const double *hq = &Hr[(size_t)q * (m + 1)];
+          for (int i = 0; i <= q + 1; ++i) rq[i] = hq[i];
+          for (int i = 0; i < q; ++i) {
+            const double x = rq[i], z = rq[i + 1];
+            rq[i] = cs[i] * x + sn[i] * z;
+            rq[i + 1] = -sn[i] * x + cs[i] * z;
+          }
+          const double rr = std::hypot(rq[q], rq[q + 1]);
+          if (!(rr > 0) || !std::isfinite(rr)) {
+            bad = true;
+            break;
+          }
+          cs[q] = rq[q] / rr;
+          sn[q] = rq[q + 1] / rr;
+          rq[q] = rr;
+          rq[q + 1] = 0.0;
+          g[q + 1] = -sn[q] * g[q];
+          g[q] = cs[q] * g[q];
+        }
+        if (bad) {
+          breakdown = true;
+          break;
+        }
+        its++;
+        jend = j + 1;
+        const double est = std::fabs(g[j + 1]) / bnorm;
+        if (info && info->history && info->history_len < info->history_cap) info->history[info->history_len++] = est;
+        if (!std::isfinite(est)) {
+          breakdown = true;
+          break;
+        }
+        if (est <= rtol || its >= maxit || eta == 0.0) break;
+      }
+    } else
+    for (int j = 0; j < m; ++j) {
+      double *w = V + (size_t)(j + 1) * n;
+      if ((rc = apply_op(j))) return rc;
+      double *col = &R[(size_t)j * (m + 1)];
+      double hn;
+      bool scaled = false;
+      if (j + 1 <= 32) {
+        // classical Gram-Schmidt with reorthogonalisation in three passes over the basis and one
+        // host read: h1 = V^T w; w -= V h1 while h2 = V^T w and ||w||^2 accumulate; the last pass
+        // subtracts V h2 and normalises with ||w - V h2||^2 = ||w||^2 - ||h2||^2 (V orthonormal)
+        CHECK_HIP(launch_gs_passes(c, V, n, j + 1, w, h1, h2), "gram-schmidt");
+        CHECK_HIP(hipMemcpyAsync(hh, c->hdev, 2 * (size_t)(m + 2) * sizeof(double), hipMemcpyDeviceToHost,
+                                 c->stream),
+                  "d2h");
+        CHECK_HIP(hipStreamSynchronize(c->stream), "sync");
+        double h2sq = 0.0;
+        for (int i = 0; i <= j; ++i) {
+          col[i] = hh[i] + hh[(m + 2) + i];
+          h2sq += hh[(m + 2) + i] * hh[(m + 2) + i];
+        }
+        double wp2 = hh[(m + 2) + j + 1];
+        hn = std::sqrt(std::max(0.0, wp2 - h2sq));
+        if (hn > 0.0 && std::isfinite(hn)) {
+          CHECK_HIP(launch_gs_finish(c, V, n, j + 1, h2, w, 1.0 / hn), "gram-schmidt finish");
+          scaled = true;
+        }
+      } else {
+        // long restart cycles: classical Gram-Schmidt, second pass when the first one cancelled
+        // more than half of the norm (||w'|| < ||w|| / sqrt(2))
+        CHECK_HIP(launch_multidot(c, V, n, j + 1, w, n, h1, true), "cgs1");
+        CHECK_HIP(launch_axpy_norm(c, V, n, j + 1, h1, w, n, nrm), "cgs1 update");
+        CHECK_HIP(hipMemcpyAsync(hh, c->hdev, 3 * (size_t)(m + 2) * sizeof(double), hipMemcpyDeviceToHost,
+                                 c->stream),
+                  "d2h");
+        CHECK_HIP(hipStreamSynchronize(c->stream), "sync");
+        for (int i = 0; i <= j; ++i) col[i] = hh[i];
+        double w2 = hh[j + 1], wp2 = hh[2 * (m + 2)];
+        if (!(wp2 >= 0.5 * w2)) {
+          CHECK_HIP(launch_multidot(c, V, n, j + 1, w, n, h2, false), "cgs2");
+          CHECK_HIP(launch_axpy_norm(c, V, n, j + 1, h2, w, n, nrm), "cgs2 update");
+          CHECK_HIP(hipMemcpyAsync(hh, c->hdev, 3 * (size_t)(m + 2) * sizeof(double), hipMemcpyDeviceToHost,
+                                   c->stream),
+                    "d2h");
+          CHECK_HIP(hipStreamSynchronize(c->stream), "sync");
+          for (int i = 0; i <= j; ++i) col[i] += hh[(m + 2) + i];
+          wp2 = hh[2 * (m + 2)];
+          c->reorth++;
+        }
+        hn = std::sqrt(wp2);
+      }
+      col[j + 1] = hn;
+      for (int i = 0; i < j; ++i) {
+        double a = col[i], bb = col[i + 1];
+        col[i] = cs[i] * a + sn[i] * bb;
+        col[i + 1] = -sn[i] * a + cs[i] * bb;
+      }
+      double a = col[j], bb = col[j + 1];
+      double rr = std::hypot(a, bb);
+      if (!(rr > 0) || !std::isfinite(rr)) {
+        breakdown = true;
+        jend = j;
+        break;
+      }
+      cs[j] = a / rr;
+      sn[j] = bb / rr;
+      col[j] = rr;
+      col[j + 1] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      its++;
+      jend = j + 1;
+      double est = std::fabs(g[j + 1]) / bnorm;
+      if (info && info->history && info->history_len < info->history_cap) info->history[info->history_len++] = est;
+      if (!std::isfinite(est)) {
+        breakdown = true;
+        break;
+      }
+      if (est <= rtol || its >= maxit || hn == 0.0) break;
+      if (!scaled) CHECK_HIP(launch_scale(c, w, n, 1.0 / hn), "scale");
+    }
+    if (jend > 0) {
+      for (int i = jend - 1; i >= 0; --i) {
+        double s = g[i];
+        for (int k = i + 1; k < jend; ++k) s -= R[(size_t)k * (m + 1) + i] * y[k];
+        y[i] = s / R[(size_t)i * (m + 1) + i];
+      }
+      // y goes to the device through the pinned buffer (after the last sync the buffer is free)
+      std::copy(y.begin(), y.begin() + jend, hh + 3 * (m + 2));
+      double *ydev = c->hdev + 3 * (m + 2);
+      CHECK_HIP(hipMemcpyAsync(ydev, hh + 3 * (m + 2), jend * sizeof(double), hipMemcpyHostToDevice, c->stream),
+                "h2d");
+      if (zf32)
+        CHECK_HIP(launch_update_solution<float>(c, (const float *)Zbuf, n, jend, ydev, x, n), "update");
+      else
+        CHECK_HIP(launch_update_solution<double>(c, (const double *)Zbuf, n, jend, ydev, x, n), "update");
+      CHECK_HIP(hipStreamSynchronize(c->stream), "sync");
+    }
+    if (breakdown && jend == 0) {
+      status = HYB_BREAKDOWN;
+      break;
+    }
+  }
+  if (info) {
+    info->iters = its;
+    info->restarts = restarts;
+    info->rel_res = rel;
+    info->status = status;
+  }
+  return status;
 }
 
 }  // namespace
@@ -566,285 +818,116 @@ int hyb_solve(hyb_ctx *c, const double *b, double *lam, double rtol, int32_t max
   // changes the preconditioner's copy of S_K, and Z stays FP64)
   const bool mixed = c->p.precision == HYB_PREC_MIXED && c->order == 0;
   double *V = c->V;
-  double *h1 = c->hdev, *h2 = c->hdev + (m + 2), *nrm = c->hdev + 2 * (m + 2);
-  double *hh = c->hhost;
-  std::vector<double> R((size_t)(m + 1) * m, 0.0), g(m + 1), cs(m), sn(m), y(m);
-  if (info) {
-    info->iters = 0, info->restarts = 0, info->history_len = 0, info->rel_res = 0, info->status = HYB_OK;
-    info->fallbacks = 0;
-  }
   const bool learned = c->p.learned && c->nn.loaded;
   if (c->p.learned && !c->nn.loaded) return fail(c, HYB_ESTATE, "learned stage requested without weights");
-  // ||b|| and ||lambda_0||^2: from a zero initial guess the first residual is b itself
-  CHECK_HIP(launch_multidot(c, b, 0, 0, b, n, nrm, true), "norm b");
-  CHECK_HIP(launch_multidot(c, lam, 0, 0, lam, n, nrm + 1, true), "norm lambda");
-  CHECK_HIP(hipMemcpyAsync(hh, nrm, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream), "d2h");
-  CHECK_HIP(hipStreamSynchronize(c->stream), "sync");
-  double bnorm = std::sqrt(hh[0]);
-  bool lam_zero = hh[1] == 0.0;
-  if (!std::isfinite(bnorm)) return fail(c, HYB_EINVAL, "right-hand side is not finite");
-  if (bnorm == 0.0) {
-    CHECK_HIP(launch_fill(c, lam, n, 0.0), "zero");
-    return HYB_OK;
-  }
-  int its = 0, restarts = 0, status = HYB_NOT_CONVERGED;
-  double rel = 0.0, fb0 = 0.0;
+  double fb0 = 0.0;
   if (learned && c->nn.scal) {
     CHECK_HIP(hipMemcpyAsync(&fb0, c->nn.scal + 2, sizeof(double), hipMemcpyDeviceToHost, c->stream), "d2h");
     CHECK_HIP(hipStreamSynchronize(c->stream), "sync");
   }
-  for (;;) {
-    // true residual r = b - S lam into V_0
-    if (lam_zero)
-      CHECK_HIP(hipMemcpyAsync(V, b, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream), "residual");
-    else if (c->order == 1)
-      CHECK_HIP(p1_rows(c, lam, V, 2, b), "residual");
+  auto resid = [&](double *V0) -> int {
+    if (c->order == 1)
+      CHECK_HIP(p1_rows(c, lam, V0, 2, b), "residual");
     else
-      CHECK_HIP((launch_trace_apply<double, double, double>(c, c->S, lam, b, V, 1)), "residual");
-    lam_zero = false;
-    CHECK_HIP(launch_multidot(c, V, 0, 0, V, n, nrm, true), "norm r");
-    CHECK_HIP(hipMemcpyAsync(hh, nrm, sizeof(double), hipMemcpyDeviceToHost, c->stream), "d2h");
-    CHECK_HIP(hipStreamSynchronize(c->stream), "sync");
-    double beta = std::sqrt(hh[0]);
-    rel = beta / bnorm;
-    if (!std::isfinite(rel)) {
-      status = HYB_BREAKDOWN;
-      break;
-    }
-    if (rel <= rtol) {
-      status = HYB_OK;
-      break;
-    }
-    if (its >= maxit) break;
-    if (its > 0) restarts++;
-    CHECK_HIP(launch_scale(c, V, n, 1.0 / beta), "scale");
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
-    int jend = 0;
-    bool breakdown = false;
-    // z_j = M(V_j) into Z, w = S z_j into V_{j+1}
-    auto apply_op = [&](int j) -> int {
-      double *vj = V + (size_t)j * n, *w = V + (size_t)(j + 1) * n;
-      if (mixed) {
-        float *zf = (float *)c->Z + (size_t)j * n;
-        // the two-pass Gram-Schmidt writes the FP32 copy of V_j with V_j itself (steps j > 0)
-        if (j == 0 || m > kDgsMax) CHECK_HIP(launch_convert(c, vj, (float *)c->tIn, n), "convert");
-        CHECK_HIP(precondition<float>(c, (const float *)c->tIn, zf), "precondition");
-        if (learned) CHECK_HIP(learned_stage<float>(c, vj, zf), "learned stage");
-        CHECK_HIP((launch_trace_apply<double, float, double>(c, c->S, zf, nullptr, w, 0)), "matvec");
-      } else if (c->order == 1) {
-        double *zj = (double *)c->Z + (size_t)j * n;
-        CHECK_HIP(p1_precondition(c, vj, zj), "precondition");
-        CHECK_HIP(p1_rows(c, zj, w, 0, nullptr), "matvec");
-      } else {
-        double *zj = (double *)c->Z + (size_t)j * n;
-        CHECK_HIP(precondition<double>(c, vj, zj), "precondition");
-        if (learned)  // the stage's own applications of S give w = S z (no separate matvec)
-          CHECK_HIP(learned_stage<double>(c, vj, zj, w), "learned stage");
-        else
-          CHECK_HIP((launch_trace_apply<double, double, double>(c, c->S, zj, nullptr, w, 0)), "matvec");
-      }
-      return HYB_OK;
-    };
-    if (m <= kDgsMax) {
-      // Arnoldi with classical Gram-Schmidt and delayed reorthogonalisation: step j applies the
-      // operator to V_j as orthogonalised once in step j - 1 (scaled by the estimated norm eta),
-      // then one reduction pass gives the dots that finish V_j (second orthogonalisation, exact
-      // norm rho) and orthogonalise w once, and one update pass writes both.  Column j - 1 of the
-      // Hessenberg matrix is completed with eta_j a and eta_j rho; the Givens QR of the columns
-      // so far is redone every step from the unrotated matrix Hr.
-      std::vector<double> Hr((size_t)(m + 1) * m, 0.0), ca(m), cb(m);
-      double eta_prev = 1.0, g0 = beta;
-      for (int j = 0; j < m; ++j) {
-        if ((rc = apply_op(j))) return rc;
-        CHECK_HIP(launch_dgs_dots(c, V, n, j, c->hdev), "gram-schmidt dots");
-        CHECK_HIP(hipMemcpyAsync(hh, c->hdev, (2 * (size_t)j + 3) * sizeof(double), hipMemcpyDeviceToHost, c->stream),
-                  "d2h");
-        CHECK_HIP(hipStreamSynchronize(c->stream), "sync");
-        double a2 = 0.0, ab = 0.0, b2 = 0.0;
-        for (int k = 0; k < j; ++k) {
-          ca[k] = hh[k], cb[k] = hh[j + 1 + k];
-          a2 += ca[k] * ca[k], ab += ca[k] * cb[k], b2 += cb[k] * cb[k];
-        }
-        const double rho2 = hh[j] - a2;
-        if (!(rho2 > 0.0) || !std::isfinite(rho2)) {
-          breakdown = true;
-          break;
-        }
-        const double rho = std::sqrt(rho2);
-        if (j == 0) {
-          g0 = beta * rho;  // r = beta V_0 (as scaled) = beta rho v_0
-        } else {
-          double *prev = &Hr[(size_t)(j - 1) * (m + 1)];
-          for (int k = 0; k < j; ++k) prev[k] += eta_prev * ca[k];
-          prev[j] = eta_prev * rho;
-        }
-        double *col = &Hr[(size_t)j * (m + 1)];
-        const double hjj = (hh[2 * j + 1] - ab) / rho;
-        for (int k = 0; k < j; ++k) col[k] = cb[k];
-        col[j] = hjj;
-        const double eta2 = hh[2 * j + 2] - b2 - hjj * hjj;
-        const double eta = (eta2 > 0.0 && std::isfinite(eta2)) ? std::sqrt(eta2) : 0.0;
-        col[j + 1] = eta;
-        CHECK_HIP(launch_dgs_update(c, V, n, j, ca.data(), cb.data(), 1.0 / rho, hjj, eta > 0.0 ? 1.0 / eta : 0.0,
-                                    mixed ? (float *)c->tIn : nullptr),
-                  "gram-schmidt update");
-        eta_prev = eta;
-        // Givens QR of columns 0..j
-        std::fill(g.begin(), g.end(), 0.0);
-        g[0] = g0;
-        bool bad = false;
-        for (int q = 0; q <= j; ++q) {
-          double *rq = &R[(size_t)q * (m + 1)];
-          const double *hq = &Hr[(size_t)q * (m + 1)];
-          for (int i = 0; i <= q + 1; ++i) rq[i] = hq[i];
-          for (int i = 0; i < q; ++i) {
-            const double x = rq[i], z = rq[i + 1];
-            rq[i] = cs[i] * x + sn[i] * z;
-            rq[i + 1] = -sn[i] * x + cs[i] * z;
-          }
-          const double rr = std::hypot(rq[q], rq[q + 1]);
-          if (!(rr > 0) || !std::isfinite(rr)) {
-            bad = true;
-            break;
-          }
-          cs[q] = rq[q] / rr;
-          sn[q] = rq[q + 1] / rr;
-          rq[q] = rr;
-          rq[q + 1] = 0.0;
-          g[q + 1] = -sn[q] * g[q];
-          g[q] = cs[q] * g[q];
-        }
-        if (bad) {
-          breakdown = true;
-          break;
-        }
-        its++;
-        jend = j + 1;
-        const double est = std::fabs(g[j + 1]) / bnorm;
-        if (info && info->history && info->history_len < info->history_cap) info->history[info->history_len++] = est;
-        if (!std::isfinite(est)) {
-          breakdown = true;
-          break;
-        }
-        if (est <= rtol || its >= maxit || eta == 0.0) break;
-      }
-    } else
-    for (int j = 0; j < m; ++j) {
-      double *w = V + (size_t)(j + 1) * n;
-      if ((rc = apply_op(j))) return rc;
-      double *col = &R[(size_t)j * (m + 1)];
-      double hn;
-      bool scaled = false;
-      if (j + 1 <= 32) {
-        // classical Gram-Schmidt with reorthogonalisation in three passes over the basis and one
-        // host read: h1 = V^T w; w -= V h1 while h2 = V^T w and ||w||^2 accumulate; the last pass
-        // subtracts V h2 and normalises with ||w - V h2||^2 = ||w||^2 - ||h2||^2 (V orthonormal)
-        CHECK_HIP(launch_gs_passes(c, V, n, j + 1, w, h1, h2), "gram-schmidt");
-        CHECK_HIP(hipMemcpyAsync(hh, c->hdev, 2 * (size_t)(m + 2) * sizeof(double), hipMemcpyDeviceToHost,
-                                 c->stream),
-                  "d2h");
-        CHECK_HIP(hipStreamSynchronize(c->stream), "sync");
-        double h2sq = 0.0;
-        for (int i = 0; i <= j; ++i) {
-          col[i] = hh[i] + hh[(m + 2) + i];
-          h2sq += hh[(m + 2) + i] * hh[(m + 2) + i];
-        }
-        double wp2 = hh[(m + 2) + j + 1];
-        hn = std::sqrt(std::max(0.0, wp2 - h2sq));
-        if (hn > 0.0 && std::isfinite(hn)) {
-          CHECK_HIP(launch_gs_finish(c, V, n, j + 1, h2, w, 1.0 / hn), "gram-schmidt finish");
-          scaled = true;
-        }
-      } else {
-        // long restart cycles: classical Gram-Schmidt, second pass when the first one cancelled
-        // more than half of the norm (||w'|| < ||w|| / sqrt(2))
-        CHECK_HIP(launch_multidot(c, V, n, j + 1, w, n, h1, true), "cgs1");
-        CHECK_HIP(launch_axpy_norm(c, V, n, j + 1, h1, w, n, nrm), "cgs1 update");
-        CHECK_HIP(hipMemcpyAsync(hh, c->hdev, 3 * (size_t)(m + 2) * sizeof(double), hipMemcpyDeviceToHost,
-                                 c->stream),
-                  "d2h");
-        CHECK_HIP(hipStreamSynchronize(c->stream), "sync");
-        for (int i = 0; i <= j; ++i) col[i] = hh[i];
-        double w2 = hh[j + 1], wp2 = hh[2 * (m + 2)];
-        if (!(wp2 >= 0.5 * w2)) {
-          CHECK_HIP(launch_multidot(c, V, n, j + 1, w, n, h2, false), "cgs2");
-          CHECK_HIP(launch_axpy_norm(c, V, n, j + 1, h2, w, n, nrm), "cgs2 update");
-          CHECK_HIP(hipMemcpyAsync(hh, c->hdev, 3 * (size_t)(m + 2) * sizeof(double), hipMemcpyDeviceToHost,
-                                   c->stream),
-                    "d2h");
-          CHECK_HIP(hipStreamSynchronize(c->stream), "sync");
-          for (int i = 0; i <= j; ++i) col[i] += hh[(m + 2) + i];
-          wp2 = hh[2 * (m + 2)];
-          c->reorth++;
-        }
-        hn = std::sqrt(wp2);
-      }
-      col[j + 1] = hn;
-      for (int i = 0; i < j; ++i) {
-        double a = col[i], bb = col[i + 1];
-        col[i] = cs[i] * a + sn[i] * bb;
-        col[i + 1] = -sn[i] * a + cs[i] * bb;
-      }
-      double a = col[j], bb = col[j + 1];
-      double rr = std::hypot(a, bb);
-      if (!(rr > 0) || !std::isfinite(rr)) {
-        breakdown = true;
-        jend = j;
-        break;
-      }
-      cs[j] = a / rr;
-      sn[j] = bb / rr;
-      col[j] = rr;
-      col[j + 1] = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
-      its++;
-      jend = j + 1;
-      double est = std::fabs(g[j + 1]) / bnorm;
-      if (info && info->history && info->history_len < info->history_cap) info->history[info->history_len++] = est;
-      if (!std::isfinite(est)) {
-        breakdown = true;
-        break;
-      }
-      if (est <= rtol || its >= maxit || hn == 0.0) break;
-      if (!scaled) CHECK_HIP(launch_scale(c, w, n, 1.0 / hn), "scale");
-    }
-    if (jend > 0) {
-      for (int i = jend - 1; i >= 0; --i) {
-        double s = g[i];
-        for (int k = i + 1; k < jend; ++k) s -= R[(size_t)k * (m + 1) + i] * y[k];
-        y[i] = s / R[(size_t)i * (m + 1) + i];
-      }
-      // y goes to the device through the pinned buffer (after the last sync the buffer is free)
-      std::copy(y.begin(), y.begin() + jend, hh + 3 * (m + 2));
-      double *ydev = c->hdev + 3 * (m + 2);
-      CHECK_HIP(hipMemcpyAsync(ydev, hh + 3 * (m + 2), jend * sizeof(double), hipMemcpyHostToDevice, c->stream),
-                "h2d");
-      if (mixed)
-        CHECK_HIP(launch_update_solution<float>(c, (const float *)c->Z, n, jend, ydev, lam, n), "update");
+      CHECK_HIP((launch_trace_apply<double, double, double>(c, c->S, lam, b, V0, 1)), "residual");
+    return HYB_OK;
+  };
+  // z_j = M(V_j) into Z, w = S z_j into V_{j+1}
+  auto apply_op = [&](int j) -> int {
+    double *vj = V + (size_t)j * n, *w = V + (size_t)(j + 1) * n;
+    if (mixed) {
+      float *zf = (float *)c->Z + (size_t)j * n;
+      // the two-pass Gram-Schmidt writes the FP32 copy of V_j with V_j itself (steps j > 0)
+      if (j == 0 || m > kDgsMax) CHECK_HIP(launch_convert(c, vj, (float *)c->tIn, n), "convert");
+      CHECK_HIP(precondition<float>(c, (const float *)c->tIn, zf), "precondition");
+      if (learned) CHECK_HIP(learned_stage<float>(c, vj, zf), "learned stage");
+      CHECK_HIP((launch_trace_apply<double, float, double>(c, c->S, zf, nullptr, w, 0)), "matvec");
+    } else if (c->order == 1) {
+      double *zj = (double *)c->Z + (size_t)j * n;
+      CHECK_HIP(p1_precondition(c, vj, zj), "precondition");
+      CHECK_HIP(p1_rows(c, zj, w, 0, nullptr), "matvec");
+    } else {
+      double *zj = (double *)c->Z + (size_t)j * n;
+      CHECK_HIP(precondition<double>(c, vj, zj), "precondition");
+      if (learned)  // the stage's own applications of S give w = S z (no separate matvec)
+        CHECK_HIP(learned_stage<double>(c, vj, zj, w), "learned stage");
       else
-        CHECK_HIP(launch_update_solution<double>(c, (const double *)c->Z, n, jend, ydev, lam, n), "update");
-      CHECK_HIP(hipStreamSynchronize(c->stream), "sync");
+        CHECK_HIP((launch_trace_apply<double, double, double>(c, c->S, zj, nullptr, w, 0)), "matvec");
     }
-    if (breakdown && jend == 0) {
-      status = HYB_BREAKDOWN;
-      break;
-    }
+    return HYB_OK;
+  };
+  const int status = fgmres(c, n, V, c->Z, mixed, b, lam, rtol, maxit, info, resid, apply_op);
+  if (status >= 0 && info && learned) {
+    double fb = 0.0;
+    CHECK_HIP(hipMemcpyAsync(&fb, c->nn.scal + 2, sizeof(double), hipMemcpyDeviceToHost, c->stream), "d2h");
+    CHECK_HIP(hipStreamSynchronize(c->stream), "sync");
+    info->fallbacks = (int32_t)(fb - fb0);
   }
-  if (info) {
-    info->iters = its;
-    info->restarts = restarts;
-    info->rel_res = rel;
-    info->status = status;
-    if (learned) {
-      double fb = 0.0;
-      CHECK_HIP(hipMemcpyAsync(&fb, c->nn.scal + 2, sizeof(double), hipMemcpyDeviceToHost, c->stream), "d2h");
-      CHECK_HIP(hipStreamSynchronize(c->stream), "sync");
-      info->fallbacks = (int32_t)(fb - fb0);
-    }
-  }
+  (void)m;
   return status;
+}
+
+// ----- Configuration 1: the unhybridised system with the approximate-Schur preconditioner -----
+
+static int mixed_ready(hyb_ctx *c) {
+  if (!c->condensed) return fail(c, HYB_ESTATE, "mixed-system call before condense");
+  if (c->order != 0) return fail(c, HYB_EINVAL, "the mixed system is built for order 0 only");
+  return HYB_OK;
+}
+
+int hyb_mixed_rhs(hyb_ctx *c, const double *r_ub, const double *r_pi, double *b) {
+  if (!c) return HYB_EINVAL;
+  int rc = mixed_ready(c);
+  if (rc) return rc;
+  if (!r_ub || !r_pi || !b) return fail(c, HYB_EINVAL, "null argument");
+  CHECK_HIP(launch_mixed_rhs(c, r_ub, r_pi, b), "mixed rhs");
+  return HYB_OK;
+}
+
+int hyb_mixed_apply(hyb_ctx *c, const double *x, double *y) {
+  if (!c) return HYB_EINVAL;
+  int rc = mixed_ready(c);
+  if (rc) return rc;
+  if (!x || !y || x == y) return fail(c, HYB_EINVAL, "bad mixed apply arguments");
+  CHECK_HIP(launch_mixed_rows(c, x, nullptr, y), "mixed apply");
+  return HYB_OK;
+}
+
+int hyb_mixed_precondition(hyb_ctx *c, const double *r, double *z) {
+  if (!c) return HYB_EINVAL;
+  int rc = mixed_ready(c);
+  if (rc) return rc;
+  if (!r || !z || r == z) return fail(c, HYB_EINVAL, "bad mixed precondition arguments");
+  CHECK_HIP(schur_precondition(c, r, z), "approximate Schur");
+  return HYB_OK;
+}
+
+int hyb_mixed_solve(hyb_ctx *c, const double *b, double *x, double rtol, int32_t maxit, hyb_info *info) {
+  if (!c) return HYB_EINVAL;
+  int rc = mixed_ready(c);
+  if (rc) return rc;
+  if (!b || !x || b == x || !(rtol >= 0) || maxit < 0) return fail(c, HYB_EINVAL, "bad mixed solve arguments");
+  if ((rc = alloc_krylov(c))) return rc;
+  const int m = c->m;
+  const size_t n = (size_t)c->ntrace + c->ncell;
+  if (!c->Vm || c->mm != m) {
+    dfree(c->Vm), dfree(c->Zm);
+    c->mm = 0;
+    if ((rc = dalloc(c, &c->Vm, (size_t)(m + 1) * n)) || (rc = dalloc(c, &c->Zm, (size_t)m * n))) return rc;
+    c->mm = m;
+  }
+  double *V = c->Vm, *Z = c->Zm;
+  auto resid = [&](double *V0) -> int {
+    CHECK_HIP(launch_mixed_rows(c, x, b, V0), "residual");
+    return HYB_OK;
+  };
+  auto apply_op = [&](int j) -> int {
+    double *vj = V + (size_t)j * n, *zj = Z + (size_t)j * n, *w = V + (size_t)(j + 1) * n;
+    CHECK_HIP(schur_precondition(c, vj, zj), "approximate Schur");
+    CHECK_HIP(launch_mixed_rows(c, zj, nullptr, w), "matvec");
+    return HYB_OK;
+  };
+  return fgmres(c, n, V, Z, false, b, x, rtol, maxit, info, resid, apply_op);
 }
 
 int hyb_recover(hyb_ctx *c, const double *r_ub, const double *r_pi, const double *lambda, double *u_b, double *pi) {

@@ -137,6 +137,9 @@ struct hyb_ctx {
   int m = 0;
   double *V = nullptr;      // [(m+1)][ntrace]
   void *Z = nullptr;        // [m][ntrace] (double or float)
+  double *Vm = nullptr;     // Configuration 1: [(m+1)][ntrace + ncell]
+  double *Zm = nullptr;     // Configuration 1: [m][ntrace + ncell]
+  int mm = 0;               // restart length Vm / Zm were allocated for
   double *partial = nullptr;  // [nblk_red][2*(m+2)]
   double *hdev = nullptr;   // [4*(m+2)]
   double *hhost = nullptr;  // pinned [4*(m+2)]
@@ -259,6 +262,12 @@ hipError_t p1_precondition(hyb_ctx *c, const double *r, double *z);
 void p1_free(hyb_ctx *c);
 // one FP64 pressure multigrid V-cycle on level 0: lv[0].b -> lv[0].x (solve.hip)
 hipError_t coarse_vcycle(hyb_ctx *c);
+
+// ----- Configuration 1: the unhybridised mixed system (schur.hip) -----
+// mixed vectors: [ntrace] facet velocities (global orientation, 0 on ground and lid), [ncell] Pi
+hipError_t launch_mixed_rows(hyb_ctx *c, const double *x, const double *b, double *y);  // y = A x or b - A x
+hipError_t launch_mixed_rhs(hyb_ctx *c, const double *r_ub, const double *r_pi, double *y);
+hipError_t schur_precondition(hyb_ctx *c, const double *r, double *z);  // Steps 1-3 of Sec. 2.3
 
 // ----- learned coarse correction (nn.hip) -----
 int nn_param_count();

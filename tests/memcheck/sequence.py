@@ -404,9 +404,59 @@ def sphere_sequence(lib):
         cd.close()
 
 
+def mixed_sequence(lib):
+    # the unhybridised system (Configuration 1) on a ragged box and a rotating sphere: the mixed
+    # right-hand side, operator and approximate-Schur preconditioner against the oracle, FGMRES
+    # with restarts, and argument errors
+    from oracle.schur import ApproximateSchur, MixedOperator
+
+    for name, prob, kw in (("box", make_box(nx=8, ny=6, nlev=7, dx=5e3, dz=250.0, mg_levels=2, perturb=0.05,
+                                            seed=4), {}),
+                           ("sphere", make_sphere(4, 5, mg_levels=2, perturb=0.05, seed=3), None)):
+        if kw is None:
+            kw = dict(omega_rot=prob.omega_rot)
+        # restart 30: the first iterations of this method make no progress (a short restart stalls)
+        c = Ctx(lib, prob, restart=30, **kw)
+        o = OracleProblem(prob)
+        op = MixedOperator(o.mixed)
+        pc = ApproximateSchur(o.mixed, o.pc.mg.vcycle)
+        n = c.ntrace + c.ncell
+        r_ub, r_pi, _ = c.rhs(2)
+        ruc, rpc = cells_from_soa(r_ub, r_pi)
+        b = np.empty(n)
+        c.call("hyb_mixed_rhs", P(r_ub), P(r_pi), P(b))
+        bref = op.rhs(ruc, rpc)
+        check(np.abs(b - bref).max() <= 1e-12 * np.abs(bref).max(), f"{name}: mixed right-hand side against the oracle")
+        x = op.expand(np.random.default_rng(5).standard_normal(o.mixed.nu + o.mixed.np_))
+        y, z = np.empty(n), np.empty(n)
+        c.call("hyb_mixed_apply", P(x), P(y))
+        yref = op(x)
+        nt = c.ntrace
+        eu = np.abs(y[:nt] - yref[:nt]).max() / np.abs(yref[:nt]).max()
+        ep = np.abs(y[nt:] - yref[nt:]).max() / np.abs(yref[nt:]).max()
+        check(eu <= 1e-11 and ep <= 1e-11, f"{name}: mixed operator against the oracle ({eu:.1e}, {ep:.1e})")
+        c.call("hyb_mixed_precondition", P(b), P(z))
+        zref = pc(b)
+        eu = np.abs(z[:nt] - zref[:nt]).max() / np.abs(zref[:nt]).max()
+        ep = np.abs(z[nt:] - zref[nt:]).max() / np.abs(zref[nt:]).max()
+        check(eu <= 1e-9 and ep <= 1e-9, f"{name}: approximate-Schur preconditioner against the oracle ({eu:.1e}, {ep:.1e})")
+        xs = np.zeros(n)
+        hist = (ctypes.c_double * 64)()
+        info = N._Info(0, 0, 0, 0.0, ctypes.cast(hist, N._f64p), 64, 0)
+        rc = c.call("hyb_mixed_solve", P(b), P(xs), 1e-7, 400, ctypes.byref(info))
+        c.call("hyb_mixed_apply", P(xs), P(y))
+        res = np.linalg.norm(b - y) / np.linalg.norm(b)
+        check(rc == 0 and res <= 1.01e-7,
+              f"{name}: mixed FGMRES(30): {info.iters} iterations, {info.restarts} restarts, residual {res:.1e}")
+        check(lib.hyb_mixed_solve(c.h, P(b), P(b), 1e-8, 10, None) < 0
+              and lib.hyb_mixed_apply(c.h, P(b), P(b)) < 0 and lib.hyb_mixed_precondition(c.h, None, P(z)) < 0,
+              f"{name}: aliased or null mixed arguments rejected")
+        c.close()
+
+
 def main():
     lib = N.declare(ctypes.CDLL(sys.argv[1]))
-    which = sys.argv[2:] or ["solver", "network", "p1", "sphere"]
+    which = sys.argv[2:] or ["solver", "network", "p1", "sphere", "mixed"]
     if "solver" in which:
         solver_sequence(lib)
     if "network" in which:
@@ -415,6 +465,8 @@ def main():
         p1_sequence(lib)
     if "sphere" in which:
         sphere_sequence(lib)
+    if "mixed" in which:
+        mixed_sequence(lib)
     print("sequence complete", flush=True)
 
 

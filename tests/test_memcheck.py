@@ -28,7 +28,7 @@ def memcheck_lib(tmp_path_factory):
     return mbuild.build(str(tmp_path_factory.mktemp("memcheck"))), asan
 
 
-@pytest.mark.parametrize("part", ["solver", "network", "p1", "sphere"])
+@pytest.mark.parametrize("part", ["solver", "network", "p1", "sphere", "mixed"])
 def test_call_sequences_stay_in_bounds(memcheck_lib, part):
     lib, asan = memcheck_lib
     env = dict(os.environ, LD_PRELOAD=asan, ASAN_OPTIONS="detect_leaks=0:halt_on_error=1:redzone=128",
