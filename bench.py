@@ -290,15 +290,17 @@ def configs_leg(args, prob, rhs):
 
 def appendix_b_leg(args, prob, rhs):
     """The paper's solver-parameter study (its appendix on solver parameters) on the benchmark box:
-    time-to-1e-8 and iterations of the hybridised single-level method (Configuration 2) over the
+    time-to-1e-8 and iterations of FGMRES on the unhybridised system (Configuration 1) over the
+    pressure multigrid's relaxation factor omega_p = 0.3 ... 1.0 and 1-2 pre- / post-smoothing
+    steps, of the hybridised single-level method (Configuration 2) over the
     smoother's relaxation factor omega = 0.3 ... 1.0 and 1, 2, 3 sweeps, and of the two-level cycle
     (Configuration 3c; pressure V-cycle fixed) over omega and 1-3 pre- / 1-2 post-smoothing steps.
-    A run that has not reached the tolerance within its iteration cap (3000 for Configuration 2,
+    A run that has not reached the tolerance within its iteration cap (300 for Configuration 1, 3000 for Configuration 2,
     300 for 3c) counts as not converged (status 1)."""
     import torch
 
     omegas = (0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9, 1.0)
-    out = {"configuration_2": {}, "configuration_3c": {}}
+    out = {"configuration_1": {}, "configuration_2": {}, "configuration_3c": {}}
 
     def one(s, maxit):
         b = torch.empty(s.ntrace, dtype=torch.float64, device="cuda")
@@ -313,6 +315,30 @@ def appendix_b_leg(args, prob, rhs):
         return dict(sec_per_solve=time.perf_counter() - t0, iters=info["iters"], rel_res=info["rel_res"],
                     status=info["status"])
 
+    bm = None
+    for mg_pre in (1, 2):
+        for mg_post in (1, 2):
+            row = out["configuration_1"][f"{mg_pre}_pre_{mg_post}_post"] = {}
+            for om in omegas:
+                s = setup_solver(prob, 0, omega_p=om, mg_pre=mg_pre, mg_post=mg_post,
+                                 mg_coarse_sweeps=args.coarse_sweeps)
+                if bm is None:
+                    bm = torch.empty(s.nmixed, dtype=torch.float64, device="cuda")
+                xm = torch.zeros_like(bm)
+                s.mixed_rhs(rhs[0][0], rhs[0][1], bm)
+                s.mixed_solve(bm, xm, rtol=args.rtol, maxit=2)  # allocates the Krylov bases
+                xm.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                info = s.mixed_solve(bm, xm, rtol=args.rtol, maxit=300)
+                torch.cuda.synchronize()
+                row[f"{om:.1f}"] = r = dict(sec_per_solve=time.perf_counter() - t0, iters=info["iters"],
+                                            rel_res=info["rel_res"], status=info["status"])
+                s.close()
+                del xm
+                log(f"appendix B, configuration 1, pressure MG {mg_pre} pre {mg_post} post, omega_p {om:.1f}: "
+                    f"{r['sec_per_solve'] * 1e3:.1f} ms, {r['iters']} iterations, status {r['status']}")
+    del bm
     for n in (1, 2, 3):
         row = out["configuration_2"][f"{n}_sweeps"] = {}
         for om in omegas:
