@@ -296,3 +296,109 @@ def test_bicgstab_and_krylov_coarse_solve():
     np.testing.assert_allclose(o3a.pc(B), zexact, rtol=0, atol=1e-10 * np.abs(zexact).max())
     dpi = bicgstab(lambda v: H0 @ v, pc.mg.vcycle, Bbar, 1e-2)
     assert np.linalg.norm(Bbar - H0 @ dpi) <= 1e-2 * np.linalg.norm(Bbar)
+
+
+def _lumped_closed_form(prob, mesh):
+    """Sec. 2.3 lumping on an axis-aligned box, worked out from the App. A cell matrices: each cell
+    adds (1/3 + 1/6) a of its velocity block to the row of a facet it shares (the -1/6 coupling to
+    the opposite facet changes sign with the global orientation), so a vertical x / y facet gets
+    a_x / a_y and an interior horizontal facet (1 + beta) a_z / 2 from each of its two cells (the
+    row sum runs over the kept dofs: the ground and lid facets have none)."""
+    L, ncol = mesh.nlev, mesh.ncol
+    hx, hy, hz = mesh.dx, mesh.dy, mesh.dz
+    th, pih = prob.theta_w, prob.exner_hat_w
+    beta = -prob.tau_u * prob.tau_theta * prob.dt**2 * prob.cp * (pih[1:] - pih[:-1]) * (th[1:] - th[:-1]) / hz[:, None] ** 2
+    az = (1.0 + beta) * (hz / (hx * hy))[:, None]  # [L][ncol]
+    # a cell's share of its top (bottom) facet row is az / 2, or az / 3 when its other horizontal
+    # facet is the ground (lid): that facet has no velocity dof, so its -1/6 coupling drops out
+    share_top = az / 2.0
+    share_bot = az / 2.0
+    share_top[0] = az[0] / 3.0
+    share_bot[L - 1] = az[L - 1] / 3.0
+    m2 = np.full(mesh.ntrace, np.nan)
+    m2[ncol:L * ncol] = (share_top[:-1] + share_bot[1:]).ravel()  # interior horizontal facets k = 1..L-1
+    ax = hx / (hy * hz)
+    ay = hy / (hx * hz)
+    for k in range(L):
+        base = mesh.n_zface + k * 2 * ncol
+        m2[base:base + ncol] = ax[k]
+        m2[base + ncol:base + 2 * ncol] = ay[k]
+    return m2
+
+
+@pytest.mark.parametrize(
+    "kw",
+    [
+        dict(nx=4, ny=3, nlev=5, dx=10e3, dy=7e3, dz=800.0, mg_levels=1),
+        dict(nx=3, ny=4, nlev=6, dx=5e3, dy=6e3, ztop=30e3, stretch="quadratic", mg_levels=1, perturb=0.1),
+    ],
+)
+def test_lumped_mass_and_pressure_operator_closed_forms(kw):
+    """The lumped velocity mass and every entry of H = -B M2l^-1 G + M3^Pi against closed forms
+    of Sec. 2.3 and App. A; the same lumping done in outward (broken) orientation fails."""
+    from oracle.mixed import MixedSystem
+    from oracle.local import local_matrices
+    from oracle.mesh import BoxMesh
+    from oracle.precond import lumped_velocity_mass, pressure_operator
+
+    prob = make_box(**kw)
+    mesh = BoxMesh(prob.nx, prob.ny, prob.nlev, prob.dx, prob.dy, prob.z)
+    loc = local_matrices(mesh, prob)
+    mixed = MixedSystem(mesh, loc, prob)
+    ref = _lumped_closed_form(prob, mesh)
+    interior = ~mesh.boundary
+    got = lumped_velocity_mass(mixed)
+    np.testing.assert_allclose(got, ref[interior], rtol=1e-12, atol=0)
+
+    # H entry by entry.  Facet F of cells K- (normal leaves) and K+: H[K-, K+] = d^{K-}_F k_F / m2(F)
+    # with the sign pattern of B (outward d) and G (outward g = -k), and
+    # H[K, K] = m_K + sum over non-boundary facets of d^K_F k_F / m2(F).
+    L, ncol, nx = mesh.nlev, mesh.ncol, mesh.nx
+    tr, tu, dt, cp = prob.tau_rho, prob.tau_u, prob.dt, prob.cp
+    th = prob.theta_w
+    q = prob.tau_theta * dt * (th[1:] - th[:-1]) / (th[1:] + th[:-1])  # [L][ncol]
+    m_k = (1 - prob.kappa) / prob.kappa * (mesh.dx * mesh.dy * mesh.dz)[:, None] / prob.exner_c
+    kbar = tu * dt * cp * 0.5 * (th[1:] + th[:-1])  # k on the vertical facets of layer k
+    Href = np.zeros((mesh.ncell, mesh.ncell))
+    cell = lambda k, ix, iy: k * ncol + (iy % mesh.ny) * nx + (ix % nx)  # noqa: E731
+    for k in range(L):
+        for iy in range(mesh.ny):
+            for ix in range(nx):
+                c = cell(k, ix, iy)
+                col = iy * nx + ix
+                diag = m_k[k, col]
+                for dxy, fn, m2f in (((1, 0), mesh.xface, None), ((0, 1), mesh.yface, None)):
+                    # the facet on the E / N side of this cell, shared with the next column
+                    f = fn(k, ix + dxy[0], iy + dxy[1])
+                    other = cell(k, ix + dxy[0], iy + dxy[1])
+                    coup = -tr * dt * kbar[k, col] / ref[f]
+                    Href[c, other] += coup
+                    Href[other, c] += coup
+                    diag += tr * dt * kbar[k, col] / ref[f]
+                    diag += tr * dt * kbar[k, col] / ref[fn(k, ix, iy)]
+                if k + 1 < L:  # interior horizontal facet above: K- = this cell, K+ = the one above
+                    f = mesh.zface(k + 1, ix, iy)
+                    up = cell(k + 1, ix, iy)
+                    kf = tu * dt * cp * th[k + 1, col]
+                    Href[c, up] += -(tr * dt + q[k, col]) * kf / ref[f]
+                    Href[up, c] += -(tr * dt - q[k + 1, col]) * kf / ref[f]
+                    diag += (tr * dt + q[k, col]) * kf / ref[f]
+                if k > 0:
+                    f = mesh.zface(k, ix, iy)
+                    kf = tu * dt * cp * th[k, col]
+                    diag += (tr * dt - q[k, col]) * kf / ref[f]
+                Href[c, c] += diag
+    H = pressure_operator(mixed).toarray()
+    np.testing.assert_allclose(H, Href, rtol=1e-11, atol=1e-12 * np.abs(Href).max())
+
+    # a plausible mistake: lumping the broken (outward-oriented) cell blocks without the sign map
+    # gives positive values a third as large on uniform cells, and H's couplings three times larger
+    wrong = np.zeros(mesh.ntrace)
+    for a in range(6):
+        for b in range(6):
+            np.add.at(wrong, mesh.cell_faces[:, a], loc["A"][:, a, b])
+    wrong = wrong[interior]
+    assert wrong.min() > 0  # it would pass a positivity pin
+    assert np.abs(wrong / ref[interior] - 1.0).min() > 0.5
+    Hwrong = pressure_operator(mixed, wrong).toarray()
+    assert np.abs(Hwrong - Href).max() > 0.5 * np.abs(Href - np.diag(np.diag(Href))).max()
