@@ -60,12 +60,15 @@ def test_mixed_operator_and_preconditioner(case):
 
 @pytest.mark.gpu
 # the tolerance stays above the rounding floor of the unweighted residual of this system (its rows
-# differ in scale by 15 orders of magnitude; on the C8 sphere even the LU solution leaves ~2e-8),
-# where a run stops is decided by rounding rather than by the method
-# the final count agrees within +-2 on the box; on the sphere the restart falls into a stall of the
-# method, where rounding moves the stopping point by several iterations, and the first 20 residual
-# estimates are compared instead
-@pytest.mark.parametrize("case,rtol,band", [("box16x16x8", 1e-8, 0.0), ("sphere_c8x10", 1e-7, 0.25)])
+# differ in scale by 15 orders of magnitude; on the C8 sphere even the LU solution leaves ~2e-8).
+# On the sphere the Hessenberg matrix of the restart cycle becomes numerically singular after
+# 25-29 steps: from there on the oracle's own residual estimates stop decreasing monotonically
+# (which a minimal-residual method cannot do in exact arithmetic; where this starts depends on the
+# host's BLAS), and both sides' estimates, and with them the step at which they stop, are set by
+# rounding (measured 48 against 51-54 iterations).  The residual histories are compared over the
+# first 20 steps, the final count within 2 on the box and within a quarter on the sphere; the
+# solutions against the sparse LU one to 1e-9 (measured 1e-11).
+@pytest.mark.parametrize("case,rtol,band", [("box16x16x8", 1e-8, 2), ("sphere_c8x10", 1e-7, 0.25)])
 def test_mixed_solve(case, rtol, band):
     import torch
 
@@ -95,9 +98,8 @@ def test_mixed_solve(case, rtol, band):
     say(f"[config 1] {case}: gpu {info['iters']} oracle {oits} iterations (3c: {its3c}), residual {res:.1e}, "
         f"error against LU {eu:.1e}/{ep:.1e}")
     assert info["status"] == 0 and res <= 1.05 * rtol
-    assert abs(info["iters"] - oits) <= max(2, int(band * oits))
-    k = min(20, len(info["history"]), len(hist) - 1)
-    np.testing.assert_allclose(info["history"][:k], hist[1 : k + 1], rtol=1e-3)
-    assert eu <= 1e-5 and ep <= 1e-5
+    np.testing.assert_allclose(info["history"][:20], hist[1:21], rtol=1e-3)  # measured 1.5e-4
+    assert abs(info["iters"] - oits) <= (band if band >= 1 else max(2, int(band * oits)))
+    assert eu <= 1e-9 and ep <= 1e-9
     assert info["iters"] > its3c
     s.close()

@@ -127,24 +127,28 @@ def test_energy_loss_gradients_match_oracle(small):
     assert max(errs) <= 1e-4
 
 
-def _stage_reference(prob, orc, vec, v):
-    """The stage inside the solve runs the network with BF16 weights and BF16 hidden activations
-    (FP32 accumulation); the input is the FP32 c / s."""
+def _stage_reference(prob, orc, vec, v, round_act):
+    """The stage with the network's BF16 weights, in FP64: with round_act = bf16_round the hidden
+    activations are rounded to BF16 as the kernels store them; with None the network is the
+    unrounded one.  Returns (z, accepted, z of the plain cycle)."""
     W, b = learned.unpack(vec)
     Wr = [onn.bf16_round(w) for w in W]
     z = orc.pc(v)
-    return onn.learned_correction(v, z, orc.pc.S, orc.pc.P, orc.pc.gamma, orc.H.diagonal(), Wr, b,
-                                  onn.neighbour_table(prob.nx, prob.ny), prob.nlev, round_act=onn.bf16_round,
-                                  static=static_for(prob))
+    zs, acc = onn.learned_correction(v, z, orc.pc.S, orc.pc.P, orc.pc.gamma, orc.H.diagonal(), Wr, b,
+                                     onn.neighbour_table(prob.nx, prob.ny), prob.nlev, round_act=round_act,
+                                     static=static_for(prob))
+    return zs, acc, z
 
 
 @pytest.mark.gpu
 def test_precondition_with_learned_stage_matches_oracle(small):
-    """hyb_precondition with the stage against the oracle's cycle + stage: an exact identity network
-    (every product is exact in BF16 / FP32, so the correction is the closed form with c / s rounded
-    to BF16 on both sides; to 1e-6) and a random one (to 1e-4: where the FP32 accumulation on the GPU
-    and the FP64 one in the oracle straddle a BF16 rounding boundary, a hidden activation differs by
-    one BF16 ulp, 2^-8 of itself)."""
+    """hyb_precondition with the stage against the oracle's cycle + stage.  Against the unrounded
+    FP64 network (BF16 weights): the kernels store hidden activations in BF16 (relative rounding
+    2^-9 per value, through two hidden layers), so the correction may differ by 2^-6 of its own size
+    (measured 2e-3 to 6e-3).  Against the network with BF16-rounded activations (the kernels'
+    storage format): an exact identity network to 1e-6 (every product is exact in BF16 / FP32) and a
+    random one to 1e-4 (where the FP32 accumulation on the GPU and the FP64 one in the oracle
+    straddle a BF16 rounding boundary, a hidden activation differs by one BF16 ulp)."""
     prob, s = small
     import torch
 
@@ -157,7 +161,8 @@ def test_precondition_with_learned_stage_matches_oracle(small):
         s.nn_set_weights(vec)
         for trial in range(3):
             v = rng.standard_normal(orc.mesh.ntrace)
-            zref, acc = _stage_reference(prob, orc, vec, v)
+            zref, acc, z0 = _stage_reference(prob, orc, vec, v, onn.bf16_round)
+            zex, acc_ex, _ = _stage_reference(prob, orc, vec, v, None)
             z = torch.empty(s.ntrace, dtype=torch.float64, device="cuda")
             p.learned = 1
             s.set_params(p)
@@ -165,7 +170,12 @@ def test_precondition_with_learned_stage_matches_oracle(small):
             p.learned = 0
             s.set_params(p)
             err = rel_max(host(z), zref)
-            say(f"[stage] {name} trial {trial}: accepted {acc}, error {err:.2e}")
+            err_ex = rel_max(host(z), zex)
+            corr = rel_max(zex, z0)  # the correction's size relative to the result
+            say(f"[stage] {name} trial {trial}: accepted {acc}, error {err:.2e}; against the unrounded network "
+                f"{err_ex:.2e} = {err_ex / max(corr, 1e-300):.1e} of the correction")
+            assert acc == acc_ex
+            assert err_ex <= 2.0**-6 * corr
             assert err <= (1e-6 if name == "identity" else 1e-4)
 
 
@@ -242,3 +252,49 @@ def test_learned_stage_falls_back_on_overflow(small):
     s.set_params(p)
     say(f"[learned] overflow weights: iters {info['iters']} fallbacks {info['fallbacks']}")
     assert info["status"] == 0 and info["fallbacks"] == info["iters"]
+
+
+@pytest.mark.gpu
+def test_call_orders_that_once_met_unallocated_buffers():
+    """Regression test of two call orders whose buffers were once used before allocation (found
+    on the CPU stand-in, fixed): a training step as the first network call of a fresh context, and
+    the FP32 preconditioner (mixed form, with and without the stage) before any solve.  The
+    results are checked against the oracle's formulas and the FP64 preconditioner."""
+    import torch
+
+    prob = make_box(nx=12, ny=10, nlev=9, dx=5e3, dz=250.0, mg_levels=2, perturb=0.05, seed=3)
+    rng = np.random.default_rng(21)
+    nb = onn.neighbour_table(prob.nx, prob.ny)
+    st = static_for(prob)
+    # a fresh context whose first network call is a training step (batch 3)
+    s = make_solver(prob)
+    vec = learned.init_params(16, seed=4)
+    s.nn_set_weights(vec)
+    x = rng.standard_normal((3, prob.ncell)).astype(np.float32)
+    t = rng.standard_normal((3, prob.ncell)).astype(np.float32)
+    loss = s.nn_train_step(_f32(x), _f32(t), 3, 1e-3)
+    W, b = learned.unpack(vec)
+    Wr = [onn.bf16_round(w) for w in W]
+    lref = np.mean([onn.loss_and_grads(x[i].astype(np.float64), t[i].astype(np.float64), Wr, b, nb, prob.nlev,
+                                       static=st)[0] for i in range(3)])
+    say(f"[call order] first call a training step: loss {loss:.6e} vs oracle {lref:.6e}")
+    assert abs(loss - lref) <= 1e-5 * abs(lref)
+    s.close()
+    # fresh contexts in the mixed form: the preconditioner before any solve, against FP64
+    s64 = make_solver(prob)
+    v = rng.standard_normal(s64.ntrace)
+    z64 = torch.empty(s64.ntrace, dtype=torch.float64, device="cuda")
+    s64.precondition(dev(v), z64)
+    for learned_on in (0, 1):
+        sm = make_solver(prob, precision=1, learned=learned_on)
+        if learned_on:
+            sm.nn_set_weights(vec)
+        zm = torch.empty(sm.ntrace, dtype=torch.float64, device="cuda")
+        sm.precondition(dev(v), zm)
+        err = rel_max(host(zm), host(z64))
+        say(f"[call order] FP32 preconditioner before any solve (stage {learned_on}): {err:.2e} from FP64")
+        assert np.all(np.isfinite(host(zm)))
+        if not learned_on:
+            assert err <= 1e-5
+        sm.close()
+    s64.close()
