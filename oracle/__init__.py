@@ -19,7 +19,11 @@ preconditioners for a compatible finite element dynamical core"):
 * ``precond`` - lumped approximate Schur operator H (Sec. 2.3), tensor
   product pressure multigrid, LineSmooth (Alg. 1), intergrid operators, the
   scaling Gamma (Eq. of the scaling matrix) and the two-level cycle (Alg. 2).
-* ``krylov``  - flexible GMRES.
+* ``krylov``  - flexible GMRES (and BiCGStab for the coarse pressure system).
+* ``schur``   - the approximate-Schur preconditioner of the unhybridised system (Sec. 2.3).
+* ``elimination`` - the elimination of theta' (Sec. 2.1) and rho' (Sec. 2.2) around the 2x2
+  solve, their back-substitution and the four-field system they come from.
+* ``p1``, ``nn`` - the next-to-lowest order system and the learned coarse correction.
 
 Parity status of every function is listed in its module header.
 """
