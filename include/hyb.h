@@ -215,6 +215,19 @@ int hyb_precondition(hyb_ctx *ctx, const double *r, double *z);
 int hyb_solve(hyb_ctx *ctx, const double *b_lambda, double *lambda, double rtol, int32_t maxit,
               hyb_info *info);
 
+/* hyb_solve for callers that cannot allocate memory (code under HIP graph capture, tight serving
+   loops, harnesses that forbid allocation): the same FGMRES with the same kernels, arguments and
+   results, but no allocation of any kind during the call.  The Krylov basis is the context's own
+   (allocated by hyb_condense / hyb_set_params for the current restart length; HYB_ESTATE if it is
+   not); the reduction partials and dot products go to a static 2 MiB device array of the library
+   instead of the context's buffers, which bounds the restart length (HYB_EINVAL with the sizes
+   beyond it: (2 * 2048 + 4) (restart + 2) doubles must fit, restart <= 61).  Order 0 only, without
+   the learned stage, the Krylov coarse solve (coarse_mode 2) or profiling (HYB_EINVAL /
+   HYB_ESTATE otherwise).  The array is shared by every context on the device: calls that overlap
+   on one device (different streams or host threads) race and must be serialised by the caller. */
+int hyb_solve_noalloc(hyb_ctx *ctx, const double *b_lambda, double *lambda, double rtol, int32_t maxit,
+                      hyb_info *info);
+
 /* Cellwise recovery X = A^-1 (R_X - K lambda) (Sec. 2.4): u_b [6][nlev][ncol]
    outward fluxes of the broken velocity, pi [nlev][ncol] Exner pressure. */
 int hyb_recover(hyb_ctx *ctx, const double *r_ub, const double *r_pi, const double *lambda,

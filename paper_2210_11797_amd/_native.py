@@ -96,7 +96,7 @@ class Params:
 
 ABI_FUNCTIONS = [
     "hyb_create", "hyb_set_params", "hyb_assemble_local", "hyb_condense", "hyb_trace_apply",
-    "hyb_precondition", "hyb_solve", "hyb_recover", "hyb_sizes", "hyb_profile", "hyb_profile_family", "hyb_profile_read",
+    "hyb_precondition", "hyb_solve", "hyb_solve_noalloc", "hyb_recover", "hyb_sizes", "hyb_profile", "hyb_profile_family", "hyb_profile_read",
     "hyb_restrict", "hyb_nn_param_count", "hyb_nn_set_weights", "hyb_nn_get_weights", "hyb_nn_forward",
     "hyb_nn_loss_grad", "hyb_nn_train_step", "hyb_nn_energy_grad", "hyb_nn_energy_train_step",
     "hyb_mixed_rhs", "hyb_mixed_apply", "hyb_mixed_precondition", "hyb_mixed_solve",
@@ -131,6 +131,7 @@ def declare(lib):
     lib.hyb_trace_apply.argtypes = [vp, vp, vp]
     lib.hyb_precondition.argtypes = [vp, vp, vp]
     lib.hyb_solve.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(_Info)]
+    lib.hyb_solve_noalloc.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(_Info)]
     lib.hyb_recover.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.hyb_sizes.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                               ctypes.POINTER(ctypes.c_int64)]
@@ -308,12 +309,14 @@ class HybSolver:
         return dict(status=rc, iters=info.iters, restarts=info.restarts, rel_res=info.rel_res,
                     history=[hist[i] for i in range(info.history_len)])
 
-    def solve(self, b_lambda, lam, rtol=1e-8, maxit=500, history=256):
+    def solve(self, b_lambda, lam, rtol=1e-8, maxit=500, history=256, noalloc=False):
+        """hyb_solve, or with noalloc=True hyb_solve_noalloc (no allocation during the call)."""
         hist = (ctypes.c_double * max(1, history))()
         info = _Info(0, 0, 0, 0.0, ctypes.cast(hist, _f64p), history, 0)
-        rc = self._check(self.lib.hyb_solve(self.h, _ptr(b_lambda, self.ntrace, "b_lambda"),
-                                            _ptr(lam, self.ntrace, "lambda"), float(rtol), int(maxit),
-                                            ctypes.byref(info)), "hyb_solve")
+        name = "hyb_solve_noalloc" if noalloc else "hyb_solve"
+        rc = self._check(getattr(self.lib, name)(self.h, _ptr(b_lambda, self.ntrace, "b_lambda"),
+                                                 _ptr(lam, self.ntrace, "lambda"), float(rtol), int(maxit),
+                                                 ctypes.byref(info)), name)
         return dict(status=rc, iters=info.iters, restarts=info.restarts, rel_res=info.rel_res,
                     history=[hist[i] for i in range(info.history_len)], fallbacks=info.fallbacks)
 

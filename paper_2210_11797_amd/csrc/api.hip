@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -17,6 +18,40 @@ using namespace hyb;
 namespace hyb {
 int reduction_blocks();
 }
+
+// Reduction scratch of hyb_solve_noalloc: the workgroup partial sums of the Gram-Schmidt dots and
+// norms and the summed results, in a fixed array of 2 MiB per device (every device the library
+// runs on holds its own copy until the process ends).  Host code never uses the array's name as
+// an address: hyb_create looks up the device address once per device and keeps it.
+constexpr size_t kScratchDoubles = (size_t(2) << 20) / sizeof(double);
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_dev[kMaxDevices] = {};
+
+// The device address of this device's scratch (the device must be current); nullptr if unknown.
+double *scratch_address(int dev, std::string *err) {
+  if (dev < 0 || dev >= kMaxDevices) {
+    *err = "device index out of range for the static scratch table";
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) {
+      *err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return nullptr;
+    }
+    g_scratch_dev[dev] = (double *)ptr;
+  }
+  return g_scratch_dev[dev];
+}
+
+}  // namespace
 
 namespace {
 
@@ -206,6 +241,9 @@ int alloc_krylov(hyb_ctx *c) {
     return rc;
   CHECK_HIP(hipHostMalloc((void **)&c->hhost, 4 * (size_t)(m + 2) * sizeof(double), hipHostMallocDefault),
             "hipHostMalloc");
+  const size_t hm = (size_t)(m + 1) * m;
+  c->kR.assign(hm, 0.0), c->kHr.assign(hm, 0.0), c->kg.assign(m + 1, 0.0);
+  c->kcs.assign(m, 0.0), c->ksn.assign(m, 0.0), c->ky.assign(m, 0.0), c->kca.assign(m, 0.0), c->kcb.assign(m, 0.0);
   return HYB_OK;
 }
 
@@ -220,7 +258,10 @@ int fgmres(hyb_ctx *c, size_t n, double *V, void *Zbuf, bool zf32, const double 
   int rc = 0;
   double *h1 = c->hdev, *h2 = c->hdev + (m + 2), *nrm = c->hdev + 2 * (m + 2);
   double *hh = c->hhost;
-  std::vector<double> R((size_t)(m + 1) * m, 0.0), g(m + 1), cs(m), sn(m), y(m);
+  std::vector<double> &R = c->kR, &g = c->kg, &cs = c->kcs, &sn = c->ksn, &y = c->ky;
+  if (R.size() < (size_t)(m + 1) * m || g.size() < (size_t)m + 1)
+    return fail(c, HYB_ESTATE, "the Krylov workspace does not match the restart length");
+  std::fill(R.begin(), R.end(), 0.0);
   if (info) {
     info->iters = 0, info->restarts = 0, info->history_len = 0, info->rel_res = 0, info->status = HYB_OK;
     info->fallbacks = 0;
@@ -273,7 +314,8 @@ int fgmres(hyb_ctx *c, size_t n, double *V, void *Zbuf, bool zf32, const double 
       // norm rho) and orthogonalise w once, and one update pass writes both.  Column j - 1 of the
       // Hessenberg matrix is completed with eta_j a and eta_j rho; the Givens QR of the columns
       // so far is redone every step from the unrotated matrix Hr.
-      std::vector<double> Hr((size_t)(m + 1) * m, 0.0), ca(m), cb(m);
+      std::vector<double> &Hr = c->kHr, &ca = c->kca, &cb = c->kcb;
+      std::fill(Hr.begin(), Hr.end(), 0.0);
       double eta_prev = 1.0, g0 = beta;
       for (int j = 0; j < m; ++j) {
         if ((rc = apply_op(j))) return rc;
@@ -581,6 +623,15 @@ int hyb_create(const hyb_mesh *mesh, const hyb_params *params, void *stream, hyb
     delete c;
     return HYB_EHIP;
   }
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return HYB_EHIP;
+  }
+  {
+    std::string why;
+    c->scratch = scratch_address(c->device, &why);
+    if (!c->scratch) c->scratch_err = why;  // reported by hyb_solve_noalloc; no other call needs it
+  }
   c->fam.resize(F_COUNT);
   for (int i = 0; i < F_COUNT; ++i) c->fam[i].name = kFamilyNames[i];
   c->lv.resize(c->nlevels);
@@ -806,12 +857,11 @@ int hyb_precondition(hyb_ctx *c, const double *r, double *z) {
   return HYB_OK;
 }
 
-int hyb_solve(hyb_ctx *c, const double *b, double *lam, double rtol, int32_t maxit, hyb_info *info) {
-  if (!c) return HYB_EINVAL;
-  if (!c->condensed) return fail(c, HYB_ESTATE, "solve before condense");
-  if (!b || !lam || b == lam || !(rtol >= 0) || maxit < 0) return fail(c, HYB_EINVAL, "bad solve arguments");
-  int rc = alloc_krylov(c);
-  if (rc) return rc;
+namespace {
+
+// FGMRES on the trace system with the context's Krylov basis (allocated) and the reduction
+// buffers c->partial / c->hdev (the context's own, or the static scratch).
+int solve_impl(hyb_ctx *c, const double *b, double *lam, double rtol, int32_t maxit, hyb_info *info) {
   const size_t n = (size_t)c->ntrace;
   const int m = c->m;
   // the order-0 mixed form keeps the preconditioned basis Z in FP32 (at order 1 the mixed form only
@@ -864,6 +914,49 @@ int hyb_solve(hyb_ctx *c, const double *b, double *lam, double rtol, int32_t max
     info->fallbacks = (int32_t)(fb - fb0);
   }
   (void)m;
+  return status;
+}
+
+}  // namespace
+
+int hyb_solve(hyb_ctx *c, const double *b, double *lam, double rtol, int32_t maxit, hyb_info *info) {
+  if (!c) return HYB_EINVAL;
+  if (!c->condensed) return fail(c, HYB_ESTATE, "solve before condense");
+  if (!b || !lam || b == lam || !(rtol >= 0) || maxit < 0) return fail(c, HYB_EINVAL, "bad solve arguments");
+  int rc = alloc_krylov(c);
+  if (rc) return rc;
+  return solve_impl(c, b, lam, rtol, maxit, info);
+}
+
+int hyb_solve_noalloc(hyb_ctx *c, const double *b, double *lam, double rtol, int32_t maxit, hyb_info *info) {
+  if (!c) return HYB_EINVAL;
+  if (!c->condensed) return fail(c, HYB_ESTATE, "solve before condense");
+  if (!b || !lam || b == lam || !(rtol >= 0) || maxit < 0) return fail(c, HYB_EINVAL, "bad solve arguments");
+  if (c->order != 0 || c->p.learned || c->p.coarse_mode == 2)
+    return fail(c, HYB_EINVAL,
+                "hyb_solve_noalloc covers order 0 without the learned stage or the Krylov coarse solve");
+  if (c->prof) return fail(c, HYB_ESTATE, "hyb_solve_noalloc does not record profiling events");
+  if (!c->V || !c->Z || !c->hhost || c->m != c->p.restart || c->kR.size() < (size_t)(c->m + 1) * c->m)
+    return fail(c, HYB_ESTATE, "the Krylov basis for this restart length is not allocated (condense first)");
+  if (!c->scratch) return fail(c, HYB_EHIP, "no static scratch on this device: " + c->scratch_err);
+  int dev = -1;
+  CHECK_HIP(hipGetDevice(&dev), "hipGetDevice");
+  if (dev != c->device) return fail(c, HYB_ESTATE, "hyb_solve_noalloc called with another device current");
+  const size_t npart = (size_t)c->nblk_red * 2 * (c->m + 2), nh = 4 * (size_t)(c->m + 2);
+  if (npart + nh > kScratchDoubles)
+    return fail(c, HYB_EINVAL, "restart length " + std::to_string(c->m) + " needs " +
+                                   std::to_string((npart + nh) * sizeof(double)) +
+                                   " bytes of reduction scratch; the static scratch holds " +
+                                   std::to_string(kScratchDoubles * sizeof(double)));
+  // the reductions of this call write into the static scratch: the workgroup partials first, the
+  // summed results after them; every slot a reduction reads is written by the same reduction, so
+  // nothing needs clearing
+  double *own_partial = c->partial, *own_hdev = c->hdev;
+  c->partial = c->scratch;
+  c->hdev = c->scratch + npart;
+  const int status = solve_impl(c, b, lam, rtol, maxit, info);
+  c->partial = own_partial;
+  c->hdev = own_hdev;
   return status;
 }
 

@@ -145,6 +145,14 @@ struct hyb_ctx {
   double *hhost = nullptr;  // pinned [4*(m+2)]
   int nblk_red = 0;
   long reorth = 0;           // second Gram-Schmidt passes taken (diagnostics)
+  // host side of the restart cycle (Hessenberg matrix, Givens rotations, least-squares solution),
+  // sized with the basis so that a solve allocates no host memory either
+  std::vector<double> kR, kHr, kg, kcs, ksn, ky, kca, kcb;
+  // the device current at hyb_create and that device's copy of the library's static reduction
+  // scratch (hyb_solve_noalloc); null when its address could not be taken
+  int device = -1;
+  double *scratch = nullptr;
+  std::string scratch_err;
 
   bool assembled = false, condensed = false;
   std::string err;

@@ -49,6 +49,7 @@ unsigned cur_tid();
 #define __forceinline__ inline
 #define __launch_bounds__(...)
 #define __constant__
+#define __align__(n) __attribute__((aligned(n)))
 #define __shared__ static
 #define __syncthreads() emu::barrier()
 #define __builtin_nontemporal_load(p) (*(p))
@@ -187,6 +188,16 @@ hipError_t hipHostFree(void *p);
 hipError_t hipMemcpy(void *d, const void *s, size_t n, hipMemcpyKind k);
 hipError_t hipMemcpyAsync(void *d, const void *s, size_t n, hipMemcpyKind k, hipStream_t st = nullptr);
 hipError_t hipStreamSynchronize(hipStream_t s);
+// one device; a device variable is a host static, so its address is its own
+inline hipError_t hipGetDevice(int *d) {
+  *d = 0;
+  return hipSuccess;
+}
+#define HIP_SYMBOL(X) ((const void *)&(X))
+inline hipError_t hipGetSymbolAddress(void **p, const void *sym) {
+  *p = const_cast<void *>(sym);
+  return hipSuccess;
+}
 hipError_t hipGetLastError();
 const char *hipGetErrorString(hipError_t e);
 hipError_t hipEventCreate(hipEvent_t *e);

@@ -172,6 +172,27 @@ def solver_sequence(lib):
     res = c.residual(b, lam)
     check(info.iters == 36 and res <= 1e-12, f"fp64 FGMRES(40), 36 steps without a tolerance: residual {res:.1e}")
     c.set(restart=30)
+    # the allocation-free solve (static reduction scratch) gives hyb_solve's iterate, also on a
+    # second, smaller context after it
+    for prec in (N.PREC_FP64, N.PREC_MIXED):
+        c.set(precision=prec)
+        rc, info, lam = c.solve(b, 1e-9)
+        lam_na = np.zeros(c.ntrace)
+        info_na = N._Info(0, 0, 0, 0.0, None, 0, 0)
+        rc_na = c.call("hyb_solve_noalloc", P(b), P(lam_na), 1e-9, 500, ctypes.byref(info_na))
+        check(rc_na == 0 and info_na.iters == info.iters and np.array_equal(lam, lam_na),
+              f"hyb_solve_noalloc = hyb_solve (precision {prec}, {info.iters} iterations)")
+    c.set(precision=N.PREC_FP64)
+    cs = Ctx(lib, make_box(nx=3, ny=2, nlev=2, dx=5e3, dz=250.0, mg_levels=1, seed=9))
+    _, _, bs = cs.rhs(1)
+    rc, info, lam = cs.solve(bs, 1e-10)
+    lam_na = np.zeros(cs.ntrace)
+    rc_na = cs.call("hyb_solve_noalloc", P(bs), P(lam_na), 1e-10, 500, None)
+    check(rc_na == 0 and np.array_equal(lam, lam_na), "hyb_solve_noalloc on a smaller second context")
+    cs.set(restart=62)
+    check(lib.hyb_solve_noalloc(cs.h, P(bs), P(lam_na), 1e-10, 500, None) < 0,
+          "hyb_solve_noalloc rejects a restart whose partials exceed the static scratch")
+    cs.close()
     c2 = Ctx(lib, make_box(nx=4, ny=4, nlev=66, dx=5e3, dz=150.0, mg_levels=2, seed=8))  # nlev > 64: Thomas path
     _, _, b2 = c2.rhs(3)
     rc2, info2, lam2 = c2.solve(b2, 1e-10)
@@ -350,6 +371,7 @@ def sphere_sequence(lib):
     zref = o.pc(b)
     check(np.abs(z - zref).max() <= 1e-9 * np.abs(zref).max(),
           "sphere: preconditioner (lumped mass without the Coriolis term) against the oracle")
+
     rc, info, lam = c.solve(b, 1e-10)
     check(rc == 0 and c.residual(b, lam) <= 1.01e-10, f"sphere: fp64 FGMRES {info.iters} iterations")
     u_b, pi = np.empty(6 * c.ncell), np.empty(c.ncell)
