@@ -396,12 +396,20 @@ hipError_t launch_dgs_dots(hyb_ctx *c, const double *V, size_t n, int j, double 
   int slot = prof_begin(c, F_KRYLOV);
   const unsigned nb = std::min<unsigned>(kRedBlocks, nblk(n, kDgsStage * kBlock));
   static_assert(kBlock == 256, "four waves split the basis vectors");
-  if (j < 8)
-    hipLaunchKernelGGL((k_dgs_dots<2>), dim3(nb), dim3(kBlock), 0, c->stream, V, n, j, n, c->partial);
-  else if (j < 16)
-    hipLaunchKernelGGL((k_dgs_dots<4>), dim3(nb), dim3(kBlock), 0, c->stream, V, n, j, n, c->partial);
-  else
-    hipLaunchKernelGGL((k_dgs_dots<8>), dim3(nb), dim3(kBlock), 0, c->stream, V, n, j, n, c->partial);
+  // the j + 1 vectors a_0..a_j over four waves: exactly as many accumulator slots as needed (spare
+  // slots cost registers and occupancy: 8 slots for j = 16 ran at 3.6 TB/s, 4 slots at 5.2)
+  const int kw = (j + 4) / 4;
+  switch (kw) {
+#define HYB_DGS_CASE(K)                                                                                   \
+  case K:                                                                                                 \
+    hipLaunchKernelGGL((k_dgs_dots<K>), dim3(nb), dim3(kBlock), 0, c->stream, V, n, j, n, c->partial); \
+    break;
+    HYB_DGS_CASE(1) HYB_DGS_CASE(2) HYB_DGS_CASE(3) HYB_DGS_CASE(4)
+    HYB_DGS_CASE(5) HYB_DGS_CASE(6) HYB_DGS_CASE(7) HYB_DGS_CASE(8)
+#undef HYB_DGS_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
   hipLaunchKernelGGL(k_multidot_final, dim3(2 * j + 3), dim3(kBlock), 0, c->stream, c->partial, (int)nb, out_dev);
   prof_end(c, F_KRYLOV, slot);
   return hipGetLastError();

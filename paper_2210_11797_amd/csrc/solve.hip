@@ -262,27 +262,42 @@ __global__ void k_restrict(const T *__restrict__ R, const T *__restrict__ gamma,
   out[c] = gamma[c] * s;
 }
 
-// lambda_F += (P dPi)_F: average of the two cells of the facet (one sided on ground / lid).
+// lambda_F += (P dPi)_F: average of the two cells of the facet (one sided on ground / lid).  Laid
+// out like the row kernels: a thread owns one column (its horizontal facets) or one edge (its
+// vertical facets) for kRowChunk consecutive layers, so the edge's two columns are read once per
+// chunk and no facet index is divided back into (layer, column) (a thread per facet with 64-bit
+// divisions ran at 3.9 TB/s).
 template <typename T>
-__global__ void k_prolong(const T *__restrict__ dpi, T *__restrict__ lam, int nlev, int ncol, int nedge, size_t nz,
-                          size_t ntr, const int32_t *__restrict__ edge_col) {
-  size_t F = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (F >= ntr) return;
-  T v;
-  if (F < nz) {
-    int k = (int)(F / ncol), col = (int)(F - (size_t)k * ncol);
-    if (k == 0)
-      v = dpi[col];
-    else if (k == nlev)
-      v = dpi[(size_t)(nlev - 1) * ncol + col];
-    else
-      v = (T)0.5 * (dpi[(size_t)(k - 1) * ncol + col] + dpi[(size_t)k * ncol + col]);
-  } else {
-    size_t h = F - nz;
-    int k = (int)(h / nedge), e = (int)(h - (size_t)k * nedge);
-    v = (T)0.5 * (dpi[(size_t)k * ncol + edge_col[e]] + dpi[(size_t)k * ncol + edge_col[nedge + e]]);
+__global__ void __launch_bounds__(kRowBlock) k_prolong(const T *__restrict__ dpi, T *__restrict__ lam, int nlev,
+                                                    int ncol, int nedge, size_t nz,
+                                                    const int32_t *__restrict__ edge_col) {
+  const int ent = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k0 = blockIdx.y * kRowChunk;
+  if (ent < ncol) {
+    const int col = ent;
+#pragma unroll
+    for (int q = 0; q < kRowChunk; ++q) {
+      const int k = k0 + q;
+      if (k > nlev) break;
+      T v;
+      if (k == 0)
+        v = dpi[col];
+      else if (k == nlev)
+        v = dpi[(size_t)(nlev - 1) * ncol + col];
+      else
+        v = (T)0.5 * (dpi[(size_t)(k - 1) * ncol + col] + dpi[(size_t)k * ncol + col]);
+      lam[(size_t)k * ncol + col] += v;
+    }
+  } else if (ent < ncol + nedge) {
+    const int e = ent - ncol;
+    const int c0 = edge_col[e], c1 = edge_col[nedge + e];
+#pragma unroll
+    for (int q = 0; q < kRowChunk; ++q) {
+      const int k = k0 + q;
+      if (k >= nlev) break;
+      lam[nz + (size_t)k * nedge + e] += (T)0.5 * (dpi[(size_t)k * ncol + c0] + dpi[(size_t)k * ncol + c1]);
+    }
   }
-  lam[F] += v;
 }
 
 // Block-Jacobi sweep of the pressure multigrid (Sec. 2.3),
@@ -471,14 +486,106 @@ __global__ void __launch_bounds__(kBlock) k_mg_sweep_pcr(const T *__restrict__ H
   }
 }
 
-// x_out = x + c1 (x - xprev) + c2 x_out (a Chebyshev step on levels without the fused sweep; x_out holds
-// H_z^-1 (b - H x) on entry; a null xprev is the zero vector)
-template <typename T>
-__global__ void k_cheb_update(const T *__restrict__ x, const T *__restrict__ xprev, T *__restrict__ xout, size_t n,
-                              T c1, T c2) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) xout[i] = x[i] + c1 * (x[i] - (xprev ? xprev[i] : T(0))) + c2 * xout[i];
+// One block-Jacobi sweep of the pressure multigrid on a large level, fused into one pass up and down
+// every column (one column per lane, 64 consecutive columns per wavefront, so every [k][col] access
+// is coalesced): x_out = base + omega H_z^-1 (b - H X), with X = xin (MODE 1), xin plus the injected
+// coarse correction xc[parent] (MODE 2), or, for a Chebyshev step, base = X + c1 (X - xprev) (MODE 3;
+// a null xprev is the zero vector); base = X otherwise.  On the way up each level's 7-point residual
+// is formed from X of the column (kept in registers) and of its four neighbours and fed straight into
+// the forward elimination with the LU factors of H_z; y_k / u_k waits in LDS for the back
+// substitution on the way down, which reloads X for the base.  The loads of KC levels are issued
+// before the recurrence runs over them.  This replaces a residual kernel and a column-solve kernel
+// (the residual no longer goes through memory) with the same arithmetic in the same order.
+template <typename T, int MODE, int KC>
+__global__ void __launch_bounds__(kColBlock) k_mg_sweep_col(const T *__restrict__ H, const T *__restrict__ b,
+                                                            const T *__restrict__ xin, const T *__restrict__ xc,
+                                                            const T *__restrict__ fac, T *__restrict__ xout,
+                                                            int nlev, int ncol, int ncolc,
+                                                            const int32_t *__restrict__ nbr,
+                                                            const int32_t *__restrict__ parent, T omega,
+                                                            const T *__restrict__ xprev, T c1) {
+  extern __shared__ unsigned char smem_raw[];
+  T *wv = reinterpret_cast<T *>(smem_raw);
+  const int tid = threadIdx.x, bd = blockDim.x;
+  const int col = blockIdx.x * bd + tid;
+  if (col >= ncol) return;
+  const size_t n = (size_t)nlev * ncol;
+  int nb[4], pn[4] = {0, 0, 0, 0}, pc = 0;
+#pragma unroll
+  for (int f = 0; f < 4; ++f) nb[f] = nbr[(size_t)f * ncol + col];
+  if (MODE == 2) {
+    pc = parent[col];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) pn[f] = parent[nb[f]];
+  }
+  auto X = [&](int k, int cc, int pcc) -> T {
+    T v = xin[(size_t)k * ncol + cc];
+    if (MODE == 2) v += xc[(size_t)k * ncolc + pcc];
+    return v;
+  };
+  T xdn = 0, x0 = X(0, col, pc), y = 0;
+  for (int k0 = 0; k0 < nlev; k0 += KC) {
+    T hv[KC][7], bv[KC], xn[KC][4], xu[KC], lv[KC], iv[KC];
+#pragma unroll
+    for (int q = 0; q < KC; ++q) {
+      const int k = k0 + q;
+      if (k < nlev) {
+        const size_t c = (size_t)k * ncol + col;
+#pragma unroll
+        for (int s = 0; s < 5; ++s) hv[q][s] = H[(size_t)s * n + c];
+        hv[q][5] = k > 0 ? H[5 * n + c] : T(0);
+        hv[q][6] = k < nlev - 1 ? H[6 * n + c] : T(0);
+        bv[q] = b[c];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) xn[q][f] = X(k, nb[f], pn[f]);
+        xu[q] = k < nlev - 1 ? X(k + 1, col, pc) : T(0);
+        lv[q] = fac[c];
+        iv[q] = fac[n + c];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < KC; ++q) {
+      const int k = k0 + q;
+      if (k < nlev) {
+        T hx = hv[q][0] * x0;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) hx += hv[q][1 + f] * xn[q][f];
+        if (k > 0) hx += hv[q][5] * xdn;
+        if (k < nlev - 1) hx += hv[q][6] * xu[q];
+        const T r = bv[q] - hx;
+        y = r - lv[q] * y;
+        wv[(size_t)k * bd + tid] = y * iv[q];
+        xdn = x0;
+        x0 = xu[q];
+      }
+    }
+  }
+  T x = 0;
+  for (int k1 = nlev - 1; k1 >= 0; k1 -= KC) {
+    T cv[KC], w[KC], base[KC];
+#pragma unroll
+    for (int q = 0; q < KC; ++q) {
+      const int k = k1 - q;
+      if (k >= 0) {
+        const size_t c = (size_t)k * ncol + col;
+        cv[q] = fac[2 * n + c];
+        w[q] = wv[(size_t)k * bd + tid];
+        base[q] = X(k, col, pc);
+        if (MODE == 3) base[q] += c1 * (base[q] - (xprev ? xprev[c] : T(0)));
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < KC; ++q) {
+      const int k = k1 - q;
+      if (k >= 0) {
+        x = w[q] - cv[q] * x;
+        xout[(size_t)k * ncol + col] = base[q] + omega * x;
+      }
+    }
+  }
 }
+
+constexpr int kMgColKC = 4;  // levels whose loads a column issues together in the fused sweep
 
 template <typename T>
 hipError_t mg_smooth(hyb_ctx *c, int l, const T *b, const T *xin, const T *xc, T *xout, int mode, T om,
@@ -486,15 +593,15 @@ hipError_t mg_smooth(hyb_ctx *c, int l, const T *b, const T *xin, const T *xc, T
   const LevelDev &Lv = c->lv[l];
   const T *H = pick<T>(Lv.H, Lv.Hf);
   const T *fac = pick<T>(Lv.zf, Lv.zff);
-  T *r = (T *)Lv.r;
   size_t n = (size_t)c->nlev * Lv.ncol;
   size_t shm = sizeof(T) * (size_t)c->nlev * kColBlock;
   int ncolc = (l + 1 < c->nlevels) ? c->lv[l + 1].ncol : 1;
-  dim3 gc(nblk(Lv.ncol, kColBlock)), bc(kColBlock), gr(nblk(n)), br(kBlock);
+  dim3 gc(nblk(Lv.ncol, kColBlock)), bc(kColBlock);
   int slot = prof_begin(c, F_MG_SMOOTH);
-  // the fused sweep with cyclic reduction pays on small levels, where the Thomas recurrence of the
-  // two-kernel path is latency bound (1024 columns: 5.9 us against 4.4 + 12.1 us); on large levels
-  // its shuffles and divisions make it compute bound (65536 columns: 305 us against 69 + 35 us)
+  // the sweep with cyclic reduction (a wavefront per column) pays on small levels, where a lane per
+  // column leaves the recurrence latency bound (1024 columns: 5.9 us against 4.4 + 12.1 us for a
+  // residual and a column-solve kernel); on large levels its shuffles and divisions make it compute
+  // bound (65536 columns: 305 us against 69 + 35 us), and the lane-per-column sweep runs there
   if (c->nlev <= 64 && Lv.ncol <= kPcrMaxColumns) {
     const dim3 gw(nblk(Lv.ncol, kBlock / 64)), bw(kBlock);
     if (mode == 0)
@@ -513,22 +620,14 @@ hipError_t mg_smooth(hyb_ctx *c, int l, const T *b, const T *xin, const T *xc, T
     hipLaunchKernelGGL((k_column_solve<T, true, false>), gc, bc, shm, c->stream, b, fac, n, xin, xc, xout, c->nlev,
                        Lv.ncol, ncolc, Lv.parent, om);
   } else if (mode == 1) {
-    hipLaunchKernelGGL((k_mg_residual<T, false>), gr, br, 0, c->stream, H, b, xin, xc, r, c->nlev, Lv.ncol, ncolc,
-                       Lv.nbr, Lv.parent);
-    hipLaunchKernelGGL((k_column_solve<T, false, false>), gc, bc, shm, c->stream, (const T *)r, fac, n, xin, xc, xout,
-                       c->nlev, Lv.ncol, ncolc, Lv.parent, om);
+    hipLaunchKernelGGL((k_mg_sweep_col<T, 1, kMgColKC>), gc, bc, shm, c->stream, H, b, xin, xc, fac, xout, c->nlev,
+                       Lv.ncol, ncolc, Lv.nbr, Lv.parent, om, xprev, c1);
   } else if (mode == 3) {
-    // residual, its column solve into xout, then the three-term update in place
-    hipLaunchKernelGGL((k_mg_residual<T, false>), gr, br, 0, c->stream, H, b, xin, xc, r, c->nlev, Lv.ncol, ncolc,
-                       Lv.nbr, Lv.parent);
-    hipLaunchKernelGGL((k_column_solve<T, true, false>), gc, bc, shm, c->stream, (const T *)r, fac, n, xin, xc, xout,
-                       c->nlev, Lv.ncol, ncolc, Lv.parent, T(1));
-    hipLaunchKernelGGL((k_cheb_update<T>), gr, br, 0, c->stream, xin, xprev, xout, n, c1, om);
+    hipLaunchKernelGGL((k_mg_sweep_col<T, 3, kMgColKC>), gc, bc, shm, c->stream, H, b, xin, xc, fac, xout, c->nlev,
+                       Lv.ncol, ncolc, Lv.nbr, Lv.parent, om, xprev, c1);
   } else {
-    hipLaunchKernelGGL((k_mg_residual<T, true>), gr, br, 0, c->stream, H, b, xin, xc, r, c->nlev, Lv.ncol, ncolc,
-                       Lv.nbr, Lv.parent);
-    hipLaunchKernelGGL((k_column_solve<T, false, true>), gc, bc, shm, c->stream, (const T *)r, fac, n, xin, xc, xout,
-                       c->nlev, Lv.ncol, ncolc, Lv.parent, om);
+    hipLaunchKernelGGL((k_mg_sweep_col<T, 2, kMgColKC>), gc, bc, shm, c->stream, H, b, xin, xc, fac, xout, c->nlev,
+                       Lv.ncol, ncolc, Lv.nbr, Lv.parent, om, xprev, c1);
   }
   prof_end(c, F_MG_SMOOTH, slot);
   return hipGetLastError();
@@ -821,8 +920,8 @@ hipError_t precondition(hyb_ctx *c, const T *r, T *z) {
     }
     // prolongation and update
     slot = prof_begin(c, F_PROLONG);
-    hipLaunchKernelGGL((k_prolong<T>), dim3(nblk(ntr)), dim3(kBlock), 0, c->stream, (const T *)c->lv[0].x, tA,
-                       c->nlev, c->ncol, c->nedge, (size_t)c->nz, ntr, L0.edge_col);
+    hipLaunchKernelGGL((k_prolong<T>), row_grid(c, false), dim3(kRowBlock), 0, c->stream, (const T *)c->lv[0].x, tA,
+                       c->nlev, c->ncol, c->nedge, (size_t)c->nz, L0.edge_col);
     prof_end(c, F_PROLONG, slot);
     HYB_TRY(hipGetLastError());
   }  // coarse_mode 1: LineSmooth alone (no coarse correction)
@@ -851,7 +950,10 @@ hipError_t configure_kernels(int nlev) {
   const void *fns[] = {
       (const void *)k_column_solve<double, true, false>, (const void *)k_column_solve<double, false, false>,
       (const void *)k_column_solve<double, false, true>, (const void *)k_column_solve<float, true, false>,
-      (const void *)k_column_solve<float, false, false>, (const void *)k_column_solve<float, false, true>};
+      (const void *)k_column_solve<float, false, false>, (const void *)k_column_solve<float, false, true>,
+      (const void *)k_mg_sweep_col<double, 1, kMgColKC>, (const void *)k_mg_sweep_col<double, 2, kMgColKC>,
+      (const void *)k_mg_sweep_col<double, 3, kMgColKC>, (const void *)k_mg_sweep_col<float, 1, kMgColKC>,
+      (const void *)k_mg_sweep_col<float, 2, kMgColKC>, (const void *)k_mg_sweep_col<float, 3, kMgColKC>};
   for (const void *f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, need);
     if (e != hipSuccess) return e;

@@ -264,3 +264,39 @@ def test_edge_cases():
     # bad arguments are rejected, not crashed on
     with pytest.raises(RuntimeError):
         s.trace_apply(b, b)
+
+
+WIDE = {
+    # 16384 columns on the fine level: its sweeps run one lane per column (residual and column solve
+    # fused); the coarse level of 4096 columns takes the wavefront-per-column sweeps
+    "wide128": dict(nx=128, ny=128, nlev=4, dx=5e3, dz=250.0, mg_levels=2, perturb=0.05),
+    # a coarsest level of 8192 columns: its Chebyshev steps run one lane per column as well
+    "wide_coarsest": dict(nx=256, ny=128, nlev=2, dx=5e3, dz=250.0, mg_levels=2, perturb=0.05),
+}
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name", list(WIDE))
+def test_precondition_large_levels(name):
+    """hyb_precondition on meshes whose multigrid levels have more than 4096 columns, against the
+    oracle, to 100 eps cond(H) (cond by the 1-norm estimate of H and H^-1)."""
+    import scipy.sparse.linalg as spla
+    import torch
+
+    say(f"[setup] case {name}: {WIDE[name]}")
+    prob = make_box(**WIDE[name])
+    orc = OracleProblem(prob)
+    s = make_solver(prob)
+    r = np.random.default_rng(3).standard_normal(orc.mesh.ntrace)
+    z = torch.empty(orc.mesh.ntrace, dtype=torch.float64, device="cuda")
+    s.precondition(dev(r), z)
+    ref = orc.pc(r)
+    err = rel_max(host(z), ref)
+    H = orc.H.tocsc()
+    lu = spla.splu(H)
+    hinv = spla.LinearOperator(H.shape, matvec=lu.solve, rmatvec=lambda v: lu.solve(v, trans="T"))
+    cond_h = spla.onenormest(H) * spla.onenormest(hinv)
+    tol = 100 * np.finfo(float).eps * cond_h
+    say(f"[precondition] {name}: rel err {err:.2e} (cond(H) ~ {cond_h:.1e}, tol {tol:.1e})")
+    assert err <= tol
+    s.close()
