@@ -179,13 +179,34 @@ def trace_prolongation(mesh: BoxMesh):
     return sp.csr_matrix((w, (rows, cols)), shape=(mesh.ntrace, mesh.ncell))
 
 
-def line_smoother_matrix(mesh: BoxMesh, S):
-    """D = blockdiag(S^zz_j) + diag(S^hh): the part of S inverted by LineSmooth."""
+def line_smoother_matrix(mesh: BoxMesh, S, patch=None):
+    """D = blockdiag(S^zz_j) + diag(S^hh): the part of S inverted by LineSmooth.
+
+    patch (optional, one patch index per column): the future-work variant of Sec. 4.2 that caches
+    the tridiagonal column matrices over small patches of the grid: every column of a patch uses
+    the same S^zz, here the mean of the patch's columns' S^zz entries (below, diagonal, above at
+    every level)."""
     Sc = sp.coo_matrix(S)
     zr, zc = Sc.row < mesh.n_zface, Sc.col < mesh.n_zface
     same_col = (Sc.row % mesh.ncol) == (Sc.col % mesh.ncol)
     keep = (zr & zc & same_col) | (~zr & (Sc.row == Sc.col))
-    return sp.csr_matrix((Sc.data[keep], (Sc.row[keep], Sc.col[keep])), shape=S.shape)
+    if patch is None:
+        return sp.csr_matrix((Sc.data[keep], (Sc.row[keep], Sc.col[keep])), shape=S.shape)
+    ncol = mesh.ncol
+    patch = np.asarray(patch, np.int64)
+    npatch = int(patch.max()) + 1
+    count = np.bincount(patch, minlength=npatch).astype(np.float64)
+    zz = keep & zr
+    rows, cols, vals = Sc.row[zz], Sc.col[zz], Sc.data[zz]
+    k, col = rows // ncol, rows % ncol
+    off = (cols // ncol) - k + 1  # 0 below, 1 diagonal, 2 above
+    mean = np.zeros((3, mesh.nlev + 1, npatch))
+    np.add.at(mean, (off, k, patch[col]), vals)
+    mean /= count[None, None, :]
+    zvals = mean[off, k, patch[col]]
+    hh = keep & ~zr
+    return sp.csr_matrix((np.concatenate([zvals, Sc.data[hh]]),
+                          (np.concatenate([rows, Sc.row[hh]]), np.concatenate([cols, Sc.col[hh]]))), shape=S.shape)
 
 
 class TwoLevel:
@@ -193,15 +214,16 @@ class TwoLevel:
 
     def __init__(self, mesh: BoxMesh, S, H, omega=0.6, n_pre=1, n_post=2, mg_levels=4,
                  omega_p=0.9, mg_pre=1, mg_post=2, mg_coarse_sweeps=6, sign=+1.0,
-                 mg_coarse_cheb=COARSE_CHEB, coarse=True):
+                 mg_coarse_cheb=COARSE_CHEB, coarse=True, smoother_patch=None):
         """coarse=False: no coarse correction, the preconditioner is n_pre + n_post LineSmooth
         sweeps from zero (the paper's hybridised single-level Configuration 2); coarse=("bicgstab",
         rtol): the coarse pressure system solved by BiCGStab preconditioned by the V-cycle to rtol
-        (the paper's Configurations 3a and 3b)."""
+        (the paper's Configurations 3a and 3b); smoother_patch: a patch index per column, for
+        LineSmooth with column matrices cached per patch (``line_smoother_matrix``)."""
         self.mesh, self.S = mesh, sp.csr_matrix(S)
         self.omega, self.n_pre, self.n_post, self.sign = omega, n_pre, n_post, sign
         self.coarse = coarse
-        self.D = line_smoother_matrix(mesh, self.S)
+        self.D = line_smoother_matrix(mesh, self.S, smoother_patch)
         self.D_lu = spla.splu(self.D.tocsc())
         self.P = trace_prolongation(mesh)
         parents = getattr(mesh, "parents", None)

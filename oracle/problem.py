@@ -22,7 +22,7 @@ def cells_from_soa(r_ub, r_pi):
 class OracleProblem:
     def __init__(self, prob, *, with_mixed=True, with_precond=True, omega=0.6, n_pre=1,
                  n_post=2, mg_levels=None, omega_p=0.9, mg_pre=1, mg_post=2, mg_coarse_sweeps=6,
-                 mg_coarse_cheb=COARSE_CHEB, coarse=True):
+                 mg_coarse_cheb=COARSE_CHEB, coarse=True, smoother_patch=False):
         self.prob = prob
         if getattr(prob, "geom", "box") == "shell":
             self.mesh = TableMesh(prob.nlev, prob.col_edge, prob.edge_col, prob.edge_lf,
@@ -41,7 +41,8 @@ class OracleProblem:
             self.pc = TwoLevel(self.mesh, self.hyb.S, self.H, omega=omega, n_pre=n_pre,
                                n_post=n_post, mg_levels=mg_levels, omega_p=omega_p, mg_pre=mg_pre,
                                mg_post=mg_post, mg_coarse_sweeps=mg_coarse_sweeps,
-                               mg_coarse_cheb=mg_coarse_cheb, coarse=coarse)
+                               mg_coarse_cheb=mg_coarse_cheb, coarse=coarse,
+                               smoother_patch=prob.levels[1].parent if smoother_patch else None)
 
     def solve_fgmres(self, B, rtol=1e-8, restart=30, maxit=500, precondition=True):
         M = self.pc if precondition else (lambda r: r)
