@@ -62,3 +62,26 @@ def static_for(prob, orc=None):
     else:
         vol = prob.dx * prob.dy * np.repeat(np.diff(prob.z), prob.ncol)
     return onn.static_inputs(vol, prob.z, prob.ncol)
+
+
+def oracle_all_rows(spec, sols, tmpdir, timeout=900):
+    """The oracle's all-rows residuals (oracle/allrows.py) of candidate solutions [(lam, u_b, pi)],
+    computed in a separate process (a pool of forked CPU workers that never touch the GPU) for the
+    synthetic problem ``spec`` and its right-hand side seed."""
+    import json
+    import os
+    import subprocess
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    path = os.path.join(str(tmpdir), "candidates.npz")
+    arrays = {"count": len(sols)}
+    for i, (lam, ub, pi) in enumerate(sols):
+        arrays.update({f"lam{i}": lam, f"ub{i}": ub, f"pi{i}": pi})
+    np.savez(path, **arrays)
+    workers = max(1, min(16, os.cpu_count() or 1))
+    say(f"[oracle all rows] {spec} with {workers} worker processes")
+    out = subprocess.run([sys.executable, "-m", "oracle.allrows", json.dumps(spec), path, str(workers)],
+                         capture_output=True, text=True, cwd=root, timeout=timeout)
+    if out.returncode != 0:
+        raise RuntimeError(out.stderr[-3000:])
+    return json.loads(out.stdout.strip().splitlines()[-1])

@@ -84,3 +84,35 @@ def test_direct_trace_solve_residual():
     assert np.linalg.norm(B - o.hyb.S @ lam) <= 1e-12 * np.linalg.norm(B)
     lu = spla.splu(o.hyb.S.tocsc())
     np.testing.assert_allclose(lu.solve(B), lam, rtol=0, atol=1e-12 * np.abs(lam).max())
+
+
+def test_all_rows_residuals_match_the_assembled_operators():
+    """The chunked all-rows residuals (used at sizes the assembled operators do not fit) equal
+    the assembled ones on a small box: ||B - S lambda|| / ||B||, the continuity defect C^T X
+    (= B - S lambda for the recovered X) and the componentwise backward error of the 2x2 system."""
+    from oracle.allrows import all_rows
+    from oracle.local import local_matrices
+    from oracle.problem import OracleProblem, cells_from_soa
+    from synth import make_box, make_rhs
+
+    prob = make_box(nx=6, ny=4, nlev=5, dx=8e3, dz=600.0, mg_levels=1, perturb=0.05)
+    o = OracleProblem(prob, with_precond=False)
+    ruc, rpc = cells_from_soa(*make_rhs(prob, 3))
+    lam_ref, _, _, B = o.hyb.solve_direct(ruc, rpc)
+    lam = lam_ref + 1e-6 * np.random.default_rng(4).standard_normal(lam_ref.shape) * np.abs(lam_ref).max()
+    ub, pi = o.hyb.recover(lam, ruc, rpc)
+    res = all_rows(lambda cells: local_matrices(o.mesh, prob, cells=cells), o.mesh, ruc, rpc,
+                   [(lam, ub, pi)], chunk=37)[0]
+    tr = np.linalg.norm(B - o.hyb.S @ lam) / np.linalg.norm(B)
+    assert abs(res["trace_res"] - tr) <= 1e-9 * tr
+    # C^T X of the recovery is B - S lambda (Sec. 2.4)
+    assert abs(res["defect_norm"] - tr) <= 1e-6 * tr
+    u = np.zeros(o.mixed.nu)
+    cnt = np.zeros(o.mixed.nu)
+    for a in range(6):
+        d = o.mixed.udof[o.mesh.cell_faces[:, a]]
+        ok = d >= 0
+        np.add.at(u, d[ok], o.mesh.cell_sign[ok, a] * ub[ok, a])
+        np.add.at(cnt, d[ok], 1.0)
+    berr = o.mixed.backward_error(u / cnt, pi, ruc, rpc)
+    assert abs(res["mixed_berr"] - berr) <= 1e-9 * berr
