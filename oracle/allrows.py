@@ -11,9 +11,9 @@ of its facets:
 * the recovered velocity's continuity: the two outward fluxes of every interior facet sum to zero
   for the exact solution (C^T X = B - S lambda, Sec. 2.4);
 * the 2x2 system of Sec. 2.2 at (u, Pi): every interior facet's velocity taken as the mean of its two
-  cells' globally oriented fluxes, the componentwise backward error
-  max_i |R - M x|_i / (|M| |x| + |R|)_i (scale invariant per row: the rows of this system differ in
-  scale by many orders of magnitude).  The facet term of g is left out, so theta* must be single
+  cells' globally oriented fluxes, the relative residual ||R - M x|| / ||R|| and the componentwise
+  backward error max_i |R - M x|_i / (|M| |x| + |R|)_i (scale invariant per row: the rows of this
+  system differ in scale by many orders of magnitude).  The facet term of g is left out, so theta* must be single
   valued on facets (horizontally homogeneous reference states).
 
 ``chunk_contributions`` is the work of one chunk (independent of the others, so a caller may run
@@ -41,8 +41,12 @@ def chunk_contributions(cell_matrices, cell_faces, cell_sign, cells, r_ub_cells,
         x = np.concatenate([sgn * u_glob[faces], pi[cells, None]], axis=1)  # outward fluxes and Pi
         ax = np.einsum("cij,cj->ci", A, x)
         aax = np.einsum("cij,cj->ci", np.abs(A), np.abs(x))
+        # |A_K| |x - X_K|: the cell's own fluxes X_K satisfy its equations, so the 2x2 residual of a
+        # row is what replacing them by the facet means changes, bounded by this
+        adev = np.einsum("cij,cj->ci", np.abs(A[:, :, :6]), np.abs(x[:, :6] - u_b[cells]))
         out["cands"].append(dict(sl=np.einsum("cfg,cg->cf", Sc, lam[faces]), mu=sgn * ax[:, :6], mu_abs=aax[:, :6],
-                                 rp=r_pi_cells[cells] - ax[:, 6], rp_abs=aax[:, 6] + np.abs(r_pi_cells[cells])))
+                                 mu_dev=adev[:, :6], rp=r_pi_cells[cells] - ax[:, 6],
+                                 rp_abs=aax[:, 6] + np.abs(r_pi_cells[cells]), rp_dev=adev[:, 6]))
     return out
 
 
@@ -50,7 +54,9 @@ def all_rows(cell_matrices, mesh, r_ub_cells, r_pi_cells, solutions, chunk=32768
     """For every candidate (lam, u_b, pi) in ``solutions`` (u_b (ncell, 6) outward fluxes, pi
     (ncell,)) returns dict(trace_res = ||B - S lambda|| / ||B||, defect_norm = ||C^T X|| / ||B||
     (the outward fluxes of every facet summed over its cells), defect = its largest entry / ||B||,
-    mixed_berr).  The cell matrices are built once per chunk for all candidates; map_fn may be a
+    mixed_res = ||R - M x|| / ||R|| and mixed_berr of the 2x2 system, and mixed_berr_bound: the
+    backward error that the continuity defect alone can cause, max_i (|M| |x - X|)_i / (|M| |x| + |R|)_i
+    with X the cells' own recovered fluxes).  The cell matrices are built once per chunk for all candidates; map_fn may be a
     thread pool's map over the chunk start indices."""
     nf, nc = mesh.ntrace, mesh.ncell
     cf, cs = mesh.cell_faces, mesh.cell_sign
@@ -68,18 +74,18 @@ def all_rows(cell_matrices, mesh, r_ub_cells, r_pi_cells, solutions, chunk=32768
         return chunk_contributions(cell_matrices, cf, cs, cells, r_ub_cells, r_pi_cells, cands)
 
     B = np.zeros(nf)
-    acc = [dict(sl=np.zeros(nf), mu=np.zeros(nf), mu_abs=np.zeros(nf), rp=np.zeros(nc), rp_abs=np.zeros(nc))
-           for _ in cands]
+    acc = [dict(sl=np.zeros(nf), mu=np.zeros(nf), mu_abs=np.zeros(nf), mu_dev=np.zeros(nf), rp=np.zeros(nc),
+                rp_abs=np.zeros(nc), rp_dev=np.zeros(nc)) for _ in cands]
     starts = list(range(0, nc, chunk))
     for s0, part in zip(starts, map_fn(work, starts)):
         f = part["faces"].ravel()
         B += np.bincount(f, weights=part["b"].ravel(), minlength=nf)
         for a, pc in zip(acc, part["cands"]):
-            for key in ("sl", "mu", "mu_abs"):
+            for key in ("sl", "mu", "mu_abs", "mu_dev"):
                 a[key] += np.bincount(f, weights=pc[key].ravel(), minlength=nf)
             n = pc["rp"].shape[0]
-            a["rp"][s0 : s0 + n] = pc["rp"]
-            a["rp_abs"][s0 : s0 + n] = pc["rp_abs"]
+            for key in ("rp", "rp_abs", "rp_dev"):
+                a[key][s0 : s0 + n] = pc[key]
     bnorm = float(np.linalg.norm(B))
     rhs_u = np.bincount(cf.ravel(), weights=(cs * r_ub_cells).ravel(), minlength=nf)
     it = ~bnd
@@ -87,9 +93,15 @@ def all_rows(cell_matrices, mesh, r_ub_cells, r_pi_cells, solutions, chunk=32768
     for a, ow in zip(acc, outward):
         berr_u = np.abs(rhs_u[it] - a["mu"][it]) / (a["mu_abs"][it] + np.abs(rhs_u[it]))
         berr_p = np.abs(a["rp"]) / a["rp_abs"]
+        bound_u = a["mu_dev"][it] / (a["mu_abs"][it] + np.abs(rhs_u[it]))
+        bound_p = a["rp_dev"] / a["rp_abs"]
+        mres = np.sqrt(np.sum((rhs_u[it] - a["mu"][it]) ** 2) + np.sum(a["rp"] ** 2))
+        rnorm = np.sqrt(np.sum(rhs_u[it] ** 2) + np.sum(r_pi_cells ** 2))
         res.append(dict(trace_res=float(np.linalg.norm(B - a["sl"])) / bnorm,
                         defect=float(np.abs(ow).max()) / bnorm, defect_norm=float(np.linalg.norm(ow)) / bnorm,
-                        mixed_berr=max(float(berr_u.max()), float(berr_p.max())), bnorm=bnorm))
+                        mixed_berr=max(float(berr_u.max()), float(berr_p.max())),
+                        mixed_berr_bound=max(float(bound_u.max()), float(bound_p.max())), mixed_res=float(mres / rnorm),
+                        bnorm=bnorm))
     return res
 
 

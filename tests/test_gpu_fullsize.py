@@ -117,7 +117,8 @@ def test_fullsize_all_rows_residuals(tmp_path):
     the oracle builds every cell matrix (in chunks) and evaluates over all rows: ||B - S lambda|| /
     ||B||, the continuity defect of the recovered velocity (the sum of the two outward fluxes of
     every facet, = B - S lambda, Sec. 2.4) and the componentwise backward error of the recovered
-    (u, Pi) in the unhybridised 2x2 system of Sec. 2.2."""
+    (u, Pi) in the unhybridised 2x2 system of Sec. 2.2, which must stay within what the continuity
+    defect alone can cause (every cell satisfies its own equations at its recovered fluxes)."""
     import torch
 
     from gpu_common import oracle_all_rows
@@ -144,10 +145,12 @@ def test_fullsize_all_rows_residuals(tmp_path):
     for (precision, rtol, info), r in zip(infos, res):
         say(f"[fullsize all rows p{precision}] its {info['iters']} reported {info['rel_res']:.3e}, oracle "
             f"||B - S lambda||/||B|| {r['trace_res']:.3e}, continuity defect {r['defect_norm']:.3e} "
-            f"(max entry {r['defect']:.1e}), 2x2 backward error {r['mixed_berr']:.1e}")
+            f"(max entry {r['defect']:.1e}), 2x2 backward error {r['mixed_berr']:.1e} "
+            f"(defect allows {r['mixed_berr_bound']:.1e})")
         assert info["status"] == 0 and info["rel_res"] <= rtol
         assert r["trace_res"] <= 1.05 * rtol
         assert abs(r["trace_res"] - info["rel_res"]) <= 0.05 * info["rel_res"]
         assert abs(r["defect_norm"] - r["trace_res"]) <= 0.05 * r["trace_res"]
-        if precision == 0:
-            assert r["mixed_berr"] <= 1e-9
+        # the recovered (u, Pi) solves the 2x2 system up to its continuity defect: every row's
+        # backward error within what |M| |x - X| of that defect allows (plus rounding)
+        assert r["mixed_berr"] <= r["mixed_berr_bound"] + 1e-13

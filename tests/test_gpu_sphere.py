@@ -234,7 +234,8 @@ def test_c192_solves_fp64_and_mixed(tmp_path):
     """C192 x 30 (the mixed-precision workload): FP64 to rtol 1e-10 and the mixed form to 1e-8,
     recovery, and the oracle's residuals over all rows from every cell matrix (built in chunks):
     ||B - S lambda|| / ||B||, the continuity defect of the recovered velocity and the componentwise
-    backward error of (u, Pi) in the 2x2 system; the mixed solution against the FP64 one."""
+    backward error of (u, Pi) in the 2x2 system, within what the continuity defect alone can cause;
+    the mixed solution's error within 10x the FP64 method's own error at the same tolerance."""
     st = big()
     import torch
 
@@ -261,16 +262,27 @@ def test_c192_solves_fp64_and_mixed(tmp_path):
     for (precision, rtol, info), r in zip(infos, res):
         say(f"[c192 all rows p{precision}] its {info['iters']} reported {info['rel_res']:.3e}, oracle "
             f"||B - S lambda||/||B|| {r['trace_res']:.3e}, continuity defect {r['defect_norm']:.3e}, "
-            f"2x2 backward error {r['mixed_berr']:.1e}")
+            f"2x2 backward error {r['mixed_berr']:.1e} "
+            f"(defect allows {r['mixed_berr_bound']:.1e})")
         assert info["status"] == 0 and info["rel_res"] <= rtol
         assert r["trace_res"] <= 1.05 * rtol
         assert abs(r["trace_res"] - info["rel_res"]) <= 0.05 * info["rel_res"]
         assert abs(r["defect_norm"] - r["trace_res"]) <= 0.05 * r["trace_res"]
-        if precision == 0:
-            assert r["mixed_berr"] <= 1e-7
+        # the recovered (u, Pi) solves the 2x2 system up to its continuity defect: every row's
+        # backward error within what |M| |x - X| of that defect allows (plus rounding)
+        assert r["mixed_berr"] <= r["mixed_berr_bound"] + 1e-13
+    # the mixed form's error against the FP64 method's own error at the same tolerance (an FP64
+    # solve to 1e-8), both measured from the FP64 solution to 1e-10
+    s = st["s"]
+    b = torch.empty(mesh.ntrace, dtype=torch.float64, device="cuda")
+    lam = torch.zeros(mesh.ntrace, dtype=torch.float64, device="cuda")
+    s.condense(dev(r_ub), dev(r_pi), b)
+    info = s.solve(b, lam, rtol=1e-8, maxit=500)
     err = rel_norm(sols[1][0], sols[0][0])
-    say(f"[c192] mixed vs FP64 solution: rel 2-norm difference {err:.2e}")
-    assert err <= 1e-5
+    err64 = rel_norm(host(lam), sols[0][0])
+    say(f"[c192] solution at 1e-8 against the one at 1e-10: mixed form {err:.2e}, FP64 ({info['iters']} "
+        f"iterations, residual {info['rel_res']:.2e}) {err64:.2e}")
+    assert info["status"] == 0 and err <= 10 * err64
 
 
 # ------------------------------------------------------------------------------------------------

@@ -116,3 +116,12 @@ def test_all_rows_residuals_match_the_assembled_operators():
         np.add.at(cnt, d[ok], 1.0)
     berr = o.mixed.backward_error(u / cnt, pi, ruc, rpc)
     assert abs(res["mixed_berr"] - berr) <= 1e-9 * berr
+    # every cell satisfies its own equations at its recovered fluxes, so the 2x2 residual is the
+    # continuity defect's doing: the backward error stays under what |M| |x - X| allows; a wrong
+    # recovered Pi breaks that
+    assert berr <= res["mixed_berr_bound"] + 1e-13
+    ub0, pi0 = o.hyb.recover(lam_ref, ruc, rpc)
+    good, bad = all_rows(lambda cells: local_matrices(o.mesh, prob, cells=cells), o.mesh, ruc, rpc,
+                         [(lam_ref, ub0, pi0), (lam_ref, ub0, pi0 * (1 + 1e-6))], chunk=37)
+    assert good["mixed_berr"] <= good["mixed_berr_bound"] + 1e-13
+    assert bad["mixed_berr"] > 10 * bad["mixed_berr_bound"]
