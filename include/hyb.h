@@ -60,6 +60,8 @@ extern "C" {
 #define HYB_ENOMEM (-4)        /* device allocation failed */
 #define HYB_NOT_CONVERGED 1    /* hyb_solve: maxit reached above rtol */
 #define HYB_BREAKDOWN 2        /* hyb_solve: NaN/Inf or a zero Arnoldi vector before convergence */
+#define HYB_STAGNATED 3        /* hyb_solve: two restart cycles in a row each left more than 99.9 %
+                                  of the true residual (e.g. a tolerance below its rounding floor) */
 
 #define HYB_PREC_FP64 0        /* every step in FP64 */
 #define HYB_PREC_MIXED 1       /* FP32 preconditioner and preconditioned basis, FP64 outer Krylov */
@@ -139,11 +141,21 @@ typedef struct {
      1e-14 and 3b with 1e-2; order 0 and HYB_PREC_FP64 only, HYB_EINVAL otherwise) */
   int32_t coarse_mode;
   double coarse_rtol;
+  /* LineSmooth's column matrices S^zz (Alg. 1): 0 = each column's own (the default); 1 = cached
+     per 2x2 patch of columns (the patches of the first multigrid coarsening; needs at least 2
+     levels): every column of a patch uses the mean of the patch's S^zz, whose LU factors are kept
+     once per patch (the future-work variant of Sec. 4.2; order 0 only, HYB_EINVAL otherwise) */
+  int32_t smoother_patch;
+  /* the network's training passes (hyb_nn_forward and the loss / gradient / train-step calls):
+     0 = BF16 activations and backpropagated fields on BF16 matrix cores (16x16x32 products, FP32
+     accumulation; the default); 1 = FP32 activations on the vector units, kept as a reference for
+     the BF16 path.  The stage inside hyb_solve always runs the BF16 inference passes. */
+  int32_t nn_fp32;
 } hyb_params;
 
 typedef struct {
   int32_t iters;        /* FGMRES iterations (preconditioner applications) */
-  int32_t status;       /* HYB_OK, HYB_NOT_CONVERGED or HYB_BREAKDOWN */
+  int32_t status;       /* HYB_OK, HYB_NOT_CONVERGED, HYB_BREAKDOWN or HYB_STAGNATED */
   int32_t restarts;
   double rel_res;       /* true ||B - S lambda||_2 / ||B||_2 at exit, computed in FP64 */
   double *history;      /* optional host array: Arnoldi residual estimate per iteration */
@@ -210,7 +222,7 @@ int hyb_precondition(hyb_ctx *ctx, const double *r, double *z);
 /* Flexible GMRES on S lambda = B_lambda, right preconditioned by Alg. 2.
    lambda [ntrace] is the initial guess on entry and the solution on exit.
    Stops when the FP64 relative residual ||B - S lambda|| / ||B|| <= rtol or
-   after maxit iterations.  Returns HYB_OK, HYB_NOT_CONVERGED, HYB_BREAKDOWN
+   after maxit iterations.  Returns HYB_OK, HYB_NOT_CONVERGED, HYB_BREAKDOWN, HYB_STAGNATED
    or a negative error; info (may be NULL) gets iterations and residuals. */
 int hyb_solve(hyb_ctx *ctx, const double *b_lambda, double *lambda, double rtol, int32_t maxit,
               hyb_info *info);
@@ -232,6 +244,30 @@ int hyb_solve_noalloc(hyb_ctx *ctx, const double *b_lambda, double *lambda, doub
    outward fluxes of the broken velocity, pi [nlev][ncol] Exner pressure. */
 int hyb_recover(hyb_ctx *ctx, const double *r_ub, const double *r_pi, const double *lambda,
                 double *u_b, double *pi);
+
+/* ----- The whole linear solve of a time step: theta' and rho' around the 2x2 system -----
+   Elimination before the solve (order 0, box or cubed sphere; HYB_ESTATE before
+   hyb_assemble_local, whose reference state it uses).  Sec. 2.1: theta' eliminated from the
+   linearised equations, which moves r_theta into the momentum right-hand side
+   (r_u - tau_u dt c_p z_hat d(Pihat*) / dz r_theta) and the equation of state (r_Pi + r_theta / theta*);
+   Sec. 2.2: rho' = M3^-1 (R_rho - D u) eliminated from the 3x3 matrix system, which adds
+   M3^rho M3^-1 R_rho to the pressure right-hand side.  Inputs: r_ub [6][nlev][ncol] the broken
+   momentum dual vector (as for hyb_condense), r_rho and r_pi [nlev][ncol] cell values of the
+   density and equation-of-state residuals, r_theta [nlev+1][ncol] the potential-temperature
+   residual on the horizontal facets (the W_theta nodes).  Outputs: r_ub_bar [6][nlev][ncol] and
+   r_pi_bar [nlev][ncol] (the pressure dual vector), the right-hand side hyb_condense and
+   hyb_recover take.  r_ub_bar may be r_ub and r_pi_bar may be r_pi (in place). */
+int hyb_eliminate(hyb_ctx *ctx, const double *r_ub, const double *r_rho, const double *r_theta, const double *r_pi,
+                  double *r_ub_bar, double *r_pi_bar);
+
+/* Back-substitution after hyb_recover (Sec. 2.1, 2.2): rho [nlev][ncol] = r_rho - tau_rho dt rho*
+   (sum of the cell's outward fluxes u_b) / |K|, and theta [2][nlev][ncol] the potential
+   temperature increment at each cell's bottom (index 0) and top (1) W_theta node,
+   r_theta - tau_theta dt (z_hat . u) d(theta*) / dz with the vertical velocity of the cell's own
+   broken velocity there (theta' jumps across a horizontal facet where d(theta*) / dz does).
+   Outputs must not alias inputs (HYB_EINVAL). */
+int hyb_back_substitute(hyb_ctx *ctx, const double *r_rho, const double *r_theta, const double *u_b, double *rho,
+                        double *theta);
 
 /* ----- Configuration 1 of the paper: the unhybridised system (Sec. 2.2, 2.3) -----
    The velocity / Exner-pressure system of Sec. 2.2 on the same assembled cells (order 0 only;
@@ -328,6 +364,19 @@ int hyb_nn_energy_grad(hyb_ctx *ctx, const float *x, const double *rhat, int32_t
 /* one Adam step on the energy loss */
 int hyb_nn_energy_train_step(hyb_ctx *ctx, const float *x, const double *rhat, int32_t nsamp, float lr,
                              double *loss);
+/* The same step on the pairs idx[0..nsamp) (HOST int32, each in [0, npairs)) of a set of pairs X
+   [npairs][nlev][ncol] (DEVICE FP32) and R (DEVICE FP64), gathered inside the library.  HYB_EINVAL
+   for an index out of range. */
+int hyb_nn_energy_train_step_pairs(hyb_ctx *ctx, const float *X, const double *R, int64_t npairs,
+                                   const int32_t *idx, int32_t nsamp, float lr, double *loss);
+/* One training pair from the plain method (the hook of the stage is the coarse correction of
+   Alg. 2): the two-level cycle (Alg. 2, without the learned stage, in the context's precision) taken
+   as a stationary iteration, z = M(r) and r <- r - S z, then c = Gamma P^T r, s = rms(c) over the
+   cells, x = c / s (FP32) and rhat = P^T r / s (FP64).  r: DEVICE FP64 [ntrace], in/out; x, rhat:
+   DEVICE [nlev][ncol]; scale (host, may be NULL): s.  Calling it again on the same r gives the next
+   pair of the iteration.  Returns HYB_BREAKDOWN (positive) when s is zero or not finite (x and rhat
+   are then not usable); HYB_ESTATE before hyb_condense or at order 1. */
+int hyb_nn_cycle_pair(hyb_ctx *ctx, double *r, float *x, double *rhat, double *scale);
 
 const char *hyb_last_error(const hyb_ctx *ctx);
 void hyb_destroy(hyb_ctx *ctx);

@@ -10,6 +10,7 @@ from ._native import (  # noqa: F401
     GEOM_BOX,
     GEOM_SHELL,
     HYB_BREAKDOWN,
+    HYB_STAGNATED,
     HYB_NOT_CONVERGED,
     HYB_OK,
     LIB_PATH,

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libhyb.so")
 HYB_OK = 0
 HYB_NOT_CONVERGED = 1
 HYB_BREAKDOWN = 2
+HYB_STAGNATED = 3
 PREC_FP64 = 0
 PREC_MIXED = 1
 PREC_MFMA_FP32 = 2
@@ -49,7 +50,8 @@ class _Params(ctypes.Structure):
                 ("mg_coarse_sweeps", ctypes.c_int32), ("restart", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("learned", ctypes.c_int32), ("learned_tau", ctypes.c_double),
                 ("mg_coarse_cheb", ctypes.c_int32), ("cheb_lo", ctypes.c_double), ("cheb_hi", ctypes.c_double),
-                ("omega_rot", ctypes.c_double), ("coarse_mode", ctypes.c_int32), ("coarse_rtol", ctypes.c_double)]
+                ("omega_rot", ctypes.c_double), ("coarse_mode", ctypes.c_int32), ("coarse_rtol", ctypes.c_double),
+                ("smoother_patch", ctypes.c_int32), ("nn_fp32", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -89,6 +91,8 @@ class Params:
     omega_rot: float = 0.0
     coarse_mode: int = 0
     coarse_rtol: float = 1e-2
+    smoother_patch: int = 0
+    nn_fp32: int = 0
 
     def to_c(self) -> _Params:
         return _Params(**{f.name: getattr(self, f.name) for f in fields(self)})
@@ -96,9 +100,11 @@ class Params:
 
 ABI_FUNCTIONS = [
     "hyb_create", "hyb_set_params", "hyb_assemble_local", "hyb_condense", "hyb_trace_apply",
-    "hyb_precondition", "hyb_solve", "hyb_solve_noalloc", "hyb_recover", "hyb_sizes", "hyb_profile", "hyb_profile_family", "hyb_profile_read",
+    "hyb_precondition", "hyb_solve", "hyb_solve_noalloc", "hyb_recover", "hyb_eliminate", "hyb_back_substitute",
+    "hyb_sizes", "hyb_profile", "hyb_profile_family", "hyb_profile_read",
     "hyb_restrict", "hyb_nn_param_count", "hyb_nn_set_weights", "hyb_nn_get_weights", "hyb_nn_forward",
     "hyb_nn_loss_grad", "hyb_nn_train_step", "hyb_nn_energy_grad", "hyb_nn_energy_train_step",
+    "hyb_nn_energy_train_step_pairs", "hyb_nn_cycle_pair",
     "hyb_mixed_rhs", "hyb_mixed_apply", "hyb_mixed_precondition", "hyb_mixed_solve",
     "hyb_last_error", "hyb_destroy",
 ]
@@ -133,6 +139,8 @@ def declare(lib):
     lib.hyb_solve.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(_Info)]
     lib.hyb_solve_noalloc.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(_Info)]
     lib.hyb_recover.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.hyb_eliminate.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.hyb_back_substitute.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.hyb_sizes.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                               ctypes.POINTER(ctypes.c_int64)]
     lib.hyb_profile.argtypes = [vp, ctypes.c_int32]
@@ -149,6 +157,9 @@ def declare(lib):
     lib.hyb_nn_energy_grad.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), vp]
     lib.hyb_nn_energy_train_step.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.c_float,
                                              ctypes.POINTER(ctypes.c_double)]
+    lib.hyb_nn_energy_train_step_pairs.argtypes = [vp, vp, vp, ctypes.c_int64, vp, ctypes.c_int32, ctypes.c_float,
+                                                   ctypes.POINTER(ctypes.c_double)]
+    lib.hyb_nn_cycle_pair.argtypes = [vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double)]
     lib.hyb_mixed_rhs.argtypes = [vp, vp, vp, vp]
     lib.hyb_mixed_apply.argtypes = [vp, vp, vp]
     lib.hyb_mixed_precondition.argtypes = [vp, vp, vp]
@@ -326,6 +337,22 @@ class HybSolver:
                                          _ptr(u_b, self.nu * self.ncell, "u_b"), _ptr(pi, self.npr * self.ncell, "pi")),
                     "hyb_recover")
 
+    def eliminate(self, r_ub, r_rho, r_theta, r_pi, r_ub_bar, r_pi_bar):
+        """hyb_eliminate: the 2x2 right-hand sides from the four residuals (theta' and rho' eliminated)."""
+        nc, ncol = self.ncell, self.ncol
+        self._check(self.lib.hyb_eliminate(self.h, _ptr(r_ub, 6 * nc, "r_ub"), _ptr(r_rho, nc, "r_rho"),
+                                           _ptr(r_theta, nc + ncol, "r_theta"), _ptr(r_pi, nc, "r_pi"),
+                                           _ptr(r_ub_bar, 6 * nc, "r_ub_bar"), _ptr(r_pi_bar, nc, "r_pi_bar")),
+                    "hyb_eliminate")
+
+    def back_substitute(self, r_rho, r_theta, u_b, rho, theta):
+        """hyb_back_substitute: rho' and theta' (each cell's bottom and top node) from the velocity."""
+        nc, ncol = self.ncell, self.ncol
+        self._check(self.lib.hyb_back_substitute(self.h, _ptr(r_rho, nc, "r_rho"), _ptr(r_theta, nc + ncol, "r_theta"),
+                                                 _ptr(u_b, 6 * nc, "u_b"), _ptr(rho, nc, "rho"),
+                                                 _ptr(theta, 2 * nc, "theta")),
+                    "hyb_back_substitute")
+
     def restrict(self, r, cells, mode=0):
         self._check(self.lib.hyb_restrict(self.h, _ptr(r, self.ntrace, "r"), _ptr(cells, self.ncell, "cells"),
                                           int(mode)), "hyb_restrict")
@@ -384,6 +411,28 @@ class HybSolver:
                                                       int(nsamp), float(lr), ctypes.byref(loss)),
                     "hyb_nn_energy_train_step")
         return loss.value
+
+    def nn_energy_train_step_pairs(self, X, R, idx, lr):
+        """One Adam step on the pairs idx (host ints) of X [npairs, ncell] (FP32) and R (FP64)."""
+        npairs = X.shape[0]
+        n = self.ncell * npairs
+        sel = np.ascontiguousarray(idx, dtype=np.int32)
+        loss = ctypes.c_double()
+        self._check(self.lib.hyb_nn_energy_train_step_pairs(
+            self.h, _ptr(X, n, "X", "float32"), _ptr(R, n, "R"), int(npairs), sel.ctypes.data_as(ctypes.c_void_p),
+            int(sel.size), float(lr), ctypes.byref(loss)), "hyb_nn_energy_train_step_pairs")
+        return loss.value
+
+    def nn_cycle_pair(self, r, x, rhat):
+        """One cycle step on r (in place) and its training pair into x (FP32) and rhat; returns the
+        scale s, or None when the residual's coarse part vanished (HYB_BREAKDOWN)."""
+        s = ctypes.c_double()
+        rc = self.lib.hyb_nn_cycle_pair(self.h, _ptr(r, self.ntrace, "r"), _ptr(x, self.ncell, "x", "float32"),
+                                        _ptr(rhat, self.ncell, "rhat"), ctypes.byref(s))
+        if rc == HYB_BREAKDOWN:
+            return None
+        self._check(rc, "hyb_nn_cycle_pair")
+        return s.value
 
     def profile(self, enable: bool):
         self._check(self.lib.hyb_profile(self.h, 1 if enable else 0), "hyb_profile")

@@ -120,6 +120,10 @@ int check_params(hyb_ctx *c, const hyb_params *p) {
     return fail(c, HYB_EINVAL, "the Krylov coarse solve (coarse_mode 2) is an order-0 FP64 mode");
   if (p->coarse_mode == 2 && !(p->coarse_rtol > 0.0 && p->coarse_rtol < 1.0))
     return fail(c, HYB_EINVAL, "coarse_rtol must be in (0, 1)");
+  if (p->smoother_patch != 0 && p->smoother_patch != 1) return fail(c, HYB_EINVAL, "smoother_patch must be 0 or 1");
+  if (p->nn_fp32 != 0 && p->nn_fp32 != 1) return fail(c, HYB_EINVAL, "nn_fp32 must be 0 or 1");
+  if (p->smoother_patch && c->ncol > 0 && (c->order != 0 || c->nlevels < 2))  // (hyb_create checks it itself)
+    return fail(c, HYB_EINVAL, "patch-cached column matrices need order 0 and a multigrid level of patches");
   if (p->omega_rot != 0.0 && c->geom != HYB_GEOM_SHELL)
     return fail(c, HYB_EINVAL, "rotation (omega_rot) is defined on HYB_GEOM_SHELL meshes only");
   return HYB_OK;
@@ -199,7 +203,7 @@ int setup_level(hyb_ctx *c, const hyb_mesh *mesh, int l) {
   if ((rc = dalloc(c, &L.H, 7 * n)) || (rc = dalloc(c, &L.Hf, 7 * n)) || (rc = dalloc(c, &L.zf, 3 * n)) ||
       (rc = dalloc(c, &L.zff, 3 * n)))
     return rc;
-  double **vecs[4] = {(double **)&L.b, (double **)&L.x, (double **)&L.y, (double **)&L.r};
+  double **vecs[3] = {(double **)&L.b, (double **)&L.x, (double **)&L.y};
   for (auto v : vecs)
     if ((rc = dalloc(c, v, n))) return rc;
   if (l == mesh->nlevels - 1 && (rc = dalloc(c, (double **)&L.w, n))) return rc;  // third Chebyshev iterate
@@ -210,10 +214,12 @@ void free_all(hyb_ctx *c) {
   for (auto &L : c->lv) {
     dfree(L.col_edge), dfree(L.edge_col), dfree(L.edge_lf), dfree(L.nbr), dfree(L.nlf), dfree(L.own);
     dfree(L.est), dfree(L.parent), dfree(L.children), dfree(L.H), dfree(L.Hf);
-    dfree(L.zf), dfree(L.zff), dfree(L.b), dfree(L.x), dfree(L.y), dfree(L.r), dfree(L.w);
+    dfree(L.zf), dfree(L.zff), dfree(L.b), dfree(L.x), dfree(L.y), dfree(L.w);
   }
   dfree(c->dz_d), dfree(c->corners_d), dfree(c->radius_d), dfree(c->vol), dfree(c->ck), dfree(c->A), dfree(c->LU), dfree(c->kv), dfree(c->Scell), dfree(c->bcell);
+  dfree(c->ec);
   dfree(c->S), dfree(c->Sf), dfree(c->m2l), dfree(c->gamma), dfree(c->gammaf), dfree(c->zfac), dfree(c->zfacf);
+  dfree(c->zfacp), dfree(c->zfacpf);
   dfree(c->tIn), dfree(c->tA), dfree(c->tB), dfree(c->tR), dfree(c->t64);
   dfree(c->V), dfree(c->Z), dfree(c->Vm), dfree(c->Zm), dfree(c->partial), dfree(c->hdev);
   if (c->hhost) (void)hipHostFree(c->hhost);
@@ -234,9 +240,10 @@ int alloc_krylov(hyb_ctx *c) {
   c->hhost = nullptr;
   c->m = m;
   size_t n = (size_t)c->ntrace;
+  c->ldv = n + kBasisPad;
   int rc;
   c->nblk_red = reduction_blocks();
-  if ((rc = dalloc(c, &c->V, (size_t)(m + 1) * n)) || (rc = dalloc(c, (double **)&c->Z, (size_t)m * n)) ||
+  if ((rc = dalloc(c, &c->V, (size_t)(m + 1) * c->ldv)) || (rc = dalloc(c, (double **)&c->Z, (size_t)m * c->ldv)) ||
       (rc = dalloc(c, &c->partial, (size_t)c->nblk_red * 2 * (m + 2))) || (rc = dalloc(c, &c->hdev, 4 * (size_t)(m + 2))))
     return rc;
   CHECK_HIP(hipHostMalloc((void **)&c->hhost, 4 * (size_t)(m + 2) * sizeof(double), hipHostMallocDefault),
@@ -247,12 +254,12 @@ int alloc_krylov(hyb_ctx *c) {
   return HYB_OK;
 }
 
-// Flexible GMRES(m) from x on n-vectors, right preconditioned, FP64 basis V [(m+1)][n] and
-// preconditioned basis Z [m][n] (FP32 when zf32).  resid(V0) writes b - A x into V0 (not called
+// Flexible GMRES(m) from x on n-vectors, right preconditioned, FP64 basis V [(m+1)][ldv] and
+// preconditioned basis Z [m][ldv] (FP32 when zf32).  resid(V0) writes b - A x into V0 (not called
 // while x is zero); apply(j) writes Z_j = M V_j and V_{j+1} = A Z_j.  Returns the status
 // (HYB_OK, HYB_NOT_CONVERGED, HYB_BREAKDOWN) or a negative error code.
 template <typename Resid, typename Apply>
-int fgmres(hyb_ctx *c, size_t n, double *V, void *Zbuf, bool zf32, const double *b, double *x, double rtol,
+int fgmres(hyb_ctx *c, size_t n, size_t ldv, double *V, void *Zbuf, bool zf32, const double *b, double *x, double rtol,
            int32_t maxit, hyb_info *info, Resid resid, Apply apply_op) {
   const int m = c->m;
   int rc = 0;
@@ -279,7 +286,8 @@ int fgmres(hyb_ctx *c, size_t n, double *V, void *Zbuf, bool zf32, const double 
     return HYB_OK;
   }
   int its = 0, restarts = 0, status = HYB_NOT_CONVERGED;
-  double rel = 0.0;
+  double rel = 0.0, rel_cycle = 0.0;
+  int stalled = 0;  // consecutive restart cycles that left the true residual almost where it was
   for (;;) {
     // true residual r = b - S lam into V_0
     if (x_zero)
@@ -301,6 +309,17 @@ int fgmres(hyb_ctx *c, size_t n, double *V, void *Zbuf, bool zf32, const double 
       break;
     }
     if (its >= maxit) break;
+    // a restart cycle that reduced the true residual by less than kStagnation twice in a row (the
+    // rounding floor of the residual, or a preconditioned operator the cycle cannot reduce) ends
+    // the solve instead of running on to maxit
+    if (its > 0) {
+      stalled = rel > kStagnation * rel_cycle ? stalled + 1 : 0;
+      if (stalled >= 2) {
+        status = HYB_STAGNATED;
+        break;
+      }
+    }
+    rel_cycle = rel;
     if (its > 0) restarts++;
     CHECK_HIP(launch_scale(c, V, n, 1.0 / beta), "scale");
     std::fill(g.begin(), g.end(), 0.0);
@@ -319,7 +338,7 @@ int fgmres(hyb_ctx *c, size_t n, double *V, void *Zbuf, bool zf32, const double 
       double eta_prev = 1.0, g0 = beta;
       for (int j = 0; j < m; ++j) {
         if ((rc = apply_op(j))) return rc;
-        CHECK_HIP(launch_dgs_dots(c, V, n, j, c->hdev), "gram-schmidt dots");
+        CHECK_HIP(launch_dgs_dots(c, V, ldv, n, j, c->hdev), "gram-schmidt dots");
         CHECK_HIP(hipMemcpyAsync(hh, c->hdev, (2 * (size_t)j + 3) * sizeof(double), hipMemcpyDeviceToHost, c->stream),
                   "d2h");
         CHECK_HIP(hipStreamSynchronize(c->stream), "sync");
@@ -348,7 +367,7 @@ int fgmres(hyb_ctx *c, size_t n, double *V, void *Zbuf, bool zf32, const double 
         const double eta2 = hh[2 * j + 2] - b2 - hjj * hjj;
         const double eta = (eta2 > 0.0 && std::isfinite(eta2)) ? std::sqrt(eta2) : 0.0;
         col[j + 1] = eta;
-        CHECK_HIP(launch_dgs_update(c, V, n, j, ca.data(), cb.data(), 1.0 / rho, hjj, eta > 0.0 ? 1.0 / eta : 0.0,
+        CHECK_HIP(launch_dgs_update(c, V, ldv, n, j, ca.data(), cb.data(), 1.0 / rho, hjj, eta > 0.0 ? 1.0 / eta : 0.0,
                                     zf32 ? (float *)c->tIn : nullptr),
                   "gram-schmidt update");
         eta_prev = eta;
@@ -393,7 +412,7 @@ int fgmres(hyb_ctx *c, size_t n, double *V, void *Zbuf, bool zf32, const double 
       }
     } else
     for (int j = 0; j < m; ++j) {
-      double *w = V + (size_t)(j + 1) * n;
+      double *w = V + (size_t)(j + 1) * ldv;
       if ((rc = apply_op(j))) return rc;
       double *col = &R[(size_t)j * (m + 1)];
       double hn;
@@ -402,7 +421,7 @@ int fgmres(hyb_ctx *c, size_t n, double *V, void *Zbuf, bool zf32, const double 
         // classical Gram-Schmidt with reorthogonalisation in three passes over the basis and one
         // host read: h1 = V^T w; w -= V h1 while h2 = V^T w and ||w||^2 accumulate; the last pass
         // subtracts V h2 and normalises with ||w - V h2||^2 = ||w||^2 - ||h2||^2 (V orthonormal)
-        CHECK_HIP(launch_gs_passes(c, V, n, j + 1, w, h1, h2), "gram-schmidt");
+        CHECK_HIP(launch_gs_passes(c, V, ldv, n, j + 1, w, h1, h2), "gram-schmidt");
         CHECK_HIP(hipMemcpyAsync(hh, c->hdev, 2 * (size_t)(m + 2) * sizeof(double), hipMemcpyDeviceToHost,
                                  c->stream),
                   "d2h");
@@ -415,14 +434,14 @@ int fgmres(hyb_ctx *c, size_t n, double *V, void *Zbuf, bool zf32, const double 
         double wp2 = hh[(m + 2) + j + 1];
         hn = std::sqrt(std::max(0.0, wp2 - h2sq));
         if (hn > 0.0 && std::isfinite(hn)) {
-          CHECK_HIP(launch_gs_finish(c, V, n, j + 1, h2, w, 1.0 / hn), "gram-schmidt finish");
+          CHECK_HIP(launch_gs_finish(c, V, ldv, n, j + 1, h2, w, 1.0 / hn), "gram-schmidt finish");
           scaled = true;
         }
       } else {
         // long restart cycles: classical Gram-Schmidt, second pass when the first one cancelled
         // more than half of the norm (||w'|| < ||w|| / sqrt(2))
-        CHECK_HIP(launch_multidot(c, V, n, j + 1, w, n, h1, true), "cgs1");
-        CHECK_HIP(launch_axpy_norm(c, V, n, j + 1, h1, w, n, nrm), "cgs1 update");
+        CHECK_HIP(launch_multidot(c, V, ldv, j + 1, w, n, h1, true), "cgs1");
+        CHECK_HIP(launch_axpy_norm(c, V, ldv, j + 1, h1, w, n, nrm), "cgs1 update");
         CHECK_HIP(hipMemcpyAsync(hh, c->hdev, 3 * (size_t)(m + 2) * sizeof(double), hipMemcpyDeviceToHost,
                                  c->stream),
                   "d2h");
@@ -430,8 +449,8 @@ int fgmres(hyb_ctx *c, size_t n, double *V, void *Zbuf, bool zf32, const double 
         for (int i = 0; i <= j; ++i) col[i] = hh[i];
         double w2 = hh[j + 1], wp2 = hh[2 * (m + 2)];
         if (!(wp2 >= 0.5 * w2)) {
-          CHECK_HIP(launch_multidot(c, V, n, j + 1, w, n, h2, false), "cgs2");
-          CHECK_HIP(launch_axpy_norm(c, V, n, j + 1, h2, w, n, nrm), "cgs2 update");
+          CHECK_HIP(launch_multidot(c, V, ldv, j + 1, w, n, h2, false), "cgs2");
+          CHECK_HIP(launch_axpy_norm(c, V, ldv, j + 1, h2, w, n, nrm), "cgs2 update");
           CHECK_HIP(hipMemcpyAsync(hh, c->hdev, 3 * (size_t)(m + 2) * sizeof(double), hipMemcpyDeviceToHost,
                                    c->stream),
                     "d2h");
@@ -484,9 +503,9 @@ int fgmres(hyb_ctx *c, size_t n, double *V, void *Zbuf, bool zf32, const double 
       CHECK_HIP(hipMemcpyAsync(ydev, hh + 3 * (m + 2), jend * sizeof(double), hipMemcpyHostToDevice, c->stream),
                 "h2d");
       if (zf32)
-        CHECK_HIP(launch_update_solution<float>(c, (const float *)Zbuf, n, jend, ydev, x, n), "update");
+        CHECK_HIP(launch_update_solution<float>(c, (const float *)Zbuf, ldv, jend, ydev, x, n), "update");
       else
-        CHECK_HIP(launch_update_solution<double>(c, (const double *)Zbuf, n, jend, ydev, x, n), "update");
+        CHECK_HIP(launch_update_solution<double>(c, (const double *)Zbuf, ldv, jend, ydev, x, n), "update");
       CHECK_HIP(hipStreamSynchronize(c->stream), "sync");
     }
     if (breakdown && jend == 0) {
@@ -585,6 +604,10 @@ int hyb_create(const hyb_mesh *mesh, const hyb_params *params, void *stream, hyb
     return HYB_EINVAL;
   }
   c->order = mesh->order;
+  if (params->smoother_patch && (c->order != 0 || c->nlevels < 2)) {
+    delete c;
+    return HYB_EINVAL;  // patch-cached column matrices: order 0 with a multigrid level of patches
+  }
   if (c->order == 1) c->ntrace *= 4;
   if (c->order == 1 && params->coarse_mode == 2) {
     delete c;
@@ -696,6 +719,8 @@ int hyb_set_params(hyb_ctx *c, const hyb_params *params) {
     CHECK_HIP(launch_to_float(c, c->S, c->Sf, s_entries(c->ntrace)), "to_float S");
     CHECK_HIP(launch_to_float(c, c->gamma, c->gammaf, (size_t)c->ncell), "to_float gamma");
     CHECK_HIP(launch_to_float(c, c->zfac, c->zfacf, 3 * (size_t)c->nz), "to_float zfac");
+    if (c->zfacp)
+      CHECK_HIP(launch_to_float(c, c->zfacp, c->zfacpf, 3 * (size_t)(c->nlev + 1) * c->lv[1].ncol), "to_float zfacp");
     for (int l = 0; l < c->nlevels; ++l)
     {
       CHECK_HIP(launch_to_float(c, c->lv[l].H, c->lv[l].Hf, (size_t)7 * c->nlev * c->lv[l].ncol), "to_float H");
@@ -726,7 +751,8 @@ int hyb_assemble_local(hyb_ctx *c, const double *theta_w, const double *exner_ha
     return HYB_OK;
   }
   if ((rc = dalloc(c, &c->A, (size_t)49 * c->ncell)) || (rc = dalloc(c, &c->kv, (size_t)6 * c->ncell)) ||
-      (rc = dalloc(c, &c->m2l, (size_t)c->ntrace)) || (rc = dalloc(c, &c->vol, (size_t)c->ncell)))
+      (rc = dalloc(c, &c->m2l, (size_t)c->ntrace)) || (rc = dalloc(c, &c->vol, (size_t)c->ncell)) ||
+      (rc = dalloc(c, &c->ec, (size_t)8 * c->ncell)))
     return rc;
   c->nn.st_ready = false;  // the network's static inputs follow the cell volumes
   // the lumped velocity mass (Sec. 2.3) leaves the Coriolis term out: on the sphere the assembly
@@ -744,6 +770,8 @@ int hyb_assemble_local(hyb_ctx *c, const double *theta_w, const double *exner_ha
     CHECK_HIP(launch_assemble_box(c, theta_w, exner_hat_w, exner_c, rho_c), "assemble_local");
     CHECK_HIP(launch_lumped_mass(c), "lumped_mass");
   }
+  // the theta' / rho' elimination needs the reference state after the call returns
+  CHECK_HIP(launch_elim_coeffs(c, theta_w, exner_hat_w, rho_c), "elimination coefficients");
   c->assembled = true;
   c->condensed = false;
   return HYB_OK;
@@ -782,6 +810,8 @@ int hyb_condense(hyb_ctx *c, const double *r_ub, const double *r_pi, double *b_l
     if ((rc = dalloc(c, &c->LU, 49 * nc)) || (rc = dalloc(c, &c->Scell, 36 * nc)) || (rc = dalloc(c, &c->S, s_entries(ntr))) ||
         (rc = dalloc(c, &c->Sf, s_entries(ntr))) || (rc = dalloc(c, &c->gamma, nc)) ||
         (rc = dalloc(c, &c->zfac, 3 * (size_t)c->nz)) || (rc = dalloc(c, &c->zfacf, 3 * (size_t)c->nz)) ||
+        (c->nlevels > 1 && (rc = dalloc(c, &c->zfacp, 3 * (size_t)(c->nlev + 1) * c->lv[1].ncol))) ||
+        (c->nlevels > 1 && (rc = dalloc(c, &c->zfacpf, 3 * (size_t)(c->nlev + 1) * c->lv[1].ncol))) ||
         (rc = dalloc(c, &c->gammaf, nc)) || (rc = dalloc(c, &c->bcell, 6 * nc)) ||
         (rc = dalloc(c, (double **)&c->tIn, ntr)) || (rc = dalloc(c, (double **)&c->tA, ntr)) ||
         (rc = dalloc(c, (double **)&c->tB, ntr)) || (rc = dalloc(c, (double **)&c->tR, ntr)) ||
@@ -798,6 +828,8 @@ int hyb_condense(hyb_ctx *c, const double *r_ub, const double *r_pi, double *b_l
     CHECK_HIP(launch_to_float(c, c->S, c->Sf, s_entries(ntr)), "to_float S");
     CHECK_HIP(launch_to_float(c, c->gamma, c->gammaf, nc), "to_float gamma");
     CHECK_HIP(launch_to_float(c, c->zfac, c->zfacf, 3 * (size_t)c->nz), "to_float zfac");
+    if (c->zfacp)
+      CHECK_HIP(launch_to_float(c, c->zfacp, c->zfacpf, 3 * (size_t)(c->nlev + 1) * c->lv[1].ncol), "to_float zfacp");
     for (int l = 0; l < c->nlevels; ++l)
     {
       CHECK_HIP(launch_to_float(c, c->lv[l].H, c->lv[l].Hf, (size_t)7 * c->nlev * c->lv[l].ncol), "to_float H");
@@ -884,20 +916,21 @@ int solve_impl(hyb_ctx *c, const double *b, double *lam, double rtol, int32_t ma
   };
   // z_j = M(V_j) into Z, w = S z_j into V_{j+1}
   auto apply_op = [&](int j) -> int {
-    double *vj = V + (size_t)j * n, *w = V + (size_t)(j + 1) * n;
+    const size_t ldv = c->ldv;
+    double *vj = V + (size_t)j * ldv, *w = V + (size_t)(j + 1) * ldv;
     if (mixed) {
-      float *zf = (float *)c->Z + (size_t)j * n;
+      float *zf = (float *)c->Z + (size_t)j * ldv;
       // the two-pass Gram-Schmidt writes the FP32 copy of V_j with V_j itself (steps j > 0)
       if (j == 0 || m > kDgsMax) CHECK_HIP(launch_convert(c, vj, (float *)c->tIn, n), "convert");
       CHECK_HIP(precondition<float>(c, (const float *)c->tIn, zf), "precondition");
       if (learned) CHECK_HIP(learned_stage<float>(c, vj, zf), "learned stage");
       CHECK_HIP((launch_trace_apply<double, float, double>(c, c->S, zf, nullptr, w, 0)), "matvec");
     } else if (c->order == 1) {
-      double *zj = (double *)c->Z + (size_t)j * n;
+      double *zj = (double *)c->Z + (size_t)j * ldv;
       CHECK_HIP(p1_precondition(c, vj, zj), "precondition");
       CHECK_HIP(p1_rows(c, zj, w, 0, nullptr), "matvec");
     } else {
-      double *zj = (double *)c->Z + (size_t)j * n;
+      double *zj = (double *)c->Z + (size_t)j * ldv;
       CHECK_HIP(precondition<double>(c, vj, zj), "precondition");
       if (learned)  // the stage's own applications of S give w = S z (no separate matvec)
         CHECK_HIP(learned_stage<double>(c, vj, zj, w), "learned stage");
@@ -906,7 +939,7 @@ int solve_impl(hyb_ctx *c, const double *b, double *lam, double rtol, int32_t ma
     }
     return HYB_OK;
   };
-  const int status = fgmres(c, n, V, c->Z, mixed, b, lam, rtol, maxit, info, resid, apply_op);
+  const int status = fgmres(c, n, c->ldv, V, c->Z, mixed, b, lam, rtol, maxit, info, resid, apply_op);
   if (status >= 0 && info && learned) {
     double fb = 0.0;
     CHECK_HIP(hipMemcpyAsync(&fb, c->nn.scal + 2, sizeof(double), hipMemcpyDeviceToHost, c->stream), "d2h");
@@ -1020,7 +1053,7 @@ int hyb_mixed_solve(hyb_ctx *c, const double *b, double *x, double rtol, int32_t
     CHECK_HIP(launch_mixed_rows(c, zj, nullptr, w), "matvec");
     return HYB_OK;
   };
-  return fgmres(c, n, V, Z, false, b, x, rtol, maxit, info, resid, apply_op);
+  return fgmres(c, n, n, V, Z, false, b, x, rtol, maxit, info, resid, apply_op);
 }
 
 int hyb_recover(hyb_ctx *c, const double *r_ub, const double *r_pi, const double *lambda, double *u_b, double *pi) {
@@ -1032,6 +1065,28 @@ int hyb_recover(hyb_ctx *c, const double *r_ub, const double *r_pi, const double
     return HYB_OK;
   }
   CHECK_HIP(launch_recover(c, r_ub, r_pi, lambda, u_b, pi), "recover");
+  return HYB_OK;
+}
+
+int hyb_eliminate(hyb_ctx *c, const double *r_ub, const double *r_rho, const double *r_theta, const double *r_pi,
+                  double *r_ub_bar, double *r_pi_bar) {
+  if (!c) return HYB_EINVAL;
+  if (c->order != 0) return fail(c, HYB_EINVAL, "the theta' / rho' elimination is built for order 0");
+  if (!c->assembled) return fail(c, HYB_ESTATE, "eliminate before assemble_local");
+  if (!r_ub || !r_rho || !r_theta || !r_pi || !r_ub_bar || !r_pi_bar) return fail(c, HYB_EINVAL, "null argument");
+  CHECK_HIP(launch_eliminate(c, r_ub, r_rho, r_theta, r_pi, r_ub_bar, r_pi_bar), "eliminate");
+  return HYB_OK;
+}
+
+int hyb_back_substitute(hyb_ctx *c, const double *r_rho, const double *r_theta, const double *u_b, double *rho,
+                        double *theta) {
+  if (!c) return HYB_EINVAL;
+  if (c->order != 0) return fail(c, HYB_EINVAL, "the theta' / rho' back-substitution is built for order 0");
+  if (!c->assembled) return fail(c, HYB_ESTATE, "back_substitute before assemble_local");
+  if (!r_rho || !r_theta || !u_b || !rho || !theta) return fail(c, HYB_EINVAL, "null argument");
+  if (rho == u_b || theta == u_b || rho == r_rho || theta == r_theta)
+    return fail(c, HYB_EINVAL, "outputs must not alias inputs");
+  CHECK_HIP(launch_back_substitute(c, r_rho, r_theta, u_b, rho, theta), "back_substitute");
   return HYB_OK;
 }
 
@@ -1162,6 +1217,49 @@ int hyb_nn_energy_train_step(hyb_ctx *c, const float *x, const double *rhat, int
   if (!c->condensed) return fail(c, HYB_ESTATE, "energy loss before condense");
   if (!x || !rhat || nsamp < 1 || !(lr > 0)) return fail(c, HYB_EINVAL, "bad train arguments");
   CHECK_HIP(nn_energy_grad(c, x, rhat, nsamp, loss), "nn energy grad");
+  CHECK_HIP(nn_adam(c, lr), "nn adam");
+  return HYB_OK;
+}
+
+int hyb_nn_cycle_pair(hyb_ctx *c, double *r, float *x, double *rhat, double *scale) {
+  if (!c) return HYB_EINVAL;
+  if (c->order == 1) return fail(c, HYB_ESTATE, "hyb_nn_cycle_pair is not available at order 1");
+  if (!c->condensed) return fail(c, HYB_ESTATE, "training pairs before condense");
+  if (!r || !x || !rhat) return fail(c, HYB_EINVAL, "bad pair arguments");
+  int rc = alloc_krylov(c);  // reduction scratch, and the FP32 slots of the mixed form
+  if (rc) return rc;
+  CHECK_HIP(nn_stage_buffers(c), "pair buffers");
+  const size_t n = (size_t)c->ntrace;
+  double *z = c->nn.d64;
+  // the plain two-level cycle (never the learned stage)
+  if (c->p.precision == HYB_PREC_FP64) {
+    CHECK_HIP(precondition<double>(c, r, z), "precondition");
+  } else {
+    float *rf = (float *)c->tIn, *zf = (float *)c->Z;
+    CHECK_HIP(launch_convert(c, r, rf, n), "convert");
+    CHECK_HIP(precondition<float>(c, rf, zf), "precondition");
+    CHECK_HIP(launch_copy_widen(c, zf, z, n), "widen");
+  }
+  CHECK_HIP((launch_trace_apply<double, double, double>(c, c->S, z, r, c->t64, 1)), "residual");
+  CHECK_HIP(hipMemcpyAsync(r, c->t64, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream), "copy residual");
+  CHECK_HIP(launch_restrict_cells(c, c->t64, c->cell64, 0), "restrict");
+  double s = 0.0;
+  CHECK_HIP(nn_pair_finish(c, x, rhat, &s), "pair");
+  if (scale) *scale = s;
+  if (!std::isfinite(s) || s == 0.0) return HYB_BREAKDOWN;
+  return HYB_OK;
+}
+
+int hyb_nn_energy_train_step_pairs(hyb_ctx *c, const float *X, const double *R, int64_t npairs, const int32_t *idx,
+                                   int32_t nsamp, float lr, double *loss) {
+  if (!c) return HYB_EINVAL;
+  if (!c->nn.loaded) return fail(c, HYB_ESTATE, "no weights");
+  if (!c->condensed) return fail(c, HYB_ESTATE, "energy loss before condense");
+  if (!X || !R || !idx || nsamp < 1 || npairs < 1 || !(lr > 0)) return fail(c, HYB_EINVAL, "bad train arguments");
+  for (int32_t i = 0; i < nsamp; ++i)
+    if (idx[i] < 0 || idx[i] >= npairs) return fail(c, HYB_EINVAL, "pair index out of range");
+  CHECK_HIP(nn_gather_batch(c, X, R, idx, nsamp), "gather batch");
+  CHECK_HIP(nn_energy_grad(c, c->nn.xb, c->nn.rb, nsamp, loss), "nn energy grad");
   CHECK_HIP(nn_adam(c, lr), "nn adam");
   return HYB_OK;
 }

@@ -588,7 +588,138 @@ __global__ void k_recover(int nlev, int ncol, int nedge, int ncell, size_t nz,
 
 inline unsigned nblk(size_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
 
+// ----- elimination of theta' and rho' around the 2x2 solve (Sec. 2.1, 2.2) -----
+// Per-cell coefficients, computed once at assembly:
+//   ec[0] = tau_u dt c_p (Pihat_T - Pihat_B)     the theta' term of the momentum rows of B and T
+//   ec[1] = w_c, the one-point (cell centre) weight of the equation-of-state forms
+//   ec[2] = 1 / theta*(centre),  ec[3] = 1 / rho*
+//   ec[4] = tau_rho dt rho* / |K|                rho' = r_rho - ec[4] (sum of the outward fluxes)
+//   ec[5] = tau_theta dt (theta_T - theta_B) / h  (h the cell height: theta* varies along it only)
+//   ec[6], ec[7] = 1 / area density at the bottom / top facet centre: the vertical velocity
+//   there is the cell's flux through that facet times it
+constexpr int kElimCoef = 8;
+
+__device__ __forceinline__ void elim_common(double *ec, size_t c, size_t nc, double thB, double thT, double piB,
+                                            double piT, double rhoc, double vol, double tu, double tr, double tt,
+                                            double dt, double cp) {
+  ec[0 * nc + c] = tu * dt * cp * (piT - piB);
+  ec[2 * nc + c] = 2.0 / (thB + thT);
+  ec[3 * nc + c] = 1.0 / rhoc;
+  ec[4 * nc + c] = tr * dt * rhoc / vol;
+  (void)tt;
+}
+
+__global__ void k_elim_coeffs_box(int ncell, int ncol, double dx, double dy, const double *__restrict__ dz,
+                                  const double *__restrict__ thw, const double *__restrict__ piw,
+                                  const double *__restrict__ rho, double dt, double tu, double tr, double tt,
+                                  double cp, double *__restrict__ ec) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  const int k = c / ncol, col = c - k * ncol;
+  const double thB = thw[(size_t)k * ncol + col], thT = thw[(size_t)(k + 1) * ncol + col];
+  const double piB = piw[(size_t)k * ncol + col], piT = piw[(size_t)(k + 1) * ncol + col];
+  const double hz = dz[k], vol = dx * dy * hz;
+  elim_common(ec, c, ncell, thB, thT, piB, piT, rho[c], vol, tu, tr, tt, dt, cp);
+  ec[1 * (size_t)ncell + c] = vol;
+  ec[5 * (size_t)ncell + c] = tt * dt * (thT - thB) / hz;
+  ec[6 * (size_t)ncell + c] = 1.0 / (dx * dy);
+  ec[7 * (size_t)ncell + c] = 1.0 / (dx * dy);
+}
+
+// Shell cells x = r(zeta) u(xi, eta): det J = (r1 - r0) r^2 [u_xi x u_eta] . u, the area density of a
+// horizontal facet at radius r is r^2 [u_xi x u_eta] . u, and d/dz along the radius is d/dzeta / (r1 - r0).
+__global__ void k_elim_coeffs_shell(int ncell, int ncol, const double *__restrict__ corners,
+                                    const double *__restrict__ radius, const double *__restrict__ thw,
+                                    const double *__restrict__ piw, const double *__restrict__ rho,
+                                    const double *__restrict__ volc, double dt, double tu, double tr, double tt,
+                                    double cp, double *__restrict__ ec) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  const int k = c / ncol, col = c - k * ncol;
+  double U[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) U[i] = corners[(size_t)i * ncol + col];
+  double u[3], ux[3], uy[3];
+  shell_point(U, 0.5, 0.5, u, ux, uy);
+  const double s = u[0] * (ux[1] * uy[2] - ux[2] * uy[1]) + u[1] * (ux[2] * uy[0] - ux[0] * uy[2]) +
+                   u[2] * (ux[0] * uy[1] - ux[1] * uy[0]);
+  const double r0 = radius[k], r1 = radius[k + 1], rc = 0.5 * (r0 + r1);
+  const double thB = thw[(size_t)k * ncol + col], thT = thw[(size_t)(k + 1) * ncol + col];
+  const double piB = piw[(size_t)k * ncol + col], piT = piw[(size_t)(k + 1) * ncol + col];
+  elim_common(ec, c, ncell, thB, thT, piB, piT, rho[c], volc[c], tu, tr, tt, dt, cp);
+  ec[1 * (size_t)ncell + c] = (r1 - r0) * rc * rc * s;
+  ec[5 * (size_t)ncell + c] = tt * dt * (thT - thB) / (r1 - r0);
+  ec[6 * (size_t)ncell + c] = 1.0 / (r0 * r0 * s);
+  ec[7 * (size_t)ncell + c] = 1.0 / (r1 * r1 * s);
+}
+
+// The right-hand sides of the 2x2 system from the four residuals, one thread per cell:
+// r_ub_bar = r_ub with the theta' term on the B and T rows (the integral of (z . v_F) r_theta dPihat/dz
+// with r_theta linear between the facet values), r_pi_bar = w_c (r_pi + r_theta(c) / theta*(c) + r_rho / rho*).
+// In place allowed (every cell reads its own entries before writing them).
+__global__ void k_eliminate(int ncell, int ncol, const double *__restrict__ ec, const double *rub,
+                            const double *__restrict__ rrho, const double *__restrict__ rth,
+                            const double *rpi, double *rub_bar, double *rpi_bar) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  const size_t nc = (size_t)ncell;
+  const double rB = rth[c], rT = rth[(size_t)c + ncol];
+  const double eu = ec[c];
+  const double uB = rub[4 * nc + c] + eu * (rB / 3.0 + rT / 6.0);
+  const double uT = rub[5 * nc + c] - eu * (rB / 6.0 + rT / 3.0);
+  const double pb = ec[nc + c] * (rpi[c] + 0.5 * (rB + rT) * ec[2 * nc + c] + rrho[c] * ec[3 * nc + c]);
+#pragma unroll
+  for (int f = 0; f < 4; ++f) rub_bar[f * nc + c] = rub[f * nc + c];
+  rub_bar[4 * nc + c] = uB;
+  rub_bar[5 * nc + c] = uT;
+  rpi_bar[c] = pb;
+}
+
+// rho' = r_rho - tau_rho dt rho* (sum of the cell's outward fluxes) / |K|; theta' at the cell's
+// bottom and top W_theta nodes = r_theta - tau_theta dt (z . u) dtheta*/dz, the vertical velocity
+// being -u_B / A_B at the bottom and u_T / A_T at the top (outward fluxes).
+__global__ void k_back_substitute(int ncell, int ncol, const double *__restrict__ ec, const double *__restrict__ ub,
+                                  const double *__restrict__ rrho, const double *__restrict__ rth,
+                                  double *__restrict__ rho, double *__restrict__ theta) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  const size_t nc = (size_t)ncell;
+  double flux = 0.0;
+#pragma unroll
+  for (int f = 0; f < 6; ++f) flux += ub[f * nc + c];
+  rho[c] = rrho[c] - ec[4 * nc + c] * flux;
+  const double g = ec[5 * nc + c];
+  theta[c] = rth[c] + g * ub[4 * nc + c] * ec[6 * nc + c];
+  theta[nc + c] = rth[(size_t)c + ncol] - g * ub[5 * nc + c] * ec[7 * nc + c];
+}
+
 }  // namespace
+
+hipError_t launch_elim_coeffs(hyb_ctx *c, const double *thw, const double *piw, const double *rhoc) {
+  const hyb_params &p = c->p;
+  if (c->geom == HYB_GEOM_SHELL)
+    hipLaunchKernelGGL(k_elim_coeffs_shell, dim3(nblk(c->ncell)), dim3(kBlock), 0, c->stream, c->ncell, c->ncol,
+                       c->corners_d, c->radius_d, thw, piw, rhoc, c->vol, p.dt, p.tau_u, p.tau_rho, p.tau_theta, p.cp,
+                       c->ec);
+  else
+    hipLaunchKernelGGL(k_elim_coeffs_box, dim3(nblk(c->ncell)), dim3(kBlock), 0, c->stream, c->ncell, c->ncol, c->dx,
+                       c->dy, c->dz_d, thw, piw, rhoc, p.dt, p.tau_u, p.tau_rho, p.tau_theta, p.cp, c->ec);
+  return hipGetLastError();
+}
+
+hipError_t launch_eliminate(hyb_ctx *c, const double *r_ub, const double *r_rho, const double *r_theta,
+                            const double *r_pi, double *r_ub_bar, double *r_pi_bar) {
+  hipLaunchKernelGGL(k_eliminate, dim3(nblk(c->ncell)), dim3(kBlock), 0, c->stream, c->ncell, c->ncol, c->ec, r_ub,
+                     r_rho, r_theta, r_pi, r_ub_bar, r_pi_bar);
+  return hipGetLastError();
+}
+
+hipError_t launch_back_substitute(hyb_ctx *c, const double *r_rho, const double *r_theta, const double *u_b,
+                                  double *rho, double *theta) {
+  hipLaunchKernelGGL(k_back_substitute, dim3(nblk(c->ncell)), dim3(kBlock), 0, c->stream, c->ncell, c->ncol, c->ec,
+                     u_b, r_rho, r_theta, rho, theta);
+  return hipGetLastError();
+}
 
 hipError_t launch_assemble_box(hyb_ctx *c, const double *thw, const double *piw, const double *pic,
                                const double *rhoc) {

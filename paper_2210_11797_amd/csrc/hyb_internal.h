@@ -32,7 +32,7 @@ struct LevelDev {
   float *Hf = nullptr;          // FP32 copy
   double *zf = nullptr;         // [3][nlev*ncol] LU factors of the column part H_z: l, 1/u, c/u
   float *zff = nullptr;
-  void *b = nullptr, *x = nullptr, *y = nullptr, *r = nullptr;  // [nlev*ncol] work vectors
+  void *b = nullptr, *x = nullptr, *y = nullptr;  // [nlev*ncol] work vectors
   void *w = nullptr;  // coarsest level only: the third iterate of the Chebyshev coarsest solve
 };
 
@@ -58,6 +58,9 @@ struct NNState {
   int32_t *isbf = nullptr;                                        // parameter -> BF16 index (-1: bias)
   int32_t *nb9 = nullptr;                                         // [9][ncol] 3x3 horizontal neighbourhood (-1: none)
   int32_t *rv9 = nullptr;                                         // [9][ncol] readers of a column: col * 9 + tap
+  int32_t *rvh = nullptr;                                         // [9][ncol] the reader through tap h (-1: none)
+  int32_t *lo_off = nullptr, *lo_list = nullptr;                  // further readers per column (CSR)
+  float *wpart = nullptr;                                         // matrix-core weight-gradient partials
   float *st = nullptr;                                            // [2][ncell] static input channels
   double *layer = nullptr;                                        // [2][nlev] log(dz), centre height / lid
   bool st_ready = false;
@@ -70,6 +73,9 @@ struct NNState {
   double *d64 = nullptr, *sd64 = nullptr;                         // correction d and S d [ntrace]
   double *gq = nullptr, *epart = nullptr;                         // energy loss: G q [nsamp][ncell], partials
   size_t gq_cap = 0;
+  float *xb = nullptr;                                            // gathered training batch: inputs
+  double *rb = nullptr;                                           // and targets [nsamp][ncell]
+  size_t batch_cap = 0;                                           // cells x samples they hold
   double dbar = 0.0;                                              // mean of the diagonal of H
   size_t cap = 0;                                                 // cells x samples the activations hold
   long step = 0;
@@ -122,12 +128,15 @@ struct hyb_ctx {
   double *ck = nullptr;     // [10][ncell] vectors of the Krylov coarse solve (coarse_mode 2)
   double *Scell = nullptr;  // [36][ncell] S_K = [A_K^-1]_uu diag(k)  (setup only)
   double *bcell = nullptr;  // [6][ncell] [A_K^-1 R_K]_u
+  double *ec = nullptr;     // [8][ncell] coefficients of the theta' / rho' elimination (assemble.hip)
   // trace operator
   double *S = nullptr;      // 11-entry rows in tiles of 64 rows (s_idx)
   float *Sf = nullptr;      // FP32 copy, same layout
   double *m2l = nullptr;    // [ntrace] lumped velocity mass (interior facets)
   double *zfac = nullptr;   // [3][nz] LU factors of S^zz per column: l, 1/u, c/u
   float *zfacf = nullptr;
+  double *zfacp = nullptr;  // [3][nlev+1][ncol of level 1] the same per 2x2 patch (smoother_patch)
+  float *zfacpf = nullptr;
   double *gamma = nullptr;  // [ncell]
   float *gammaf = nullptr;
   // preconditioner work vectors (precision of the preconditioner)
@@ -135,8 +144,9 @@ struct hyb_ctx {
   double *t64 = nullptr;    // [ntrace]
   // Krylov workspace
   int m = 0;
-  double *V = nullptr;      // [(m+1)][ntrace]
-  void *Z = nullptr;        // [m][ntrace] (double or float)
+  double *V = nullptr;      // [(m+1)][ldv]
+  void *Z = nullptr;        // [m][ldv] (double or float)
+  size_t ldv = 0;           // leading dimension of V and Z: ntrace plus kBasisPad
   double *Vm = nullptr;     // Configuration 1: [(m+1)][ntrace + ncell]
   double *Zm = nullptr;     // Configuration 1: [m][ntrace + ncell]
   int mm = 0;               // restart length Vm / Zm were allocated for
@@ -206,6 +216,12 @@ hipError_t launch_pressure_stencil(hyb_ctx *c);
 hipError_t launch_galerkin(hyb_ctx *c, int coarse_level);
 hipError_t launch_gamma(hyb_ctx *c);
 hipError_t launch_to_float(hyb_ctx *c, const double *src, float *dst, size_t n);
+// elimination of theta' and rho' (Sec. 2.1, 2.2): coefficients at assembly, then the pointwise passes
+hipError_t launch_elim_coeffs(hyb_ctx *c, const double *theta_w, const double *exner_hat_w, const double *rho_c);
+hipError_t launch_eliminate(hyb_ctx *c, const double *r_ub, const double *r_rho, const double *r_theta,
+                            const double *r_pi, double *r_ub_bar, double *r_pi_bar);
+hipError_t launch_back_substitute(hyb_ctx *c, const double *r_rho, const double *r_theta, const double *u_b,
+                                  double *rho, double *theta);
 hipError_t launch_fill(hyb_ctx *c, double *dst, size_t n, double v);
 
 // ----- cell solves (assemble.hip) -----
@@ -234,16 +250,24 @@ hipError_t launch_multi_axpy_dev(hyb_ctx *c, const double *a, size_t lda, int nv
                                  double *w, size_t n);
 // fused classical Gram-Schmidt with reorthogonalisation (nv <= 32): h1 = V w, w -= V^T h1,
 // h2n[0..nv-1] = V w, h2n[nv] = ||w||^2; then w = (w - V^T h2) * s
-hipError_t launch_gs_passes(hyb_ctx *c, const double *V, size_t n, int nv, double *w, double *h1, double *h2n);
-hipError_t launch_gs_finish(hyb_ctx *c, const double *V, size_t n, int nv, const double *h2, double *w, double s);
+hipError_t launch_gs_passes(hyb_ctx *c, const double *V, size_t lda, size_t n, int nv, double *w, double *h1,
+                            double *h2n);
+hipError_t launch_gs_finish(hyb_ctx *c, const double *V, size_t lda, size_t n, int nv, const double *h2, double *w,
+                            double s);
 // Gram-Schmidt with delayed reorthogonalisation (steps j < kDgsMax): dots of V_j and V_{j+1}
 // against V_0..V_j and ||V_{j+1}||^2 (2 j + 3 values into out_dev: [V_k . V_j], [V_k . V_{j+1}],
 // ||V_{j+1}||^2); then V_j <- (V_j - sum_{k<j} ca_k V_k) rinv and
 // V_{j+1} <- (V_{j+1} - sum_{k<j} cb_k V_k - hjj V_j) einv in one pass (and its FP32 copy into wf
 // if wf is not null).
 constexpr int kDgsMax = 31;
-hipError_t launch_dgs_dots(hyb_ctx *c, const double *V, size_t n, int j, double *out_dev);
-hipError_t launch_dgs_update(hyb_ctx *c, double *V, size_t n, int j, const double *ca, const double *cb, double rinv,
+// the basis vectors of V and Z start kBasisPad entries apart beyond their length, so that entry i
+// of the vectors does not fall on the same HBM channel for all of them (a leading dimension of
+// 2^16 times an odd number made the reduction pass over 18 vectors 50 % slower than over 17)
+constexpr size_t kBasisPad = 256;
+// a restart cycle that leaves more than this fraction of the true residual counts as stalled
+constexpr double kStagnation = 0.999;
+hipError_t launch_dgs_dots(hyb_ctx *c, const double *V, size_t lda, size_t n, int j, double *out_dev);
+hipError_t launch_dgs_update(hyb_ctx *c, double *V, size_t lda, size_t n, int j, const double *ca, const double *cb, double rinv,
                              double hjj, double einv, float *wf = nullptr);
 // w -= sum_k h[k] a[k], then nrm_dev[0] = ||w||^2
 hipError_t launch_axpy_norm(hyb_ctx *c, const double *a, size_t lda, int nv, const double *h_dev, double *w,
@@ -286,6 +310,9 @@ hipError_t nn_forward(hyb_ctx *c, const float *x, float *out, int nsamp);
 hipError_t nn_loss_grad(hyb_ctx *c, const float *x, const float *target, int nsamp, float *loss_host);
 hipError_t nn_energy_grad(hyb_ctx *c, const float *x, const double *rhat, int nsamp, double *loss_host);
 hipError_t nn_adam(hyb_ctx *c, float lr);
+hipError_t nn_stage_buffers(hyb_ctx *c);
+hipError_t nn_pair_finish(hyb_ctx *c, float *x, double *rhat, double *scale_host);
+hipError_t nn_gather_batch(hyb_ctx *c, const float *X, const double *R, const int32_t *idx, int nsamp);
 void nn_free(hyb_ctx *c);
 // restriction of a trace vector to cells: mode 0 Gamma P^T r, mode 1 P^T r / P^T 1 (cell average),
 // mode 2 H_diag times mode 1, mode 3 P^T r

@@ -202,10 +202,10 @@ __global__ void __launch_bounds__(kBlock) k_gs_update_scale(const double *__rest
 // [j + 1 + k], and w . w at [2 j + 2].  A workgroup stages kDgsStage x 256 entries of u and w in LDS; its
 // waves split the basis vectors (wave q takes k = q, q + 4, ...) and each runs over all of them, so
 // every vector entry is loaded once and a thread keeps at most 2 KW accumulators.
-template <int KW>
-__global__ void __launch_bounds__(kBlock) k_dgs_dots(const double *__restrict__ a, size_t lda, int j, size_t n,
-                                                     double *__restrict__ partial) {
-  constexpr int NW = kBlock / 64, RS = kDgsStage, NE = RS * kBlock;  // entries staged per step
+template <int KW, int NW>
+__global__ void __launch_bounds__(NW * 64) k_dgs_dots(const double *__restrict__ a, size_t lda, int j, size_t n,
+                                                      double *__restrict__ partial) {
+  constexpr int NT = NW * 64, RS = kDgsStage, NE = RS * NT;  // entries staged per step
   __shared__ double su[NE], sw[NE], red[NW];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double au[KW], aw[KW], ww = 0.0;
@@ -217,13 +217,13 @@ __global__ void __launch_bounds__(kBlock) k_dgs_dots(const double *__restrict__ 
     double ur[RS], wr[RS];
 #pragma unroll
     for (int q = 0; q < RS; ++q) {
-      const size_t i = base + q * kBlock + threadIdx.x;
+      const size_t i = base + q * NT + threadIdx.x;
       ur[q] = i < n ? u[i] : 0.0, wr[q] = i < n ? w[i] : 0.0;
       ww += wr[q] * wr[q];
     }
     __syncthreads();  // the previous entries are no longer read
 #pragma unroll
-    for (int q = 0; q < RS; ++q) su[q * kBlock + threadIdx.x] = ur[q], sw[q * kBlock + threadIdx.x] = wr[q];
+    for (int q = 0; q < RS; ++q) su[q * NT + threadIdx.x] = ur[q], sw[q * NT + threadIdx.x] = wr[q];
     __syncthreads();
 #pragma unroll
     for (int g = 0; g < NE / 64; ++g) {
@@ -351,11 +351,12 @@ hipError_t launch_axpy_norm(hyb_ctx *c, const double *a, size_t lda, int nv, con
 }
 
 template <int NV>
-hipError_t gs_passes_nv(hyb_ctx *c, const double *V, size_t n, int nv, double *w, double *h1, double *h2n) {
+hipError_t gs_passes_nv(hyb_ctx *c, const double *V, size_t lda, size_t n, int nv, double *w, double *h1,
+                        double *h2n) {
   unsigned nb = std::min<unsigned>(kRedBlocks, nblk(n));
-  hipLaunchKernelGGL((k_gs_dots<NV>), dim3(nb), dim3(kBlock), 0, c->stream, V, n, nv, w, n, c->partial);
+  hipLaunchKernelGGL((k_gs_dots<NV>), dim3(nb), dim3(kBlock), 0, c->stream, V, lda, nv, w, n, c->partial);
   hipLaunchKernelGGL(k_multidot_final, dim3(nv), dim3(kBlock), 0, c->stream, c->partial, (int)nb, h1);
-  hipLaunchKernelGGL((k_gs_update_dots<NV>), dim3(nb), dim3(kBlock), 0, c->stream, V, n, nv, (const double *)h1, w,
+  hipLaunchKernelGGL((k_gs_update_dots<NV>), dim3(nb), dim3(kBlock), 0, c->stream, V, lda, nv, (const double *)h1, w,
                      n, c->partial);
   hipLaunchKernelGGL(k_multidot_final, dim3(nv + 1), dim3(kBlock), 0, c->stream, c->partial, (int)nb, h2n);
   return hipGetLastError();
@@ -364,48 +365,51 @@ hipError_t gs_passes_nv(hyb_ctx *c, const double *V, size_t n, int nv, double *w
 // Classical Gram-Schmidt with reorthogonalisation against the nv orthonormal rows of V (stride n):
 // h1 = V w; w -= V^T h1; h2 = V w; ||w||^2 -> h2n[nv]; the final update and normalisation is
 // launch_gs_finish once the host knows the norm.
-hipError_t launch_gs_passes(hyb_ctx *c, const double *V, size_t n, int nv, double *w, double *h1, double *h2n) {
+hipError_t launch_gs_passes(hyb_ctx *c, const double *V, size_t lda, size_t n, int nv, double *w, double *h1,
+                            double *h2n) {
   if (nv < 1 || nv > 32 || nv + 1 > c->m + 2) return hipErrorInvalidValue;
   int slot = prof_begin(c, F_KRYLOV);
   hipError_t e;
   if (nv <= 8)
-    e = gs_passes_nv<8>(c, V, n, nv, w, h1, h2n);
+    e = gs_passes_nv<8>(c, V, lda, n, nv, w, h1, h2n);
   else if (nv <= 16)
-    e = gs_passes_nv<16>(c, V, n, nv, w, h1, h2n);
+    e = gs_passes_nv<16>(c, V, lda, n, nv, w, h1, h2n);
   else
-    e = gs_passes_nv<32>(c, V, n, nv, w, h1, h2n);
+    e = gs_passes_nv<32>(c, V, lda, n, nv, w, h1, h2n);
   prof_end(c, F_KRYLOV, slot);
   return e;
 }
 
-hipError_t launch_gs_finish(hyb_ctx *c, const double *V, size_t n, int nv, const double *h2, double *w, double s) {
+hipError_t launch_gs_finish(hyb_ctx *c, const double *V, size_t lda, size_t n, int nv, const double *h2, double *w,
+                            double s) {
   if (nv < 1 || nv > 32) return hipErrorInvalidValue;
   int slot = prof_begin(c, F_KRYLOV);
   if (nv <= 8)
-    hipLaunchKernelGGL((k_gs_update_scale<8>), dim3(nblk(n)), dim3(kBlock), 0, c->stream, V, n, nv, h2, w, n, s);
+    hipLaunchKernelGGL((k_gs_update_scale<8>), dim3(nblk(n)), dim3(kBlock), 0, c->stream, V, lda, nv, h2, w, n, s);
   else if (nv <= 16)
-    hipLaunchKernelGGL((k_gs_update_scale<16>), dim3(nblk(n)), dim3(kBlock), 0, c->stream, V, n, nv, h2, w, n, s);
+    hipLaunchKernelGGL((k_gs_update_scale<16>), dim3(nblk(n)), dim3(kBlock), 0, c->stream, V, lda, nv, h2, w, n, s);
   else
-    hipLaunchKernelGGL((k_gs_update_scale<32>), dim3(nblk(n)), dim3(kBlock), 0, c->stream, V, n, nv, h2, w, n, s);
+    hipLaunchKernelGGL((k_gs_update_scale<32>), dim3(nblk(n)), dim3(kBlock), 0, c->stream, V, lda, nv, h2, w, n, s);
   prof_end(c, F_KRYLOV, slot);
   return hipGetLastError();
 }
 
-hipError_t launch_dgs_dots(hyb_ctx *c, const double *V, size_t n, int j, double *out_dev) {
+hipError_t launch_dgs_dots(hyb_ctx *c, const double *V, size_t lda, size_t n, int j, double *out_dev) {
   if (j < 0 || j >= kDgsMax || 2 * j + 3 > 2 * (c->m + 2)) return hipErrorInvalidValue;
   int slot = prof_begin(c, F_KRYLOV);
-  const unsigned nb = std::min<unsigned>(kRedBlocks, nblk(n, kDgsStage * kBlock));
-  static_assert(kBlock == 256, "four waves split the basis vectors");
-  // the j + 1 vectors a_0..a_j over four waves: exactly as many accumulator slots as needed (spare
-  // slots cost registers and occupancy: 8 slots for j = 16 ran at 3.6 TB/s, 4 slots at 5.2)
-  const int kw = (j + 4) / 4;
-  switch (kw) {
-#define HYB_DGS_CASE(K)                                                                                   \
-  case K:                                                                                                 \
-    hipLaunchKernelGGL((k_dgs_dots<K>), dim3(nb), dim3(kBlock), 0, c->stream, V, n, j, n, c->partial); \
+  // the j + 1 vectors a_0..a_j split over the waves of a workgroup, exactly as many accumulator
+  // slots as needed (spare slots cost registers and occupancy): four waves up to j = 15, eight
+  // beyond (five slots on four waves ran at 3.4 TB/s against 5.3 for four)
+  const int nw = j < 16 ? 4 : 8;
+  const unsigned nb = std::min<unsigned>(kRedBlocks, nblk(n, kDgsStage * 64 * nw));
+  const int kw = (j + nw) / nw;
+  switch (nw * 16 + kw) {
+#define HYB_DGS_CASE(W, K)                                                                                   \
+  case W * 16 + K:                                                                                           \
+    hipLaunchKernelGGL((k_dgs_dots<K, W>), dim3(nb), dim3(64 * W), 0, c->stream, V, lda, j, n, c->partial); \
     break;
-    HYB_DGS_CASE(1) HYB_DGS_CASE(2) HYB_DGS_CASE(3) HYB_DGS_CASE(4)
-    HYB_DGS_CASE(5) HYB_DGS_CASE(6) HYB_DGS_CASE(7) HYB_DGS_CASE(8)
+    HYB_DGS_CASE(4, 1) HYB_DGS_CASE(4, 2) HYB_DGS_CASE(4, 3) HYB_DGS_CASE(4, 4)
+    HYB_DGS_CASE(8, 3) HYB_DGS_CASE(8, 4)
 #undef HYB_DGS_CASE
     default:
       return hipErrorInvalidValue;
@@ -415,20 +419,21 @@ hipError_t launch_dgs_dots(hyb_ctx *c, const double *V, size_t n, int j, double 
   return hipGetLastError();
 }
 
-hipError_t launch_dgs_update(hyb_ctx *c, double *V, size_t n, int j, const double *ca, const double *cb, double rinv,
+hipError_t launch_dgs_update(hyb_ctx *c, double *V, size_t lda, size_t n, int j, const double *ca, const double *cb,
+                             double rinv,
                              double hjj, double einv, float *wf) {
   if (j < 0 || j >= kDgsMax) return hipErrorInvalidValue;
   DgsCoef cf{};
   for (int k = 0; k < j; ++k) cf.a[k] = ca[k], cf.b[k] = cb[k];
   int slot = prof_begin(c, F_KRYLOV);
   if (j < 8)
-    hipLaunchKernelGGL((k_dgs_update<8>), dim3(nblk(n)), dim3(kBlock), 0, c->stream, V, n, j, cf, rinv, hjj, einv, n,
+    hipLaunchKernelGGL((k_dgs_update<8>), dim3(nblk(n)), dim3(kBlock), 0, c->stream, V, lda, j, cf, rinv, hjj, einv, n,
                        wf);
   else if (j < 16)
-    hipLaunchKernelGGL((k_dgs_update<16>), dim3(nblk(n)), dim3(kBlock), 0, c->stream, V, n, j, cf, rinv, hjj, einv, n,
+    hipLaunchKernelGGL((k_dgs_update<16>), dim3(nblk(n)), dim3(kBlock), 0, c->stream, V, lda, j, cf, rinv, hjj, einv, n,
                        wf);
   else
-    hipLaunchKernelGGL((k_dgs_update<32>), dim3(nblk(n)), dim3(kBlock), 0, c->stream, V, n, j, cf, rinv, hjj, einv, n,
+    hipLaunchKernelGGL((k_dgs_update<32>), dim3(nblk(n)), dim3(kBlock), 0, c->stream, V, lda, j, cf, rinv, hjj, einv, n,
                        wf);
   prof_end(c, F_KRYLOV, slot);
   return hipGetLastError();

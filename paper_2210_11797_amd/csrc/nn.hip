@@ -187,10 +187,9 @@ __global__ void __launch_bounds__(kBlock) k_mse(const float *__restrict__ y, con
                                                 float *__restrict__ dy, size_t total, float *__restrict__ part) {
   __shared__ float red[kBlock / 64];
   float acc = 0.f;
-  const float sc = 2.f / (float)total;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
     float d = y[i] - t[i];
-    dy[i] = sc * d;
+    dy[i] = 2.f * d;  // d loss / d y without the 1 / total of the mean (applied to the gradients)
     acc += d * d;
   }
 #pragma unroll
@@ -202,6 +201,12 @@ __global__ void __launch_bounds__(kBlock) k_mse(const float *__restrict__ y, con
     for (int q = 0; q < kBlock / 64; ++q) s += red[q];
     part[blockIdx.x] = s;
   }
+}
+
+// g *= a (the loss scale, backpropagated as 1 so that the backward passes do not carry it)
+__global__ void k_scale_f32(float *__restrict__ g, int n, float a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) g[i] *= a;
 }
 
 // Adam on the FP32 master weights; refresh the BF16 copy of the weights (not of the biases)
@@ -291,6 +296,14 @@ __global__ void k_normalise(const double *__restrict__ c, const double *__restri
   if (i >= n) return;
   double s = sqrt(scal[0] / (double)n);
   x[i] = s > 0.0 ? (float)(c[i] / s) : 0.f;
+}
+
+// v /= s with s = sqrt(scal[0] / ncell) (0 when s = 0)
+__global__ void k_div_rms(double *__restrict__ v, const double *__restrict__ scal, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double s = sqrt(scal[0] / (double)n);
+  v[i] = s > 0.0 ? v[i] / s : 0.0;
 }
 
 // d_F = s (P (y / H_diag))_F when the network output is finite (scal[1] = sum y^2), else 0
@@ -397,17 +410,17 @@ __global__ void k_prolong_q(const float *__restrict__ y, const double *__restric
 }
 
 // Energy loss over a batch: q = y / H_diag per cell (H_diag repeats for every sample), partial sums of
-// q (Gq - 2 rhat) per block, and dy = 2 (Gq - rhat) / H_diag * scale
+// q (Gq - 2 rhat) per block, and dy = 2 (Gq - rhat) / H_diag (the loss scale is applied to the gradients)
 __global__ void __launch_bounds__(kBlock) k_energy(const float *__restrict__ y, const double *__restrict__ gq,
                                                   const double *__restrict__ rhat, const double *__restrict__ hdiag,
-                                                  float *__restrict__ dy, size_t ncell, size_t total, double scale,
+                                                  float *__restrict__ dy, size_t ncell, size_t total,
                                                   double *__restrict__ part) {
   __shared__ double red[kBlock / 64];
   double acc = 0.0;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
     double h = hdiag[i % ncell], q = (double)y[i] / h, g = gq[i], r = rhat[i];
     acc += q * (g - 2.0 * r);
-    dy[i] = (float)(2.0 * (g - r) / h * scale);
+    dy[i] = (float)(2.0 * (g - r) / h);  // without the loss scale (applied to the gradients)
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
@@ -430,15 +443,18 @@ typedef short nn_bf16x4 __attribute__((ext_vector_type(4)));
 
 __global__ void __launch_bounds__(kBlock) k_inf_layer1(const float *__restrict__ x, const uint16_t *__restrict__ wb,
                                                       const float *__restrict__ bias, uint16_t *__restrict__ a1,
-                                                      int nlev, int ncol, const int32_t *__restrict__ nb9,
+                                                      int nlev, int ncol, int nsamp, const int32_t *__restrict__ nb9,
                                                       const float *__restrict__ xst) {
   constexpr int CIN = kNNInputs;  // x, then the static fields xst[CIN - 1][cell]
   __shared__ float w[C1 * CIN * NTAP];
   for (int i = threadIdx.x; i < C1 * CIN * NTAP; i += blockDim.x) w[i] = bf2f(wb[i]);
   __syncthreads();
-  const int cell = blockIdx.x * blockDim.x + threadIdx.x;
-  if (cell >= nlev * ncol) return;
+  const size_t n = (size_t)nlev * ncol;
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= n * nsamp) return;
+  const int smp = (int)(gid / n), cell = (int)(gid - (size_t)smp * n);
   const int k = cell / ncol, col = cell - k * ncol;
+  x += (size_t)smp * n;
   float acc[C1];
 #pragma unroll
   for (int co = 0; co < C1; ++co) acc[co] = bias[co];
@@ -461,78 +477,273 @@ __global__ void __launch_bounds__(kBlock) k_inf_layer1(const float *__restrict__
     }
   }
 #pragma unroll
-  for (int co = 0; co < C1; ++co) a1[(size_t)cell * C1 + co] = f2bf(fmaxf(acc[co], 0.f));
+  for (int co = 0; co < C1; ++co) a1[gid * C1 + co] = f2bf(fmaxf(acc[co], 0.f));
 }
 
-constexpr int kInfTiles = 8;  // 16-cell tiles per wavefront
-__global__ void __launch_bounds__(kBlock) k_inf_layer2_mfma(const uint16_t *__restrict__ a1,
-                                                           const uint16_t *__restrict__ wb2,
-                                                           const float *__restrict__ bias, uint16_t *__restrict__ a2,
-                                                           int nlev, int ncol, const int32_t *__restrict__ nb9) {
-  // the B operands of every tap in LDS, [tap][co][ci], so a lane reads its 4 input channels at once
-  __shared__ uint2 sB[NTAP][C1][C1 / 4];
-  for (int i = threadIdx.x; i < NTAP * C1 * (C1 / 4); i += blockDim.x) {
-    const int t = i / (C1 * C1 / 4), rem = i - t * (C1 * C1 / 4), co = rem / (C1 / 4), c4 = rem - co * (C1 / 4);
-    const unsigned w0 = wb2[(co * C1 + 4 * c4) * NTAP + t], w1 = wb2[(co * C1 + 4 * c4 + 1) * NTAP + t];
-    const unsigned w2 = wb2[(co * C1 + 4 * c4 + 2) * NTAP + t], w3 = wb2[(co * C1 + 4 * c4 + 3) * NTAP + t];
-    sB[t][co][c4] = make_uint2(w0 | (w1 << 16), w2 | (w3 << 16));
+// Layer 2 (16 -> 16 channels) as an implicit GEMM on BF16 MFMA (v_mfma_f32_16x16x32_bf16, FP32
+// accumulation): a wavefront takes tiles of 16 rows (sample, cell); one product covers two taps, the
+// A operand holding the 16 rows' tapped activations (lanes of quarter q: tap 2p + q / 2, channels
+// 8 (q % 2) .. + 7, one 16-byte load) and B the two taps' weights from LDS.  23 products cover the 45
+// taps.  Forward: out = bf16(relu(conv2(in) + b2)) with tap_col = the 3x3 neighbourhood.  Backward
+// (BWD): out = bf16(conv2^T(in) * (gate > 0)), the transposed convolution gathered through the readers
+// of each column: tap_col[h][col] is the column that reads col through horizontal tap h (its level
+// offset reversed); where several columns read col through the same tap (next to cube edges), the
+// others are listed in lo_list[lo_off[col] .. lo_off[col + 1]) as reader * 9 + h and added by the
+// lanes after the products.  Rows are [sample][cell], 16 BF16 channels contiguous.
+typedef __bf16 nn_bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int nn_u32x4 __attribute__((ext_vector_type(4)));
+typedef short nn_s16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ nn_f32x4 mfma_bf16_32(nn_u32x4 a, nn_u32x4 b, nn_f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(nn_bf16x8, a), __builtin_bit_cast(nn_bf16x8, b), c,
+                                                 0, 0, 0);
+}
+
+constexpr int kC2Tiles = 4;  // 16-row tiles per wavefront
+template <bool BWD>
+__global__ void __launch_bounds__(kBlock) k_conv2_mfma(const uint16_t *__restrict__ in, const uint16_t *__restrict__ wb2,
+                                                      const float *__restrict__ bias, const uint16_t *__restrict__ gate,
+                                                      uint16_t *__restrict__ out, int nlev, int ncol, int nsamp,
+                                                      const int32_t *__restrict__ tap_col,
+                                                      const int32_t *__restrict__ lo_off,
+                                                      const int32_t *__restrict__ lo_list) {
+  // weights as [tap][n][k]: forward n = output channel, k = input channel; backward the transpose
+  __shared__ nn_u32x4 sW[NTAP][C1][2];
+  for (int i = threadIdx.x; i < NTAP * C1 * C1; i += blockDim.x) {
+    const int t = i / (C1 * C1), rem = i - t * (C1 * C1), nn = rem / C1, kk = rem - nn * C1;
+    const int co = BWD ? kk : nn, ci = BWD ? nn : kk;
+    reinterpret_cast<uint16_t *>(&sW[t][nn][0])[kk] = wb2[(co * C1 + ci) * NTAP + t];
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const int ncell = nlev * ncol;
-  const int r = lane & 15, q = lane >> 4;  // operand row / k-quarter
-  const float bco = bias[r];
-  for (int tile = 0; tile < kInfTiles; ++tile) {
-    const int base = (wave * kInfTiles + tile) * 16;
-    if (base >= ncell) break;  // uniform over the wavefront
-    const int cell = base + r;  // the cell whose tapped values this lane loads
-    const bool live = cell < ncell;
-    const int k = live ? cell / ncol : 0, col = live ? cell - k * ncol : 0;
+  const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4, half = q & 1;
+  const bool second = q >= 2;
+  const size_t n = (size_t)nlev * ncol, total = n * nsamp;
+  const size_t wave = (size_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const nn_u32x4 zero4 = {0u, 0u, 0u, 0u};
+  for (int tile = 0; tile < kC2Tiles; ++tile) {
+    const size_t base = (wave * kC2Tiles + tile) * 16;
+    if (base >= total) break;  // uniform over the wavefront
+    const size_t g = base + r;
+    const bool live = g < total;
+    const size_t gs = live ? g : base;
+    const int smp = (int)(gs / n), cell = (int)(gs - (size_t)smp * n);
+    const int k = cell / ncol, col = cell - k * ncol;
+    const uint16_t *ins = in + (size_t)smp * n * C1;
+    int cn[NHT];  // the 3x3 neighbourhood first, so that the tap loads do not wait on it
+#pragma unroll
+    for (int h = 0; h < NHT; ++h) cn[h] = tap_col[(size_t)h * ncol + col];
     nn_f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    int cn[NHT];  // the 3x3 neighbourhood first, so that the 45 activation loads do not wait on it
 #pragma unroll
-    for (int h = 0; h < NHT; ++h) cn[h] = live ? nb9[(size_t)h * ncol + col] : 0;
-#pragma unroll
-    for (int h = 0; h < NHT; ++h) {
-      // a missing corner neighbour (cube vertex) loads from the column itself and is discarded
-      const bool has = cn[h] >= 0;
-      const int c2 = has ? cn[h] : col;
-#pragma unroll
-      for (int v = 0; v < NVT; ++v) {
-        // unconditional load from a clamped level (the value is discarded outside the column), so
-        // the loads of all taps can be issued ahead of the products
-        const int kk = k + v - 2, kc = kk < 0 ? 0 : (kk >= nlev ? nlev - 1 : kk);
-        const uint2 u = *reinterpret_cast<const uint2 *>(a1 + ((size_t)kc * ncol + c2) * C1 + 4 * q);
-        const bool in = live && has && kk == kc;
-        nn_bf16x4 A;
-        A[0] = in ? (short)(u.x & 0xFFFFu) : (short)0, A[1] = in ? (short)(u.x >> 16) : (short)0;
-        A[2] = in ? (short)(u.y & 0xFFFFu) : (short)0, A[3] = in ? (short)(u.y >> 16) : (short)0;
-        // B: lane holds W2[co = r][ci = 4 q + j][tap], j = 0..3
-        const uint2 w = sB[h * NVT + v][r][q];
-        nn_bf16x4 B;
-        B[0] = (short)(w.x & 0xFFFFu), B[1] = (short)(w.x >> 16), B[2] = (short)(w.y & 0xFFFFu), B[3] = (short)(w.y >> 16);
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, B, acc, 0, 0, 0);
-      }
+    for (int p = 0; p < (NTAP + 1) / 2; ++p) {
+      constexpr int kLast = NTAP - 1;
+      const int t0 = 2 * p, t1 = (2 * p + 1 <= kLast) ? 2 * p + 1 : kLast;
+      const bool has = second ? (2 * p + 1 <= kLast) : true;
+      const int t = second ? t1 : t0;
+      const int c2 = second ? cn[t1 / NVT] : cn[t0 / NVT];
+      const int v = second ? t1 % NVT : t0 % NVT;
+      const int kk = BWD ? k - (v - 2) : k + (v - 2);
+      const int kc = kk < 0 ? 0 : (kk >= nlev ? nlev - 1 : kk);
+      // unconditional load from a clamped place (discarded outside), so the loads issue ahead
+      const nn_u32x4 u = *reinterpret_cast<const nn_u32x4 *>(ins + ((size_t)kc * ncol + (c2 >= 0 ? c2 : col)) * C1 +
+                                                              8 * half);
+      const bool ok = live && has && c2 >= 0 && kk == kc;
+      const nn_u32x4 a = ok ? u : zero4;
+      const nn_u32x4 b = has ? sW[t][r][half] : zero4;
+      acc = mfma_bf16_32(a, b, acc);
     }
-    // acc[j] = output channel r of cell base + 4 q + j
+    // acc[j] = channel r of row base + 4 q + j
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int oc = base + 4 * q + j;
-      if (oc < ncell) a2[(size_t)oc * C1 + r] = f2bf(fmaxf(acc[j] + bco, 0.f));
+      const size_t go = base + 4 * q + j;
+      if (go >= total) continue;
+      float val = acc[j];
+      if (!BWD) {
+        out[go * C1 + r] = f2bf(fmaxf(val + bias[r], 0.f));
+      } else {
+        const int so = (int)(go / n), oc = (int)(go - (size_t)so * n), ko = oc / ncol, colo = oc - ko * ncol;
+        for (int e = lo_off[colo]; e < lo_off[colo + 1]; ++e) {
+          const int pk = lo_list[e], cr = pk / NHT, hh = pk - cr * NHT;
+          for (int v = 0; v < NVT; ++v) {
+            const int kk = ko - (v - 2);
+            if (kk < 0 || kk >= nlev) continue;
+            const uint16_t *src = in + ((size_t)so * n + (size_t)kk * ncol + cr) * C1;
+            const uint16_t *w = reinterpret_cast<const uint16_t *>(&sW[hh * NVT + v][r][0]);
+            for (int co = 0; co < C1; ++co) val += bf2f(w[co]) * bf2f(src[co]);
+          }
+        }
+        out[go * C1 + r] = bf2f(gate[go * C1 + r]) > 0.f ? f2bf(val) : (uint16_t)0;
+      }
     }
   }
+}
+
+// Weight gradients on BF16 MFMA: for horizontal tap h = blockIdx.y and the five vertical offsets v,
+//   part[blk][h][v][co][ci] = sum over this workgroup's rows of dA[row][co] * act[tap(row, h, v)][ci]
+// (D = A B with A = dA^T: 16 output channels x 32 rows, B = the tapped activations: 32 rows x 16 input
+// channels), and for h = 0 the bias sums bpart[blk][co] = sum over the rows of dA[row][co].
+// dA: CA = 16 BF16 [sample][cell][16], CA = 1 FP32 [sample][cell] (rounded to BF16 for the product; the
+// bias sum takes it unrounded).  act: CB = 16 BF16 [sample][cell][16]; CB = 3 the network's input, x
+// FP32 [sample][cell] and the static fields st FP32 [2][cell].  Channels beyond CA / CB are zero.
+constexpr int kWgBlocks = 128;
+template <int CA, int CB>
+__global__ void __launch_bounds__(kBlock) k_wgrad_mfma(const void *__restrict__ dA_, const void *__restrict__ act_,
+                                                      const float *__restrict__ st, float *__restrict__ part,
+                                                      float *__restrict__ bpart, int nlev, int ncol, int nsamp,
+                                                      const int32_t *__restrict__ nb9) {
+  constexpr int NW = kBlock / 64;
+  __shared__ float red[NW][NVT][4][64];
+  __shared__ float bred[NW][64];
+  const int h = blockIdx.y;
+  const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4, wv = threadIdx.x >> 6;
+  const size_t n = (size_t)nlev * ncol, total = n * nsamp, nchunks = (total + 31) / 32;
+  const size_t nwaves = (size_t)gridDim.x * NW;
+  const nn_f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  nn_f32x4 acc[NVT];
+#pragma unroll
+  for (int v = 0; v < NVT; ++v) acc[v] = zero;
+  float bsum = 0.f;
+  for (size_t ch = (size_t)blockIdx.x * NW + wv; ch < nchunks; ch += nwaves) {
+    const size_t base = ch * 32 + 8 * q;
+    nn_s16x8 a;
+    size_t soff[8];
+    int kr[8], cnb[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const size_t g = base + j;
+      const bool live = g < total;
+      const size_t gs = live ? g : 0;
+      if (CA == 16) {
+        const uint16_t av = live ? reinterpret_cast<const uint16_t *>(dA_)[gs * 16 + r] : (uint16_t)0;
+        bsum += bf2f(av);
+        a[j] = (short)av;
+      } else {
+        const float fv = (live && r == 0) ? reinterpret_cast<const float *>(dA_)[gs] : 0.f;
+        bsum += fv;
+        a[j] = (short)f2bf(fv);
+      }
+      const int smp = (int)(gs / n), cell = (int)(gs - (size_t)smp * n);
+      const int k = cell / ncol, col = cell - k * ncol;
+      soff[j] = (size_t)smp * n;
+      kr[j] = k;
+      cnb[j] = live ? nb9[(size_t)h * ncol + col] : -1;
+    }
+#pragma unroll
+    for (int v = 0; v < NVT; ++v) {
+      nn_s16x8 b;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int kk = kr[j] + v - 2;
+        const bool ok = cnb[j] >= 0 && kk >= 0 && kk < nlev && r < CB;
+        const size_t c2 = ok ? (size_t)kk * ncol + cnb[j] : 0;
+        uint16_t bv = 0;
+        if (CB == 16) {
+          if (ok) bv = reinterpret_cast<const uint16_t *>(act_)[(soff[j] + c2) * 16 + r];
+        } else {
+          float fv = 0.f;
+          if (ok) fv = r == 0 ? reinterpret_cast<const float *>(act_)[soff[j] + c2] : st[(size_t)(r - 1) * n + c2];
+          bv = f2bf(fv);
+        }
+        b[j] = (short)bv;
+      }
+      acc[v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(nn_bf16x8, a), __builtin_bit_cast(nn_bf16x8, b),
+                                                       acc[v], 0, 0, 0);
+    }
+  }
+  // the block's waves in a fixed order; lane (r, q) holds entry j of output channel 4 q + j, input r
+#pragma unroll
+  for (int v = 0; v < NVT; ++v)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) red[wv][v][j][lane] = acc[v][j];
+  bred[wv][lane] = bsum;
+  __syncthreads();
+  float *out = part + ((size_t)blockIdx.x * NHT + h) * (NVT * 256);
+  for (int o = threadIdx.x; o < NVT * 256; o += blockDim.x) {
+    const int v = o >> 8, co = (o >> 4) & 15, ci = o & 15;
+    const int src = ci + 16 * (co >> 2), j = co & 3;
+    float sacc = 0.f;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) sacc += red[w][v][j][src];
+    out[o] = sacc;
+  }
+  if (h == 0 && threadIdx.x < 16) {
+    float sacc = 0.f;
+#pragma unroll
+    for (int w = 0; w < NW; ++w)
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) sacc += bred[w][threadIdx.x + 16 * qq];
+    bpart[(size_t)blockIdx.x * 16 + threadIdx.x] = sacc;
+  }
+}
+
+// grad_w[(co * CI + ci) * 45 + 5 h + v] and grad_b[co] summed over the workgroups' partials in a
+// fixed order (co < CO, ci < CI); one thread per partial entry, so consecutive threads read
+// consecutive partials.
+__global__ void k_wgrad_sum(const float *__restrict__ part, const float *__restrict__ bpart, int nparts, int CO,
+                            int CI, float *__restrict__ grad_w, float *__restrict__ grad_b) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  constexpr int PER = NHT * NVT * 256;
+  if (o < PER) {
+    const int hv = o >> 8, co = (o >> 4) & 15, ci = o & 15;
+    if (co >= CO || ci >= CI) return;
+    float sacc = 0.f;
+    for (int b = 0; b < nparts; ++b) sacc += part[(size_t)b * PER + o];
+    grad_w[(co * CI + ci) * NTAP + hv] = sacc;
+  } else if (o < PER + CO) {
+    const int co = o - PER;
+    float sacc = 0.f;
+    for (int b = 0; b < nparts; ++b) sacc += bpart[(size_t)b * 16 + co];
+    grad_b[co] = sacc;
+  }
+}
+
+// Layer 3 backward to its input: dz2[row][ci] = bf16((a2[row][ci] > 0) * sum over the readers (c', h)
+// of the column and v of W3[0][ci][5 h + v] dy[sample][k - (v - 2)][c']) (rv9: the readers, any order).
+__global__ void __launch_bounds__(kBlock) k_bwd3_bf16(const float *__restrict__ dy, const uint16_t *__restrict__ wb3,
+                                                     const uint16_t *__restrict__ a2, uint16_t *__restrict__ dz2,
+                                                     int nlev, int ncol, int nsamp, const int32_t *__restrict__ rv9) {
+  __shared__ float w[C1 * NTAP];
+  for (int i = threadIdx.x; i < C1 * NTAP; i += blockDim.x) w[i] = bf2f(wb3[i]);
+  __syncthreads();
+  const size_t n = (size_t)nlev * ncol;
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= n * nsamp) return;
+  const int smp = (int)(gid / n), cell = (int)(gid - (size_t)smp * n);
+  const int k = cell / ncol, col = cell - k * ncol;
+  const float *dys = dy + (size_t)smp * n;
+  float acc[C1];
+#pragma unroll
+  for (int ci = 0; ci < C1; ++ci) acc[ci] = 0.f;
+  for (int rr = 0; rr < NHT; ++rr) {
+    const int pk = rv9[(size_t)rr * ncol + col];
+    if (pk < 0) continue;
+    const int c2 = pk / NHT, hh = pk - c2 * NHT;
+#pragma unroll
+    for (int v = 0; v < NVT; ++v) {
+      const int kk = k - (v - 2);
+      if (kk < 0 || kk >= nlev) continue;
+      const float g = dys[(size_t)kk * ncol + c2];
+#pragma unroll
+      for (int ci = 0; ci < C1; ++ci) acc[ci] += w[ci * NTAP + hh * NVT + v] * g;
+    }
+  }
+  const uint16_t *ag = a2 + gid * C1;
+  uint16_t *o = dz2 + gid * C1;
+#pragma unroll
+  for (int ci = 0; ci < C1; ++ci) o[ci] = bf2f(ag[ci]) > 0.f ? f2bf(acc[ci]) : (uint16_t)0;
 }
 
 __global__ void __launch_bounds__(kBlock) k_inf_layer3(const uint16_t *__restrict__ a2, const uint16_t *__restrict__ wb3,
                                                       const float *__restrict__ bias, float *__restrict__ y, int nlev,
-                                                      int ncol, const int32_t *__restrict__ nb9) {
+                                                      int ncol, int nsamp, const int32_t *__restrict__ nb9) {
   __shared__ float w[C1 * NTAP];
   for (int i = threadIdx.x; i < C1 * NTAP; i += blockDim.x) w[i] = bf2f(wb3[i]);
   __syncthreads();
-  const int cell = blockIdx.x * blockDim.x + threadIdx.x;
-  if (cell >= nlev * ncol) return;
+  const size_t n = (size_t)nlev * ncol;
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= n * nsamp) return;
+  const int smp = (int)(gid / n), cell = (int)(gid - (size_t)smp * n);
   const int k = cell / ncol, col = cell - k * ncol;
+  a2 += (size_t)smp * n * C1;
   float acc = bias[0];
   for (int h = 0; h < NHT; ++h) {
     const int c2 = nb9[(size_t)h * ncol + col];
@@ -551,7 +762,7 @@ __global__ void __launch_bounds__(kBlock) k_inf_layer3(const uint16_t *__restric
       }
     }
   }
-  y[cell] = acc;
+  y[gid] = acc;
 }
 
 // Static input channels of the network: st[0] = log(h / dz) with h = sqrt(|K| / dz) the cell's
@@ -646,8 +857,34 @@ hipError_t nn_setup(hyb_ctx *c) {
       if (cnt[t] >= 9) return hipErrorInvalidValue;  // more than 9 readers of one column
       rv9[(size_t)cnt[t]++ * n + t] = (int32_t)(col * 9 + h);
     }
+  // the same readers by tap for the transposed convolution on matrix cores: rvh[h][col] = the first
+  // column that reads col through tap h (-1: none), the further ones (next to cube edges) listed
+  // per column as col' * 9 + h
+  std::vector<int32_t> rvh(9 * n, -1), lo_off(n + 1, 0), lo_list;
+  std::vector<std::vector<int32_t>> extra(n);
+  for (int h = 0; h < 9; ++h)
+    for (size_t col = 0; col < n; ++col) {
+      const int t = nb9[h * n + col];
+      if (t < 0) continue;
+      if (rvh[h * n + t] < 0)
+        rvh[h * n + t] = (int32_t)col;
+      else
+        extra[t].push_back((int32_t)(col * 9 + h));
+    }
+  for (size_t col = 0; col < n; ++col) {
+    lo_off[col + 1] = lo_off[col] + (int32_t)extra[col].size();
+    lo_list.insert(lo_list.end(), extra[col].begin(), extra[col].end());
+  }
+  if (lo_list.empty()) lo_list.push_back(0);  // a valid pointer when no column has further readers
+  auto A2 = [&](int32_t **p, const std::vector<int32_t> &v) -> hipError_t {
+    hipError_t r = hipMalloc((void **)p, v.size() * 4);
+    if (r) return r;
+    c->bytes += v.size() * 4;
+    return hipMemcpy(*p, v.data(), v.size() * 4, hipMemcpyHostToDevice);
+  };
   if ((e = hipMemcpy(s.nb9, nb9.data(), nb9.size() * 4, hipMemcpyHostToDevice)) ||
-      (e = hipMemcpy(s.rv9, rv9.data(), rv9.size() * 4, hipMemcpyHostToDevice)))
+      (e = hipMemcpy(s.rv9, rv9.data(), rv9.size() * 4, hipMemcpyHostToDevice)) || (e = A2(&s.rvh, rvh)) ||
+      (e = A2(&s.lo_off, lo_off)) || (e = A2(&s.lo_list, lo_list)))
     return e;
   std::vector<float> zero(NPARAM, 0.f);
   if ((e = hipMemcpy(s.m, zero.data(), NPARAM * 4, hipMemcpyHostToDevice)) ||
@@ -728,15 +965,34 @@ static hipError_t nn_static(hyb_ctx *c) {
   return hipSuccess;
 }
 
-// Forward pass of nsamp fields x [nsamp][ncell] -> out [nsamp][ncell] (activations kept for backward).
+// The BF16 matrix-core forward pass of nsamp fields: a1, a2 BF16 [nsamp][ncell][16] (in the
+// activation buffers), out FP32 [nsamp][ncell].
+static hipError_t forward_bf16(hyb_ctx *c, const float *x, uint16_t *a1, uint16_t *a2, float *out, int nsamp) {
+  NNState &s = c->nn;
+  const size_t n = (size_t)c->ncell * nsamp;
+  const int L = c->nlev, nc = c->ncol;
+  hipLaunchKernelGGL(k_inf_layer1, dim3(nblk(n)), dim3(kBlock), 0, c->stream, x, s.wb, s.w + OFF_B1, a1, L, nc, nsamp,
+                     s.nb9, (const float *)s.st);
+  const size_t waves = (n + 16 * kC2Tiles - 1) / (16 * kC2Tiles);
+  hipLaunchKernelGGL((k_conv2_mfma<false>), dim3(nblk(waves, kBlock / 64)), dim3(kBlock), 0, c->stream,
+                     (const uint16_t *)a1, s.wb + W1N, s.w + OFF_B2, (const uint16_t *)nullptr, a2, L, nc, nsamp, s.nb9,
+                     (const int32_t *)nullptr, (const int32_t *)nullptr);
+  hipLaunchKernelGGL(k_inf_layer3, dim3(nblk(n)), dim3(kBlock), 0, c->stream, (const uint16_t *)a2, s.wb + W1N + W2N,
+                     s.w + OFF_B3, out, L, nc, nsamp, s.nb9);
+  return hipGetLastError();
+}
+
+// Forward pass of nsamp fields x [nsamp][ncell] -> out [nsamp][ncell] (activations kept for backward):
+// BF16 activations on matrix cores, or with params.nn_fp32 FP32 activations on the vector units.
 hipError_t nn_forward(hyb_ctx *c, const float *x, float *out, int nsamp) {
   NNState &s = c->nn;
   hipError_t e = ensure_acts(c, nsamp);
   if (e) return e;
+  if ((e = nn_static(c))) return e;
+  if (!c->p.nn_fp32) return forward_bf16(c, x, (uint16_t *)s.a1, (uint16_t *)s.a2, out, nsamp);
   size_t n = (size_t)c->ncell * nsamp;
   dim3 g(nblk(n)), b(kBlock);
   int L = c->nlev, nc = c->ncol;
-  if ((e = nn_static(c))) return e;
   hipLaunchKernelGGL((k_conv_fwd<CIN, C, true, CIN - 1>), g, b, 0, c->stream, x, s.wb, s.w + OFF_B1, s.a1, L, nc,
                      nsamp, s.nb9, (const float *)s.st);
   hipLaunchKernelGGL((k_conv_fwd<C, C, true>), g, b, 0, c->stream, s.a1, s.wb + W1N, s.w + OFF_B2, s.a2, L, nc, nsamp,
@@ -757,15 +1013,49 @@ static hipError_t nn_forward_inference(hyb_ctx *c, const float *x, float *out) {
     c->bytes += 2 * n * C * 2;
   }
   if ((e = nn_static(c))) return e;
-  const int L = c->nlev, nc = c->ncol;
-  hipLaunchKernelGGL(k_inf_layer1, dim3(nblk(n)), dim3(kBlock), 0, c->stream, x, s.wb, s.w + OFF_B1, s.a1h, L, nc,
-                     s.nb9, (const float *)s.st);
-  const size_t waves = (n + 16 * kInfTiles - 1) / (16 * kInfTiles);
-  hipLaunchKernelGGL(k_inf_layer2_mfma, dim3(nblk(waves, kBlock / 64)), dim3(kBlock), 0, c->stream, s.a1h, s.wb + W1N,
-                     s.w + OFF_B2, s.a2h, L, nc, s.nb9);
-  hipLaunchKernelGGL(k_inf_layer3, dim3(nblk(n)), dim3(kBlock), 0, c->stream, s.a2h, s.wb + W1N + W2N, s.w + OFF_B3,
-                     out, L, nc, s.nb9);
+  return forward_bf16(c, x, s.a1h, s.a2h, out, 1);
+}
+
+// Weight and bias gradients of one layer on matrix cores (k_wgrad_mfma, then the fixed-order sum).
+template <int CA, int CB>
+static hipError_t wgrad_mfma(hyb_ctx *c, const void *dA, const void *act, int nsamp, int CO, int CI, float *grad_w,
+                             float *grad_b) {
+  NNState &s = c->nn;
+  const size_t nchunks = ((size_t)c->ncell * nsamp + 31) / 32;
+  const int nparts = (int)std::min<size_t>(kWgBlocks, (nchunks + 3) / 4);
+  float *bp = s.wpart + (size_t)kWgBlocks * NHT * NVT * 256;
+  hipLaunchKernelGGL((k_wgrad_mfma<CA, CB>), dim3(nparts, NHT), dim3(kBlock), 0, c->stream, dA, act,
+                     (const float *)s.st, s.wpart, bp, c->nlev, c->ncol, nsamp, s.nb9);
+  hipError_t e = hipGetLastError();
+  if (e) return e;
+  hipLaunchKernelGGL(k_wgrad_sum, dim3(nblk(NHT * NVT * 256 + 16)), dim3(kBlock), 0, c->stream, (const float *)s.wpart,
+                     (const float *)bp, nparts, CO, CI, grad_w, grad_b);
   return hipGetLastError();
+}
+
+// Gradients of every parameter into s.g from dL/dy in s.dy, BF16 matrix-core path: activations of
+// forward_bf16 in s.a1 / s.a2 (BF16), the backpropagated fields in s.d2 / s.d1 (BF16 [nsamp][ncell][16]).
+static hipError_t backward_bf16(hyb_ctx *c, const float *x, int nsamp) {
+  NNState &s = c->nn;
+  hipError_t e;
+  const size_t n = (size_t)c->ncell * nsamp;
+  const int L = c->nlev, nc = c->ncol;
+  const uint16_t *a1 = (const uint16_t *)s.a1, *a2 = (const uint16_t *)s.a2;
+  uint16_t *dz2 = (uint16_t *)s.d2, *dz1 = (uint16_t *)s.d1;
+  // layer 3 (16 -> 1): dW3, db3, then dz2 = conv3^T(dy) * (a2 > 0)
+  if ((e = wgrad_mfma<1, C1>(c, s.dy, a2, nsamp, 1, C, s.g + OFF_W3, s.g + OFF_B3))) return e;
+  hipLaunchKernelGGL(k_bwd3_bf16, dim3(nblk(n)), dim3(kBlock), 0, c->stream, (const float *)s.dy, s.wb + W1N + W2N, a2,
+                     dz2, L, nc, nsamp, s.rv9);
+  if ((e = hipGetLastError())) return e;
+  // layer 2 (16 -> 16): dW2, db2, then dz1 = conv2^T(dz2) * (a1 > 0)
+  if ((e = wgrad_mfma<C1, C1>(c, dz2, a1, nsamp, C, C, s.g + OFF_W2, s.g + OFF_B2))) return e;
+  const size_t waves = (n + 16 * kC2Tiles - 1) / (16 * kC2Tiles);
+  hipLaunchKernelGGL((k_conv2_mfma<true>), dim3(nblk(waves, kBlock / 64)), dim3(kBlock), 0, c->stream,
+                     (const uint16_t *)dz2, s.wb + W1N, (const float *)nullptr, a1, dz1, L, nc, nsamp, s.rvh, s.lo_off,
+                     s.lo_list);
+  if ((e = hipGetLastError())) return e;
+  // layer 1 (the input x and the two static fields -> 16)
+  return wgrad_mfma<C1, CIN>(c, dz1, x, nsamp, C, CIN, s.g + OFF_W1, s.g + OFF_B1);
 }
 
 template <int CI, int CO, int CS = 0>
@@ -793,6 +1083,9 @@ static hipError_t ensure_grad_scratch(NNState &s) {
     if ((e = hipMalloc((void **)&s.tmpg, (W2N + C) * 4))) return e;
     if ((e = hipMalloc((void **)&s.lpart, 1024 * 4))) return e;
   }
+  if (!s.wpart) {  // partial weight gradients of the matrix-core path, then the bias partials
+    if ((e = hipMalloc((void **)&s.wpart, (size_t)kWgBlocks * (NHT * NVT * 256 + 16) * 4))) return e;
+  }
   return e;
 }
 
@@ -800,6 +1093,10 @@ static hipError_t ensure_grad_scratch(NNState &s) {
 static hipError_t nn_backward(hyb_ctx *c, const float *x, int nsamp) {
   NNState &s = c->nn;
   hipError_t e;
+  if (!c->p.nn_fp32) {
+    if ((e = ensure_grad_scratch(s))) return e;
+    return backward_bf16(c, x, nsamp);
+  }
   size_t n = (size_t)c->ncell * nsamp;
   dim3 g(nblk(n)), b(kBlock);
   int L = c->nlev, nc = c->ncol;
@@ -830,6 +1127,8 @@ hipError_t nn_loss_grad(hyb_ctx *c, const float *x, const float *target, int nsa
   hipLaunchKernelGGL(k_mse, dim3(nb), dim3(kBlock), 0, c->stream, s.y, target, s.dy, n, s.lpart);
   if ((e = hipGetLastError())) return e;
   if ((e = nn_backward(c, x, nsamp))) return e;
+  hipLaunchKernelGGL(k_scale_f32, dim3(nblk(NPARAM)), dim3(kBlock), 0, c->stream, s.g, NPARAM, (float)(1.0 / (double)n));
+  if ((e = hipGetLastError())) return e;
   if (loss_host) {
     std::vector<float> lp(nb);
     if ((e = hipMemcpyAsync(lp.data(), s.lpart, nb * 4, hipMemcpyDeviceToHost, c->stream))) return e;
@@ -881,10 +1180,11 @@ hipError_t nn_energy_grad(hyb_ctx *c, const float *x, const double *rhat, int ns
     if ((e = hipMalloc((void **)&s.epart, 1024 * 8))) return e;
     part = s.epart;
   }
-  hipLaunchKernelGGL(k_energy, dim3(nb), dim3(kBlock), 0, c->stream, s.y, s.gq, rhat, L0.H, s.dy, ncell, n, scale,
-                     part);
+  hipLaunchKernelGGL(k_energy, dim3(nb), dim3(kBlock), 0, c->stream, s.y, s.gq, rhat, L0.H, s.dy, ncell, n, part);
   if ((e = hipGetLastError())) return e;
   if ((e = nn_backward(c, x, nsamp))) return e;
+  hipLaunchKernelGGL(k_scale_f32, dim3(nblk(NPARAM)), dim3(kBlock), 0, c->stream, s.g, NPARAM, (float)scale);
+  if ((e = hipGetLastError())) return e;
   if (loss_host) {
     std::vector<double> lp(nb);
     if ((e = hipMemcpyAsync(lp.data(), part, nb * 8, hipMemcpyDeviceToHost, c->stream))) return e;
@@ -906,13 +1206,9 @@ hipError_t nn_adam(hyb_ctx *c, float lr) {
   return hipGetLastError();
 }
 
-// The learned coarse correction applied after the two-level cycle z = M(r):
-//   r' = r - S z,  c = Gamma P^T r',  s = rms(c),  d = s P (N(c / s) / H_diag),
-//   z += d  if ||r' - S d|| < ||r'||  (the FP64 residual judges every correction),
-// otherwise z stays the plain cycle's output and the fallback counter scal[2] grows (also when the
-// network output is not finite).  Everything stays on the device; no host synchronisation.
-template <typename Tz>
-hipError_t learned_stage(hyb_ctx *c, const double *r, Tz *z, double *Sz) {
+// Buffers of the stage and of the training pairs: network input / output [ncell], scalars, the
+// correction and its image [ntrace], a cell field in FP64 (allocated on first use).
+hipError_t nn_stage_buffers(hyb_ctx *c) {
   NNState &s = c->nn;
   hipError_t e;
   const size_t n = (size_t)c->ncell, ntr = (size_t)c->ntrace;
@@ -932,6 +1228,65 @@ hipError_t learned_stage(hyb_ctx *c, const double *r, Tz *z, double *Sz) {
     if ((e = hipMalloc((void **)&c->cell64, n * 8))) return e;
     c->bytes += n * 8;
   }
+  return hipSuccess;
+}
+
+// The training pair of a residual r' (in c->t64) whose Gamma P^T r' is in c->cell64:
+// s = rms(Gamma P^T r'), x = Gamma P^T r' / s (FP32), rhat = P^T r' / s; s to the host.
+hipError_t nn_pair_finish(hyb_ctx *c, float *x, double *rhat, double *scale_host) {
+  NNState &s = c->nn;
+  const size_t n = (size_t)c->ncell;
+  const unsigned nb = std::min<unsigned>(1024, nblk(n));
+  double *part = c->partial;
+  hipLaunchKernelGGL((k_sumsq<double>), dim3(nb), dim3(kBlock), 0, c->stream, c->cell64, n, part);
+  hipLaunchKernelGGL(k_sum_into, dim3(1), dim3(64), 0, c->stream, part, (int)nb, s.scal);
+  hipLaunchKernelGGL(k_normalise, dim3(nblk(n)), dim3(kBlock), 0, c->stream, c->cell64, s.scal, x, n);
+  hipError_t e = hipGetLastError();
+  if (e) return e;
+  if ((e = launch_restrict_cells(c, c->t64, rhat, 3))) return e;
+  hipLaunchKernelGGL(k_div_rms, dim3(nblk(n)), dim3(kBlock), 0, c->stream, rhat, s.scal, n);
+  if ((e = hipGetLastError())) return e;
+  double ss = 0.0;
+  if ((e = hipMemcpyAsync(&ss, s.scal, sizeof(double), hipMemcpyDeviceToHost, c->stream))) return e;
+  if ((e = hipStreamSynchronize(c->stream))) return e;
+  *scale_host = std::sqrt(ss / (double)n);
+  return hipSuccess;
+}
+
+// Gathers pairs idx[0..nsamp) of X [npairs][ncell] (FP32) and R (FP64) into the batch buffers.
+hipError_t nn_gather_batch(hyb_ctx *c, const float *X, const double *R, const int32_t *idx, int nsamp) {
+  NNState &s = c->nn;
+  const size_t n = (size_t)c->ncell, need = n * nsamp;
+  hipError_t e;
+  if (s.batch_cap < need) {
+    if (s.xb) (void)hipFree(s.xb), s.xb = nullptr;
+    if (s.rb) (void)hipFree(s.rb), s.rb = nullptr;
+    s.batch_cap = 0;
+    if ((e = hipMalloc((void **)&s.xb, need * 4)) || (e = hipMalloc((void **)&s.rb, need * 8))) return e;
+    c->bytes += need * 12;
+    s.batch_cap = need;
+  }
+  for (int i = 0; i < nsamp; ++i) {
+    if ((e = hipMemcpyAsync(s.xb + (size_t)i * n, X + (size_t)idx[i] * n, n * 4, hipMemcpyDeviceToDevice,
+                            c->stream)) ||
+        (e = hipMemcpyAsync(s.rb + (size_t)i * n, R + (size_t)idx[i] * n, n * 8, hipMemcpyDeviceToDevice,
+                            c->stream)))
+      return e;
+  }
+  return hipSuccess;
+}
+
+// The learned coarse correction applied after the two-level cycle z = M(r):
+//   r' = r - S z,  c = Gamma P^T r',  s = rms(c),  d = s P (N(c / s) / H_diag),
+//   z += d  if ||r' - S d|| < ||r'||  (the FP64 residual judges every correction),
+// otherwise z stays the plain cycle's output and the fallback counter scal[2] grows (also when the
+// network output is not finite).  Everything stays on the device; no host synchronisation.
+template <typename Tz>
+hipError_t learned_stage(hyb_ctx *c, const double *r, Tz *z, double *Sz) {
+  NNState &s = c->nn;
+  hipError_t e;
+  const size_t n = (size_t)c->ncell, ntr = (size_t)c->ntrace;
+  if ((e = nn_stage_buffers(c))) return e;
   int slot = prof_begin(c, F_NN);
   const LevelDev &L0 = c->lv[0];
   if ((e = launch_trace_apply<double, Tz, double>(c, c->S, z, r, c->t64, 1))) return e;
@@ -973,6 +1328,9 @@ void nn_free(hyb_ctx *c) {
   if (s.isbf) (void)hipFree(s.isbf), s.isbf = nullptr;
   if (s.nb9) (void)hipFree(s.nb9), s.nb9 = nullptr;
   if (s.rv9) (void)hipFree(s.rv9), s.rv9 = nullptr;
+  for (int32_t **p : {&s.rvh, &s.lo_off, &s.lo_list})
+    if (*p) (void)hipFree(*p), *p = nullptr;
+  if (s.wpart) (void)hipFree(s.wpart), s.wpart = nullptr;
   if (s.st) (void)hipFree(s.st), s.st = nullptr;
   if (s.layer) (void)hipFree(s.layer), s.layer = nullptr;
   s.st_ready = false;
@@ -983,6 +1341,9 @@ void nn_free(hyb_ctx *c) {
   if (s.sd64) (void)hipFree(s.sd64), s.sd64 = nullptr;
   if (s.gq) (void)hipFree(s.gq), s.gq = nullptr;
   if (s.epart) (void)hipFree(s.epart), s.epart = nullptr;
+  if (s.xb) (void)hipFree(s.xb), s.xb = nullptr;
+  if (s.rb) (void)hipFree(s.rb), s.rb = nullptr;
+  s.batch_cap = 0;
   s.gq_cap = 0;
   s.dbar = 0.0;
   if (c->cell64) (void)hipFree(c->cell64), c->cell64 = nullptr;

@@ -160,19 +160,24 @@ inline int row_ent0(const hyb_ctx *c, bool edges_only) { return edges_only ? c->
 //   y_k = R_k - l_k y_{k-1};  x_k = y_k/u_k - (c_k/u_k) x_{k+1};  out_k = base_k + omega x_k,
 // base = 0 (ZERO), xin, or xin plus the injected coarse correction (ADDC).  The loads of KC levels
 // are issued together before the recurrence runs over them, so a column pays the memory latency
-// once per KC levels; y_k/u_k waits in LDS for the back substitution.
+// once per KC levels; y_k/u_k waits in LDS for the back substitution.  The factors of row k are at
+// k * fcols + fmap[col] (fmap null: k * ncol + col): with fmap the patch of the column, a patch of
+// columns shares one set of factors.
 template <typename T, bool ZERO, bool ADDC>
 __global__ void __launch_bounds__(kColBlock) k_column_solve(const T *__restrict__ R, const T *__restrict__ fac,
                                                             size_t fstride, const T *__restrict__ xin,
                                                             const T *__restrict__ xc, T *__restrict__ xout,
                                                             int nrows, int ncol, int ncolc,
-                                                            const int32_t *__restrict__ parent, T omega) {
+                                                            const int32_t *__restrict__ parent, T omega,
+                                                            const int32_t *__restrict__ fmap, int fcols) {
   constexpr int KC = 8;
   extern __shared__ unsigned char smem_raw[];
   T *wv = reinterpret_cast<T *>(smem_raw);
   const int tid = threadIdx.x, bd = blockDim.x;
   const int col = blockIdx.x * bd + tid;
   if (col >= ncol) return;
+  const int fc = fmap ? fmap[col] : col;
+  const int fcs = fmap ? fcols : ncol;
   T y = 0;
   for (int k0 = 0; k0 < nrows; k0 += KC) {
     T rv[KC], lv[KC], iv[KC];
@@ -180,10 +185,10 @@ __global__ void __launch_bounds__(kColBlock) k_column_solve(const T *__restrict_
     for (int q = 0; q < KC; ++q) {
       int k = k0 + q;
       if (k < nrows) {
-        size_t i = (size_t)k * ncol + col;
+        size_t i = (size_t)k * ncol + col, f = (size_t)k * fcs + fc;
         rv[q] = R[i];
-        lv[q] = fac[i];
-        iv[q] = fac[fstride + i];
+        lv[q] = fac[f];
+        iv[q] = fac[fstride + f];
       }
     }
 #pragma unroll
@@ -204,7 +209,7 @@ __global__ void __launch_bounds__(kColBlock) k_column_solve(const T *__restrict_
       int k = k1 - q;
       if (k >= 0) {
         size_t i = (size_t)k * ncol + col;
-        cv[q] = fac[2 * fstride + i];
+        cv[q] = fac[2 * fstride + (size_t)k * fcs + fc];
         w[q] = wv[(size_t)k * bd + tid];
         bv[q] = 0;
         if (!ZERO) {
@@ -239,6 +244,37 @@ __global__ void k_thomas_factor(const double *__restrict__ S, double *__restrict
     fac[F] = l;
     fac[nz + F] = 1.0 / u;
     fac[2 * nz + F] = c / u;
+    up = u;
+    cprev = c;
+  }
+}
+
+// LU factors of the patch-cached column matrices (setup): the tridiagonal of each 2x2 patch of
+// columns is the mean of its four columns' S^zz (below, diagonal, above per level), factored as in
+// k_thomas_factor; one thread per patch, factors at k * npatch + patch.
+__global__ void k_thomas_factor_patch(const double *__restrict__ S, double *__restrict__ fac, int nlev, int ncol,
+                                      int npatch, const int32_t *__restrict__ children) {
+  const int P = blockIdx.x * blockDim.x + threadIdx.x;
+  if (P >= npatch) return;
+  int ch[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) ch[q] = children[(size_t)q * npatch + P];
+  const size_t nzp = (size_t)(nlev + 1) * npatch;
+  double up = 1.0, cprev = 0.0;
+  for (int k = 0; k <= nlev; ++k) {
+    double a = 0.0, b = 0.0, c = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const size_t F = (size_t)k * ncol + ch[q];
+      a += S[s_idx(F, 1)], b += S[s_idx(F, 0)], c += S[s_idx(F, 2)];
+    }
+    a *= 0.25, b *= 0.25, c *= 0.25;
+    const double l = (k == 0) ? 0.0 : a / up;
+    const double u = b - l * cprev;
+    const size_t f = (size_t)k * npatch + P;
+    fac[f] = l;
+    fac[nzp + f] = 1.0 / u;
+    fac[2 * nzp + f] = c / u;
     up = u;
     cprev = c;
   }
@@ -300,32 +336,6 @@ __global__ void __launch_bounds__(kRowBlock) k_prolong(const T *__restrict__ dpi
   }
 }
 
-// Block-Jacobi sweep of the pressure multigrid (Sec. 2.3),
-//   x_out = x_in + omega H_z^-1 (b - H x_in),  H_z = the column (tridiagonal) part of H,
-// in two launches: the 7-point residual (one thread per cell) and the column solve with the LU
-// factors of H_z computed at setup (one column per lane).  ADDC: x_in is the fine iterate plus
-// the injected coarse correction (prolongation fused into the first post-smoothing sweep).
-template <typename T, bool ADDC>
-__global__ void k_mg_residual(const T *__restrict__ H, const T *__restrict__ b, const T *__restrict__ xin,
-                              const T *__restrict__ xc, T *__restrict__ r, int nlev, int ncol, int ncolc,
-                              const int32_t *__restrict__ nbr, const int32_t *__restrict__ parent) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  size_t n = (size_t)nlev * ncol;
-  if (c >= (int)n) return;
-  int k = c / ncol, col = c - k * ncol;
-  auto X = [&](int kk, int cc) -> T {
-    T v = xin[(size_t)kk * ncol + cc];
-    if (ADDC) v += xc[(size_t)kk * ncolc + parent[cc]];
-    return v;
-  };
-  T hx = H[c] * X(k, col);
-#pragma unroll
-  for (int f = 0; f < 4; ++f) hx += H[(1 + f) * n + c] * X(k, nbr[(size_t)f * ncol + col]);
-  if (k > 0) hx += H[5 * n + c] * X(k - 1, col);
-  if (k < nlev - 1) hx += H[6 * n + c] * X(k + 1, col);
-  r[c] = b[c] - hx;
-}
-
 // LU factors of H_z per column (setup): a = coupling below, b = diagonal, c = coupling above.
 __global__ void k_mg_factor(const double *__restrict__ H, double *__restrict__ fac, int nlev, int ncol) {
   int col = blockIdx.x * blockDim.x + threadIdx.x;
@@ -345,16 +355,28 @@ __global__ void k_mg_factor(const double *__restrict__ H, double *__restrict__ f
   }
 }
 
-// Coarse right-hand side b_c = R r: sum of the fine residual r = b - H x over the four children.
+// Coarse right-hand side b_c = R (b - H x) (Sec. 2.3): the 7-point residual of the four children of a
+// coarse cell, summed without going through memory; one thread per coarse cell.
 template <typename T>
-__global__ void k_mg_restrict_sum(const T *__restrict__ r, T *__restrict__ bc, int nlev, int ncolf, int ncolc,
-                                  const int32_t *__restrict__ children) {
-  int cc = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_mg_restrict_residual(const T *__restrict__ H, const T *__restrict__ b, const T *__restrict__ x,
+                                       T *__restrict__ bc, int nlev, int ncolf, int ncolc,
+                                       const int32_t *__restrict__ children, const int32_t *__restrict__ nbr) {
+  const int cc = blockIdx.x * blockDim.x + threadIdx.x;
   if (cc >= nlev * ncolc) return;
-  int k = cc / ncolc, P = cc - k * ncolc;
+  const int k = cc / ncolc, P = cc - k * ncolc;
+  const size_t n = (size_t)nlev * ncolf;
   T s = 0;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) s += r[(size_t)k * ncolf + children[(size_t)q * ncolc + P]];
+  for (int q = 0; q < 4; ++q) {
+    const int col = children[(size_t)q * ncolc + P];
+    const size_t c = (size_t)k * ncolf + col;
+    T hx = H[c] * x[c];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) hx += H[(1 + f) * n + c] * x[(size_t)k * ncolf + nbr[(size_t)f * ncolf + col]];
+    if (k > 0) hx += H[5 * n + c] * x[c - ncolf];
+    if (k < nlev - 1) hx += H[6 * n + c] * x[c + ncolf];
+    s += b[c] - hx;
+  }
   bc[cc] = s;
 }
 
@@ -393,7 +415,11 @@ const float *pick<float>(const double *, const float *f) {
 template <typename T>
 hipError_t line_smooth(hyb_ctx *c, const T *S, const T *B, const T *lin, T *lout, bool zero) {
   const LevelDev &L0 = c->lv[0];
-  const T *fac = pick<T>(c->zfac, c->zfacf);
+  const bool patch = c->p.smoother_patch != 0;
+  const T *fac = patch ? pick<T>(c->zfacp, c->zfacpf) : pick<T>(c->zfac, c->zfacf);
+  const size_t fstride = patch ? (size_t)(c->nlev + 1) * c->lv[1].ncol : (size_t)c->nz;
+  const int32_t *fmap = patch ? L0.parent : nullptr;
+  const int fcols = patch ? c->lv[1].ncol : c->ncol;
   T *R = (T *)c->tR;
   T om = (T)c->p.omega;
   size_t ntr = (size_t)c->ntrace, nz = (size_t)c->nz;
@@ -412,12 +438,12 @@ hipError_t line_smooth(hyb_ctx *c, const T *S, const T *B, const T *lin, T *lout
   slot = prof_begin(c, F_THOMAS);
   if (zero)
     hipLaunchKernelGGL((k_column_solve<T, true, false>), dim3(nblk(c->ncol, kColBlock)), dim3(kColBlock), shm,
-                       c->stream, B, fac, nz, lin, (const T *)nullptr, lout, c->nlev + 1, c->ncol, 1,
-                       (const int32_t *)nullptr, om);
+                       c->stream, B, fac, fstride, lin, (const T *)nullptr, lout, c->nlev + 1, c->ncol, 1,
+                       (const int32_t *)nullptr, om, fmap, fcols);
   else
     hipLaunchKernelGGL((k_column_solve<T, false, false>), dim3(nblk(c->ncol, kColBlock)), dim3(kColBlock), shm,
-                       c->stream, (const T *)R, fac, nz, lin, (const T *)nullptr, lout, c->nlev + 1, c->ncol, 1,
-                       (const int32_t *)nullptr, om);
+                       c->stream, (const T *)R, fac, fstride, lin, (const T *)nullptr, lout, c->nlev + 1, c->ncol, 1,
+                       (const int32_t *)nullptr, om, fmap, fcols);
   prof_end(c, F_THOMAS, slot);
   return hipGetLastError();
 }
@@ -488,9 +514,8 @@ __global__ void __launch_bounds__(kBlock) k_mg_sweep_pcr(const T *__restrict__ H
 
 // One block-Jacobi sweep of the pressure multigrid on a large level, fused into one pass up and down
 // every column (one column per lane, 64 consecutive columns per wavefront, so every [k][col] access
-// is coalesced): x_out = base + omega H_z^-1 (b - H X), with X = xin (MODE 1), xin plus the injected
-// coarse correction xc[parent] (MODE 2), or, for a Chebyshev step, base = X + c1 (X - xprev) (MODE 3;
-// a null xprev is the zero vector); base = X otherwise.  On the way up each level's 7-point residual
+// is coalesced): x_out = base + omega H_z^-1 (b - H X), with X = xin and base = X (MODE 1), or, for a
+// Chebyshev step, base = X + c1 (X - xprev) (MODE 3; a null xprev is the zero vector).  On the way up each level's 7-point residual
 // is formed from X of the column (kept in registers) and of its four neighbours and fed straight into
 // the forward elimination with the LU factors of H_z; y_k / u_k waits in LDS for the back
 // substitution on the way down, which reloads X for the base.  The loads of KC levels are issued
@@ -498,32 +523,22 @@ __global__ void __launch_bounds__(kBlock) k_mg_sweep_pcr(const T *__restrict__ H
 // (the residual no longer goes through memory) with the same arithmetic in the same order.
 template <typename T, int MODE, int KC>
 __global__ void __launch_bounds__(kColBlock) k_mg_sweep_col(const T *__restrict__ H, const T *__restrict__ b,
-                                                            const T *__restrict__ xin, const T *__restrict__ xc,
-                                                            const T *__restrict__ fac, T *__restrict__ xout,
-                                                            int nlev, int ncol, int ncolc,
-                                                            const int32_t *__restrict__ nbr,
-                                                            const int32_t *__restrict__ parent, T omega,
+                                                            const T *__restrict__ xin, const T *__restrict__ fac,
+                                                            T *__restrict__ xout, int nlev, int ncol,
+                                                            const int32_t *__restrict__ nbr, T omega,
                                                             const T *__restrict__ xprev, T c1) {
   extern __shared__ unsigned char smem_raw[];
   T *wv = reinterpret_cast<T *>(smem_raw);
   const int tid = threadIdx.x, bd = blockDim.x;
   const int col = blockIdx.x * bd + tid;
   if (col >= ncol) return;
+  static_assert(MODE == 1 || MODE == 3, "plain and Chebyshev sweeps");
   const size_t n = (size_t)nlev * ncol;
-  int nb[4], pn[4] = {0, 0, 0, 0}, pc = 0;
+  int nb[4];
 #pragma unroll
   for (int f = 0; f < 4; ++f) nb[f] = nbr[(size_t)f * ncol + col];
-  if (MODE == 2) {
-    pc = parent[col];
-#pragma unroll
-    for (int f = 0; f < 4; ++f) pn[f] = parent[nb[f]];
-  }
-  auto X = [&](int k, int cc, int pcc) -> T {
-    T v = xin[(size_t)k * ncol + cc];
-    if (MODE == 2) v += xc[(size_t)k * ncolc + pcc];
-    return v;
-  };
-  T xdn = 0, x0 = X(0, col, pc), y = 0;
+  auto X = [&](int k, int cc) -> T { return xin[(size_t)k * ncol + cc]; };
+  T xdn = 0, x0 = X(0, col), y = 0;
   for (int k0 = 0; k0 < nlev; k0 += KC) {
     T hv[KC][7], bv[KC], xn[KC][4], xu[KC], lv[KC], iv[KC];
 #pragma unroll
@@ -537,8 +552,8 @@ __global__ void __launch_bounds__(kColBlock) k_mg_sweep_col(const T *__restrict_
         hv[q][6] = k < nlev - 1 ? H[6 * n + c] : T(0);
         bv[q] = b[c];
 #pragma unroll
-        for (int f = 0; f < 4; ++f) xn[q][f] = X(k, nb[f], pn[f]);
-        xu[q] = k < nlev - 1 ? X(k + 1, col, pc) : T(0);
+        for (int f = 0; f < 4; ++f) xn[q][f] = X(k, nb[f]);
+        xu[q] = k < nlev - 1 ? X(k + 1, col) : T(0);
         lv[q] = fac[c];
         iv[q] = fac[n + c];
       }
@@ -570,7 +585,7 @@ __global__ void __launch_bounds__(kColBlock) k_mg_sweep_col(const T *__restrict_
         const size_t c = (size_t)k * ncol + col;
         cv[q] = fac[2 * n + c];
         w[q] = wv[(size_t)k * bd + tid];
-        base[q] = X(k, col, pc);
+        base[q] = X(k, col);
         if (MODE == 3) base[q] += c1 * (base[q] - (xprev ? xprev[c] : T(0)));
       }
     }
@@ -618,16 +633,23 @@ hipError_t mg_smooth(hyb_ctx *c, int l, const T *b, const T *xin, const T *xc, T
                          Lv.nbr, Lv.parent, om, xprev, c1);
   } else if (mode == 0) {
     hipLaunchKernelGGL((k_column_solve<T, true, false>), gc, bc, shm, c->stream, b, fac, n, xin, xc, xout, c->nlev,
-                       Lv.ncol, ncolc, Lv.parent, om);
+                       Lv.ncol, ncolc, Lv.parent, om, (const int32_t *)nullptr, 0);
   } else if (mode == 1) {
-    hipLaunchKernelGGL((k_mg_sweep_col<T, 1, kMgColKC>), gc, bc, shm, c->stream, H, b, xin, xc, fac, xout, c->nlev,
-                       Lv.ncol, ncolc, Lv.nbr, Lv.parent, om, xprev, c1);
+    hipLaunchKernelGGL((k_mg_sweep_col<T, 1, kMgColKC>), gc, bc, shm, c->stream, H, b, xin, fac, xout, c->nlev,
+                       Lv.ncol, Lv.nbr, om, xprev, c1);
   } else if (mode == 3) {
-    hipLaunchKernelGGL((k_mg_sweep_col<T, 3, kMgColKC>), gc, bc, shm, c->stream, H, b, xin, xc, fac, xout, c->nlev,
-                       Lv.ncol, ncolc, Lv.nbr, Lv.parent, om, xprev, c1);
+    hipLaunchKernelGGL((k_mg_sweep_col<T, 3, kMgColKC>), gc, bc, shm, c->stream, H, b, xin, fac, xout, c->nlev,
+                       Lv.ncol, Lv.nbr, om, xprev, c1);
   } else {
-    hipLaunchKernelGGL((k_mg_sweep_col<T, 2, kMgColKC>), gc, bc, shm, c->stream, H, b, xin, xc, fac, xout, c->nlev,
-                       Lv.ncol, ncolc, Lv.nbr, Lv.parent, om, xprev, c1);
+    // the coarse correction is injected into xin in place first (its caller drops xin after this
+    // sweep): one streaming pass, then the plain sweep, which is cheaper than gathering the
+    // correction for the column and its four neighbours at every level inside the sweep (65536
+    // columns: 121 us fused)
+    T *xw = const_cast<T *>(xin);
+    hipLaunchKernelGGL((k_mg_prolong_add<T>), dim3(nblk(n)), dim3(kBlock), 0, c->stream, xw, xc, c->nlev, Lv.ncol,
+                       ncolc, Lv.parent);
+    hipLaunchKernelGGL((k_mg_sweep_col<T, 1, kMgColKC>), gc, bc, shm, c->stream, H, b, (const T *)xw, fac, xout,
+                       c->nlev, Lv.ncol, Lv.nbr, om, xprev, c1);
   }
   prof_end(c, F_MG_SMOOTH, slot);
   return hipGetLastError();
@@ -678,10 +700,8 @@ hipError_t vcycle(hyb_ctx *c, int l) {
   LevelDev &Lc = c->lv[l + 1];
   const T *H = pick<T>(Lv.H, Lv.Hf);
   int slot = prof_begin(c, F_RESTRICT);
-  hipLaunchKernelGGL((k_mg_residual<T, false>), dim3(nblk(n)), dim3(kBlock), 0, c->stream, H, b, (const T *)Lv.x,
-                     (const T *)nullptr, (T *)Lv.r, c->nlev, Lv.ncol, 1, Lv.nbr, (const int32_t *)nullptr);
-  hipLaunchKernelGGL((k_mg_restrict_sum<T>), dim3(nblk((size_t)c->nlev * Lc.ncol)), dim3(kBlock), 0, c->stream,
-                     (const T *)Lv.r, (T *)Lc.b, c->nlev, Lv.ncol, Lc.ncol, Lc.children);
+  hipLaunchKernelGGL((k_mg_restrict_residual<T>), dim3(nblk((size_t)c->nlev * Lc.ncol)), dim3(kBlock), 0, c->stream,
+                     H, b, (const T *)Lv.x, (T *)Lc.b, c->nlev, Lv.ncol, Lc.ncol, Lc.children, Lv.nbr);
   prof_end(c, F_RESTRICT, slot);
   HYB_TRY(hipGetLastError());
   HYB_TRY(vcycle<T>(c, l + 1));
@@ -951,9 +971,8 @@ hipError_t configure_kernels(int nlev) {
       (const void *)k_column_solve<double, true, false>, (const void *)k_column_solve<double, false, false>,
       (const void *)k_column_solve<double, false, true>, (const void *)k_column_solve<float, true, false>,
       (const void *)k_column_solve<float, false, false>, (const void *)k_column_solve<float, false, true>,
-      (const void *)k_mg_sweep_col<double, 1, kMgColKC>, (const void *)k_mg_sweep_col<double, 2, kMgColKC>,
-      (const void *)k_mg_sweep_col<double, 3, kMgColKC>, (const void *)k_mg_sweep_col<float, 1, kMgColKC>,
-      (const void *)k_mg_sweep_col<float, 2, kMgColKC>, (const void *)k_mg_sweep_col<float, 3, kMgColKC>};
+      (const void *)k_mg_sweep_col<double, 1, kMgColKC>, (const void *)k_mg_sweep_col<double, 3, kMgColKC>,
+      (const void *)k_mg_sweep_col<float, 1, kMgColKC>, (const void *)k_mg_sweep_col<float, 3, kMgColKC>};
   for (const void *f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, need);
     if (e != hipSuccess) return e;
@@ -971,6 +990,11 @@ hipError_t launch_mg_factor(hyb_ctx *c, int l) {
 hipError_t launch_thomas_factor(hyb_ctx *c) {
   hipLaunchKernelGGL(k_thomas_factor, dim3(nblk(c->ncol, kColBlock)), dim3(kColBlock), 0, c->stream, c->S, c->zfac,
                      c->nlev, c->ncol, (size_t)c->nz, (size_t)c->ntrace);
+  if (c->zfacp) {
+    const int np = c->lv[1].ncol;
+    hipLaunchKernelGGL(k_thomas_factor_patch, dim3(nblk(np, kColBlock)), dim3(kColBlock), 0, c->stream, c->S, c->zfacp,
+                       c->nlev, c->ncol, np, c->lv[1].children);
+  }
   return hipGetLastError();
 }
 

@@ -7,8 +7,9 @@ and rhat = P^T r' / s.  Training minimises the error energy that the stage's cor
 d = s P (N(x) / H_KK) leaves, through the library's energy loss q^T G q - 2 q^T rhat with
 q = N(x) / H_KK and G = P^T S P: no solve with S is needed (see include/hyb.h).
 
-The cycle, S, the restrictions and every network pass (forward, backward, Adam) run in libhyb.so;
-torch only holds the vectors and does the vector updates between calls.
+The cycle, S, the restrictions, the residual update and normalisation of a pair
+(hyb_nn_cycle_pair), the gathering of a mini-batch and every network pass (forward, backward, Adam)
+run in libhyb.so; torch only holds the vectors.
 """
 
 from __future__ import annotations
@@ -54,49 +55,69 @@ def init_params(channels=16, seed=0):
 
 def generate_pairs(solver, rhs_list, steps=8):
     """rhs_list: device FP64 trace right-hand sides.  Returns (X FP32, Rhat FP64), both
-    [npairs][ncell] on the device."""
+    [npairs][ncell] on the device; each right-hand side gives up to ``steps`` pairs
+    (hyb_nn_cycle_pair: the cycle step, the residual update and the normalisation run in the
+    library)."""
     import torch
 
-    n, nc = solver.ntrace, solver.ncell
     X, R = [], []
-    z = torch.empty(n, dtype=torch.float64, device="cuda")
-    sz = torch.empty_like(z)
-    cells = torch.empty(nc, dtype=torch.float64, device="cuda")
-    pt = torch.empty_like(cells)
     for b in rhs_list:
         r = b.clone()
         for _ in range(steps):
-            solver.precondition(r, z)
-            solver.trace_apply(z, sz)
-            r -= sz
-            solver.restrict(r, cells, 0)
-            s = torch.sqrt(torch.mean(cells * cells))
-            if not torch.isfinite(s) or float(s) == 0.0:
+            x = torch.empty(solver.ncell, dtype=torch.float32, device="cuda")
+            rh = torch.empty(solver.ncell, dtype=torch.float64, device="cuda")
+            if solver.nn_cycle_pair(r, x, rh) is None:
                 break
-            solver.restrict(r, pt, 3)
-            X.append((cells / s).float())
-            R.append(pt / s)
+            X.append(x)
+            R.append(rh)
     return torch.stack(X), torch.stack(R)
 
 
 def train(solver, X, R, steps=1000, batch=8, lr=2e-3, seed=0, log=None):
-    """Adam on the energy loss over random mini-batches of pairs; returns the loss history."""
-    import torch
-
-    g = torch.Generator(device="cpu").manual_seed(seed)
+    """Adam on the energy loss over random mini-batches of pairs (gathered inside the library);
+    returns the loss history."""
+    rng = np.random.default_rng(seed)
     npairs = X.shape[0]
-    xb = torch.empty((batch, X.shape[1]), dtype=torch.float32, device="cuda")
-    rb = torch.empty((batch, R.shape[1]), dtype=torch.float64, device="cuda")
     hist = []
     for it in range(steps):
-        idx = torch.randint(0, npairs, (batch,), generator=g).cuda()
-        torch.index_select(X, 0, idx, out=xb)
-        torch.index_select(R, 0, idx, out=rb)
-        loss = solver.nn_energy_train_step(xb, rb, batch, lr)
+        loss = solver.nn_energy_train_step_pairs(X, R, rng.integers(0, npairs, batch), lr)
         hist.append(loss)
         if log and (it % 250 == 0 or it == steps - 1):
             log(f"train step {it}: energy loss {loss:.4e}")
     return hist
+
+
+def train_streaming(solver, next_rhs, npairs=4096, pool=256, steps_per_rhs=8, batch=8, lr=2e-3, updates=1000,
+                    seed=0, log=None):
+    """Training on pairs generated on the fly, for meshes where all pairs do not fit in memory:
+    a pool of ``pool`` pairs is refilled from new right-hand sides (``next_rhs()``, each giving
+    ``steps_per_rhs`` pairs of the cycle iteration) until ``npairs`` pairs have been made, and
+    ``updates`` Adam steps on random mini-batches of the pool are spread over the refills.
+    Returns (loss history, pairs made)."""
+    import torch
+
+    rng = np.random.default_rng(seed)
+    nc = solver.ncell
+    X = torch.empty((pool, nc), dtype=torch.float32, device="cuda")
+    R = torch.empty((pool, nc), dtype=torch.float64, device="cuda")
+    made, filled, slot, done, hist = 0, 0, 0, 0, []
+    while made < npairs:
+        r = next_rhs().clone()
+        for _ in range(steps_per_rhs):
+            if made >= npairs or solver.nn_cycle_pair(r, X[slot], R[slot]) is None:
+                break
+            made += 1
+            filled = min(pool, filled + 1)
+            slot = (slot + 1) % pool
+        if filled < min(pool, npairs):
+            continue
+        target = updates * made // npairs
+        while done < target:
+            hist.append(solver.nn_energy_train_step_pairs(X[:filled], R[:filled], rng.integers(0, filled, batch), lr))
+            if log and (done % 250 == 0 or done == updates - 1):
+                log(f"train step {done} ({made} pairs made): energy loss {hist[-1]:.4e}")
+            done += 1
+    return hist, made
 
 
 def save(path, weights, meta):

@@ -42,6 +42,11 @@ def _prepare(outdir: str) -> list[str]:
         text = text.replace("typedef float nn_f32x4 __attribute__((ext_vector_type(4)));", "typedef emu_f32x4 nn_f32x4;")
         text = text.replace("typedef short nn_bf16x4 __attribute__((ext_vector_type(4)));",
                             "typedef emu_bf16x4 nn_bf16x4;")
+        text = text.replace("typedef __bf16 nn_bf16x8 __attribute__((ext_vector_type(8)));",
+                            "typedef emu_s16x8 nn_bf16x8;")
+        text = text.replace("typedef unsigned int nn_u32x4 __attribute__((ext_vector_type(4)));",
+                            "typedef emu_u32x4 nn_u32x4;")
+        text = text.replace("typedef short nn_s16x8 __attribute__((ext_vector_type(8)));", "typedef emu_s16x8 nn_s16x8;")
         dst = os.path.join(outdir, name if name.endswith(".h") else name.replace(".hip", ".cpp"))
         with open(dst, "w") as f:
             f.write(text)

@@ -168,8 +168,40 @@ inline emu_f32x4 emu_mfma_f32_16x16x16bf16_1k(emu_bf16x4 a, emu_bf16x4 b, emu_f3
   emu::wave_barrier();
   return c;
 }
+// bf16 16x16x32 (gfx950): a[j] = A[l%16][8(l/16)+j], b[j] = B[8(l/16)+j][l%16]; d as above
+struct emu_s16x8 {
+  short v[8];
+  short &operator[](int i) { return v[i]; }
+  short operator[](int i) const { return v[i]; }
+};
+struct emu_u32x4 {
+  uint32_t v[4];
+  uint32_t &operator[](int i) { return v[i]; }
+  uint32_t operator[](int i) const { return v[i]; }
+};
+inline emu_f32x4 emu_mfma_f32_16x16x32_bf16(emu_s16x8 a, emu_s16x8 b, emu_f32x4 c, int, int, int) {
+  const unsigned tid = emu::cur_tid(), lane = tid % 64, base = tid - lane;
+  short ab[16];
+  for (int j = 0; j < 8; ++j) ab[j] = a[j], ab[8 + j] = b[j];
+  std::memcpy(emu::xchg(tid), ab, 32);
+  emu::wave_barrier();
+  for (int j = 0; j < 4; ++j) {
+    const unsigned row = 4 * (lane / 16) + j, col = lane % 16;
+    float acc = 0.f;
+    for (unsigned k = 0; k < 32; ++k) {
+      short A[16], B[16];
+      std::memcpy(A, emu::xchg(base + (k / 8) * 16 + row), 32);
+      std::memcpy(B, emu::xchg(base + (k / 8) * 16 + col), 32);
+      acc += emu_bf16_to_f32(A[k % 8]) * emu_bf16_to_f32(B[8 + k % 8]);
+    }
+    c[j] += acc;
+  }
+  emu::wave_barrier();
+  return c;
+}
 #define __builtin_amdgcn_mfma_f32_16x16x4f32 emu_mfma_f32_16x16x4f32
 #define __builtin_amdgcn_mfma_f32_16x16x16bf16_1k emu_mfma_f32_16x16x16bf16_1k
+#define __builtin_amdgcn_mfma_f32_16x16x32_bf16 emu_mfma_f32_16x16x32_bf16
 
 inline float __uint_as_float(uint32_t u) { float f; std::memcpy(&f, &u, 4); return f; }
 inline uint32_t __float_as_uint(float f) { uint32_t u; std::memcpy(&u, &f, 4); return u; }

@@ -151,6 +151,23 @@ def solver_sequence(lib):
     c.call("hyb_precondition", P(b), P(z))
     rc, info, lam = c.solve(b, 1e-8)
     check(rc == 0 and c.residual(b, lam) <= 1.01e-8, f"mixed FGMRES: {info.iters} iterations")
+    # LineSmooth with the column matrices cached per 2x2 patch (the parent coarse column), against
+    # the oracle's variant, in both precisions
+    # (100 eps cond(H) as in the parity tests; the variant moves z by ~4e-7 on this machine)
+    orc = OracleProblem(prob, with_mixed=False, smoother_patch=True)
+    c.set(precision=N.PREC_FP64, restart=30, smoother_patch=1)
+    c.call("hyb_precondition", P(b), P(z))
+    zref = orc.pc(b)
+    ez = float(np.abs(z - zref).max() / np.abs(zref).max())
+    moved = float(np.abs(OracleProblem(prob, with_mixed=False).pc(b) - zref).max() / np.abs(zref).max())
+    rc, info, lam = c.solve(b, 1e-10)
+    check(ez <= 1.5e-9 and moved > 100 * ez and rc == 0 and c.residual(b, lam) <= 1.01e-10,
+          f"patch-cached LineSmooth: preconditioner vs oracle {ez:.1e} (variant moves it {moved:.1e}), "
+          f"FGMRES {info.iters} iterations")
+    c.set(precision=N.PREC_MIXED)
+    rc, info, lam = c.solve(b, 1e-8)
+    check(rc == 0 and c.residual(b, lam) <= 1.01e-8, f"patch-cached LineSmooth, mixed: {info.iters} iterations")
+    c.set(precision=N.PREC_MIXED, smoother_patch=0)
     c.call("hyb_profile", 1)
     c.solve(b, 1e-6)
     n, ms = ctypes.c_int64(), ctypes.c_double()
@@ -172,6 +189,9 @@ def solver_sequence(lib):
     res = c.residual(b, lam)
     check(info.iters == 36 and res <= 1e-12, f"fp64 FGMRES(40), 36 steps without a tolerance: residual {res:.1e}")
     c.set(restart=30)
+    rc, info, lam = c.solve(b, 1e-20, maxit=3000)
+    check(rc == N.HYB_STAGNATED and info.iters < 3000 and c.residual(b, lam) <= 1e-13,
+          f"a tolerance below the rounding floor ends as stagnated after {info.iters} iterations")
     # the allocation-free solve (static reduction scratch) gives hyb_solve's iterate, also on a
     # second, smaller context after it
     for prec in (N.PREC_FP64, N.PREC_MIXED):
@@ -231,30 +251,71 @@ def network_sequence(lib):
         c.call("hyb_nn_energy_grad", P(xe), P(re), ns, ctypes.byref(el), P(ge))
         c.call("hyb_nn_energy_train_step", P(xe), P(re), ns, ctypes.c_float(1e-3), None)
     check(np.isfinite(el.value) and np.all(np.isfinite(ge)), f"energy loss and gradient: {el.value:.3e}")
+    # training pairs in the library: the cycle step, residual update and normalisation against the
+    # same steps through the separate calls; a gathered step against the step on the copied batch
+    _, _, bp = c.rhs(4)
+    r_lib, r_ref = bp.copy(), bp.copy()
+    xp, rp = np.empty((2, nc), np.float32), np.empty((2, nc))
+    zz, sz, gc, pt = np.empty(c.ntrace), np.empty(c.ntrace), np.empty(nc), np.empty(nc)
+    ok = True
+    for k in range(2):
+        sc = ctypes.c_double()
+        c.call("hyb_nn_cycle_pair", P(r_lib), P(xp[k]), P(rp[k]), ctypes.byref(sc))
+        c.call("hyb_precondition", P(r_ref), P(zz))
+        c.call("hyb_trace_apply", P(zz), P(sz))
+        r_ref -= sz
+        c.call("hyb_restrict", P(r_ref), P(gc), 0)
+        c.call("hyb_restrict", P(r_ref), P(pt), 3)
+        s_ref = np.sqrt(np.mean(gc * gc))
+        ok &= abs(sc.value - s_ref) <= 1e-12 * s_ref and np.abs(r_lib - r_ref).max() <= 1e-12 * np.abs(r_ref).max()
+        ok &= np.abs(xp[k] - (gc / s_ref).astype(np.float32)).max() <= 1e-6 * np.abs(xp[k]).max()
+        ok &= np.abs(rp[k] - pt / s_ref).max() <= 1e-12 * np.abs(rp[k]).max()
+    check(ok, "hyb_nn_cycle_pair = precondition, S z, residual, Gamma P^T r / s and P^T r / s")
+    zero, xz, rz = np.zeros(c.ntrace), np.empty(nc, np.float32), np.empty(nc)
+    check(c.call("hyb_nn_cycle_pair", P(zero), P(xz), P(rz), None) == N.HYB_BREAKDOWN,
+          "a vanished residual gives HYB_BREAKDOWN")
     c.call("hyb_nn_set_weights", P(w), w.size)
-    loss = ctypes.c_float()
-    # a training step as the very first network call (activation buffers not yet allocated)
-    x3 = rng.standard_normal((3, nc)).astype(np.float32)
-    t3 = rng.standard_normal((3, nc)).astype(np.float32)
-    c.call("hyb_nn_train_step", P(x3), P(t3), 3, ctypes.c_float(1e-3), ctypes.byref(loss))
-    check(np.isfinite(loss.value), f"first call is a training step (batch 3): loss {loss.value:.4f}")
-    g = np.empty(w.size, np.float32)
-    c.call("hyb_nn_loss_grad", P(x3[:2].copy()), P(t3[:2].copy()), 2, ctypes.byref(loss), P(g))
-    x5 = rng.standard_normal((5, nc)).astype(np.float32)  # larger batch: buffers grow
-    y5 = np.empty((5, nc), np.float32)
-    c.call("hyb_nn_forward", P(x5), P(y5), 5)
-    c.call("hyb_nn_train_step", P(x5), P(x5), 5, ctypes.c_float(1e-3), None)
-    x1 = x5[:1].copy()
-    y1 = np.empty((1, nc), np.float32)
-    c.call("hyb_nn_forward", P(x1), P(y1), 1)
-    wc = np.empty(w.size, np.float32)
-    c.call("hyb_nn_get_weights", P(wc), wc.size)
-    W, bias = learned.unpack(wc)
-    st = onn.static_inputs(prob.dx * prob.dy * np.repeat(np.diff(prob.z), prob.ncol), prob.z, prob.ncol)
-    ref = onn.forward(x1[0].astype(np.float64), [onn.bf16_round(a) for a in W], bias,
-                      onn.neighbour_table(prob.nx, prob.ny), prob.nlev, static=st)[0]
-    err = float(np.abs(y1[0] - ref).max() / np.abs(ref).max())
-    check(err <= 1e-5, f"forward after training matches the oracle's formula: {err:.1e}")
+    idx = np.array([1, 0, 1], np.int32)
+    l1, l2 = ctypes.c_double(), ctypes.c_double()
+    c.call("hyb_nn_energy_train_step_pairs", P(xp), P(rp), 2, P(idx), 3, ctypes.c_float(1e-3), ctypes.byref(l1))
+    w1 = np.empty(w.size, np.float32)
+    c.call("hyb_nn_get_weights", P(w1), w1.size)
+    c.call("hyb_nn_set_weights", P(w), w.size)
+    xg, rg = np.ascontiguousarray(xp[idx]), np.ascontiguousarray(rp[idx])
+    c.call("hyb_nn_energy_train_step", P(xg), P(rg), 3, ctypes.c_float(1e-3), ctypes.byref(l2))
+    w2 = np.empty(w.size, np.float32)
+    c.call("hyb_nn_get_weights", P(w2), w2.size)
+    bad_idx = np.array([2], np.int32)
+    check(l1.value == l2.value and np.array_equal(w1, w2)
+          and lib.hyb_nn_energy_train_step_pairs(c.h, P(xp), P(rp), 2, P(bad_idx), 1, ctypes.c_float(1e-3), None) < 0,
+          "gathered training step = step on the copied batch; an index out of range is rejected")
+    for fp32 in (1, 0):  # the FP32 reference passes and the BF16 matrix-core ones
+        c.set(nn_fp32=fp32)
+        c.call("hyb_nn_set_weights", P(w), w.size)
+        loss = ctypes.c_float()
+        # a training step as the very first network call (activation buffers not yet allocated)
+        x3 = rng.standard_normal((3, nc)).astype(np.float32)
+        t3 = rng.standard_normal((3, nc)).astype(np.float32)
+        c.call("hyb_nn_train_step", P(x3), P(t3), 3, ctypes.c_float(1e-3), ctypes.byref(loss))
+        check(np.isfinite(loss.value), f"first call is a training step (batch 3, fp32 {fp32}): loss {loss.value:.4f}")
+        g = np.empty(w.size, np.float32)
+        c.call("hyb_nn_loss_grad", P(x3[:2].copy()), P(t3[:2].copy()), 2, ctypes.byref(loss), P(g))
+        x5 = rng.standard_normal((5, nc)).astype(np.float32)  # larger batch: buffers grow
+        y5 = np.empty((5, nc), np.float32)
+        c.call("hyb_nn_forward", P(x5), P(y5), 5)
+        c.call("hyb_nn_train_step", P(x5), P(x5), 5, ctypes.c_float(1e-3), None)
+        x1 = x5[:1].copy()
+        y1 = np.empty((1, nc), np.float32)
+        c.call("hyb_nn_forward", P(x1), P(y1), 1)
+        wc = np.empty(w.size, np.float32)
+        c.call("hyb_nn_get_weights", P(wc), wc.size)
+        W, bias = learned.unpack(wc)
+        st = onn.static_inputs(prob.dx * prob.dy * np.repeat(np.diff(prob.z), prob.ncol), prob.z, prob.ncol)
+        ref = onn.forward(x1[0].astype(np.float64), [onn.bf16_round(a) for a in W], bias,
+                          onn.neighbour_table(prob.nx, prob.ny), prob.nlev, static=st)[0]
+        err = float(np.abs(y1[0] - ref).max() / np.abs(ref).max())
+        check(err <= (1e-5 if fp32 else 2.0**-6),
+              f"forward after training matches the oracle's formula (fp32 {fp32}): {err:.1e}")
     _, _, b = c.rhs(2)
     for prec in (N.PREC_FP64, N.PREC_MIXED):
         c.set(learned=1, precision=prec)
@@ -371,7 +432,33 @@ def sphere_sequence(lib):
     zref = o.pc(b)
     check(np.abs(z - zref).max() <= 1e-9 * np.abs(zref).max(),
           "sphere: preconditioner (lumped mass without the Coriolis term) against the oracle")
+    # the theta' / rho' elimination and back-substitution against the oracle (in place too)
+    from oracle.elimination import back_substitute, eliminate_rhs
+    from oracle.local import shell_cells, shell_fields, shell_map
 
+    rng = np.random.default_rng(6)
+    L, ncol = prob.nlev, prob.ncol
+    e_ub, e_rho, e_th, e_pi = (rng.standard_normal((6, L, ncol)), rng.standard_normal((L, ncol)),
+                               rng.standard_normal((L + 1, ncol)), rng.standard_normal((L, ncol)))
+    ub_bar, pi_bar = e_ub.copy(), e_pi.copy()
+    c.call("hyb_eliminate", P(ub_bar), P(e_rho), P(e_th), P(pi_bar), P(ub_bar), P(pi_bar))
+    tm = o.mesh
+    U, r0, r1 = shell_cells(tm, prob)
+    cm, fl = shell_map(U, r0, r1), shell_fields(tm, prob)
+    cs = dict(dt=prob.dt, tau_u=prob.tau_u, tau_rho=prob.tau_rho, tau_theta=prob.tau_theta, cp=prob.cp)
+    kk, cc = tm.cell_layer, tm.cell_col
+    rb, rp = eliminate_rhs(cm, True, fl, cs, e_ub.reshape(6, -1).T, e_rho.ravel(), e_th[kk, cc], e_th[kk + 1, cc],
+                           e_pi.ravel())
+    rho_e, th_e = np.empty((L, ncol)), np.empty((2, L, ncol))
+    c.call("hyb_back_substitute", P(e_rho), P(e_th), P(e_ub), P(rho_e), P(th_e))
+    rho_r, th_r = back_substitute(cm, True, fl, cs, e_rho.ravel(), e_th[kk, cc], e_th[kk + 1, cc], e_ub.reshape(6, -1).T)
+    check(np.abs(ub_bar.reshape(6, -1).T - rb).max() <= 1e-12 * np.abs(rb).max()
+          and np.abs(pi_bar.ravel() - rp).max() <= 1e-12 * np.abs(rp).max()
+          and np.abs(rho_e.ravel() - rho_r).max() <= 1e-12 * np.abs(rho_r).max()
+          and np.abs(th_e.reshape(2, -1).T - th_r).max() <= 1e-12 * np.abs(th_r).max(),
+          "sphere: theta' / rho' elimination and back-substitution against the oracle")
+    check(lib.hyb_back_substitute(c.h, P(e_rho), P(e_th), P(e_ub), P(e_ub), P(th_e)) < 0,
+          "back-substitution outputs aliasing an input rejected")
     rc, info, lam = c.solve(b, 1e-10)
     check(rc == 0 and c.residual(b, lam) <= 1.01e-10, f"sphere: fp64 FGMRES {info.iters} iterations")
     u_b, pi = np.empty(6 * c.ncell), np.empty(c.ncell)

@@ -261,6 +261,15 @@ def test_edge_cases():
     say(f"[restart 40] 36 steps: true residual {res4:.1e}")
     assert info4["iters"] == 36 and res4 <= 1e-11
     s.set_params(params_for(prob))
+    # a tolerance below the rounding floor of the residual: the solve stops once two restart cycles
+    # in a row leave the true residual where it was, and says so
+    from paper_2210_11797_amd import HYB_STAGNATED
+
+    lam.zero_()
+    info5 = s.solve(b, lam, rtol=1e-20, maxit=2000)
+    say(f"[stagnation] rtol 1e-20: status {info5['status']} after {info5['iters']} iterations, "
+        f"residual {info5['rel_res']:.1e}")
+    assert info5["status"] == HYB_STAGNATED and info5["iters"] < 2000 and info5["rel_res"] <= 1e-14
     # bad arguments are rejected, not crashed on
     with pytest.raises(RuntimeError):
         s.trace_apply(b, b)
@@ -273,6 +282,53 @@ WIDE = {
     # a coarsest level of 8192 columns: its Chebyshev steps run one lane per column as well
     "wide_coarsest": dict(nx=256, ny=128, nlev=2, dx=5e3, dz=250.0, mg_levels=2, perturb=0.05),
 }
+
+
+PATCH = {
+    "ragged": dict(nx=12, ny=10, nlev=5, dx=7e3, dy=5e3, dz=400.0, mg_levels=2, perturb=0.1),
+    "tiles_stretched": dict(nx=24, ny=20, nlev=12, dx=5e3, ztop=6e3, stretch="quadratic", mg_levels=3,
+                            perturb=0.2, theta_col_perturb=0.05),
+}
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name", list(PATCH))
+@pytest.mark.parametrize("precision", [0, 1])
+def test_precondition_patch_cached_smoother(name, precision):
+    """LineSmooth with the tridiagonal column matrices cached per 2x2 patch (the mean of the
+    patch's S^zz, future work of Sec. 4.2) against the oracle's variant: the preconditioner at
+    100 eps cond(H) (FP64), and the solve (to 1e-14, or its rounding floor below 1e-13) against the
+    direct solution to 1e-10 in both precisions."""
+    import torch
+
+    prob = make_box(**PATCH[name])
+    say(f"[setup] patch-cached smoother {name} precision {precision}")
+    orc = OracleProblem(prob, with_mixed=False, smoother_patch=True)
+    s = make_solver(prob, smoother_patch=1, precision=precision)
+    rng = np.random.default_rng(6)
+    r = rng.standard_normal(orc.mesh.ntrace)
+    ref = orc.pc(r)
+    cond_h = np.linalg.cond(orc.H.toarray())
+    tol = max(1e-12, 100 * np.finfo(float).eps * cond_h)
+    moved = rel_max(OracleProblem(prob, with_mixed=False).pc(r), ref)
+    if precision == 0:
+        z = torch.empty(orc.mesh.ntrace, dtype=torch.float64, device="cuda")
+        s.precondition(dev(r), z)
+        err = rel_max(host(z), ref)
+        say(f"[precondition, patch] {name}: rel err {err:.2e} (tol {tol:.1e}; the variant moves z by {moved:.1e})")
+        assert err <= tol and moved > 10 * tol
+    r_ub, r_pi = make_rhs(prob, 3)
+    ruc, rpc = cells_from_soa(r_ub, r_pi)
+    b = torch.empty(orc.mesh.ntrace, dtype=torch.float64, device="cuda")
+    s.condense(dev(r_ub), dev(r_pi), b)
+    lam_ref = orc.hyb.solve_direct(ruc, rpc)[0]
+    lam = torch.zeros_like(b)
+    info = s.solve(b, lam, rtol=1e-14, maxit=400)
+    err = rel_norm(host(lam), lam_ref)
+    say(f"[solve, patch] {name} precision {precision}: {info['iters']} iterations, residual {info['rel_res']:.1e}, "
+        f"lambda err {err:.1e}")
+    assert info["rel_res"] <= 1e-13 and err <= 1e-10
+    s.close()
 
 
 @pytest.mark.gpu
