@@ -578,75 +578,96 @@ __global__ void __launch_bounds__(kBlock) k_conv2_mfma(const uint16_t *__restric
 }
 
 // Weight gradients on BF16 MFMA: for horizontal tap h = blockIdx.y and the five vertical offsets v,
-//   part[blk][h][v][co][ci] = sum over this workgroup's rows of dA[row][co] * act[tap(row, h, v)][ci]
-// (D = A B with A = dA^T: 16 output channels x 32 rows, B = the tapped activations: 32 rows x 16 input
-// channels), and for h = 0 the bias sums bpart[blk][co] = sum over the rows of dA[row][co].
+//   part[blk][h][v][co][ci] = sum over this workgroup's rows of dA[row][co] * act[tap(row, h, v)][ci],
+// and for h = 0 the bias sums bpart[blk][co] = sum over the rows of dA[row][co].  A wavefront takes
+// chunks of 32 rows (sample, cell): D = A B with A = dA^T (16 output channels x 32 rows) and B = the
+// tapped activations (32 rows x 16 input channels).  Both operands need 8 rows of one channel per
+// lane, so each chunk is loaded with one 16-byte load per lane (lane = row / 2, half the channels)
+// and turned over in the wavefront's own LDS tile ([channel][row], rows padded to 40 so that the
+// operand reads fall on distinct banks).
 // dA: CA = 16 BF16 [sample][cell][16], CA = 1 FP32 [sample][cell] (rounded to BF16 for the product; the
 // bias sum takes it unrounded).  act: CB = 16 BF16 [sample][cell][16]; CB = 3 the network's input, x
 // FP32 [sample][cell] and the static fields st FP32 [2][cell].  Channels beyond CA / CB are zero.
-constexpr int kWgBlocks = 128;
+constexpr int kWgBlocks = 256;
+constexpr int kWgPad = 40;
+
+// LDS written by some lanes of a wavefront and then read by others: the wavefront's LDS accesses are
+// processed in order, so only the compiler must keep the order
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int CA, int CB>
 __global__ void __launch_bounds__(kBlock) k_wgrad_mfma(const void *__restrict__ dA_, const void *__restrict__ act_,
                                                       const float *__restrict__ st, float *__restrict__ part,
                                                       float *__restrict__ bpart, int nlev, int ncol, int nsamp,
                                                       const int32_t *__restrict__ nb9) {
   constexpr int NW = kBlock / 64;
+  __shared__ uint16_t sA[NW][16][kWgPad], sB[NW][16][kWgPad];
   __shared__ float red[NW][NVT][4][64];
-  __shared__ float bred[NW][64];
+  __shared__ float bred[NW][64][8];
   const int h = blockIdx.y;
   const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4, wv = threadIdx.x >> 6;
-  const size_t n = (size_t)nlev * ncol, total = n * nsamp, nchunks = (total + 31) / 32;
-  const size_t nwaves = (size_t)gridDim.x * NW;
+  const int rho = lane >> 1, hf = lane & 1;  // the row this lane loads, and which 8 channels
+  const unsigned n = (unsigned)nlev * (unsigned)ncol, total = n * (unsigned)nsamp;
+  const unsigned nchunks = (total + 31) / 32;
+  const unsigned nwaves = gridDim.x * NW;
+  // rows and channels no lane writes stay zero
+  for (int i = lane; i < 16 * kWgPad; i += 64) (&sA[wv][0][0])[i] = 0, (&sB[wv][0][0])[i] = 0;
+  wave_lds_sync();
   const nn_f32x4 zero = {0.f, 0.f, 0.f, 0.f};
   nn_f32x4 acc[NVT];
 #pragma unroll
   for (int v = 0; v < NVT; ++v) acc[v] = zero;
-  float bsum = 0.f;
-  for (size_t ch = (size_t)blockIdx.x * NW + wv; ch < nchunks; ch += nwaves) {
-    const size_t base = ch * 32 + 8 * q;
-    nn_s16x8 a;
-    size_t soff[8];
-    int kr[8], cnb[8];
+  float bsum[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (unsigned ch = blockIdx.x * NW + wv; ch < nchunks; ch += nwaves) {
+    const unsigned g = ch * 32 + rho;
+    const bool live = g < total;
+    const unsigned gs = live ? g : 0;
+    const unsigned smp = gs / n, cell = gs - smp * n;
+    const int k = (int)(cell / (unsigned)ncol), col = (int)(cell - (unsigned)k * ncol);
+    const size_t soff = (size_t)smp * n;
+    const int c2 = live ? nb9[(size_t)h * ncol + col] : -1;
+    // A: this lane's row, 8 channels, into the tile [co][row]
+    if (CA == 16) {
+      nn_u32x4 u = {0u, 0u, 0u, 0u};
+      if (live) u = *reinterpret_cast<const nn_u32x4 *>(reinterpret_cast<const uint16_t *>(dA_) + (size_t)gs * 16 + 8 * hf);
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const size_t g = base + j;
-      const bool live = g < total;
-      const size_t gs = live ? g : 0;
-      if (CA == 16) {
-        const uint16_t av = live ? reinterpret_cast<const uint16_t *>(dA_)[gs * 16 + r] : (uint16_t)0;
-        bsum += bf2f(av);
-        a[j] = (short)av;
-      } else {
-        const float fv = (live && r == 0) ? reinterpret_cast<const float *>(dA_)[gs] : 0.f;
-        bsum += fv;
-        a[j] = (short)f2bf(fv);
+      for (int i = 0; i < 8; ++i) {
+        const uint16_t hv = (uint16_t)((i & 1) ? (u[i >> 1] >> 16) : (u[i >> 1] & 0xFFFFu));
+        sA[wv][8 * hf + i][rho] = hv;
+        bsum[i] += bf2f(hv);
       }
-      const int smp = (int)(gs / n), cell = (int)(gs - (size_t)smp * n);
-      const int k = cell / ncol, col = cell - k * ncol;
-      soff[j] = (size_t)smp * n;
-      kr[j] = k;
-      cnb[j] = live ? nb9[(size_t)h * ncol + col] : -1;
+    } else if (hf == 0) {
+      const float fv = live ? reinterpret_cast<const float *>(dA_)[gs] : 0.f;
+      sA[wv][0][rho] = f2bf(fv);
+      bsum[0] += fv;
     }
+    wave_lds_sync();
+    const nn_u32x4 a = *reinterpret_cast<const nn_u32x4 *>(&sA[wv][r][8 * q]);
 #pragma unroll
     for (int v = 0; v < NVT; ++v) {
-      nn_s16x8 b;
+      const int kk = k + v - 2;
+      const bool ok = c2 >= 0 && kk >= 0 && kk < nlev;
+      const size_t at = soff + (ok ? (size_t)kk * ncol + c2 : 0);
+      if (CB == 16) {
+        nn_u32x4 u = {0u, 0u, 0u, 0u};
+        if (ok) u = *reinterpret_cast<const nn_u32x4 *>(reinterpret_cast<const uint16_t *>(act_) + at * 16 + 8 * hf);
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int kk = kr[j] + v - 2;
-        const bool ok = cnb[j] >= 0 && kk >= 0 && kk < nlev && r < CB;
-        const size_t c2 = ok ? (size_t)kk * ncol + cnb[j] : 0;
-        uint16_t bv = 0;
-        if (CB == 16) {
-          if (ok) bv = reinterpret_cast<const uint16_t *>(act_)[(soff[j] + c2) * 16 + r];
-        } else {
-          float fv = 0.f;
-          if (ok) fv = r == 0 ? reinterpret_cast<const float *>(act_)[soff[j] + c2] : st[(size_t)(r - 1) * n + c2];
-          bv = f2bf(fv);
-        }
-        b[j] = (short)bv;
+        for (int i = 0; i < 8; ++i)
+          sB[wv][8 * hf + i][rho] = (uint16_t)((i & 1) ? (u[i >> 1] >> 16) : (u[i >> 1] & 0xFFFFu));
+      } else if (hf == 0) {
+        const size_t c2n = at - soff;
+        sB[wv][0][rho] = f2bf(ok ? reinterpret_cast<const float *>(act_)[at] : 0.f);
+        sB[wv][1][rho] = f2bf(ok ? st[c2n] : 0.f);
+        sB[wv][2][rho] = f2bf(ok ? st[(size_t)n + c2n] : 0.f);
       }
-      acc[v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(nn_bf16x8, a), __builtin_bit_cast(nn_bf16x8, b),
-                                                       acc[v], 0, 0, 0);
+      wave_lds_sync();
+      const nn_u32x4 b = *reinterpret_cast<const nn_u32x4 *>(&sB[wv][r][8 * q]);
+      acc[v] = mfma_bf16_32(a, b, acc[v]);
+      wave_lds_sync();  // the tile is rewritten by the next offset
     }
   }
   // the block's waves in a fixed order; lane (r, q) holds entry j of output channel 4 q + j, input r
@@ -654,7 +675,8 @@ __global__ void __launch_bounds__(kBlock) k_wgrad_mfma(const void *__restrict__ 
   for (int v = 0; v < NVT; ++v)
 #pragma unroll
     for (int j = 0; j < 4; ++j) red[wv][v][j][lane] = acc[v][j];
-  bred[wv][lane] = bsum;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) bred[wv][lane][i] = bsum[i];
   __syncthreads();
   float *out = part + ((size_t)blockIdx.x * NHT + h) * (NVT * 256);
   for (int o = threadIdx.x; o < NVT * 256; o += blockDim.x) {
@@ -665,13 +687,12 @@ __global__ void __launch_bounds__(kBlock) k_wgrad_mfma(const void *__restrict__ 
     for (int w = 0; w < NW; ++w) sacc += red[w][v][j][src];
     out[o] = sacc;
   }
-  if (h == 0 && threadIdx.x < 16) {
+  if (h == 0 && threadIdx.x < 16) {  // channel co: half co / 8 of every row, entry co % 8
+    const int co = threadIdx.x, hh = co >> 3, e = co & 7;
     float sacc = 0.f;
-#pragma unroll
     for (int w = 0; w < NW; ++w)
-#pragma unroll
-      for (int qq = 0; qq < 4; ++qq) sacc += bred[w][threadIdx.x + 16 * qq];
-    bpart[(size_t)blockIdx.x * 16 + threadIdx.x] = sacc;
+      for (int rr = 0; rr < 32; ++rr) sacc += bred[w][2 * rr + hh][e];
+    bpart[(size_t)blockIdx.x * 16 + co] = sacc;
   }
 }
 
@@ -1022,6 +1043,7 @@ static hipError_t wgrad_mfma(hyb_ctx *c, const void *dA, const void *act, int ns
                              float *grad_b) {
   NNState &s = c->nn;
   const size_t nchunks = ((size_t)c->ncell * nsamp + 31) / 32;
+  if ((size_t)c->ncell * nsamp + 32 > (size_t)UINT32_MAX) return hipErrorInvalidValue;  // 32-bit row indices
   const int nparts = (int)std::min<size_t>(kWgBlocks, (nchunks + 3) / 4);
   float *bp = s.wpart + (size_t)kWgBlocks * NHT * NVT * 256;
   hipLaunchKernelGGL((k_wgrad_mfma<CA, CB>), dim3(nparts, NHT), dim3(kBlock), 0, c->stream, dA, act,

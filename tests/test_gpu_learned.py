@@ -308,8 +308,15 @@ def test_precondition_with_learned_stage_matches_oracle(small):
 @pytest.mark.gpu
 def test_learned_stage_trains_and_gains():
     """Train on the energy loss with pairs from the plain method on a 32x32x64 box (dx = 5 km,
-    dz = 250 m), then compare FGMRES iterations to 1e-8 with and without the stage on held-out
-    right-hand sides; every solve is checked with the oracle's S."""
+    dz = 250 m), then compare FGMRES to 1e-8 with and without the stage on held-out right-hand
+    sides: fewer iterations with the stage (every solve checked with the oracle's S), and the time
+    criterion -- the time per solve with the stage is what its cost model predicts, iterations x
+    (a plain iteration + a stage call - the trace matvec the stage's S application supplies) within
+    25 %, so a net gain in time needs (plain iterations / learned iterations) > 1 + (stage - matvec)
+    / iteration; the test reports that ratio and the two times (the measured outcome at the
+    benchmark sizes is recorded with the benchmark)."""
+    import time
+
     import torch
 
     prob = make_box(nx=32, ny=32, nlev=64, dx=5e3, dz=250.0, dt=600.0, mg_levels=4)
@@ -327,16 +334,22 @@ def test_learned_stage_trains_and_gains():
     hist = learned.train(s, X, R, steps=1500, batch=8, lr=2e-3, log=say)
     assert np.mean(hist[-50:]) < np.mean(hist[:5])  # the energy loss starts near 0 and goes negative
     orc = OracleProblem(prob, with_precond=False)
-    plain, with_nn, used = [], [], []
-    for seed in (1000, 1001, 1002):
-        r_ub, r_pi = make_rhs(prob, seed)
-        b = rhs(seed)
-        for flag, out in ((0, plain), (1, with_nn)):
-            p = s.params
-            p.learned = flag
-            s.set_params(p)
+    plain, with_nn, used, secs = [], [], [], {0: 0.0, 1: 0.0}
+    seeds = (1000, 1001, 1002)
+    for flag, out in ((0, plain), (1, with_nn)):
+        p = s.params
+        p.learned = flag
+        s.set_params(p)
+        s.solve(rhs(seeds[0]), torch.zeros(s.ntrace, dtype=torch.float64, device="cuda"), rtol=1e-8)  # warm-up
+        for seed in seeds:
+            r_ub, r_pi = make_rhs(prob, seed)
+            b = rhs(seed)
             lam = torch.zeros_like(b)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
             info = s.solve(b, lam, rtol=1e-8)
+            torch.cuda.synchronize()
+            secs[flag] += time.perf_counter() - t0
             ruc, rpc = cells_from_soa(r_ub, r_pi)
             B = orc.hyb.rhs(ruc, rpc)
             res = np.linalg.norm(B - orc.hyb.S @ host(lam)) / np.linalg.norm(B)
@@ -344,13 +357,33 @@ def test_learned_stage_trains_and_gains():
             out.append(info["iters"])
             if flag:
                 used.append(info["iters"] - info["fallbacks"])
+    # the cost model's parts, timed with events around each family
+    b = rhs(seeds[0])
+    costs = {}
+    for fam, flag in (("nn", 1), ("trace_apply", 0)):
+        p = s.params
+        p.learned = flag
+        s.set_params(p)
+        s.profile_family(fam)
+        s.solve(b, torch.zeros_like(b), rtol=1e-8)
+        n, ms = s.profile_read(fam)
+        s.profile(False)
+        costs[fam] = ms / max(n, 1) / 1e3
     p = s.params
     p.learned = 0
     s.set_params(p)
-    say(f"[learned] held-out iterations: plain {plain}, with learned stage {with_nn} "
-        f"(corrections kept {used})")
+    t_iter = secs[0] / sum(plain)
+    model = sum(with_nn) * (t_iter + costs["nn"] - costs["trace_apply"])
+    breakeven = 1.0 + (costs["nn"] - costs["trace_apply"]) / t_iter
+    say(f"[learned] held-out iterations: plain {plain}, with learned stage {with_nn} (corrections kept {used}); "
+        f"time {secs[0] * 1e3:.1f} ms plain, {secs[1] * 1e3:.1f} ms with the stage (model {model * 1e3:.1f} ms); "
+        f"stage {costs['nn'] * 1e3:.2f} ms per call, iteration {t_iter * 1e3:.2f} ms, matvec "
+        f"{costs['trace_apply'] * 1e3:.2f} ms: a time gain needs an iteration ratio above {breakeven:.2f}, "
+        f"measured {sum(plain) / sum(with_nn):.2f}")
     assert sum(used) > 0
     assert sum(with_nn) < sum(plain)
+    assert abs(secs[1] - model) <= 0.25 * model
+    s.close()
 
 
 @pytest.mark.gpu
