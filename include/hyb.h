@@ -151,7 +151,15 @@ typedef struct {
      accumulation; the default); 1 = FP32 activations on the vector units, kept as a reference for
      the BF16 path.  The stage inside hyb_solve always runs the BF16 inference passes. */
   int32_t nn_fp32;
+  /* failure injection for tests (0 in normal use): HYB_DEBUG_ZERO_GAMMA takes Gamma as zero, so the
+     coarse correction of Alg. 2 adds nothing and the cycle is its LineSmooth sweeps alone;
+     HYB_DEBUG_NAN_STAGE fills the learned stage's network output with NaN, so every correction
+     falls back to the plain cycle */
+  int32_t debug;
 } hyb_params;
+
+#define HYB_DEBUG_ZERO_GAMMA 1
+#define HYB_DEBUG_NAN_STAGE 2
 
 typedef struct {
   int32_t iters;        /* FGMRES iterations (preconditioner applications) */
@@ -369,6 +377,13 @@ int hyb_nn_energy_train_step(hyb_ctx *ctx, const float *x, const double *rhat, i
    for an index out of range. */
 int hyb_nn_energy_train_step_pairs(hyb_ctx *ctx, const float *X, const double *R, int64_t npairs,
                                    const int32_t *idx, int32_t nsamp, float lr, double *loss);
+/* Adam state of the training, to resume it in another context or process: the first and second
+   moments (host FP32 arrays of hyb_nn_param_count() values, in the parameter layout) and the step
+   count.  hyb_nn_set_weights resets the state, so hyb_nn_set_state follows it.  HYB_ESTATE before
+   hyb_nn_set_weights; HYB_EINVAL for NULL arrays, a wrong count, a negative step or non-finite or
+   (second moment) negative entries. */
+int hyb_nn_get_state(hyb_ctx *ctx, float *m, float *v, int64_t n, int64_t *step);
+int hyb_nn_set_state(hyb_ctx *ctx, const float *m, const float *v, int64_t n, int64_t step);
 /* One training pair from the plain method (the hook of the stage is the coarse correction of
    Alg. 2): the two-level cycle (Alg. 2, without the learned stage, in the context's precision) taken
    as a stationary iteration, z = M(r) and r <- r - S z, then c = Gamma P^T r, s = rms(c) over the

@@ -22,7 +22,9 @@ def cells_from_soa(r_ub, r_pi):
 class OracleProblem:
     def __init__(self, prob, *, with_mixed=True, with_precond=True, omega=0.6, n_pre=1,
                  n_post=2, mg_levels=None, omega_p=0.9, mg_pre=1, mg_post=2, mg_coarse_sweeps=6,
-                 mg_coarse_cheb=COARSE_CHEB, coarse=True, smoother_patch=False):
+                 mg_coarse_cheb=COARSE_CHEB, coarse=True, smoother_patch=False, log=None):
+        """log (optional): called with a line after each setup step (for long setups)."""
+        say = log or (lambda msg: None)
         self.prob = prob
         if getattr(prob, "geom", "box") == "shell":
             self.mesh = TableMesh(prob.nlev, prob.col_edge, prob.edge_col, prob.edge_lf,
@@ -31,8 +33,11 @@ class OracleProblem:
         else:
             self.mesh = BoxMesh(prob.nx, prob.ny, prob.nlev, prob.dx, prob.dy, prob.z)
             self.loc = local_matrices(self.mesh, prob)
+        say("oracle setup: cell matrices")
         self.hyb = HybridSystem(self.mesh, self.loc)
+        say("oracle setup: hybrid system")
         self.mixed = MixedSystem(self.mesh, self.loc, prob) if (with_mixed or with_precond) else None
+        say("oracle setup: mixed system")
         self.pc = None
         if with_precond:
             self.H = pressure_operator(self.mixed)
@@ -43,6 +48,7 @@ class OracleProblem:
                                mg_post=mg_post, mg_coarse_sweeps=mg_coarse_sweeps,
                                mg_coarse_cheb=mg_coarse_cheb, coarse=coarse,
                                smoother_patch=prob.levels[1].parent if smoother_patch else None)
+            say("oracle setup: preconditioner")
 
     def solve_fgmres(self, B, rtol=1e-8, restart=30, maxit=500, precondition=True):
         M = self.pc if precondition else (lambda r: r)

@@ -10,6 +10,8 @@ from ._native import (  # noqa: F401
     GEOM_BOX,
     GEOM_SHELL,
     HYB_BREAKDOWN,
+    HYB_DEBUG_NAN_STAGE,
+    HYB_DEBUG_ZERO_GAMMA,
     HYB_STAGNATED,
     HYB_NOT_CONVERGED,
     HYB_OK,

@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libhyb.so")
 HYB_OK = 0
 HYB_NOT_CONVERGED = 1
 HYB_BREAKDOWN = 2
+HYB_DEBUG_ZERO_GAMMA = 1
+HYB_DEBUG_NAN_STAGE = 2
 HYB_STAGNATED = 3
 PREC_FP64 = 0
 PREC_MIXED = 1
@@ -51,7 +53,7 @@ class _Params(ctypes.Structure):
                 ("learned", ctypes.c_int32), ("learned_tau", ctypes.c_double),
                 ("mg_coarse_cheb", ctypes.c_int32), ("cheb_lo", ctypes.c_double), ("cheb_hi", ctypes.c_double),
                 ("omega_rot", ctypes.c_double), ("coarse_mode", ctypes.c_int32), ("coarse_rtol", ctypes.c_double),
-                ("smoother_patch", ctypes.c_int32), ("nn_fp32", ctypes.c_int32)]
+                ("smoother_patch", ctypes.c_int32), ("nn_fp32", ctypes.c_int32), ("debug", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -93,6 +95,7 @@ class Params:
     coarse_rtol: float = 1e-2
     smoother_patch: int = 0
     nn_fp32: int = 0
+    debug: int = 0
 
     def to_c(self) -> _Params:
         return _Params(**{f.name: getattr(self, f.name) for f in fields(self)})
@@ -104,7 +107,7 @@ ABI_FUNCTIONS = [
     "hyb_sizes", "hyb_profile", "hyb_profile_family", "hyb_profile_read",
     "hyb_restrict", "hyb_nn_param_count", "hyb_nn_set_weights", "hyb_nn_get_weights", "hyb_nn_forward",
     "hyb_nn_loss_grad", "hyb_nn_train_step", "hyb_nn_energy_grad", "hyb_nn_energy_train_step",
-    "hyb_nn_energy_train_step_pairs", "hyb_nn_cycle_pair",
+    "hyb_nn_energy_train_step_pairs", "hyb_nn_cycle_pair", "hyb_nn_get_state", "hyb_nn_set_state",
     "hyb_mixed_rhs", "hyb_mixed_apply", "hyb_mixed_precondition", "hyb_mixed_solve",
     "hyb_last_error", "hyb_destroy",
 ]
@@ -160,6 +163,8 @@ def declare(lib):
     lib.hyb_nn_energy_train_step_pairs.argtypes = [vp, vp, vp, ctypes.c_int64, vp, ctypes.c_int32, ctypes.c_float,
                                                    ctypes.POINTER(ctypes.c_double)]
     lib.hyb_nn_cycle_pair.argtypes = [vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double)]
+    lib.hyb_nn_get_state.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+    lib.hyb_nn_set_state.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.c_int64]
     lib.hyb_mixed_rhs.argtypes = [vp, vp, vp, vp]
     lib.hyb_mixed_apply.argtypes = [vp, vp, vp]
     lib.hyb_mixed_precondition.argtypes = [vp, vp, vp]
@@ -422,6 +427,22 @@ class HybSolver:
             self.h, _ptr(X, n, "X", "float32"), _ptr(R, n, "R"), int(npairs), sel.ctypes.data_as(ctypes.c_void_p),
             int(sel.size), float(lr), ctypes.byref(loss)), "hyb_nn_energy_train_step_pairs")
         return loss.value
+
+    def nn_get_state(self):
+        """(m, v, step): the Adam moments (FP32) and step count of the training."""
+        n = self.nn_param_count()
+        m, v, step = np.empty(n, np.float32), np.empty(n, np.float32), ctypes.c_int64()
+        self._check(self.lib.hyb_nn_get_state(self.h, m.ctypes.data_as(ctypes.c_void_p),
+                                              v.ctypes.data_as(ctypes.c_void_p), n, ctypes.byref(step)),
+                    "hyb_nn_get_state")
+        return m, v, step.value
+
+    def nn_set_state(self, m, v, step):
+        m = np.ascontiguousarray(m, dtype=np.float32)
+        v = np.ascontiguousarray(v, dtype=np.float32)
+        self._check(self.lib.hyb_nn_set_state(self.h, m.ctypes.data_as(ctypes.c_void_p),
+                                              v.ctypes.data_as(ctypes.c_void_p), m.size, int(step)),
+                    "hyb_nn_set_state")
 
     def nn_cycle_pair(self, r, x, rhat):
         """One cycle step on r (in place) and its training pair into x (FP32) and rhat; returns the

@@ -122,6 +122,7 @@ int check_params(hyb_ctx *c, const hyb_params *p) {
     return fail(c, HYB_EINVAL, "coarse_rtol must be in (0, 1)");
   if (p->smoother_patch != 0 && p->smoother_patch != 1) return fail(c, HYB_EINVAL, "smoother_patch must be 0 or 1");
   if (p->nn_fp32 != 0 && p->nn_fp32 != 1) return fail(c, HYB_EINVAL, "nn_fp32 must be 0 or 1");
+  if (p->debug & ~(HYB_DEBUG_ZERO_GAMMA | HYB_DEBUG_NAN_STAGE)) return fail(c, HYB_EINVAL, "unknown debug bits");
   if (p->smoother_patch && c->ncol > 0 && (c->order != 0 || c->nlevels < 2))  // (hyb_create checks it itself)
     return fail(c, HYB_EINVAL, "patch-cached column matrices need order 0 and a multigrid level of patches");
   if (p->omega_rot != 0.0 && c->geom != HYB_GEOM_SHELL)
@@ -1166,6 +1167,24 @@ int hyb_nn_get_weights(hyb_ctx *c, float *w, int64_t n) {
   if (!c->nn.loaded) return fail(c, HYB_ESTATE, "no weights");
   if (!w || n != nn_param_count()) return fail(c, HYB_EINVAL, "weights: wrong size");
   CHECK_HIP(nn_get_weights(c, w), "nn get weights");
+  return HYB_OK;
+}
+
+int hyb_nn_get_state(hyb_ctx *c, float *m, float *v, int64_t n, int64_t *step) {
+  if (!c) return HYB_EINVAL;
+  if (!c->nn.loaded) return fail(c, HYB_ESTATE, "no weights");
+  if (!m || !v || !step || n != nn_param_count()) return fail(c, HYB_EINVAL, "state: wrong size");
+  CHECK_HIP(nn_get_state(c, m, v, step), "nn get state");
+  return HYB_OK;
+}
+
+int hyb_nn_set_state(hyb_ctx *c, const float *m, const float *v, int64_t n, int64_t step) {
+  if (!c) return HYB_EINVAL;
+  if (!c->nn.loaded) return fail(c, HYB_ESTATE, "no weights");
+  if (!m || !v || n != nn_param_count() || step < 0) return fail(c, HYB_EINVAL, "state: wrong size or step");
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(m[i]) || !std::isfinite(v[i]) || v[i] < 0.f) return fail(c, HYB_EINVAL, "state: bad moment");
+  CHECK_HIP(nn_set_state(c, m, v, step), "nn set state");
   return HYB_OK;
 }
 

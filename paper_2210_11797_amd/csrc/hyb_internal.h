@@ -306,6 +306,8 @@ int nn_param_count();
 hipError_t nn_setup(hyb_ctx *c);
 hipError_t nn_set_weights(hyb_ctx *c, const float *host_w);
 hipError_t nn_get_weights(hyb_ctx *c, float *host_w);
+hipError_t nn_get_state(hyb_ctx *c, float *m, float *v, int64_t *step);
+hipError_t nn_set_state(hyb_ctx *c, const float *m, const float *v, int64_t step);
 hipError_t nn_forward(hyb_ctx *c, const float *x, float *out, int nsamp);
 hipError_t nn_loss_grad(hyb_ctx *c, const float *x, const float *target, int nsamp, float *loss_host);
 hipError_t nn_energy_grad(hyb_ctx *c, const float *x, const double *rhat, int nsamp, double *loss_host);

@@ -798,6 +798,11 @@ __global__ void k_static_inputs(int ncell, int ncol, const double *__restrict__ 
   st[(size_t)ncell + c] = (float)layer[nlev + k];
 }
 
+__global__ void k_fill_nan(float *p, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = __uint_as_float(0x7FC00000u);
+}
+
 __global__ void k_zero_scal(double *p, int n) {
   if (threadIdx.x < n) p[threadIdx.x] = 0.0;
 }
@@ -929,6 +934,26 @@ hipError_t nn_set_weights(hyb_ctx *c, const float *host_w) {
   e = hipGetLastError();
   if (e) return e;
   return hipStreamSynchronize(c->stream);
+}
+
+hipError_t nn_get_state(hyb_ctx *c, float *m, float *v, int64_t *step) {
+  NNState &s = c->nn;
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e || (e = hipMemcpy(m, s.m, NPARAM * 4, hipMemcpyDeviceToHost)) ||
+      (e = hipMemcpy(v, s.v, NPARAM * 4, hipMemcpyDeviceToHost)))
+    return e;
+  *step = s.step;
+  return hipSuccess;
+}
+
+hipError_t nn_set_state(hyb_ctx *c, const float *m, const float *v, int64_t step) {
+  NNState &s = c->nn;
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e || (e = hipMemcpy(s.m, m, NPARAM * 4, hipMemcpyHostToDevice)) ||
+      (e = hipMemcpy(s.v, v, NPARAM * 4, hipMemcpyHostToDevice)))
+    return e;
+  s.step = (long)step;
+  return hipSuccess;
 }
 
 hipError_t nn_get_weights(hyb_ctx *c, float *host_w) {
@@ -1320,6 +1345,10 @@ hipError_t learned_stage(hyb_ctx *c, const double *r, Tz *z, double *Sz) {
   hipLaunchKernelGGL(k_normalise, dim3(nblk(n)), dim3(kBlock), 0, c->stream, c->cell64, s.scal, s.cin, n);
   if ((e = hipGetLastError())) return e;
   if ((e = nn_forward_inference(c, s.cin, s.cout))) return e;
+  if (c->p.debug & HYB_DEBUG_NAN_STAGE) {
+    hipLaunchKernelGGL(k_fill_nan, dim3(nblk(n)), dim3(kBlock), 0, c->stream, s.cout, n);
+    if ((e = hipGetLastError())) return e;
+  }
   hipLaunchKernelGGL((k_sumsq<float>), dim3(nb), dim3(kBlock), 0, c->stream, s.cout, n, part);
   hipLaunchKernelGGL(k_sum_into, dim3(1), dim3(64), 0, c->stream, part, (int)nb, s.scal + 1);
   hipLaunchKernelGGL(k_prolong_correction, dim3(nblk(ntr)), dim3(kBlock), 0, c->stream, s.cout, s.scal, L0.H, s.d64,

@@ -281,7 +281,8 @@ __global__ void k_thomas_factor_patch(const double *__restrict__ S, double *__re
 }
 
 // Restriction to the pressure space and scaling: Bbar_K = Gamma_K sum_F w_F R_F over the six
-// facets of K, w = 1/2 (1 on ground and lid facets, where prolongation is one sided).
+// facets of K, w = 1/2 (1 on ground and lid facets, where prolongation is one sided); gamma null:
+// Gamma = 0.
 template <typename T>
 __global__ void k_restrict(const T *__restrict__ R, const T *__restrict__ gamma, T *__restrict__ out, int nlev,
                            int ncol, int nedge, size_t nz, const int32_t *__restrict__ col_edge) {
@@ -295,7 +296,7 @@ __global__ void k_restrict(const T *__restrict__ R, const T *__restrict__ gamma,
   s *= (T)0.5;
   s += (k == 0 ? (T)1 : (T)0.5) * R[(size_t)k * ncol + col];
   s += (k == nlev - 1 ? (T)1 : (T)0.5) * R[(size_t)(k + 1) * ncol + col];
-  out[c] = gamma[c] * s;
+  out[c] = gamma ? gamma[c] * s : (T)0;
 }
 
 // lambda_F += (P dPi)_F: average of the two cells of the facet (one sided on ground / lid).  Laid
@@ -906,7 +907,8 @@ template <typename T>
 hipError_t precondition(hyb_ctx *c, const T *r, T *z) {
   const hyb_params &p = c->p;
   const T *S = pick<T>(c->S, c->Sf);
-  const T *gam = pick<T>(c->gamma, c->gammaf);
+  // debug bit 1: Gamma taken as zero, so the coarse correction adds nothing (failure injection)
+  const T *gam = (p.debug & HYB_DEBUG_ZERO_GAMMA) ? nullptr : pick<T>(c->gamma, c->gammaf);
   T *tA = (T *)c->tA, *tB = (T *)c->tB, *tR = (T *)c->tR;
   size_t ntr = (size_t)c->ntrace;
   const LevelDev &L0 = c->lv[0];

@@ -114,17 +114,37 @@ def train_streaming(solver, next_rhs, npairs=4096, pool=256, steps_per_rhs=8, ba
         target = updates * made // npairs
         while done < target:
             hist.append(solver.nn_energy_train_step_pairs(X[:filled], R[:filled], rng.integers(0, filled, batch), lr))
-            if log and (done % 250 == 0 or done == updates - 1):
+            if log and (done % 50 == 0 or done == updates - 1):
                 log(f"train step {done} ({made} pairs made): energy loss {hist[-1]:.4e}")
             done += 1
     return hist, made
 
 
-def save(path, weights, meta):
-    """Weights as a .npz (FP32 vector plus a JSON header string)."""
-    np.savez(path, weights=np.asarray(weights, np.float32), meta=np.array(json.dumps(meta)))
+def save(path, weights, meta, state=None):
+    """Weights as a .npz (FP32 vector plus a JSON header string: shape, seed, loss, ...); with
+    state = (m, v, step) from HybSolver.nn_get_state also the Adam moments, so that training can
+    resume (``resume``)."""
+    arrays = dict(weights=np.asarray(weights, np.float32), meta=np.array(json.dumps(meta)))
+    if state is not None:
+        m, v, step = state
+        arrays.update(adam_m=np.asarray(m, np.float32), adam_v=np.asarray(v, np.float32),
+                      adam_step=np.array(int(step), np.int64))
+    np.savez(path, **arrays)
 
 
 def load(path):
+    """(weights, meta, state): state = (m, v, step), or None when the file has no Adam state."""
     d = np.load(path, allow_pickle=False)
-    return d["weights"], json.loads(str(d["meta"]))
+    state = None
+    if "adam_m" in d.files:
+        state = (d["adam_m"], d["adam_v"], int(d["adam_step"]))
+    return d["weights"], json.loads(str(d["meta"])), state
+
+
+def resume(solver, path):
+    """Load weights and, if saved, the Adam state into a context, to continue training there."""
+    w, meta, state = load(path)
+    solver.nn_set_weights(w)
+    if state is not None:
+        solver.nn_set_state(*state)
+    return meta

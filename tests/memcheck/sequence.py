@@ -167,7 +167,20 @@ def solver_sequence(lib):
     c.set(precision=N.PREC_MIXED)
     rc, info, lam = c.solve(b, 1e-8)
     check(rc == 0 and c.residual(b, lam) <= 1.01e-8, f"patch-cached LineSmooth, mixed: {info.iters} iterations")
-    c.set(precision=N.PREC_MIXED, smoother_patch=0)
+    # failure injection: Gamma = 0 leaves the cycle its LineSmooth sweeps (bitwise the smoother-only
+    # configuration with the same sweeps), and unknown debug bits are rejected
+    c.set(precision=N.PREC_FP64, smoother_patch=0, debug=N.HYB_DEBUG_ZERO_GAMMA)
+    z0 = np.empty(c.ntrace)
+    c.call("hyb_precondition", P(b), P(z0))
+    c.set(debug=0, coarse_mode=1)
+    z1 = np.empty(c.ntrace)
+    c.call("hyb_precondition", P(b), P(z1))
+    c.set(coarse_mode=0)
+    bad = N.Params(**{**c.params.__dict__, "debug": 4})
+    cp_bad = bad.to_c()
+    check(np.array_equal(z0, z1) and lib.hyb_set_params(c.h, ctypes.byref(cp_bad)) < 0,
+          "Gamma = 0 gives the smoother-only cycle bit for bit; unknown debug bits rejected")
+    c.set(precision=N.PREC_MIXED)
     c.call("hyb_profile", 1)
     c.solve(b, 1e-6)
     n, ms = ctypes.c_int64(), ctypes.c_double()
@@ -289,6 +302,29 @@ def network_sequence(lib):
     check(l1.value == l2.value and np.array_equal(w1, w2)
           and lib.hyb_nn_energy_train_step_pairs(c.h, P(xp), P(rp), 2, P(bad_idx), 1, ctypes.c_float(1e-3), None) < 0,
           "gathered training step = step on the copied batch; an index out of range is rejected")
+    # resuming from the Adam state: 2 + 2 steps with the state carried over = 4 steps in a row
+    def steps(k):
+        for _ in range(k):
+            c.call("hyb_nn_energy_train_step", P(xg), P(rg), 3, ctypes.c_float(1e-3), None)
+    c.call("hyb_nn_set_weights", P(w), w.size)
+    steps(4)
+    w4 = np.empty(w.size, np.float32)
+    c.call("hyb_nn_get_weights", P(w4), w4.size)
+    c.call("hyb_nn_set_weights", P(w), w.size)
+    steps(2)
+    w2s, am, av, ast = np.empty(w.size, np.float32), np.empty(w.size, np.float32), np.empty(w.size, np.float32), \
+        ctypes.c_int64()
+    c.call("hyb_nn_get_weights", P(w2s), w2s.size)
+    c.call("hyb_nn_get_state", P(am), P(av), w.size, ctypes.byref(ast))
+    c.call("hyb_nn_set_weights", P(w), w.size)  # resets the state
+    c.call("hyb_nn_set_weights", P(w2s), w2s.size)
+    c.call("hyb_nn_set_state", P(am), P(av), w.size, ast.value)
+    steps(2)
+    w22 = np.empty(w.size, np.float32)
+    c.call("hyb_nn_get_weights", P(w22), w22.size)
+    neg = -np.abs(av) - 1.0
+    check(ast.value == 2 and np.array_equal(w4, w22) and lib.hyb_nn_set_state(c.h, P(am), P(neg), w.size, 2) < 0,
+          "training resumed from the Adam state = training without a break; a negative moment is rejected")
     for fp32 in (1, 0):  # the FP32 reference passes and the BF16 matrix-core ones
         c.set(nn_fp32=fp32)
         c.call("hyb_nn_set_weights", P(w), w.size)
@@ -328,6 +364,11 @@ def network_sequence(lib):
     c.set(precision=N.PREC_FP64)
     rc, info, lam = c.solve(b, 1e-8)
     check(rc == 0 and info.fallbacks == info.iters, f"overflowing network falls back: {info.fallbacks}/{info.iters}")
+    c.call("hyb_nn_set_weights", P(w), w.size)
+    c.set(debug=N.HYB_DEBUG_NAN_STAGE)
+    rc, info, lam = c.solve(b, 1e-8)
+    c.set(debug=0, learned=0)
+    check(rc == 0 and info.fallbacks == info.iters, f"a NaN network output falls back: {info.fallbacks}/{info.iters}")
     c.close()
 
 

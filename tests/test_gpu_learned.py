@@ -414,6 +414,49 @@ def test_learned_stage_falls_back_on_overflow(small):
 
 
 @pytest.mark.gpu
+def test_training_resumes_from_saved_adam_state(small, tmp_path):
+    """Training saved with its Adam state (learned.save) and resumed in a fresh context
+    (learned.resume) continues exactly as training without a break (bitwise: the passes are
+    deterministic); a NaN network output, forced from the host, falls back at every iteration."""
+    prob, s = small
+    rng = np.random.default_rng(31)
+    x = _f32(rng.standard_normal((3, prob.ncell)))
+    rhat = dev(rng.standard_normal((3, prob.ncell)))
+    vec = learned.init_params(16, seed=5)
+    s.nn_set_weights(vec)
+    for _ in range(4):
+        s.nn_energy_train_step(x, rhat, 3, 1e-3)
+    w4 = s.nn_get_weights()
+    s.nn_set_weights(vec)
+    for _ in range(2):
+        s.nn_energy_train_step(x, rhat, 3, 1e-3)
+    path = str(tmp_path / "stage.npz")
+    learned.save(path, s.nn_get_weights(), {"steps": 2}, state=s.nn_get_state())
+    s2 = make_solver(prob)
+    meta = learned.resume(s2, path)
+    for _ in range(2):
+        s2.nn_energy_train_step(x, rhat, 3, 1e-3)
+    w22 = s2.nn_get_weights()
+    say(f"[resume] after {meta['steps']} + 2 steps: max difference {np.abs(w22 - w4).max():.1e}")
+    assert np.array_equal(w22, w4)
+    import torch
+
+    from paper_2210_11797_amd import HYB_DEBUG_NAN_STAGE
+
+    p = s2.params
+    p.learned, p.debug = 1, HYB_DEBUG_NAN_STAGE
+    s2.set_params(p)
+    r_ub, r_pi = make_rhs(prob, 3)
+    b = torch.empty(s2.ntrace, dtype=torch.float64, device="cuda")
+    s2.condense(dev(r_ub), dev(r_pi), b)
+    info = s2.solve(b, torch.zeros_like(b), rtol=1e-8)
+    say(f"[resume] NaN stage output: iters {info['iters']} fallbacks {info['fallbacks']}")
+    assert info["status"] == 0 and info["fallbacks"] == info["iters"]
+    s2.close()
+    s.nn_set_weights(vec)
+
+
+@pytest.mark.gpu
 def test_call_orders_that_once_met_unallocated_buffers():
     """Regression test of two call orders whose buffers were once used before allocation (found
     on the CPU stand-in, fixed): a training step as the first network call of a fresh context, and

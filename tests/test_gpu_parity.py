@@ -284,6 +284,39 @@ WIDE = {
 }
 
 
+@pytest.mark.gpu
+def test_zero_gamma_switch_leaves_the_smoother_sweeps():
+    """Failure injection from the host: with Gamma taken as zero the coarse correction adds nothing,
+    so the two-level cycle is bit for bit its LineSmooth sweeps (the smoother-only configuration
+    with the same sweeps), and FGMRES still converges, with more iterations."""
+    import torch
+
+    from paper_2210_11797_amd import HYB_DEBUG_ZERO_GAMMA
+
+    prob = make_box(**CASES["ragged"])
+    s = make_solver(prob)
+    r = dev(np.random.default_rng(8).standard_normal(s.ntrace))
+    z = {}
+    for name, kw in (("zero_gamma", dict(debug=HYB_DEBUG_ZERO_GAMMA)), ("smoother_only", dict(coarse_mode=1)),
+                     ("two_level", {})):
+        p = s.params
+        p.debug, p.coarse_mode = kw.get("debug", 0), kw.get("coarse_mode", 0)
+        s.set_params(p)
+        z[name] = torch.empty_like(r)
+        s.precondition(r, z[name])
+    assert torch.equal(z["zero_gamma"], z["smoother_only"])
+    assert not torch.equal(z["zero_gamma"], z["two_level"])
+    its = {}
+    for flag in (0, HYB_DEBUG_ZERO_GAMMA):
+        p = s.params
+        p.debug, p.coarse_mode = flag, 0
+        s.set_params(p)
+        its[flag] = s.solve(r, torch.zeros_like(r), rtol=1e-8, maxit=3000)["iters"]
+    say(f"[zero gamma] FGMRES iterations: two-level {its[0]}, Gamma = 0 {its[HYB_DEBUG_ZERO_GAMMA]}")
+    assert its[HYB_DEBUG_ZERO_GAMMA] > its[0]
+    s.close()
+
+
 PATCH = {
     "ragged": dict(nx=12, ny=10, nlev=5, dx=7e3, dy=5e3, dz=400.0, mg_levels=2, perturb=0.1),
     "tiles_stretched": dict(nx=24, ny=20, nlev=12, dx=5e3, ztop=6e3, stretch="quadratic", mg_levels=3,

@@ -293,9 +293,10 @@ def test_c192_solves_fp64_and_mixed(tmp_path):
 @pytest.mark.gpu
 def test_sphere_network_and_stage_match_oracle():
     """Network forward and MSE gradients (BF16 weights in the oracle) on C8 x 6, whose 24 columns at
-    the cube vertices lack a corner neighbour, and hyb_precondition with the stage against the
-    oracle's cycle + stage (identity network to 1e-6, random network to 1e-4, the tolerances of the
-    box tests)."""
+    the cube vertices lack a corner neighbour, through the FP32 reference passes (the BF16 ones are
+    checked exactly on a sphere in test_gpu_learned.py), and hyb_precondition with the stage against
+    the oracle's cycle + stage (identity network to 1e-6, random network to 1e-4, the tolerances of
+    the box tests)."""
     import torch
 
     from oracle import nn as onn
@@ -304,6 +305,9 @@ def test_sphere_network_and_stage_match_oracle():
     prob, orc, s = setup("c8")
     nb = onn.neighbour_table_from_tables(prob.col_edge, prob.edge_col, prob.edge_lf)
     assert (nb < 0).sum() == 24
+    p = s.params
+    p.nn_fp32 = 1
+    s.set_params(p)
     rng = np.random.default_rng(0)
     vec = learned.init_params(16, seed=1)
     vec[16 * learned.NIN * 45 : 16 * learned.NIN * 45 + 16] = rng.standard_normal(16) * 0.1
@@ -325,6 +329,9 @@ def test_sphere_network_and_stage_match_oracle():
                         [0.5 * (refs[0][2][j] + refs[1][2][j]) for j in range(3)]).astype(np.float64)
     err_g = rel_max(np.asarray(g, np.float64), gref)
     say(f"[sphere nn] forward {err_y:.2e} gradients {err_g:.2e}")
+    p = s.params
+    p.nn_fp32 = 0
+    s.set_params(p)
     assert err_y <= 1e-5 and err_g <= 1e-4
     Wi, bi = onn.identity_weights(16)
     p = s.params
