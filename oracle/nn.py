@@ -165,11 +165,9 @@ def conv_grads(x, W, dy, nb, nlev):
     return dx.reshape(ci, n), dW, dyr.sum(axis=(1, 2))
 
 
-def forward(x, W, b, nb, nlev, round_act=None, static=None):
-    """Returns the output and the post-activation values of every layer (x is (L*ncol,)).
-    round_act: applied to the hidden activations after the ReLU (e.g. ``bf16_round`` for networks
-    whose hidden activations are stored in BF16); static: the static input channels (zeros if
-    None)."""
+def forward(x, W, b, nb, nlev, static=None):
+    """Returns the output and the post-activation values of every layer (x is (L*ncol,)), in FP64;
+    static: the static input channels (zeros if None)."""
     nst = W[0].shape[1] - 1
     if nst == 0:
         acts = [x[None, :]]
@@ -182,8 +180,6 @@ def forward(x, W, b, nb, nlev, round_act=None, static=None):
         h = conv(h, W[i], b[i], nb, nlev)
         if i < 2:
             h = np.maximum(h, 0.0)
-            if round_act is not None:
-                h = round_act(h)
         acts.append(h)
     return h[0], acts
 
@@ -213,13 +209,13 @@ def bf16_round(a):
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
-def learned_correction(v, z, S, P, gamma, hdiag, W, b, nb, nlev, tau=3.0, round_act=None, static=None):
+def learned_correction(v, z, S, P, gamma, hdiag, W, b, nb, nlev, tau=3.0, static=None):
     """The learned stage after z = M(v).  Returns (z_new, accepted)."""
     rp = v - S @ z
     c = gamma * (P.T @ rp)
     s = float(np.sqrt(np.mean(c * c)))
     x = c / s if s > 0.0 else np.zeros_like(c)
-    y, _ = forward(x, W, b, nb, nlev, round_act, static=static)
+    y, _ = forward(x, W, b, nb, nlev, static=static)
     if not np.all(np.isfinite(y)):
         return z, False
     d = s * (P @ (y / hdiag))

@@ -253,28 +253,28 @@ def test_energy_loss_gradients_match_oracle(small, fp32):
     assert max(errs) <= TOL[fp32]["grad"]
 
 
-def _stage_reference(prob, orc, vec, v, round_act):
-    """The stage with the network's BF16 weights, in FP64: with round_act = bf16_round the hidden
-    activations are rounded to BF16 as the kernels store them; with None the network is the
-    unrounded one.  Returns (z, accepted, z of the plain cycle)."""
+def _stage_reference(prob, orc, vec, v):
+    """The stage with the network's BF16 weights, in FP64 (the oracle's unrounded network).
+    Returns (z, accepted, z of the plain cycle)."""
     W, b = learned.unpack(vec)
     Wr = [onn.bf16_round(w) for w in W]
     z = orc.pc(v)
     zs, acc = onn.learned_correction(v, z, orc.pc.S, orc.pc.P, orc.pc.gamma, orc.H.diagonal(), Wr, b,
-                                     onn.neighbour_table(prob.nx, prob.ny), prob.nlev, round_act=round_act,
-                                     static=static_for(prob))
+                                     onn.neighbour_table(prob.nx, prob.ny), prob.nlev, static=static_for(prob))
     return zs, acc, z
+
+
+# the stage's BF16 hidden activations (2^-9 per stored value) move its correction by at most this
+# fraction of the correction's own size: the identity network rounds only its input once (its
+# products are exact), a random one rounds two hidden layers that feed 720 and 11520 products per cell
+STAGE_TOL = {"identity": 2.0**-8, "random": 2.0**-6}
 
 
 @pytest.mark.gpu
 def test_precondition_with_learned_stage_matches_oracle(small):
-    """hyb_precondition with the stage against the oracle's cycle + stage.  Against the unrounded
-    FP64 network (BF16 weights): the kernels store hidden activations in BF16 (relative rounding
-    2^-9 per value, through two hidden layers), so the correction may differ by 2^-6 of its own size
-    (measured 2e-3 to 6e-3).  Against the network with BF16-rounded activations (the kernels'
-    storage format): an exact identity network to 1e-6 (every product is exact in BF16 / FP32) and a
-    random one to 1e-4 (where the FP32 accumulation on the GPU and the FP64 one in the oracle
-    straddle a BF16 rounding boundary, a hidden activation differs by one BF16 ulp)."""
+    """hyb_precondition with the stage against the oracle's cycle + stage with the unrounded FP64
+    network (BF16 weights): the same acceptance decision, and the correction within STAGE_TOL of its
+    size (measured 2e-3 to 6e-3 for the random network)."""
     prob, s = small
     import torch
 
@@ -287,22 +287,19 @@ def test_precondition_with_learned_stage_matches_oracle(small):
         s.nn_set_weights(vec)
         for trial in range(3):
             v = rng.standard_normal(orc.mesh.ntrace)
-            zref, acc, z0 = _stage_reference(prob, orc, vec, v, onn.bf16_round)
-            zex, acc_ex, _ = _stage_reference(prob, orc, vec, v, None)
+            zex, acc_ex, z0 = _stage_reference(prob, orc, vec, v)
             z = torch.empty(s.ntrace, dtype=torch.float64, device="cuda")
             p.learned = 1
             s.set_params(p)
             s.precondition(dev(v), z)
             p.learned = 0
             s.set_params(p)
-            err = rel_max(host(z), zref)
             err_ex = rel_max(host(z), zex)
             corr = rel_max(zex, z0)  # the correction's size relative to the result
-            say(f"[stage] {name} trial {trial}: accepted {acc}, error {err:.2e}; against the unrounded network "
+            say(f"[stage] {name} trial {trial}: accepted {acc_ex}; against the unrounded network "
                 f"{err_ex:.2e} = {err_ex / max(corr, 1e-300):.1e} of the correction")
-            assert acc == acc_ex
-            assert err_ex <= 2.0**-6 * corr
-            assert err <= (1e-6 if name == "identity" else 1e-4)
+            assert acc_ex and rel_max(host(z), z0) > 0.5 * corr  # the correction was applied
+            assert err_ex <= STAGE_TOL[name] * corr
 
 
 @pytest.mark.gpu
