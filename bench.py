@@ -859,9 +859,23 @@ def main():
     if args.cpu_baseline_full or args.splu_scaling:
         cpu_full = {"host_cpu_count": os.cpu_count(), "threads": 1}
     if args.cpu_baseline_full:
-        cf = cpu_baseline(prob, args.coarse_sweeps, args.coarse_jacobi, seeds=tuple(range(args.cpu_full_seeds)))
-        cpu_full.update({"workload_box": f"{args.nx}x{args.nx}x{args.nlev}", "median_s": cf["median_s"],
-                         "times_s": cf["times"], "iters": cf["iters"], "setup_s": cf["setup_s"]})
+        # the full box, then halved in each horizontal direction until the oracle's setup fits
+        cpu_full["boxes"] = []
+        nxf = args.nx
+        while nxf >= 16:
+            box = f"{nxf}x{nxf}x{args.nlev}"
+            try:
+                pf = prob if nxf == args.nx else make_box(nx=nxf, ny=nxf, nlev=args.nlev, dx=dx, dz=dz, dt=dt,
+                                                          mg_levels=4)
+                cf = cpu_baseline(pf, args.coarse_sweeps, args.coarse_jacobi, seeds=tuple(range(args.cpu_full_seeds)))
+            except (RuntimeError, MemoryError) as err:
+                cpu_full["boxes"].append({"box": box, "status": f"oracle setup failed: {str(err)[:160]}"})
+                log(f"cpu baseline: {box}: oracle setup failed ({str(err)[:120]})")
+                nxf //= 2
+                continue
+            cpu_full["boxes"].append({"box": box, "ncell": cf["ncell"], "median_s": cf["median_s"],
+                                      "times_s": cf["times"], "iters": cf["iters"], "setup_s": cf["setup_s"]})
+            break
     if args.splu_scaling:
         cpu_full["splu_mixed"] = splu_scaling([16, 32, 64, 128], dx, dz, dt, lambda nx: nx // 4 if nx > 16 else 8, 170)
 
