@@ -265,9 +265,11 @@ def _stage_reference(prob, orc, vec, v):
 
 
 # the stage's BF16 hidden activations (2^-9 per stored value) move its correction by at most this
-# fraction of the correction's own size: the identity network rounds only its input once (its
-# products are exact), a random one rounds two hidden layers that feed 720 and 11520 products per cell
-STAGE_TOL = {"identity": 2.0**-8, "random": 2.0**-6}
+# fraction of the correction's largest entry: the identity network rounds only its input (its
+# products are exact; measured 2.3e-3 to 2.9e-3, the largest error and the largest correction
+# falling on different facets), a random one rounds two hidden layers that feed 720 and 11520
+# products per cell (measured 4.2e-3 to 5.2e-3)
+STAGE_TOL = {"identity": 2.0**-7, "random": 2.0**-6}
 
 
 @pytest.mark.gpu

@@ -295,7 +295,7 @@ def test_sphere_network_and_stage_match_oracle():
     """Network forward and MSE gradients (BF16 weights in the oracle) on C8 x 6, whose 24 columns at
     the cube vertices lack a corner neighbour, through the FP32 reference passes (the BF16 ones are
     checked exactly on a sphere in test_gpu_learned.py), and hyb_precondition with the stage against
-    the oracle's cycle + stage with the unrounded network (the correction within 2^-8 / 2^-6 of its
+    the oracle's cycle + stage with the unrounded network (the correction within 2^-7 / 2^-6 of its
     size for the identity / a random network, the tolerances of the box tests)."""
     import torch
 
@@ -343,8 +343,8 @@ def test_sphere_network_and_stage_match_oracle():
             v = rng.standard_normal(orc.mesh.ntrace)
             z0 = orc.pc(v)
             # the unrounded FP64 network: the kernels' BF16 hidden activations (2^-9 per value) may
-            # move the correction by 2^-8 (identity network: its input rounded once) or 2^-6 (random:
-            # two hidden layers) of its own size
+            # move the correction by 2^-7 (identity network: its input rounded once) or 2^-6 (random:
+            # two hidden layers) of its largest entry
             zex, acc_ex = onn.learned_correction(v, z0, orc.pc.S, orc.pc.P, orc.pc.gamma, orc.H.diagonal(), Wvr,
                                                  bv, nb, prob.nlev, static=st)
             z = torch.empty(s.ntrace, dtype=torch.float64, device="cuda")
@@ -357,7 +357,7 @@ def test_sphere_network_and_stage_match_oracle():
             say(f"[sphere stage] {name} trial {trial}: accepted {acc_ex}; against the unrounded network "
                 f"{err_ex:.2e} = {err_ex / max(corr, 1e-300):.1e} of the correction")
             assert acc_ex and rel_max(host(z), z0) > 0.5 * corr
-            assert err_ex <= (2.0**-8 if name == "identity" else 2.0**-6) * corr
+            assert err_ex <= (2.0**-7 if name == "identity" else 2.0**-6) * corr
 
 
 # ------------------------------------------------------------------------------------------------
