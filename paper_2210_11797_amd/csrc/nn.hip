@@ -446,13 +446,19 @@ __global__ void __launch_bounds__(kBlock) k_inf_layer1(const float *__restrict__
                                                       int nlev, int ncol, int nsamp, const int32_t *__restrict__ nb9,
                                                       const float *__restrict__ xst) {
   constexpr int CIN = kNNInputs;  // x, then the static fields xst[CIN - 1][cell]
+  // weights in LDS as [tap][ci][co], so that a tap's weights are read as whole vectors
   __shared__ float w[C1 * CIN * NTAP];
-  for (int i = threadIdx.x; i < C1 * CIN * NTAP; i += blockDim.x) w[i] = bf2f(wb[i]);
+  for (int i = threadIdx.x; i < C1 * CIN * NTAP; i += blockDim.x) {
+    const int t = i / (CIN * C1), rem = i - t * (CIN * C1), ci = rem / C1, co = rem - ci * C1;
+    w[i] = bf2f(wb[(co * CIN + ci) * NTAP + t]);
+  }
   __syncthreads();
-  const size_t n = (size_t)nlev * ncol;
-  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= n * nsamp) return;
-  const int smp = (int)(gid / n), cell = (int)(gid - (size_t)smp * n);
+  // 32-bit row arithmetic (the host keeps rows x samples below 2^32)
+  const unsigned n = (unsigned)nlev * (unsigned)ncol;
+  const unsigned gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= n * (unsigned)nsamp) return;
+  const unsigned smp = gid / n;
+  const int cell = (int)(gid - smp * n);
   const int k = cell / ncol, col = cell - k * ncol;
   x += (size_t)smp * n;
   float acc[C1];
@@ -473,11 +479,11 @@ __global__ void __launch_bounds__(kBlock) k_inf_layer1(const float *__restrict__
 #pragma unroll
       for (int co = 0; co < C1; ++co)
 #pragma unroll
-        for (int ci = 0; ci < CIN; ++ci) acc[co] += w[(co * CIN + ci) * NTAP + h * NVT + v] * xv[ci];
+        for (int ci = 0; ci < CIN; ++ci) acc[co] += w[((h * NVT + v) * CIN + ci) * C1 + co] * xv[ci];
     }
   }
 #pragma unroll
-  for (int co = 0; co < C1; ++co) a1[gid * C1 + co] = f2bf(fmaxf(acc[co], 0.f));
+  for (int co = 0; co < C1; ++co) a1[(size_t)gid * C1 + co] = f2bf(fmaxf(acc[co], 0.f));
 }
 
 // Layer 2 (16 -> 16 channels) as an implicit GEMM on BF16 MFMA (v_mfma_f32_16x16x32_bf16, FP32
@@ -499,7 +505,7 @@ __device__ __forceinline__ nn_f32x4 mfma_bf16_32(nn_u32x4 a, nn_u32x4 b, nn_f32x
                                                  0, 0, 0);
 }
 
-constexpr int kC2Tiles = 4;  // 16-row tiles per wavefront
+constexpr int kC2Tiles = 8;  // 16-row tiles per wavefront
 template <bool BWD>
 __global__ void __launch_bounds__(kBlock) k_conv2_mfma(const uint16_t *__restrict__ in, const uint16_t *__restrict__ wb2,
                                                       const float *__restrict__ bias, const uint16_t *__restrict__ gate,
@@ -517,16 +523,17 @@ __global__ void __launch_bounds__(kBlock) k_conv2_mfma(const uint16_t *__restric
   __syncthreads();
   const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4, half = q & 1;
   const bool second = q >= 2;
-  const size_t n = (size_t)nlev * ncol, total = n * nsamp;
-  const size_t wave = (size_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const unsigned n = (unsigned)nlev * (unsigned)ncol, total = n * (unsigned)nsamp;
+  const unsigned wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const nn_u32x4 zero4 = {0u, 0u, 0u, 0u};
   for (int tile = 0; tile < kC2Tiles; ++tile) {
-    const size_t base = (wave * kC2Tiles + tile) * 16;
+    const unsigned base = (wave * kC2Tiles + tile) * 16;
     if (base >= total) break;  // uniform over the wavefront
-    const size_t g = base + r;
+    const unsigned g = base + r;
     const bool live = g < total;
-    const size_t gs = live ? g : base;
-    const int smp = (int)(gs / n), cell = (int)(gs - (size_t)smp * n);
+    const unsigned gs = live ? g : base;
+    const unsigned smp = gs / n;
+    const int cell = (int)(gs - smp * n);
     const int k = cell / ncol, col = cell - k * ncol;
     const uint16_t *ins = in + (size_t)smp * n * C1;
     int cn[NHT];  // the 3x3 neighbourhood first, so that the tap loads do not wait on it
@@ -554,13 +561,14 @@ __global__ void __launch_bounds__(kBlock) k_conv2_mfma(const uint16_t *__restric
     // acc[j] = channel r of row base + 4 q + j
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const size_t go = base + 4 * q + j;
+      const unsigned go = base + 4 * q + j;
       if (go >= total) continue;
       float val = acc[j];
       if (!BWD) {
-        out[go * C1 + r] = f2bf(fmaxf(val + bias[r], 0.f));
+        out[(size_t)go * C1 + r] = f2bf(fmaxf(val + bias[r], 0.f));
       } else {
-        const int so = (int)(go / n), oc = (int)(go - (size_t)so * n), ko = oc / ncol, colo = oc - ko * ncol;
+        const unsigned so = go / n;
+        const int oc = (int)(go - so * n), ko = oc / ncol, colo = oc - ko * ncol;
         for (int e = lo_off[colo]; e < lo_off[colo + 1]; ++e) {
           const int pk = lo_list[e], cr = pk / NHT, hh = pk - cr * NHT;
           for (int v = 0; v < NVT; ++v) {
@@ -571,7 +579,7 @@ __global__ void __launch_bounds__(kBlock) k_conv2_mfma(const uint16_t *__restric
             for (int co = 0; co < C1; ++co) val += bf2f(w[co]) * bf2f(src[co]);
           }
         }
-        out[go * C1 + r] = bf2f(gate[go * C1 + r]) > 0.f ? f2bf(val) : (uint16_t)0;
+        out[(size_t)go * C1 + r] = bf2f(gate[(size_t)go * C1 + r]) > 0.f ? f2bf(val) : (uint16_t)0;
       }
     }
   }
@@ -722,13 +730,14 @@ __global__ void k_wgrad_sum(const float *__restrict__ part, const float *__restr
 __global__ void __launch_bounds__(kBlock) k_bwd3_bf16(const float *__restrict__ dy, const uint16_t *__restrict__ wb3,
                                                      const uint16_t *__restrict__ a2, uint16_t *__restrict__ dz2,
                                                      int nlev, int ncol, int nsamp, const int32_t *__restrict__ rv9) {
-  __shared__ float w[C1 * NTAP];
-  for (int i = threadIdx.x; i < C1 * NTAP; i += blockDim.x) w[i] = bf2f(wb3[i]);
+  __shared__ float w[C1 * NTAP];  // [tap][ci]
+  for (int i = threadIdx.x; i < C1 * NTAP; i += blockDim.x) w[i] = bf2f(wb3[(i % C1) * NTAP + i / C1]);
   __syncthreads();
-  const size_t n = (size_t)nlev * ncol;
-  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= n * nsamp) return;
-  const int smp = (int)(gid / n), cell = (int)(gid - (size_t)smp * n);
+  const unsigned n = (unsigned)nlev * (unsigned)ncol;
+  const unsigned gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= n * (unsigned)nsamp) return;
+  const unsigned smp = gid / n;
+  const int cell = (int)(gid - smp * n);
   const int k = cell / ncol, col = cell - k * ncol;
   const float *dys = dy + (size_t)smp * n;
   float acc[C1];
@@ -744,11 +753,11 @@ __global__ void __launch_bounds__(kBlock) k_bwd3_bf16(const float *__restrict__ 
       if (kk < 0 || kk >= nlev) continue;
       const float g = dys[(size_t)kk * ncol + c2];
 #pragma unroll
-      for (int ci = 0; ci < C1; ++ci) acc[ci] += w[ci * NTAP + hh * NVT + v] * g;
+      for (int ci = 0; ci < C1; ++ci) acc[ci] += w[(hh * NVT + v) * C1 + ci] * g;
     }
   }
-  const uint16_t *ag = a2 + gid * C1;
-  uint16_t *o = dz2 + gid * C1;
+  const uint16_t *ag = a2 + (size_t)gid * C1;
+  uint16_t *o = dz2 + (size_t)gid * C1;
 #pragma unroll
   for (int ci = 0; ci < C1; ++ci) o[ci] = bf2f(ag[ci]) > 0.f ? f2bf(acc[ci]) : (uint16_t)0;
 }
@@ -756,13 +765,14 @@ __global__ void __launch_bounds__(kBlock) k_bwd3_bf16(const float *__restrict__ 
 __global__ void __launch_bounds__(kBlock) k_inf_layer3(const uint16_t *__restrict__ a2, const uint16_t *__restrict__ wb3,
                                                       const float *__restrict__ bias, float *__restrict__ y, int nlev,
                                                       int ncol, int nsamp, const int32_t *__restrict__ nb9) {
-  __shared__ float w[C1 * NTAP];
-  for (int i = threadIdx.x; i < C1 * NTAP; i += blockDim.x) w[i] = bf2f(wb3[i]);
+  __shared__ float w[C1 * NTAP];  // [tap][ci]
+  for (int i = threadIdx.x; i < C1 * NTAP; i += blockDim.x) w[i] = bf2f(wb3[(i % C1) * NTAP + i / C1]);
   __syncthreads();
-  const size_t n = (size_t)nlev * ncol;
-  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= n * nsamp) return;
-  const int smp = (int)(gid / n), cell = (int)(gid - (size_t)smp * n);
+  const unsigned n = (unsigned)nlev * (unsigned)ncol;
+  const unsigned gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= n * (unsigned)nsamp) return;
+  const unsigned smp = gid / n;
+  const int cell = (int)(gid - smp * n);
   const int k = cell / ncol, col = cell - k * ncol;
   a2 += (size_t)smp * n * C1;
   float acc = bias[0];
@@ -779,7 +789,7 @@ __global__ void __launch_bounds__(kBlock) k_inf_layer3(const uint16_t *__restric
 #pragma unroll
       for (int ci = 0; ci < C1; ++ci) {
         const uint16_t hv = (uint16_t)((ci & 1) ? (words[ci >> 1] >> 16) : (words[ci >> 1] & 0xFFFFu));
-        acc += w[ci * NTAP + h * NVT + v] * bf2f(hv);
+        acc += w[(h * NVT + v) * C1 + ci] * bf2f(hv);
       }
     }
   }
@@ -1016,6 +1026,7 @@ static hipError_t nn_static(hyb_ctx *c) {
 static hipError_t forward_bf16(hyb_ctx *c, const float *x, uint16_t *a1, uint16_t *a2, float *out, int nsamp) {
   NNState &s = c->nn;
   const size_t n = (size_t)c->ncell * nsamp;
+  if (n + 64 > (size_t)UINT32_MAX) return hipErrorInvalidValue;  // the kernels index rows in 32 bits
   const int L = c->nlev, nc = c->ncol;
   hipLaunchKernelGGL(k_inf_layer1, dim3(nblk(n)), dim3(kBlock), 0, c->stream, x, s.wb, s.w + OFF_B1, a1, L, nc, nsamp,
                      s.nb9, (const float *)s.st);
