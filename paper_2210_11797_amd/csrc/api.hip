@@ -225,6 +225,8 @@ void free_all(hyb_ctx *c) {
   dfree(c->V), dfree(c->Z), dfree(c->Vm), dfree(c->Zm), dfree(c->partial), dfree(c->hdev);
   if (c->hhost) (void)hipHostFree(c->hhost);
   c->hhost = nullptr;
+  if (c->ev_coef) (void)hipEventDestroy(c->ev_coef);
+  c->ev_coef = nullptr;
   for (auto &f : c->fam)
     for (auto ev : f.ev) (void)hipEventDestroy(ev);
   c->fam.clear();
@@ -249,6 +251,7 @@ int alloc_krylov(hyb_ctx *c) {
     return rc;
   CHECK_HIP(hipHostMalloc((void **)&c->hhost, 4 * (size_t)(m + 2) * sizeof(double), hipHostMallocDefault),
             "hipHostMalloc");
+  if (!c->ev_coef) CHECK_HIP(hipEventCreateWithFlags(&c->ev_coef, hipEventDisableTiming), "hipEventCreate");
   const size_t hm = (size_t)(m + 1) * m;
   c->kR.assign(hm, 0.0), c->kHr.assign(hm, 0.0), c->kg.assign(m + 1, 0.0);
   c->kcs.assign(m, 0.0), c->ksn.assign(m, 0.0), c->ky.assign(m, 0.0), c->kca.assign(m, 0.0), c->kcb.assign(m, 0.0);
@@ -339,21 +342,25 @@ int fgmres(hyb_ctx *c, size_t n, size_t ldv, double *V, void *Zbuf, bool zf32, c
       double eta_prev = 1.0, g0 = beta;
       for (int j = 0; j < m; ++j) {
         if ((rc = apply_op(j))) return rc;
+        // dots, then the step's coefficients on the device, whose read-back is queued before the
+        // update pass that uses them: the host waits for the read-back only, and its Hessenberg
+        // and Givens work below overlaps the update pass
+        double *coef = c->hdev + 2 * (size_t)(m + 2);
+        const double *hc = hh + 2 * (size_t)(m + 2);
         CHECK_HIP(launch_dgs_dots(c, V, ldv, n, j, c->hdev), "gram-schmidt dots");
-        CHECK_HIP(hipMemcpyAsync(hh, c->hdev, (2 * (size_t)j + 3) * sizeof(double), hipMemcpyDeviceToHost, c->stream),
+        CHECK_HIP(launch_dgs_coef(c, c->hdev, j, coef), "gram-schmidt coefficients");
+        CHECK_HIP(hipMemcpyAsync((void *)hc, coef, (2 * (size_t)j + 6) * sizeof(double), hipMemcpyDeviceToHost,
+                                 c->stream),
                   "d2h");
-        CHECK_HIP(hipStreamSynchronize(c->stream), "sync");
-        double a2 = 0.0, ab = 0.0, b2 = 0.0;
-        for (int k = 0; k < j; ++k) {
-          ca[k] = hh[k], cb[k] = hh[j + 1 + k];
-          a2 += ca[k] * ca[k], ab += ca[k] * cb[k], b2 += cb[k] * cb[k];
-        }
-        const double rho2 = hh[j] - a2;
-        if (!(rho2 > 0.0) || !std::isfinite(rho2)) {
+        CHECK_HIP(hipEventRecord(c->ev_coef, c->stream), "event");
+        CHECK_HIP(launch_dgs_update(c, V, ldv, n, j, coef, zf32 ? (float *)c->tIn : nullptr), "gram-schmidt update");
+        CHECK_HIP(hipEventSynchronize(c->ev_coef), "event sync");
+        if (hc[2 * j + 3] != 0.0) {  // rho^2 not positive: the update pass wrote nothing
           breakdown = true;
           break;
         }
-        const double rho = std::sqrt(rho2);
+        for (int k = 0; k < j; ++k) ca[k] = hc[k], cb[k] = hc[j + k];
+        const double rho = hc[2 * j];
         if (j == 0) {
           g0 = beta * rho;  // r = beta V_0 (as scaled) = beta rho v_0
         } else {
@@ -362,15 +369,11 @@ int fgmres(hyb_ctx *c, size_t n, size_t ldv, double *V, void *Zbuf, bool zf32, c
           prev[j] = eta_prev * rho;
         }
         double *col = &Hr[(size_t)j * (m + 1)];
-        const double hjj = (hh[2 * j + 1] - ab) / rho;
+        const double hjj = hc[2 * j + 1];
         for (int k = 0; k < j; ++k) col[k] = cb[k];
         col[j] = hjj;
-        const double eta2 = hh[2 * j + 2] - b2 - hjj * hjj;
-        const double eta = (eta2 > 0.0 && std::isfinite(eta2)) ? std::sqrt(eta2) : 0.0;
+        const double eta = hc[2 * j + 2];
         col[j + 1] = eta;
-        CHECK_HIP(launch_dgs_update(c, V, ldv, n, j, ca.data(), cb.data(), 1.0 / rho, hjj, eta > 0.0 ? 1.0 / eta : 0.0,
-                                    zf32 ? (float *)c->tIn : nullptr),
-                  "gram-schmidt update");
         eta_prev = eta;
         // Givens QR of columns 0..j
         std::fill(g.begin(), g.end(), 0.0);
@@ -970,7 +973,7 @@ int hyb_solve_noalloc(hyb_ctx *c, const double *b, double *lam, double rtol, int
     return fail(c, HYB_EINVAL,
                 "hyb_solve_noalloc covers order 0 without the learned stage or the Krylov coarse solve");
   if (c->prof) return fail(c, HYB_ESTATE, "hyb_solve_noalloc does not record profiling events");
-  if (!c->V || !c->Z || !c->hhost || c->m != c->p.restart || c->kR.size() < (size_t)(c->m + 1) * c->m)
+  if (!c->V || !c->Z || !c->hhost || !c->ev_coef || c->m != c->p.restart || c->kR.size() < (size_t)(c->m + 1) * c->m)
     return fail(c, HYB_ESTATE, "the Krylov basis for this restart length is not allocated (condense first)");
   if (!c->scratch) return fail(c, HYB_EHIP, "no static scratch on this device: " + c->scratch_err);
   int dev = -1;

@@ -153,6 +153,7 @@ struct hyb_ctx {
   double *partial = nullptr;  // [nblk_red][2*(m+2)]
   double *hdev = nullptr;   // [4*(m+2)]
   double *hhost = nullptr;  // pinned [4*(m+2)]
+  hipEvent_t ev_coef = nullptr;  // the read-back of a Gram-Schmidt step's coefficients has landed
   int nblk_red = 0;
   long reorth = 0;           // second Gram-Schmidt passes taken (diagnostics)
   // host side of the restart cycle (Hessenberg matrix, Givens rotations, least-squares solution),
@@ -256,9 +257,11 @@ hipError_t launch_gs_finish(hyb_ctx *c, const double *V, size_t lda, size_t n, i
                             double s);
 // Gram-Schmidt with delayed reorthogonalisation (steps j < kDgsMax): dots of V_j and V_{j+1}
 // against V_0..V_j and ||V_{j+1}||^2 (2 j + 3 values into out_dev: [V_k . V_j], [V_k . V_{j+1}],
-// ||V_{j+1}||^2); then V_j <- (V_j - sum_{k<j} ca_k V_k) rinv and
-// V_{j+1} <- (V_{j+1} - sum_{k<j} cb_k V_k - hjj V_j) einv in one pass (and its FP32 copy into wf
-// if wf is not null).
+// ||V_{j+1}||^2); the step's coefficients from them on the device (2 j + 6 values into coef: ca,
+// cb, rho, hjj, eta, breakdown flag, 1 / rho, 1 / eta); then V_j <- (V_j - sum_{k<j} ca_k V_k) / rho
+// and V_{j+1} <- (V_{j+1} - sum_{k<j} cb_k V_k - hjj V_j) / eta in one pass (and its FP32 copy into
+// wf if wf is not null), reading the coefficients from coef, so that no host round trip sits
+// between the reduction and the update.
 constexpr int kDgsMax = 31;
 // the basis vectors of V and Z start kBasisPad entries apart beyond their length, so that entry i
 // of the vectors does not fall on the same HBM channel for all of them (a leading dimension of
@@ -267,8 +270,9 @@ constexpr size_t kBasisPad = 256;
 // a restart cycle that leaves more than this fraction of the true residual counts as stalled
 constexpr double kStagnation = 0.999;
 hipError_t launch_dgs_dots(hyb_ctx *c, const double *V, size_t lda, size_t n, int j, double *out_dev);
-hipError_t launch_dgs_update(hyb_ctx *c, double *V, size_t lda, size_t n, int j, const double *ca, const double *cb, double rinv,
-                             double hjj, double einv, float *wf = nullptr);
+hipError_t launch_dgs_coef(hyb_ctx *c, const double *dots, int j, double *coef);
+hipError_t launch_dgs_update(hyb_ctx *c, double *V, size_t lda, size_t n, int j, const double *coef,
+                             float *wf = nullptr);
 // w -= sum_k h[k] a[k], then nrm_dev[0] = ||w||^2
 hipError_t launch_axpy_norm(hyb_ctx *c, const double *a, size_t lda, int nv, const double *h_dev, double *w,
                             size_t n, double *nrm_dev);

@@ -263,30 +263,60 @@ __global__ void __launch_bounds__(NW * 64) k_dgs_dots(const double *__restrict__
   }
 }
 
-struct DgsCoef {
-  double a[32], b[32];
-};
+// Coefficients of delayed Gram-Schmidt step j from its 2 j + 3 dot products d: with a_k = V_k . V_j
+// and b_k = V_k . V_{j+1} (k < j), rho^2 = V_j . V_j - sum a_k^2 is the squared norm of V_j after its
+// second orthogonalisation, hjj = (V_j . V_{j+1} - sum a_k b_k) / rho, and
+// eta^2 = V_{j+1} . V_{j+1} - sum b_k^2 - hjj^2 that of V_{j+1} after its first.
+// out: [0, j) a, [j, 2 j) b, then rho, hjj, eta, a breakdown flag (rho^2 not positive or not
+// finite), 1 / rho and 1 / eta (0 where eta is 0).  One lane, in the order written, without
+// contracted multiply-adds; the host reads the values back for the Hessenberg matrix.
+__global__ void k_dgs_coef(const double *__restrict__ d, int j, double *__restrict__ out) {
+#pragma clang fp contract(off)
+  if (threadIdx.x != 0) return;
+  double a2 = 0.0, ab = 0.0, b2 = 0.0;
+  for (int k = 0; k < j; ++k) {
+    const double a = d[k], b = d[j + 1 + k];
+    out[k] = a;
+    out[j + k] = b;
+    a2 += a * a;
+    ab += a * b;
+    b2 += b * b;
+  }
+  const double rho2 = d[j] - a2;
+  const bool bad = !(rho2 > 0.0) || !isfinite(rho2);
+  const double rho = bad ? 0.0 : sqrt(rho2);
+  const double hjj = bad ? 0.0 : (d[2 * j + 1] - ab) / rho;
+  const double eta2 = d[2 * j + 2] - b2 - hjj * hjj;
+  const double eta = (!bad && eta2 > 0.0 && isfinite(eta2)) ? sqrt(eta2) : 0.0;
+  out[2 * j] = rho;
+  out[2 * j + 1] = hjj;
+  out[2 * j + 2] = eta;
+  out[2 * j + 3] = bad ? 1.0 : 0.0;
+  out[2 * j + 4] = bad ? 0.0 : 1.0 / rho;
+  out[2 * j + 5] = eta > 0.0 ? 1.0 / eta : 0.0;
+}
 
-// The update pass: a_j <- (u - sum_{k<j} ca_k a_k) rinv (the reorthogonalised, normalised u) and
-// a_{j+1} <- (w - sum_{k<j} cb_k a_k - hjj a_j) einv (w orthogonalised once and scaled).
+// The update pass: a_j <- (u - sum_{k<j} ca_k a_k) / rho (the reorthogonalised, normalised u) and
+// a_{j+1} <- (w - sum_{k<j} cb_k a_k - hjj a_j) / eta (w orthogonalised once and scaled), with the
+// coefficients cf written by k_dgs_coef; nothing is written after a breakdown.
 template <int NV>
-__global__ void __launch_bounds__(kBlock) k_dgs_update(double *__restrict__ a, size_t lda, int j, DgsCoef cf,
-                                                       double rinv, double hjj, double einv, size_t n,
+__global__ void __launch_bounds__(kBlock) k_dgs_update(double *__restrict__ a, size_t lda, int j,
+                                                       const double *__restrict__ cf, size_t n,
                                                        float *__restrict__ wf) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (i >= n || cf[2 * j + 3] != 0.0) return;
   double su = 0.0, sw = 0.0;
 #pragma unroll
   for (int k = 0; k < NV; ++k)
     if (k < j) {
       const double v = __builtin_nontemporal_load(&a[(size_t)k * lda + i]);  // streamed
-      su += cf.a[k] * v;
-      sw += cf.b[k] * v;
+      su += cf[k] * v;
+      sw += cf[j + k] * v;
     }
   double *u = a + (size_t)j * lda, *w = a + (size_t)(j + 1) * lda;
-  const double vj = (u[i] - su) * rinv;
+  const double vj = (u[i] - su) * cf[2 * j + 4];
   u[i] = vj;
-  const double wn = (w[i] - sw - hjj * vj) * einv;
+  const double wn = (w[i] - sw - cf[2 * j + 1] * vj) * cf[2 * j + 5];
   w[i] = wn;
   if (wf) wf[i] = (float)wn;  // the FP32 input of the next preconditioner application (mixed form)
 }
@@ -400,8 +430,10 @@ hipError_t launch_dgs_dots(hyb_ctx *c, const double *V, size_t lda, size_t n, in
   // the j + 1 vectors a_0..a_j split over the waves of a workgroup, exactly as many accumulator
   // slots as needed (spare slots cost registers and occupancy): four waves up to j = 15, eight
   // beyond (five slots on four waves ran at 3.4 TB/s against 5.3 for four)
+  // eight-wave workgroups run best at half as many workgroups (j = 17: 362 us against 375, j = 20:
+  // 386 against 458)
   const int nw = j < 16 ? 4 : 8;
-  const unsigned nb = std::min<unsigned>(kRedBlocks, nblk(n, kDgsStage * 64 * nw));
+  const unsigned nb = std::min<unsigned>(nw == 4 ? kRedBlocks : kRedBlocks / 2, nblk(n, kDgsStage * 64 * nw));
   const int kw = (j + nw) / nw;
   switch (nw * 16 + kw) {
 #define HYB_DGS_CASE(W, K)                                                                                   \
@@ -419,22 +451,23 @@ hipError_t launch_dgs_dots(hyb_ctx *c, const double *V, size_t lda, size_t n, in
   return hipGetLastError();
 }
 
-hipError_t launch_dgs_update(hyb_ctx *c, double *V, size_t lda, size_t n, int j, const double *ca, const double *cb,
-                             double rinv,
-                             double hjj, double einv, float *wf) {
+hipError_t launch_dgs_coef(hyb_ctx *c, const double *dots, int j, double *coef) {
   if (j < 0 || j >= kDgsMax) return hipErrorInvalidValue;
-  DgsCoef cf{};
-  for (int k = 0; k < j; ++k) cf.a[k] = ca[k], cf.b[k] = cb[k];
+  int slot = prof_begin(c, F_KRYLOV);
+  hipLaunchKernelGGL(k_dgs_coef, dim3(1), dim3(64), 0, c->stream, dots, j, coef);
+  prof_end(c, F_KRYLOV, slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_dgs_update(hyb_ctx *c, double *V, size_t lda, size_t n, int j, const double *coef, float *wf) {
+  if (j < 0 || j >= kDgsMax) return hipErrorInvalidValue;
   int slot = prof_begin(c, F_KRYLOV);
   if (j < 8)
-    hipLaunchKernelGGL((k_dgs_update<8>), dim3(nblk(n)), dim3(kBlock), 0, c->stream, V, lda, j, cf, rinv, hjj, einv, n,
-                       wf);
+    hipLaunchKernelGGL((k_dgs_update<8>), dim3(nblk(n)), dim3(kBlock), 0, c->stream, V, lda, j, coef, n, wf);
   else if (j < 16)
-    hipLaunchKernelGGL((k_dgs_update<16>), dim3(nblk(n)), dim3(kBlock), 0, c->stream, V, lda, j, cf, rinv, hjj, einv, n,
-                       wf);
+    hipLaunchKernelGGL((k_dgs_update<16>), dim3(nblk(n)), dim3(kBlock), 0, c->stream, V, lda, j, coef, n, wf);
   else
-    hipLaunchKernelGGL((k_dgs_update<32>), dim3(nblk(n)), dim3(kBlock), 0, c->stream, V, lda, j, cf, rinv, hjj, einv, n,
-                       wf);
+    hipLaunchKernelGGL((k_dgs_update<32>), dim3(nblk(n)), dim3(kBlock), 0, c->stream, V, lda, j, coef, n, wf);
   prof_end(c, F_KRYLOV, slot);
   return hipGetLastError();
 }

@@ -357,28 +357,64 @@ __global__ void k_mg_factor(const double *__restrict__ H, double *__restrict__ f
 }
 
 // Coarse right-hand side b_c = R (b - H x) (Sec. 2.3): the 7-point residual of the four children of a
-// coarse cell, summed without going through memory; one thread per coarse cell.
+// coarse cell, summed without going through memory.  One thread per coarse column and chunk of kl
+// levels (consecutive threads take consecutive coarse columns of one chunk): the children's columns
+// and their horizontal neighbours are read once per chunk, and x of the children at the levels below
+// and above rides along in registers, so only the chunk's first level reloads them.  The arithmetic
+// and its order per coarse cell do not depend on kl.
 template <typename T>
-__global__ void k_mg_restrict_residual(const T *__restrict__ H, const T *__restrict__ b, const T *__restrict__ x,
-                                       T *__restrict__ bc, int nlev, int ncolf, int ncolc,
-                                       const int32_t *__restrict__ children, const int32_t *__restrict__ nbr) {
-  const int cc = blockIdx.x * blockDim.x + threadIdx.x;
-  if (cc >= nlev * ncolc) return;
-  const int k = cc / ncolc, P = cc - k * ncolc;
+__global__ void __launch_bounds__(kBlock) k_mg_restrict_residual(const T *__restrict__ H, const T *__restrict__ b,
+                                                                const T *__restrict__ x, T *__restrict__ bc, int nlev,
+                                                                int ncolf, int ncolc, int kl,
+                                                                const int32_t *__restrict__ children,
+                                                                const int32_t *__restrict__ nbr) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nchunk = (nlev + kl - 1) / kl;
+  if (t >= ncolc * nchunk) return;
+  const int ch = t / ncolc, P = t - ch * ncolc;
+  const int k0 = ch * kl, k1 = min(nlev, k0 + kl);
   const size_t n = (size_t)nlev * ncolf;
-  T s = 0;
+  int col[4], nb[4][4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const int col = children[(size_t)q * ncolc + P];
-    const size_t c = (size_t)k * ncolf + col;
-    T hx = H[c] * x[c];
+    col[q] = children[(size_t)q * ncolc + P];
 #pragma unroll
-    for (int f = 0; f < 4; ++f) hx += H[(1 + f) * n + c] * x[(size_t)k * ncolf + nbr[(size_t)f * ncolf + col]];
-    if (k > 0) hx += H[5 * n + c] * x[c - ncolf];
-    if (k < nlev - 1) hx += H[6 * n + c] * x[c + ncolf];
-    s += b[c] - hx;
+    for (int f = 0; f < 4; ++f) nb[q][f] = nbr[(size_t)f * ncolf + col[q]];
   }
-  bc[cc] = s;
+  T xd[4], x0[4];  // x of each child at levels k - 1 and k
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    xd[q] = k0 > 0 ? x[(size_t)(k0 - 1) * ncolf + col[q]] : T(0);
+    x0[q] = x[(size_t)k0 * ncolf + col[q]];
+  }
+#pragma unroll 2
+  for (int k = k0; k < k1; ++k) {
+    const size_t row = (size_t)k * ncolf;
+    T s = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const size_t c = row + col[q];
+      const T xu = k < nlev - 1 ? x[c + ncolf] : T(0);
+      T hx = H[c] * x0[q];
+#pragma unroll
+      for (int f = 0; f < 4; ++f) hx += H[(1 + f) * n + c] * x[row + nb[q][f]];
+      if (k > 0) hx += H[5 * n + c] * xd[q];
+      if (k < nlev - 1) hx += H[6 * n + c] * xu;
+      s += b[c] - hx;
+      xd[q] = x0[q];
+      x0[q] = xu;
+    }
+    bc[(size_t)k * ncolc + P] = s;
+  }
+}
+
+// Levels per thread of the restriction: the largest power of two up to 8 that still leaves about
+// 2^17 threads (measured on the 256x256x64 box: 77 us with 8 levels on the finest restriction
+// against 90 us with one thread per coarse cell, 17.4 us with 2 on the next; one level below that).
+inline int restrict_chunk(int nlev, int ncolc) {
+  int kl = 1;
+  while (kl < 8 && (size_t)ncolc * (size_t)(nlev / (2 * kl)) >= ((size_t)1 << 17)) kl *= 2;
+  return kl;
 }
 
 template <typename T>
@@ -466,8 +502,14 @@ __global__ void __launch_bounds__(kBlock) k_mg_sweep_pcr(const T *__restrict__ H
                                                         const int32_t *__restrict__ nbr,
                                                         const int32_t *__restrict__ parent, T omega,
                                                         const T *__restrict__ xprev, T c1) {
+  // Workgroups are dealt to the 8 XCDs in turn, each with its own L2; a 128-byte line of a [k][col]
+  // array holds 16 columns, i.e. 4 workgroups.  Hand every XCD a contiguous range of columns instead,
+  // so those 4 workgroups (and most horizontal neighbours) share one L2 (4096 columns: 14 us
+  // against 20 us).  Any bijection of the blocks gives the same result.
+  const int nb = gridDim.x;
+  const int blk = (nb & 7) == 0 ? (int)(blockIdx.x & 7) * (nb >> 3) + (int)(blockIdx.x >> 3) : (int)blockIdx.x;
   const int k = threadIdx.x & 63;
-  const int col = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int col = blk * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (col >= ncol) return;  // the whole wavefront
   const bool on = k < nlev;
   const size_t n = (size_t)nlev * ncol, c = (size_t)k * ncol + col;
@@ -601,7 +643,11 @@ __global__ void __launch_bounds__(kColBlock) k_mg_sweep_col(const T *__restrict_
   }
 }
 
-constexpr int kMgColKC = 4;  // levels whose loads a column issues together in the fused sweep
+// levels whose loads a column issues together in the fused sweep: 8 where the level fills at most
+// one wavefront per SIMD (65536 columns: 84 us against 87 with 4), 4 beyond, where a second
+// resident wavefront (the 8-level form needs all 256 registers) hides more of the latency
+constexpr int kMgColKC = 4, kMgColKCWide = 8;
+constexpr int kSimds = 1024;
 
 template <typename T>
 hipError_t mg_smooth(hyb_ctx *c, int l, const T *b, const T *xin, const T *xc, T *xout, int mode, T om,
@@ -635,12 +681,20 @@ hipError_t mg_smooth(hyb_ctx *c, int l, const T *b, const T *xin, const T *xc, T
   } else if (mode == 0) {
     hipLaunchKernelGGL((k_column_solve<T, true, false>), gc, bc, shm, c->stream, b, fac, n, xin, xc, xout, c->nlev,
                        Lv.ncol, ncolc, Lv.parent, om, (const int32_t *)nullptr, 0);
-  } else if (mode == 1) {
-    hipLaunchKernelGGL((k_mg_sweep_col<T, 1, kMgColKC>), gc, bc, shm, c->stream, H, b, xin, fac, xout, c->nlev,
-                       Lv.ncol, Lv.nbr, om, xprev, c1);
-  } else if (mode == 3) {
-    hipLaunchKernelGGL((k_mg_sweep_col<T, 3, kMgColKC>), gc, bc, shm, c->stream, H, b, xin, fac, xout, c->nlev,
-                       Lv.ncol, Lv.nbr, om, xprev, c1);
+  } else if (mode == 1 || mode == 3) {
+    const bool wide = (size_t)Lv.ncol <= (size_t)64 * kSimds;
+    if (mode == 1 && wide)
+      hipLaunchKernelGGL((k_mg_sweep_col<T, 1, kMgColKCWide>), gc, bc, shm, c->stream, H, b, xin, fac, xout, c->nlev,
+                         Lv.ncol, Lv.nbr, om, xprev, c1);
+    else if (mode == 1)
+      hipLaunchKernelGGL((k_mg_sweep_col<T, 1, kMgColKC>), gc, bc, shm, c->stream, H, b, xin, fac, xout, c->nlev,
+                         Lv.ncol, Lv.nbr, om, xprev, c1);
+    else if (wide)
+      hipLaunchKernelGGL((k_mg_sweep_col<T, 3, kMgColKCWide>), gc, bc, shm, c->stream, H, b, xin, fac, xout, c->nlev,
+                         Lv.ncol, Lv.nbr, om, xprev, c1);
+    else
+      hipLaunchKernelGGL((k_mg_sweep_col<T, 3, kMgColKC>), gc, bc, shm, c->stream, H, b, xin, fac, xout, c->nlev,
+                         Lv.ncol, Lv.nbr, om, xprev, c1);
   } else {
     // the coarse correction is injected into xin in place first (its caller drops xin after this
     // sweep): one streaming pass, then the plain sweep, which is cheaper than gathering the
@@ -649,8 +703,12 @@ hipError_t mg_smooth(hyb_ctx *c, int l, const T *b, const T *xin, const T *xc, T
     T *xw = const_cast<T *>(xin);
     hipLaunchKernelGGL((k_mg_prolong_add<T>), dim3(nblk(n)), dim3(kBlock), 0, c->stream, xw, xc, c->nlev, Lv.ncol,
                        ncolc, Lv.parent);
-    hipLaunchKernelGGL((k_mg_sweep_col<T, 1, kMgColKC>), gc, bc, shm, c->stream, H, b, (const T *)xw, fac, xout,
-                       c->nlev, Lv.ncol, Lv.nbr, om, xprev, c1);
+    if ((size_t)Lv.ncol <= (size_t)64 * kSimds)
+      hipLaunchKernelGGL((k_mg_sweep_col<T, 1, kMgColKCWide>), gc, bc, shm, c->stream, H, b, (const T *)xw, fac, xout,
+                         c->nlev, Lv.ncol, Lv.nbr, om, xprev, c1);
+    else
+      hipLaunchKernelGGL((k_mg_sweep_col<T, 1, kMgColKC>), gc, bc, shm, c->stream, H, b, (const T *)xw, fac, xout,
+                         c->nlev, Lv.ncol, Lv.nbr, om, xprev, c1);
   }
   prof_end(c, F_MG_SMOOTH, slot);
   return hipGetLastError();
@@ -701,8 +759,10 @@ hipError_t vcycle(hyb_ctx *c, int l) {
   LevelDev &Lc = c->lv[l + 1];
   const T *H = pick<T>(Lv.H, Lv.Hf);
   int slot = prof_begin(c, F_RESTRICT);
-  hipLaunchKernelGGL((k_mg_restrict_residual<T>), dim3(nblk((size_t)c->nlev * Lc.ncol)), dim3(kBlock), 0, c->stream,
-                     H, b, (const T *)Lv.x, (T *)Lc.b, c->nlev, Lv.ncol, Lc.ncol, Lc.children, Lv.nbr);
+  const int kl = restrict_chunk(c->nlev, Lc.ncol);
+  hipLaunchKernelGGL((k_mg_restrict_residual<T>), dim3(nblk((size_t)Lc.ncol * ((c->nlev + kl - 1) / kl))),
+                     dim3(kBlock), 0, c->stream, H, b, (const T *)Lv.x, (T *)Lc.b, c->nlev, Lv.ncol, Lc.ncol, kl,
+                     Lc.children, Lv.nbr);
   prof_end(c, F_RESTRICT, slot);
   HYB_TRY(hipGetLastError());
   HYB_TRY(vcycle<T>(c, l + 1));
@@ -974,7 +1034,9 @@ hipError_t configure_kernels(int nlev) {
       (const void *)k_column_solve<double, false, true>, (const void *)k_column_solve<float, true, false>,
       (const void *)k_column_solve<float, false, false>, (const void *)k_column_solve<float, false, true>,
       (const void *)k_mg_sweep_col<double, 1, kMgColKC>, (const void *)k_mg_sweep_col<double, 3, kMgColKC>,
-      (const void *)k_mg_sweep_col<float, 1, kMgColKC>, (const void *)k_mg_sweep_col<float, 3, kMgColKC>};
+      (const void *)k_mg_sweep_col<float, 1, kMgColKC>, (const void *)k_mg_sweep_col<float, 3, kMgColKC>,
+      (const void *)k_mg_sweep_col<double, 1, kMgColKCWide>, (const void *)k_mg_sweep_col<double, 3, kMgColKCWide>,
+      (const void *)k_mg_sweep_col<float, 1, kMgColKCWide>, (const void *)k_mg_sweep_col<float, 3, kMgColKCWide>};
   for (const void *f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, need);
     if (e != hipSuccess) return e;

@@ -389,3 +389,34 @@ def test_precondition_large_levels(name):
     say(f"[precondition] {name}: rel err {err:.2e} (cond(H) ~ {cond_h:.1e}, tol {tol:.1e})")
     assert err <= tol
     s.close()
+
+
+@pytest.mark.gpu
+def test_precondition_chunked_restriction():
+    """hyb_precondition where the finest restriction gives each thread a chunk of levels (1M cells:
+    4096 coarse columns x 67 levels, chunks of 2 with a ragged last one), against the oracle.  The
+    tolerance is 100 eps cond(H) with cond(H) taken on a 16x16 box of the same spacings and levels:
+    on a periodic box H splits into horizontal Fourier modes, the 16x16 box holds the modes of the
+    extreme eigenvalues (zero and Nyquist wavenumbers) of the 128x128 one, and a factor 2 covers the
+    5 % perturbation of the mesh."""
+    import scipy.sparse.linalg as spla
+    import torch
+
+    spec = dict(nx=128, ny=128, nlev=67, dx=5e3, dz=250.0, mg_levels=2, perturb=0.05)
+    say(f"[setup] chunked restriction: {spec}")
+    proxy = OracleProblem(make_box(**dict(spec, nx=16, ny=16)))
+    H = proxy.H.tocsc()
+    lu = spla.splu(H)
+    hinv = spla.LinearOperator(H.shape, matvec=lu.solve, rmatvec=lambda v: lu.solve(v, trans="T"))
+    cond_h = spla.onenormest(H) * spla.onenormest(hinv)
+    prob = make_box(**spec)
+    orc = OracleProblem(prob)
+    s = make_solver(prob)
+    r = np.random.default_rng(5).standard_normal(orc.mesh.ntrace)
+    z = torch.empty(orc.mesh.ntrace, dtype=torch.float64, device="cuda")
+    s.precondition(dev(r), z)
+    err = rel_max(host(z), orc.pc(r))
+    tol = 2 * 100 * np.finfo(float).eps * cond_h
+    say(f"[precondition] chunked restriction: rel err {err:.2e} (cond(H) ~ {cond_h:.1e}, tol {tol:.1e})")
+    assert err <= tol
+    s.close()
