@@ -151,15 +151,18 @@ typedef struct {
      accumulation; the default); 1 = FP32 activations on the vector units, kept as a reference for
      the BF16 path.  The stage inside hyb_solve always runs the BF16 inference passes. */
   int32_t nn_fp32;
-  /* failure injection for tests (0 in normal use): HYB_DEBUG_ZERO_GAMMA takes Gamma as zero, so the
-     coarse correction of Alg. 2 adds nothing and the cycle is its LineSmooth sweeps alone;
+  /* switches for tests (0 in normal use): HYB_DEBUG_ZERO_GAMMA takes Gamma as zero, so the coarse
+     correction of Alg. 2 adds nothing and the cycle is its LineSmooth sweeps alone;
      HYB_DEBUG_NAN_STAGE fills the learned stage's network output with NaN, so every correction
-     falls back to the plain cycle */
+     falls back to the plain cycle; HYB_DEBUG_UNPAIRED_RESTRICT makes the multigrid restriction
+     read every child through the children map even where the children of a coarse column come as
+     two pairs of adjacent columns (the results are the same bits) */
   int32_t debug;
 } hyb_params;
 
 #define HYB_DEBUG_ZERO_GAMMA 1
 #define HYB_DEBUG_NAN_STAGE 2
+#define HYB_DEBUG_UNPAIRED_RESTRICT 4
 
 typedef struct {
   int32_t iters;        /* FGMRES iterations (preconditioner applications) */

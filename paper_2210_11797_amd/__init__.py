@@ -11,6 +11,7 @@ from ._native import (  # noqa: F401
     GEOM_SHELL,
     HYB_BREAKDOWN,
     HYB_DEBUG_NAN_STAGE,
+    HYB_DEBUG_UNPAIRED_RESTRICT,
     HYB_DEBUG_ZERO_GAMMA,
     HYB_STAGNATED,
     HYB_NOT_CONVERGED,

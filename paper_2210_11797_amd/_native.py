@@ -21,6 +21,7 @@ HYB_NOT_CONVERGED = 1
 HYB_BREAKDOWN = 2
 HYB_DEBUG_ZERO_GAMMA = 1
 HYB_DEBUG_NAN_STAGE = 2
+HYB_DEBUG_UNPAIRED_RESTRICT = 4
 HYB_STAGNATED = 3
 PREC_FP64 = 0
 PREC_MIXED = 1

@@ -122,7 +122,8 @@ int check_params(hyb_ctx *c, const hyb_params *p) {
     return fail(c, HYB_EINVAL, "coarse_rtol must be in (0, 1)");
   if (p->smoother_patch != 0 && p->smoother_patch != 1) return fail(c, HYB_EINVAL, "smoother_patch must be 0 or 1");
   if (p->nn_fp32 != 0 && p->nn_fp32 != 1) return fail(c, HYB_EINVAL, "nn_fp32 must be 0 or 1");
-  if (p->debug & ~(HYB_DEBUG_ZERO_GAMMA | HYB_DEBUG_NAN_STAGE)) return fail(c, HYB_EINVAL, "unknown debug bits");
+  if (p->debug & ~(HYB_DEBUG_ZERO_GAMMA | HYB_DEBUG_NAN_STAGE | HYB_DEBUG_UNPAIRED_RESTRICT))
+    return fail(c, HYB_EINVAL, "unknown debug bits");
   if (p->smoother_patch && c->ncol > 0 && (c->order != 0 || c->nlevels < 2))  // (hyb_create checks it itself)
     return fail(c, HYB_EINVAL, "patch-cached column matrices need order 0 and a multigrid level of patches");
   if (p->omega_rot != 0.0 && c->geom != HYB_GEOM_SHELL)
@@ -198,6 +199,14 @@ int setup_level(hyb_ctx *c, const hyb_mesh *mesh, int l) {
     }
     for (int P = 0; P < ncol; ++P)
       if (cnt[P] != 4) return fail(c, HYB_EINVAL, "every coarse column needs 4 children");
+    // children as two pairs of adjacent columns, each starting at an even column of a level with an
+    // even column count (the box and the cubed sphere number their children that way): the
+    // restriction then loads each pair as one aligned vector
+    L.child_pairs = fine.ncol % 2 == 0;
+    for (int P = 0; P < ncol && L.child_pairs; ++P) {
+      const int32_t a = ch[P], b = ch[(size_t)ncol + P], e = ch[2 * (size_t)ncol + P], f = ch[3 * (size_t)ncol + P];
+      L.child_pairs = a % 2 == 0 && b == a + 1 && e % 2 == 0 && f == e + 1;
+    }
     if ((rc = upload(c, &L.children, ch)) || (rc = upload(c, &c->lv[l - 1].parent, par))) return rc;
   }
   size_t n = (size_t)ncol * c->nlev;

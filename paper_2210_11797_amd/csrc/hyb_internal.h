@@ -28,6 +28,7 @@ struct LevelDev {
   int32_t *est = nullptr;       // [8][nedge]: c0, c1, other 3 edges of c0, other 3 edges of c1
   int32_t *parent = nullptr;    // [ncol] -> column of level l+1 (nullptr on the coarsest level)
   int32_t *children = nullptr;  // [4][ncol] -> columns of level l-1 (nullptr on level 0)
+  bool child_pairs = false;     // children[1] = children[0] + 1 and children[3] = children[2] + 1, both even
   double *H = nullptr;          // [7][nlev*ncol] pressure stencil: diag, W, E, S, N, below, above
   float *Hf = nullptr;          // FP32 copy
   double *zf = nullptr;         // [3][nlev*ncol] LU factors of the column part H_z: l, 1/u, c/u

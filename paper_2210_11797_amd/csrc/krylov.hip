@@ -268,20 +268,20 @@ __global__ void __launch_bounds__(NW * 64) k_dgs_dots(const double *__restrict__
 // second orthogonalisation, hjj = (V_j . V_{j+1} - sum a_k b_k) / rho, and
 // eta^2 = V_{j+1} . V_{j+1} - sum b_k^2 - hjj^2 that of V_{j+1} after its first.
 // out: [0, j) a, [j, 2 j) b, then rho, hjj, eta, a breakdown flag (rho^2 not positive or not
-// finite), 1 / rho and 1 / eta (0 where eta is 0).  One lane, in the order written, without
-// contracted multiply-adds; the host reads the values back for the Hessenberg matrix.
-__global__ void k_dgs_coef(const double *__restrict__ d, int j, double *__restrict__ out) {
-#pragma clang fp contract(off)
-  if (threadIdx.x != 0) return;
-  double a2 = 0.0, ab = 0.0, b2 = 0.0;
-  for (int k = 0; k < j; ++k) {
-    const double a = d[k], b = d[j + 1 + k];
-    out[k] = a;
-    out[j + k] = b;
-    a2 += a * a;
-    ab += a * b;
-    b2 += b * b;
+// finite), 1 / rho and 1 / eta (0 where eta is 0).  One wavefront (j < 64): lane k loads a_k and
+// b_k, the three sums are fixed-order shuffle trees; the host reads the values back for the
+// Hessenberg matrix.
+__global__ void __launch_bounds__(64) k_dgs_coef(const double *__restrict__ d, int j, double *__restrict__ out) {
+  const int l = threadIdx.x;
+  double a = 0.0, b = 0.0;
+  if (l < j) {
+    a = d[l];
+    b = d[j + 1 + l];
+    out[l] = a;
+    out[j + l] = b;
   }
+  const double a2 = wave_sum(a * a), ab = wave_sum(a * b), b2 = wave_sum(b * b);
+  if (l != 0) return;
   const double rho2 = d[j] - a2;
   const bool bad = !(rho2 > 0.0) || !isfinite(rho2);
   const double rho = bad ? 0.0 : sqrt(rho2);

@@ -356,13 +356,26 @@ __global__ void k_mg_factor(const double *__restrict__ H, double *__restrict__ f
   }
 }
 
+// Two entries of a [k][col] array at an even column, read as one aligned vector.
+template <typename T>
+struct alignas(2 * sizeof(T)) Pair {
+  T a, b;
+};
+template <typename T>
+__device__ __forceinline__ Pair<T> ld_pair(const T *p) {
+  return *reinterpret_cast<const Pair<T> *>(p);
+}
+
 // Coarse right-hand side b_c = R (b - H x) (Sec. 2.3): the 7-point residual of the four children of a
 // coarse cell, summed without going through memory.  One thread per coarse column and chunk of kl
 // levels (consecutive threads take consecutive coarse columns of one chunk): the children's columns
 // and their horizontal neighbours are read once per chunk, and x of the children at the levels below
-// and above rides along in registers, so only the chunk's first level reloads them.  The arithmetic
-// and its order per coarse cell do not depend on kl.
-template <typename T>
+// and above rides along in registers, so only the chunk's first level reloads them.  PAIRED: the
+// children are columns c0, c0 + 1, c2, c2 + 1 with c0 and c2 even, and the stencil, b and x of each
+// pair are loaded as one vector, so a wavefront's loads cover whole cache lines (with single loads
+// every line is fetched by two instructions that each use half of it).  The arithmetic and its order
+// per coarse cell do not depend on kl or PAIRED.
+template <typename T, bool PAIRED>
 __global__ void __launch_bounds__(kBlock) k_mg_restrict_residual(const T *__restrict__ H, const T *__restrict__ b,
                                                                 const T *__restrict__ x, T *__restrict__ bc, int nlev,
                                                                 int ncolf, int ncolc, int kl,
@@ -375,34 +388,59 @@ __global__ void __launch_bounds__(kBlock) k_mg_restrict_residual(const T *__rest
   const int k0 = ch * kl, k1 = min(nlev, k0 + kl);
   const size_t n = (size_t)nlev * ncolf;
   int col[4], nb[4][4];
+  if (PAIRED) {
+    col[0] = children[P];
+    col[1] = col[0] + 1;
+    col[2] = children[(size_t)2 * ncolc + P];
+    col[3] = col[2] + 1;
+  } else {
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    col[q] = children[(size_t)q * ncolc + P];
+    for (int q = 0; q < 4; ++q) col[q] = children[(size_t)q * ncolc + P];
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
 #pragma unroll
     for (int f = 0; f < 4; ++f) nb[q][f] = nbr[(size_t)f * ncolf + col[q]];
-  }
-  T xd[4], x0[4];  // x of each child at levels k - 1 and k
+  // load the four children's entries of array a at level row `row` into v[0..3]
+  auto load4 = [&](const T *a, size_t row, T v[4]) {
+    if (PAIRED) {
+      const Pair<T> p0 = ld_pair(a + row + col[0]), p1 = ld_pair(a + row + col[2]);
+      v[0] = p0.a, v[1] = p0.b, v[2] = p1.a, v[3] = p1.b;
+    } else {
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    xd[q] = k0 > 0 ? x[(size_t)(k0 - 1) * ncolf + col[q]] : T(0);
-    x0[q] = x[(size_t)k0 * ncolf + col[q]];
-  }
+      for (int q = 0; q < 4; ++q) v[q] = a[row + col[q]];
+    }
+  };
+  T xd[4], x0[4];  // x of each child at levels k - 1 and k
+  if (k0 > 0)
+    load4(x, (size_t)(k0 - 1) * ncolf, xd);
+  else
+#pragma unroll
+    for (int q = 0; q < 4; ++q) xd[q] = T(0);
+  load4(x, (size_t)k0 * ncolf, x0);
 #pragma unroll 2
   for (int k = k0; k < k1; ++k) {
     const size_t row = (size_t)k * ncolf;
+    T xu[4], h[7][4], bv[4];
+    if (k < nlev - 1)
+      load4(x, row + ncolf, xu);
+    else
+#pragma unroll
+      for (int q = 0; q < 4; ++q) xu[q] = T(0);
+#pragma unroll
+    for (int s = 0; s < 7; ++s) load4(H + (size_t)s * n, row, h[s]);
+    load4(b, row, bv);
     T s = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const size_t c = row + col[q];
-      const T xu = k < nlev - 1 ? x[c + ncolf] : T(0);
-      T hx = H[c] * x0[q];
+      T hx = h[0][q] * x0[q];
 #pragma unroll
-      for (int f = 0; f < 4; ++f) hx += H[(1 + f) * n + c] * x[row + nb[q][f]];
-      if (k > 0) hx += H[5 * n + c] * xd[q];
-      if (k < nlev - 1) hx += H[6 * n + c] * xu;
-      s += b[c] - hx;
+      for (int f = 0; f < 4; ++f) hx += h[1 + f][q] * x[row + nb[q][f]];
+      if (k > 0) hx += h[5][q] * xd[q];
+      if (k < nlev - 1) hx += h[6][q] * xu[q];
+      s += bv[q] - hx;
       xd[q] = x0[q];
-      x0[q] = xu;
+      x0[q] = xu[q];
     }
     bc[(size_t)k * ncolc + P] = s;
   }
@@ -760,9 +798,14 @@ hipError_t vcycle(hyb_ctx *c, int l) {
   const T *H = pick<T>(Lv.H, Lv.Hf);
   int slot = prof_begin(c, F_RESTRICT);
   const int kl = restrict_chunk(c->nlev, Lc.ncol);
-  hipLaunchKernelGGL((k_mg_restrict_residual<T>), dim3(nblk((size_t)Lc.ncol * ((c->nlev + kl - 1) / kl))),
-                     dim3(kBlock), 0, c->stream, H, b, (const T *)Lv.x, (T *)Lc.b, c->nlev, Lv.ncol, Lc.ncol, kl,
-                     Lc.children, Lv.nbr);
+  const dim3 rg(nblk((size_t)Lc.ncol * ((c->nlev + kl - 1) / kl)));
+  auto al = [](const void *p) { return ((uintptr_t)p % (2 * sizeof(T))) == 0; };
+  if (Lc.child_pairs && !(p.debug & HYB_DEBUG_UNPAIRED_RESTRICT) && al(H) && al(b) && al(Lv.x))
+    hipLaunchKernelGGL((k_mg_restrict_residual<T, true>), rg, dim3(kBlock), 0, c->stream, H, b, (const T *)Lv.x,
+                       (T *)Lc.b, c->nlev, Lv.ncol, Lc.ncol, kl, Lc.children, Lv.nbr);
+  else
+    hipLaunchKernelGGL((k_mg_restrict_residual<T, false>), rg, dim3(kBlock), 0, c->stream, H, b, (const T *)Lv.x,
+                       (T *)Lc.b, c->nlev, Lv.ncol, Lc.ncol, kl, Lc.children, Lv.nbr);
   prof_end(c, F_RESTRICT, slot);
   HYB_TRY(hipGetLastError());
   HYB_TRY(vcycle<T>(c, l + 1));

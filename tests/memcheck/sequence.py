@@ -176,10 +176,22 @@ def solver_sequence(lib):
     z1 = np.empty(c.ntrace)
     c.call("hyb_precondition", P(b), P(z1))
     c.set(coarse_mode=0)
-    bad = N.Params(**{**c.params.__dict__, "debug": 4})
+    bad = N.Params(**{**c.params.__dict__, "debug": 8})
     cp_bad = bad.to_c()
     check(np.array_equal(z0, z1) and lib.hyb_set_params(c.h, ctypes.byref(cp_bad)) < 0,
           "Gamma = 0 gives the smoother-only cycle bit for bit; unknown debug bits rejected")
+    # the restriction reading child pairs as vectors and through the children map: same bits
+    for prec in (N.PREC_FP64, N.PREC_MIXED):
+        zz = []
+        for flag in (0, N.HYB_DEBUG_UNPAIRED_RESTRICT):
+            c.set(precision=prec, debug=flag)
+            zq = np.empty(c.ntrace)
+            c.call("hyb_precondition", P(b), P(zq))
+            rc, info, lam = c.solve(b, 1e-8)
+            zz.append((zq, info.iters, lam))
+        c.set(debug=0)
+        check(np.array_equal(zz[0][0], zz[1][0]) and zz[0][1] == zz[1][1] and np.array_equal(zz[0][2], zz[1][2]),
+              f"paired and unpaired restriction agree bit for bit (precision {prec}, {zz[0][1]} iterations)")
     c.set(precision=N.PREC_MIXED)
     c.call("hyb_profile", 1)
     c.solve(b, 1e-6)

@@ -317,6 +317,40 @@ def test_zero_gamma_switch_leaves_the_smoother_sweeps():
     s.close()
 
 
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("mesh", ["box_tiles", "sphere_c8x6"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_paired_restriction_matches_the_children_map(mesh, precision):
+    """Where the children of every coarse column are two pairs of adjacent columns (the box and the
+    cubed sphere number them so) the multigrid restriction loads each pair as one vector; with
+    HYB_DEBUG_UNPAIRED_RESTRICT it reads every child through the children map.  Same arithmetic in
+    the same order: the preconditioner and whole solves agree bit for bit, in both precisions."""
+    import torch
+
+    from paper_2210_11797_amd import HYB_DEBUG_UNPAIRED_RESTRICT
+    from synth import make_sphere
+
+    if mesh == "box_tiles":
+        prob = make_box(nx=24, ny=20, nlev=6, dx=5e3, dz=500.0, mg_levels=3, perturb=0.02)
+    else:
+        prob = make_sphere(8, 6, mg_levels=3, perturb=0.05)
+    s = make_solver(prob, precision=precision)
+    r = dev(np.random.default_rng(11).standard_normal(s.ntrace))
+    z, lam, its = {}, {}, {}
+    for flag in (0, HYB_DEBUG_UNPAIRED_RESTRICT):
+        p = s.params
+        p.debug = flag
+        s.set_params(p)
+        z[flag] = torch.empty_like(r)
+        s.precondition(r, z[flag])
+        lam[flag] = torch.zeros_like(r)
+        its[flag] = s.solve(r, lam[flag], rtol=1e-10, maxit=400)["iters"]
+    say(f"[paired restriction] {mesh} precision {precision}: {its[0]} iterations both ways")
+    assert torch.equal(z[0], z[HYB_DEBUG_UNPAIRED_RESTRICT])
+    assert its[0] == its[HYB_DEBUG_UNPAIRED_RESTRICT] and torch.equal(lam[0], lam[HYB_DEBUG_UNPAIRED_RESTRICT])
+    s.close()
+
 PATCH = {
     "ragged": dict(nx=12, ny=10, nlev=5, dx=7e3, dy=5e3, dz=400.0, mg_levels=2, perturb=0.1),
     "tiles_stretched": dict(nx=24, ny=20, nlev=12, dx=5e3, ztop=6e3, stretch="quadratic", mg_levels=3,
