@@ -504,24 +504,25 @@ __device__ __forceinline__ void dof_blk(int a, int &blk, int &r) {
   }
 }
 
-constexpr int kSW = 4;  // cells (wavefronts) per workgroup
-__global__ void __launch_bounds__(64 * kSW) k_p1_condense_struct(int ncell, const double *__restrict__ A,
-                                                                const double *__restrict__ cdiag,
-                                                                const double *__restrict__ kdiag,
-                                                                double *__restrict__ SK, double *__restrict__ fac,
-                                                                int write_sk) {
-  __shared__ double sMi[kSW][108], sG[kSW][288], sDr[kSW][288], sMiG[kSW][288], sDrMi[kSW][288], sSg[kSW][64],
-      sT[kSW][192], sCK[kSW][2 * NF];
+// One wavefront per cell, SW cells per workgroup.  LDS per cell: Mi, Dr, Mi G, Sg, the diagonals of
+// C_K and K_K, and T (first the trace-face columns of Dr Mi, then Sg^-1 times them in place): 988
+// doubles.  G is read from A_K where Mi G is formed rather than staged.
+template <int SW>
+__global__ void __launch_bounds__(64 * SW) k_p1_condense_struct(int ncell, const double *__restrict__ A,
+                                                               const double *__restrict__ cdiag,
+                                                               const double *__restrict__ kdiag,
+                                                               double *__restrict__ SK, double *__restrict__ fac,
+                                                               int write_sk) {
+  __shared__ double sMi[SW][108], sDr[SW][288], sMiG[SW][288], sSg[SW][64], sT[SW][192], sCK[SW][2 * NF];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int c = xcd_block() * kSW + wv;
+  const int c = xcd_block() * SW + wv;
   const bool active = c < ncell;
-  double *Mi = sMi[wv], *G = sG[wv], *Dr = sDr[wv], *MiG = sMiG[wv], *DrMi = sDrMi[wv], *Sg = sSg[wv], *T = sT[wv];
+  double *Mi = sMi[wv], *Dr = sDr[wv], *MiG = sMiG[wv], *Sg = sSg[wv], *T = sT[wv];
   const double *Ac = A + (size_t)c * NA;
   if (active) {
 #pragma unroll
     for (int e = lane; e < 288; e += 64) {
       const int a = e >> 3, p = e & 7;
-      G[e] = Ac[a * NX + NU + p];              // G[a][p]
       Dr[p * NU + a] = Ac[(NU + p) * NX + a];  // Dr[p][a]
     }
     if (lane < NF) sCK[wv][lane] = cdiag[(size_t)c * NF + lane];
@@ -543,22 +544,24 @@ __global__ void __launch_bounds__(64 * kSW) k_p1_condense_struct(int ncell, cons
     }
   }
   __syncthreads();
-  if (active)
-    for (int e = lane; e < 288; e += 64) {
+  if (active) {
+    for (int e = lane; e < 288; e += 64) {  // (Mi G)[a][p], G[a][p] = A_K[a][NU + p]
       int blk, r;
-      // (Mi G)[a][p]
       const int a = e >> 3, p = e & 7;
       dof_blk(a, blk, r);
       double s1 = 0.0;
-      for (int q = 0; q < 3; ++q) s1 += Mi[9 * blk + 3 * r + q] * G[blk_dof(blk, q) * 8 + p];
+      for (int q = 0; q < 3; ++q) s1 += Mi[9 * blk + 3 * r + q] * Ac[blk_dof(blk, q) * NX + NU + p];
       MiG[e] = s1;
-      // (Dr Mi)[p2][a2] stored at p2 * 36 + a2
-      const int p2 = e / NU, a2 = e - p2 * NU;
-      dof_blk(a2, blk, r);
-      double s2 = 0.0;
-      for (int q = 0; q < 3; ++q) s2 += Dr[p2 * NU + blk_dof(blk, q)] * Mi[9 * blk + 3 * q + r];
-      DrMi[e] = s2;
     }
+    for (int e = lane; e < 192; e += 64) {  // (Dr Mi)[p][f] for the trace-face dofs f < NF
+      int blk, r;
+      const int p = e / NF, f = e - p * NF;
+      dof_blk(f, blk, r);
+      double s2 = 0.0;
+      for (int q = 0; q < 3; ++q) s2 += Dr[p * NU + blk_dof(blk, q)] * Mi[9 * blk + 3 * q + r];
+      T[e] = s2;
+    }
+  }
   __syncthreads();
   if (active) {  // Sg = P - Dr (Mi G)
     const int p = lane >> 3, q = lane & 7;
@@ -584,22 +587,28 @@ __global__ void __launch_bounds__(64 * kSW) k_p1_condense_struct(int ncell, cons
     Sg[lane] = a;
   }
   __syncthreads();
+  double tv[3] = {0.0, 0.0, 0.0};  // T = Sg^-1 [Dr Mi]_F, formed in registers, then written over its input
   if (active)
-    for (int e = lane; e < 192; e += 64) {  // T = Sg^-1 [Dr Mi]_F
-      const int p = e / NF, f = e - p * NF;
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int e = lane + 64 * u, p = e / NF, f = e - p * NF;
       double s = 0.0;
-      for (int q = 0; q < 8; ++q) s += Sg[8 * p + q] * DrMi[q * NU + f];
-      T[e] = s;
+      for (int q = 0; q < 8; ++q) s += Sg[8 * p + q] * T[q * NF + f];
+      tv[u] = s;
     }
   __syncthreads();
-  // Writes: thread t takes cell w = t mod kSW of the workgroup, so each store covers kSW consecutive
-  // cells of 64 / kSW entries (32-byte pieces) instead of 64 scattered doubles.
-  const int w = threadIdx.x % kSW, c0 = c - wv;
+  if (active)
+#pragma unroll
+    for (int u = 0; u < 3; ++u) T[lane + 64 * u] = tv[u];
+  __syncthreads();
+  // Writes: thread t takes cell w = t mod SW of the workgroup, so each store covers SW consecutive
+  // cells of 64 / SW entries (8 SW-byte pieces) instead of 64 scattered doubles.
+  const int w = threadIdx.x % SW, c0 = c - wv;
   if (c0 + w >= ncell) return;
   const double *wMi = sMi[w], *wMiG = sMiG[w], *wT = sT[w], *wDr = sDr[w], *wSg = sSg[w];
   const size_t cw = (size_t)c0 + w;
   if (write_sk)
-    for (int e = threadIdx.x / kSW; e < NS; e += 64) {
+    for (int e = threadIdx.x / SW; e < NS; e += 64) {
       const int r = e / NF, f = e - r * NF;
       int br, pr, bf, pf;
       dof_blk(r, br, pr);
@@ -608,7 +617,7 @@ __global__ void __launch_bounds__(64 * kSW) k_p1_condense_struct(int ncell, cons
       for (int p = 0; p < 8; ++p) v += wMiG[r * 8 + p] * wT[p * NF + f];
       SK[(size_t)e * ncell + cw] = sCK[w][r] * v * sCK[w][NF + f];
     }
-  for (int e = threadIdx.x / kSW; e < NFAC; e += 64) {
+  for (int e = threadIdx.x / SW; e < NFAC; e += 64) {
     double v;
     if (e < FO_MIG) v = wMi[e];
     else if (e < FO_DR) v = wMiG[e - FO_MIG];
@@ -617,6 +626,11 @@ __global__ void __launch_bounds__(64 * kSW) k_p1_condense_struct(int ncell, cons
     fac[(size_t)e * ncell + cw] = v;
   }
 }
+
+#ifndef HYB_P1_SW
+#define HYB_P1_SW 8
+#endif
+constexpr int kSW = HYB_P1_SW;  // cells (wavefronts) per workgroup of the structured condensation
 
 // Thread per cell: X = A_K^-1 (R - [K lambda; 0]) from the structured factors.  mode 0: the cell's
 // share C_F [X_u]_F of B_lambda into bK [24][ncell]; mode 1: recovery into u [36][ncell], pi [8][ncell].
@@ -941,7 +955,7 @@ hipError_t p1_factor(hyb_ctx *c) {
     if (e) return e;
   }
   const int slot = prof_begin(c, F_P1_FACTOR);
-  hipLaunchKernelGGL(k_p1_condense_struct, dim3(nblk(c->ncell, kSW)), dim3(64 * kSW), 0, c->stream, c->ncell, s.A,
+  hipLaunchKernelGGL((k_p1_condense_struct<kSW>), dim3(nblk(c->ncell, kSW)), dim3(64 * kSW), 0, c->stream, c->ncell, s.A,
                      s.cdiag, s.kdiag, s.SK, s.fac, p1_sk_fp32(c) ? 0 : 1);
   prof_end(c, F_P1_FACTOR, slot);
   hipError_t e = hipGetLastError();
