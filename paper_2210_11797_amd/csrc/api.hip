@@ -356,7 +356,8 @@ int fgmres(hyb_ctx *c, size_t n, size_t ldv, double *V, void *Zbuf, bool zf32, c
         // and Givens work below overlaps the update pass
         double *coef = c->hdev + 2 * (size_t)(m + 2);
         const double *hc = hh + 2 * (size_t)(m + 2);
-        CHECK_HIP(launch_dgs_dots(c, V, ldv, n, j, c->hdev, coef), "gram-schmidt dots and coefficients");
+        CHECK_HIP(launch_dgs_dots(c, V, ldv, n, j, c->hdev), "gram-schmidt dots");
+        CHECK_HIP(launch_dgs_coef(c, c->hdev, j, coef), "gram-schmidt coefficients");
         CHECK_HIP(hipMemcpyAsync((void *)hc, coef, (2 * (size_t)j + 6) * sizeof(double), hipMemcpyDeviceToHost,
                                  c->stream),
                   "d2h");

@@ -258,7 +258,7 @@ hipError_t launch_gs_finish(hyb_ctx *c, const double *V, size_t lda, size_t n, i
                             double s);
 // Gram-Schmidt with delayed reorthogonalisation (steps j < kDgsMax): dots of V_j and V_{j+1}
 // against V_0..V_j and ||V_{j+1}||^2 (2 j + 3 values into out_dev: [V_k . V_j], [V_k . V_{j+1}],
-// ||V_{j+1}||^2) and, in the same launch, the step's coefficients from them (2 j + 6 values into coef: ca,
+// ||V_{j+1}||^2); the step's coefficients from them on the device (2 j + 6 values into coef: ca,
 // cb, rho, hjj, eta, breakdown flag, 1 / rho, 1 / eta); then V_j <- (V_j - sum_{k<j} ca_k V_k) / rho
 // and V_{j+1} <- (V_{j+1} - sum_{k<j} cb_k V_k - hjj V_j) / eta in one pass (and its FP32 copy into
 // wf if wf is not null), reading the coefficients from coef, so that no host round trip sits
@@ -270,8 +270,8 @@ constexpr int kDgsMax = 31;
 constexpr size_t kBasisPad = 256;
 // a restart cycle that leaves more than this fraction of the true residual counts as stalled
 constexpr double kStagnation = 0.999;
-hipError_t launch_dgs_dots(hyb_ctx *c, const double *V, size_t lda, size_t n, int j, double *out_dev,
-                           double *coef);
+hipError_t launch_dgs_dots(hyb_ctx *c, const double *V, size_t lda, size_t n, int j, double *out_dev);
+hipError_t launch_dgs_coef(hyb_ctx *c, const double *dots, int j, double *coef);
 hipError_t launch_dgs_update(hyb_ctx *c, double *V, size_t lda, size_t n, int j, const double *coef,
                              float *wf = nullptr);
 // w -= sum_k h[k] a[k], then nrm_dev[0] = ||w||^2

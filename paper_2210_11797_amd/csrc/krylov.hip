@@ -263,38 +263,25 @@ __global__ void __launch_bounds__(NW * 64) k_dgs_dots(const double *__restrict__
   }
 }
 
-// The reduction pass's fixed-order sums and the step's coefficients in one workgroup of kFinW
-// wavefronts: wavefront w sums outputs w, w + kFinW, ... over the nb workgroup partials (lane l
-// takes partials l, l + 64, ..., then a shuffle tree) into dots, then wavefront 0 forms the
-// coefficients of delayed Gram-Schmidt step j.  With d the 2 j + 3 dots, a_k = V_k . V_j and
-// b_k = V_k . V_{j+1} (k < j): rho^2 = V_j . V_j - sum a_k^2 is the squared norm of V_j after its
+// Coefficients of delayed Gram-Schmidt step j from its 2 j + 3 dot products d: with a_k = V_k . V_j
+// and b_k = V_k . V_{j+1} (k < j), rho^2 = V_j . V_j - sum a_k^2 is the squared norm of V_j after its
 // second orthogonalisation, hjj = (V_j . V_{j+1} - sum a_k b_k) / rho, and
 // eta^2 = V_{j+1} . V_{j+1} - sum b_k^2 - hjj^2 that of V_{j+1} after its first.
 // out: [0, j) a, [j, 2 j) b, then rho, hjj, eta, a breakdown flag (rho^2 not positive or not
-// finite), 1 / rho and 1 / eta (0 where eta is 0); the host reads them back for the Hessenberg
-// matrix.
-constexpr int kFinW = 16;
-__global__ void __launch_bounds__(64 * kFinW) k_dgs_final_coef(const double *__restrict__ partial, int nb, int j,
-                                                              double *__restrict__ dots, double *__restrict__ out) {
-  __shared__ double d[2 * kDgsMax + 3];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int k = w; k < 2 * j + 3; k += kFinW) {
-    double s = 0.0;
-    for (int b = lane; b < nb; b += 64) s += partial[(size_t)k * nb + b];
-    s = wave_sum(s);
-    if (lane == 0) d[k] = s, dots[k] = s;
-  }
-  __syncthreads();
-  if (w != 0) return;
+// finite), 1 / rho and 1 / eta (0 where eta is 0).  One wavefront (j < 64): lane k loads a_k and
+// b_k, the three sums are fixed-order shuffle trees; the host reads the values back for the
+// Hessenberg matrix.
+__global__ void __launch_bounds__(64) k_dgs_coef(const double *__restrict__ d, int j, double *__restrict__ out) {
+  const int l = threadIdx.x;
   double a = 0.0, b = 0.0;
-  if (lane < j) {
-    a = d[lane];
-    b = d[j + 1 + lane];
-    out[lane] = a;
-    out[j + lane] = b;
+  if (l < j) {
+    a = d[l];
+    b = d[j + 1 + l];
+    out[l] = a;
+    out[j + l] = b;
   }
   const double a2 = wave_sum(a * a), ab = wave_sum(a * b), b2 = wave_sum(b * b);
-  if (lane != 0) return;
+  if (l != 0) return;
   const double rho2 = d[j] - a2;
   const bool bad = !(rho2 > 0.0) || !isfinite(rho2);
   const double rho = bad ? 0.0 : sqrt(rho2);
@@ -311,7 +298,7 @@ __global__ void __launch_bounds__(64 * kFinW) k_dgs_final_coef(const double *__r
 
 // The update pass: a_j <- (u - sum_{k<j} ca_k a_k) / rho (the reorthogonalised, normalised u) and
 // a_{j+1} <- (w - sum_{k<j} cb_k a_k - hjj a_j) / eta (w orthogonalised once and scaled), with the
-// coefficients cf written by k_dgs_final_coef; nothing is written after a breakdown.
+// coefficients cf written by k_dgs_coef; nothing is written after a breakdown.
 template <int NV>
 __global__ void __launch_bounds__(kBlock) k_dgs_update(double *__restrict__ a, size_t lda, int j,
                                                        const double *__restrict__ cf, size_t n,
@@ -437,7 +424,7 @@ hipError_t launch_gs_finish(hyb_ctx *c, const double *V, size_t lda, size_t n, i
   return hipGetLastError();
 }
 
-hipError_t launch_dgs_dots(hyb_ctx *c, const double *V, size_t lda, size_t n, int j, double *out_dev, double *coef) {
+hipError_t launch_dgs_dots(hyb_ctx *c, const double *V, size_t lda, size_t n, int j, double *out_dev) {
   if (j < 0 || j >= kDgsMax || 2 * j + 3 > 2 * (c->m + 2)) return hipErrorInvalidValue;
   int slot = prof_begin(c, F_KRYLOV);
   // the j + 1 vectors a_0..a_j split over the waves of a workgroup, exactly as many accumulator
@@ -459,7 +446,15 @@ hipError_t launch_dgs_dots(hyb_ctx *c, const double *V, size_t lda, size_t n, in
     default:
       return hipErrorInvalidValue;
   }
-  hipLaunchKernelGGL(k_dgs_final_coef, dim3(1), dim3(64 * kFinW), 0, c->stream, c->partial, (int)nb, j, out_dev, coef);
+  hipLaunchKernelGGL(k_multidot_final, dim3(2 * j + 3), dim3(kBlock), 0, c->stream, c->partial, (int)nb, out_dev);
+  prof_end(c, F_KRYLOV, slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_dgs_coef(hyb_ctx *c, const double *dots, int j, double *coef) {
+  if (j < 0 || j >= kDgsMax) return hipErrorInvalidValue;
+  int slot = prof_begin(c, F_KRYLOV);
+  hipLaunchKernelGGL(k_dgs_coef, dim3(1), dim3(64), 0, c->stream, dots, j, coef);
   prof_end(c, F_KRYLOV, slot);
   return hipGetLastError();
 }
