@@ -524,72 +524,90 @@ hipError_t line_smooth(hyb_ctx *c, const T *S, const T *B, const T *lin, T *lout
 }
 
 constexpr int kPcrMaxColumns = 4096;
+// columns per workgroup of the cyclic-reduction sweep (swept on the 256x256x64 box, multigrid
+// smoothing per solve: 2 columns 7.5 ms, 4 columns 7.3, 8 columns 7.4, 16 columns 7.8; the form
+// with a lane per level reading its column directly, 7.6)
+constexpr int kPcrColumns = 4;
 
 // One block-Jacobi sweep of the pressure multigrid, fused: x_out = base + omega H_z^-1 (b - H X) with
 // X = 0 (MODE 0), xin (MODE 1) or xin plus the injected coarse correction xc[parent] (MODE 2), base = X;
-// MODE 3 is a step of the Chebyshev semi-iteration, base = X + c1 (X - xprev).
-// One wavefront per column, lane k = level k (nlev <= 64): the vertical neighbours of the residual
-// come from the adjacent lanes, and the tridiagonal column system (entries below / diagonal / above
-// = H slots 5, 0, 6) is solved by parallel cyclic reduction: at stride s every row eliminates its
-// couplings to rows k -/+ s, so after ceil(log2 nlev) steps it is diagonal.  Lanes k >= nlev carry
-// the identity row.
-template <typename T, int MODE>
-__global__ void __launch_bounds__(kBlock) k_mg_sweep_pcr(const T *__restrict__ H, const T *__restrict__ b,
-                                                        const T *__restrict__ xin, const T *__restrict__ xc,
-                                                        T *__restrict__ xout, int nlev, int ncol, int ncolc,
-                                                        const int32_t *__restrict__ nbr,
-                                                        const int32_t *__restrict__ parent, T omega,
-                                                        const T *__restrict__ xprev, T c1) {
-  // Workgroups are dealt to the 8 XCDs in turn, each with its own L2; a 128-byte line of a [k][col]
-  // array holds 16 columns, i.e. 4 workgroups.  Hand every XCD a contiguous range of columns instead,
-  // so those 4 workgroups (and most horizontal neighbours) share one L2 (4096 columns: 14 us
-  // against 20 us).  Any bijection of the blocks gives the same result.
+// MODE 3 is a step of the Chebyshev semi-iteration, base = X + c1 (X - xprev).  A workgroup takes CPB
+// consecutive columns of all levels (nlev <= 64) in three phases:
+//  1. thread (k, c) = (t / CPB, t mod CPB) forms the residual of level k of column c and the row's
+//     entries below / diagonal / above (H slots 5, 0, 6); a load covers CPB consecutive entries of
+//     a level, so the loads are coalesced;
+//  2. wavefront c takes column c, lane k = level k, and solves the tridiagonal column system by
+//     parallel cyclic reduction: at stride s every row eliminates its couplings to rows k -/+ s, so
+//     after ceil(log2 nlev) steps it is diagonal (lanes k >= nlev carry the identity row);
+//  3. thread (k, c) stores the result, again coalesced.
+// The rows meet in LDS with a stride of CPB + 1 entries.  The workgroups are handed to the 8 XCDs
+// (workgroup b runs on XCD b mod 8, each with its own L2) in contiguous ranges of columns, so that
+// horizontal neighbours mostly meet in one L2; any bijection of the blocks gives the same result.
+template <typename T, int MODE, int CPB>
+__global__ void __launch_bounds__(64 * CPB) k_mg_sweep_pcr(const T *__restrict__ H, const T *__restrict__ b,
+                                                          const T *__restrict__ xin, const T *__restrict__ xc,
+                                                          T *__restrict__ xout, int nlev, int ncol, int ncolc,
+                                                          const int32_t *__restrict__ nbr,
+                                                          const int32_t *__restrict__ parent, T omega,
+                                                          const T *__restrict__ xprev, T c1) {
+  constexpr int LS = CPB + 1;
+  __shared__ T sa[64 * LS], sb[64 * LS], sc[64 * LS], sd[64 * LS], sx[64 * LS];
   const int nb = gridDim.x;
   const int blk = (nb & 7) == 0 ? (int)(blockIdx.x & 7) * (nb >> 3) + (int)(blockIdx.x >> 3) : (int)blockIdx.x;
-  const int k = threadIdx.x & 63;
-  const int col = blk * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (col >= ncol) return;  // the whole wavefront
-  const bool on = k < nlev;
-  const size_t n = (size_t)nlev * ncol, c = (size_t)k * ncol + col;
-  auto X = [&](int cc) -> T {
+  const int col0 = blk * CPB;
+  const size_t n = (size_t)nlev * ncol;
+  auto X = [&](int k, int cc) -> T {
     T v = xin[(size_t)k * ncol + cc];
     if (MODE == 2) v += xc[(size_t)k * ncolc + parent[cc]];
     return v;
   };
-  T am = 0, bm = 1, cm = 0, dm = 0, xk = 0;
-  if (on) {
-    am = k > 0 ? H[5 * n + c] : T(0);
-    bm = H[c];
-    cm = k < nlev - 1 ? H[6 * n + c] : T(0);
-    dm = b[c];
-    if (MODE != 0) {
-      xk = X(col);
-      T hx = bm * xk;
+  {  // phase 1
+    const int k = threadIdx.x / CPB, cc = threadIdx.x - k * CPB, col = col0 + cc;
+    T am = 0, bm = 1, cm = 0, dm = 0, base = 0;
+    if (k < nlev && col < ncol) {
+      const size_t c = (size_t)k * ncol + col;
+      am = k > 0 ? H[5 * n + c] : T(0);
+      bm = H[c];
+      cm = k < nlev - 1 ? H[6 * n + c] : T(0);
+      dm = b[c];
+      if (MODE != 0) {
+        const T xk = X(k, col);
+        T hx = bm * xk;
 #pragma unroll
-      for (int f = 0; f < 4; ++f) hx += H[(1 + f) * n + c] * X(nbr[(size_t)f * ncol + col]);
-      dm -= hx;
+        for (int f = 0; f < 4; ++f) hx += H[(1 + f) * n + c] * X(k, nbr[(size_t)f * ncol + col]);
+        dm -= hx;
+        const T xdn = k > 0 ? X(k - 1, col) : T(0), xup = k < nlev - 1 ? X(k + 1, col) : T(0);
+        dm -= am * xdn + cm * xup;  // am = 0 at the ground, cm = 0 at the lid
+        base = xk;
+        if (MODE == 3) base += c1 * (xk - (xprev ? xprev[c] : T(0)));  // a null xprev is the zero vector
+      }
     }
+    const int s = k * LS + cc;
+    sa[s] = am, sb[s] = bm, sc[s] = cm, sd[s] = dm, sx[s] = base;
   }
-  if (MODE != 0) {
-    const T xdn = __shfl_up(xk, 1, 64), xup = __shfl_down(xk, 1, 64);
-    if (on) dm -= am * xdn + cm * xup;  // am = 0 at the ground, cm = 0 at the lid
+  __syncthreads();
+  {  // phase 2
+    const int k = threadIdx.x & 63, w = threadIdx.x >> 6, s = k * LS + w;
+    const bool on = k < nlev;
+    T am = sa[s], bm = sb[s], cm = sc[s], dm = sd[s];
+    for (int st = 1; st < nlev; st <<= 1) {
+      const T a1 = __shfl_up(am, st, 64), b1 = __shfl_up(bm, st, 64), c1u = __shfl_up(cm, st, 64),
+              d1 = __shfl_up(dm, st, 64);
+      const T a2 = __shfl_down(am, st, 64), b2 = __shfl_down(bm, st, 64), c2 = __shfl_down(cm, st, 64),
+              d2 = __shfl_down(dm, st, 64);
+      const bool lo = k >= st, hi = k + st < nlev;
+      const T al = (on && lo) ? -am / b1 : T(0), ga = (on && hi) ? -cm / b2 : T(0);
+      const T an = lo ? al * a1 : T(0), cn = hi ? ga * c2 : T(0);
+      const T bn = bm + (lo ? al * c1u : T(0)) + (hi ? ga * a2 : T(0));
+      const T dn = dm + (lo ? al * d1 : T(0)) + (hi ? ga * d2 : T(0));
+      if (on) am = an, bm = bn, cm = cn, dm = dn;
+    }
+    if (on) sx[s] = sx[s] + omega * (dm / bm);
   }
-  for (int st = 1; st < nlev; st <<= 1) {
-    const T a1 = __shfl_up(am, st, 64), b1 = __shfl_up(bm, st, 64), c1 = __shfl_up(cm, st, 64),
-            d1 = __shfl_up(dm, st, 64);
-    const T a2 = __shfl_down(am, st, 64), b2 = __shfl_down(bm, st, 64), c2 = __shfl_down(cm, st, 64),
-            d2 = __shfl_down(dm, st, 64);
-    const bool lo = k >= st, hi = k + st < nlev;
-    const T al = (on && lo) ? -am / b1 : T(0), ga = (on && hi) ? -cm / b2 : T(0);
-    const T an = lo ? al * a1 : T(0), cn = hi ? ga * c2 : T(0);
-    const T bn = bm + (lo ? al * c1 : T(0)) + (hi ? ga * a2 : T(0));
-    const T dn = dm + (lo ? al * d1 : T(0)) + (hi ? ga * d2 : T(0));
-    if (on) am = an, bm = bn, cm = cn, dm = dn;
-  }
-  if (on) {
-    T base = MODE == 0 ? T(0) : xk;
-    if (MODE == 3) base += c1 * (xk - (xprev ? xprev[c] : T(0)));  // a null xprev is the zero vector
-    xout[c] = base + omega * (dm / bm);
+  __syncthreads();
+  {  // phase 3
+    const int k = threadIdx.x / CPB, cc = threadIdx.x - k * CPB, col = col0 + cc;
+    if (k < nlev && col < ncol) xout[(size_t)k * ncol + col] = sx[k * LS + cc];
   }
 }
 
@@ -703,19 +721,20 @@ hipError_t mg_smooth(hyb_ctx *c, int l, const T *b, const T *xin, const T *xc, T
   // residual and a column-solve kernel); on large levels its shuffles and divisions make it compute
   // bound (65536 columns: 305 us against 69 + 35 us), and the lane-per-column sweep runs there
   if (c->nlev <= 64 && Lv.ncol <= kPcrMaxColumns) {
-    const dim3 gw(nblk(Lv.ncol, kBlock / 64)), bw(kBlock);
+    constexpr int CPB = kPcrColumns;
+    const dim3 gw(nblk(Lv.ncol, CPB)), bw(64 * CPB);
     if (mode == 0)
-      hipLaunchKernelGGL((k_mg_sweep_pcr<T, 0>), gw, bw, 0, c->stream, H, b, xin, xc, xout, c->nlev, Lv.ncol, ncolc,
-                         Lv.nbr, Lv.parent, om, xprev, c1);
+      hipLaunchKernelGGL((k_mg_sweep_pcr<T, 0, CPB>), gw, bw, 0, c->stream, H, b, xin, xc, xout, c->nlev, Lv.ncol,
+                         ncolc, Lv.nbr, Lv.parent, om, xprev, c1);
     else if (mode == 1)
-      hipLaunchKernelGGL((k_mg_sweep_pcr<T, 1>), gw, bw, 0, c->stream, H, b, xin, xc, xout, c->nlev, Lv.ncol, ncolc,
-                         Lv.nbr, Lv.parent, om, xprev, c1);
+      hipLaunchKernelGGL((k_mg_sweep_pcr<T, 1, CPB>), gw, bw, 0, c->stream, H, b, xin, xc, xout, c->nlev, Lv.ncol,
+                         ncolc, Lv.nbr, Lv.parent, om, xprev, c1);
     else if (mode == 2)
-      hipLaunchKernelGGL((k_mg_sweep_pcr<T, 2>), gw, bw, 0, c->stream, H, b, xin, xc, xout, c->nlev, Lv.ncol, ncolc,
-                         Lv.nbr, Lv.parent, om, xprev, c1);
+      hipLaunchKernelGGL((k_mg_sweep_pcr<T, 2, CPB>), gw, bw, 0, c->stream, H, b, xin, xc, xout, c->nlev, Lv.ncol,
+                         ncolc, Lv.nbr, Lv.parent, om, xprev, c1);
     else
-      hipLaunchKernelGGL((k_mg_sweep_pcr<T, 3>), gw, bw, 0, c->stream, H, b, xin, xc, xout, c->nlev, Lv.ncol, ncolc,
-                         Lv.nbr, Lv.parent, om, xprev, c1);
+      hipLaunchKernelGGL((k_mg_sweep_pcr<T, 3, CPB>), gw, bw, 0, c->stream, H, b, xin, xc, xout, c->nlev, Lv.ncol,
+                         ncolc, Lv.nbr, Lv.parent, om, xprev, c1);
   } else if (mode == 0) {
     hipLaunchKernelGGL((k_column_solve<T, true, false>), gc, bc, shm, c->stream, b, fac, n, xin, xc, xout, c->nlev,
                        Lv.ncol, ncolc, Lv.parent, om, (const int32_t *)nullptr, 0);
