@@ -523,7 +523,7 @@ hipError_t line_smooth(hyb_ctx *c, const T *S, const T *B, const T *lin, T *lout
   return hipGetLastError();
 }
 
-constexpr int kPcrMaxColumns = 4096;
+constexpr int kPcrMaxColumns = 16384;
 // columns per workgroup of the cyclic-reduction sweep (swept on the 256x256x64 box, multigrid
 // smoothing per solve: 2 columns 7.5 ms, 4 columns 7.3, 8 columns 7.4, 16 columns 7.8; the form
 // with a lane per level reading its column directly, 7.6)
@@ -716,10 +716,11 @@ hipError_t mg_smooth(hyb_ctx *c, int l, const T *b, const T *xin, const T *xc, T
   int ncolc = (l + 1 < c->nlevels) ? c->lv[l + 1].ncol : 1;
   dim3 gc(nblk(Lv.ncol, kColBlock)), bc(kColBlock);
   int slot = prof_begin(c, F_MG_SMOOTH);
-  // the sweep with cyclic reduction (a wavefront per column) pays on small levels, where a lane per
-  // column leaves the recurrence latency bound (1024 columns: 5.9 us against 4.4 + 12.1 us for a
-  // residual and a column-solve kernel); on large levels its shuffles and divisions make it compute
-  // bound (65536 columns: 305 us against 69 + 35 us), and the lane-per-column sweep runs there
+  // the sweep with cyclic reduction (a wavefront per column) pays on levels of up to 16384 columns,
+  // where a lane per column leaves the recurrence latency bound (256x256x64 box, multigrid smoothing
+  // per solve: 7.36 ms with cyclic reduction up to 4096 columns, 7.30 up to 16384); on larger levels
+  // its shuffles and divisions outweigh the latency it hides (up to 65536 columns: 9.34 ms), and the
+  // lane-per-column sweep runs there
   if (c->nlev <= 64 && Lv.ncol <= kPcrMaxColumns) {
     constexpr int CPB = kPcrColumns;
     const dim3 gw(nblk(Lv.ncol, CPB)), bw(64 * CPB);

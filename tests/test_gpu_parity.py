@@ -276,11 +276,11 @@ def test_edge_cases():
 
 
 WIDE = {
-    # 16384 columns on the fine level: its sweeps run one lane per column (residual and column solve
-    # fused); the coarse level of 4096 columns takes the wavefront-per-column sweeps
-    "wide128": dict(nx=128, ny=128, nlev=4, dx=5e3, dz=250.0, mg_levels=2, perturb=0.05),
-    # a coarsest level of 8192 columns: its Chebyshev steps run one lane per column as well
-    "wide_coarsest": dict(nx=256, ny=128, nlev=2, dx=5e3, dz=250.0, mg_levels=2, perturb=0.05),
+    # 32768 columns on the fine level: its sweeps run one lane per column (residual and column solve
+    # fused); the coarse level of 8192 columns takes the cyclic-reduction sweeps
+    "wide256": dict(nx=256, ny=128, nlev=4, dx=5e3, dz=250.0, mg_levels=2, perturb=0.05),
+    # a coarsest level of 32768 columns: its Chebyshev steps run one lane per column as well
+    "wide_coarsest": dict(nx=256, ny=256, nlev=2, dx=5e3, dz=250.0, mg_levels=2, perturb=0.05),
 }
 
 
@@ -401,7 +401,7 @@ def test_precondition_patch_cached_smoother(name, precision):
 @pytest.mark.gpu
 @pytest.mark.parametrize("name", list(WIDE))
 def test_precondition_large_levels(name):
-    """hyb_precondition on meshes whose multigrid levels have more than 4096 columns, against the
+    """hyb_precondition on meshes whose multigrid levels have more than 16384 columns, against the
     oracle, to 100 eps cond(H) (cond by the 1-norm estimate of H and H^-1)."""
     import scipy.sparse.linalg as spla
     import torch
