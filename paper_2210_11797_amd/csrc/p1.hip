@@ -723,6 +723,49 @@ __global__ void __launch_bounds__(kBlock) k_p1_cell_mv(int ncell, int ncol, int 
   }
 }
 
+// The same with FP32 entries and two cells of a layer per thread (ncol even): the entries of the
+// adjacent cells 2i and 2i + 1 sit side by side in the [entry][cell] layout, so one 8-byte load
+// takes both and a wavefront reads 512 contiguous bytes per entry instead of 256.  Per cell the
+// arithmetic and its order are those of k_p1_cell_mv<float>.
+typedef float p1_f2 __attribute__((ext_vector_type(2)));
+__global__ void __launch_bounds__(kBlock) k_p1_cell_mv_pair(int ncell, int ncol, int nedge, size_t nz,
+                                                           const int32_t *__restrict__ col_edge,
+                                                           const float *__restrict__ SK,
+                                                           const double *__restrict__ x, int mode,
+                                                           double *__restrict__ t) {
+  const int c = 2 * (blockIdx.x * blockDim.x + threadIdx.x);
+  if (c >= ncell) return;
+  auto ld2 = [&](size_t e) { return __builtin_nontemporal_load(reinterpret_cast<const p1_f2 *>(SK + e * ncell + c)); };
+  if (mode == 1) {
+#pragma unroll 4
+    for (int r = 0; r < NF; ++r) {
+      const p1_f2 v = ld2((size_t)r * NF + r);
+      t[(size_t)r * ncell + c] = v[0];
+      t[(size_t)r * ncell + c + 1] = v[1];
+    }
+    return;
+  }
+  const int k = c / ncol, col = c - k * ncol;
+  double xa[NF], xb[NF];
+#pragma unroll
+  for (int j = 0; j < NF; ++j) {
+    xa[j] = x[p1_dof(j, k, col, ncol, nedge, nz, col_edge)];
+    xb[j] = x[p1_dof(j, k, col + 1, ncol, nedge, nz, col_edge)];
+  }
+#pragma unroll 2
+  for (int r = 0; r < NF; ++r) {
+    double sa = 0.0, sb = 0.0;
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+      const p1_f2 v = ld2((size_t)r * NF + j);
+      sa += (double)v[0] * xa[j];
+      sb += (double)v[1] * xb[j];
+    }
+    t[(size_t)r * ncell + c] = sa;
+    t[(size_t)r * ncell + c + 1] = sb;
+  }
+}
+
 // Thread per trace row T = 4 F + i: the sum of the shares t_K of the (up to two) cells of facet F,
 // y = sum (sub = 0) or y = b - sum (sub = 1).  t is [24][ncell] (the cells' shares of S x, of
 // diag(S), or of B_lambda).
@@ -980,7 +1023,11 @@ hipError_t p1_rows(hyb_ctx *c, const double *x, double *y, int mode, const doubl
   const size_t ntr = (size_t)c->ntrace;
   int slot = prof_begin(c, F_TRACE_APPLY);
   if (mode != 1) {  // mode 1 gathers the shares already in bK
-    if (p1_sk_fp32(c) || (precond && c->p.precision == HYB_PREC_MIXED))
+    if ((p1_sk_fp32(c) || (precond && c->p.precision == HYB_PREC_MIXED)) && c->ncol % 2 == 0)
+      hipLaunchKernelGGL(k_p1_cell_mv_pair, dim3(nblk((size_t)c->ncell / 2)), dim3(kBlock), 0, c->stream, c->ncell,
+                         c->ncol, c->nedge, (size_t)c->nz, L0.col_edge, (const float *)s.SKf, x, mode == 3 ? 1 : 0,
+                         s.bK);
+    else if (p1_sk_fp32(c) || (precond && c->p.precision == HYB_PREC_MIXED))
       hipLaunchKernelGGL(k_p1_cell_mv<float>, dim3(nblk(c->ncell)), dim3(kBlock), 0, c->stream, c->ncell, c->ncol,
                          c->nedge, (size_t)c->nz, L0.col_edge, (const float *)s.SKf, x, mode == 3 ? 1 : 0, s.bK);
     else

@@ -39,6 +39,7 @@ def _prepare(outdir: str) -> list[str]:
                             "unsigned char *smem_raw = emu::dyn_smem();")
         text = text.replace("typedef float f32x4 __attribute__((ext_vector_type(4)));", "typedef emu_f32x4 f32x4;")
         text = text.replace("typedef short bf16x4 __attribute__((ext_vector_type(4)));", "typedef emu_bf16x4 bf16x4;")
+        text = text.replace("typedef float p1_f2 __attribute__((ext_vector_type(2)));", "typedef emu_f32x2 p1_f2;")
         text = text.replace("typedef float nn_f32x4 __attribute__((ext_vector_type(4)));", "typedef emu_f32x4 nn_f32x4;")
         text = text.replace("typedef short nn_bf16x4 __attribute__((ext_vector_type(4)));",
                             "typedef emu_bf16x4 nn_bf16x4;")

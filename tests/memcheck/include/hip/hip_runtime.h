@@ -168,6 +168,10 @@ inline emu_f32x4 emu_mfma_f32_16x16x16bf16_1k(emu_bf16x4 a, emu_bf16x4 b, emu_f3
   emu::wave_barrier();
   return c;
 }
+struct alignas(8) emu_f32x2 {
+  float v[2];
+  float operator[](int i) const { return v[i]; }
+};
 // bf16 16x16x32 (gfx950): a[j] = A[l%16][8(l/16)+j], b[j] = B[8(l/16)+j][l%16]; d as above
 struct emu_s16x8 {
   short v[8];
