@@ -725,21 +725,23 @@ __global__ void __launch_bounds__(kBlock) k_p1_cell_mv(int ncell, int ncol, int 
 
 // The same with FP32 entries and two cells of a layer per thread (ncol even): the entries of the
 // adjacent cells 2i and 2i + 1 sit side by side in the [entry][cell] layout, so one 8-byte load
-// takes both and a wavefront reads 512 contiguous bytes per entry instead of 256.  Per cell the
-// arithmetic and its order are those of k_p1_cell_mv<float>.
+// takes both and a wavefront reads 512 contiguous bytes per entry instead of 256 (0.24 ms against
+// 0.33 ms at 128^2x32; with FP64 entries the same pairing was slower, 0.53 ms against 0.48).  Per
+// cell the arithmetic and its order are those of k_p1_cell_mv<float>.
 typedef float p1_f2 __attribute__((ext_vector_type(2)));
 __global__ void __launch_bounds__(kBlock) k_p1_cell_mv_pair(int ncell, int ncol, int nedge, size_t nz,
                                                            const int32_t *__restrict__ col_edge,
                                                            const float *__restrict__ SK,
                                                            const double *__restrict__ x, int mode,
                                                            double *__restrict__ t) {
+  using V2 = p1_f2;
   const int c = 2 * (blockIdx.x * blockDim.x + threadIdx.x);
   if (c >= ncell) return;
-  auto ld2 = [&](size_t e) { return __builtin_nontemporal_load(reinterpret_cast<const p1_f2 *>(SK + e * ncell + c)); };
+  auto ld2 = [&](size_t e) { return __builtin_nontemporal_load(reinterpret_cast<const V2 *>(SK + e * ncell + c)); };
   if (mode == 1) {
 #pragma unroll 4
     for (int r = 0; r < NF; ++r) {
-      const p1_f2 v = ld2((size_t)r * NF + r);
+      const V2 v = ld2((size_t)r * NF + r);
       t[(size_t)r * ncell + c] = v[0];
       t[(size_t)r * ncell + c + 1] = v[1];
     }
@@ -757,7 +759,7 @@ __global__ void __launch_bounds__(kBlock) k_p1_cell_mv_pair(int ncell, int ncol,
     double sa = 0.0, sb = 0.0;
 #pragma unroll
     for (int j = 0; j < NF; ++j) {
-      const p1_f2 v = ld2((size_t)r * NF + j);
+      const V2 v = ld2((size_t)r * NF + j);
       sa += (double)v[0] * xa[j];
       sb += (double)v[1] * xb[j];
     }
@@ -1023,16 +1025,17 @@ hipError_t p1_rows(hyb_ctx *c, const double *x, double *y, int mode, const doubl
   const size_t ntr = (size_t)c->ntrace;
   int slot = prof_begin(c, F_TRACE_APPLY);
   if (mode != 1) {  // mode 1 gathers the shares already in bK
-    if ((p1_sk_fp32(c) || (precond && c->p.precision == HYB_PREC_MIXED)) && c->ncol % 2 == 0)
-      hipLaunchKernelGGL(k_p1_cell_mv_pair, dim3(nblk((size_t)c->ncell / 2)), dim3(kBlock), 0, c->stream, c->ncell,
-                         c->ncol, c->nedge, (size_t)c->nz, L0.col_edge, (const float *)s.SKf, x, mode == 3 ? 1 : 0,
-                         s.bK);
-    else if (p1_sk_fp32(c) || (precond && c->p.precision == HYB_PREC_MIXED))
-      hipLaunchKernelGGL(k_p1_cell_mv<float>, dim3(nblk(c->ncell)), dim3(kBlock), 0, c->stream, c->ncell, c->ncol,
-                         c->nedge, (size_t)c->nz, L0.col_edge, (const float *)s.SKf, x, mode == 3 ? 1 : 0, s.bK);
+    const bool f32 = p1_sk_fp32(c) || (precond && c->p.precision == HYB_PREC_MIXED);
+    const dim3 g2(nblk((size_t)c->ncell / 2)), g1(nblk(c->ncell));
+    if (f32 && c->ncol % 2 == 0)
+      hipLaunchKernelGGL(k_p1_cell_mv_pair, g2, dim3(kBlock), 0, c->stream, c->ncell, c->ncol, c->nedge,
+                         (size_t)c->nz, L0.col_edge, (const float *)s.SKf, x, mode == 3 ? 1 : 0, s.bK);
+    else if (f32)
+      hipLaunchKernelGGL(k_p1_cell_mv<float>, g1, dim3(kBlock), 0, c->stream, c->ncell, c->ncol, c->nedge,
+                         (size_t)c->nz, L0.col_edge, (const float *)s.SKf, x, mode == 3 ? 1 : 0, s.bK);
     else
-      hipLaunchKernelGGL(k_p1_cell_mv<double>, dim3(nblk(c->ncell)), dim3(kBlock), 0, c->stream, c->ncell, c->ncol,
-                         c->nedge, (size_t)c->nz, L0.col_edge, (const double *)s.SK, x, mode == 3 ? 1 : 0, s.bK);
+      hipLaunchKernelGGL(k_p1_cell_mv<double>, g1, dim3(kBlock), 0, c->stream, c->ncell, c->ncol, c->nedge,
+                         (size_t)c->nz, L0.col_edge, (const double *)s.SK, x, mode == 3 ? 1 : 0, s.bK);
   }
   hipLaunchKernelGGL(k_p1_gather, dim3(nblk(ntr)), dim3(kBlock), 0, c->stream, ntr, c->nlev, c->ncol, c->nedge,
                      (size_t)c->nz, L0.edge_col, L0.edge_lf, s.bK, b, y, mode == 2 ? 1 : 0);

@@ -16,6 +16,8 @@ CASES = {
     "3x2x3": dict(nx=3, ny=2, nlev=3, dx=5e3, dz=250.0, perturb=0.05),
     "8x6x5": dict(nx=8, ny=6, nlev=5, dx=5e3, dz=250.0, perturb=0.1, theta_col_perturb=0.02),
     "stretched": dict(nx=4, ny=4, nlev=9, dx=10e3, dz=None, stretch="quadratic", ztop=16e3),
+    # an odd number of columns: S x one cell per thread (two cells per thread where ncol is even)
+    "odd_3x3x4": dict(nx=3, ny=3, nlev=4, dx=5e3, dz=250.0, perturb=0.05),
 }
 
 
@@ -113,7 +115,7 @@ def test_p1_fullsize_sampled_rows():
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("size", ["8x6x5", "128x128x32"])
+@pytest.mark.parametrize("size", ["8x6x5", "odd_3x3x4", "128x128x32"])
 def test_p1_mfma_condensation_error_vs_fp64(size):
     """S_K condensed on matrix cores against the FP64 condensation: FP32 MFMA to 1e-5 and BF16 split
     hi + lo (three products, FP32 accumulation) to 1e-4 of the largest entry of S x; the elimination
@@ -123,8 +125,8 @@ def test_p1_mfma_condensation_error_vs_fp64(size):
 
     from paper_2210_11797_amd import PREC_FP64, PREC_MFMA_BF16X, PREC_MFMA_FP32
 
-    if size == "8x6x5":
-        prob = _box(CASES["8x6x5"])
+    if size in CASES:
+        prob = _box(CASES[size])
     else:
         prob = make_box(nx=128, ny=128, nlev=32, dx=10e3, dz=500.0, mg_levels=1)
     rng = np.random.default_rng(8)
