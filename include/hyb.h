@@ -37,7 +37,8 @@
  * Krylov basis), allocated by hyb_create / hyb_assemble_local / hyb_condense
  * and freed by hyb_destroy.  Calls enqueue work on the context's stream and
  * return without synchronising, except hyb_solve, which reads one small
- * vector back to the host per iteration for its stopping test.
+ * vector back to the host per iteration for its stopping test (the step's
+ * Gram-Schmidt coefficients, read while the GPU runs the step's update).
  *
  * Errors: every call returns HYB_OK (0) or a negative code; no exception or
  * abort crosses the ABI.  hyb_last_error gives the text of the last error of
