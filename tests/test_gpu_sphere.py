@@ -88,6 +88,34 @@ def test_sphere_precondition(name):
 
 
 @pytest.mark.gpu
+def test_sphere_patch_cached_smoother():
+    """LineSmooth with the column matrices cached per 2x2 patch (future work of Sec. 4.2) on the
+    rotating C8 x 6 sphere, where the cells of a patch differ: the preconditioner against the
+    oracle's variant (100 eps cond(H)), which moves z away from the per-column smoother, and FGMRES
+    with it to 1e-10."""
+    import torch
+
+    prob = make_sphere(**CASES["c8"])
+    orc = OracleProblem(prob, with_mixed=False, smoother_patch=True)
+    s = make_solver(prob, smoother_patch=1)
+    r = np.random.default_rng(7).standard_normal(orc.mesh.ntrace)
+    z = torch.empty(orc.mesh.ntrace, dtype=torch.float64, device="cuda")
+    s.precondition(dev(r), z)
+    ref = orc.pc(r)
+    err = rel_max(host(z), ref)
+    moved = rel_max(OracleProblem(prob, with_mixed=False).pc(r), ref)
+    tol = max(1e-11, 100 * np.finfo(float).eps * np.linalg.cond(orc.H.toarray()))
+    b = dev(np.random.default_rng(8).standard_normal(orc.mesh.ntrace))
+    lam = torch.zeros_like(b)
+    info = s.solve(b, lam, rtol=1e-10, maxit=400)
+    say(f"[sphere, patch] preconditioner rel err {err:.2e} (tol {tol:.1e}; the variant moves z by {moved:.1e}); "
+        f"FGMRES {info['iters']} iterations, residual {info['rel_res']:.1e}")
+    assert err <= tol and moved > 10 * tol
+    assert info["status"] == 0 and info["rel_res"] <= 1e-10
+    s.close()
+
+
+@pytest.mark.gpu
 @pytest.mark.parametrize("name", ["c8", "c6", "c16", "c1", "c2x1"])
 def test_sphere_solve_matches_direct(name):
     """FP64 solve to rtol 1e-15 against the oracle's sparse direct solutions (lambda; (u, Pi) of the
