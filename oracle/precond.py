@@ -37,6 +37,12 @@ details to earlier work and prints one sign that diverges):
 * Prolongation to a facet on the ground or lid is one sided (the value of the
   single adjacent cell), so the restriction weight there is 1 (1/2 elsewhere).
 
+Coarse-space devices (measurements, not part of the path): the conforming
+vertex (Q1) coarse space that Sec. 4.2 names, read as the trilinear function on
+the hexahedral box whose facet value is its mean over the facet; the
+agglomerated cell spaces of the multigrid levels; Alg. 2 with an exact Galerkin
+coarse solve; and the best correction in a space after a given cycle.
+
 Parity: the smoother, V-cycle and two-level cycle are fixed linear maps;
 they are pinned by tests against textbook limits (exact column solves when
 the horizontal coupling vanishes, convergence of the stationary iterations,
@@ -255,3 +261,88 @@ class TwoLevel:
             dpi = self.mg.vcycle(Bbar)
         lam = lam + self.P @ dpi
         return self.line_smooth(lam, B, self.n_post)
+
+
+def vertex_trace_prolongation(mesh: BoxMesh):
+    """P_v: vertex values -> trace facets, lambda_F = the mean over F of the trilinear (Q1)
+    function with those vertex values, i.e. the average of the facet's four corners.
+
+    The conforming piecewise linear coarse space that Sec. 4.2 names as an alternative to the
+    piecewise constant one, in its tensor-product form on the extruded hexahedral box: one value per
+    vertex, vertex (k, ix, iy) at height z[k] on the south-west corner of column (ix, iy), numbered
+    k * ncol + iy * nx + ix (periodic in x and y, levels 0..L)."""
+    L, nx, ny, ncol = mesh.nlev, mesh.nx, mesh.ny, mesh.ncol
+
+    def vert(k, ix, iy):
+        return k * ncol + (iy % ny) * nx + (ix % nx)
+
+    k = np.arange(L + 1)[:, None, None]
+    iy = np.arange(ny)[None, :, None]
+    ix = np.arange(nx)[None, None, :]
+    rows, cols = [], []
+    zf = np.broadcast_to(mesh.zface(k, ix, iy), (L + 1, ny, nx))
+    for a, b in ((0, 0), (1, 0), (0, 1), (1, 1)):
+        rows.append(zf.ravel())
+        cols.append(np.broadcast_to(vert(k, ix + a, iy + b), zf.shape).ravel())
+    k = k[:-1]
+    xf = np.broadcast_to(mesh.xface(k, ix, iy), (L, ny, nx))
+    yf = np.broadcast_to(mesh.yface(k, ix, iy), (L, ny, nx))
+    for dk in (0, 1):
+        for b in (0, 1):  # the west facet spans the corners (ix, iy) and (ix, iy + 1)
+            rows.append(xf.ravel())
+            cols.append(np.broadcast_to(vert(k + dk, ix, iy + b), xf.shape).ravel())
+        for a in (0, 1):  # the south facet spans the corners (ix, iy) and (ix + 1, iy)
+            rows.append(yf.ravel())
+            cols.append(np.broadcast_to(vert(k + dk, ix + a, iy), yf.shape).ravel())
+    rows, cols = np.concatenate(rows), np.concatenate(cols)
+    return sp.csr_matrix((np.full(rows.size, 0.25), (rows, cols)), shape=(mesh.ntrace, ncol * (L + 1)))
+
+
+def agglomerated_cell_injection(mesh: BoxMesh, parents):
+    """Q_l: cells of the 2^l x 2^l agglomerated level -> fine cells (injection), for the parent maps
+    of the horizontal agglomeration (one per level below the finest); no vertical coarsening."""
+    cols = np.arange(mesh.ncol)
+    for par in parents:
+        cols = np.asarray(par)[cols]
+    ncl = int(cols.max()) + 1
+    rows = np.arange(mesh.ncell)
+    return sp.csr_matrix((np.ones(rows.size), (rows, (rows // mesh.ncol) * ncl + cols[rows % mesh.ncol])),
+                         shape=(mesh.ncell, mesh.nlev * ncl))
+
+
+class GalerkinTwoLevel:
+    """Alg. 2 with LineSmooth (Alg. 1) as in ``TwoLevel``, the coarse space given by its
+    prolongation P_c to the trace space and the coarse system solved exactly: after the
+    pre-smoothing, lambda += P_c (P_c^T S P_c)^-1 P_c^T (B - S lambda).  With P_c = P (the DG0
+    space) this is the best correction that space admits; with ``vertex_trace_prolongation`` it is
+    the conforming coarse space of Sec. 4.2.  A measuring device for what a coarse space could
+    give at best, not a method to run at scale (a sparse LU of the coarse system)."""
+
+    def __init__(self, smoother: TwoLevel, Pc):
+        self.sm = smoother
+        self.Pc = sp.csr_matrix(Pc)
+        self.A = (self.Pc.T @ smoother.S @ self.Pc).tocsc()
+        self.lu = spla.splu(self.A)
+
+    def __call__(self, B):
+        sm = self.sm
+        lam = sm.line_smooth(np.zeros_like(B), B, sm.n_pre)
+        R = B - sm.S @ lam
+        lam = lam + self.Pc @ self.lu.solve(self.Pc.T @ R)
+        return sm.line_smooth(lam, B, sm.n_post)
+
+
+class BestCorrectionAfter:
+    """The best correction in a coarse space after a preconditioner M: z = M(B), then
+    z += P_c (P_c^T S P_c)^-1 P_c^T (B - S z).  The upper bound on what any correction stage
+    placed after the coarse correction of Alg. 2 can do with its output confined to the range of
+    P_c (the S-orthogonal projection of the remaining error onto that range)."""
+
+    def __init__(self, M, S, Pc):
+        self.M, self.S = M, sp.csr_matrix(S)
+        self.Pc = sp.csr_matrix(Pc)
+        self.lu = spla.splu((self.Pc.T @ self.S @ self.Pc).tocsc())
+
+    def __call__(self, B):
+        z = self.M(B)
+        return z + self.Pc @ self.lu.solve(self.Pc.T @ (B - self.S @ z))
