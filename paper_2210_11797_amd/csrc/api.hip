@@ -751,7 +751,7 @@ int hyb_assemble_local(hyb_ctx *c, const double *theta_w, const double *exner_ha
   if (c->order == 1) {
     hyb::P1State &s = c->p1;
     const size_t nc = (size_t)c->ncell;
-    if ((rc = dalloc(c, &s.A, 44 * 44 * nc)) || (rc = dalloc(c, &s.cdiag, 24 * nc)) ||
+    if ((rc = dalloc(c, &s.A, 748 * nc)) || (rc = dalloc(c, &s.cdiag, 24 * nc)) ||
         (rc = dalloc(c, &s.kdiag, 24 * nc)) || (rc = dalloc(c, &s.SK, 24 * 24 * nc)) || (rc = dalloc(c, &s.bK, 24 * nc)) ||
         (rc = dalloc(c, &s.fac, 748 * nc)) || (rc = dalloc(c, &s.SKf, 24 * 24 * nc)))
       return rc;

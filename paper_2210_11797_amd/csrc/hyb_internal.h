@@ -86,7 +86,7 @@ struct NNState {
 // p = 1 system (p1.hip): cell data per cell (array of structures)
 struct P1State {
   double *tbl = nullptr;    // reference tables of the assembly
-  double *A = nullptr;      // [ncell][44][44] A_K
+  double *A = nullptr;      // [ncell][748] the entries of A_K left non-zero by its block structure
   double *cdiag = nullptr;  // [ncell][24] diagonal of C_K on the face dofs
   double *kdiag = nullptr;  // [ncell][24] diagonal of K_K
   double *SK = nullptr;     // [24 x 24][ncell] S_K = C_K [A_K^-1]_ff K_K, entry (r, j) at (r * 24 + j) * ncell

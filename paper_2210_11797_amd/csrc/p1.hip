@@ -8,8 +8,8 @@
 // and top facets, the cell values of Pi* and rho*), so the assembly multiplies reference tables --
 // integrals of products of the reference basis functions, computed once on the host with exact
 // Gauss rules -- by per-cell scalars.  Cell data are stored per cell (array of structures): one
-// wavefront owns one cell in the assembly and the condensation, and reads its 44 x 44 block
-// contiguously.  The condensed blocks S_K are stored entry by entry over
+// wavefront owns one cell in the assembly and the condensation, and reads the 748 entries of A_K
+// that the block structure leaves non-zero contiguously.  The condensed blocks S_K are stored entry by entry over
 // the cells ([24 x 24][ncell]): the trace rows of consecutive cells then read consecutive addresses.
 //
 // Dof order per cell: velocity face dofs 4 f + i (f = W, E, S, N, B, T; face point i = 2 t1 + t2
@@ -24,7 +24,7 @@ namespace hyb {
 
 namespace {
 
-constexpr int NU = 36, NPR = 8, NF = 24, NX = 44, NA = NX * NX, NS = NF * NF;
+constexpr int NU = 36, NPR = 8, NF = 24, NX = 44, NS = NF * NF;
 
 inline unsigned nblk(size_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
 
@@ -155,7 +155,59 @@ __device__ __forceinline__ int xcd_block() {
   return x * base + (x < rem ? x : rem) + b / kXcd;
 }
 
-// One wavefront per cell writes A_K (44 x 44, row-major) and the diagonals of C_K and K_K.
+// The velocity block M = m2 - q22 of an axis-aligned cell in twelve 3 x 3 blocks: block 4 d + i holds the
+// two face functions and the interior function of direction d at tangential point i.
+__device__ __forceinline__ int blk_dof(int blk, int r) {  // dof of position r (0: "-" face, 1: "+" face, 2: interior)
+  const int d = blk >> 2, i = blk & 3;
+  return r == 0 ? 8 * d + i : (r == 1 ? 8 * d + 4 + i : 24 + 4 * d + i);
+}
+__device__ __forceinline__ void dof_blk(int a, int &blk, int &r) {
+  if (a < 24) {
+    const int f = a >> 2, i = a & 3;
+    blk = 4 * (f >> 1) + i, r = f & 1;
+  } else {
+    blk = a - 24, r = 2;  // 24 + 4 d + i  ->  block 4 d + i
+  }
+}
+
+// A_K as the library keeps it: the entries that the block structure of an axis-aligned cell leaves
+// non-zero (M block diagonal in the twelve 3 x 3 blocks, the pressure block diagonal), cell by cell
+// ([ncell][NAC]: the condensation kernels give each cell a wavefront, whose loads then stay inside
+// the cell's 6 KB; laid out entry by entry over the cells they ran 1.2-1.4x slower): block b of M at
+// AO_M + 9 b + 3 r + q (rows and columns blk_dof(b, .)), G (velocity row a, pressure column p) at
+// AO_G + 8 a + p, the pressure rows Dr = q32 + M3^rho M3^-1 D at AO_DR + 36 p + a, the pressure
+// block at AO_P + 8 p + q.  Every other entry of the 44 x 44 matrix is zero.
+constexpr int AO_M = 0, AO_G = 108, AO_DR = AO_G + 288, AO_P = AO_DR + 288, NAC = AO_P + 64;
+
+// position of entry (i, j) of A_K in the compact layout, -1 where the structure makes it zero
+__device__ __forceinline__ int a_compact(int i, int j) {
+  if (i < NU && j < NU) {
+    int bi, ri, bj, rj;
+    dof_blk(i, bi, ri);
+    dof_blk(j, bj, rj);
+    return bi == bj ? AO_M + 9 * bi + 3 * ri + rj : -1;
+  }
+  if (i < NU) return AO_G + NPR * i + (j - NU);
+  if (j < NU) return AO_DR + NU * (i - NU) + j;
+  return AO_P + NPR * (i - NU) + (j - NU);
+}
+
+// entry (i, j) of A_K at position e of the compact layout
+__device__ __forceinline__ void a_entry_of(int e, int &i, int &j) {
+  if (e < AO_G) {
+    const int b = e / 9, r = (e % 9) / 3;
+    i = blk_dof(b, r), j = blk_dof(b, e % 3);
+  } else if (e < AO_DR) {
+    i = (e - AO_G) / NPR, j = NU + (e - AO_G) % NPR;
+  } else if (e < AO_P) {
+    i = NU + (e - AO_DR) / NU, j = (e - AO_DR) % NU;
+  } else {
+    i = NU + (e - AO_P) / NPR, j = NU + (e - AO_P) % NPR;
+  }
+}
+
+// One wavefront per cell writes the compact A_K (its lanes along the entries) and the diagonals of
+// C_K and K_K ([ncell][24]).
 __global__ void __launch_bounds__(kBlock) k_p1_assemble(int ncell, int ncol, const double *__restrict__ dz, double dx,
                                                         double dy, const double *__restrict__ theta_w,
                                                         const double *__restrict__ exner_hat_w,
@@ -173,11 +225,12 @@ __global__ void __launch_bounds__(kBlock) k_p1_assemble(int ncell, int ncol, con
   const double h[3] = {q.hx, q.hy, q.hz};
   const double c22 = tu * tt * dt * dt * cp * q.dpi * dth * vol, cg = -tu * dt * cp * vol, cd = tr * dt * vol;
   const double G0 = 0.5 - 0.5 / sqrt(3.0), G1 = 0.5 + 0.5 / sqrt(3.0);
-  double *Ac = A + (size_t)c * NA;
-  for (int e = lane; e < NA; e += 64) {
-    const int i = e / NX, j = e - i * NX;
+  double *Ac = A + (size_t)c * NAC;
+  for (int e = lane; e < NAC; e += 64) {
+    int i, j;
+    a_entry_of(e, i, j);
     double v;
-    if (i < NU && j < NU) {
+    if (i < NU && j < NU) {  // m2 - q22
       v = vol * T[OFF_M2 + i * NU + j] - c22 * T[OFF_ZZ + i * NU + j];
     } else if (i < NU) {  // g^b: velocity row i, pressure column
       const int p = j - NU;
@@ -189,7 +242,7 @@ __global__ void __launch_bounds__(kBlock) k_p1_assemble(int ncell, int ncol, con
       const double zp = (p % 2) ? G1 : G0;
       const double thp = q.thB * (1.0 - zp) + q.thT * zp;
       v = tt * dt * 0.125 * vol * T[OFF_UZ + j * NPR + p] * dth / thp + cd * T[OFF_TD + p * NU + j] / hj;
-    } else {
+    } else {  // m3^Pi, nodal
       v = (i == j) ? (1.0 - kappa) / kappa * 0.125 * vol / q.pic : 0.0;
     }
     Ac[e] = v;
@@ -391,9 +444,18 @@ __global__ void __launch_bounds__(64 * kMW) k_p1_condense_mfma(int ncell, const 
   const int c = xcd_block() * kMW + wv;
   const bool active = c < ncell;  // uniform within a wavefront
   MfmaLds &S = sL[wv];
+  // the cell's compact A_K staged in FP32 through the tile area (coalesced loads), then spread over
+  // the accumulator tiles from there
+  static_assert(NAC <= 6 * 16 * TS, "the compact A_K fits the staging area");
+  float *Ast = &S.stg[0][0];
+  if (active) {
+    const double *Ac = A + (size_t)c * NAC;
+    for (int e = lane; e < NAC; e += 64) Ast[e] = (float)Ac[e];
+    if (lane < NF) sC[wv][lane] = cdiag[(size_t)c * NF + lane];
+  }
+  __syncthreads();
   f32x4 acc[3][5];
   if (active) {
-    const double *Ac = A + (size_t)c * NA;
 #pragma unroll
     for (int ti = 0; ti < 3; ++ti)
 #pragma unroll
@@ -402,18 +464,23 @@ __global__ void __launch_bounds__(64 * kMW) k_p1_condense_mfma(int ncell, const 
         for (int q = 0; q < 4; ++q) {
           const int r = 16 * ti + 4 * lg + q, j = 16 * tj + lc;
           float v;
-          if (r < NX && j < NX) v = (float)Ac[r * NX + j];
-          else if (j < MP) v = (r == j) ? 1.f : 0.f;
-          else v = (j - MP == r && r < NF) ? (float)kdiag[(size_t)c * NF + r] : 0.f;
+          if (r < NX && j < NX) {
+            const int e = a_compact(r, j);
+            v = e < 0 ? 0.f : Ast[e];
+          } else if (j < MP) {
+            v = (r == j) ? 1.f : 0.f;
+          } else {
+            v = (j - MP == r && r < NF) ? (float)kdiag[(size_t)c * NF + r] : 0.f;
+          }
           acc[ti][tj][q] = v;
         }
-    if (lane < NF) sC[wv][lane] = cdiag[(size_t)c * NF + lane];
   } else {
 #pragma unroll
     for (int ti = 0; ti < 3; ++ti)
 #pragma unroll
       for (int tj = 0; tj < 5; ++tj) acc[ti][tj] = f32x4{0.f, 0.f, 0.f, 0.f};
   }
+  __syncthreads();  // the staging area is the elimination's from here on
   if (active) mf_elim_block<0>(acc, lc, lg);
   mf_trailing<0, SPLIT>(acc, S, active, lc, lg);
   if (active) mf_elim_block<1>(acc, lc, lg);
@@ -491,18 +558,6 @@ __device__ __forceinline__ int p1_row_cells(size_t T, int nlev, int ncol, int ne
 // Sg^-1 (8 x 8).
 constexpr int FO_MI = 0, FO_MIG = 108, FO_DR = FO_MIG + 288, FO_SGI = FO_DR + 288, NFAC = FO_SGI + 64;
 
-__device__ __forceinline__ int blk_dof(int blk, int r) {  // dof of position r (0: "-" face, 1: "+" face, 2: interior)
-  const int d = blk >> 2, i = blk & 3;
-  return r == 0 ? 8 * d + i : (r == 1 ? 8 * d + 4 + i : 24 + 4 * d + i);
-}
-__device__ __forceinline__ void dof_blk(int a, int &blk, int &r) {
-  if (a < 24) {
-    const int f = a >> 2, i = a & 3;
-    blk = 4 * (f >> 1) + i, r = f & 1;
-  } else {
-    blk = a - 24, r = 2;  // 24 + 4 d + i  ->  block 4 d + i
-  }
-}
 
 // One wavefront per cell, SW cells per workgroup.  LDS per cell: Mi, Dr, Mi G, Sg, the diagonals of
 // C_K and K_K, and T (first the trace-face columns of Dr Mi, then Sg^-1 times them in place): 988
@@ -518,20 +573,20 @@ __global__ void __launch_bounds__(64 * SW) k_p1_condense_struct(int ncell, const
   const int c = xcd_block() * SW + wv;
   const bool active = c < ncell;
   double *Mi = sMi[wv], *Dr = sDr[wv], *MiG = sMiG[wv], *Sg = sSg[wv], *T = sT[wv];
-  const double *Ac = A + (size_t)c * NA;
+  auto Ae = [&](int e) { return A[(size_t)c * NAC + e]; };  // compact A_K
   if (active) {
 #pragma unroll
     for (int e = lane; e < 288; e += 64) {
       const int a = e >> 3, p = e & 7;
-      Dr[p * NU + a] = Ac[(NU + p) * NX + a];  // Dr[p][a]
+      Dr[p * NU + a] = Ae(AO_DR + NU * p + a);  // Dr[p][a]
     }
     if (lane < NF) sCK[wv][lane] = cdiag[(size_t)c * NF + lane];
     else if (lane < 2 * NF) sCK[wv][lane] = kdiag[(size_t)c * NF + lane - NF];
-    Sg[lane] = Ac[(NU + (lane >> 3)) * NX + NU + (lane & 7)];  // P
+    Sg[lane] = Ae(AO_P + lane);  // P
     if (lane < 12) {  // invert the 3x3 block by cofactors
       double m[3][3];
       for (int r = 0; r < 3; ++r)
-        for (int q = 0; q < 3; ++q) m[r][q] = Ac[blk_dof(lane, r) * NX + blk_dof(lane, q)];
+        for (int q = 0; q < 3; ++q) m[r][q] = Ae(AO_M + 9 * lane + 3 * r + q);
       const double c00 = m[1][1] * m[2][2] - m[1][2] * m[2][1], c01 = m[1][2] * m[2][0] - m[1][0] * m[2][2],
                    c02 = m[1][0] * m[2][1] - m[1][1] * m[2][0];
       const double inv = 1.0 / (m[0][0] * c00 + m[0][1] * c01 + m[0][2] * c02);
@@ -550,7 +605,7 @@ __global__ void __launch_bounds__(64 * SW) k_p1_condense_struct(int ncell, const
       const int a = e >> 3, p = e & 7;
       dof_blk(a, blk, r);
       double s1 = 0.0;
-      for (int q = 0; q < 3; ++q) s1 += Mi[9 * blk + 3 * r + q] * Ac[blk_dof(blk, q) * NX + NU + p];
+      for (int q = 0; q < 3; ++q) s1 += Mi[9 * blk + 3 * r + q] * Ae(AO_G + NPR * blk_dof(blk, q) + p);
       MiG[e] = s1;
     }
     for (int e = lane; e < 192; e += 64) {  // (Dr Mi)[p][f] for the trace-face dofs f < NF
