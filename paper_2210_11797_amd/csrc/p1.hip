@@ -561,14 +561,18 @@ constexpr int FO_MI = 0, FO_MIG = 108, FO_DR = FO_MIG + 288, FO_SGI = FO_DR + 28
 
 // One wavefront per cell, SW cells per workgroup.  LDS per cell: Mi, Dr, Mi G, Sg, the diagonals of
 // C_K and K_K, and T (first the trace-face columns of Dr Mi, then Sg^-1 times them in place): 988
-// doubles.  G is read from A_K where Mi G is formed rather than staged.
+// doubles, each array padded per cell (1008 in all) so that the write-out, where consecutive lanes
+// read the same entry of different cells, finds the cells' copies in different LDS banks (unpadded,
+// the strides of 288, 192 and 64 doubles put all eight cells on one bank).  G is read from A_K
+// where Mi G is formed rather than staged.
+constexpr int LP_DR = 292, LP_MIG = 292, LP_SG = 68, LP_T = 196, LP_CK = 2 * NF + 4;
 template <int SW>
 __global__ void __launch_bounds__(64 * SW) k_p1_condense_struct(int ncell, const double *__restrict__ A,
                                                                const double *__restrict__ cdiag,
                                                                const double *__restrict__ kdiag,
                                                                double *__restrict__ SK, double *__restrict__ fac,
                                                                int write_sk) {
-  __shared__ double sMi[SW][108], sDr[SW][288], sMiG[SW][288], sSg[SW][64], sT[SW][192], sCK[SW][2 * NF];
+  __shared__ double sMi[SW][108], sDr[SW][LP_DR], sMiG[SW][LP_MIG], sSg[SW][LP_SG], sT[SW][LP_T], sCK[SW][LP_CK];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int c = xcd_block() * SW + wv;
   const bool active = c < ncell;
@@ -662,16 +666,38 @@ __global__ void __launch_bounds__(64 * SW) k_p1_condense_struct(int ncell, const
   if (c0 + w >= ncell) return;
   const double *wMi = sMi[w], *wMiG = sMiG[w], *wT = sT[w], *wDr = sDr[w], *wSg = sSg[w];
   const size_t cw = (size_t)c0 + w;
-  if (write_sk)
-    for (int e = threadIdx.x / SW; e < NS; e += 64) {
-      const int r = e / NF, f = e - r * NF;
-      int br, pr, bf, pf;
+  // S_K: the 64 threads of a cell take rows r = j / 8 + 8 i and columns f = j mod 8 + 8 u (i, u < 3),
+  // so the eight T entries of a column and the eight Mi G entries of a row are read once per three
+  // products (about 5 LDS reads per entry instead of 16).
+  static_assert(NF == 24, "three row and three column groups of eight");
+  if (write_sk) {
+    const int j = threadIdx.x / SW, rg = j >> 3, f0 = j & 7;
+    double tc[3][8];
+#pragma unroll
+    for (int u = 0; u < 3; ++u)
+#pragma unroll
+      for (int p = 0; p < 8; ++p) tc[u][p] = wT[p * NF + f0 + 8 * u];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int r = rg + 8 * i;
+      double mr[8];
+#pragma unroll
+      for (int p = 0; p < 8; ++p) mr[p] = wMiG[r * 8 + p];
+      int br, pr;
       dof_blk(r, br, pr);
-      dof_blk(f, bf, pf);
-      double v = (br == bf) ? wMi[9 * br + 3 * pr + pf] : 0.0;
-      for (int p = 0; p < 8; ++p) v += wMiG[r * 8 + p] * wT[p * NF + f];
-      SK[(size_t)e * ncell + cw] = sCK[w][r] * v * sCK[w][NF + f];
+      const double ckr = sCK[w][r];
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        const int f = f0 + 8 * u;
+        int bf, pf;
+        dof_blk(f, bf, pf);
+        double v = (br == bf) ? wMi[9 * br + 3 * pr + pf] : 0.0;
+#pragma unroll
+        for (int p = 0; p < 8; ++p) v += mr[p] * tc[u][p];
+        SK[(size_t)(r * NF + f) * ncell + cw] = ckr * v * sCK[w][NF + f];
+      }
     }
+  }
   for (int e = threadIdx.x / SW; e < NFAC; e += 64) {
     double v;
     if (e < FO_MIG) v = wMi[e];
