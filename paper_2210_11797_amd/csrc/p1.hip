@@ -709,7 +709,8 @@ __global__ void __launch_bounds__(64 * SW) k_p1_condense_struct(int ncell, const
 }
 
 // cells (wavefronts) per workgroup of the structured condensation (128^2x32, FP64 call: 4 cells
-// 5.6 ms, 8 cells 5.0 ms, 16 cells, one workgroup per CU, 9.2 ms)
+// 5.6 ms, 8 cells 5.0 ms, 16 cells 9.2 ms with the unpadded LDS arrays; with them padded, 8 cells
+// 3.51 ms with S_K and 2.27 ms for the factors alone, 16 cells, one workgroup per CU, 3.46 and 2.54)
 constexpr int kSW = 8;
 
 // Thread per cell: X = A_K^-1 (R - [K lambda; 0]) from the structured factors.  mode 0: the cell's
