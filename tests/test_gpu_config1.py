@@ -67,7 +67,7 @@ def test_mixed_operator_and_preconditioner(case):
 # host's BLAS), and both sides' estimates, and with them the step at which they stop, are set by
 # rounding (measured 48 against 51-54 iterations).  The residual histories are compared over the
 # first 20 steps, the final count within 2 on the box and within a quarter on the sphere; the
-# solutions against the sparse LU one to 1e-9 (measured 1e-11).
+# solutions against the sparse LU one to 1e-10 (measured 2.3e-11 on the box, 1.1e-11 on the sphere).
 @pytest.mark.parametrize("case,rtol,band", [("box16x16x8", 1e-8, 2), ("sphere_c8x10", 1e-7, 0.25)])
 def test_mixed_solve(case, rtol, band):
     import torch
@@ -100,6 +100,6 @@ def test_mixed_solve(case, rtol, band):
     assert info["status"] == 0 and res <= 1.05 * rtol
     np.testing.assert_allclose(info["history"][:20], hist[1:21], rtol=1e-3)  # measured 1.5e-4
     assert abs(info["iters"] - oits) <= (band if band >= 1 else max(2, int(band * oits)))
-    assert eu <= 1e-9 and ep <= 1e-9
+    assert eu <= 1e-10 and ep <= 1e-10
     assert info["iters"] > its3c
     s.close()
